@@ -1,0 +1,72 @@
+"""Quantised basis T_lm and the projection omega_lm <-> W (oracle).
+
+Sec. 3.2: since Delta_N T_lm = -l(l+1) T_lm (eq. (lap_prop)) and the Laplacian splits into
+the tridiagonal blocks Delta^m of eq. (delta_tria), the basis elements with m >= 0 are the
+eigenvectors of Delta^m placed on the m-th sub-diagonal; those with m < 0 follow by
+skew-symmetry.  W is then assembled as W = sum_lm i omega_lm T_lm, eq. (W0).  Here the
+eigenvectors come from LAPACK (``scipy.linalg.eigh_tridiagonal``), standing in for the
+paper's ``pdstedc``.
+
+Readings taken here:
+
+* l runs over m..N-1 on diagonal m (l = 0 is the identity direction on m = 0); the
+  eigenvalues of Delta^m, in ascending order, are l(l+1) for l = m, m+1, ..., N-1;
+* each eigenvector has unit 2-norm (so T_lm has unit Frobenius norm), and its sign is fixed
+  by making the entry of largest magnitude among indices 0..floor((n-1)/2) positive (the
+  paper leaves the sign open; the first entry is no good, it underflows for large N);
+* T_{l,-m} = (-1)^m T_lm^H, so W[i+m, i] = i sum_l omega_lm v^{lm}_i and
+  W[i, i+m] = i (-1)^m sum_l omega_{l,-m} v^{lm}_i; real vorticity,
+  omega_{l,-m} = (-1)^m conj(omega_lm), makes W skew-Hermitian;
+* coefficients are stored flat at index l*l + l + m (length N*N).
+"""
+
+import numpy as np
+from scipy.linalg import eigh_tridiagonal
+
+from .laplacian import delta_tridiag
+
+
+def eigvecs(N: int, m: int):
+    """Eigenvalues (ascending) and sign-fixed unit eigenvectors (columns) of Delta^m."""
+    d, e = delta_tridiag(N, m)
+    n = N - m
+    if n == 1:
+        return d.copy(), np.ones((1, 1))
+    w, V = eigh_tridiagonal(d, e)
+    half = (n - 1) // 2 + 1
+    k = np.argmax(np.abs(V[:half, :]), axis=0)
+    sgn = np.sign(V[k, np.arange(n)])
+    sgn[sgn == 0] = 1.0
+    return w, V * sgn
+
+
+def assemble(N: int, omega: np.ndarray) -> np.ndarray:
+    """W = sum_{l,m} i omega_lm T_lm (eq. (W0)) from flat coefficients omega[l*l+l+m]."""
+    omega = np.asarray(omega, dtype=np.complex128)
+    W = np.zeros((N, N), dtype=np.complex128)
+    for m in range(N):
+        _, V = eigvecs(N, m)
+        n = N - m
+        i = np.arange(n)
+        l = np.arange(m, N)
+        W[i + m, i] = 1j * (V @ omega[l * l + l + m])
+        if m > 0:
+            W[i, i + m] = 1j * (-1) ** m * (V @ omega[l * l + l - m])
+    return W
+
+
+def extract(W: np.ndarray) -> np.ndarray:
+    """omega_lm = -i <T_lm, W>_F, the inverse of ``assemble`` on u(N) (Sec. 3.2, post-processing)."""
+    W = np.asarray(W, dtype=np.complex128)
+    N = W.shape[0]
+    omega = np.zeros(N * N, dtype=np.complex128)
+    for m in range(N):
+        _, V = eigvecs(N, m)
+        n = N - m
+        i = np.arange(n)
+        l = np.arange(m, N)
+        c = -1j * (V.T @ W[i + m, i])
+        omega[l * l + l + m] = c
+        if m > 0:
+            omega[l * l + l - m] = (-1) ** m * np.conj(c)
+    return omega

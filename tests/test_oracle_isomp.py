@@ -1,0 +1,155 @@
+"""Pins of the oracle's IsoMP step (eqs. (isomp), (isomp_iter)).
+
+No numeric worked example is printed in the paper, so the step is pinned by what the
+scheme and the mathematics fix:
+
+* convergence to the continuous flow dW/dt = [P, W], Delta_N P = W (eq. (Euler_vort_mat))
+  at second order, against an independent high-order ODE integration whose right-hand
+  side uses the dense pseudo-inverse Laplacian (this pins the sign of time and every term);
+* isospectrality and Casimir conservation to the fixed-point tolerance (Sec. 2);
+* skew-Hermitian, traceless output; reversibility under h -> -h (midpoint rule symmetry);
+* steady states: zonal (and by rotation, degree-1) vorticity is exactly stationary; for a
+  single degree l >= 2 the commutator vanishes and the step drifts only at O(h^3);
+* SU(2) rotation equivariance;
+* iteration counts of a few (2..5) at tolerance 1e-12 (Sec. 2 reports 2 to 3).
+"""
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+from scipy.linalg import expm
+
+import oracle as O
+from workloads import omega_coeffs
+
+
+def w0(N, seed=0, law="inv1", lmax=None):
+    return O.assemble(N, omega_coeffs(N, seed, law, lmax))
+
+
+def spec(W):
+    return np.linalg.eigvalsh(1j * W)
+
+
+def test_structure_and_isospectral_n64():
+    W = w0(64)
+    W1, k, r = O.isomp_step(W, 0.01, 1e-12, 50)
+    assert 2 <= k <= 5 and r < 1e-12
+    assert np.abs(W1 + W1.conj().T).max() < 1e-15
+    assert abs(np.trace(W1)) < 1e-13
+    assert np.abs(spec(W1) - spec(W)).max() < 1e-12
+    c0, c1 = O.casimirs(W, 4), O.casimirs(W1, 4)
+    assert np.abs(c1 - c0)[1:].max() < 1e-12 * np.abs(c0[1])
+    assert np.abs(W1 - W).max() > 1e-6  # it moved
+
+
+def test_fixed_iteration_count_with_zero_tol():
+    W = w0(16)
+    _, k, r = O.isomp_step(W, 0.05, 0.0, 3)
+    assert k == 3 and r > 0
+
+
+def test_reversible():
+    W = w0(24, 1)
+    W1, _, _ = O.isomp_step(W, 0.05, 1e-14, 50)
+    Wb, _, _ = O.isomp_step(W1, -0.05, 1e-14, 50)
+    assert np.abs(Wb - W).max() < 1e-13
+
+
+def _ode_reference(W0, T):
+    """dW/dt = [P, W], P = pinv(Delta_N) W, integrated with DOP853 at tight tolerance."""
+    N = W0.shape[0]
+    Lp = np.linalg.pinv(O.brute_laplacian(N), rcond=1e-10)
+
+    def rhs(_, y):
+        W = (y[: N * N] + 1j * y[N * N:]).reshape(N, N)
+        P = (Lp @ W.reshape(-1)).reshape(N, N)
+        D = (P @ W - W @ P).reshape(-1)
+        return np.concatenate([D.real, D.imag])
+
+    y0 = np.concatenate([W0.real.reshape(-1), W0.imag.reshape(-1)])
+    sol = solve_ivp(rhs, (0.0, T), y0, method="DOP853", rtol=1e-13, atol=1e-15)
+    y = sol.y[:, -1]
+    return (y[: N * N] + 1j * y[N * N:]).reshape(N, N)
+
+
+def test_second_order_against_independent_ode():
+    N = 8
+    W = 3.0 * w0(N, 2)
+    T = 0.8
+    ref = _ode_reference(W, T)
+    errs = []
+    for nsteps in (4, 8, 16):
+        Wh, _, _ = O.isomp_run(W, T / nsteps, nsteps, 1e-14, 100)
+        errs.append(np.abs(Wh - ref).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.8 < r2 < 4.2, errs
+    assert errs[-1] < 1e-3 * np.abs(W).max()
+
+
+def test_zonal_and_degree_one_are_steady():
+    N = 16
+    om = np.zeros(N * N, complex)
+    for l in range(1, N):
+        om[l * l + l] = 1.0 / (l + 1)  # m = 0 only: zonal
+    Wz = O.assemble(N, om)
+    W1, _, _ = O.isomp_step(Wz, 0.1, 1e-14, 50)
+    assert np.abs(W1 - Wz).max() < 1e-14
+    om = np.zeros(N * N, complex)
+    om[1 * 1 + 1 + 1] = 0.3 - 0.2j
+    om[1 * 1 + 1 - 1] = -np.conj(om[3])
+    om[1 * 1 + 1] = 0.5
+    Wr = O.assemble(N, om)
+    W1, _, _ = O.isomp_step(Wr, 0.1, 1e-14, 50)
+    assert np.abs(W1 - Wr).max() < 1e-13
+
+
+def test_single_degree_commutator_vanishes_and_drift_is_cubic():
+    N, l = 32, 3
+    rng = np.random.default_rng(4)
+    om = np.zeros(N * N, complex)
+    om[l * l + l] = rng.standard_normal()
+    for m in range(1, l + 1):
+        c = rng.standard_normal() + 1j * rng.standard_normal()
+        om[l * l + l + m] = c
+        om[l * l + l - m] = (-1) ** m * np.conj(c)
+    W = O.assemble(N, om)
+    W /= np.linalg.norm(W, 2)
+    P = O.stream_solve(W)
+    assert np.abs(P @ W - W @ P).max() < 1e-15
+    d = []
+    for h in (0.1, 0.05, 0.025):
+        W1, _, _ = O.isomp_step(W, h, 1e-15, 50)
+        d.append(np.abs(W1 - W).max())
+    assert 7.0 < d[0] / d[1] < 9.0 and 7.0 < d[1] / d[2] < 9.0, d
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_su2_equivariance(axis):
+    N = 12
+    W = w0(N, 3)
+    U = expm(0.9j * O.spin_matrices(N)[axis])
+    W1, _, _ = O.isomp_step(W, 0.05, 1e-14, 50)
+    W1r, _, _ = O.isomp_step(U @ W @ U.conj().T, 0.05, 1e-14, 50)
+    assert np.abs(W1r - U @ W1 @ U.conj().T).max() < 1e-13
+
+
+def test_ten_steps_casimir_drift_n64():
+    W = w0(64, 0)
+    W10, iters, res = O.isomp_run(W, 0.01, 10, 1e-12, 50)
+    assert all(2 <= k <= 5 for k in iters) and max(res) < 1e-12
+    c0, c1 = O.casimirs(W, 4), O.casimirs(W10, 4)
+    rel = np.abs(c1 - c0) / np.abs(c0)
+    assert rel[1] < 1e-11 and rel[3] < 1e-11
+    assert abs(c1[2] - c0[2]) / np.linalg.norm(W) ** 3 < 1e-11
+
+
+def test_isospectral_in_strong_regime():
+    """Large h ||P||: the step must still be an exact similarity (to the tolerance);
+    a wrong h^2 term (e.g. P P W~ for P W~ P) shows up here at O(h^3)."""
+    N = 10
+    W = 4.0 * w0(N, 5)
+    W1, k, r = O.isomp_step(W, 0.25, 1e-14, 200)
+    assert r < 1e-14
+    assert np.abs(spec(W1) - spec(W)).max() < 1e-12 * np.abs(spec(W)).max()
+    assert np.abs(W1 - W).max() > 1e-2
