@@ -1,0 +1,159 @@
+/*
+ * zeuler.h -- C ABI of libzeuler.so: the isospectral-midpoint (IsoMP) Zeitlin--Euler step on
+ * the sphere for MI355X (gfx950), after Cifani, Viviani & Modin, "An efficient geometric
+ * method for incompressible hydrodynamics on the sphere" (arXiv 2206.05466).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Matrices are N x N complex128, row-major, interleaved (re, im): entry (r, c) at
+ *   element r*N + c, i.e. the memory of a contiguous torch.complex128 tensor.  Matrix
+ *   arguments are DEVICE pointers on the context's GPU, 16-byte aligned, owned by the
+ *   caller; the library never frees or keeps them.
+ * - Diagonal m >= 0 of a matrix means its entries (i+m, i), i = 0..N-m-1 (0-based).
+ * - The vorticity W and stream matrix P lie in u(N)/su(N) (skew-Hermitian).  The library
+ *   reads only the lower triangle and diagonal of a skew-Hermitian input and writes both
+ *   triangles of every skew-Hermitian output (the upper one as -conj of the lower).
+ * - Calls are asynchronous on the stream given to ze_create, except where a call returns
+ *   host values (documented per call): those synchronise that stream.
+ * - Status codes only; nothing is thrown across the ABI.  A context is not thread-safe:
+ *   calls on one context must not overlap.
+ */
+#ifndef ZEULER_H
+#define ZEULER_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ze_ctx ze_ctx;  /* opaque: Laplacian factors and workspaces for one N */
+typedef struct ze_ens ze_ens;  /* opaque: an ensemble of independent simulations */
+
+typedef enum {
+    ZE_OK = 0,
+    ZE_EINVAL = 1,      /* bad argument: N < 1, null pointer, h or tol not finite, ... */
+    ZE_ENOMEM = 2,      /* device or host allocation failed */
+    ZE_ENOTCONV = 3,    /* fixed point not below tol after maxit evaluations (result still written) */
+    ZE_ENONFINITE = 4,  /* NaN or Inf met in the fixed-point residual */
+    ZE_EHIP = 5         /* a HIP runtime call failed */
+} ze_status;
+
+/* Arithmetic of the complex matrix products. */
+typedef enum {
+    ZE_PREC_FP64 = 0,   /* FP64 MFMA products */
+    ZE_PREC_SPLIT = 1   /* split-precision emulation of the FP64 products on low-precision MFMA */
+} ze_prec;
+
+/* Message for a status code (static string). */
+const char* ze_strerror(ze_status s);
+
+/* Last HIP error message recorded by the library in this thread ("" if none). */
+const char* ze_last_error(void);
+
+/*
+ * ze_create -- set up the quantised Laplacian for matrix size N (Sec. 3.2, eq. (delta_tria)):
+ * the tridiagonal block Delta^m of every diagonal m = 0..N-1 is factored (LDL^T, FP64, on
+ * the host) and uploaded, and the step's workspaces (about 4 padded N x N complex matrices)
+ * are allocated on the current HIP device.
+ *   N       matrix size, 1 <= N <= 65536.
+ *   stream  hipStream_t (as void*) all work of this context is queued on; NULL = default stream.
+ *   out     receives the context.
+ * Errors: ZE_EINVAL (N out of range, out NULL), ZE_ENOMEM, ZE_EHIP.  Synchronous.
+ */
+ze_status ze_create(int N, void* stream, ze_ctx** out);
+
+/* Free a context and everything it owns (synchronises its stream).  NULL is accepted. */
+ze_status ze_destroy(ze_ctx* ctx);
+
+/* Matrix size of a context (0 for NULL). */
+int ze_size(const ze_ctx* ctx);
+
+/*
+ * ze_stream_solve -- P = Delta_N^+ W (Sec. 3.3, eq. (sub_tria_W)): one tridiagonal solve per
+ * diagonal m, P_m = -(Delta^m)^{-1} W_m (the Laplacian is -Delta^m on diagonal m, its
+ * eigenvalues being -l(l+1), eq. (lap_prop)), the upper triangle by skew-symmetry.  The
+ * singular m = 0 block is solved as the pseudo-inverse: tr(W)/N is removed from its
+ * right-hand side and the result is made traceless, so P is in su(N) even for W in u(N).
+ *   W  device, N x N complex128 (lower triangle and diagonal read).
+ *   P  device, N x N complex128 (fully written); must not alias W.
+ * Errors: ZE_EINVAL (NULL pointers, P == W), ZE_EHIP.  Asynchronous.
+ */
+ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
+
+/*
+ * ze_isomp_step -- one isospectral-midpoint step, eq. (isomp) (Sec. 2): W_n -> W_{n+1}, with
+ * the implicit W~ found by the fixed-point iteration eq. (isomp_iter) from W~ = W_n.  Each
+ * evaluation is one stream solve, A = P W~, and the lower triangle of Q = A P, the
+ * commutator being A - A^H (Sec. 3.1).  It stops once the matrix infinity norm of the change
+ * of W~ is below tol, and W_{n+1} = W~ + h/2 (A - A^H) - h^2/4 Q from that same evaluation.
+ *   W       device, N x N complex128, skew-Hermitian; in: W_n, out: W_{n+1}.
+ *   h       time step (any finite sign).
+ *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
+ *   maxit   evaluation cap, >= 1.
+ *   prec    ZE_PREC_FP64 or ZE_PREC_SPLIT.
+ *   iters   host, may be NULL: evaluations done.
+ *   resid   host, may be NULL: final residual.
+ * Errors: ZE_EINVAL, ZE_ENOTCONV (W holds the maxit-th W_{n+1}), ZE_ENONFINITE, ZE_EHIP.
+ * Synchronises the stream once per evaluation (the convergence test).
+ */
+ze_status ze_isomp_step(ze_ctx* ctx, void* W, double h, double tol, int maxit, int prec,
+                        int* iters, double* resid);
+
+/*
+ * ze_isomp_run -- nsteps calls of ze_isomp_step on the same W.
+ *   iters, resid  host arrays of nsteps entries, may be NULL.
+ * Stops at the first step that returns an error and returns it.
+ */
+ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, int nsteps,
+                       int prec, int* iters, double* resid);
+
+/*
+ * ze_casimirs -- C_k(W) = Tr(W^k), k = 1..kmax (eq. (W_pow)), in FP64, from powers of W
+ * formed with the library's FP64 products: C_{a+b} = sum_ij (W^a)_ij (W^b)_ji.
+ *   W     device, N x N complex128 (any matrix; all of it is read).
+ *   kmax  1 <= kmax <= 64.
+ *   out   host, 2*kmax doubles: (re, im) of C_1..C_kmax.
+ * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Synchronous.
+ */
+ze_status ze_casimirs(ze_ctx* ctx, const void* W, int kmax, double* out);
+
+/*
+ * ze_basis_assemble -- W = sum_{l,m} i omega_lm T_lm (eq. (W0)), the T_lm being the unit
+ * eigenvectors of Delta^m for the eigenvalue l(l+1) (eq. (lap_prop)) placed on diagonal m
+ * (Sec. 3.2), with T_{l,-m} = (-1)^m T_lm^H.  Eigenvector signs: the entry of largest
+ * magnitude among indices 0..floor((N-m-1)/2) is positive.
+ *   omega  device, N*N complex128 coefficients, omega_lm at index l*l + l + m.
+ *   W      device, N x N complex128, fully written.
+ * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Asynchronous.
+ */
+ze_status ze_basis_assemble(ze_ctx* ctx, const void* omega, void* W);
+
+/*
+ * ze_zgemm -- C = A B for N x N complex128 matrices with the library's product kernels
+ * (the GEMM of Sec. 3.1 on its own; for tests and timing).
+ *   A, B, C  device, N x N complex128; C must not alias A or B.
+ *   prec     ZE_PREC_FP64 or ZE_PREC_SPLIT.
+ * Errors: ZE_EINVAL, ZE_EHIP.  Asynchronous.
+ */
+ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec);
+
+/*
+ * ze_profile -- per-phase timing of ze_isomp_step, for measurement.  While on, every
+ * evaluation records HIP events on the context's stream around its four phases and adds
+ * their elapsed times (read back at the evaluation's convergence test, so no extra
+ * synchronisation).  Phases: 0 stream solve, 1 product A = P W~, 2 lower product Q = A P
+ * with the fixed-point epilogue, 3 residual reduction.
+ * Errors: ZE_EINVAL, ZE_EHIP (event creation).  Synchronous.
+ */
+ze_status ze_profile(ze_ctx* ctx, int on);
+
+/*
+ * ze_profile_read -- accumulated milliseconds (ms[4]) and launch counts (launches[4]) per
+ * phase since the last reset; both host arrays, either may be NULL.  reset != 0 clears them.
+ */
+ze_status ze_profile_read(ze_ctx* ctx, double* ms, long long* launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZEULER_H */

@@ -26,29 +26,42 @@ from scipy.linalg import eigh_tridiagonal
 from .laplacian import delta_tridiag
 
 
-def eigvecs(N: int, m: int):
-    """Eigenvalues (ascending) and sign-fixed unit eigenvectors (columns) of Delta^m."""
+def eigvecs(N: int, m: int, count: int | None = None):
+    """Eigenvalues (ascending) and sign-fixed unit eigenvectors (columns) of Delta^m.
+
+    ``count`` limits the result to the lowest ``count`` eigenpairs (l = m..m+count-1).
+    """
     d, e = delta_tridiag(N, m)
     n = N - m
     if n == 1:
         return d.copy(), np.ones((1, 1))
-    w, V = eigh_tridiagonal(d, e)
+    if count is None or count >= n:
+        w, V = eigh_tridiagonal(d, e)
+    else:
+        w, V = eigh_tridiagonal(d, e, select="i", select_range=(0, count - 1))
     half = (n - 1) // 2 + 1
     k = np.argmax(np.abs(V[:half, :]), axis=0)
-    sgn = np.sign(V[k, np.arange(n)])
+    sgn = np.sign(V[k, np.arange(V.shape[1])])
     sgn[sgn == 0] = 1.0
     return w, V * sgn
 
 
-def assemble(N: int, omega: np.ndarray) -> np.ndarray:
-    """W = sum_{l,m} i omega_lm T_lm (eq. (W0)) from flat coefficients omega[l*l+l+m]."""
+def assemble(N: int, omega: np.ndarray, lmax: int | None = None) -> np.ndarray:
+    """W = sum_{l,m} i omega_lm T_lm (eq. (W0)) from flat coefficients omega[l*l+l+m].
+
+    With ``lmax`` the coefficients of degree l > lmax must be zero, and only the basis
+    elements up to degree lmax are computed (the large-scale initial conditions).
+    """
     omega = np.asarray(omega, dtype=np.complex128)
     W = np.zeros((N, N), dtype=np.complex128)
-    for m in range(N):
-        _, V = eigvecs(N, m)
+    top = N - 1 if lmax is None else min(int(lmax), N - 1)
+    if np.any(omega[(top + 1) ** 2:] != 0):
+        raise ValueError("coefficients beyond lmax must be zero")
+    for m in range(top + 1):
+        _, V = eigvecs(N, m, top - m + 1)
         n = N - m
         i = np.arange(n)
-        l = np.arange(m, N)
+        l = np.arange(m, top + 1)
         W[i + m, i] = 1j * (V @ omega[l * l + l + m])
         if m > 0:
             W[i, i + m] = 1j * (-1) ** m * (V @ omega[l * l + l - m])

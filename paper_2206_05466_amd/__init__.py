@@ -1,0 +1,12 @@
+"""MI355X-native isospectral-midpoint Zeitlin--Euler step on the sphere (arXiv 2206.05466).
+
+The computation lives in ``libzeuler.so`` (HIP, gfx950; C ABI in ``include/zeuler.h``);
+``zeuler`` is its ctypes binding.
+"""
+
+from .zeuler import (
+    LIB_PATH, PREC_FP64, PREC_SPLIT, SIGNATURES, StepInfo, Zeuler, ZeulerError, load_library,
+)
+
+__all__ = ["LIB_PATH", "PREC_FP64", "PREC_SPLIT", "SIGNATURES", "StepInfo", "Zeuler",
+           "ZeulerError", "load_library"]

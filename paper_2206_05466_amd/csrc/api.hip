@@ -1,0 +1,322 @@
+// C ABI of libzeuler: context set-up (Laplacian factors), stream solve, IsoMP step driver,
+// Casimirs, products.  Host code; the arithmetic of every step runs in the HIP kernels.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// LDL^T factors of every block Delta^m of eq. (delta_tria), packed row-major lower
+// triangle (entry (i+m, i) for element i of diagonal m), and ubar for the m = 0
+// pseudo-inverse.  Delta^m: d_i = 2 (s(2i+1+m) - i(i+m)), off-diagonal
+// e_i = -sqrt((i+m+1)(N-1-i-m)) sqrt((i+1)(N-1-i)), s = (N-1)/2.  Block m is symmetric
+// positive definite for m >= 1; for m = 0 only its leading (N-1) x (N-1) block is.
+void build_factors(int N, std::vector<double>& fl, std::vector<double>& fd,
+                   std::vector<double>& ubar) {
+    const size_t tot = tri_off(N, 0);
+    fl.assign(tot, 0.0);
+    fd.assign(tot, 0.0);
+    ubar.assign(N, 0.0);
+    const double s = 0.5 * (N - 1);
+    std::vector<double> D(N), L(N);
+    for (int m = 0; m < N; ++m) {
+        const int n = N - m;
+        const int nf = (m == 0) ? n - 1 : n;  // factored length
+        for (int i = 0; i < nf; ++i) {
+            const double d = 2.0 * (s * (2.0 * i + 1.0 + m) - (double)i * (double)(i + m));
+            if (i == 0) {
+                D[0] = d;
+            } else {
+                const double k = i - 1;
+                const double e = -std::sqrt((k + m + 1.0) * (N - 1.0 - k - m)) *
+                                 std::sqrt((k + 1.0) * (N - 1.0 - k));
+                L[i - 1] = e / D[i - 1];
+                D[i] = d - L[i - 1] * e;
+            }
+            const size_t po = tri_off(i + m, i);
+            fl[po] = (i == 0) ? 0.0 : L[i - 1];
+            fd[po] = 1.0 / D[i];
+        }
+        if (m == 0 && nf > 0) {
+            // u = B^{-1} 1 on the leading block with the same factors, u_{N-1} = 0.
+            std::vector<double> y(nf);
+            for (int i = 0; i < nf; ++i) y[i] = 1.0 - (i ? L[i - 1] * y[i - 1] : 0.0);
+            for (int i = 0; i < nf; ++i) y[i] /= D[i];
+            for (int i = nf - 2; i >= 0; --i) y[i] -= L[i] * y[i + 1];
+            double mean = 0.0;
+            for (int i = 0; i < nf; ++i) mean += y[i];
+            mean /= N;
+            for (int i = 0; i < N; ++i) ubar[i] = (i < nf ? y[i] : 0.0) - mean;
+        }
+    }
+}
+
+template <class T>
+ze_status dalloc(T** p, size_t count) {
+    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 256) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return ZE_ENOMEM;
+    }
+    return ZE_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+ze_status ze_record_hip(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return ZE_EHIP;
+}
+
+extern "C" {
+
+const char* ze_strerror(ze_status s) {
+    switch (s) {
+        case ZE_OK: return "ok";
+        case ZE_EINVAL: return "invalid argument";
+        case ZE_ENOMEM: return "out of memory";
+        case ZE_ENOTCONV: return "fixed-point iteration not converged within maxit";
+        case ZE_ENONFINITE: return "non-finite fixed-point residual";
+        case ZE_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* ze_last_error(void) { return g_last_error.c_str(); }
+
+int ze_size(const ze_ctx* ctx) { return ctx ? ctx->N : 0; }
+
+ze_status ze_destroy(ze_ctx* c) {
+    if (!c) return ZE_OK;
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c->fac_l);
+    dfree(c->fac_dinv);
+    dfree(c->ubar);
+    dfree(c->diagstat);
+    dfree(c->Wn);
+    dfree(c->F);
+    dfree(c->P);
+    dfree(c->A);
+    dfree(c->rowpart);
+    dfree(c->blockmax);
+    dfree(c->resid);
+    if (c->host_resid) (void)hipHostFree(c->host_resid);
+    for (hipEvent_t e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return ZE_OK;
+}
+
+ze_status ze_create(int N, void* stream, ze_ctx** out) {
+    if (!out) return ZE_EINVAL;
+    *out = nullptr;
+    if (N < 1 || N > 65536) return ZE_EINVAL;
+    ze_ctx* c = new ze_ctx();
+    c->N = N;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return ze_record_hip(hipGetLastError(), "hipGetDevice");
+    }
+    std::vector<double> fl, fd, ub;
+    build_factors(N, fl, fd, ub);
+    const size_t nn = (size_t)N * N;
+    const int T = (N + 63) / 64;
+    ze_status st = ZE_OK;
+    if (st == ZE_OK) st = dalloc(&c->fac_l, fl.size());
+    if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
+    if (st == ZE_OK) st = dalloc(&c->ubar, (size_t)N);
+    if (st == ZE_OK) st = dalloc(&c->diagstat, 2);
+    if (st == ZE_OK) st = dalloc(&c->Wn, nn);
+    if (st == ZE_OK) st = dalloc(&c->F, nn);
+    if (st == ZE_OK) st = dalloc(&c->P, nn);
+    if (st == ZE_OK) st = dalloc(&c->A, nn);
+    if (st == ZE_OK) st = dalloc(&c->rowpart, (size_t)T * N);
+    if (st == ZE_OK) st = dalloc(&c->blockmax, (size_t)(N + 255) / 256 + 1);
+    if (st == ZE_OK) st = dalloc(&c->resid, 1);
+    if (st == ZE_OK && hipHostMalloc(reinterpret_cast<void**>(&c->host_resid), sizeof(double)) != hipSuccess) {
+        c->host_resid = nullptr;
+        (void)hipGetLastError();
+        st = ZE_ENOMEM;
+    }
+    if (st != ZE_OK) {
+        ze_destroy(c);
+        return st;
+    }
+    hipError_t e = hipMemcpy(c->fac_l, fl.data(), fl.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->fac_dinv, fd.data(), fd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ubar, ub.data(), ub.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ze_destroy(c);
+        return ze_record_hip(e, "hipMemcpy(factors)");
+    }
+    *out = c;
+    return ZE_OK;
+}
+
+ze_status ze_stream_solve(ze_ctx* c, const void* W, void* P) {
+    if (!c || !W || !P || W == P) return ZE_EINVAL;
+    ZE_HIP(launch_stream_solve(c, static_cast<const double2*>(W), static_cast<double2*>(P), c->stream));
+    return ZE_OK;
+}
+
+ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
+    if (!c || !A || !B || !C || C == A || C == B) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    ZE_HIP(launch_zgemm_f64(static_cast<const double2*>(A), static_cast<const double2*>(B),
+                            static_cast<double2*>(C), c->N, c->stream));
+    return ZE_OK;
+}
+
+ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                        int* iters, double* resid) {
+    if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    const int N = c->N;
+    const size_t bytes = (size_t)N * N * sizeof(double2);
+    double2* Wu = static_cast<double2*>(W);
+    hipStream_t s = c->stream;
+    ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
+    const double2* Wt = c->Wn;
+    double r = 0.0;
+    int k = 0;
+    const bool prof = c->prof;
+    for (k = 1; k <= maxit; ++k) {
+        if (prof) ZE_HIP(hipEventRecord(c->ev[0], s));
+        ZE_HIP(launch_stream_solve(c, Wt, c->P, s));
+        if (prof) ZE_HIP(hipEventRecord(c->ev[1], s));
+        ZE_HIP(launch_zgemm_f64(c->P, Wt, c->A, N, s));
+        if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
+        ZE_HIP(launch_zgemm_lower_epilogue(c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, N, h, s));
+        if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
+        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));
+        if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
+        ZE_HIP(hipMemcpyAsync(c->host_resid, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+        ZE_HIP(hipStreamSynchronize(s));
+        if (prof) {
+            for (int p = 0; p < 4; ++p) {
+                float ms = 0.f;
+                ZE_HIP(hipEventElapsedTime(&ms, c->ev[p], c->ev[p + 1]));
+                c->prof_ms[p] += ms;
+                c->prof_n[p] += 1;
+            }
+        }
+        r = *c->host_resid;
+        if (!std::isfinite(r)) break;
+        if (r < tol || k == maxit) break;
+        Wt = c->F;
+    }
+    if (k > maxit) k = maxit;
+    if (iters) *iters = k;
+    if (resid) *resid = r;
+    if (!std::isfinite(r)) return ZE_ENONFINITE;
+    if (!(r < tol)) return ZE_ENOTCONV;
+    return ZE_OK;
+}
+
+ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps, int prec,
+                       int* iters, double* resid) {
+    if (!c || !W || nsteps < 0) return ZE_EINVAL;
+    for (int n = 0; n < nsteps; ++n) {
+        int k = 0;
+        double r = 0.0;
+        ze_status st = ze_isomp_step(c, W, h, tol, maxit, prec, &k, &r);
+        if (iters) iters[n] = k;
+        if (resid) resid[n] = r;
+        if (st != ZE_OK) return st;
+    }
+    return ZE_OK;
+}
+
+ze_status ze_casimirs(ze_ctx* c, const void* W, int kmax, double* out) {
+    if (!c || !W || !out || kmax < 1 || kmax > 64) return ZE_EINVAL;
+    const int N = c->N;
+    const size_t nn = (size_t)N * N;
+    const int hp = (kmax + 1) / 2;  // powers W^1..W^hp
+    std::vector<double2*> pw(hp + 1, nullptr);
+    pw[1] = const_cast<double2*>(static_cast<const double2*>(W));
+    double2* partial = nullptr;
+    double2* dres = nullptr;
+    ze_status st = ZE_OK;
+    for (int a = 2; a <= hp && st == ZE_OK; ++a) st = dalloc(&pw[a], nn);
+    if (st == ZE_OK) st = dalloc(&partial, (size_t)ze_trace_partials(N) + (size_t)N);
+    if (st == ZE_OK) st = dalloc(&dres, (size_t)kmax);
+    hipError_t e = hipSuccess;
+    for (int a = 2; a <= hp && st == ZE_OK && e == hipSuccess; ++a)
+        e = launch_zgemm_f64(pw[a - 1], pw[1], pw[a], N, c->stream);
+    for (int k = 1; k <= kmax && st == ZE_OK && e == hipSuccess; ++k) {
+        if (k == 1) {
+            e = launch_trace(pw[1], partial, dres, N, c->stream);
+        } else {
+            const int a = (k + 1) / 2, b = k / 2;
+            e = launch_trace_product(pw[a], pw[b], partial, dres + (k - 1), N, c->stream);
+        }
+    }
+    std::vector<double2> host(kmax);
+    if (st == ZE_OK && e == hipSuccess)
+        e = hipMemcpy(host.data(), dres, kmax * sizeof(double2), hipMemcpyDeviceToHost);
+    for (int a = 2; a <= hp; ++a) dfree(pw[a]);
+    dfree(partial);
+    dfree(dres);
+    if (st != ZE_OK) return st;
+    if (e != hipSuccess) return ze_record_hip(e, "ze_casimirs");
+    for (int k = 0; k < kmax; ++k) {
+        out[2 * k] = host[k].x;
+        out[2 * k + 1] = host[k].y;
+    }
+    return ZE_OK;
+}
+
+ze_status ze_basis_assemble(ze_ctx* c, const void* omega, void* W) {
+    if (!c || !omega || !W || omega == W) return ZE_EINVAL;
+    void* scratch = nullptr;
+    if (hipMalloc(&scratch, ze_basis_scratch_bytes(c->N)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ZE_ENOMEM;
+    }
+    hipError_t e = launch_basis_assemble(static_cast<const double2*>(omega), static_cast<double2*>(W),
+                                         scratch, c->N, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return ze_record_hip(e, "launch_basis_assemble");
+    if (e2 != hipSuccess) return ze_record_hip(e2, "hipStreamSynchronize(basis)");
+    return ZE_OK;
+}
+
+ze_status ze_profile(ze_ctx* c, int on) {
+    if (!c) return ZE_EINVAL;
+    if (on) {
+        for (hipEvent_t& e : c->ev)
+            if (!e) ZE_HIP(hipEventCreate(&e));
+    }
+    c->prof = on != 0;
+    return ZE_OK;
+}
+
+ze_status ze_profile_read(ze_ctx* c, double* ms, long long* launches, int reset) {
+    if (!c) return ZE_EINVAL;
+    for (int p = 0; p < 4; ++p) {
+        if (ms) ms[p] = c->prof_ms[p];
+        if (launches) launches[p] = c->prof_n[p];
+        if (reset) {
+            c->prof_ms[p] = 0.0;
+            c->prof_n[p] = 0;
+        }
+    }
+    return ZE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations of libzeuler: the context layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "zeuler.h"
+
+// Records a HIP failure (message kept per thread for ze_last_error) and returns ZE_EHIP.
+ze_status ze_record_hip(hipError_t e, const char* what);
+
+#define ZE_HIP(call)                                         \
+    do {                                                     \
+        hipError_t ze_e_ = (call);                           \
+        if (ze_e_ != hipSuccess) return ze_record_hip(ze_e_, #call); \
+    } while (0)
+
+#define ZE_TRY(call)                                         \
+    do {                                                     \
+        ze_status ze_s_ = (call);                            \
+        if (ze_s_ != ZE_OK) return ze_s_;                    \
+    } while (0)
+
+// Offset of entry (r, c), c <= r, in a packed row-major lower triangle.
+__host__ __device__ inline size_t tri_off(size_t r, size_t c) { return r * (r + 1) / 2 + c; }
+
+struct ze_ctx {
+    int N = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    // LDL^T factors of every Delta^m, packed lower-triangle row-major: the entry at
+    // (i+m, i) belongs to element i of diagonal m.
+    //   fac_l[i+m, i]    = l_{i-1}, the multiplier met when the forward sweep reaches element i
+    //                      (0 for i = 0, and for the excluded last element of m = 0),
+    //   fac_dinv[i+m, i] = 1 / D_i (0 for the excluded last element of m = 0).
+    double* fac_l = nullptr;
+    double* fac_dinv = nullptr;
+    // m = 0 pseudo-inverse: ubar = u - mean(u), u = B^{-1} 1 for the leading (N-1) block B
+    // (u_{N-1} = 0); and the two sums the solve kernel leaves for the diagonal fix-up.
+    double* ubar = nullptr;
+    double2* diagstat = nullptr;
+
+    // Step workspaces, N x N complex each.
+    double2* Wn = nullptr;   // copy of W_n
+    double2* F = nullptr;    // fixed-point iterate W~ (after the first evaluation)
+    double2* P = nullptr;    // stream matrix
+    double2* A = nullptr;    // A = P W~
+    double* rowpart = nullptr;  // ntile64 x N partial row sums of |F - W~|
+    double* blockmax = nullptr; // per-block maxima of the row sums
+    double* resid = nullptr;    // device scalar: infinity norm of F - W~
+    double* host_resid = nullptr;  // pinned host copy
+
+    // Optional per-phase timing (ze_profile).
+    bool prof = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double prof_ms[4] = {0, 0, 0, 0};
+    long long prof_n[4] = {0, 0, 0, 0};
+};
+
+// ---- kernel launchers (all asynchronous on `s`) ----
+
+// Stream solve P = Delta_N^+ W (both N x N, row-major, leading dimension N).
+hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s);
+
+// C = A B, all N x N complex (leading dimension N), FP64 MFMA.
+hipError_t launch_zgemm_f64(const double2* A, const double2* B, double2* C, int N, hipStream_t s);
+
+// Lower-triangle Q = A P with the fixed-point epilogue:
+//   F     = Wn + h/2 (A - A^H) + h^2/4 Q       (both triangles; may alias Wt)
+//   Wout  = Wt + h/2 (A - A^H) - h^2/4 Q       (both triangles)
+//   rowpart[X*N + r]  partial row sums of |F - Wt| (see the kernel for the slot layout)
+hipError_t launch_zgemm_lower_epilogue(const double2* A, const double2* P, const double2* Wn,
+                                       const double2* Wt, double2* F, double2* Wout,
+                                       double* rowpart, int N, double h, hipStream_t s);
+
+// resid = max_r sum_X rowpart[X*N + r]  (NaN propagates).
+hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, double* resid, int N,
+                               hipStream_t s);
+
+// out[0] = sum_ij X_ij Y_ji (complex), through `partial` (>= ze_trace_partials(N) doubles2).
+int ze_trace_partials(int N);
+hipError_t launch_trace_product(const double2* X, const double2* Y, double2* partial,
+                                double2* out, int N, hipStream_t s);
+// out[0] = sum_i X_ii.
+hipError_t launch_trace(const double2* X, double2* partial, double2* out, int N, hipStream_t s);
+
+// W = sum_lm i omega_lm T_lm; scratch as returned by ze_basis_scratch_bytes(N).
+size_t ze_basis_scratch_bytes(int N);
+hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch, int N,
+                                 hipStream_t s);

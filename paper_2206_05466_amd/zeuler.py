@@ -1,0 +1,198 @@
+"""ctypes binding of libzeuler.so (include/zeuler.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor arguments (device,
+dtype, shape, contiguity), passes their device pointers and raises on error codes.  Torch is
+used for device memory and streams only.  There is no fallback: without the built library
+(``python -m paper_2206_05466_amd.build``) every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzeuler.so")
+
+ZE_OK, ZE_EINVAL, ZE_ENOMEM, ZE_ENOTCONV, ZE_ENONFINITE, ZE_EHIP = range(6)
+PREC_FP64, PREC_SPLIT = 0, 1
+
+# Exported names and signatures, as declared in include/zeuler.h.
+_c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+_P_int, _P_double = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "ze_strerror": (ctypes.c_char_p, [_c_int]),
+    "ze_last_error": (ctypes.c_char_p, []),
+    "ze_create": (_c_int, [_c_int, _vp, ctypes.POINTER(_vp)]),
+    "ze_destroy": (_c_int, [_vp]),
+    "ze_size": (_c_int, [_vp]),
+    "ze_stream_solve": (_c_int, [_vp, _vp, _vp]),
+    "ze_isomp_step": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int, _c_int, _P_int, _P_double]),
+    "ze_isomp_run": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int, _c_int, _c_int, _P_int, _P_double]),
+    "ze_casimirs": (_c_int, [_vp, _vp, _c_int, _P_double]),
+    "ze_basis_assemble": (_c_int, [_vp, _vp, _vp]),
+    "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
+    "ze_profile": (_c_int, [_vp, _c_int]),
+    "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
+}
+
+PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
+
+_lib = None
+
+
+def load_library():
+    """Load libzeuler.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2206_05466_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class ZeulerError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        msg = lib.ze_strerror(status).decode()
+        extra = lib.ze_last_error().decode() if status == ZE_EHIP else ""
+        super().__init__(f"{where}: {msg}" + (f" ({extra})" if extra else ""))
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != ZE_OK:
+        raise ZeulerError(status, where)
+
+
+@dataclass
+class StepInfo:
+    iters: int
+    resid: float
+    converged: bool
+
+
+class Zeuler:
+    """One context of libzeuler for matrix size N on the current torch device and stream."""
+
+    def __init__(self, N: int, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libzeuler needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.N = int(N)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        self._ctx = ctypes.c_void_p()
+        _check(self.lib.ze_create(self.N, ctypes.c_void_p(st.cuda_stream), ctypes.byref(self._ctx)),
+               "ze_create")
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.ze_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- argument checks ------------------------------------------------------------
+    def _mat(self, X, name):
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.complex128:
+            raise TypeError(f"{name} must be a torch.complex128 tensor")
+        if X.device != self.device or not X.is_contiguous() or tuple(X.shape) != (self.N, self.N):
+            raise ValueError(f"{name} must be a contiguous ({self.N}, {self.N}) tensor on {self.device}")
+        return ctypes.c_void_p(X.data_ptr())
+
+    def empty(self):
+        import torch
+
+        return torch.empty((self.N, self.N), dtype=torch.complex128, device=self.device)
+
+    # -- calls ------------------------------------------------------------------------
+    def stream_solve(self, W, out=None):
+        """P = Delta_N^+ W (device tensors)."""
+        P = self.empty() if out is None else out
+        _check(self.lib.ze_stream_solve(self._ctx, self._mat(W, "W"), self._mat(P, "P")),
+               "ze_stream_solve")
+        return P
+
+    def zgemm(self, A, B, out=None, prec: int = PREC_FP64):
+        C = self.empty() if out is None else out
+        _check(self.lib.ze_zgemm(self._ctx, self._mat(A, "A"), self._mat(B, "B"), self._mat(C, "C"),
+                                 int(prec)), "ze_zgemm")
+        return C
+
+    def isomp_step(self, W, h: float, tol: float = 1e-12, maxit: int = 50,
+                   prec: int = PREC_FP64, allow_notconv: bool = True) -> StepInfo:
+        """One IsoMP step, W updated in place (W_n -> W_{n+1})."""
+        k = ctypes.c_int(0)
+        r = ctypes.c_double(0.0)
+        st = self.lib.ze_isomp_step(self._ctx, self._mat(W, "W"), float(h), float(tol), int(maxit),
+                                    int(prec), ctypes.byref(k), ctypes.byref(r))
+        if st == ZE_ENOTCONV and allow_notconv:
+            return StepInfo(k.value, r.value, False)
+        _check(st, "ze_isomp_step")
+        return StepInfo(k.value, r.value, True)
+
+    def isomp_run(self, W, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
+                  prec: int = PREC_FP64):
+        """nsteps IsoMP steps in place.  Returns (iterations, residuals) per step."""
+        its = (ctypes.c_int * max(nsteps, 1))()
+        res = (ctypes.c_double * max(nsteps, 1))()
+        st = self.lib.ze_isomp_run(self._ctx, self._mat(W, "W"), float(h), float(tol), int(maxit),
+                                   int(nsteps), int(prec), its, res)
+        if st not in (ZE_OK, ZE_ENOTCONV):
+            _check(st, "ze_isomp_run")
+        return list(its)[:nsteps], list(res)[:nsteps]
+
+    def casimirs(self, W, kmax: int) -> np.ndarray:
+        """[Tr W, Tr W^2, ..., Tr W^kmax] (complex128 numpy array)."""
+        out = (ctypes.c_double * (2 * kmax))()
+        _check(self.lib.ze_casimirs(self._ctx, self._mat(W, "W"), int(kmax), out), "ze_casimirs")
+        a = np.frombuffer(out, dtype=np.float64).copy()
+        return a[0::2] + 1j * a[1::2]
+
+    def basis_assemble(self, omega, out=None):
+        """W = sum_lm i omega_lm T_lm from flat coefficients omega[l*l+l+m] (length N*N)."""
+        import torch
+
+        om = torch.as_tensor(omega, dtype=torch.complex128).to(self.device).contiguous()
+        if om.numel() != self.N * self.N:
+            raise ValueError("omega must hold N*N coefficients")
+        W = self.empty() if out is None else out
+        _check(self.lib.ze_basis_assemble(self._ctx, ctypes.c_void_p(om.data_ptr()), self._mat(W, "W")),
+               "ze_basis_assemble")
+        return W
+
+    def profile(self, on: bool = True):
+        """Turn per-phase event timing of isomp_step on or off."""
+        _check(self.lib.ze_profile(self._ctx, int(bool(on))), "ze_profile")
+
+    def profile_read(self, reset: bool = False) -> dict:
+        """{phase: (total ms, launches)} accumulated since the last reset."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_longlong * 4)()
+        _check(self.lib.ze_profile_read(self._ctx, ms, n, int(bool(reset))), "ze_profile_read")
+        return {PHASES[i]: (ms[i], n[i]) for i in range(4)}

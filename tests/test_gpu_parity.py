@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by element.
+
+Tolerances (FP64 throughout):
+* stream solve: each diagonal is a forward/backward recurrence of length <= N with
+  multipliers below 1 in magnitude; relative error <~ N eps -> 1e-12 relative (max-norm).
+* products: FP64 MFMA accumulates K = N terms; |C - C_ref| <= ~N eps |A||B| -> 1e-13
+  relative to max|A| max|B| N; exact on small integers (all partial sums are integers
+  below 2^53).
+* IsoMP steps: the spec bar, 1e-10 relative Frobenius error after 10 steps, with the
+  same iteration counts (the residuals differ only by rounding).
+* basis assembly: the eigenvectors agree with LAPACK's to ~1e-13 (twisted factorisation
+  with the exact eigenvalue); W is compared at 1e-11 relative.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import omega_coeffs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_05466_amd import load_library
+
+    load_library()  # must load: no fallback
+    return torch.device("cuda", 0)
+
+
+def ctx(N):
+    from paper_2206_05466_amd import Zeuler
+
+    return Zeuler(N)
+
+
+def to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X, dtype=np.complex128)).cuda()
+
+
+def to_host(X):
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+def rand_skew(N, seed, traceless=True):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    W = X - X.conj().T
+    if traceless:
+        W -= np.trace(W) / N * np.eye(N)
+    return W
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------------ stream solve
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 63, 64, 65, 130, 257, 512])
+@pytest.mark.parametrize("traceless", [True, False])
+def test_stream_solve_parity(dev, N, traceless):
+    W = rand_skew(N, N, traceless)
+    with ctx(N) as z:
+        P = to_host(z.stream_solve(to_dev(W)))
+    P_ref = O.stream_solve(W)
+    assert relmax(P, P_ref) < 1e-12, (N, relmax(P, P_ref))
+    assert np.abs(P + P.conj().T).max() == 0.0
+
+
+def test_stream_solve_single_degree(dev):
+    N, l, m = 96, 7, 3
+    om = np.zeros(N * N, complex)
+    om[l * l + l + m] = 0.6 - 0.2j
+    om[l * l + l - m] = (-1) ** m * np.conj(om[l * l + l + m])
+    W = O.assemble(N, om)
+    with ctx(N) as z:
+        P = to_host(z.stream_solve(to_dev(W)))
+    assert np.abs(P + W / (l * (l + 1))).max() < 1e-14
+
+
+# ------------------------------------------------------------------ products
+@pytest.mark.parametrize("N", [1, 7, 64, 100, 128, 129, 200, 256])
+def test_zgemm_small_integers_exact(dev, N):
+    rng = np.random.default_rng(N)
+    A = rng.integers(-8, 9, (N, N)) + 1j * rng.integers(-8, 9, (N, N))
+    B = rng.integers(-8, 9, (N, N)) + 1j * rng.integers(-8, 9, (N, N))
+    with ctx(N) as z:
+        C = to_host(z.zgemm(to_dev(A), to_dev(B)))
+    assert np.array_equal(C, A @ B)
+
+
+@pytest.mark.parametrize("N", [64, 131, 384])
+def test_zgemm_random(dev, N):
+    rng = np.random.default_rng(N + 1)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    B = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    with ctx(N) as z:
+        C = to_host(z.zgemm(to_dev(A), to_dev(B)))
+    err = np.abs(C - A @ B).max() / (N * np.abs(A).max() * np.abs(B).max())
+    assert err < 1e-15, err
+
+
+# ------------------------------------------------------------------ IsoMP step
+def w0(N, seed, law="inv1", lmax=None):
+    return O.assemble(N, omega_coeffs(N, seed, law, lmax))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_isomp_ten_steps_n64(dev, seed):
+    N, h = 64, 0.01
+    W0 = w0(N, seed)
+    Wr, it_ref, res_ref = O.isomp_run(W0, h, 10, 1e-12, 50)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        its, res = z.isomp_run(Wd, h, 10, 1e-12, 50)
+        W = to_host(Wd)
+    assert its == it_ref, (its, it_ref)
+    assert max(res) < 1e-12
+    err = np.linalg.norm(W - Wr) / np.linalg.norm(Wr)
+    assert err < 1e-10, err
+    assert np.abs(W + W.conj().T).max() == 0.0
+    c0, c1 = O.casimirs(W0, 4), O.casimirs(W, 4)
+    rel = np.abs(c1 - c0) / np.abs(c0)
+    assert rel[1] < 1e-11 and rel[3] < 1e-11
+    assert abs(c1[2] - c0[2]) / np.linalg.norm(W0) ** 3 < 1e-11
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 65, 130, 200])
+def test_isomp_ragged_sizes(dev, N):
+    h = 0.02
+    W0 = w0(N, 5) if N > 1 else np.zeros((1, 1), complex)
+    W1, k, r = O.isomp_step(W0, h, 1e-13, 50)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        info = z.isomp_step(Wd, h, 1e-13, 50)
+        W = to_host(Wd)
+    assert info.converged and info.iters == k
+    assert np.linalg.norm(W - W1) <= 1e-12 * max(np.linalg.norm(W1), 1e-300) + 1e-300
+
+
+def test_isomp_one_step_n512(dev):
+    N, h = 512, 0.005
+    W0 = w0(N, 0)
+    W1, k, r = O.isomp_step(W0, h, 1e-12, 50)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        info = z.isomp_step(Wd, h, 1e-12, 50)
+        W = to_host(Wd)
+    assert info.iters == k and info.converged
+    assert np.linalg.norm(W - W1) / np.linalg.norm(W1) < 1e-12
+
+
+def test_isomp_fixed_iterations_and_errors(dev):
+    from paper_2206_05466_amd import ZeulerError
+
+    N = 32
+    W0 = w0(N, 3)
+    W1, k, r = O.isomp_step(W0, 0.05, 0.0, 3)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        info = z.isomp_step(Wd, 0.05, 0.0, 3)
+        assert info.iters == 3 and not info.converged
+        assert abs(info.resid - r) <= 1e-3 * r
+        assert np.linalg.norm(to_host(Wd) - W1) / np.linalg.norm(W1) < 1e-13
+        with pytest.raises(ZeulerError):
+            z.isomp_step(Wd, float("nan"), 1e-12, 5)
+        with pytest.raises(ZeulerError):
+            z.isomp_step(Wd, 0.1, 1e-12, 0)
+        bad = Wd.clone()
+        bad[3, 1] = float("nan")
+        with pytest.raises(ZeulerError, match="non-finite"):
+            z.isomp_step(bad, 0.1, 1e-12, 5)
+
+
+# ------------------------------------------------------------------ Casimirs
+@pytest.mark.parametrize("N,kmax", [(1, 3), (17, 5), (64, 8), (200, 4)])
+def test_casimirs_parity(dev, N, kmax):
+    W = w0(N, 7) if N > 1 else np.array([[0.3j]])
+    with ctx(N) as z:
+        c = z.casimirs(to_dev(W), kmax)
+    c_ref = O.casimirs(W, kmax)
+    scale = np.array([np.linalg.norm(W) ** k for k in range(1, kmax + 1)])
+    assert np.all(np.abs(c - c_ref) <= 1e-13 * N * scale + 1e-300), (c, c_ref)
+
+
+# ------------------------------------------------------------------ basis assembly
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 129, 256])
+def test_basis_assemble_parity(dev, N):
+    om = omega_coeffs(N, 11, "inv1")
+    with ctx(N) as z:
+        W = to_host(z.basis_assemble(om))
+    W_ref = O.assemble(N, om)
+    assert np.abs(W - W_ref).max() <= 1e-11 * max(np.abs(W_ref).max(), 1e-300), relmax(W, W_ref)
+    assert np.abs(W + W.conj().T).max() == 0.0
+
+
+def test_basis_single_elements(dev):
+    """Each single coefficient reproduces i T_lm (eigenvector of Delta_N, eq. (lap_prop))."""
+    N = 24
+    with ctx(N) as z:
+        for l in (0, 1, 5, 23):
+            for m in sorted({-l, 0, l // 2, l}):
+                om = np.zeros(N * N, complex)
+                om[l * l + l + m] = 1.0
+                W = to_host(z.basis_assemble(om))
+                assert np.abs(W - O.assemble(N, om)).max() < 1e-13

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point include/zeuler.h declares.
+
+CPU only: no call here reaches the GPU (ze_create with an invalid N fails before any HIP
+call; ze_strerror is a table lookup).
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2206_05466_amd as pkg
+from paper_2206_05466_amd import zeuler
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zeuler.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ze_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ze_create", "ze_destroy", "ze_stream_solve", "ze_isomp_step",
+                     "ze_casimirs", "ze_basis_assemble"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert sorted(zeuler.SIGNATURES) == declared_functions()
+
+
+def test_strerror_and_invalid_create_without_gpu():
+    lib = pkg.load_library()
+    assert lib.ze_strerror(zeuler.ZE_ENOTCONV).decode().startswith("fixed-point")
+    out = ctypes.c_void_p(123)
+    assert lib.ze_create(0, None, ctypes.byref(out)) == zeuler.ZE_EINVAL
+    assert out.value is None
+    assert lib.ze_create(70000, None, ctypes.byref(out)) == zeuler.ZE_EINVAL
+    assert lib.ze_create(16, None, None) == zeuler.ZE_EINVAL
+    assert lib.ze_size(None) == 0
+    assert lib.ze_destroy(None) == zeuler.ZE_OK
+    assert lib.ze_stream_solve(None, None, None) == zeuler.ZE_EINVAL
+    assert lib.ze_isomp_step(None, None, 0.1, 1e-12, 5, 0, None, None) == zeuler.ZE_EINVAL
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(zeuler, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(zeuler, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        zeuler.load_library()

@@ -81,3 +81,11 @@ def test_generator_reality_and_law():
     assert np.array_equal(om, omega_coeffs(N, 1, "inv1"))
     p = omega_coeffs(64, 0, "paper")
     assert np.all(p[: 4] == 0) and np.all(p[21 * 21:] == 0) and np.any(p[4:21 * 21] != 0)
+
+
+def test_truncated_assembly_matches_full():
+    N, L = 80, 12
+    om = omega_coeffs(N, 2, "inv1", lmax=L)
+    assert np.abs(O.assemble(N, om, lmax=L) - O.assemble(N, om)).max() < 1e-13
+    with pytest.raises(ValueError):
+        O.assemble(N, omega_coeffs(N, 2, "inv1"), lmax=L)
