@@ -52,9 +52,9 @@ const char* ze_last_error(void);
 /*
  * ze_create -- set up the quantised Laplacian for matrix size N (Sec. 3.2, eq. (delta_tria)):
  * the tridiagonal block Delta^m of every diagonal m = 0..N-1 is factored (LDL^T, FP64, on
- * the host) and uploaded, and the step's workspaces (about 4 padded N x N complex matrices)
+ * the host) and uploaded, and the step's workspaces (4 N x N complex matrices)
  * are allocated on the current HIP device.
- *   N       matrix size, 1 <= N <= 65536.
+ *   N       matrix size, 1 <= N <= 16384.
  *   stream  hipStream_t (as void*) all work of this context is queued on; NULL = default stream.
  *   out     receives the context.
  * Errors: ZE_EINVAL (N out of range, out NULL), ZE_ENOMEM, ZE_EHIP.  Synchronous.
@@ -119,8 +119,9 @@ ze_status ze_casimirs(ze_ctx* ctx, const void* W, int kmax, double* out);
 /*
  * ze_basis_assemble -- W = sum_{l,m} i omega_lm T_lm (eq. (W0)), the T_lm being the unit
  * eigenvectors of Delta^m for the eigenvalue l(l+1) (eq. (lap_prop)) placed on diagonal m
- * (Sec. 3.2), with T_{l,-m} = (-1)^m T_lm^H.  Eigenvector signs: the entry of largest
- * magnitude among indices 0..floor((N-m-1)/2) is positive.
+ * (Sec. 3.2), with T_{l,-m} = (-1)^m T_lm^H.  Eigenvector signs (the paper leaves them
+ * open): among the entries with index 0..floor((N-m-1)/2) whose magnitude is within a
+ * relative 1e-8 of the largest there, the one with the lowest index is positive.
  *   omega  device, N*N complex128 coefficients, omega_lm at index l*l + l + m.
  *   W      device, N x N complex128, fully written.
  * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Asynchronous.

@@ -11,9 +11,12 @@ Readings taken here:
 
 * l runs over m..N-1 on diagonal m (l = 0 is the identity direction on m = 0); the
   eigenvalues of Delta^m, in ascending order, are l(l+1) for l = m, m+1, ..., N-1;
-* each eigenvector has unit 2-norm (so T_lm has unit Frobenius norm), and its sign is fixed
-  by making the entry of largest magnitude among indices 0..floor((n-1)/2) positive (the
-  paper leaves the sign open; the first entry is no good, it underflows for large N);
+* each eigenvector has unit 2-norm (so T_lm has unit Frobenius norm).  The paper leaves its
+  sign open; here, among the entries with index 0..floor((n-1)/2) whose magnitude is within a
+  relative 1e-8 of the largest there, the one with the lowest index is made positive.  (The
+  first entry alone is no good: it underflows for large N.  The largest entry alone is no
+  good either: these blocks have eigenvectors with exactly equal magnitudes at different
+  indices, e.g. N = 8, l = 3, m = 0 at indices 0 and 2, with opposite signs.)
 * T_{l,-m} = (-1)^m T_lm^H, so W[i+m, i] = i sum_l omega_lm v^{lm}_i and
   W[i, i+m] = i (-1)^m sum_l omega_{l,-m} v^{lm}_i; real vorticity,
   omega_{l,-m} = (-1)^m conj(omega_lm), makes W skew-Hermitian;
@@ -24,6 +27,8 @@ import numpy as np
 from scipy.linalg import eigh_tridiagonal
 
 from .laplacian import delta_tridiag
+
+SIGN_TIE_REL = 1e-8  # magnitudes within this relative distance of the largest count as ties
 
 
 def eigvecs(N: int, m: int, count: int | None = None):
@@ -40,7 +45,8 @@ def eigvecs(N: int, m: int, count: int | None = None):
     else:
         w, V = eigh_tridiagonal(d, e, select="i", select_range=(0, count - 1))
     half = (n - 1) // 2 + 1
-    k = np.argmax(np.abs(V[:half, :]), axis=0)
+    a = np.abs(V[:half, :])
+    k = np.argmax(a >= (1.0 - SIGN_TIE_REL) * a.max(axis=0), axis=0)  # lowest such index
     sgn = np.sign(V[k, np.arange(V.shape[1])])
     sgn[sgn == 0] = 1.0
     return w, V * sgn

@@ -15,51 +15,6 @@ thread_local std::string g_last_error;
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-// LDL^T factors of every block Delta^m of eq. (delta_tria), packed row-major lower
-// triangle (entry (i+m, i) for element i of diagonal m), and ubar for the m = 0
-// pseudo-inverse.  Delta^m: d_i = 2 (s(2i+1+m) - i(i+m)), off-diagonal
-// e_i = -sqrt((i+m+1)(N-1-i-m)) sqrt((i+1)(N-1-i)), s = (N-1)/2.  Block m is symmetric
-// positive definite for m >= 1; for m = 0 only its leading (N-1) x (N-1) block is.
-void build_factors(int N, std::vector<double>& fl, std::vector<double>& fd,
-                   std::vector<double>& ubar) {
-    const size_t tot = tri_off(N, 0);
-    fl.assign(tot, 0.0);
-    fd.assign(tot, 0.0);
-    ubar.assign(N, 0.0);
-    const double s = 0.5 * (N - 1);
-    std::vector<double> D(N), L(N);
-    for (int m = 0; m < N; ++m) {
-        const int n = N - m;
-        const int nf = (m == 0) ? n - 1 : n;  // factored length
-        for (int i = 0; i < nf; ++i) {
-            const double d = 2.0 * (s * (2.0 * i + 1.0 + m) - (double)i * (double)(i + m));
-            if (i == 0) {
-                D[0] = d;
-            } else {
-                const double k = i - 1;
-                const double e = -std::sqrt((k + m + 1.0) * (N - 1.0 - k - m)) *
-                                 std::sqrt((k + 1.0) * (N - 1.0 - k));
-                L[i - 1] = e / D[i - 1];
-                D[i] = d - L[i - 1] * e;
-            }
-            const size_t po = tri_off(i + m, i);
-            fl[po] = (i == 0) ? 0.0 : L[i - 1];
-            fd[po] = 1.0 / D[i];
-        }
-        if (m == 0 && nf > 0) {
-            // u = B^{-1} 1 on the leading block with the same factors, u_{N-1} = 0.
-            std::vector<double> y(nf);
-            for (int i = 0; i < nf; ++i) y[i] = 1.0 - (i ? L[i - 1] * y[i - 1] : 0.0);
-            for (int i = 0; i < nf; ++i) y[i] /= D[i];
-            for (int i = nf - 2; i >= 0; --i) y[i] -= L[i] * y[i + 1];
-            double mean = 0.0;
-            for (int i = 0; i < nf; ++i) mean += y[i];
-            mean /= N;
-            for (int i = 0; i < N; ++i) ubar[i] = (i < nf ? y[i] : 0.0) - mean;
-        }
-    }
-}
-
 template <class T>
 ze_status dalloc(T** p, size_t count) {
     if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 256) != hipSuccess) {
@@ -104,8 +59,6 @@ ze_status ze_destroy(ze_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     dfree(c->fac_l);
     dfree(c->fac_dinv);
-    dfree(c->ubar);
-    dfree(c->diagstat);
     dfree(c->Wn);
     dfree(c->F);
     dfree(c->P);
@@ -123,7 +76,7 @@ ze_status ze_destroy(ze_ctx* c) {
 ze_status ze_create(int N, void* stream, ze_ctx** out) {
     if (!out) return ZE_EINVAL;
     *out = nullptr;
-    if (N < 1 || N > 65536) return ZE_EINVAL;
+    if (N < 1 || N > kMaxN) return ZE_EINVAL;
     ze_ctx* c = new ze_ctx();
     c->N = N;
     c->stream = reinterpret_cast<hipStream_t>(stream);
@@ -131,15 +84,13 @@ ze_status ze_create(int N, void* stream, ze_ctx** out) {
         delete c;
         return ze_record_hip(hipGetLastError(), "hipGetDevice");
     }
-    std::vector<double> fl, fd, ub;
-    build_factors(N, fl, fd, ub);
+    std::vector<double> fl, fd;
+    ze_build_factors(N, fl, fd);
     const size_t nn = (size_t)N * N;
     const int T = (N + 63) / 64;
     ze_status st = ZE_OK;
     if (st == ZE_OK) st = dalloc(&c->fac_l, fl.size());
     if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
-    if (st == ZE_OK) st = dalloc(&c->ubar, (size_t)N);
-    if (st == ZE_OK) st = dalloc(&c->diagstat, 2);
     if (st == ZE_OK) st = dalloc(&c->Wn, nn);
     if (st == ZE_OK) st = dalloc(&c->F, nn);
     if (st == ZE_OK) st = dalloc(&c->P, nn);
@@ -158,7 +109,6 @@ ze_status ze_create(int N, void* stream, ze_ctx** out) {
     }
     hipError_t e = hipMemcpy(c->fac_l, fl.data(), fl.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->fac_dinv, fd.data(), fd.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->ubar, ub.data(), ub.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         ze_destroy(c);
         return ze_record_hip(e, "hipMemcpy(factors)");

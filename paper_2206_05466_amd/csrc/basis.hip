@@ -19,8 +19,10 @@
 //   trailing sub-block).  A zero pivot is replaced by 1e-200, small enough to be exact in the
 //   limit and large enough that e^2 / pivot stays finite, so the next z is the finite limit.
 //
-// Each vector is normalised to unit 2-norm and its sign fixed so that the entry of largest
-// magnitude among indices 0..floor((n-1)/2) is positive (first such index on ties).
+// Each vector is normalised to unit 2-norm.  Its sign: among the entries with index
+// 0..floor((n-1)/2) whose magnitude is within a relative 1e-8 of the largest there, the one
+// with the lowest index is made positive (these blocks have eigenvectors with exactly equal
+// magnitudes at different indices, so the largest entry alone does not fix the sign).
 //
 // Memory: the vectors of a batch of diagonals are kept in scratch as V_m[i][j] (row i,
 // column j = l - m), so the lanes of a wave (consecutive j) touch consecutive addresses at
@@ -33,6 +35,7 @@ namespace {
 
 constexpr double kTiny = 1e-200;
 constexpr double kSigma = 1e-3;
+constexpr double kSignTieRel = 1e-8;  // magnitudes this close to the largest count as ties
 
 __device__ inline double nz(double x) { return x == 0.0 ? kTiny : x; }
 
@@ -106,13 +109,9 @@ __global__ __launch_bounds__(64) void basis_vectors_kernel(int N, int m_begin, i
         }
     }
     // Twisted solve with the exact lambda: downward from r (uses D+ in v), upward (D- in sp).
-    double ss = 1.0, zbest = 1.0, abest = 1.0;
-    int ibest = r;
-    const int half = (n - 1) / 2;  // sign rule looks at indices 0..half
-    if (r > half) {
-        abest = -1.0;
-        ibest = n;
-    }
+    const int half = (n - 1) / 2;  // the sign rule looks at indices 0..half
+    double ss = 1.0;               // sum of squares, z_r = 1 included
+    double amax = (r <= half) ? 1.0 : 0.0;
     double z = 1.0;
     for (int i = n - 1; i >= 0; --i) {
         if (act && i < r) {
@@ -121,12 +120,7 @@ __global__ __launch_bounds__(64) void basis_vectors_kernel(int N, int m_begin, i
             z = -(e / nz(v[o])) * z;
             v[o] = z;
             ss += z * z;
-            const double az = fabs(z);
-            if (i <= half && (az > abest || (az == abest && i < ibest))) {
-                abest = az;
-                ibest = i;
-                zbest = z;
-            }
+            if (i <= half) amax = fmax(amax, fabs(z));
         }
     }
     if (act) v[(size_t)r * n + j] = 1.0;
@@ -138,15 +132,23 @@ __global__ __launch_bounds__(64) void basis_vectors_kernel(int N, int m_begin, i
             z = -(e / nz(sp[o])) * z;
             v[o] = z;
             ss += z * z;
-            const double az = fabs(z);
-            if (i <= half && (az > abest || (az == abest && i < ibest))) {
-                abest = az;
-                ibest = i;
-                zbest = z;
+            if (i <= half) amax = fmax(amax, fabs(z));
+        }
+    }
+    // Sign: the lowest index i <= half with |z_i| >= (1 - kSignTieRel) max |z_0..z_half|.
+    const double thr = (1.0 - kSignTieRel) * amax;
+    double sgn = 1.0;
+    bool found = false;
+    for (int i = 0; i <= half; ++i) {
+        if (act && !found) {
+            const double zi = v[(size_t)i * n + j];
+            if (fabs(zi) >= thr) {
+                sgn = zi < 0.0 ? -1.0 : 1.0;
+                found = true;
             }
         }
     }
-    const double scale = (zbest < 0.0 ? -1.0 : 1.0) / sqrt(ss);
+    const double scale = sgn / sqrt(ss);
     for (int i = 0; i < n; ++i)
         if (act) v[(size_t)i * n + j] *= scale;
 }

@@ -13,7 +13,7 @@
 // reads one component of one B element, with a lane-constant sign.
 //
 // MFMA operand layout (16x16x4, f64): lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator register r of lane l holds D[4*(l/16) + r][l%16].
+// accumulator register r of lane l holds D[l/16 + 4*r][l%16].
 
 #include "internal.h"
 
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
             if (cc >= 2 * N) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wrow + mt * 16 + 4 * q + r;
+                const int row = row0 + wrow + mt * 16 + q + 4 * r;
                 if (row < N) Cd[(size_t)row * ld + cc] = acc[mt][nt][r];
             }
         }
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
         for (int nt = 0; nt < C::NT; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int lr = wrow + mt * 16 + 4 * q + r;            // local row
+                const int lr = wrow + mt * 16 + q + 4 * r;            // local row
                 const int lcc = wcc + nt * 16 + l16;                 // local real column
                 const int lc = lcc >> 1;                              // local complex column
                 const int R = row0 + lr, c = col0 + lc;

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "zeuler.h"
 
@@ -31,17 +32,12 @@ struct ze_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
 
-    // LDL^T factors of every Delta^m, packed lower-triangle row-major: the entry at
-    // (i+m, i) belongs to element i of diagonal m.
-    //   fac_l[i+m, i]    = l_{i-1}, the multiplier met when the forward sweep reaches element i
-    //                      (0 for i = 0, and for the excluded last element of m = 0),
-    //   fac_dinv[i+m, i] = 1 / D_i (0 for the excluded last element of m = 0).
+    // LDL^T factors of every Delta^m in the stream solve's workgroup order (diagonal m = 0
+    // first, then the pairs (m, N-m), m = 1..N/2, each at offset m*N): per element, the
+    // multiplier met when the forward sweep reaches it (0 at the first element of each
+    // diagonal) and 1/D (0 for the excluded last element of the singular m = 0 block).
     double* fac_l = nullptr;
     double* fac_dinv = nullptr;
-    // m = 0 pseudo-inverse: ubar = u - mean(u), u = B^{-1} 1 for the leading (N-1) block B
-    // (u_{N-1} = 0); and the two sums the solve kernel leaves for the diagonal fix-up.
-    double* ubar = nullptr;
-    double2* diagstat = nullptr;
 
     // Step workspaces, N x N complex each.
     double2* Wn = nullptr;   // copy of W_n
@@ -59,6 +55,12 @@ struct ze_ctx {
     double prof_ms[4] = {0, 0, 0, 0};
     long long prof_n[4] = {0, 0, 0, 0};
 };
+
+// Largest matrix size a context accepts.
+constexpr int kMaxN = 16384;
+
+// Host: the factors held in ze_ctx::fac_l / fac_dinv (N (N+1) / 2 entries each).
+void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd);
 
 // ---- kernel launchers (all asynchronous on `s`) ----
 

@@ -1,107 +1,279 @@
 // Stream solve P = Delta_N^+ W: one tridiagonal system per matrix diagonal (Sec. 3.3,
 // eq. (sub_tria_W)), with the LDL^T factors of the blocks Delta^m of eq. (delta_tria).
 //
-// Layout and parallelisation.  Lane m of the grid owns diagonal m (entries (i+m, i)).  The
-// sweeps advance row by row: at row t every active lane m handles its element i = t - m,
-// i.e. entry (t, t - m), so the 64 lanes of a wave read 64 neighbouring entries of one
-// matrix row -- a coalesced access -- and the packed factors are stored in the same
-// row-major lower-triangle order.  Forward sweep (rows ascending): y_i = b_i - l_{i-1} y_{i-1},
-// z_i = y_i / D_i, with z kept in P as scratch.  Backward sweep (rows descending):
-// x_i = z_i - l_i x_{i+1}; the lower triangle gets -x (the Laplacian is -Delta^m on diagonal
-// m), the upper triangle conj(x) (P skew-Hermitian).
+// Work split.  Diagonal m has N - m entries, so diagonals m and N - m together have exactly
+// N; workgroup w >= 1 solves that pair (w = m), workgroup 0 solves m = 0 alone and, for even
+// N, workgroup N/2 the single middle diagonal.  The pair is laid out as one "virtual" array
+// of length L <= N, diagonal m first: element k is (m, i = k) for k < N - m, else
+// (N - m, i = k - (N - m)).  The factors are stored in the same order, so each workgroup
+// reads its factors contiguously; the multiplier stored at the first element of each
+// diagonal is 0, which keeps the two recurrences apart.
 //
-// Diagonal m = 0 (singular block, pseudo-inverse): the factors cover only the leading
-// (N-1) block and zero the last element, so the sweeps return x_raw = B^{-1} b[0..N-2]
-// (x_raw[N-1] = 0) for the raw right-hand side; lane 0 also sums tr = sum_i b_i and
-// sum_i x_raw_i.  The fix-up kernel then applies, by linearity,
-//   x = x_raw - (tr/N) ubar - mean(x_raw),    ubar = B^{-1} 1 - mean(B^{-1} 1),
-// which equals removing tr/N from the right-hand side and subtracting the mean.
+// Within a workgroup, thread t owns the chunk k = t*C .. t*C + C - 1 in registers.  Each
+// sweep is a first-order linear recurrence, solved as: local sweep of every chunk with a
+// zero carry, a block scan of the chunks' affine maps x -> G x + Y (G the product of the
+// chunk's factors, Y its zero-carry result), then a local fix-up with the scanned carry.
+//   forward:  y_k = b_k - l_k y_{k-1}            (l_k: multiplier met at element k)
+//             z_k = y_k / D_k
+//   backward: x_k = z_k - l_{k+1} x_{k+1}
+// The lower triangle gets -x (the Laplacian is -Delta^m on diagonal m), the upper conj(x)
+// (P skew-Hermitian).  The multipliers satisfy |l| <= 1, so the chunk products stay bounded.
+//
+// Diagonal m = 0 is singular (pseudo-inverse): workgroup 0 removes tr(W)/N from the
+// right-hand side first, its factors cover the leading (N-1) block only (1/D = 0 on the last
+// element, so x_{N-1} = 0), and the mean of x is subtracted at the end.
+//
+// XCD-aware order: the hardware sends workgroup b to XCD b % 8; workgroups are renumbered so
+// that each XCD takes a contiguous range of pairs.  Neighbouring diagonals touch neighbouring
+// entries of the same matrix rows, so their scattered accesses meet in the XCD's L2.
+
+#include <cmath>
+#include <vector>
 
 #include "internal.h"
 
 namespace {
 
-constexpr int kSolveLanes = 64;
-
-__global__ __launch_bounds__(kSolveLanes) void stream_solve_kernel(
-    const double2* __restrict__ W, double2* __restrict__ P, const double* __restrict__ fl,
-    const double* __restrict__ fd, int N, double2* __restrict__ diagstat) {
-    const int m0 = blockIdx.x * kSolveLanes;
-    const int m = m0 + threadIdx.x;
-    const bool lane_ok = m < N;
-    const size_t ldN = (size_t)N;
-
-    // Forward sweep.
-    double yr = 0.0, yi = 0.0, tr_r = 0.0, tr_i = 0.0;
-    for (int t = m0; t < N; ++t) {
-        if (lane_ok && m <= t) {
-            const int i = t - m;
-            const size_t off = (size_t)t * ldN + i;
-            const size_t po = tri_off(t, i);
-            const double2 b = W[off];
-            const double l = fl[po];
-            const double dv = fd[po];
-            yr = b.x - l * yr;
-            yi = b.y - l * yi;
-            P[off] = make_double2(yr * dv, yi * dv);
-            if (m == 0) {
-                tr_r += b.x;
-                tr_i += b.y;
-            }
+template <int T>
+__device__ inline void block_scan_affine(double& G, double2& Y, bool reverse, double* sG,
+                                         double2* sY) {
+    // Inclusive scan over threads (in reverse thread order if `reverse`) of the affine maps
+    // f_t(x) = G_t x + Y_t composed in scan order: earlier maps are applied first.
+    const int t = threadIdx.x;
+    for (int off = 1; off < T; off <<= 1) {
+        sG[t] = G;
+        sY[t] = Y;
+        __syncthreads();
+        const int src = reverse ? t + off : t - off;
+        if (src >= 0 && src < T) {
+            const double pg = sG[src];
+            const double2 py = sY[src];
+            Y.x += G * py.x;
+            Y.y += G * py.y;
+            G *= pg;
         }
-    }
-
-    // Backward sweep.
-    double xr = 0.0, xi = 0.0, lnext = 0.0, sx_r = 0.0, sx_i = 0.0;
-    for (int t = N - 1; t >= m0; --t) {
-        if (lane_ok && m <= t) {
-            const int i = t - m;
-            const size_t off = (size_t)t * ldN + i;
-            const double2 z = P[off];
-            xr = z.x - lnext * xr;
-            xi = z.y - lnext * xi;
-            lnext = fl[tri_off(t, i)];
-            P[off] = make_double2(-xr, -xi);
-            if (m > 0) {
-                P[(size_t)i * ldN + t] = make_double2(xr, -xi);
-            } else {
-                sx_r += xr;
-                sx_i += xi;
-            }
-        }
-    }
-    if (m == 0) {
-        diagstat[0] = make_double2(tr_r, tr_i);
-        diagstat[1] = make_double2(sx_r, sx_i);
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void stream_solve_diag_fixup(double2* __restrict__ P,
-                                                                const double* __restrict__ ubar,
-                                                                const double2* __restrict__ diagstat,
-                                                                int N) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double invN = 1.0 / (double)N;
-    const double2 tr = diagstat[0];
-    const double2 sx = diagstat[1];
-    const double u = ubar[i];
-    double2 p = P[(size_t)i * N + i];  // holds -x_raw_i
-    p.x += tr.x * invN * u + sx.x * invN;
-    p.y += tr.y * invN * u + sx.y * invN;
-    P[(size_t)i * N + i] = p;
+template <int T>
+__device__ inline double2 block_sum(double2 v, double2* s) {
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int h = T / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s[t].x += s[t + h].x;
+            s[t].y += s[t + h].y;
+        }
+        __syncthreads();
+    }
+    const double2 r = s[0];
+    __syncthreads();
+    return r;
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(T) void stream_solve_kernel(const double2* __restrict__ W,
+                                                         double2* __restrict__ P,
+                                                         const double* __restrict__ fl,
+                                                         const double* __restrict__ fd,
+                                                         int N, int nwg, int per) {
+    __shared__ double sG[T];
+    __shared__ double2 sY[T];
+    const int b = blockIdx.x;
+    const int w = (b & 7) * per + (b >> 3);
+    if (w >= nwg) return;  // uniform for the block
+
+    int m1, n1, m2;
+    if (w == 0) {
+        m1 = 0;
+        n1 = N;
+        m2 = -1;
+    } else {
+        m1 = w;
+        n1 = N - w;
+        m2 = (N - w != w) ? N - w : -1;
+    }
+    const int L = n1 + (m2 >= 0 ? w : 0);
+    const size_t base = (size_t)w * N;
+    const double* flw = fl + base;
+    const double* fdw = fd + base;
+    const int t = threadIdx.x;
+    const int k0 = t * C;
+
+    auto entry = [&](int k) -> size_t {  // matrix offset of virtual element k
+        const int m = k < n1 ? m1 : m2;
+        const int i = k < n1 ? k : k - n1;
+        return (size_t)(i + m) * N + i;
+    };
+
+    double2 v[C];
+    double l[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = k0 + c;
+        if (k < L) {
+            v[c] = W[entry(k)];
+            l[c] = flw[k];
+        } else {
+            v[c] = make_double2(0.0, 0.0);
+            l[c] = 0.0;
+        }
+    }
+
+    if (w == 0) {  // trace removal on the singular block (all L = N elements are diagonal 0)
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s.x += v[c].x;
+            s.y += v[c].y;
+        }
+        const double2 tr = block_sum<T>(s, sY);
+        const double ir = tr.x / N, ii = tr.y / N;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (k0 + c < L) {
+                v[c].x -= ir;
+                v[c].y -= ii;
+            }
+    }
+
+    // Forward sweep: local pass with zero carry.
+    double G = 1.0;
+    double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        y.x = v[c].x - l[c] * y.x;
+        y.y = v[c].y - l[c] * y.y;
+        G *= -l[c];
+        v[c] = y;
+    }
+    double2 Y = y;
+    block_scan_affine<T>(G, Y, false, sG, sY);
+    sY[t] = Y;  // inclusive: true y at the end of chunk t
+    __syncthreads();
+    const double2 cin = t > 0 ? sY[t - 1] : make_double2(0.0, 0.0);
+    __syncthreads();
+    double g = 1.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = k0 + c;
+        g *= -l[c];
+        const double dv = k < L ? fdw[k] : 0.0;
+        v[c].x = (v[c].x + g * cin.x) * dv;
+        v[c].y = (v[c].y + g * cin.y) * dv;
+    }
+
+    // Backward sweep: x_k = z_k - l_{k+1} x_{k+1}; local pass from the chunk end.
+    const double lend = (k0 + C < L) ? flw[k0 + C] : 0.0;
+    G = 1.0;
+    double2 x = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        const double ln = (c == C - 1) ? lend : l[c + 1];
+        x.x = v[c].x - ln * x.x;
+        x.y = v[c].y - ln * x.y;
+        G *= -ln;
+        v[c] = x;
+    }
+    Y = x;
+    block_scan_affine<T>(G, Y, true, sG, sY);
+    sY[t] = Y;  // inclusive from the right: true x at the start of chunk t
+    __syncthreads();
+    const double2 cr = t + 1 < T ? sY[t + 1] : make_double2(0.0, 0.0);
+    __syncthreads();
+    g = 1.0;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        const double ln = (c == C - 1) ? lend : l[c + 1];
+        g *= -ln;
+        v[c].x += g * cr.x;
+        v[c].y += g * cr.y;
+    }
+
+    if (w == 0) {  // minimum-norm solution: subtract the mean
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s.x += v[c].x;
+            s.y += v[c].y;
+        }
+        const double2 sx = block_sum<T>(s, sY);
+        const double mr = sx.x / N, mi = sx.y / N;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            v[c].x -= mr;
+            v[c].y -= mi;
+        }
+    }
+
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = k0 + c;
+        if (k < L) {
+            const int m = k < n1 ? m1 : m2;
+            const int i = k < n1 ? k : k - n1;
+            P[(size_t)(i + m) * N + i] = make_double2(-v[c].x, -v[c].y);
+            if (m > 0) P[(size_t)i * N + i + m] = make_double2(v[c].x, -v[c].y);
+        }
+    }
+}
+
+template <int T, int C>
+hipError_t launch_tc(const ze_ctx* c, const double2* W, double2* P, hipStream_t s) {
+    const int N = c->N;
+    const int nwg = N / 2 + 1;
+    const int per = (nwg + 7) / 8;
+    hipLaunchKernelGGL((stream_solve_kernel<T, C>), dim3(8 * per), dim3(T), 0, s, W, P, c->fac_l,
+                       c->fac_dinv, N, nwg, per);
+    return hipGetLastError();
 }
 
 }  // namespace
 
+// Factors in the workgroup order described above (host, FP64).  Delta^m:
+// d_i = 2 (s (2i+1+m) - i (i+m)), e_i = -sqrt((i+m+1)(N-1-i-m)) sqrt((i+1)(N-1-i)).
+void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd) {
+    const size_t tot = (size_t)N * (N + 1) / 2;
+    fl.assign(tot, 0.0);
+    fd.assign(tot, 0.0);
+    const double s = 0.5 * (N - 1);
+    std::vector<double> D(N), Lm(N);
+    auto factor = [&](int m, size_t at) {
+        const int n = N - m;
+        const int nf = (m == 0) ? n - 1 : n;  // m = 0: leading (N-1) block only
+        for (int i = 0; i < nf; ++i) {
+            const double d = 2.0 * (s * (2.0 * i + 1.0 + m) - (double)i * (double)(i + m));
+            if (i == 0) {
+                D[0] = d;
+            } else {
+                const double k = i - 1;
+                const double e = -std::sqrt((k + m + 1.0) * (N - 1.0 - k - m)) *
+                                 std::sqrt((k + 1.0) * (N - 1.0 - k));
+                Lm[i - 1] = e / D[i - 1];
+                D[i] = d - Lm[i - 1] * e;
+            }
+            fl[at + i] = (i == 0) ? 0.0 : Lm[i - 1];
+            fd[at + i] = 1.0 / D[i];
+        }
+    };
+    factor(0, 0);
+    for (int w = 1; w <= N / 2; ++w) {
+        factor(w, (size_t)w * N);
+        if (N - w != w && N - w < N) factor(N - w, (size_t)w * N + (N - w));
+    }
+}
+
 hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s) {
     const int N = c->N;
-    const int nb = (N + kSolveLanes - 1) / kSolveLanes;
-    hipLaunchKernelGGL(stream_solve_kernel, dim3(nb), dim3(kSolveLanes), 0, s, W, P, c->fac_l,
-                       c->fac_dinv, N, c->diagstat);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(stream_solve_diag_fixup, dim3((N + 255) / 256), dim3(256), 0, s, P,
-                       c->ubar, c->diagstat, N);
-    return hipGetLastError();
+    if (N <= 64) return launch_tc<64, 1>(c, W, P, s);
+    if (N <= 128) return launch_tc<128, 1>(c, W, P, s);
+    if (N <= 256) return launch_tc<256, 1>(c, W, P, s);
+    if (N <= 512) return launch_tc<256, 2>(c, W, P, s);
+    if (N <= 1024) return launch_tc<256, 4>(c, W, P, s);
+    if (N <= 2048) return launch_tc<256, 8>(c, W, P, s);
+    if (N <= 4096) return launch_tc<256, 16>(c, W, P, s);
+    if (N <= 8192) return launch_tc<512, 16>(c, W, P, s);
+    return launch_tc<1024, 16>(c, W, P, s);
 }

@@ -46,7 +46,7 @@ def test_strerror_and_invalid_create_without_gpu():
     out = ctypes.c_void_p(123)
     assert lib.ze_create(0, None, ctypes.byref(out)) == zeuler.ZE_EINVAL
     assert out.value is None
-    assert lib.ze_create(70000, None, ctypes.byref(out)) == zeuler.ZE_EINVAL
+    assert lib.ze_create(16385, None, ctypes.byref(out)) == zeuler.ZE_EINVAL
     assert lib.ze_create(16, None, None) == zeuler.ZE_EINVAL
     assert lib.ze_size(None) == 0
     assert lib.ze_destroy(None) == zeuler.ZE_OK

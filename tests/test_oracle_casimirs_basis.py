@@ -62,8 +62,18 @@ def test_sign_rule_and_eigvals():
             l = np.arange(m, N)
             assert np.abs(w - l * (l + 1)).max() < 1e-11 * N * N
             half = (n - 1) // 2 + 1
-            k = np.argmax(np.abs(V[:half]), axis=0)
-            assert np.all(V[k, np.arange(n)] > 0)
+            a = np.abs(V[:half])
+            for j in range(n):
+                k = np.nonzero(a[:, j] >= (1 - 1e-8) * a[:, j].max())[0][0]
+                assert V[k, j] > 0
+
+
+def test_sign_rule_exact_tie():
+    """N = 8, l = 3, m = 0: |v_0| = |v_2| exactly (opposite signs); the lowest index wins."""
+    _, V = O.eigvecs(8, 0)
+    v = V[:, 3]
+    assert abs(abs(v[0]) - abs(v[2])) < 1e-15 and v[0] * v[2] < 0
+    assert v[0] > 0
 
 
 def test_generator_reality_and_law():
