@@ -65,6 +65,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->A);
     dfree(c->rowpart);
     dfree(c->blockmax);
+    dfree(c->gemm_part);
     dfree(c->resid);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
     for (hipEvent_t e : c->ev)
@@ -88,7 +89,15 @@ ze_status ze_create(int N, void* stream, ze_ctx** out) {
     ze_build_factors(N, fl, fd);
     const size_t nn = (size_t)N * N;
     const int T = (N + 63) / 64;
+    {
+        hipError_t ce = ze_gemm_capacity(&c->cap_full, &c->cap_low);
+        if (ce != hipSuccess) {
+            delete c;
+            return ze_record_hip(ce, "ze_gemm_capacity");
+        }
+    }
     ze_status st = ZE_OK;
+    if (st == ZE_OK) st = dalloc(&c->gemm_part, ze_gemm_part_bytes(c->cap_full, c->cap_low) / sizeof(double));
     if (st == ZE_OK) st = dalloc(&c->fac_l, fl.size());
     if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
     if (st == ZE_OK) st = dalloc(&c->Wn, nn);
@@ -126,8 +135,8 @@ ze_status ze_stream_solve(ze_ctx* c, const void* W, void* P) {
 ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     if (!c || !A || !B || !C || C == A || C == B) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
-    ZE_HIP(launch_zgemm_f64(static_cast<const double2*>(A), static_cast<const double2*>(B),
-                            static_cast<double2*>(C), c->N, c->stream));
+    ZE_HIP(launch_zgemm_f64(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
+                            static_cast<double2*>(C), c->stream));
     return ZE_OK;
 }
 
@@ -148,9 +157,9 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
         if (prof) ZE_HIP(hipEventRecord(c->ev[0], s));
         ZE_HIP(launch_stream_solve(c, Wt, c->P, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[1], s));
-        ZE_HIP(launch_zgemm_f64(c->P, Wt, c->A, N, s));
+        ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
-        ZE_HIP(launch_zgemm_lower_epilogue(c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, N, h, s));
+        ZE_HIP(launch_zgemm_lower_epilogue(c, c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
         ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
@@ -206,7 +215,7 @@ ze_status ze_casimirs(ze_ctx* c, const void* W, int kmax, double* out) {
     if (st == ZE_OK) st = dalloc(&dres, (size_t)kmax);
     hipError_t e = hipSuccess;
     for (int a = 2; a <= hp && st == ZE_OK && e == hipSuccess; ++a)
-        e = launch_zgemm_f64(pw[a - 1], pw[1], pw[a], N, c->stream);
+        e = launch_zgemm_f64(c, pw[a - 1], pw[1], pw[a], c->stream);
     for (int k = 1; k <= kmax && st == ZE_OK && e == hipSuccess; ++k) {
         if (k == 1) {
             e = launch_trace(pw[1], partial, dres, N, c->stream);

@@ -119,11 +119,12 @@ __device__ inline void compute_stage(const double* __restrict__ st, int wrow, in
     }
 }
 
-// acc += A[row0:row0+BM, :] * B[:, col0:col0+BNC] over the full K, double-buffered in LDS.
+// acc = A[row0:row0+BM, K range] * B[K range, col0:col0+BNC] for the K stages [kb, ke),
+// double-buffered in LDS.
 template <class C>
 __device__ inline void mainloop(const double2* __restrict__ A, int lda, int row0, int M,
                                 const double2* __restrict__ B, int ldb, int col0, int Nc, int K,
-                                double* smem, d4 (&acc)[C::MT][C::NT]) {
+                                int kb, int ke, double* smem, d4 (&acc)[C::MT][C::NT]) {
     const int wave = threadIdx.x >> 6;
     const int wrow = (wave / C::WAVES_N) * C::WM;
     const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
@@ -131,34 +132,75 @@ __device__ inline void mainloop(const double2* __restrict__ A, int lda, int row0
     for (int mt = 0; mt < C::MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < C::NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    if (kb >= ke) return;
 
-    const int nk = (K + kBK - 1) / kBK;
     double2 ra[C::A_LOADS], rb[C::B_LOADS];
-    load_stage<C>(A, lda, row0, M, B, ldb, col0, Nc, K, 0, ra, rb);
+    load_stage<C>(A, lda, row0, M, B, ldb, col0, Nc, K, kb * kBK, ra, rb);
     store_stage<C>(smem, ra, rb);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const bool more = kt + 1 < nk;
+    for (int kt = kb; kt < ke; ++kt) {
+        const bool more = kt + 1 < ke;
+        const int buf = (kt - kb) & 1;
         if (more) load_stage<C>(A, lda, row0, M, B, ldb, col0, Nc, K, (kt + 1) * kBK, ra, rb);
-        compute_stage<C>(smem + (kt & 1) * C::STAGE, wrow, wcc, acc);
-        if (more) store_stage<C>(smem + ((kt + 1) & 1) * C::STAGE, ra, rb);
+        compute_stage<C>(smem + buf * C::STAGE, wrow, wcc, acc);
+        if (more) store_stage<C>(smem + (buf ^ 1) * C::STAGE, ra, rb);
         __syncthreads();
     }
+}
+
+// Split-K partial accumulators, one block's registers in thread-major order.
+template <class C>
+__device__ inline void store_partial(double* __restrict__ part, const d4 (&acc)[C::MT][C::NT]) {
+#pragma unroll
+    for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[((mt * C::NT + nt) * 4 + r) * kThreads + threadIdx.x] = acc[mt][nt][r];
+}
+
+template <class C>
+__device__ inline void sum_partials(const double* __restrict__ part, int S,
+                                    d4 (&acc)[C::MT][C::NT]) {
+    constexpr int PS = C::MT * C::NT * 4 * kThreads;
+#pragma unroll
+    for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < C::NT; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[mt][nt][r] += part[(size_t)s * PS + ((mt * C::NT + nt) * 4 + r) * kThreads + threadIdx.x];
+}
+
+// Work split of one launch: tiles [0, full) whole, one block each; tiles [full, full + tail)
+// split into S ranges of K stages (blocks full + t*S + s), whose partial sums a fix-up kernel
+// adds in a fixed order.  The split only covers the last, partial round of tiles.
+struct Split {
+    int full, tail, S;
+};
+
+Split make_split(int ntiles, int nk, int cap) {
+    const int rounds = ntiles / cap, rem = ntiles % cap;
+    if (rem == 0) return {ntiles, 0, 1};
+    int S = cap / rem;
+    const int smax = nk / 8 > 1 ? nk / 8 : 1;  // at least 8 stages (64 complex k) per range
+    if (S > smax) S = smax;
+    if (S <= 1) return {ntiles, 0, 1};
+    return {rounds * cap, rem, S};
 }
 
 // ---------------------------------------------------------------- full product
 using FullCfg = Cfg<128, 64, 64, 32>;
 
-__global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __restrict__ A,
-                                                             const double2* __restrict__ B,
-                                                             double2* __restrict__ Cm, int N) {
+__device__ inline void store_full_tile(const d4 (&acc)[FullCfg::MT][FullCfg::NT], double2* Cm,
+                                       int N, int row0, int col0) {
     using C = FullCfg;
-    __shared__ double smem[2 * C::STAGE];
-    const int row0 = blockIdx.y * C::BM;
-    const int col0 = blockIdx.x * C::BNC;
-    d4 acc[C::MT][C::NT];
-    mainloop<C>(A, N, row0, N, B, N, col0, N, N, smem, acc);
-
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wrow = (wave / C::WAVES_N) * C::WM;
     const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
@@ -179,11 +221,49 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
         }
 }
 
+__global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __restrict__ A,
+                                                             const double2* __restrict__ B,
+                                                             double2* __restrict__ Cm, int N,
+                                                             int tiles_n, int full, int S,
+                                                             double* __restrict__ part) {
+    using C = FullCfg;
+    __shared__ double smem[2 * C::STAGE];
+    const int nk = (N + kBK - 1) / kBK;
+    const int b = blockIdx.x;
+    int tile, kb = 0, ke = nk;
+    if (b < full) {
+        tile = b;
+    } else {
+        const int e = b - full, s = e % S;
+        tile = full + e / S;
+        kb = (int)((long long)s * nk / S);
+        ke = (int)((long long)(s + 1) * nk / S);
+    }
+    const int row0 = (tile / tiles_n) * C::BM;
+    const int col0 = (tile % tiles_n) * C::BNC;
+    d4 acc[C::MT][C::NT];
+    mainloop<C>(A, N, row0, N, B, N, col0, N, N, kb, ke, smem, acc);
+    if (b < full)
+        store_full_tile(acc, Cm, N, row0, col0);
+    else
+        store_partial<C>(part + (size_t)(b - full) * (C::MT * C::NT * 4 * kThreads), acc);
+}
+
+__global__ __launch_bounds__(kThreads) void zgemm_f64_fixup(double2* __restrict__ Cm, int N,
+                                                            int tiles_n, int full, int S,
+                                                            const double* __restrict__ part) {
+    using C = FullCfg;
+    const int tile = full + blockIdx.x;
+    d4 acc[C::MT][C::NT];
+    sum_partials<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads), S, acc);
+    store_full_tile(acc, Cm, N, (tile / tiles_n) * C::BM, (tile % tiles_n) * C::BNC);
+}
+
 // ---------------------------------------------------------------- lower product + epilogue
 using LowCfg = Cfg<64, 64, 32, 32>;
 constexpr int kTile = 64;  // square complex tile of the lower-triangle product
 
-// Block b of the lower-triangle grid -> tile (I, J), I >= J, b = I (I+1)/2 + J.
+// Tile index b of the lower triangle -> (I, J), I >= J, b = I (I+1)/2 + J.
 __device__ inline void lower_tile(int b, int& I, int& J) {
     int i = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((i + 1) * (i + 2) / 2 <= b) ++i;
@@ -192,24 +272,23 @@ __device__ inline void lower_tile(int b, int& I, int& J) {
     J = b - i * (i + 1) / 2;
 }
 
+// Epilogue of tile (I, J) of Q = A P (lower triangle, I >= J), acc in MFMA layout:
+//   F    = Wn + h/2 (A - A^H) + h^2/4 Q,    Wout = Wt + h/2 (A - A^H) - h^2/4 Q,
+// both written to the lower entries and mirrored (-conj) to the upper ones, Re Q_RR := 0.
 // Row-sum slots: rowpart[X*N + r] for tile-column X and row r.  Tile (I, J), I > J, writes
 // the row sums of its |F - W~| entries to slots (J, rows of I) and their column sums (the
 // mirrored upper entries, which lie in the rows of J) to slots (I, rows of J); a diagonal
 // tile (I, I) writes the full row sums of its rows to (I, rows of I).  Every slot with r < N
 // is written exactly once, so the reduction is deterministic.
-__global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
-    const double2* __restrict__ Am, const double2* __restrict__ Pm, const double2* __restrict__ Wn,
-    const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
-    int N, double h) {
+__device__ inline void lower_epilogue(const d4 (&acc)[LowCfg::MT][LowCfg::NT], int I, int J,
+                                      const double2* __restrict__ Am,
+                                      const double2* __restrict__ Wn, const double2* Wt,
+                                      double2* F, double2* __restrict__ Wout,
+                                      double* __restrict__ rowpart, int N, double h,
+                                      double* absd) {
     using C = LowCfg;
-    __shared__ double smem[2 * C::STAGE > kTile * kTile ? 2 * C::STAGE : kTile * kTile];
-    int I, J;
-    lower_tile(blockIdx.x, I, J);
     const int row0 = I * kTile;
     const int col0 = J * kTile;
-    d4 acc[C::MT][C::NT];
-    mainloop<C>(Am, N, row0, N, Pm, N, col0, N, N, smem, acc);
-
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wrow = (wave / C::WAVES_N) * C::WM;
     const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
@@ -222,7 +301,6 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
     double* Wod = reinterpret_cast<double*>(Wout);
     const size_t ld = 2 * (size_t)N;
     const double h2 = 0.5 * h, h4 = 0.25 * h * h;
-    double* absd = smem;  // [kTile][kTile] |F - W~| of this tile (lower part), reuses staging LDS
 
 #pragma unroll
     for (int mt = 0; mt < C::MT; ++mt)
@@ -230,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
         for (int nt = 0; nt < C::NT; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int lr = wrow + mt * 16 + q + 4 * r;            // local row
+                const int lr = wrow + mt * 16 + q + 4 * r;           // local row
                 const int lcc = wcc + nt * 16 + l16;                 // local real column
                 const int lc = lcc >> 1;                              // local complex column
                 const int R = row0 + lr, c = col0 + lc;
@@ -279,6 +357,48 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
     }
 }
 
+constexpr int kLowSmem = 2 * LowCfg::STAGE > kTile * kTile ? 2 * LowCfg::STAGE : kTile * kTile;
+
+__global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
+    const double2* __restrict__ Am, const double2* __restrict__ Pm, const double2* __restrict__ Wn,
+    const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
+    int N, double h, int full, int S, double* __restrict__ part) {
+    using C = LowCfg;
+    __shared__ double smem[kLowSmem];
+    const int nk = (N + kBK - 1) / kBK;
+    const int b = blockIdx.x;
+    int tile, kb = 0, ke = nk;
+    if (b < full) {
+        tile = b;
+    } else {
+        const int e = b - full, s = e % S;
+        tile = full + e / S;
+        kb = (int)((long long)s * nk / S);
+        ke = (int)((long long)(s + 1) * nk / S);
+    }
+    int I, J;
+    lower_tile(tile, I, J);
+    d4 acc[C::MT][C::NT];
+    mainloop<C>(Am, N, I * kTile, N, Pm, N, J * kTile, N, N, kb, ke, smem, acc);
+    if (b < full)
+        lower_epilogue(acc, I, J, Am, Wn, Wt, F, Wout, rowpart, N, h, smem);
+    else
+        store_partial<C>(part + (size_t)(b - full) * (C::MT * C::NT * 4 * kThreads), acc);
+}
+
+__global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(
+    const double2* __restrict__ Am, const double2* __restrict__ Wn, const double2* Wt, double2* F,
+    double2* __restrict__ Wout, double* __restrict__ rowpart, int N, double h, int full, int S,
+    const double* __restrict__ part) {
+    using C = LowCfg;
+    __shared__ double smem[kTile * kTile];
+    int I, J;
+    lower_tile(full + blockIdx.x, I, J);
+    d4 acc[C::MT][C::NT];
+    sum_partials<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads), S, acc);
+    lower_epilogue(acc, I, J, Am, Wn, Wt, F, Wout, rowpart, N, h, smem);
+}
+
 // ---------------------------------------------------------------- residual reduction
 constexpr int kRedThreads = 256;
 
@@ -324,19 +444,52 @@ __global__ __launch_bounds__(kRedThreads) void max_final_kernel(const double* __
 
 }  // namespace
 
-hipError_t launch_zgemm_f64(const double2* A, const double2* B, double2* C, int N, hipStream_t s) {
-    dim3 grid((N + FullCfg::BNC - 1) / FullCfg::BNC, (N + FullCfg::BM - 1) / FullCfg::BM);
-    hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(kThreads), 0, s, A, B, C, N);
+size_t ze_gemm_part_bytes(int cap_full, int cap_low) {
+    const size_t a = (size_t)cap_full * FullCfg::MT * FullCfg::NT * 4 * kThreads;
+    const size_t b = (size_t)cap_low * LowCfg::MT * LowCfg::NT * 4 * kThreads;
+    return (a > b ? a : b) * sizeof(double);
+}
+
+hipError_t ze_gemm_capacity(int* cap_full, int* cap_low) {
+    int dev = 0, cus = 0, nf = 0, nl = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, zgemm_f64_kernel, kThreads, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, zgemm_lower_epilogue_kernel, kThreads, 0);
+    if (e != hipSuccess) return e;
+    *cap_full = (nf > 0 ? nf : 1) * cus;
+    *cap_low = (nl > 0 ? nl : 1) * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* Cm,
+                            hipStream_t s) {
+    const int N = c->N;
+    const int tiles_n = (N + FullCfg::BNC - 1) / FullCfg::BNC;
+    const int tiles = tiles_n * ((N + FullCfg::BM - 1) / FullCfg::BM);
+    const Split sp = make_split(tiles, (N + kBK - 1) / kBK, c->cap_full);
+    hipLaunchKernelGGL(zgemm_f64_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A, B,
+                       Cm, N, tiles_n, sp.full, sp.S, c->gemm_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sp.tail == 0) return e;
+    hipLaunchKernelGGL(zgemm_f64_fixup, dim3(sp.tail), dim3(kThreads), 0, s, Cm, N, tiles_n, sp.full,
+                       sp.S, c->gemm_part);
     return hipGetLastError();
 }
 
-hipError_t launch_zgemm_lower_epilogue(const double2* A, const double2* P, const double2* Wn,
-                                       const double2* Wt, double2* F, double2* Wout,
-                                       double* rowpart, int N, double h, hipStream_t s) {
+hipError_t launch_zgemm_lower_epilogue(const ze_ctx* c, const double2* A, const double2* P,
+                                       const double2* Wn, const double2* Wt, double2* F,
+                                       double2* Wout, double* rowpart, double h, hipStream_t s) {
+    const int N = c->N;
     const int T = (N + kTile - 1) / kTile;
-    const int nblocks = T * (T + 1) / 2;
-    hipLaunchKernelGGL(zgemm_lower_epilogue_kernel, dim3(nblocks), dim3(kThreads), 0, s, A, P,
-                       Wn, Wt, F, Wout, rowpart, N, h);
+    const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low);
+    hipLaunchKernelGGL(zgemm_lower_epilogue_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads),
+                       0, s, A, P, Wn, Wt, F, Wout, rowpart, N, h, sp.full, sp.S, c->gemm_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sp.tail == 0) return e;
+    hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail), dim3(kThreads), 0, s, A, Wn, Wt, F, Wout,
+                       rowpart, N, h, sp.full, sp.S, c->gemm_part);
     return hipGetLastError();
 }
 

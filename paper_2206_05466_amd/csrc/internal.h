@@ -49,6 +49,10 @@ struct ze_ctx {
     double* resid = nullptr;    // device scalar: infinity norm of F - W~
     double* host_resid = nullptr;  // pinned host copy
 
+    // Products: concurrent-block capacities and the split-K partial buffer.
+    int cap_full = 0, cap_low = 0;
+    double* gemm_part = nullptr;
+
     // Optional per-phase timing (ze_profile).
     bool prof = false;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -67,16 +71,22 @@ void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd);
 // Stream solve P = Delta_N^+ W (both N x N, row-major, leading dimension N).
 hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s);
 
-// C = A B, all N x N complex (leading dimension N), FP64 MFMA.
-hipError_t launch_zgemm_f64(const double2* A, const double2* B, double2* C, int N, hipStream_t s);
+// Blocks of the two product kernels that fit on the device at once, and the bytes of the
+// split-K partial buffer (ze_ctx::gemm_part) those capacities need.
+hipError_t ze_gemm_capacity(int* cap_full, int* cap_low);
+size_t ze_gemm_part_bytes(int cap_full, int cap_low);
+
+// C = A B, all N x N complex (leading dimension N = c->N), FP64 MFMA.
+hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* C,
+                            hipStream_t s);
 
 // Lower-triangle Q = A P with the fixed-point epilogue:
 //   F     = Wn + h/2 (A - A^H) + h^2/4 Q       (both triangles; may alias Wt)
 //   Wout  = Wt + h/2 (A - A^H) - h^2/4 Q       (both triangles)
 //   rowpart[X*N + r]  partial row sums of |F - Wt| (see the kernel for the slot layout)
-hipError_t launch_zgemm_lower_epilogue(const double2* A, const double2* P, const double2* Wn,
-                                       const double2* Wt, double2* F, double2* Wout,
-                                       double* rowpart, int N, double h, hipStream_t s);
+hipError_t launch_zgemm_lower_epilogue(const ze_ctx* c, const double2* A, const double2* P,
+                                       const double2* Wn, const double2* Wt, double2* F,
+                                       double2* Wout, double* rowpart, double h, hipStream_t s);
 
 // resid = max_r sum_X rowpart[X*N + r]  (NaN propagates).
 hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, double* resid, int N,
