@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, run 3 plain device-to-device copies of this many "
+                         "MiB (a known-size reference for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU decomposition of the step is a "
@@ -123,6 +126,14 @@ def main():
     z.profile(False)
     log(f"timed {args.steps} steps: {dt:.3f} s, iters={iters}")
     c1 = z.casimirs(W, 4)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     s_per_step = dt / args.steps
     gemm_ms, gemm_n = prof["product_PW"]

@@ -40,7 +40,10 @@ typedef enum {
 /* Arithmetic of the complex matrix products. */
 typedef enum {
     ZE_PREC_FP64 = 0,   /* FP64 MFMA products */
-    ZE_PREC_SPLIT = 1   /* split-precision emulation of the FP64 products on low-precision MFMA */
+    ZE_PREC_SPLIT = 1   /* FP64 products emulated on INT8 MFMA: Ozaki splitting into s slices
+                           of 7 bits per row / column scale (ze_set_split_slices), exact int32
+                           slice products, FP64 accumulation; error ~2^(-7 s) relative to
+                           max|row| max|column| per term of the inner sum */
 } ze_prec;
 
 /* Message for a status code (static string). */
@@ -136,6 +139,14 @@ ze_status ze_basis_assemble(ze_ctx* ctx, const void* omega, void* W);
  * Errors: ZE_EINVAL, ZE_EHIP.  Asynchronous.
  */
 ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec);
+
+/*
+ * ze_set_split_slices -- number s of 7-bit slices per operand of the ZE_PREC_SPLIT products
+ * (2 <= s <= 8, default 6); the products then cost s (s + 1) / 2 INT8 products each.  The first
+ * split-precision call of a context allocates its slice buffers (about 24 N^2 bytes).
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_set_split_slices(ze_ctx* ctx, int slices);
 
 /*
  * ze_profile -- per-phase timing of ze_isomp_step, for measurement.  While on, every

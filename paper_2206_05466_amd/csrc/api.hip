@@ -29,6 +29,31 @@ void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
 
+// Workspaces of the split-precision products, allocated on first use.
+ze_status ensure_split(ze_ctx* c) {
+    if (c->split_a) return ZE_OK;
+    const size_t n = (size_t)c->N, ldk = (size_t)ze_split_ldk(c->N);
+    ze_status st = dalloc(&c->split_a, (size_t)kSplitMax * n * ldk);
+    if (st == ZE_OK) st = dalloc(&c->split_b, (size_t)kSplitMax * 2 * n * ldk);
+    if (st == ZE_OK) st = dalloc(&c->split_ea, n);
+    if (st == ZE_OK) st = dalloc(&c->split_eb, n);
+    if (st == ZE_OK) st = dalloc(&c->split_colmax, 64 * n);
+    if (st == ZE_OK) st = dalloc(&c->Q, n * n);
+    if (st != ZE_OK) {
+        dfree(c->split_a);
+        dfree(c->split_b);
+        dfree(c->split_ea);
+        dfree(c->split_eb);
+        dfree(c->split_colmax);
+        dfree(c->Q);
+        c->split_a = c->split_b = nullptr;
+        c->split_ea = c->split_eb = nullptr;
+        c->split_colmax = nullptr;
+        c->Q = nullptr;
+    }
+    return st;
+}
+
 }  // namespace
 
 ze_status ze_record_hip(hipError_t e, const char* what) {
@@ -66,6 +91,12 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->rowpart);
     dfree(c->blockmax);
     dfree(c->gemm_part);
+    dfree(c->split_a);
+    dfree(c->split_b);
+    dfree(c->split_ea);
+    dfree(c->split_eb);
+    dfree(c->split_colmax);
+    dfree(c->Q);
     dfree(c->resid);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
     for (hipEvent_t e : c->ev)
@@ -135,6 +166,12 @@ ze_status ze_stream_solve(ze_ctx* c, const void* W, void* P) {
 ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     if (!c || !A || !B || !C || C == A || C == B) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    if (prec == ZE_PREC_SPLIT) {
+        ZE_TRY(ensure_split(c));
+        ZE_HIP(launch_zgemm_split(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
+                                  static_cast<double2*>(C), 0, c->stream));
+        return ZE_OK;
+    }
     ZE_HIP(launch_zgemm_f64(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
                             static_cast<double2*>(C), c->stream));
     return ZE_OK;
@@ -147,6 +184,8 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     const int N = c->N;
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
+    const bool split = prec == ZE_PREC_SPLIT;
+    if (split) ZE_TRY(ensure_split(c));
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
@@ -157,9 +196,17 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
         if (prof) ZE_HIP(hipEventRecord(c->ev[0], s));
         ZE_HIP(launch_stream_solve(c, Wt, c->P, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[1], s));
-        ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
+        if (split)
+            ZE_HIP(launch_zgemm_split(c, c->P, Wt, c->A, 0, s));
+        else
+            ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
-        ZE_HIP(launch_zgemm_lower_epilogue(c, c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+        if (split) {
+            ZE_HIP(launch_zgemm_split(c, c->A, c->P, c->Q, 1, s));
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+        } else {
+            ZE_HIP(launch_zgemm_lower_epilogue(c, c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+        }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
         ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
@@ -252,6 +299,12 @@ ze_status ze_basis_assemble(ze_ctx* c, const void* omega, void* W) {
     (void)hipFree(scratch);
     if (e != hipSuccess) return ze_record_hip(e, "launch_basis_assemble");
     if (e2 != hipSuccess) return ze_record_hip(e2, "hipStreamSynchronize(basis)");
+    return ZE_OK;
+}
+
+ze_status ze_set_split_slices(ze_ctx* c, int slices) {
+    if (!c || slices < 2 || slices > kSplitMax) return ZE_EINVAL;
+    c->split_slices = slices;
     return ZE_OK;
 }
 

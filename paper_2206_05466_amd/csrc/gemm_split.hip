@@ -1,0 +1,449 @@
+// Split-precision complex products: FP64 matrix products emulated on INT8 MFMA
+// (v_mfma_i32_16x16x64_i8) by the error-free splitting of Ozaki, Ogita, Oishi & Rump,
+// "Error-free transformations of matrix multiplication by using fast routines of matrix
+// multiplication and its applications", Numer. Algorithms 59 (2012), in its integer form
+// (Ootomo, Ozaki & Yokota, "DGEMM on integer matrix multiplication unit", 2024).
+//
+// The products are the two of the fixed-point map (Sec. 3.1, eq. (isomp_iter)).  As in the
+// FP64 kernels, a complex product C = A B is the real product C~ = A~ B~ of the interleaved
+// A~ (N x 2N) and the 2 x 2-block form B~ (2N x 2N) of B.
+//
+// Splitting.  Row r of A~ is scaled by 2^-ea_r (ea_r = exponent of its largest magnitude, so
+// |entries| < 1) and cut into s signed 7-bit slices by exact truncation:
+//     y = x 2^-ea;  for i = 1..s:  y = 128 y;  a_i = trunc(y) in [-127, 127];  y = y - a_i.
+// Column cc of B~ likewise with 2^-eb_c (one exponent per complex column c; both real columns
+// 2c, 2c+1 hold the same magnitudes).  Then
+//     C~[r][cc] ~= 2^(ea_r + eb_c) sum_{i + j <= s + 1} 2^(-7 (i + j)) (a_i b_j)[r][cc],
+// each a_i b_j an exact int32 product (|sum| <= 2N 127^2 < 2^31 for N <= 16384), added into
+// an FP64 accumulator in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
+// max|row of A~| max|column of B~| per term of the K sum, so s trades accuracy for speed.
+//
+// Slices: A~ slices row-major [r][kk] (N x 2N bytes each); B~ slices transposed,
+// B~^T[cc][kk] (2N x 2N bytes each), which is the MFMA's B-operand order (K contiguous).
+// INT8 MFMA operand layout (16x16x64): lane l supplies 16 bytes of A~ row l%16 and of B~^T row
+// l%16, at the same 16 k positions (k = 16 (l/16) + 0..15 here); accumulator register r of
+// lane l holds D[4 (l/16) + r][l%16].
+
+#include "internal.h"
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------- slicing
+
+__device__ inline int exponent_of(double m) {  // smallest e with m < 2^e (0 for m == 0)
+    if (!(m > 0.0)) return 0;
+    int e;
+    frexp(m, &e);
+    return e;
+}
+
+// One block per row r of A~: scale exponent and s slices (rows of ldk bytes, zero padded).
+__global__ __launch_bounds__(kThreads) void split_rows_kernel(const double2* __restrict__ A,
+                                                              int N, int s, int ldk,
+                                                              signed char* __restrict__ slices,
+                                                              int* __restrict__ ea) {
+    __shared__ double red[kThreads];
+    const int r = blockIdx.x;
+    const double2* row = A + (size_t)r * N;
+    double m = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) {
+        const double2 v = row[c];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const int e = exponent_of(red[0]);
+    if (threadIdx.x == 0) ea[r] = e;
+    const size_t ss = (size_t)N * ldk;  // bytes per slice
+    signed char* base = slices + (size_t)r * ldk;
+    for (int c = threadIdx.x; c < ldk / 2; c += kThreads) {
+        double yr = 0.0, yi = 0.0;
+        if (c < N) {
+            const double2 v = row[c];
+            yr = ldexp(v.x, -e);
+            yi = ldexp(v.y, -e);
+        }
+        for (int i = 0; i < s; ++i) {
+            yr *= 128.0;
+            yi *= 128.0;
+            const double tr = trunc(yr), ti = trunc(yi);
+            yr -= tr;
+            yi -= ti;
+            const unsigned short pk = (unsigned short)((unsigned char)(signed char)tr) |
+                                      ((unsigned short)((unsigned char)(signed char)ti) << 8);
+            *reinterpret_cast<unsigned short*>(base + i * ss + 2 * c) = pk;
+        }
+    }
+}
+
+// Column maxima of B (complex N x N, row-major), two stages: block (x, y) takes 256
+// columns over the row chunk y; then one thread per column combines the chunks.
+constexpr int kColChunks = 64;
+__global__ __launch_bounds__(kThreads) void col_max_partial(const double2* __restrict__ B, int N,
+                                                            double* __restrict__ part) {
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= N) return;
+    const int k0 = (int)((long long)blockIdx.y * N / kColChunks);
+    const int k1 = (int)((long long)(blockIdx.y + 1) * N / kColChunks);
+    double m = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double2 v = B[(size_t)k * N + c];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    part[(size_t)blockIdx.y * N + c] = m;
+}
+
+__global__ __launch_bounds__(kThreads) void col_exponent_kernel(const double* __restrict__ part,
+                                                                int N, int* __restrict__ eb) {
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= N) return;
+    double m = 0.0;
+    for (int y = 0; y < kColChunks; ++y) m = fmax(m, part[(size_t)y * N + c]);
+    eb[c] = exponent_of(m);
+}
+
+// B~^T slices: tile of 32 rows (k) x 32 complex columns (c) of B through LDS.  Output row
+// cc = 2c + u of B~^T holds, at kk = 2k + t:  u = 0: (Re b, -Im b), u = 1: (Im b, Re b).
+// Rows are ldk bytes; tiles with k >= N write the zero padding.
+constexpr int kCT = 32;
+__global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __restrict__ B,
+                                                              int N, int s, int ldk,
+                                                              const int* __restrict__ eb,
+                                                              signed char* __restrict__ slices) {
+    __shared__ double2 tile[kCT][kCT + 1];
+    const int k0 = blockIdx.y * kCT, c0 = blockIdx.x * kCT;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int a = ty; a < kCT; a += 8) {
+        const int k = k0 + a, c = c0 + tx;
+        tile[a][tx] = (k < N && c < N) ? B[(size_t)k * N + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // Thread (tx = k offset, ty) writes, for columns c0 + ty + 8 j, the 2 bytes (t = 0, 1) of
+    // output rows 2c and 2c+1 at kk = 2 (k0 + tx) + t.
+    const size_t ss = (size_t)2 * N * ldk;  // bytes per slice
+    const int k = k0 + tx;
+    if (2 * k >= ldk) return;
+    for (int a = ty; a < kCT; a += 8) {
+        const int c = c0 + a;
+        if (c >= N) break;
+        const double2 v = tile[tx][a];  // B[k][c] (0 beyond N)
+        const int e = eb[c];
+        double br = ldexp(v.x, -e), bi = ldexp(v.y, -e);
+        signed char* o0 = slices + (size_t)(2 * c) * ldk + 2 * k;
+        signed char* o1 = slices + (size_t)(2 * c + 1) * ldk + 2 * k;
+        for (int i = 0; i < s; ++i) {
+            br *= 128.0;
+            bi *= 128.0;
+            const double tr = trunc(br), ti = trunc(bi);
+            br -= tr;
+            bi -= ti;
+            const unsigned char ur = (unsigned char)(signed char)tr;
+            const unsigned char ui = (unsigned char)(signed char)ti;
+            const unsigned char nui = (unsigned char)(signed char)(-ti);
+            *reinterpret_cast<unsigned short*>(o0 + i * ss) = (unsigned short)ur | ((unsigned short)nui << 8);
+            *reinterpret_cast<unsigned short*>(o1 + i * ss) = (unsigned short)ui | ((unsigned short)ur << 8);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- INT8 product
+// Block tile 128 rows x 128 real columns (64 complex), 4 waves as 2 x 2 of 64 x 64;
+// K stage of 128 bytes (two MFMA k-steps), double-buffered in LDS.
+constexpr int kBM = 128, kBN = 128, kBKB = 128;
+constexpr int kLD = kBKB + 16;  // padded LDS row (bytes)
+constexpr int kStage = (kBM + kBN) * kLD;
+
+__device__ inline void pair_of(int p, int s, int& i, int& j) {
+    // Pairs (i, j), i + j <= s + 1, ordered by decreasing i + j (smallest terms first), then i.
+    int idx = 0;
+    for (int t = s + 1; t >= 2; --t)
+        for (int a = 1; a <= t - 1; ++a) {
+            if (idx == p) {
+                i = a;
+                j = t - a;
+                return;
+            }
+            ++idx;
+        }
+    i = j = 1;
+}
+
+// mode 0: full product, tile b -> (b / tiles_n, b % tiles_n), C written complex N x N.
+// mode 1: tiles meeting the lower triangle: row tile I (128 rows) has column tiles
+//         J = 0..2I+1 (64 complex columns each), b = I (I+1) + J.
+__global__ __launch_bounds__(kThreads) void zgemm_i8_kernel(
+    const signed char* __restrict__ sa, const int* __restrict__ ea,
+    const signed char* __restrict__ sb, const int* __restrict__ eb, double2* __restrict__ Cm,
+    int N, int s, int ldk, int mode, int tiles_n) {
+    __shared__ __attribute__((aligned(16))) signed char smem[2 * kStage];
+    int ti, tj;
+    const int b = blockIdx.x;
+    if (mode == 0) {
+        ti = b / tiles_n;
+        tj = b % tiles_n;
+    } else {
+        int I = (int)((sqrt(4.0 * (double)b + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) <= b) ++I;
+        while (I * (I + 1) > b) --I;
+        ti = I;
+        tj = b - I * (I + 1);
+        if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
+    }
+    const int row0 = ti * kBM;        // rows of A~ / C
+    const int cc0 = tj * kBN;         // real columns of C~ (rows of B~^T)
+    const int M2 = 2 * N;             // real columns
+    const size_t sA = (size_t)N * ldk, sB = (size_t)M2 * ldk;  // bytes per slice
+    const int nk = ldk / kBKB;        // K stages (real K = 2N, zero padded to ldk)
+    const int npairs = s * (s + 1) / 2;
+    const int total = npairs * nk;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int q = lane >> 4, l16 = lane & 15;
+
+    v4i acc[4][4];
+    double accd[4][4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            acc[a][c] = v4i{0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accd[a][c][r] = 0.0;
+        }
+
+    // Global -> register loads of one stage: 8 chunks of 16 bytes per thread (4 A, 4 B).
+    uint4 ra[4], rb[4];
+    auto load = [&](int it) {
+        int pi, pj;
+        pair_of(it / nk, s, pi, pj);
+        const int k0 = (it % nk) * kBKB;
+        const signed char* A = sa + (size_t)(pi - 1) * sA;
+        const signed char* B = sb + (size_t)(pj - 1) * sB;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int id = tid + x * kThreads;
+            const int rr = id >> 3, cb = (id & 7) * 16;
+            const int gr = row0 + rr, gk = k0 + cb;
+            ra[x] = gr < N ? *reinterpret_cast<const uint4*>(A + (size_t)gr * ldk + gk)
+                           : make_uint4(0, 0, 0, 0);
+            const int gc = cc0 + rr;
+            rb[x] = gc < M2 ? *reinterpret_cast<const uint4*>(B + (size_t)gc * ldk + gk)
+                            : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto store = [&](signed char* st) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int id = tid + x * kThreads;
+            const int rr = id >> 3, cb = (id & 7) * 16;
+            *reinterpret_cast<uint4*>(st + rr * kLD + cb) = ra[x];
+            *reinterpret_cast<uint4*>(st + (kBM + rr) * kLD + cb) = rb[x];
+        }
+    };
+
+    load(0);
+    store(smem);
+    __syncthreads();
+    for (int it = 0; it < total; ++it) {
+        const bool more = it + 1 < total;
+        if (more) load(it + 1);
+        const signed char* st = smem + (it & 1) * kStage;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            v4i fa[4], fb[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                fa[x] = *reinterpret_cast<const v4i*>(st + (wr + x * 16 + l16) * kLD + ks * 64 + q * 16);
+                fb[x] = *reinterpret_cast<const v4i*>(st + (kBM + wc + x * 16 + l16) * kLD + ks * 64 + q * 16);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[c], acc[a][c], 0, 0, 0);
+        }
+        if ((it + 1) % nk == 0) {  // end of a slice pair: flush the exact int32 sums
+            int pi, pj;
+            pair_of(it / nk, s, pi, pj);
+            const double sc = ldexp(1.0, -7 * (pi + pj));
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) accd[a][c][r] += sc * (double)acc[a][c][r];
+                    acc[a][c] = v4i{0, 0, 0, 0};
+                }
+        }
+        if (more) store(smem + ((it + 1) & 1) * kStage);
+        __syncthreads();
+    }
+
+    // Epilogue: C~[row][cc] = 2^(ea_row + eb_c) accd.
+    double* Cd = reinterpret_cast<double*>(Cm);
+    const size_t ld = 2 * (size_t)N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int cc = cc0 + wc + c * 16 + l16;
+            if (cc >= M2) continue;
+            const int eb_c = eb[cc >> 1];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wr + a * 16 + 4 * q + r;
+                if (row < N) Cd[(size_t)row * ld + cc] = ldexp(accd[a][c][r], ea[row] + eb_c);
+            }
+        }
+}
+
+// ---------------------------------------------------------------- fixed-point update
+// For tile (I, J), I >= J, of 64 x 64 complex entries, from Q (lower tiles valid):
+//   F = Wn + h/2 (A - A^H) + h^2/4 Q,  Wout = Wt + h/2 (A - A^H) - h^2/4 Q   (Re Q_RR := 0),
+// lower entries written directly, upper ones (-conj) through an LDS transpose so every
+// global access is a coalesced row segment; row sums of |F - Wt| into the same slots as the
+// fused FP64 epilogue (see zgemm_lower_epilogue_kernel).
+constexpr int kUT = 64;
+__global__ __launch_bounds__(kThreads) void lower_update_kernel(
+    const double2* __restrict__ Q, const double2* __restrict__ Am, const double2* __restrict__ Wn,
+    const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
+    int N, double h) {
+    __shared__ double2 sT[kUT][kUT + 1];
+    double(*sD)[kUT + 1] = reinterpret_cast<double(*)[kUT + 1]>(&sT[0][0]);  // reused at the end
+    const int b = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int J = b - I * (I + 1) / 2;
+    const int R0 = I * kUT, C0 = J * kUT;
+    const int tid = threadIdx.x;
+    const int lc = tid & 63, lr0 = tid >> 6;  // 4 rows per pass, 64 consecutive columns
+    const double h2 = 0.5 * h, h4 = 0.25 * h * h;
+
+    // A^T tile: sT[c][R] = A[C0 + c][R0 + R].
+    for (int rr = lr0; rr < kUT; rr += 4) {
+        const int gr = C0 + rr, gc = R0 + lc;
+        sT[rr][lc] = (gr < N && gc < N) ? Am[(size_t)gr * N + gc] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    double2 fv[kUT / 4], wv[kUT / 4];
+    double dv[kUT / 4];
+#pragma unroll
+    for (int x = 0; x < kUT / 4; ++x) {
+        const int r = lr0 + 4 * x, R = R0 + r, c = C0 + lc;
+        const bool ok = R < N && c < N && c <= R;
+        double2 f = make_double2(0.0, 0.0), wo = f, d = f;
+        if (ok) {
+            const size_t o = (size_t)R * N + c;
+            double2 qv = Q[o];
+            if (c == R) qv.x = 0.0;
+            const double2 arc = Am[o], acr = sT[lc][r];
+            const double cr = arc.x - acr.x, ci = arc.y + acr.y;  // (A - A^H)_{Rc}
+            const double2 wn = Wn[o], wt = Wt[o];
+            f = make_double2(wn.x + h2 * cr + h4 * qv.x, wn.y + h2 * ci + h4 * qv.y);
+            wo = make_double2(wt.x + h2 * cr - h4 * qv.x, wt.y + h2 * ci - h4 * qv.y);
+            d = make_double2(f.x - wt.x, f.y - wt.y);
+            F[o] = f;
+            Wout[o] = wo;
+        }
+        fv[x] = f;
+        wv[x] = wo;
+        dv[x] = ok ? sqrt(d.x * d.x + d.y * d.y) : 0.0;
+    }
+    __syncthreads();
+    // Upper entries: F[c][R] = -conj(F[R][c]) for c < R, via sT.
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int x = 0; x < kUT / 4; ++x) {
+            const int r = lr0 + 4 * x;
+            const double2 v = pass == 0 ? fv[x] : wv[x];
+            sT[lc][r] = make_double2(-v.x, v.y);
+        }
+        __syncthreads();
+        double2* out = pass == 0 ? F : Wout;
+        for (int cr = lr0; cr < kUT; cr += 4) {  // row C0 + cr of the upper tile, columns R0 + lc
+            const int gc = C0 + cr, gR = R0 + lc;
+            if (gc < N && gR < N && gc < gR) out[(size_t)gc * N + gR] = sT[cr][lc];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < kUT / 4; ++x) sD[lr0 + 4 * x][lc] = dv[x];
+    __syncthreads();
+    if (I != J) {
+        if (tid < kUT) {
+            double sum = 0.0;
+            for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
+            if (R0 + tid < N) rowpart[(size_t)J * N + R0 + tid] = sum;
+        } else if (tid < 2 * kUT) {
+            const int j = tid - kUT;
+            double sum = 0.0;
+            for (int k = 0; k < kUT; ++k) sum += sD[k][j];
+            if (C0 + j < N) rowpart[(size_t)I * N + C0 + j] = sum;
+        }
+    } else if (tid < kUT) {
+        double sum = 0.0;
+        for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
+        for (int k = tid + 1; k < kUT; ++k) sum += sD[k][tid];
+        if (R0 + tid < N) rowpart[(size_t)I * N + R0 + tid] = sum;
+    }
+}
+
+}  // namespace
+
+int ze_split_ldk(int N) { return ((2 * N + kBKB - 1) / kBKB) * kBKB; }
+
+hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B,
+                                hipStream_t st) {
+    const int N = c->N, s = c->split_slices, ldk = ze_split_ldk(N);
+    hipLaunchKernelGGL(split_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, s, ldk, c->split_a,
+                       c->split_ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gx = (N + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(col_max_partial, dim3(gx, kColChunks), dim3(kThreads), 0, st, B, N,
+                       c->split_colmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(col_exponent_kernel, dim3(gx), dim3(kThreads), 0, st, c->split_colmax, N,
+                       c->split_eb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g((N + kCT - 1) / kCT, (ldk / 2 + kCT - 1) / kCT);
+    hipLaunchKernelGGL(split_cols_kernel, g, dim3(kThreads), 0, st, B, N, s, ldk, c->split_eb,
+                       c->split_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
+                              int lower, hipStream_t st) {
+    const int N = c->N, s = c->split_slices;
+    hipError_t e = launch_split_prepare(c, A, B, st);
+    if (e != hipSuccess) return e;
+    const int tr = (N + kBM - 1) / kBM;
+    const int tn = (2 * N + kBN - 1) / kBN;
+    const int nb = lower ? tr * (tr + 1) : tr * tn;
+    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->split_a, c->split_ea,
+                       c->split_b, c->split_eb, C, N, s, ze_split_ldk(N), lower ? 1 : 0, tn);
+    return hipGetLastError();
+}
+
+hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
+                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
+                               double* rowpart, double h, hipStream_t st) {
+    const int N = c->N;
+    const int T = (N + kUT - 1) / kUT;
+    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q, A, Wn,
+                       Wt, F, Wout, rowpart, N, h);
+    return hipGetLastError();
+}

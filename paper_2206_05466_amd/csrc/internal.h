@@ -53,6 +53,17 @@ struct ze_ctx {
     int cap_full = 0, cap_low = 0;
     double* gemm_part = nullptr;
 
+    // Split-precision products (allocated on first use): slice count s, INT8 slices of the
+    // A~ and B~^T operands (kSplitMax slices each, rows of ze_split_ldk(N) bytes), their scale
+    // exponents, column-maximum partials, and the buffer for the lower product Q.
+    int split_slices = 6;
+    signed char* split_a = nullptr;
+    signed char* split_b = nullptr;
+    int* split_ea = nullptr;
+    int* split_eb = nullptr;
+    double* split_colmax = nullptr;
+    double2* Q = nullptr;
+
     // Optional per-phase timing (ze_profile).
     bool prof = false;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -62,6 +73,8 @@ struct ze_ctx {
 
 // Largest matrix size a context accepts.
 constexpr int kMaxN = 16384;
+// Largest number of slices of the split-precision products.
+constexpr int kSplitMax = 8;
 
 // Host: the factors held in ze_ctx::fac_l / fac_dinv (N (N+1) / 2 entries each).
 void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd);
@@ -103,3 +116,16 @@ hipError_t launch_trace(const double2* X, double2* partial, double2* out, int N,
 size_t ze_basis_scratch_bytes(int N);
 hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch, int N,
                                  hipStream_t s);
+
+// ---- split-precision products (INT8 MFMA, Ozaki splitting) ----
+int ze_split_ldk(int N);  // bytes per slice row: 2N rounded up to the K stage
+// Slices A (rows) and B (columns) into the context's buffers.
+hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, hipStream_t s);
+// C = A B (lower != 0: only the tiles meeting the lower triangle are formed).
+hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
+                              int lower, hipStream_t s);
+// The fixed-point update of launch_zgemm_lower_epilogue from a precomputed Q (lower tiles).
+hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
+                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
+                               double* rowpart, double h, hipStream_t s);
+

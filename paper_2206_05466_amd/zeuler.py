@@ -35,6 +35,7 @@ SIGNATURES = {
     "ze_casimirs": (_c_int, [_vp, _vp, _c_int, _P_double]),
     "ze_basis_assemble": (_c_int, [_vp, _vp, _vp]),
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
+    "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
 }
@@ -185,6 +186,10 @@ class Zeuler:
         _check(self.lib.ze_basis_assemble(self._ctx, ctypes.c_void_p(om.data_ptr()), self._mat(W, "W")),
                "ze_basis_assemble")
         return W
+
+    def set_split_slices(self, slices: int):
+        """Slices per operand of the PREC_SPLIT products (2..8)."""
+        _check(self.lib.ze_set_split_slices(self._ctx, int(slices)), "ze_set_split_slices")
 
     def profile(self, on: bool = True):
         """Turn per-phase event timing of isomp_step on or off."""

@@ -210,3 +210,71 @@ def test_basis_single_elements(dev):
                 om[l * l + l + m] = 1.0
                 W = to_host(z.basis_assemble(om))
                 assert np.abs(W - O.assemble(N, om)).max() < 1e-13
+
+
+# ------------------------------------------------------------------ split precision
+# Ozaki splitting on INT8 MFMA with s slices of 7 bits per row/column scale: small integers
+# are exact (one slice carries them); otherwise |C - AB| <~ 3 * 2^(-7 s) * 2N max|A| max|B|
+# (truncation of both operands plus the dropped slice products), tested with a factor 10.
+@pytest.mark.parametrize("N", [1, 7, 64, 100, 129, 256])
+def test_zgemm_split_small_integers_exact(dev, N):
+    from paper_2206_05466_amd import PREC_SPLIT
+
+    rng = np.random.default_rng(N + 7)
+    A = rng.integers(-8, 9, (N, N)) + 1j * rng.integers(-8, 9, (N, N))
+    B = rng.integers(-8, 9, (N, N)) + 1j * rng.integers(-8, 9, (N, N))
+    with ctx(N) as z:
+        C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_SPLIT))
+    assert np.array_equal(C, A @ B)
+
+
+@pytest.mark.parametrize("N,s", [(64, 6), (131, 4), (131, 6), (200, 8), (384, 5)])
+def test_zgemm_split_random_bound(dev, N, s):
+    from paper_2206_05466_amd import PREC_SPLIT
+
+    rng = np.random.default_rng(N + s)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    B = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    with ctx(N) as z:
+        z.set_split_slices(s)
+        C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_SPLIT))
+    scale = 2 * N * np.abs(A).max() * np.abs(B).max()
+    err = np.abs(C - A @ B).max() / scale
+    assert err < 10 * 3 * 2.0 ** (-7 * s) + 1e-16, (s, err)
+
+
+def test_zgemm_split_error_decreases_with_slices(dev):
+    from paper_2206_05466_amd import PREC_SPLIT
+
+    N = 96
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    B = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    errs = []
+    with ctx(N) as z:
+        for s in (2, 3, 4, 5, 6):
+            z.set_split_slices(s)
+            C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_SPLIT))
+            errs.append(np.abs(C - A @ B).max())
+    assert all(errs[i + 1] < errs[i] / 20 for i in range(4)), errs
+
+
+@pytest.mark.parametrize("s", [5, 6, 8])
+def test_isomp_split_ten_steps_n64(dev, s):
+    from paper_2206_05466_amd import PREC_SPLIT
+
+    N, h = 64, 0.01
+    W0 = w0(N, 0)
+    Wr, it_ref, _ = O.isomp_run(W0, h, 10, 1e-12, 50)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_split_slices(s)
+        its, res = z.isomp_run(Wd, h, 10, 1e-12, 50, prec=PREC_SPLIT)
+        W = to_host(Wd)
+    err = np.linalg.norm(W - Wr) / np.linalg.norm(Wr)
+    assert err < 1e-10, (s, err)
+    assert max(res) < 1e-12
+    assert np.abs(W + W.conj().T).max() == 0.0
+    c0, c1 = O.casimirs(W0, 4), O.casimirs(W, 4)
+    rel = np.abs(c1 - c0) / np.abs(c0)
+    assert rel[1] < 1e-11 and rel[3] < 1e-11
