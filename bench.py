@@ -26,6 +26,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+
+# HBM bytes per launch of zgemm_f64_kernel (A = P W~) at N = 4096, from two rocprofv3 --pmc
+# passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors read off a plain 1 GiB device
+# copy in the same runs).  Valid only for the kernel source the counters were taken on.
+MEASURED_TRAFFIC = {"N": 4096, "source": "paper_2206_05466_amd/csrc/gemm_f64.hip",
+                    "sha256_16": "bcbc1b14ffdeb040", "bytes": 2070693.6 * 1024 * 2.0 + 262144.0 * 1024 * 1.0}
+
+
+def measured_traffic(N):
+    import hashlib
+
+    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
+    with open(path, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if N == MEASURED_TRAFFIC["N"] and sha == MEASURED_TRAFFIC["sha256_16"]:
+        return MEASURED_TRAFFIC["bytes"]
+    return None
 PAPER_S_PER_STEP_N4096 = 0.55  # Sec. 3.4: ~2500 CPU cores, ScaLAPACK, N = 4096, 3 iterations
 
 
@@ -80,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split-slices", type=int, default=6,
+                    help="slices of the split-precision run (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, run 3 plain device-to-device copies of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -107,6 +126,7 @@ def main():
     torch.cuda.synchronize()
     log(f"W0 assembled on GPU in {time.perf_counter() - t0:.2f} s")
     c0 = z.casimirs(W, 4)
+    W0 = W.clone()
 
     for i in range(args.warmup):
         info = z.isomp_step(W, h, tol, maxit, PREC_FP64)
@@ -134,6 +154,47 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    split = None
+    if args.split_slices > 0:
+        from paper_2206_05466_amd import PREC_SPLIT
+
+        z.set_split_slices(args.split_slices)
+        Ws = W0.clone()
+        for i in range(args.warmup):
+            z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
+        z.profile(True)
+        z.profile_read(reset=True)
+        its_s = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            info = z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
+            its_s.append(info.iters)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0
+        profs = z.profile_read()
+        z.profile(False)
+        cs = z.casimirs(Ws, 4)
+        diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
+        sps = dts / args.steps
+        p1 = profs["product_PW"][0] / max(profs["product_PW"][1], 1)
+        split = {
+            "slices": args.split_slices,
+            "s_per_step": sps,
+            "speedup_vs_fp64": (dt / args.steps) / sps,
+            "iters_per_step": its_s,
+            "rel_frobenius_vs_fp64_run": diff,
+            "casimir_drift_rel": {
+                f"C{k+1}": float(abs(cs[k] - c0[k]) / (abs(c0[k]) if k != 2 else np.linalg.norm(
+                    Ws.cpu().numpy()) ** 3)) for k in (1, 2, 3)},
+            "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in profs.items()},
+            "product_PW_fp64_equiv_tflops": 8.0 * N ** 3 / (p1 * 1e-3) / 1e12,
+            "product_PW_int8_tops": 8.0 * N ** 3 * args.split_slices * (args.split_slices + 1) / 2
+                                    / (p1 * 1e-3) / 1e12,
+            "note": "same W0 and steps as the FP64 run; product_PW includes the slicing kernels",
+        }
+        log(f"split s={args.split_slices}: {sps*1e3:.2f} ms/step, rel diff vs fp64 {diff:.2e}")
 
     s_per_step = dt / args.steps
     gemm_ms, gemm_n = prof["product_PW"]
@@ -182,7 +243,7 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(N),
         },
         "solve_hbm": {
             "achieved_GBps": solve_bytes / solve_avg_s / 1e9,
@@ -192,6 +253,7 @@ def main():
         },
         "lower_product_tflops": 4.0 * N ** 3 / (low_ms * 1e-3) / 1e12,
         "cpu_baseline": None,
+        "split_precision": split,
     }
     if not args.no_cpu_baseline:
         K = int(round(sum(iters) / len(iters)))
