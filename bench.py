@@ -97,8 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--split-slices", type=int, default=6,
-                    help="slices of the split-precision run (0: skip it)")
+    ap.add_argument("--split-slices", default="4,5,6",
+                    help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, run 3 plain device-to-device copies of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -156,45 +156,59 @@ def main():
         del src, dst
 
     split = None
-    if args.split_slices > 0:
+    slist = [int(x) for x in str(args.split_slices).split(",") if x.strip() and int(x) > 0]
+    if slist:
         from paper_2206_05466_amd import PREC_SPLIT
 
-        z.set_split_slices(args.split_slices)
-        Ws = W0.clone()
-        for i in range(args.warmup):
-            z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
-        z.profile(True)
-        z.profile_read(reset=True)
-        its_s = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            info = z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
-            its_s.append(info.iters)
-        torch.cuda.synchronize()
-        dts = time.perf_counter() - t0
-        profs = z.profile_read()
-        z.profile(False)
-        cs = z.casimirs(Ws, 4)
-        diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
-        sps = dts / args.steps
-        p1 = profs["product_PW"][0] / max(profs["product_PW"][1], 1)
+        runs = []
+        for ns in slist:
+            z.set_split_slices(ns)
+            Ws = W0.clone()
+            for i in range(args.warmup):
+                z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
+            z.profile(True)
+            z.profile_read(reset=True)
+            its_s = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                info = z.isomp_step(Ws, h, tol, maxit, PREC_SPLIT)
+                its_s.append(info.iters)
+            torch.cuda.synchronize()
+            dts = time.perf_counter() - t0
+            profs = z.profile_read()
+            z.profile(False)
+            cs = z.casimirs(Ws, 4)
+            diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
+            sps = dts / args.steps
+            p1 = profs["product_PW"][0] / max(profs["product_PW"][1], 1)
+            drift_s = {f"C{k+1}": float(abs(cs[k] - c0[k]) / (abs(c0[k]) if k != 2 else np.linalg.norm(
+                Ws.cpu().numpy()) ** 3)) for k in (1, 2, 3)}
+            runs.append({
+                "slices": ns,
+                "s_per_step": sps,
+                "speedup_vs_fp64": (dt / args.steps) / sps,
+                "iters_per_step": its_s,
+                "rel_frobenius_vs_fp64_run": diff,
+                "casimir_drift_rel": drift_s,
+                "meets_stated_accuracy": diff <= 1e-10 and max(drift_s.values()) <= 1e-11,
+                "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in profs.items()},
+                "product_PW_fp64_equiv_tflops": 8.0 * N ** 3 / (p1 * 1e-3) / 1e12,
+                "product_PW_int8_tops": 8.0 * N ** 3 * ns * (ns + 1) / 2 / (p1 * 1e-3) / 1e12,
+            })
+            log(f"split s={ns}: {sps*1e3:.2f} ms/step, rel diff vs fp64 {diff:.2e}")
+        ok = [r for r in runs if r["meets_stated_accuracy"]]
+        best = min(ok, key=lambda r: r["s_per_step"]) if ok else None
         split = {
-            "slices": args.split_slices,
-            "s_per_step": sps,
-            "speedup_vs_fp64": (dt / args.steps) / sps,
-            "iters_per_step": its_s,
-            "rel_frobenius_vs_fp64_run": diff,
-            "casimir_drift_rel": {
-                f"C{k+1}": float(abs(cs[k] - c0[k]) / (abs(c0[k]) if k != 2 else np.linalg.norm(
-                    Ws.cpu().numpy()) ** 3)) for k in (1, 2, 3)},
-            "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in profs.items()},
-            "product_PW_fp64_equiv_tflops": 8.0 * N ** 3 / (p1 * 1e-3) / 1e12,
-            "product_PW_int8_tops": 8.0 * N ** 3 * args.split_slices * (args.split_slices + 1) / 2
-                                    / (p1 * 1e-3) / 1e12,
-            "note": "same W0 and steps as the FP64 run; product_PW includes the slicing kernels",
+            "stated_accuracy": "after the timed steps, rel. Frobenius distance to the FP64 run <= 1e-10 "
+                               "and Casimir drift <= 1e-11 (the FP64 path's parity bar)",
+            "best_at_stated_accuracy": None if best is None else {
+                "slices": best["slices"], "s_per_step": best["s_per_step"],
+                "speedup_vs_fp64": best["speedup_vs_fp64"],
+                "rel_frobenius_vs_fp64_run": best["rel_frobenius_vs_fp64_run"]},
+            "runs": runs,
+            "note": "same W0 and step count as the FP64 run; product_PW includes the slicing kernels",
         }
-        log(f"split s={args.split_slices}: {sps*1e3:.2f} ms/step, rel diff vs fp64 {diff:.2e}")
 
     s_per_step = dt / args.steps
     gemm_ms, gemm_n = prof["product_PW"]

@@ -38,18 +38,18 @@ ze_status ensure_split(ze_ctx* c) {
     if (st == ZE_OK) st = dalloc(&c->split_ea, n);
     if (st == ZE_OK) st = dalloc(&c->split_eb, n);
     if (st == ZE_OK) st = dalloc(&c->split_colmax, 64 * n);
-    if (st == ZE_OK) st = dalloc(&c->Q, n * n);
+    if (st == ZE_OK) st = dalloc(&c->split_g, (size_t)kSplitMax * 2 * n * n);
     if (st != ZE_OK) {
         dfree(c->split_a);
         dfree(c->split_b);
         dfree(c->split_ea);
         dfree(c->split_eb);
         dfree(c->split_colmax);
-        dfree(c->Q);
+        dfree(c->split_g);
         c->split_a = c->split_b = nullptr;
         c->split_ea = c->split_eb = nullptr;
         c->split_colmax = nullptr;
-        c->Q = nullptr;
+        c->split_g = nullptr;
     }
     return st;
 }
@@ -96,7 +96,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->split_ea);
     dfree(c->split_eb);
     dfree(c->split_colmax);
-    dfree(c->Q);
+    dfree(c->split_g);
     dfree(c->resid);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
     for (hipEvent_t e : c->ev)
@@ -202,8 +202,8 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
             ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
         if (split) {
-            ZE_HIP(launch_zgemm_split(c, c->A, c->P, c->Q, 1, s));
-            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+            ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, s));
+            ZE_HIP(launch_lower_update(c, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
         } else {
             ZE_HIP(launch_zgemm_lower_epilogue(c, c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
         }

@@ -14,8 +14,8 @@
 // Column cc of B~ likewise with 2^-eb_c (one exponent per complex column c; both real columns
 // 2c, 2c+1 hold the same magnitudes).  Then
 //     C~[r][cc] ~= 2^(ea_r + eb_c) sum_{i + j <= s + 1} 2^(-7 (i + j)) (a_i b_j)[r][cc],
-// each a_i b_j an exact int32 product (|sum| <= 2N 127^2 < 2^31 for N <= 16384), added into
-// an FP64 accumulator in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
+// the products of one t = i + j summed exactly in int32 ((t-1) 2N 127^2 < 2^31 for the sizes
+// and slice counts allowed), then weighted and added in FP64 in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
 // max|row of A~| max|column of B~| per term of the K sum, so s trades accuracy for speed.
 //
 // Slices: A~ slices row-major [r][kk] (N x 2N bytes each); B~ slices transposed,
@@ -23,6 +23,8 @@
 // INT8 MFMA operand layout (16x16x64): lane l supplies 16 bytes of A~ row l%16 and of B~^T row
 // l%16, at the same 16 k positions (k = 16 (l/16) + 0..15 here); accumulator register r of
 // lane l holds D[4 (l/16) + r][l%16].
+
+#include <type_traits>
 
 #include "internal.h"
 
@@ -156,34 +158,24 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __r
 
 // ---------------------------------------------------------------- INT8 product
 // Block tile 128 rows x 128 real columns (64 complex), 4 waves as 2 x 2 of 64 x 64;
-// K stage of 128 bytes (two MFMA k-steps), double-buffered in LDS.
+// K stage of 128 bytes (two MFMA k-steps), double-buffered in LDS, global loads one stage
+// ahead.  Slice pairs run in order of decreasing t = i + j; the pairs of one t share one
+// exact int32 accumulator ((t-1) 2N 127^2 < 2^31), which is stored to the slab G[t-2]
+// (int32, N x 2N) when t changes.  The FP64 weighting happens afterwards (combine kernel or
+// the fixed-point update), so no FP64 accumulator occupies registers here.
 constexpr int kBM = 128, kBN = 128, kBKB = 128;
 constexpr int kLD = kBKB + 16;  // padded LDS row (bytes)
 constexpr int kStage = (kBM + kBN) * kLD;
+constexpr int kMaxPairs = kSplitMax * (kSplitMax + 1) / 2;
 
-__device__ inline void pair_of(int p, int s, int& i, int& j) {
-    // Pairs (i, j), i + j <= s + 1, ordered by decreasing i + j (smallest terms first), then i.
-    int idx = 0;
-    for (int t = s + 1; t >= 2; --t)
-        for (int a = 1; a <= t - 1; ++a) {
-            if (idx == p) {
-                i = a;
-                j = t - a;
-                return;
-            }
-            ++idx;
-        }
-    i = j = 1;
-}
-
-// mode 0: full product, tile b -> (b / tiles_n, b % tiles_n), C written complex N x N.
+// mode 0: full product, tile b -> (b / tiles_n, b % tiles_n).
 // mode 1: tiles meeting the lower triangle: row tile I (128 rows) has column tiles
 //         J = 0..2I+1 (64 complex columns each), b = I (I+1) + J.
-__global__ __launch_bounds__(kThreads) void zgemm_i8_kernel(
-    const signed char* __restrict__ sa, const int* __restrict__ ea,
-    const signed char* __restrict__ sb, const int* __restrict__ eb, double2* __restrict__ Cm,
+__global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
+    const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
     int N, int s, int ldk, int mode, int tiles_n) {
     __shared__ __attribute__((aligned(16))) signed char smem[2 * kStage];
+    __shared__ unsigned char pt_i[kMaxPairs], pt_j[kMaxPairs], pt_flush[kMaxPairs];
     int ti, tj;
     const int b = blockIdx.x;
     if (mode == 0) {
@@ -197,66 +189,66 @@ __global__ __launch_bounds__(kThreads) void zgemm_i8_kernel(
         tj = b - I * (I + 1);
         if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
     }
-    const int row0 = ti * kBM;        // rows of A~ / C
-    const int cc0 = tj * kBN;         // real columns of C~ (rows of B~^T)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) {
+        int p = 0;
+        for (int t = s + 1; t >= 2; --t)
+            for (int a = 1; a <= t - 1; ++a, ++p) {
+                pt_i[p] = (unsigned char)a;
+                pt_j[p] = (unsigned char)(t - a);
+                pt_flush[p] = (unsigned char)(a == t - 1);
+            }
+    }
+    const int row0 = ti * kBM;        // rows of A~ / G
+    const int cc0 = tj * kBN;         // real columns of G (rows of B~^T)
     const int M2 = 2 * N;             // real columns
     const size_t sA = (size_t)N * ldk, sB = (size_t)M2 * ldk;  // bytes per slice
     const int nk = ldk / kBKB;        // K stages (real K = 2N, zero padded to ldk)
-    const int npairs = s * (s + 1) / 2;
-    const int total = npairs * nk;
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int total = s * (s + 1) / 2 * nk;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int q = lane >> 4, l16 = lane & 15;
+    __syncthreads();
 
     v4i acc[4][4];
-    double accd[4][4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            acc[a][c] = v4i{0, 0, 0, 0};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) accd[a][c][r] = 0.0;
-        }
+        for (int c = 0; c < 4; ++c) acc[a][c] = v4i{0, 0, 0, 0};
 
-    // Global -> register loads of one stage: 8 chunks of 16 bytes per thread (4 A, 4 B).
-    uint4 ra[4], rb[4];
-    auto load = [&](int it) {
-        int pi, pj;
-        pair_of(it / nk, s, pi, pj);
-        const int k0 = (it % nk) * kBKB;
-        const signed char* A = sa + (size_t)(pi - 1) * sA;
-        const signed char* B = sb + (size_t)(pj - 1) * sB;
+    uint4 ra[1][4], rb[1][4];
+    auto load = [&](int it, int slot) {
+        const int p = it / nk;
+        const int k0 = (it - p * nk) * kBKB;
+        const signed char* A = sa + (size_t)(pt_i[p] - 1) * sA;
+        const signed char* B = sb + (size_t)(pt_j[p] - 1) * sB;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             const int id = tid + x * kThreads;
             const int rr = id >> 3, cb = (id & 7) * 16;
-            const int gr = row0 + rr, gk = k0 + cb;
-            ra[x] = gr < N ? *reinterpret_cast<const uint4*>(A + (size_t)gr * ldk + gk)
-                           : make_uint4(0, 0, 0, 0);
-            const int gc = cc0 + rr;
-            rb[x] = gc < M2 ? *reinterpret_cast<const uint4*>(B + (size_t)gc * ldk + gk)
-                            : make_uint4(0, 0, 0, 0);
+            const int gr = row0 + rr, gc = cc0 + rr;
+            ra[slot][x] = gr < N ? *reinterpret_cast<const uint4*>(A + (size_t)gr * ldk + k0 + cb)
+                                 : make_uint4(0, 0, 0, 0);
+            rb[slot][x] = gc < M2 ? *reinterpret_cast<const uint4*>(B + (size_t)gc * ldk + k0 + cb)
+                                  : make_uint4(0, 0, 0, 0);
         }
     };
-    auto store = [&](signed char* st) {
+    auto store = [&](signed char* st, int slot) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             const int id = tid + x * kThreads;
             const int rr = id >> 3, cb = (id & 7) * 16;
-            *reinterpret_cast<uint4*>(st + rr * kLD + cb) = ra[x];
-            *reinterpret_cast<uint4*>(st + (kBM + rr) * kLD + cb) = rb[x];
+            *reinterpret_cast<uint4*>(st + rr * kLD + cb) = ra[slot][x];
+            *reinterpret_cast<uint4*>(st + (kBM + rr) * kLD + cb) = rb[slot][x];
         }
     };
 
-    load(0);
-    store(smem);
+    load(0, 0);
+    store(smem, 0);
     __syncthreads();
     for (int it = 0; it < total; ++it) {
-        const bool more = it + 1 < total;
-        if (more) load(it + 1);
-        const signed char* st = smem + (it & 1) * kStage;
+        const int cur = it & 1;
+        if (it + 1 < total) load(it + 1, 0);
+        const signed char* st = smem + cur * kStage;
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             v4i fa[4], fb[4];
@@ -271,39 +263,48 @@ __global__ __launch_bounds__(kThreads) void zgemm_i8_kernel(
                 for (int c = 0; c < 4; ++c)
                     acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[c], acc[a][c], 0, 0, 0);
         }
-        if ((it + 1) % nk == 0) {  // end of a slice pair: flush the exact int32 sums
-            int pi, pj;
-            pair_of(it / nk, s, pi, pj);
-            const double sc = ldexp(1.0, -7 * (pi + pj));
+        const int p = it / nk;
+        if (it - p * nk == nk - 1 && pt_flush[p]) {  // last stage of the last pair of this t
+            int* g = G + (size_t)(pt_i[p] + pt_j[p] - 2) * N * M2;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
+                    const int cc = cc0 + wc + c * 16 + l16;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) accd[a][c][r] += sc * (double)acc[a][c][r];
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = row0 + wr + a * 16 + 4 * q + r;
+                        if (row < N && cc < M2) g[(size_t)row * M2 + cc] = acc[a][c][r];
+                    }
                     acc[a][c] = v4i{0, 0, 0, 0};
                 }
         }
-        if (more) store(smem + ((it + 1) & 1) * kStage);
+        if (it + 1 < total) store(smem + (cur ^ 1) * kStage, 0);
         __syncthreads();
     }
+}
 
-    // Epilogue: C~[row][cc] = 2^(ea_row + eb_c) accd.
-    double* Cd = reinterpret_cast<double*>(Cm);
-    const size_t ld = 2 * (size_t)N;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int cc = cc0 + wc + c * 16 + l16;
-            if (cc >= M2) continue;
-            const int eb_c = eb[cc >> 1];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wr + a * 16 + 4 * q + r;
-                if (row < N) Cd[(size_t)row * ld + cc] = ldexp(accd[a][c][r], ea[row] + eb_c);
-            }
+// C~[r][cc] = 2^(ea_r + eb_c) sum_{t=2}^{s+1} 2^(-7 t) G[t-2][r][cc], complex pairs per thread.
+__global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __restrict__ G,
+                                                                 const int* __restrict__ ea,
+                                                                 const int* __restrict__ eb,
+                                                                 double2* __restrict__ Cm, int N,
+                                                                 int s) {
+    const size_t n2 = (size_t)N * N;
+    const size_t slab = 2 * n2;
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
+         e += (size_t)gridDim.x * kThreads) {
+        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
+        double vr = 0.0, vi = 0.0;
+        for (int t = s + 1; t >= 2; --t) {
+            const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * slab + 2 * e);
+            const double w = ldexp(1.0, -7 * t);
+            vr += w * (double)g.x;
+            vi += w * (double)g.y;
         }
+        const int ex = ea[r] + eb[c];
+        Cm[e] = make_double2(ldexp(vr, ex), ldexp(vi, ex));
+    }
 }
 
 // ---------------------------------------------------------------- fixed-point update
@@ -314,7 +315,8 @@ __global__ __launch_bounds__(kThreads) void zgemm_i8_kernel(
 // fused FP64 epilogue (see zgemm_lower_epilogue_kernel).
 constexpr int kUT = 64;
 __global__ __launch_bounds__(kThreads) void lower_update_kernel(
-    const double2* __restrict__ Q, const double2* __restrict__ Am, const double2* __restrict__ Wn,
+    const int* __restrict__ G, const int* __restrict__ ea, const int* __restrict__ eb, int s,
+    const double2* __restrict__ Am, const double2* __restrict__ Wn,
     const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
     int N, double h) {
     __shared__ double2 sT[kUT][kUT + 1];
@@ -345,7 +347,16 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
         double2 f = make_double2(0.0, 0.0), wo = f, d = f;
         if (ok) {
             const size_t o = (size_t)R * N + c;
-            double2 qv = Q[o];
+            double2 qv = make_double2(0.0, 0.0);  // Q = A P from the int32 slabs
+            for (int t = s + 1; t >= 2; --t) {
+                const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
+                const double w = ldexp(1.0, -7 * t);
+                qv.x += w * (double)g.x;
+                qv.y += w * (double)g.y;
+            }
+            const int ex = ea[R] + eb[c];
+            qv.x = ldexp(qv.x, ex);
+            qv.y = ldexp(qv.y, ex);
             if (c == R) qv.x = 0.0;
             const double2 arc = Am[o], acr = sT[lc][r];
             const double cr = arc.x - acr.x, ci = arc.y + acr.y;  // (A - A^H)_{Rc}
@@ -433,17 +444,24 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     const int tr = (N + kBM - 1) / kBM;
     const int tn = (2 * N + kBN - 1) / kBN;
     const int nb = lower ? tr * (tr + 1) : tr * tn;
-    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->split_a, c->split_ea,
-                       c->split_b, c->split_eb, C, N, s, ze_split_ldk(N), lower ? 1 : 0, tn);
+    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->split_a, c->split_b,
+                       c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn);
+    e = hipGetLastError();
+    if (e != hipSuccess || lower) return e;
+    const size_t n2 = (size_t)N * N;
+    const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
+    hipLaunchKernelGGL(split_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->split_g,
+                       c->split_ea, c->split_eb, C, N, s);
     return hipGetLastError();
 }
 
-hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
-                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
-                               double* rowpart, double h, hipStream_t st) {
+hipError_t launch_lower_update(const ze_ctx* c, const double2* A, const double2* Wn,
+                               const double2* Wt, double2* F, double2* Wout, double* rowpart,
+                               double h, hipStream_t st) {
     const int N = c->N;
     const int T = (N + kUT - 1) / kUT;
-    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q, A, Wn,
-                       Wt, F, Wout, rowpart, N, h);
+    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st,
+                       c->split_g, c->split_ea, c->split_eb, c->split_slices, A, Wn, Wt, F, Wout,
+                       rowpart, N, h);
     return hipGetLastError();
 }

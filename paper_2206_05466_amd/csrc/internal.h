@@ -55,14 +55,14 @@ struct ze_ctx {
 
     // Split-precision products (allocated on first use): slice count s, INT8 slices of the
     // A~ and B~^T operands (kSplitMax slices each, rows of ze_split_ldk(N) bytes), their scale
-    // exponents, column-maximum partials, and the buffer for the lower product Q.
+    // exponents, column-maximum partials, and the int32 product slabs.
     int split_slices = 6;
     signed char* split_a = nullptr;
     signed char* split_b = nullptr;
     int* split_ea = nullptr;
     int* split_eb = nullptr;
     double* split_colmax = nullptr;
-    double2* Q = nullptr;
+    int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
 
     // Optional per-phase timing (ze_profile).
     bool prof = false;
@@ -121,11 +121,12 @@ hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch
 int ze_split_ldk(int N);  // bytes per slice row: 2N rounded up to the K stage
 // Slices A (rows) and B (columns) into the context's buffers.
 hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, hipStream_t s);
-// C = A B (lower != 0: only the tiles meeting the lower triangle are formed).
+// C = A B (lower != 0: only the tiles meeting the lower triangle are formed, and left in the
+// int32 slabs for launch_lower_update).
 hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                               int lower, hipStream_t s);
-// The fixed-point update of launch_zgemm_lower_epilogue from a precomputed Q (lower tiles).
-hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
-                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
-                               double* rowpart, double h, hipStream_t s);
-
+// The fixed-point update of launch_zgemm_lower_epilogue, with Q taken from the int32 slabs of
+// the preceding lower split product.
+hipError_t launch_lower_update(const ze_ctx* c, const double2* A, const double2* Wn,
+                               const double2* Wt, double2* F, double2* Wout, double* rowpart,
+                               double h, hipStream_t s);
