@@ -90,6 +90,60 @@ def cpu_baseline(N, om_seed, law, h, K, lmax=32):
     }
 
 
+def ensemble_leg(nsteps):
+    """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step."""
+    import torch
+
+    from paper_2206_05466_amd import Ensemble, Zeuler
+    from workloads import WORKLOADS, ensemble_sizes, omega_coeffs
+
+    cfg = WORKLOADS["ensemble64"]
+    sizes = ensemble_sizes(cfg["nsim"], cfg["size_seed"], cfg["sizes"])
+    h, K, tol = cfg["h"], 8, 1e-12
+    ctxs = {n: Zeuler(n) for n in sorted(set(sizes))}
+    Ws = [ctxs[n].basis_assemble(omega_coeffs(n, cfg["seed0"] + j, cfg["law"])) for j, n in enumerate(sizes)]
+    Wseq = [W.clone() for W in Ws]
+    ens = Ensemble(sizes)
+    ens.run(Ws, h, 1, tol, K)  # first run: autotuning + capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(Ws, h, nsteps, tol, K)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its, res = ens.stats()
+    choice, tune_ms = ens.tuning()
+    # sequential reference: the single-simulation entry point, one simulation after the other
+    seq_steps = max(1, min(5, nsteps))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(seq_steps):
+        for j, n in enumerate(sizes):
+            ctxs[n].isomp_step(Wseq[j], h, tol, K)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t1
+    ens.close()
+    for z in ctxs.values():
+        z.close()
+    n3 = sum(n ** 3 for n in sizes) / len(sizes)
+    return {
+        "workload": f"ensemble64: {len(sizes)} simulations, N drawn from {cfg['sizes']} (seed "
+                    f"{cfg['size_seed']}), simulation j seeded {cfg['seed0']}+j, sigma_l law "
+                    f"{cfg['law']}, h={h}, tol={tol}, maxit={K}, FP64 products",
+        "sizes_histogram": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+        "steps": nsteps,
+        "s_per_ensemble_step": dt / nsteps,
+        "aggregate_steps_per_s": len(sizes) * nsteps / dt,
+        "last_step_iters": {"min": min(its), "max": max(its)},
+        "last_step_max_resid": max(res),
+        "fp64_equiv_tflops": 12.0 * n3 * len(sizes) * sum(its) / len(its) / (dt / nsteps) / 1e12,
+        "autotune": {"choice": choice, "ms_per_step": tune_ms,
+                     "candidates": ["128x64 tiles, largest first", "128x64 tiles, interleaved",
+                                    "64x64 tiles, largest first", "64x64 tiles, interleaved"]},
+        "sequential_single_context_steps_per_s": len(sizes) * seq_steps / dts,
+        "speedup_vs_sequential": (len(sizes) * nsteps / dt) / (len(sizes) * seq_steps / dts),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--split-slices", default="4,5,6",
                     help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=50,
+                    help="steps of the 64-simulation ensemble leg (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, run 3 plain device-to-device copies of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -210,6 +266,10 @@ def main():
             "note": "same W0 and step count as the FP64 run; product_PW includes the slicing kernels",
         }
 
+    ens_out = None
+    if args.ensemble_steps > 0:
+        ens_out = ensemble_leg(args.ensemble_steps)
+
     s_per_step = dt / args.steps
     gemm_ms, gemm_n = prof["product_PW"]
     gemm_avg_s = gemm_ms / gemm_n * 1e-3
@@ -268,6 +328,7 @@ def main():
         "lower_product_tflops": 4.0 * N ** 3 / (low_ms * 1e-3) / 1e12,
         "cpu_baseline": None,
         "split_precision": split,
+        "ensemble": ens_out,
     }
     if not args.no_cpu_baseline:
         K = int(round(sum(iters) / len(iters)))

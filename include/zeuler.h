@@ -164,6 +164,51 @@ ze_status ze_profile(ze_ctx* ctx, int on);
  */
 ze_status ze_profile_read(ze_ctx* ctx, double* ms, long long* launches, int reset);
 
+/*
+ * Ensembles: nsim independent simulations of (possibly different) sizes N_j stepped together,
+ * for statistics over many initial conditions.  Each phase of a fixed-point evaluation is one
+ * grouped launch over all simulations' tiles, and a step's launches are captured once into a
+ * HIP graph that is replayed (one graph launch per step) on a private default-priority stream
+ * ordered after / before the caller's stream with events.  Per-simulation device flags keep the
+ * stopping rule of ze_isomp_step: a simulation stops at its first evaluation whose residual is
+ * below tol (or at K = maxit), without host synchronisation.  The first run of an ensemble
+ * times the candidate tile shapes / work orders on copies of the inputs and keeps the fastest.
+ *
+ * ze_ensemble_create -- set up nsim simulations of sizes N[0..nsim-1] (host array,
+ *   1 <= N_j <= 4096, nsim <= 4096); stream: the caller's hipStream_t (NULL = default).
+ *   Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Synchronous.
+ */
+ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out);
+
+/* Free an ensemble (synchronises).  NULL is accepted. */
+ze_status ze_ensemble_destroy(ze_ens* ens);
+
+/*
+ * ze_ensemble_run -- nsteps IsoMP steps of every simulation (eqs. (isomp), (isomp_iter)).
+ *   W      host array of nsim device pointers, W[j] an N_j x N_j complex128 skew-Hermitian
+ *          matrix (in: W_n, out: W_{n+nsteps}); the pointers may change between calls.
+ *   h, tol as in ze_isomp_step; K = maxit (1..64); prec: ZE_PREC_FP64.
+ * Asynchronous on the caller's stream; ze_ensemble_stats reads the outcome of the last step.
+ * Errors: ZE_EINVAL (also for prec != ZE_PREC_FP64), ZE_ENOMEM, ZE_EHIP.
+ */
+ze_status ze_ensemble_run(ze_ens* ens, void* const* W, double h, double tol, int K, int nsteps,
+                          int prec);
+
+/* One step: ze_ensemble_run with nsteps = 1. */
+ze_status ze_ensemble_step(ze_ens* ens, void* const* W, double h, double tol, int K, int prec);
+
+/*
+ * ze_ensemble_stats -- evaluations done (iters[j]) and final residual (resid[j]) of every
+ * simulation in the last step; host arrays of nsim entries, either may be NULL.  Synchronous.
+ */
+ze_status ze_ensemble_stats(ze_ens* ens, int* iters, double* resid);
+
+/*
+ * ze_ensemble_tuning -- the autotuner's choice (0..3: 2 * tile shape + work order; -1 before
+ * the first run) and the measured milliseconds per step of the four candidates (ms[4]).
+ */
+ze_status ze_ensemble_tuning(ze_ens* ens, int* choice, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

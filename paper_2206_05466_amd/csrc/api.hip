@@ -105,7 +105,11 @@ ze_status ze_destroy(ze_ctx* c) {
     return ZE_OK;
 }
 
-ze_status ze_create(int N, void* stream, ze_ctx** out) {
+ze_status ze_create(int N, void* stream, ze_ctx** out) { return ze_create_ctx(N, stream, true, out); }
+
+}  // extern "C"
+
+ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
     if (!out) return ZE_EINVAL;
     *out = nullptr;
     if (N < 1 || N > kMaxN) return ZE_EINVAL;
@@ -128,7 +132,8 @@ ze_status ze_create(int N, void* stream, ze_ctx** out) {
         }
     }
     ze_status st = ZE_OK;
-    if (st == ZE_OK) st = dalloc(&c->gemm_part, ze_gemm_part_bytes(c->cap_full, c->cap_low) / sizeof(double));
+    if (st == ZE_OK && split_k)
+        st = dalloc(&c->gemm_part, ze_gemm_part_bytes(c->cap_full, c->cap_low) / sizeof(double));
     if (st == ZE_OK) st = dalloc(&c->fac_l, fl.size());
     if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
     if (st == ZE_OK) st = dalloc(&c->Wn, nn);
@@ -156,6 +161,8 @@ ze_status ze_create(int N, void* stream, ze_ctx** out) {
     *out = c;
     return ZE_OK;
 }
+
+extern "C" {
 
 ze_status ze_stream_solve(ze_ctx* c, const void* W, void* P) {
     if (!c || !W || !P || W == P) return ZE_EINVAL;

@@ -1,0 +1,471 @@
+// Ensembles of independent IsoMP simulations of uneven N (statistics over many initial
+// conditions): every phase of a fixed-point evaluation -- copy, stream solve, A = P W~, lower
+// Q = A P with the update, residual -- runs as ONE grouped launch over a work list of
+// (simulation, tile) items, and the 1 + 4K launches of a step are captured once into a HIP
+// graph and replayed, one graph launch per step.
+//
+// Convergence stays tolerance-driven without host round trips: per-simulation device flags
+// `done` are cleared at the start of a step and set by the residual kernel once the change of
+// W~ is below tol; every later block of that simulation exits at once, so its W keeps the
+// W_{n+1} of the converged evaluation (the same result as ze_isomp_step with maxit = K).
+//
+// Autotuning: the product A = P W~ has two tile shapes (128 x 64 and 64 x 64 complex) and the
+// work lists two orders (largest problems first, or simulations interleaved); the first step
+// times the four graphs on copies of the inputs and keeps the fastest.
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "solve_wg.h"
+#include "tile_f64.h"
+
+namespace {
+
+using namespace zk;
+
+struct EnsProb {
+    int N;
+    int pad;
+    double2* W;  // caller's matrix (in: W_n, out: W_{n+1})
+    double2* Wn;
+    double2* F;
+    double2* P;
+    double2* A;
+    double* rowpart;
+    const double* fl;
+    const double* fd;
+};
+
+constexpr int kCopyParts = 16;
+
+__global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restrict__ probs,
+                                                        int* __restrict__ done) {
+    const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
+    const EnsProb p = probs[sim];
+    const size_t n2 = (size_t)p.N * p.N;
+    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256)
+        p.Wn[e] = p.W[e];
+    if (part == 0 && threadIdx.x == 0) done[sim] = 0;
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(T) void ens_solve_kernel(const EnsProb* __restrict__ probs,
+                                                      const int2* __restrict__ work,
+                                                      const int* __restrict__ done, int eval) {
+    __shared__ double sG[T];
+    __shared__ double2 sY[T];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    solve_pair<T, C>(Wt, p.P, p.fl, p.fd, p.N, it.y, sG, sY);
+}
+
+template <class C>
+__global__ __launch_bounds__(kThreads) void ens_product_kernel(const EnsProb* __restrict__ probs,
+                                                               const int2* __restrict__ work,
+                                                               const int* __restrict__ done,
+                                                               int eval) {
+    __shared__ double smem[2 * C::STAGE];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const int N = p.N;
+    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    const int tiles_n = (N + C::BNC - 1) / C::BNC;
+    const int row0 = (it.y / tiles_n) * C::BM, col0 = (it.y % tiles_n) * C::BNC;
+    d4 acc[C::MT][C::NT];
+    const int nk = (N + kBK - 1) / kBK;
+    mainloop<C>(p.P, N, row0, N, Wt, N, col0, N, N, 0, nk, smem, acc);
+    store_tile<C>(acc, p.A, N, row0, col0);
+}
+
+constexpr int kLowSmemE = 2 * LowCfg::STAGE > kTile * kTile ? 2 * LowCfg::STAGE : kTile * kTile;
+
+__global__ __launch_bounds__(kThreads) void ens_lower_kernel(const EnsProb* __restrict__ probs,
+                                                             const int2* __restrict__ work,
+                                                             const int* __restrict__ done,
+                                                             int eval, double h) {
+    __shared__ double smem[kLowSmemE];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const int N = p.N;
+    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    int I, J;
+    lower_tile(it.y, I, J);
+    d4 acc[LowCfg::MT][LowCfg::NT];
+    const int nk = (N + kBK - 1) / kBK;
+    mainloop<LowCfg>(p.A, N, I * kTile, N, p.P, N, J * kTile, N, N, 0, nk, smem, acc);
+    lower_epilogue(acc, I, J, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, N, h, smem);
+}
+
+__global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restrict__ probs,
+                                                        int* __restrict__ done,
+                                                        int* __restrict__ iters,
+                                                        double* __restrict__ resid, int eval,
+                                                        double tol) {
+    __shared__ double sm[256];
+    const int sim = blockIdx.x;
+    if (done[sim]) return;
+    const EnsProb p = probs[sim];
+    const int N = p.N, T = (N + kTile - 1) / kTile;
+    double best = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        double v = 0.0;
+        for (int X = 0; X < T; ++X) v += p.rowpart[(size_t)X * N + i];
+        best = (v != v || v > best) ? v : best;
+    }
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = sm[threadIdx.x + s], a = sm[threadIdx.x];
+            sm[threadIdx.x] = (o != o || o > a) ? o : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double r = sm[0];
+        resid[sim] = r;
+        iters[sim] = eval;
+        if (!(r < tol) && r == r && r < INFINITY) return;  // keep iterating
+        done[sim] = 1;  // converged, or non-finite: stop this simulation
+    }
+}
+
+// Grouped launches of one evaluation phase, by the solve's (T, C) for the largest N.
+template <int T, int C>
+hipError_t launch_ens_solve(const EnsProb* probs, const int2* work, int n, const int* done,
+                            int eval, hipStream_t s) {
+    hipLaunchKernelGGL((ens_solve_kernel<T, C>), dim3(n), dim3(T), 0, s, probs, work, done, eval);
+    return hipGetLastError();
+}
+
+hipError_t ens_solve(int maxN, const EnsProb* probs, const int2* work, int n, const int* done,
+                     int eval, hipStream_t s) {
+    if (maxN <= 64) return launch_ens_solve<64, 1>(probs, work, n, done, eval, s);
+    if (maxN <= 128) return launch_ens_solve<128, 1>(probs, work, n, done, eval, s);
+    if (maxN <= 256) return launch_ens_solve<256, 1>(probs, work, n, done, eval, s);
+    if (maxN <= 512) return launch_ens_solve<256, 2>(probs, work, n, done, eval, s);
+    if (maxN <= 1024) return launch_ens_solve<256, 4>(probs, work, n, done, eval, s);
+    if (maxN <= 2048) return launch_ens_solve<256, 8>(probs, work, n, done, eval, s);
+    return launch_ens_solve<256, 16>(probs, work, n, done, eval, s);
+}
+
+using WideCfg = FullCfg;  // 128 x 64 complex
+using SmallCfg = LowCfg;  // 64 x 64 complex
+
+int tiles_of(int N, int variant) {
+    if (variant == 0) return ((N + WideCfg::BM - 1) / WideCfg::BM) * ((N + WideCfg::BNC - 1) / WideCfg::BNC);
+    return ((N + SmallCfg::BM - 1) / SmallCfg::BM) * ((N + SmallCfg::BNC - 1) / SmallCfg::BNC);
+}
+
+// Work list: all (sim, item) pairs, either largest N first or simulations interleaved.
+std::vector<int2> make_work(const std::vector<int>& N, const std::vector<int>& count, int order) {
+    std::vector<int2> w;
+    const int ns = (int)N.size();
+    if (order == 0) {
+        std::vector<int> idx(ns);
+        for (int i = 0; i < ns; ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return N[a] > N[b]; });
+        for (int i : idx)
+            for (int k = 0; k < count[i]; ++k) w.push_back(make_int2(i, k));
+    } else {
+        int maxc = 0;
+        for (int c : count) maxc = std::max(maxc, c);
+        for (int k = 0; k < maxc; ++k)
+            for (int i = 0; i < ns; ++i)
+                if (k < count[i]) w.push_back(make_int2(i, k));
+    }
+    return w;
+}
+
+}  // namespace
+
+struct ze_ens {
+    int nsim = 0, maxN = 0;
+    hipStream_t user = nullptr;   // caller's stream
+    hipStream_t own = nullptr;    // private stream the graph is captured on and replayed on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+    std::vector<int> N;
+    std::vector<ze_ctx*> ctx;     // per-simulation factors and workspaces
+    std::vector<EnsProb> hp;
+    EnsProb* dp = nullptr;
+    int* done = nullptr;
+    int* iters = nullptr;
+    double* resid = nullptr;
+    int2* work_solve = nullptr;
+    int n_solve = 0;
+    int2* work_prod[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [variant][order]
+    int n_prod[2] = {0, 0};
+    int2* work_low[2] = {nullptr, nullptr};                            // [order]
+    int n_low = 0;
+    // tuning
+    int variant = -1, order = 0;
+    double tune_ms[4] = {0, 0, 0, 0};
+    // captured graph and the parameters it was captured with
+    hipGraphExec_t exec = nullptr;
+    int g_variant = -1, g_order = -1, g_K = -1;
+    double g_h = 0.0, g_tol = -1.0;
+};
+
+namespace {
+
+hipError_t record_step(ze_ens* e, double h, double tol, int K, int variant, int order,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done);
+    hipError_t err = hipGetLastError();
+    for (int k = 1; k <= K && err == hipSuccess; ++k) {
+        err = ens_solve(e->maxN, e->dp, e->work_solve, e->n_solve, e->done, k, s);
+        if (err != hipSuccess) break;
+        if (variant == 0)
+            hipLaunchKernelGGL(ens_product_kernel<WideCfg>, dim3(e->n_prod[0]), dim3(kThreads), 0, s,
+                               e->dp, e->work_prod[0][order], e->done, k);
+        else
+            hipLaunchKernelGGL(ens_product_kernel<SmallCfg>, dim3(e->n_prod[1]), dim3(kThreads), 0, s,
+                               e->dp, e->work_prod[1][order], e->done, k);
+        err = hipGetLastError();
+        if (err != hipSuccess) break;
+        hipLaunchKernelGGL(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
+                           e->work_low[order], e->done, k, h);
+        err = hipGetLastError();
+        if (err != hipSuccess) break;
+        hipLaunchKernelGGL(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done,
+                           e->iters, e->resid, k, tol);
+        err = hipGetLastError();
+    }
+    return err;
+}
+
+hipError_t capture(ze_ens* e, double h, double tol, int K, int variant, int order) {
+    if (e->exec) {
+        (void)hipGraphExecDestroy(e->exec);
+        e->exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t err = hipStreamBeginCapture(e->own, hipStreamCaptureModeRelaxed);
+    if (err != hipSuccess) return err;
+    hipError_t rec = record_step(e, h, tol, K, variant, order, e->own);
+    err = hipStreamEndCapture(e->own, &g);
+    if (rec != hipSuccess) err = rec;
+    if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (err == hipSuccess) {
+        e->g_variant = variant;
+        e->g_order = order;
+        e->g_K = K;
+        e->g_h = h;
+        e->g_tol = tol;
+    }
+    return err;
+}
+
+template <class T>
+ze_status ens_alloc(T** p, size_t n) {
+    if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T) + 64) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return ZE_ENOMEM;
+    }
+    return ZE_OK;
+}
+
+ze_status upload_work(const std::vector<int2>& w, int2** dst) {
+    ZE_TRY(ens_alloc(dst, w.size()));
+    ZE_HIP(hipMemcpy(*dst, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return ZE_OK;
+}
+
+ze_status set_pointers(ze_ens* e, void* const* W) {
+    bool changed = false;
+    for (int i = 0; i < e->nsim; ++i) {
+        if (!W[i]) return ZE_EINVAL;
+        if (e->hp[i].W != W[i]) {
+            e->hp[i].W = static_cast<double2*>(W[i]);
+            changed = true;
+        }
+    }
+    if (changed) {  // rare: drain the private stream, then replace the descriptors
+        ZE_HIP(hipStreamSynchronize(e->own));
+        ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
+    }
+    return ZE_OK;
+}
+
+// Times the four (tile shape, order) graphs on copies of the inputs; keeps the fastest.
+ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K) {
+    std::vector<double2*> copies(e->nsim, nullptr);
+    std::vector<EnsProb> saved = e->hp;
+    ze_status st = ZE_OK;
+    for (int i = 0; i < e->nsim && st == ZE_OK; ++i) {
+        const size_t n2 = (size_t)e->N[i] * e->N[i];
+        st = ens_alloc(&copies[i], n2);
+        if (st == ZE_OK &&
+            hipMemcpyAsync(copies[i], W[i], n2 * sizeof(double2), hipMemcpyDeviceToDevice, e->own) != hipSuccess)
+            st = ZE_EHIP;
+    }
+    double best = 1e300;
+    for (int cand = 0; cand < 4 && st == ZE_OK; ++cand) {
+        const int variant = cand >> 1, order = cand & 1;
+        if (st == ZE_OK) st = set_pointers(e, reinterpret_cast<void* const*>(copies.data()));
+        if (st != ZE_OK) break;
+        if (capture(e, h, tol, K, variant, order) != hipSuccess) {
+            st = ze_record_hip(hipGetLastError(), "ensemble autotune capture");
+            break;
+        }
+        float ms = 0.f;
+        hipError_t err = hipGraphLaunch(e->exec, e->own);  // warm-up
+        if (err == hipSuccess) err = hipEventRecord(e->t0, e->own);
+        for (int r = 0; r < 3 && err == hipSuccess; ++r) err = hipGraphLaunch(e->exec, e->own);
+        if (err == hipSuccess) err = hipEventRecord(e->t1, e->own);
+        if (err == hipSuccess) err = hipEventSynchronize(e->t1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e->t0, e->t1);
+        if (err != hipSuccess) {
+            st = ze_record_hip(err, "ensemble autotune run");
+            break;
+        }
+        e->tune_ms[cand] = ms / 3.0;
+        if (ms < best) {
+            best = ms;
+            e->variant = variant;
+            e->order = order;
+        }
+    }
+    (void)hipStreamSynchronize(e->own);
+    for (double2* c : copies)
+        if (c) (void)hipFree(c);
+    // restore the caller's pointers (set_pointers compares against hp)
+    for (int i = 0; i < e->nsim; ++i) e->hp[i].W = nullptr;
+    if (e->exec) {
+        (void)hipGraphExecDestroy(e->exec);
+        e->exec = nullptr;
+    }
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ze_status ze_ensemble_destroy(ze_ens* e) {
+    if (!e) return ZE_OK;
+    if (e->own) (void)hipStreamSynchronize(e->own);
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    for (ze_ctx* c : e->ctx) ze_destroy(c);
+    (void)hipFree(e->dp);
+    (void)hipFree(e->done);
+    (void)hipFree(e->iters);
+    (void)hipFree(e->resid);
+    (void)hipFree(e->work_solve);
+    for (auto& v : e->work_prod)
+        for (int2* p : v) (void)hipFree(p);
+    for (int2* p : e->work_low) (void)hipFree(p);
+    for (hipEvent_t ev : {e->ev_in, e->ev_out, e->t0, e->t1})
+        if (ev) (void)hipEventDestroy(ev);
+    if (e->own) (void)hipStreamDestroy(e->own);
+    delete e;
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out) {
+    if (!out || !N || nsim < 1 || nsim > 4096) return ZE_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < nsim; ++i)
+        if (N[i] < 1 || N[i] > 4096) return ZE_EINVAL;
+    ze_ens* e = new ze_ens();
+    e->nsim = nsim;
+    e->user = reinterpret_cast<hipStream_t>(stream);
+    e->N.assign(N, N + nsim);
+    e->maxN = *std::max_element(e->N.begin(), e->N.end());
+    ze_status st = ZE_OK;
+    auto fail = [&](ze_status s) {
+        ze_ensemble_destroy(e);
+        return s;
+    };
+    if (hipStreamCreateWithFlags(&e->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&e->t0) != hipSuccess || hipEventCreate(&e->t1) != hipSuccess)
+        return fail(ze_record_hip(hipGetLastError(), "ensemble stream/events"));
+    e->ctx.assign(nsim, nullptr);
+    e->hp.resize(nsim);
+    for (int i = 0; i < nsim; ++i) {
+        st = ze_create_ctx(e->N[i], e->own, false, &e->ctx[i]);
+        if (st != ZE_OK) return fail(st);
+        ze_ctx* c = e->ctx[i];
+        e->hp[i] = EnsProb{c->N, 0, nullptr, c->Wn, c->F, c->P, c->A, c->rowpart, c->fac_l, c->fac_dinv};
+    }
+    if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
+    if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);
+    if ((st = ens_alloc(&e->iters, (size_t)nsim)) != ZE_OK) return fail(st);
+    if ((st = ens_alloc(&e->resid, (size_t)nsim)) != ZE_OK) return fail(st);
+    std::vector<int> cs(nsim), c0(nsim), c1(nsim), cl(nsim);
+    for (int i = 0; i < nsim; ++i) {
+        const int n = e->N[i], T = (n + kTile - 1) / kTile;
+        cs[i] = n / 2 + 1;
+        c0[i] = tiles_of(n, 0);
+        c1[i] = tiles_of(n, 1);
+        cl[i] = T * (T + 1) / 2;
+    }
+    std::vector<int2> ws = make_work(e->N, cs, 0);
+    e->n_solve = (int)ws.size();
+    if ((st = upload_work(ws, &e->work_solve)) != ZE_OK) return fail(st);
+    for (int order = 0; order < 2; ++order) {
+        std::vector<int2> w0 = make_work(e->N, c0, order), w1 = make_work(e->N, c1, order);
+        std::vector<int2> wl = make_work(e->N, cl, order);
+        e->n_prod[0] = (int)w0.size();
+        e->n_prod[1] = (int)w1.size();
+        e->n_low = (int)wl.size();
+        if ((st = upload_work(w0, &e->work_prod[0][order])) != ZE_OK) return fail(st);
+        if ((st = upload_work(w1, &e->work_prod[1][order])) != ZE_OK) return fail(st);
+        if ((st = upload_work(wl, &e->work_low[order])) != ZE_OK) return fail(st);
+    }
+    if (hipMemcpy(e->dp, e->hp.data(), nsim * sizeof(EnsProb), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ze_record_hip(hipGetLastError(), "ensemble descriptors"));
+    *out = e;
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K, int nsteps,
+                          int prec) {
+    if (!e || !W || !std::isfinite(h) || !(tol >= 0.0) || !std::isfinite(tol) || K < 1 || K > 64 ||
+        nsteps < 0)
+        return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64) return ZE_EINVAL;
+    // order after the caller's pending work
+    ZE_HIP(hipEventRecord(e->ev_in, e->user));
+    ZE_HIP(hipStreamWaitEvent(e->own, e->ev_in, 0));
+    if (e->variant < 0) ZE_TRY(autotune(e, W, h, tol, K));
+    ZE_TRY(set_pointers(e, W));
+    if (!e->exec || e->g_variant != e->variant || e->g_order != e->order || e->g_K != K ||
+        e->g_h != h || e->g_tol != tol)
+        ZE_HIP(capture(e, h, tol, K, e->variant, e->order));
+    for (int n = 0; n < nsteps; ++n) ZE_HIP(hipGraphLaunch(e->exec, e->own));
+    ZE_HIP(hipEventRecord(e->ev_out, e->own));
+    ZE_HIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_step(ze_ens* e, void* const* W, double h, double tol, int K, int prec) {
+    return ze_ensemble_run(e, W, h, tol, K, 1, prec);
+}
+
+ze_status ze_ensemble_stats(ze_ens* e, int* iters, double* resid) {
+    if (!e) return ZE_EINVAL;
+    ZE_HIP(hipStreamSynchronize(e->own));
+    if (iters) ZE_HIP(hipMemcpy(iters, e->iters, e->nsim * sizeof(int), hipMemcpyDeviceToHost));
+    if (resid) ZE_HIP(hipMemcpy(resid, e->resid, e->nsim * sizeof(double), hipMemcpyDeviceToHost));
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_tuning(ze_ens* e, int* choice, double* ms) {
+    if (!e) return ZE_EINVAL;
+    if (choice) *choice = e->variant < 0 ? -1 : 2 * e->variant + e->order;
+    if (ms)
+        for (int i = 0; i < 4; ++i) ms[i] = e->tune_ms[i];
+    return ZE_OK;
+}
+
+}  // extern "C"

@@ -76,6 +76,9 @@ constexpr int kMaxN = 16384;
 // Largest number of slices of the split-precision products.
 constexpr int kSplitMax = 8;
 
+// ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
+ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out);
+
 // Host: the factors held in ze_ctx::fac_l / fac_dinv (N (N+1) / 2 entries each).
 void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd);
 

@@ -1,0 +1,268 @@
+// Device building blocks of the FP64 complex products (shared by the single-problem and the
+// ensemble kernels).  See gemm_f64.hip for the method.
+#pragma once
+
+#include "internal.h"
+
+namespace zk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kBK = 8;         // complex k per LDS stage (16 real k = 4 MFMA k-steps)
+
+template <int BM_, int BNC_, int WM_, int WNC_>
+struct Cfg {
+    static constexpr int BM = BM_;     // block rows
+    static constexpr int BNC = BNC_;   // block columns (complex)
+    static constexpr int WM = WM_;     // wave rows
+    static constexpr int WNC = WNC_;   // wave columns (complex)
+    static constexpr int MT = WM / 16;        // MFMA tiles per wave, rows
+    static constexpr int NT = 2 * WNC / 16;   // MFMA tiles per wave, real columns
+    static constexpr int WAVES_N = BNC / WNC;
+    static constexpr int AS_LD = BM + 1;           // A stage: [16 real k][BM rows] (+1 pad)
+    static constexpr int BS_LD = 2 * BNC + 2;      // B stage: [8 complex k][2*BNC doubles] (+pad)
+    static constexpr int AS = 2 * kBK * AS_LD;
+    static constexpr int BS = kBK * BS_LD;
+    static constexpr int STAGE = AS + BS;          // doubles per stage
+    static constexpr int A_LOADS = BM * kBK / kThreads;
+    static constexpr int B_LOADS = kBK * BNC / kThreads;
+    static_assert((BM / WM) * (BNC / WNC) == 4, "4 waves per block");
+    static_assert(A_LOADS * kThreads == BM * kBK && B_LOADS * kThreads == kBK * BNC, "loads");
+};
+
+// Global -> register loads of one K stage (zero outside the matrices).
+template <class C>
+__device__ inline void load_stage(const double2* __restrict__ A, int lda, int row0, int M,
+                                  const double2* __restrict__ B, int ldb, int col0, int Nc,
+                                  int K, int k0, double2 (&ra)[C::A_LOADS],
+                                  double2 (&rb)[C::B_LOADS]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < C::A_LOADS; ++j) {
+        const int idx = tid + j * kThreads;
+        const int r = idx / kBK, kc = idx % kBK;
+        const int gr = row0 + r, gk = k0 + kc;
+        ra[j] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < C::B_LOADS; ++j) {
+        const int idx = tid + j * kThreads;
+        const int kc = idx / C::BNC, c = idx % C::BNC;
+        const int gk = k0 + kc, gc = col0 + c;
+        rb[j] = (gk < K && gc < Nc) ? B[(size_t)gk * ldb + gc] : make_double2(0.0, 0.0);
+    }
+}
+
+template <class C>
+__device__ inline void store_stage(double* __restrict__ st, const double2 (&ra)[C::A_LOADS],
+                                   const double2 (&rb)[C::B_LOADS]) {
+    const int tid = threadIdx.x;
+    double* as = st;
+    double* bs = st + C::AS;
+#pragma unroll
+    for (int j = 0; j < C::A_LOADS; ++j) {
+        const int idx = tid + j * kThreads;
+        const int r = idx / kBK, kc = idx % kBK;
+        as[(2 * kc) * C::AS_LD + r] = ra[j].x;
+        as[(2 * kc + 1) * C::AS_LD + r] = ra[j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < C::B_LOADS; ++j) {
+        const int idx = tid + j * kThreads;
+        const int kc = idx / C::BNC, c = idx % C::BNC;
+        *reinterpret_cast<double2*>(bs + kc * C::BS_LD + 2 * c) = rb[j];
+    }
+}
+
+// MFMAs of one stage for this wave.
+template <class C>
+__device__ inline void compute_stage(const double* __restrict__ st, int wrow, int wcc,
+                                     d4 (&acc)[C::MT][C::NT]) {
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 4, l16 = lane & 15;
+    const int t = q & 1;        // real-k parity: 0 -> Re(a) row of B~, 1 -> Im(a) row
+    const int u = lane & 1;     // real-column parity: 0 -> Re(c), 1 -> Im(c)
+    const double sgn = (t == 1 && u == 0) ? -1.0 : 1.0;
+    const double* as = st;
+    const double* bs = st + C::AS;
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+        const int kk = 4 * k4 + q;
+        const int kc = 2 * k4 + (q >> 1);
+        double a[C::MT], b[C::NT];
+#pragma unroll
+        for (int mt = 0; mt < C::MT; ++mt) a[mt] = as[kk * C::AS_LD + wrow + mt * 16 + l16];
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) {
+            const int cc = wcc + nt * 16 + l16;
+            b[nt] = sgn * bs[kc * C::BS_LD + (cc & ~1) + (t ^ u)];
+        }
+#pragma unroll
+        for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < C::NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+    }
+}
+
+// acc = A[row0:row0+BM, K range] * B[K range, col0:col0+BNC] for the K stages [kb, ke),
+// double-buffered in LDS.
+template <class C>
+__device__ inline void mainloop(const double2* __restrict__ A, int lda, int row0, int M,
+                                const double2* __restrict__ B, int ldb, int col0, int Nc, int K,
+                                int kb, int ke, double* smem, d4 (&acc)[C::MT][C::NT]) {
+    const int wave = threadIdx.x >> 6;
+    const int wrow = (wave / C::WAVES_N) * C::WM;
+    const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
+#pragma unroll
+    for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    if (kb >= ke) return;
+
+    double2 ra[C::A_LOADS], rb[C::B_LOADS];
+    load_stage<C>(A, lda, row0, M, B, ldb, col0, Nc, K, kb * kBK, ra, rb);
+    store_stage<C>(smem, ra, rb);
+    __syncthreads();
+    for (int kt = kb; kt < ke; ++kt) {
+        const bool more = kt + 1 < ke;
+        const int buf = (kt - kb) & 1;
+        if (more) load_stage<C>(A, lda, row0, M, B, ldb, col0, Nc, K, (kt + 1) * kBK, ra, rb);
+        compute_stage<C>(smem + buf * C::STAGE, wrow, wcc, acc);
+        if (more) store_stage<C>(smem + (buf ^ 1) * C::STAGE, ra, rb);
+        __syncthreads();
+    }
+}
+
+using FullCfg = Cfg<128, 64, 64, 32>;
+
+// Store a block's accumulators (MFMA layout of config C) to C~ (complex N x N), bounds-checked.
+template <class C>
+__device__ inline void store_tile(const d4 (&acc)[C::MT][C::NT], double2* Cm, int N, int row0,
+                                  int col0) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wrow = (wave / C::WAVES_N) * C::WM;
+    const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
+    const int q = lane >> 4, l16 = lane & 15;
+    double* Cd = reinterpret_cast<double*>(Cm);
+    const size_t ld = 2 * (size_t)N;
+#pragma unroll
+    for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt) {
+            const int cc = 2 * col0 + wcc + nt * 16 + l16;
+            if (cc >= 2 * N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wrow + mt * 16 + q + 4 * r;
+                if (row < N) Cd[(size_t)row * ld + cc] = acc[mt][nt][r];
+            }
+        }
+}
+
+__device__ inline void store_full_tile(const d4 (&acc)[FullCfg::MT][FullCfg::NT], double2* Cm,
+                                       int N, int row0, int col0) {
+    store_tile<FullCfg>(acc, Cm, N, row0, col0);
+}
+
+// ---------------------------------------------------------------- lower product + epilogue
+using LowCfg = Cfg<64, 64, 32, 32>;
+constexpr int kTile = 64;  // square complex tile of the lower-triangle product
+
+// Tile index b of the lower triangle -> (I, J), I >= J, b = I (I+1)/2 + J.
+__device__ inline void lower_tile(int b, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    while (i * (i + 1) / 2 > b) --i;
+    I = i;
+    J = b - i * (i + 1) / 2;
+}
+
+// Epilogue of tile (I, J) of Q = A P (lower triangle, I >= J), acc in MFMA layout:
+//   F    = Wn + h/2 (A - A^H) + h^2/4 Q,    Wout = Wt + h/2 (A - A^H) - h^2/4 Q,
+// both written to the lower entries and mirrored (-conj) to the upper ones, Re Q_RR := 0.
+// Row-sum slots: rowpart[X*N + r] for tile-column X and row r.  Tile (I, J), I > J, writes
+// the row sums of its |F - W~| entries to slots (J, rows of I) and their column sums (the
+// mirrored upper entries, which lie in the rows of J) to slots (I, rows of J); a diagonal
+// tile (I, I) writes the full row sums of its rows to (I, rows of I).  Every slot with r < N
+// is written exactly once, so the reduction is deterministic.
+__device__ inline void lower_epilogue(const d4 (&acc)[LowCfg::MT][LowCfg::NT], int I, int J,
+                                      const double2* __restrict__ Am,
+                                      const double2* __restrict__ Wn, const double2* Wt,
+                                      double2* F, double2* __restrict__ Wout,
+                                      double* __restrict__ rowpart, int N, double h,
+                                      double* absd) {
+    using C = LowCfg;
+    const int row0 = I * kTile;
+    const int col0 = J * kTile;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wrow = (wave / C::WAVES_N) * C::WM;
+    const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
+    const int q = lane >> 4, l16 = lane & 15;
+    const int comp = lane & 1;  // 0: real part, 1: imaginary part
+    const double* Ad = reinterpret_cast<const double*>(Am);
+    const double* Wnd = reinterpret_cast<const double*>(Wn);
+    const double* Wtd = reinterpret_cast<const double*>(Wt);
+    double* Fd = reinterpret_cast<double*>(F);
+    double* Wod = reinterpret_cast<double*>(Wout);
+    const size_t ld = 2 * (size_t)N;
+    const double h2 = 0.5 * h, h4 = 0.25 * h * h;
+
+#pragma unroll
+    for (int mt = 0; mt < C::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C::NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lr = wrow + mt * 16 + q + 4 * r;           // local row
+                const int lcc = wcc + nt * 16 + l16;                 // local real column
+                const int lc = lcc >> 1;                              // local complex column
+                const int R = row0 + lr, c = col0 + lc;
+                const bool ok = R < N && c < N && c <= R;
+                double d = 0.0;
+                if (ok) {
+                    double qv = acc[mt][nt][r];
+                    if (c == R && comp == 0) qv = 0.0;  // Q is skew-Hermitian: Re Q_RR = 0
+                    const size_t o = (size_t)R * ld + 2 * (size_t)c + comp;
+                    const size_t ot = (size_t)c * ld + 2 * (size_t)R + comp;  // transposed entry
+                    const double arc = Ad[o], acr = Ad[ot];
+                    const double cv = comp ? arc + acr : arc - acr;  // (A - A^H)_{Rc}
+                    const double wt = Wtd[o];
+                    const double f = Wnd[o] + h2 * cv + h4 * qv;
+                    const double wo = wt + h2 * cv - h4 * qv;
+                    d = f - wt;
+                    Fd[o] = f;
+                    Wod[o] = wo;
+                    if (c != R) {  // upper triangle: -conj
+                        Fd[ot] = comp ? f : -f;
+                        Wod[ot] = comp ? wo : -wo;
+                    }
+                }
+                const double dpart = __shfl_xor(d, 1);
+                if (comp == 0) absd[lr * kTile + lc] = ok ? sqrt(d * d + dpart * dpart) : 0.0;
+            }
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    if (I != J) {
+        if (tid < kTile) {  // row sums -> slot (J, row0 + tid)
+            double s = 0.0;
+            for (int k = 0; k < kTile; ++k) s += absd[tid * kTile + k];
+            if (row0 + tid < N) rowpart[(size_t)J * N + row0 + tid] = s;
+        } else if (tid < 2 * kTile) {  // column sums -> slot (I, col0 + j)
+            const int j = tid - kTile;
+            double s = 0.0;
+            for (int k = 0; k < kTile; ++k) s += absd[k * kTile + j];
+            if (col0 + j < N) rowpart[(size_t)I * N + col0 + j] = s;
+        }
+    } else if (tid < kTile) {
+        double s = 0.0;
+        for (int k = 0; k < kTile; ++k) s += absd[tid * kTile + k];
+        for (int k = tid + 1; k < kTile; ++k) s += absd[k * kTile + tid];
+        if (row0 + tid < N) rowpart[(size_t)I * N + row0 + tid] = s;
+    }
+}
+
+
+}  // namespace zk

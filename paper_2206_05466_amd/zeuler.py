@@ -38,6 +38,12 @@ SIGNATURES = {
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
+    "ze_ensemble_create": (_c_int, [_c_int, _P_int, _vp, ctypes.POINTER(_vp)]),
+    "ze_ensemble_destroy": (_c_int, [_vp]),
+    "ze_ensemble_run": (_c_int, [_vp, ctypes.POINTER(_vp), _c_double, _c_double, _c_int, _c_int, _c_int]),
+    "ze_ensemble_step": (_c_int, [_vp, ctypes.POINTER(_vp), _c_double, _c_double, _c_int, _c_int]),
+    "ze_ensemble_stats": (_c_int, [_vp, _P_int, _P_double]),
+    "ze_ensemble_tuning": (_c_int, [_vp, _P_int, _P_double]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -201,3 +207,72 @@ class Zeuler:
         n = (ctypes.c_longlong * 4)()
         _check(self.lib.ze_profile_read(self._ctx, ms, n, int(bool(reset))), "ze_profile_read")
         return {PHASES[i]: (ms[i], n[i]) for i in range(4)}
+
+
+class Ensemble:
+    """nsim independent simulations of sizes N_j stepped together (ze_ensemble_*)."""
+
+    def __init__(self, sizes, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libzeuler needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.sizes = [int(n) for n in sizes]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
+        self._ens = ctypes.c_void_p()
+        _check(self.lib.ze_ensemble_create(len(self.sizes), arr, ctypes.c_void_p(st.cuda_stream),
+                                           ctypes.byref(self._ens)), "ze_ensemble_create")
+
+    def close(self):
+        if getattr(self, "_ens", None) is not None and self._ens.value:
+            self.lib.ze_ensemble_destroy(self._ens)
+            self._ens = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _ptrs(self, Ws):
+        import torch
+
+        if len(Ws) != len(self.sizes):
+            raise ValueError("one matrix per simulation")
+        for W, n in zip(Ws, self.sizes):
+            if (not isinstance(W, torch.Tensor) or W.dtype != torch.complex128 or W.device != self.device
+                    or not W.is_contiguous() or tuple(W.shape) != (n, n)):
+                raise ValueError(f"each W must be a contiguous ({n}, {n}) complex128 tensor on {self.device}")
+        return (ctypes.c_void_p * len(Ws))(*[W.data_ptr() for W in Ws])
+
+    def run(self, Ws, h: float, nsteps: int = 1, tol: float = 1e-12, K: int = 8,
+            prec: int = PREC_FP64):
+        """nsteps steps of every simulation, each W updated in place."""
+        _check(self.lib.ze_ensemble_run(self._ens, self._ptrs(Ws), float(h), float(tol), int(K),
+                                        int(nsteps), int(prec)), "ze_ensemble_run")
+
+    def stats(self):
+        """(evaluations, residual) per simulation for the last step."""
+        n = len(self.sizes)
+        its = (ctypes.c_int * n)()
+        res = (ctypes.c_double * n)()
+        _check(self.lib.ze_ensemble_stats(self._ens, its, res), "ze_ensemble_stats")
+        return list(its), list(res)
+
+    def tuning(self):
+        """(choice, [ms per step of the 4 candidates]) of the autotuner."""
+        ch = ctypes.c_int(0)
+        ms = (ctypes.c_double * 4)()
+        _check(self.lib.ze_ensemble_tuning(self._ens, ctypes.byref(ch), ms), "ze_ensemble_tuning")
+        return ch.value, list(ms)
+

@@ -278,3 +278,53 @@ def test_isomp_split_ten_steps_n64(dev, s):
     c0, c1 = O.casimirs(W0, 4), O.casimirs(W, 4)
     rel = np.abs(c1 - c0) / np.abs(c0)
     assert rel[1] < 1e-11 and rel[3] < 1e-11
+
+
+# ------------------------------------------------------------------ ensemble (graph replays)
+def test_ensemble_matches_oracle_and_eager_each_replay(dev):
+    """One graph replay per step; between replays the eager single-context path runs on the
+    same inputs (and the host synchronises); every replay must match it and the oracle."""
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [48, 64, 100, 128, 32, 96]
+    h, tol, K = 0.01, 1e-12, 8
+    W0s = [w0(n, 40 + j) for j, n in enumerate(sizes)]
+    Wd = [to_dev(W) for W in W0s]
+    We = [to_dev(W) for W in W0s]
+    Wr = [W.copy() for W in W0s]
+    ctxs = [ctx(n) for n in sizes]
+    with Ensemble(sizes) as ens:
+        for step in range(3):
+            ens.run(Wd, h, 1, tol, K)
+            its, res = ens.stats()
+            for j, z in enumerate(ctxs):
+                info = z.isomp_step(We[j], h, tol, K)
+                Wr[j], k, _ = O.isomp_step(Wr[j], h, tol, K)
+                assert its[j] == info.iters == k, (step, j, its[j], info.iters, k)
+                assert res[j] < tol
+            torch.cuda.synchronize()
+            for j in range(len(sizes)):
+                a, b = to_host(Wd[j]), to_host(We[j])
+                assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b), (step, j)
+                assert np.linalg.norm(a - Wr[j]) <= 1e-12 * np.linalg.norm(Wr[j]), (step, j)
+        choice, ms = ens.tuning()
+        assert 0 <= choice < 4 and min(ms) > 0
+    for z in ctxs:
+        z.close()
+
+
+def test_ensemble_multi_step_run_and_fixed_K(dev):
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [64, 40]
+    W0s = [w0(n, 7 + j) for j, n in enumerate(sizes)]
+    Wd = [to_dev(W) for W in W0s]
+    with Ensemble(sizes) as ens:
+        ens.run(Wd, 0.02, 4, 0.0, 2)  # tol 0: exactly K = 2 evaluations per step
+        its, _ = ens.stats()
+        assert its == [2, 2]
+    for j, n in enumerate(sizes):
+        W = W0s[j]
+        for _ in range(4):
+            W, _, _ = O.isomp_step(W, 0.02, 0.0, 2)
+        assert np.linalg.norm(to_host(Wd[j]) - W) <= 1e-12 * np.linalg.norm(W)
