@@ -102,12 +102,25 @@ ze_status ze_isomp_step(ze_ctx* ctx, void* W, double h, double tol, int maxit, i
                         int* iters, double* resid);
 
 /*
- * ze_isomp_run -- nsteps calls of ze_isomp_step on the same W.
+ * ze_isomp_run -- nsteps IsoMP steps on the same W (the first exactly as ze_isomp_step; the
+ * later ones start their fixed-point iteration as ze_set_initial_guess selects).
  *   iters, resid  host arrays of nsteps entries, may be NULL.
  * Stops at the first step that returns an error and returns it.
  */
 ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, int nsteps,
                        int prec, int* iters, double* resid);
+
+/*
+ * ze_set_initial_guess -- starting iterate of the fixed-point iteration (eq. (isomp_iter))
+ * for the steps after the first in one ze_isomp_run call; the paper does not fix it.
+ *   mode 0  W~ = W_n (default; ze_isomp_step always uses it).
+ *   mode 1  W~ = 2 W_n - F_prev, F_prev the previous step's converged midpoint: W~
+ *           approximates W half a step ahead, so this linear extrapolation is second-order
+ *           accurate and usually saves one evaluation per step; the iteration still runs
+ *           to the same tolerance and reaches the same fixed point.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
 
 /*
  * ze_casimirs -- C_k(W) = Tr(W^k), k = 1..kmax (eq. (W_pow)), in FP64, from powers of W

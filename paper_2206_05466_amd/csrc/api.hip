@@ -184,8 +184,12 @@ ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     return ZE_OK;
 }
 
-ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                        int* iters, double* resid) {
+namespace {
+
+// One step; with `extrapolate` the fixed point starts from 2 W_n - F (F = the previous step's
+// converged midpoint, still in c->F) instead of W_n.
+ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                          bool extrapolate, int* iters, double* resid) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
     const int N = c->N;
@@ -196,6 +200,10 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
+    if (extrapolate) {
+        ZE_HIP(launch_extrapolate(Wu, c->F, N, s));
+        Wt = c->F;
+    }
     double r = 0.0;
     int k = 0;
     const bool prof = c->prof;
@@ -240,13 +248,20 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     return ZE_OK;
 }
 
+}  // namespace
+
+ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                        int* iters, double* resid) {
+    return isomp_step_impl(c, W, h, tol, maxit, prec, false, iters, resid);
+}
+
 ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps, int prec,
                        int* iters, double* resid) {
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = ze_isomp_step(c, W, h, tol, maxit, prec, &k, &r);
+        ze_status st = isomp_step_impl(c, W, h, tol, maxit, prec, n > 0 && c->guess_mode == 1, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) return st;
@@ -306,6 +321,12 @@ ze_status ze_basis_assemble(ze_ctx* c, const void* omega, void* W) {
     (void)hipFree(scratch);
     if (e != hipSuccess) return ze_record_hip(e, "launch_basis_assemble");
     if (e2 != hipSuccess) return ze_record_hip(e2, "hipStreamSynchronize(basis)");
+    return ZE_OK;
+}
+
+ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
+    if (!c || mode < 0 || mode > 1) return ZE_EINVAL;
+    c->guess_mode = mode;
     return ZE_OK;
 }
 

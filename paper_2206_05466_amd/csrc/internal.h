@@ -64,6 +64,10 @@ struct ze_ctx {
     double* split_colmax = nullptr;
     int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
 
+    // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
+    // (F = the previous step's converged midpoint, left in ze_ctx::F).
+    int guess_mode = 0;
+
     // Optional per-phase timing (ze_profile).
     bool prof = false;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -133,3 +137,7 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
 hipError_t launch_lower_update(const ze_ctx* c, const double2* A, const double2* Wn,
                                const double2* Wt, double2* F, double2* Wout, double* rowpart,
                                double h, hipStream_t s);
+
+// F <- 2 W - F (N x N complex).
+hipError_t launch_extrapolate(const double2* W, double2* F, int N, hipStream_t s);
+

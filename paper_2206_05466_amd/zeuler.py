@@ -36,6 +36,7 @@ SIGNATURES = {
     "ze_basis_assemble": (_c_int, [_vp, _vp, _vp]),
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
+    "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
     "ze_ensemble_create": (_c_int, [_c_int, _P_int, _vp, ctypes.POINTER(_vp)]),
@@ -192,6 +193,11 @@ class Zeuler:
         _check(self.lib.ze_basis_assemble(self._ctx, ctypes.c_void_p(om.data_ptr()), self._mat(W, "W")),
                "ze_basis_assemble")
         return W
+
+    def set_initial_guess(self, mode: int):
+        """0: each step starts from W_n; 1: steps after the first in isomp_run start from the
+        extrapolation 2 W_n - F_prev of the previous converged midpoint."""
+        _check(self.lib.ze_set_initial_guess(self._ctx, int(mode)), "ze_set_initial_guess")
 
     def set_split_slices(self, slices: int):
         """Slices per operand of the PREC_SPLIT products (2..8)."""

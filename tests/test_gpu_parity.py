@@ -328,3 +328,19 @@ def test_ensemble_multi_step_run_and_fixed_K(dev):
         for _ in range(4):
             W, _, _ = O.isomp_step(W, 0.02, 0.0, 2)
         assert np.linalg.norm(to_host(Wd[j]) - W) <= 1e-12 * np.linalg.norm(W)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "split"])
+def test_isomp_run_extrapolated_guess(dev, prec_name):
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT
+
+    N, h = 128, 0.005
+    W0 = w0(N, 0)
+    Wr, it_ref, _ = O.isomp_run(W0, h, 6, 1e-12, 50, extrapolate=True)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_initial_guess(1)
+        its, res = z.isomp_run(Wd, h, 6, 1e-12, 50, prec=PREC_SPLIT if prec_name == "split" else PREC_FP64)
+        W = to_host(Wd)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
