@@ -1,0 +1,154 @@
+"""Parity at the workloads' full sizes, in the launch configurations bench.py times.
+
+The oracle cannot build the full-spectrum W_0 at N = 4096 quickly (a full eigen-decomposition
+of every block), so the step tests start from the oracle's own assembly of the same seeded
+coefficients truncated to low degree (same N, same kernels and launch shapes on the GPU);
+the full-spectrum GPU basis assembly is checked on sampled diagonals, which the oracle can
+form one at a time.  Bars: 1e-10 relative Frobenius after the steps (the spec bar), the
+same evaluation counts, and Casimir drift <= 1e-11.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import WORKLOADS, ensemble_sizes, omega_coeffs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_05466_amd import load_library
+
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X, dtype=np.complex128)).cuda()
+
+
+def to_host(X):
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def casimir_ok(W0, W):
+    c0, c1 = O.casimirs(W0, 4), O.casimirs(W, 4)
+    r = np.abs(c1 - c0) / np.abs(c0)
+    return r[1] < 1e-11 and r[3] < 1e-11 and abs(c1[2] - c0[2]) / np.linalg.norm(W0) ** 3 < 1e-11
+
+
+def test_n4096_steps_fp64_and_split(dev):
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
+
+    cfg = WORKLOADS["n4096"]
+    N, h, L = cfg["N"], cfg["h"], 32
+    W0 = O.assemble(N, omega_coeffs(N, 0, cfg["law"], lmax=L), lmax=L)
+    Wr, it_ref, _ = O.isomp_run(W0, h, 2, cfg["tol"], cfg["maxit"], extrapolate=True)
+    z = Zeuler(N)
+    z.set_initial_guess(1)
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, 2, cfg["tol"], cfg["maxit"], PREC_FP64)
+    W = to_host(Wd)
+    assert its == it_ref and max(res) < cfg["tol"], (its, it_ref)
+    assert rel(W, Wr) < 1e-12, rel(W, Wr)
+    assert np.abs(W + W.conj().T).max() == 0.0
+    z.set_split_slices(5)
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, 2, cfg["tol"], cfg["maxit"], PREC_SPLIT)
+    W = to_host(Wd)
+    assert its == it_ref and rel(W, Wr) < 1e-10, (its, rel(W, Wr))
+    z.close()
+
+
+def test_n4096_basis_sampled_diagonals(dev):
+    from paper_2206_05466_amd import Zeuler
+
+    N = 4096
+    om = omega_coeffs(N, 0, "inv1.5")
+    z = Zeuler(N)
+    W = z.basis_assemble(om)
+    for m in (0, 1, 1500, 4094, 4095):
+        _, V = O.eigvecs(N, m)
+        n = N - m
+        i = np.arange(n)
+        l = np.arange(m, N)
+        ref = 1j * (V @ om[l * l + l + m])
+        got = W[torch.arange(n) + m, torch.arange(n)].cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), m
+        if m > 0:
+            refu = 1j * (-1) ** m * (V @ om[l * l + l - m])
+            gotu = W[torch.arange(n), torch.arange(n) + m].cpu().numpy()
+            assert np.abs(gotu - refu).max() <= 1e-11 * np.abs(refu).max(), m
+    z.close()
+
+
+def test_n2048_twenty_steps(dev):
+    from paper_2206_05466_amd import Zeuler
+
+    cfg = WORKLOADS["n2048"]
+    N, h, L = cfg["N"], cfg["h"], 48
+    W0 = O.assemble(N, omega_coeffs(N, 0, cfg["law"], lmax=L), lmax=L)
+    Wr, it_ref, _ = O.isomp_run(W0, h, cfg["steps"], cfg["tol"], cfg["maxit"], extrapolate=True)
+    z = Zeuler(N)
+    z.set_initial_guess(1)
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, cfg["steps"], cfg["tol"], cfg["maxit"])
+    W = to_host(Wd)
+    assert its == it_ref and max(res) < cfg["tol"]
+    assert rel(W, Wr) < 1e-10, rel(W, Wr)
+    assert casimir_ok(W0, W)
+    z.close()
+
+
+def test_n512_hundred_steps(dev):
+    from paper_2206_05466_amd import Zeuler
+
+    cfg = WORKLOADS["n512"]
+    N, h = cfg["N"], cfg["h"]
+    W0 = O.assemble(N, omega_coeffs(N, 0, cfg["law"]))
+    Wr, it_ref, _ = O.isomp_run(W0, h, cfg["steps"], cfg["tol"], cfg["maxit"])
+    z = Zeuler(N)
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, cfg["steps"], cfg["tol"], cfg["maxit"])
+    W = to_host(Wd)
+    assert its == it_ref and max(res) < cfg["tol"]
+    assert rel(W, Wr) < 1e-10, rel(W, Wr)
+    assert casimir_ok(W0, W)
+    z.close()
+
+
+def test_ensemble64_sampled_members(dev):
+    """The full 64-simulation ensemble (bench.py's leg) for 5 steps; one member of each size
+    class is checked against the oracle."""
+    from paper_2206_05466_amd import Ensemble, Zeuler
+
+    cfg = WORKLOADS["ensemble64"]
+    sizes = ensemble_sizes(cfg["nsim"], cfg["size_seed"], cfg["sizes"])
+    h, tol, K, steps = cfg["h"], 1e-12, 8, 5
+    picks = [sizes.index(n) for n in sorted(set(sizes))]
+    # checked members start from the oracle's own assembly; the others from the GPU basis
+    W0s = {j: O.assemble(sizes[j], omega_coeffs(sizes[j], cfg["seed0"] + j, cfg["law"])) for j in picks}
+    ctxs = {n: Zeuler(n) for n in sorted(set(sizes))}
+    Ws = [to_dev(W0s[j]) if j in W0s else
+          ctxs[n].basis_assemble(omega_coeffs(n, cfg["seed0"] + j, cfg["law"])) for j, n in enumerate(sizes)]
+    for z in ctxs.values():
+        z.close()
+    with Ensemble(sizes) as ens:
+        ens.run(Ws, h, steps, tol, K)
+        its, res = ens.stats()
+    assert max(res) < tol
+    for j in picks:
+        Wr, it_ref, _ = O.isomp_run(W0s[j], h, steps, tol, K)
+        assert its[j] == it_ref[-1]
+        assert rel(to_host(Ws[j]), Wr) < 1e-12, (j, sizes[j])
