@@ -88,9 +88,11 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->F);
     dfree(c->P);
     dfree(c->A);
+    dfree(c->Q);
     dfree(c->rowpart);
     dfree(c->blockmax);
     dfree(c->gemm_part);
+    dfree(c->low_order);
     dfree(c->split_a);
     dfree(c->split_b);
     dfree(c->split_ea);
@@ -140,6 +142,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
     if (st == ZE_OK) st = dalloc(&c->F, nn);
     if (st == ZE_OK) st = dalloc(&c->P, nn);
     if (st == ZE_OK) st = dalloc(&c->A, nn);
+    if (st == ZE_OK) st = dalloc(&c->Q, nn);
     if (st == ZE_OK) st = dalloc(&c->rowpart, (size_t)T * N);
     if (st == ZE_OK) st = dalloc(&c->blockmax, (size_t)(N + 255) / 256 + 1);
     if (st == ZE_OK) st = dalloc(&c->resid, 1);
@@ -152,7 +155,15 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
         ze_destroy(c);
         return st;
     }
+    std::vector<int> order;
+    ze_lower_tile_order(N, order);
+    if (st == ZE_OK) st = dalloc(&c->low_order, order.size());
+    if (st != ZE_OK) {
+        ze_destroy(c);
+        return st;
+    }
     hipError_t e = hipMemcpy(c->fac_l, fl.data(), fl.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->low_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->fac_dinv, fd.data(), fd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         ze_destroy(c);
@@ -218,9 +229,10 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
         if (split) {
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, s));
-            ZE_HIP(launch_lower_update(c, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
         } else {
-            ZE_HIP(launch_zgemm_lower_epilogue(c, c->A, c->P, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+            ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s));
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
         }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
         ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));

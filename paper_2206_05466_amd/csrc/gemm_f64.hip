@@ -3,7 +3,7 @@
 // The commutator and the P W~ P term of the fixed-point map (eq. (isomp_iter)) need two
 // complex products per evaluation (Sec. 3.1): A = P W~ (full) and Q = A P, of which only the
 // lower triangle is formed, since Q is skew-Hermitian; C = A - A^H and the update of W~ are
-// applied in the epilogue of the second product.
+// applied afterwards by the coalesced update kernel (gemm_split.hip).
 //
 // Complex arithmetic on a real MFMA.  With X (M x K complex) stored interleaved (re, im),
 // its memory is a real M x 2K matrix X~.  For B (K x N complex) let B~ be the real 2K x 2N
@@ -14,6 +14,8 @@
 //
 // MFMA operand layout (16x16x4, f64): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator register r of lane l holds D[l/16 + 4*r][l%16].
+
+#include <vector>
 
 #include "tile_f64.h"
 
@@ -107,22 +109,25 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_fixup(double2* __restrict_
     store_full_tile(acc, Cm, N, (tile / tiles_n) * C::BM, (tile % tiles_n) * C::BNC);
 }
 
-constexpr int kLowSmem = 2 * LowCfg::STAGE > kTile * kTile ? 2 * LowCfg::STAGE : kTile * kTile;
 
-__global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
-    const double2* __restrict__ Am, const double2* __restrict__ Pm, const double2* __restrict__ Wn,
-    const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
-    int N, double h, int full, int S, double* __restrict__ part) {
+// Lower-triangle product Q = A P into a buffer (64 x 64 complex tiles meeting the lower
+// triangle; the fixed-point update reads them).  Tiles are taken from `order` (8 x 8
+// super-tile order): the whole-tile blocks of XCD x (blocks b with b % 8 == x) run the
+// contiguous chunk x * full/8 .. (x+1) * full/8 - 1 of it, so the tiles an XCD holds at once
+// share A row panels and P column panels in its L2.
+__global__ __launch_bounds__(kThreads) void zgemm_lower_kernel(
+    const double2* __restrict__ Am, const double2* __restrict__ Pm, double2* __restrict__ Q,
+    int N, int full, int S, double* __restrict__ part, const int* __restrict__ order) {
     using C = LowCfg;
-    __shared__ double smem[kLowSmem];
+    __shared__ double smem[2 * C::STAGE];
     const int nk = (N + kBK - 1) / kBK;
     const int b = blockIdx.x;
     int tile, kb = 0, ke = nk;
     if (b < full) {
-        tile = b;
+        tile = (full & 7) == 0 ? order[(b & 7) * (full >> 3) + (b >> 3)] : order[b];
     } else {
         const int e = b - full, s = e % S;
-        tile = full + e / S;
+        tile = order[full + e / S];
         kb = (int)((long long)s * nk / S);
         ke = (int)((long long)(s + 1) * nk / S);
     }
@@ -131,22 +136,21 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_epilogue_kernel(
     d4 acc[C::MT][C::NT];
     mainloop<C>(Am, N, I * kTile, N, Pm, N, J * kTile, N, N, kb, ke, smem, acc);
     if (b < full)
-        lower_epilogue(acc, I, J, Am, Wn, Wt, F, Wout, rowpart, N, h, smem);
+        store_tile<C>(acc, Q, N, I * kTile, J * kTile);
     else
         store_partial<C>(part + (size_t)(b - full) * (C::MT * C::NT * 4 * kThreads), acc);
 }
 
-__global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(
-    const double2* __restrict__ Am, const double2* __restrict__ Wn, const double2* Wt, double2* F,
-    double2* __restrict__ Wout, double* __restrict__ rowpart, int N, double h, int full, int S,
-    const double* __restrict__ part) {
+__global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(double2* __restrict__ Q, int N,
+                                                              int full, int S,
+                                                              const double* __restrict__ part,
+                                                              const int* __restrict__ order) {
     using C = LowCfg;
-    __shared__ double smem[kTile * kTile];
     int I, J;
-    lower_tile(full + blockIdx.x, I, J);
+    lower_tile(order[full + blockIdx.x], I, J);
     d4 acc[C::MT][C::NT];
     sum_partials<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads), S, acc);
-    lower_epilogue(acc, I, J, Am, Wn, Wt, F, Wout, rowpart, N, h, smem);
+    store_tile<C>(acc, Q, N, I * kTile, J * kTile);
 }
 
 // ---------------------------------------------------------------- residual reduction
@@ -194,6 +198,15 @@ __global__ __launch_bounds__(kRedThreads) void max_final_kernel(const double* __
 
 }  // namespace
 
+void ze_lower_tile_order(int N, std::vector<int>& order) {
+    const int T = (N + kTile - 1) / kTile;
+    order.clear();
+    for (int si = 0; si * 8 < T; ++si)
+        for (int sj = 0; sj <= si; ++sj)
+            for (int I = si * 8; I < si * 8 + 8 && I < T; ++I)
+                for (int J = sj * 8; J < sj * 8 + 8 && J <= I; ++J) order.push_back(I * (I + 1) / 2 + J);
+}
+
 size_t ze_gemm_part_bytes(int cap_full, int cap_low) {
     const size_t a = (size_t)cap_full * FullCfg::MT * FullCfg::NT * 4 * kThreads;
     const size_t b = (size_t)cap_low * LowCfg::MT * LowCfg::NT * 4 * kThreads;
@@ -206,7 +219,7 @@ hipError_t ze_gemm_capacity(int* cap_full, int* cap_low) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, zgemm_f64_kernel, kThreads, 0);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, zgemm_lower_epilogue_kernel, kThreads, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, zgemm_lower_kernel, kThreads, 0);
     if (e != hipSuccess) return e;
     *cap_full = (nf > 0 ? nf : 1) * cus;
     *cap_low = (nl > 0 ? nl : 1) * cus;
@@ -228,18 +241,17 @@ hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B,
     return hipGetLastError();
 }
 
-hipError_t launch_zgemm_lower_epilogue(const ze_ctx* c, const double2* A, const double2* P,
-                                       const double2* Wn, const double2* Wt, double2* F,
-                                       double2* Wout, double* rowpart, double h, hipStream_t s) {
+hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
+                              hipStream_t s) {
     const int N = c->N;
     const int T = (N + kTile - 1) / kTile;
     const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low);
-    hipLaunchKernelGGL(zgemm_lower_epilogue_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads),
-                       0, s, A, P, Wn, Wt, F, Wout, rowpart, N, h, sp.full, sp.S, c->gemm_part);
+    hipLaunchKernelGGL(zgemm_lower_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A,
+                       P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
-    hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail), dim3(kThreads), 0, s, A, Wn, Wt, F, Wout,
-                       rowpart, N, h, sp.full, sp.S, c->gemm_part);
+    hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail), dim3(kThreads), 0, s, Q, N, sp.full, sp.S,
+                       c->gemm_part, c->low_order);
     return hipGetLastError();
 }
 

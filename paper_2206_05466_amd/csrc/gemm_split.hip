@@ -311,14 +311,19 @@ __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __re
 // For tile (I, J), I >= J, of 64 x 64 complex entries, from Q (lower tiles valid):
 //   F = Wn + h/2 (A - A^H) + h^2/4 Q,  Wout = Wt + h/2 (A - A^H) - h^2/4 Q   (Re Q_RR := 0),
 // lower entries written directly, upper ones (-conj) through an LDS transpose so every
-// global access is a coalesced row segment; row sums of |F - Wt| into the same slots as the
-// fused FP64 epilogue (see zgemm_lower_epilogue_kernel).
+// global access is a coalesced row segment.  Row sums of |F - Wt| go to slots
+// rowpart[X*N + r] (tile-column X, row r): tile (I, J), I > J, writes the row sums of its
+// entries to slots (J, rows of I) and their column sums (the mirrored upper entries, which
+// lie in the rows of J) to slots (I, rows of J); a diagonal tile writes the full row sums of
+// its rows to (I, rows of I).  Every slot with r < N is written once (deterministic sums).
 constexpr int kUT = 64;
+// Q comes from the FP64 lower product (Qf != nullptr, complex N x N, lower tiles) or from the
+// int32 slabs of the split lower product (G, ea, eb, s).
 __global__ __launch_bounds__(kThreads) void lower_update_kernel(
-    const int* __restrict__ G, const int* __restrict__ ea, const int* __restrict__ eb, int s,
-    const double2* __restrict__ Am, const double2* __restrict__ Wn,
-    const double2* Wt, double2* F, double2* __restrict__ Wout, double* __restrict__ rowpart,
-    int N, double h) {
+    const double2* __restrict__ Qf, const int* __restrict__ G, const int* __restrict__ ea,
+    const int* __restrict__ eb, int s, const double2* __restrict__ Am,
+    const double2* __restrict__ Wn, const double2* Wt, double2* F, double2* __restrict__ Wout,
+    double* __restrict__ rowpart, int N, double h) {
     __shared__ double2 sT[kUT][kUT + 1];
     double(*sD)[kUT + 1] = reinterpret_cast<double(*)[kUT + 1]>(&sT[0][0]);  // reused at the end
     const int b = blockIdx.x;
@@ -347,16 +352,20 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
         double2 f = make_double2(0.0, 0.0), wo = f, d = f;
         if (ok) {
             const size_t o = (size_t)R * N + c;
-            double2 qv = make_double2(0.0, 0.0);  // Q = A P from the int32 slabs
-            for (int t = s + 1; t >= 2; --t) {
-                const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
-                const double w = ldexp(1.0, -7 * t);
-                qv.x += w * (double)g.x;
-                qv.y += w * (double)g.y;
+            double2 qv = make_double2(0.0, 0.0);
+            if (Qf) {
+                qv = Qf[o];
+            } else {  // Q = A P from the int32 slabs
+                for (int t = s + 1; t >= 2; --t) {
+                    const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
+                    const double w = ldexp(1.0, -7 * t);
+                    qv.x += w * (double)g.x;
+                    qv.y += w * (double)g.y;
+                }
+                const int ex = ea[R] + eb[c];
+                qv.x = ldexp(qv.x, ex);
+                qv.y = ldexp(qv.y, ex);
             }
-            const int ex = ea[R] + eb[c];
-            qv.x = ldexp(qv.x, ex);
-            qv.y = ldexp(qv.y, ex);
             if (c == R) qv.x = 0.0;
             const double2 arc = Am[o], acr = sT[lc][r];
             const double cr = arc.x - acr.x, ci = arc.y + acr.y;  // (A - A^H)_{Rc}
@@ -455,12 +464,12 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     return hipGetLastError();
 }
 
-hipError_t launch_lower_update(const ze_ctx* c, const double2* A, const double2* Wn,
-                               const double2* Wt, double2* F, double2* Wout, double* rowpart,
-                               double h, hipStream_t st) {
+hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
+                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
+                               double* rowpart, double h, hipStream_t st) {
     const int N = c->N;
     const int T = (N + kUT - 1) / kUT;
-    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q,
                        c->split_g, c->split_ea, c->split_eb, c->split_slices, A, Wn, Wt, F, Wout,
                        rowpart, N, h);
     return hipGetLastError();

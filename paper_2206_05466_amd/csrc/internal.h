@@ -44,6 +44,7 @@ struct ze_ctx {
     double2* F = nullptr;    // fixed-point iterate W~ (after the first evaluation)
     double2* P = nullptr;    // stream matrix
     double2* A = nullptr;    // A = P W~
+    double2* Q = nullptr;    // lower product Q = A P (FP64 path)
     double* rowpart = nullptr;  // ntile64 x N partial row sums of |F - W~|
     double* blockmax = nullptr; // per-block maxima of the row sums
     double* resid = nullptr;    // device scalar: infinity norm of F - W~
@@ -52,6 +53,7 @@ struct ze_ctx {
     // Products: concurrent-block capacities and the split-K partial buffer.
     int cap_full = 0, cap_low = 0;
     double* gemm_part = nullptr;
+    int* low_order = nullptr;  // lower-product tiles in 8 x 8 super-tile order
 
     // Split-precision products (allocated on first use): slice count s, INT8 slices of the
     // A~ and B~^T operands (kSplitMax slices each, rows of ze_split_ldk(N) bytes), their scale
@@ -95,18 +97,16 @@ hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hi
 // split-K partial buffer (ze_ctx::gemm_part) those capacities need.
 hipError_t ze_gemm_capacity(int* cap_full, int* cap_low);
 size_t ze_gemm_part_bytes(int cap_full, int cap_low);
+// Lower-triangle tile indices (64 x 64 complex tiles) in 8 x 8 super-tile order.
+void ze_lower_tile_order(int N, std::vector<int>& order);
 
 // C = A B, all N x N complex (leading dimension N = c->N), FP64 MFMA.
 hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                             hipStream_t s);
 
-// Lower-triangle Q = A P with the fixed-point epilogue:
-//   F     = Wn + h/2 (A - A^H) + h^2/4 Q       (both triangles; may alias Wt)
-//   Wout  = Wt + h/2 (A - A^H) - h^2/4 Q       (both triangles)
-//   rowpart[X*N + r]  partial row sums of |F - Wt| (see the kernel for the slot layout)
-hipError_t launch_zgemm_lower_epilogue(const ze_ctx* c, const double2* A, const double2* P,
-                                       const double2* Wn, const double2* Wt, double2* F,
-                                       double2* Wout, double* rowpart, double h, hipStream_t s);
+// Lower-triangle Q = A P (64 x 64 complex tiles meeting the lower triangle) into Q.
+hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
+                              hipStream_t s);
 
 // resid = max_r sum_X rowpart[X*N + r]  (NaN propagates).
 hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, double* resid, int N,
@@ -132,12 +132,15 @@ hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2
 // int32 slabs for launch_lower_update).
 hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                               int lower, hipStream_t s);
-// The fixed-point update of launch_zgemm_lower_epilogue, with Q taken from the int32 slabs of
-// the preceding lower split product.
-hipError_t launch_lower_update(const ze_ctx* c, const double2* A, const double2* Wn,
-                               const double2* Wt, double2* F, double2* Wout, double* rowpart,
-                               double h, hipStream_t s);
+// The fixed-point update from the lower product:
+//   F     = Wn + h/2 (A - A^H) + h^2/4 Q       (both triangles; may alias Wt)
+//   Wout  = Wt + h/2 (A - A^H) - h^2/4 Q       (both triangles)
+//   rowpart[X*N + r]  partial row sums of |F - Wt| (slot layout in gemm_split.hip)
+// with Q read from Q (FP64, lower tiles) or, if Q is null, from the int32 slabs of the
+// preceding split lower product.
+hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
+                               const double2* Wn, const double2* Wt, double2* F, double2* Wout,
+                               double* rowpart, double h, hipStream_t s);
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, hipStream_t s);
-
