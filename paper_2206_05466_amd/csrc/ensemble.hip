@@ -1,7 +1,7 @@
 // Ensembles of independent IsoMP simulations of uneven N (statistics over many initial
 // conditions): every phase of a fixed-point evaluation -- copy, stream solve, A = P W~, lower
-// Q = A P with the update, residual -- runs as ONE grouped launch over a work list of
-// (simulation, tile) items, and the 1 + 4K launches of a step are captured once into a HIP
+// Q = A P, the update, residual -- runs as ONE grouped launch over a work list of
+// (simulation, tile) items, and the 1 + 5K launches of a step are captured once into a HIP
 // graph and replayed, one graph launch per step.
 //
 // Convergence stays tolerance-driven without host round trips: per-simulation device flags
@@ -19,6 +19,7 @@
 
 #include "solve_wg.h"
 #include "tile_f64.h"
+#include "update_tile.h"
 
 namespace {
 
@@ -32,6 +33,7 @@ struct EnsProb {
     double2* F;
     double2* P;
     double2* A;
+    double2* Q;
     double* rowpart;
     const double* fl;
     const double* fd;
@@ -81,24 +83,35 @@ __global__ __launch_bounds__(kThreads) void ens_product_kernel(const EnsProb* __
     store_tile<C>(acc, p.A, N, row0, col0);
 }
 
-constexpr int kLowSmemE = 2 * LowCfg::STAGE > kTile * kTile ? 2 * LowCfg::STAGE : kTile * kTile;
-
 __global__ __launch_bounds__(kThreads) void ens_lower_kernel(const EnsProb* __restrict__ probs,
                                                              const int2* __restrict__ work,
-                                                             const int* __restrict__ done,
-                                                             int eval, double h) {
-    __shared__ double smem[kLowSmemE];
+                                                             const int* __restrict__ done) {
+    __shared__ double smem[2 * LowCfg::STAGE];
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
     const int N = p.N;
-    const double2* Wt = eval == 1 ? p.Wn : p.F;
     int I, J;
     lower_tile(it.y, I, J);
     d4 acc[LowCfg::MT][LowCfg::NT];
     const int nk = (N + kBK - 1) / kBK;
     mainloop<LowCfg>(p.A, N, I * kTile, N, p.P, N, J * kTile, N, N, 0, nk, smem, acc);
-    lower_epilogue(acc, I, J, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, N, h, smem);
+    store_tile<LowCfg>(acc, p.Q, N, I * kTile, J * kTile);
+}
+
+__global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __restrict__ probs,
+                                                               const int2* __restrict__ work,
+                                                               const int* __restrict__ done,
+                                                               int eval, double h) {
+    __shared__ double2 sT[kUT][kUT + 1];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    int I, J;
+    lower_tile(it.y, I, J);
+    lower_update_tile(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W, p.rowpart,
+                      p.N, h, sT);
 }
 
 __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restrict__ probs,
@@ -229,6 +242,10 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int variant, int 
         err = hipGetLastError();
         if (err != hipSuccess) break;
         hipLaunchKernelGGL(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
+                           e->work_low[order], e->done);
+        err = hipGetLastError();
+        if (err != hipSuccess) break;
+        hipLaunchKernelGGL(ens_update_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
                            e->work_low[order], e->done, k, h);
         err = hipGetLastError();
         if (err != hipSuccess) break;
@@ -395,7 +412,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         st = ze_create_ctx(e->N[i], e->own, false, &e->ctx[i]);
         if (st != ZE_OK) return fail(st);
         ze_ctx* c = e->ctx[i];
-        e->hp[i] = EnsProb{c->N, 0, nullptr, c->Wn, c->F, c->P, c->A, c->rowpart, c->fac_l, c->fac_dinv};
+        e->hp[i] = EnsProb{c->N, 0, nullptr, c->Wn, c->F, c->P, c->A, c->Q, c->rowpart, c->fac_l, c->fac_dinv};
     }
     if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);

@@ -26,9 +26,11 @@
 
 #include <type_traits>
 
-#include "internal.h"
+#include "update_tile.h"
 
 namespace {
+
+using namespace zk;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -308,115 +310,18 @@ __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __re
 }
 
 // ---------------------------------------------------------------- fixed-point update
-// For tile (I, J), I >= J, of 64 x 64 complex entries, from Q (lower tiles valid):
-//   F = Wn + h/2 (A - A^H) + h^2/4 Q,  Wout = Wt + h/2 (A - A^H) - h^2/4 Q   (Re Q_RR := 0),
-// lower entries written directly, upper ones (-conj) through an LDS transpose so every
-// global access is a coalesced row segment.  Row sums of |F - Wt| go to slots
-// rowpart[X*N + r] (tile-column X, row r): tile (I, J), I > J, writes the row sums of its
-// entries to slots (J, rows of I) and their column sums (the mirrored upper entries, which
-// lie in the rows of J) to slots (I, rows of J); a diagonal tile writes the full row sums of
-// its rows to (I, rows of I).  Every slot with r < N is written once (deterministic sums).
-constexpr int kUT = 64;
-// Q comes from the FP64 lower product (Qf != nullptr, complex N x N, lower tiles) or from the
-// int32 slabs of the split lower product (G, ea, eb, s).
 __global__ __launch_bounds__(kThreads) void lower_update_kernel(
     const double2* __restrict__ Qf, const int* __restrict__ G, const int* __restrict__ ea,
     const int* __restrict__ eb, int s, const double2* __restrict__ Am,
     const double2* __restrict__ Wn, const double2* Wt, double2* F, double2* __restrict__ Wout,
     double* __restrict__ rowpart, int N, double h) {
     __shared__ double2 sT[kUT][kUT + 1];
-    double(*sD)[kUT + 1] = reinterpret_cast<double(*)[kUT + 1]>(&sT[0][0]);  // reused at the end
     const int b = blockIdx.x;
     int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= b) ++I;
     while (I * (I + 1) / 2 > b) --I;
     const int J = b - I * (I + 1) / 2;
-    const int R0 = I * kUT, C0 = J * kUT;
-    const int tid = threadIdx.x;
-    const int lc = tid & 63, lr0 = tid >> 6;  // 4 rows per pass, 64 consecutive columns
-    const double h2 = 0.5 * h, h4 = 0.25 * h * h;
-
-    // A^T tile: sT[c][R] = A[C0 + c][R0 + R].
-    for (int rr = lr0; rr < kUT; rr += 4) {
-        const int gr = C0 + rr, gc = R0 + lc;
-        sT[rr][lc] = (gr < N && gc < N) ? Am[(size_t)gr * N + gc] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-
-    double2 fv[kUT / 4], wv[kUT / 4];
-    double dv[kUT / 4];
-#pragma unroll
-    for (int x = 0; x < kUT / 4; ++x) {
-        const int r = lr0 + 4 * x, R = R0 + r, c = C0 + lc;
-        const bool ok = R < N && c < N && c <= R;
-        double2 f = make_double2(0.0, 0.0), wo = f, d = f;
-        if (ok) {
-            const size_t o = (size_t)R * N + c;
-            double2 qv = make_double2(0.0, 0.0);
-            if (Qf) {
-                qv = Qf[o];
-            } else {  // Q = A P from the int32 slabs
-                for (int t = s + 1; t >= 2; --t) {
-                    const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
-                    const double w = ldexp(1.0, -7 * t);
-                    qv.x += w * (double)g.x;
-                    qv.y += w * (double)g.y;
-                }
-                const int ex = ea[R] + eb[c];
-                qv.x = ldexp(qv.x, ex);
-                qv.y = ldexp(qv.y, ex);
-            }
-            if (c == R) qv.x = 0.0;
-            const double2 arc = Am[o], acr = sT[lc][r];
-            const double cr = arc.x - acr.x, ci = arc.y + acr.y;  // (A - A^H)_{Rc}
-            const double2 wn = Wn[o], wt = Wt[o];
-            f = make_double2(wn.x + h2 * cr + h4 * qv.x, wn.y + h2 * ci + h4 * qv.y);
-            wo = make_double2(wt.x + h2 * cr - h4 * qv.x, wt.y + h2 * ci - h4 * qv.y);
-            d = make_double2(f.x - wt.x, f.y - wt.y);
-            F[o] = f;
-            Wout[o] = wo;
-        }
-        fv[x] = f;
-        wv[x] = wo;
-        dv[x] = ok ? sqrt(d.x * d.x + d.y * d.y) : 0.0;
-    }
-    __syncthreads();
-    // Upper entries: F[c][R] = -conj(F[R][c]) for c < R, via sT.
-    for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-        for (int x = 0; x < kUT / 4; ++x) {
-            const int r = lr0 + 4 * x;
-            const double2 v = pass == 0 ? fv[x] : wv[x];
-            sT[lc][r] = make_double2(-v.x, v.y);
-        }
-        __syncthreads();
-        double2* out = pass == 0 ? F : Wout;
-        for (int cr = lr0; cr < kUT; cr += 4) {  // row C0 + cr of the upper tile, columns R0 + lc
-            const int gc = C0 + cr, gR = R0 + lc;
-            if (gc < N && gR < N && gc < gR) out[(size_t)gc * N + gR] = sT[cr][lc];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int x = 0; x < kUT / 4; ++x) sD[lr0 + 4 * x][lc] = dv[x];
-    __syncthreads();
-    if (I != J) {
-        if (tid < kUT) {
-            double sum = 0.0;
-            for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
-            if (R0 + tid < N) rowpart[(size_t)J * N + R0 + tid] = sum;
-        } else if (tid < 2 * kUT) {
-            const int j = tid - kUT;
-            double sum = 0.0;
-            for (int k = 0; k < kUT; ++k) sum += sD[k][j];
-            if (C0 + j < N) rowpart[(size_t)I * N + C0 + j] = sum;
-        }
-    } else if (tid < kUT) {
-        double sum = 0.0;
-        for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
-        for (int k = tid + 1; k < kUT; ++k) sum += sD[k][tid];
-        if (R0 + tid < N) rowpart[(size_t)I * N + R0 + tid] = sum;
-    }
+    lower_update_tile(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, sT);
 }
 
 }  // namespace

@@ -179,90 +179,4 @@ __device__ inline void lower_tile(int b, int& I, int& J) {
     J = b - i * (i + 1) / 2;
 }
 
-// Epilogue of tile (I, J) of Q = A P (lower triangle, I >= J), acc in MFMA layout:
-//   F    = Wn + h/2 (A - A^H) + h^2/4 Q,    Wout = Wt + h/2 (A - A^H) - h^2/4 Q,
-// both written to the lower entries and mirrored (-conj) to the upper ones, Re Q_RR := 0.
-// Row-sum slots: rowpart[X*N + r] for tile-column X and row r.  Tile (I, J), I > J, writes
-// the row sums of its |F - W~| entries to slots (J, rows of I) and their column sums (the
-// mirrored upper entries, which lie in the rows of J) to slots (I, rows of J); a diagonal
-// tile (I, I) writes the full row sums of its rows to (I, rows of I).  Every slot with r < N
-// is written exactly once, so the reduction is deterministic.
-__device__ inline void lower_epilogue(const d4 (&acc)[LowCfg::MT][LowCfg::NT], int I, int J,
-                                      const double2* __restrict__ Am,
-                                      const double2* __restrict__ Wn, const double2* Wt,
-                                      double2* F, double2* __restrict__ Wout,
-                                      double* __restrict__ rowpart, int N, double h,
-                                      double* absd) {
-    using C = LowCfg;
-    const int row0 = I * kTile;
-    const int col0 = J * kTile;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wrow = (wave / C::WAVES_N) * C::WM;
-    const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
-    const int q = lane >> 4, l16 = lane & 15;
-    const int comp = lane & 1;  // 0: real part, 1: imaginary part
-    const double* Ad = reinterpret_cast<const double*>(Am);
-    const double* Wnd = reinterpret_cast<const double*>(Wn);
-    const double* Wtd = reinterpret_cast<const double*>(Wt);
-    double* Fd = reinterpret_cast<double*>(F);
-    double* Wod = reinterpret_cast<double*>(Wout);
-    const size_t ld = 2 * (size_t)N;
-    const double h2 = 0.5 * h, h4 = 0.25 * h * h;
-
-#pragma unroll
-    for (int mt = 0; mt < C::MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < C::NT; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int lr = wrow + mt * 16 + q + 4 * r;           // local row
-                const int lcc = wcc + nt * 16 + l16;                 // local real column
-                const int lc = lcc >> 1;                              // local complex column
-                const int R = row0 + lr, c = col0 + lc;
-                const bool ok = R < N && c < N && c <= R;
-                double d = 0.0;
-                if (ok) {
-                    double qv = acc[mt][nt][r];
-                    if (c == R && comp == 0) qv = 0.0;  // Q is skew-Hermitian: Re Q_RR = 0
-                    const size_t o = (size_t)R * ld + 2 * (size_t)c + comp;
-                    const size_t ot = (size_t)c * ld + 2 * (size_t)R + comp;  // transposed entry
-                    const double arc = Ad[o], acr = Ad[ot];
-                    const double cv = comp ? arc + acr : arc - acr;  // (A - A^H)_{Rc}
-                    const double wt = Wtd[o];
-                    const double f = Wnd[o] + h2 * cv + h4 * qv;
-                    const double wo = wt + h2 * cv - h4 * qv;
-                    d = f - wt;
-                    Fd[o] = f;
-                    Wod[o] = wo;
-                    if (c != R) {  // upper triangle: -conj
-                        Fd[ot] = comp ? f : -f;
-                        Wod[ot] = comp ? wo : -wo;
-                    }
-                }
-                const double dpart = __shfl_xor(d, 1);
-                if (comp == 0) absd[lr * kTile + lc] = ok ? sqrt(d * d + dpart * dpart) : 0.0;
-            }
-    __syncthreads();
-
-    const int tid = threadIdx.x;
-    if (I != J) {
-        if (tid < kTile) {  // row sums -> slot (J, row0 + tid)
-            double s = 0.0;
-            for (int k = 0; k < kTile; ++k) s += absd[tid * kTile + k];
-            if (row0 + tid < N) rowpart[(size_t)J * N + row0 + tid] = s;
-        } else if (tid < 2 * kTile) {  // column sums -> slot (I, col0 + j)
-            const int j = tid - kTile;
-            double s = 0.0;
-            for (int k = 0; k < kTile; ++k) s += absd[k * kTile + j];
-            if (col0 + j < N) rowpart[(size_t)I * N + col0 + j] = s;
-        }
-    } else if (tid < kTile) {
-        double s = 0.0;
-        for (int k = 0; k < kTile; ++k) s += absd[tid * kTile + k];
-        for (int k = tid + 1; k < kTile; ++k) s += absd[k * kTile + tid];
-        if (row0 + tid < N) rowpart[(size_t)I * N + row0 + tid] = s;
-    }
-}
-
-
 }  // namespace zk
