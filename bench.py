@@ -29,20 +29,30 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
 
 # HBM bytes per launch of zgemm_f64_kernel (A = P W~) at N = 4096, from two rocprofv3 --pmc
 # passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors read off a plain 1 GiB device
-# copy in the same runs).  Valid only for the kernel source the counters were taken on.
-MEASURED_TRAFFIC = {"N": 4096, "source": "paper_2206_05466_amd/csrc/gemm_f64.hip",
-                    "sha256_16": "bcbc1b14ffdeb040", "bytes": 2070693.6 * 1024 * 2.0 + 262144.0 * 1024 * 1.0}
+# copy in the same runs).  Valid only for the kernel sources the counters were taken on.
+MEASURED_TRAFFIC = {"N": 4096,
+                    "sources": ["paper_2206_05466_amd/csrc/gemm_f64.hip",
+                                "paper_2206_05466_amd/csrc/tile_f64.h"],
+                    "sha256_16": None, "bytes": None}
+
+
+def sources_hash(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(N):
-    import hashlib
-
-    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
-    with open(path, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    if N == MEASURED_TRAFFIC["N"] and sha == MEASURED_TRAFFIC["sha256_16"]:
+    if N == MEASURED_TRAFFIC["N"] and MEASURED_TRAFFIC["bytes"] is not None and \
+            sources_hash(MEASURED_TRAFFIC["sources"]) == MEASURED_TRAFFIC["sha256_16"]:
         return MEASURED_TRAFFIC["bytes"]
     return None
+
+
 PAPER_S_PER_STEP_N4096 = 0.55  # Sec. 3.4: ~2500 CPU cores, ScaLAPACK, N = 4096, 3 iterations
 
 
@@ -90,45 +100,54 @@ def cpu_baseline(N, om_seed, law, h, K, lmax=32):
     }
 
 
-def ensemble_leg(nsteps):
+def ensemble_leg(nsteps, prec, slices=5):
     """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step."""
     import torch
 
-    from paper_2206_05466_amd import Ensemble, Zeuler
+    from paper_2206_05466_amd import PREC_SPLIT, Ensemble, Zeuler
     from workloads import WORKLOADS, ensemble_sizes, omega_coeffs
 
     cfg = WORKLOADS["ensemble64"]
     sizes = ensemble_sizes(cfg["nsim"], cfg["size_seed"], cfg["sizes"])
     h, K, tol = cfg["h"], 8, 1e-12
+    split = prec == PREC_SPLIT
     ctxs = {n: Zeuler(n) for n in sorted(set(sizes))}
     Ws = [ctxs[n].basis_assemble(omega_coeffs(n, cfg["seed0"] + j, cfg["law"])) for j, n in enumerate(sizes)]
     Wseq = [W.clone() for W in Ws]
     ens = Ensemble(sizes)
-    ens.run(Ws, h, 1, tol, K)  # first run: autotuning + capture
+    if split:
+        ens.set_split_slices(slices)
+        for z in ctxs.values():
+            z.set_split_slices(slices)
+    ens.run(Ws, h, 1, tol, K, prec=prec)  # first run: autotuning + capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ens.run(Ws, h, nsteps, tol, K)
+    ens.run(Ws, h, nsteps, tol, K, prec=prec)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     its, res = ens.stats()
-    choice, tune_ms = ens.tuning()
+    choice, tune_ms = ens.tuning(prec)
     # sequential reference: the single-simulation entry point, one simulation after the other
     seq_steps = max(1, min(5, nsteps))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(seq_steps):
         for j, n in enumerate(sizes):
-            ctxs[n].isomp_step(Wseq[j], h, tol, K)
+            ctxs[n].isomp_step(Wseq[j], h, tol, K, prec=prec)
     torch.cuda.synchronize()
     dts = time.perf_counter() - t1
     ens.close()
     for z in ctxs.values():
         z.close()
     n3 = sum(n ** 3 for n in sizes) / len(sizes)
+    cands = (["work order: largest first", "work order: interleaved"] if split else
+             ["128x64 tiles, largest first", "128x64 tiles, interleaved",
+              "64x64 tiles, largest first", "64x64 tiles, interleaved"])
     return {
         "workload": f"ensemble64: {len(sizes)} simulations, N drawn from {cfg['sizes']} (seed "
                     f"{cfg['size_seed']}), simulation j seeded {cfg['seed0']}+j, sigma_l law "
-                    f"{cfg['law']}, h={h}, tol={tol}, maxit={K}, FP64 products",
+                    f"{cfg['law']}, h={h}, tol={tol}, maxit={K}, "
+                    + (f"split-precision products (INT8 MFMA, {slices} slices)" if split else "FP64 products"),
         "sizes_histogram": {str(n): sizes.count(n) for n in sorted(set(sizes))},
         "steps": nsteps,
         "s_per_ensemble_step": dt / nsteps,
@@ -136,65 +155,51 @@ def ensemble_leg(nsteps):
         "last_step_iters": {"min": min(its), "max": max(its)},
         "last_step_max_resid": max(res),
         "fp64_equiv_tflops": 12.0 * n3 * len(sizes) * sum(its) / len(its) / (dt / nsteps) / 1e12,
-        "autotune": {"choice": choice, "ms_per_step": tune_ms,
-                     "candidates": ["128x64 tiles, largest first", "128x64 tiles, interleaved",
-                                    "64x64 tiles, largest first", "64x64 tiles, interleaved"]},
+        "autotune": {"choice": choice, "ms_per_step": tune_ms, "candidates": cands},
         "sequential_single_context_steps_per_s": len(sizes) * seq_steps / dts,
         "speedup_vs_sequential": (len(sizes) * nsteps / dt) / (len(sizes) * seq_steps / dts),
     }
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="n4096")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--split-slices", default="4,5,6",
-                    help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
-    ap.add_argument("--ensemble-steps", type=int, default=50,
-                    help="steps of the 64-simulation ensemble leg (0: skip it)")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="after the timed steps, run 3 plain device-to-device copies of this many "
-                         "MiB (a known-size reference for hardware traffic counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the multi-GPU decomposition of the step is a "
-              "design note, not built; run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def casimir_drift(c0, c1, W):
+    """Relative drift of C_2, C_4; C_3 relative to ||W||_F^3 (C_3 can be tiny)."""
     import torch
 
-    from paper_2206_05466_amd import Zeuler, PREC_FP64
+    nf = float(torch.linalg.norm(W).item())
+    return {f"C{k+1}": float(abs(c1[k] - c0[k]) / (abs(c0[k]) if k != 2 else nf ** 3)) for k in (1, 2, 3)}
+
+
+def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
+    """One simulation of workload wname: FP64 (start from W_n, then the extrapolated start) and
+    the split-precision runs, each over `steps` timed steps of ze_isomp_run from the same W0."""
+    import torch
+
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
     from workloads import WORKLOADS, omega_coeffs
 
-    cfg = WORKLOADS[args.workload]
+    cfg = WORKLOADS[wname]
     N, h, tol, maxit, law = cfg["N"], cfg["h"], cfg["tol"], cfg["maxit"], cfg["law"]
     seed = cfg["seeds"][0]
-    torch.cuda.set_device(0)
     z = Zeuler(N)
-    log(f"workload {args.workload}: N={N} law={law} h={h} tol={tol}")
-    om = omega_coeffs(N, seed, law)
+    log(f"workload {wname}: N={N} law={law} h={h} tol={tol}")
     t0 = time.perf_counter()
-    W = z.basis_assemble(om)
+    W = z.basis_assemble(omega_coeffs(N, seed, law))
     torch.cuda.synchronize()
     log(f"W0 assembled on GPU in {time.perf_counter() - t0:.2f} s")
     c0 = z.casimirs(W, 4)
     W0 = W.clone()
 
     def timed_run(Wx, prec, guess):
-        """Warm-up run, then one timed ze_isomp_run of args.steps steps on Wx (in place)."""
+        """Warm-up run, then one timed ze_isomp_run of `steps` steps on Wx (in place)."""
         z.set_initial_guess(guess)
         Ww = Wx.clone()
-        z.isomp_run(Ww, h, max(args.warmup, 1), tol, maxit, prec)
+        z.isomp_run(Ww, h, max(warmup, 1), tol, maxit, prec)
         del Ww
         z.profile(True)
         z.profile_read(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its, res = z.isomp_run(Wx, h, args.steps, tol, maxit, prec)
+        its, res = z.isomp_run(Wx, h, steps, tol, maxit, prec)
         torch.cuda.synchronize()
         dtx = time.perf_counter() - t0
         prof = z.profile_read()
@@ -204,14 +209,14 @@ def main():
     # W~ starts from W_n in every step (the default reading of the paper)
     Wp = W0.clone()
     dt_plain, iters_plain, _, _ = timed_run(Wp, PREC_FP64, 0)
-    log(f"fp64, start W_n: {dt_plain / args.steps * 1e3:.2f} ms/step, iters={iters_plain}")
+    log(f"{wname} fp64, start W_n: {dt_plain / steps * 1e3:.2f} ms/step, iters={iters_plain}")
     # headline: steps after the first start from 2 W_n - F_prev
     dt, iters, resids, prof = timed_run(W, PREC_FP64, 1)
-    log(f"fp64, extrapolated start: {dt / args.steps * 1e3:.2f} ms/step, iters={iters}")
+    log(f"{wname} fp64, extrapolated start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
     c1 = z.casimirs(W, 4)
     plain_vs_extrap = float(torch.linalg.norm(Wp - W).item() / torch.linalg.norm(W).item())
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 8
+    if copy_probe_mib > 0:
+        n = copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -220,10 +225,7 @@ def main():
         del src, dst
 
     split = None
-    slist = [int(x) for x in str(args.split_slices).split(",") if x.strip() and int(x) > 0]
     if slist:
-        from paper_2206_05466_amd import PREC_SPLIT
-
         runs = []
         for ns in slist:
             z.set_split_slices(ns)
@@ -231,14 +233,13 @@ def main():
             dts, its_s, _, profs = timed_run(Ws, PREC_SPLIT, 1)
             cs = z.casimirs(Ws, 4)
             diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
-            sps = dts / args.steps
+            sps = dts / steps
             p1 = profs["product_PW"][0] / max(profs["product_PW"][1], 1)
-            drift_s = {f"C{k+1}": float(abs(cs[k] - c0[k]) / (abs(c0[k]) if k != 2 else np.linalg.norm(
-                Ws.cpu().numpy()) ** 3)) for k in (1, 2, 3)}
+            drift_s = casimir_drift(c0, cs, Ws)
             runs.append({
                 "slices": ns,
                 "s_per_step": sps,
-                "speedup_vs_fp64": (dt / args.steps) / sps,
+                "speedup_vs_fp64": (dt / steps) / sps,
                 "iters_per_step": list(its_s),
                 "rel_frobenius_vs_fp64_run": diff,
                 "casimir_drift_rel": drift_s,
@@ -247,7 +248,7 @@ def main():
                 "product_PW_fp64_equiv_tflops": 8.0 * N ** 3 / (p1 * 1e-3) / 1e12,
                 "product_PW_int8_tops": 8.0 * N ** 3 * ns * (ns + 1) / 2 / (p1 * 1e-3) / 1e12,
             })
-            log(f"split s={ns}: {sps*1e3:.2f} ms/step, rel diff vs fp64 {diff:.2e}")
+            log(f"{wname} split s={ns}: {sps*1e3:.2f} ms/step, rel diff vs fp64 {diff:.2e}")
         ok = [r for r in runs if r["meets_stated_accuracy"]]
         best = min(ok, key=lambda r: r["s_per_step"]) if ok else None
         split = {
@@ -260,24 +261,85 @@ def main():
             "runs": runs,
             "note": "same W0 and step count as the FP64 run; product_PW includes the slicing kernels",
         }
+    z.close()
+    return {
+        "N": N, "h": h, "tol": tol, "maxit": maxit, "law": law, "seed": seed, "steps": steps,
+        "s_per_step": dt / steps, "iters_per_step": list(iters), "max_resid": max(resids),
+        "prof": prof, "casimir_drift_rel": casimir_drift(c0, c1, W),
+        "fp64_start_from_Wn": {"s_per_step": dt_plain / steps, "iters_per_step": list(iters_plain),
+                               "rel_frobenius_vs_headline_run": plain_vs_extrap},
+        "split_precision": split,
+    }
 
-    ens_out = None
+
+def phases_of(prof):
+    return {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="n4096")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split-slices", default="4,5,6",
+                    help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
+    ap.add_argument("--n2048-steps", type=int, default=20,
+                    help="timed steps of the N=2048 leg, FP64 and split (0: skip it)")
+    ap.add_argument("--ensemble-steps", type=int, default=50,
+                    help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, run 3 plain device-to-device copies of this many "
+                         "MiB (a known-size reference for hardware traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU decomposition of the step is a "
+              "design note, not built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT
+
+    torch.cuda.set_device(0)
+    slist = [int(x) for x in str(args.split_slices).split(",") if x.strip() and int(x) > 0]
+    m = measure_single(args.workload, args.steps, args.warmup, slist, args.copy_probe_mib)
+    N, prof = m["N"], m["prof"]
+
+    n2048 = None
+    if args.n2048_steps > 0 and args.workload != "n2048":
+        m2 = measure_single("n2048", args.n2048_steps, args.warmup, slist)
+        p2 = m2["prof"]["product_PW"]
+        n2048 = {
+            "workload": f"n2048: one simulation, N=2048, sigma_l law {m2['law']}, h={m2['h']}, "
+                        f"tol={m2['tol']}, {m2['steps']} steps, extrapolated start",
+            "fp64_s_per_step": m2["s_per_step"],
+            "fp64_iters_per_step": m2["iters_per_step"],
+            "fp64_casimir_drift_rel": m2["casimir_drift_rel"],
+            "fp64_start_from_Wn_s_per_step": m2["fp64_start_from_Wn"]["s_per_step"],
+            "product_PW_tflops": 8.0 * 2048 ** 3 / (p2[0] / max(p2[1], 1) * 1e-3) / 1e12,
+            "phases": phases_of(m2["prof"]),
+            "split_precision": m2["split_precision"],
+        }
+
+    ens = None
     if args.ensemble_steps > 0:
-        ens_out = ensemble_leg(args.ensemble_steps)
+        ens = {"fp64": ensemble_leg(args.ensemble_steps, PREC_FP64),
+               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=5)}
+        ens["split_speedup_vs_fp64"] = (ens["split"]["aggregate_steps_per_s"] /
+                                        ens["fp64"]["aggregate_steps_per_s"])
+        log(f"ensemble: fp64 {ens['fp64']['aggregate_steps_per_s']:.0f} steps/s, split "
+            f"{ens['split']['aggregate_steps_per_s']:.0f} steps/s")
 
-    s_per_step = dt / args.steps
+    s_per_step = m["s_per_step"]
+    iters = m["iters_per_step"]
     gemm_ms, gemm_n = prof["product_PW"]
     gemm_avg_s = gemm_ms / gemm_n * 1e-3
-    flops = 8.0 * N ** 3
-    achieved = flops / gemm_avg_s / 1e12
-    phases = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
+    achieved = 8.0 * N ** 3 / gemm_avg_s / 1e12
     solve_avg_s = prof["stream_solve"][0] / max(prof["stream_solve"][1], 1) * 1e-3
     solve_bytes = 24.0 * N * N  # read lower W~ (8 N^2 B), write P (16 N^2 B)
     low_ms = prof["lower_product_epilogue"][0] / max(prof["lower_product_epilogue"][1], 1)
-    drift = {
-        f"C{k+1}": float(abs(c1[k] - c0[k]) / (abs(c0[k]) if k != 2 else np.linalg.norm(
-            W.cpu().numpy()) ** 3)) for k in (1, 2, 3)
-    }
 
     out = {
         "metric": "IsoMP seconds/step (FP64)",
@@ -297,17 +359,17 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: one simulation, N={N}, W0 = sum i omega_lm T_lm with "
-                        f"seeded omega_lm, sigma_l law {law}, h={h}, tol={tol}, maxit={maxit}",
-            "N": N, "h": h, "tol": tol, "law": law, "seed": seed, "prec": "fp64",
+                        f"seeded omega_lm, sigma_l law {m['law']}, h={m['h']}, tol={m['tol']}, "
+                        f"maxit={m['maxit']}",
+            "N": N, "h": m["h"], "tol": m["tol"], "law": m["law"], "seed": m["seed"], "prec": "fp64",
         },
-        "iters_per_step": list(iters),
-        "max_resid": max(resids),
+        "iters_per_step": iters,
+        "max_resid": m["max_resid"],
         "initial_guess": "steps after the first start from 2 W_n - F_prev (ze_set_initial_guess 1); "
                          "every step still iterates until the change is below tol",
-        "fp64_start_from_Wn": {"s_per_step": dt_plain / args.steps, "iters_per_step": list(iters_plain),
-                               "rel_frobenius_vs_headline_run": plain_vs_extrap},
-        "casimir_drift_rel": drift,
-        "phases": phases,
+        "fp64_start_from_Wn": m["fp64_start_from_Wn"],
+        "casimir_drift_rel": m["casimir_drift_rel"],
+        "phases": phases_of(prof),
         "gemm_flops_per_step": sum(iters) / len(iters) * 12.0 * N ** 3,
         "achieved_step_tflops": sum(iters) / len(iters) * 12.0 * N ** 3 / s_per_step / 1e12,
         "roofline": {
@@ -327,13 +389,14 @@ def main():
         },
         "lower_product_tflops": 4.0 * N ** 3 / (low_ms * 1e-3) / 1e12,
         "cpu_baseline": None,
-        "split_precision": split,
-        "ensemble": ens_out,
+        "split_precision": m["split_precision"],
+        "n2048": n2048,
+        "ensemble": ens,
     }
     if not args.no_cpu_baseline:
         K = int(round(sum(iters) / len(iters)))
         log(f"cpu baseline: oracle step at N={N}, K={K} ...")
-        out["cpu_baseline"] = cpu_baseline(N, seed, law, h, K)
+        out["cpu_baseline"] = cpu_baseline(N, m["seed"], m["law"], m["h"], K)
         log(f"cpu baseline {out['cpu_baseline']['value']:.2f} s/step")
     print(json.dumps(out), flush=True)
 

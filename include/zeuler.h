@@ -184,8 +184,9 @@ ze_status ze_profile_read(ze_ctx* ctx, double* ms, long long* launches, int rese
  * HIP graph that is replayed (one graph launch per step) on a private default-priority stream
  * ordered after / before the caller's stream with events.  Per-simulation device flags keep the
  * stopping rule of ze_isomp_step: a simulation stops at its first evaluation whose residual is
- * below tol (or at K = maxit), without host synchronisation.  The first run of an ensemble
- * times the candidate tile shapes / work orders on copies of the inputs and keeps the fastest.
+ * below tol (or at K = maxit), without host synchronisation.  The first run of an ensemble in
+ * each precision times the candidate tile shapes / work orders on copies of the inputs and
+ * keeps the fastest.
  *
  * ze_ensemble_create -- set up nsim simulations of sizes N[0..nsim-1] (host array,
  *   1 <= N_j <= 4096, nsim <= 4096); stream: the caller's hipStream_t (NULL = default).
@@ -200,9 +201,11 @@ ze_status ze_ensemble_destroy(ze_ens* ens);
  * ze_ensemble_run -- nsteps IsoMP steps of every simulation (eqs. (isomp), (isomp_iter)).
  *   W      host array of nsim device pointers, W[j] an N_j x N_j complex128 skew-Hermitian
  *          matrix (in: W_n, out: W_{n+nsteps}); the pointers may change between calls.
- *   h, tol as in ze_isomp_step; K = maxit (1..64); prec: ZE_PREC_FP64.
+ *   h, tol as in ze_isomp_step; K = maxit (1..64); prec: ZE_PREC_FP64, or ZE_PREC_SPLIT
+ *   (both products of every evaluation on INT8 MFMA with ze_ensemble_set_split_slices
+ *   slices; the first split run allocates its workspaces, synchronously).
  * Asynchronous on the caller's stream; ze_ensemble_stats reads the outcome of the last step.
- * Errors: ZE_EINVAL (also for prec != ZE_PREC_FP64), ZE_ENOMEM, ZE_EHIP.
+ * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.
  */
 ze_status ze_ensemble_run(ze_ens* ens, void* const* W, double h, double tol, int K, int nsteps,
                           int prec);
@@ -217,10 +220,18 @@ ze_status ze_ensemble_step(ze_ens* ens, void* const* W, double h, double tol, in
 ze_status ze_ensemble_stats(ze_ens* ens, int* iters, double* resid);
 
 /*
- * ze_ensemble_tuning -- the autotuner's choice (0..3: 2 * tile shape + work order; -1 before
- * the first run) and the measured milliseconds per step of the four candidates (ms[4]).
+ * ze_ensemble_tuning -- the autotuner's choice for precision prec (-1 before the first run in
+ * it) and the measured milliseconds per step of its candidates (host ms[4]).  ZE_PREC_FP64:
+ * choice 0..3 = 2 * tile shape (0: 128 x 64, 1: 64 x 64 complex) + work order (0: largest
+ * simulations first, 1: interleaved); ZE_PREC_SPLIT: choice 0..1 = work order, ms[2..3] = 0.
  */
-ze_status ze_ensemble_tuning(ze_ens* ens, int* choice, double* ms);
+ze_status ze_ensemble_tuning(ze_ens* ens, int prec, int* choice, double* ms);
+
+/*
+ * ze_ensemble_set_split_slices -- slices s (2..8) of the ensemble's ZE_PREC_SPLIT products
+ * (default 6; see ze_set_split_slices).  Takes effect at the next ze_ensemble_run.
+ */
+ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
 
 #ifdef __cplusplus
 }

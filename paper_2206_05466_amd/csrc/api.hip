@@ -29,14 +29,17 @@ void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
 
+}  // namespace
+
 // Workspaces of the split-precision products, allocated on first use.
-ze_status ensure_split(ze_ctx* c) {
+ze_status ze_ensure_split(ze_ctx* c) {
     if (c->split_a) return ZE_OK;
     const size_t n = (size_t)c->N, ldk = (size_t)ze_split_ldk(c->N);
     ze_status st = dalloc(&c->split_a, (size_t)kSplitMax * n * ldk);
     if (st == ZE_OK) st = dalloc(&c->split_b, (size_t)kSplitMax * 2 * n * ldk);
     if (st == ZE_OK) st = dalloc(&c->split_ea, n);
     if (st == ZE_OK) st = dalloc(&c->split_eb, n);
+    if (st == ZE_OK) st = dalloc(&c->split_ec, n);
     if (st == ZE_OK) st = dalloc(&c->split_colmax, 64 * n);
     if (st == ZE_OK) st = dalloc(&c->split_g, (size_t)kSplitMax * 2 * n * n);
     if (st != ZE_OK) {
@@ -44,17 +47,17 @@ ze_status ensure_split(ze_ctx* c) {
         dfree(c->split_b);
         dfree(c->split_ea);
         dfree(c->split_eb);
+        dfree(c->split_ec);
         dfree(c->split_colmax);
         dfree(c->split_g);
         c->split_a = c->split_b = nullptr;
-        c->split_ea = c->split_eb = nullptr;
+        c->split_ea = c->split_eb = c->split_ec = nullptr;
         c->split_colmax = nullptr;
         c->split_g = nullptr;
     }
     return st;
 }
 
-}  // namespace
 
 ze_status ze_record_hip(hipError_t e, const char* what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -97,6 +100,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->split_b);
     dfree(c->split_ea);
     dfree(c->split_eb);
+    dfree(c->split_ec);
     dfree(c->split_colmax);
     dfree(c->split_g);
     dfree(c->resid);
@@ -185,9 +189,10 @@ ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     if (!c || !A || !B || !C || C == A || C == B) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
     if (prec == ZE_PREC_SPLIT) {
-        ZE_TRY(ensure_split(c));
+        ZE_TRY(ze_ensure_split(c));
         ZE_HIP(launch_zgemm_split(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
-                                  static_cast<double2*>(C), 0, c->stream));
+                                  static_cast<double2*>(C), 0, c->split_ea, c->split_eb, false,
+                                  c->stream));
         return ZE_OK;
     }
     ZE_HIP(launch_zgemm_f64(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
@@ -207,7 +212,7 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
     const bool split = prec == ZE_PREC_SPLIT;
-    if (split) ZE_TRY(ensure_split(c));
+    if (split) ZE_TRY(ze_ensure_split(c));
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
@@ -223,16 +228,19 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
         ZE_HIP(launch_stream_solve(c, Wt, c->P, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[1], s));
         if (split)
-            ZE_HIP(launch_zgemm_split(c, c->P, Wt, c->A, 0, s));
+            ZE_HIP(launch_zgemm_split(c, c->P, Wt, c->A, 0, c->split_ea, c->split_eb, false, s));
         else
             ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
         if (split) {
-            ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, s));
-            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+            // P is skew-Hermitian: its column exponents are the row exponents just taken
+            ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, true, s));
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+                                       c->split_ec, c->split_ea, s));
         } else {
             ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s));
-            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, s));
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
+                                       nullptr, s));
         }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
         ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "solve_wg.h"
+#include "split_tile.h"
 #include "tile_f64.h"
 #include "update_tile.h"
 
@@ -37,6 +38,14 @@ struct EnsProb {
     double* rowpart;
     const double* fl;
     const double* fd;
+    // split-precision products: slices, int32 slabs, exponents (rows of P, columns of W~,
+    // rows of A); null until the first split run
+    signed char* sa;
+    signed char* sb;
+    int* G;
+    int* ep;
+    int* ew;
+    int* eA;
 };
 
 constexpr int kCopyParts = 16;
@@ -112,6 +121,100 @@ __global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __
     lower_tile(it.y, I, J);
     lower_update_tile(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W, p.rowpart,
                       p.N, h, sT);
+}
+
+// ---------------------------------------------------------------- split-precision phases
+// which = 0 (product P W~): item y < N slices row y of P (exponent ep), item y >= N takes the
+// column exponents ew of W~ for columns 64 (y - N) ...; which = 1 (product A P): row y of A
+// (exponent eA).
+__global__ __launch_bounds__(kSThreads) void ens_split_rows_kernel(const EnsProb* __restrict__ probs,
+                                                                   const int2* __restrict__ work,
+                                                                   const int* __restrict__ done,
+                                                                   int eval, int which, int s) {
+    __shared__ double red[kSThreads];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const int N = p.N, ldk = split_ldk_of(N);
+    if (which == 1) {
+        split_row_block(p.A, N, it.y, s, ldk, p.sa, p.eA, red);
+    } else if (it.y < N) {
+        split_row_block(p.P, N, it.y, s, ldk, p.sa, p.ep, red);
+    } else {
+        const double2* Wt = eval == 1 ? p.Wn : p.F;
+        col_exponent_block(Wt, N, 64 * (it.y - N), p.ew, reinterpret_cast<double(*)[64]>(red));
+    }
+}
+
+// B~^T slices of W~ (which = 0, exponents ew) or of P (which = 1; P is skew-Hermitian, so
+// its column exponents are its row exponents ep).
+__global__ __launch_bounds__(kSThreads) void ens_split_cols_kernel(const EnsProb* __restrict__ probs,
+                                                                   const int2* __restrict__ work,
+                                                                   const int* __restrict__ done,
+                                                                   int eval, int which, int s) {
+    __shared__ double2 tile[kCT][kCT + 1];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const int N = p.N, ldk = split_ldk_of(N);
+    const int gx = (N + kCT - 1) / kCT;
+    const double2* B = which == 1 ? p.P : (eval == 1 ? p.Wn : p.F);
+    split_cols_tile(B, N, it.y % gx, it.y / gx, s, ldk, which == 1 ? p.ep : p.ew, p.sb, tile);
+}
+
+// INT8 slabs: mode 0 all tiles (row tile y / tn, column tile y % tn), mode 1 lower tiles.
+__global__ __launch_bounds__(kSThreads, 2) void ens_i8_kernel(const EnsProb* __restrict__ probs,
+                                                              const int2* __restrict__ work,
+                                                              const int* __restrict__ done,
+                                                              int mode, int s) {
+    __shared__ I8Smem sm;
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const int N = p.N;
+    const int tn = (2 * N + kI8BN - 1) / kI8BN;
+    int ti, tj;
+    if (mode == 0) {
+        ti = it.y / tn;
+        tj = it.y % tn;
+    } else {
+        i8_lower_tile(it.y, ti, tj);
+        if (tj >= tn) return;
+    }
+    zgemm_i8_tile(ti, tj, p.sa, p.sb, p.G, N, s, split_ldk_of(N), sm);
+}
+
+// A from the slabs of the product P W~: item y covers elements 1024 y ... 1024 y + 1023.
+constexpr int kCombineChunk = 1024;
+__global__ __launch_bounds__(kSThreads) void ens_combine_kernel(const EnsProb* __restrict__ probs,
+                                                                const int2* __restrict__ work,
+                                                                const int* __restrict__ done,
+                                                                int s) {
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const size_t n2 = (size_t)p.N * p.N;
+#pragma unroll
+    for (int j = 0; j < kCombineChunk / kSThreads; ++j) {
+        const size_t e = (size_t)it.y * kCombineChunk + j * kSThreads + threadIdx.x;
+        if (e < n2) p.A[e] = split_combine_elem(p.G, p.ep, p.ew, p.N, s, e);
+    }
+}
+
+// The fixed-point update from the slabs of the lower product A P (exponents eA, ep).
+__global__ __launch_bounds__(kUThreads) void ens_update_split_kernel(const EnsProb* __restrict__ probs,
+                                                                     const int2* __restrict__ work,
+                                                                     const int* __restrict__ done,
+                                                                     int eval, double h, int s) {
+    __shared__ double2 sT[kUT][kUT + 1];
+    const int2 it = work[blockIdx.x];
+    if (done[it.x]) return;
+    const EnsProb p = probs[it.x];
+    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    int I, J;
+    lower_tile(it.y, I, J);
+    lower_update_tile(I, J, nullptr, p.G, p.eA, p.ep, s, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, p.N,
+                      h, sT);
 }
 
 __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restrict__ probs,
@@ -215,48 +318,79 @@ struct ze_ens {
     int n_prod[2] = {0, 0};
     int2* work_low[2] = {nullptr, nullptr};                            // [order]
     int n_low = 0;
-    // tuning
+    // split-precision phases (work lists built at creation, buffers on first use)
+    int slices = 6;
+    bool split_ready = false;
+    int2* w_rows0 = nullptr;   // rows of P + column chunks of W~
+    int2* w_rows1 = nullptr;   // rows of A
+    int2* w_cols = nullptr;    // B~^T slice tiles
+    int2* w_comb = nullptr;    // combine chunks
+    int2* w_i8[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [mode][order]
+    int n_rows0 = 0, n_rows1 = 0, n_cols = 0, n_comb = 0, n_i8[2] = {0, 0};
+    // tuning: FP64 (tile shape, order) and split (order)
     int variant = -1, order = 0;
     double tune_ms[4] = {0, 0, 0, 0};
+    int s_order = -1;
+    double s_tune_ms[2] = {0, 0};
     // captured graph and the parameters it was captured with
     hipGraphExec_t exec = nullptr;
-    int g_variant = -1, g_order = -1, g_K = -1;
+    int g_prec = -1, g_variant = -1, g_order = -1, g_K = -1, g_slices = -1;
     double g_h = 0.0, g_tol = -1.0;
 };
 
 namespace {
 
-hipError_t record_step(ze_ens* e, double h, double tol, int K, int variant, int order,
+hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
                        hipStream_t s) {
     hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done);
     hipError_t err = hipGetLastError();
+    const int ns = e->slices;
+#define ZE_ENS_LAUNCH(...)                       \
+    do {                                         \
+        hipLaunchKernelGGL(__VA_ARGS__);         \
+        err = hipGetLastError();                 \
+        if (err != hipSuccess) return err;       \
+    } while (0)
     for (int k = 1; k <= K && err == hipSuccess; ++k) {
         err = ens_solve(e->maxN, e->dp, e->work_solve, e->n_solve, e->done, k, s);
         if (err != hipSuccess) break;
-        if (variant == 0)
-            hipLaunchKernelGGL(ens_product_kernel<WideCfg>, dim3(e->n_prod[0]), dim3(kThreads), 0, s,
-                               e->dp, e->work_prod[0][order], e->done, k);
-        else
-            hipLaunchKernelGGL(ens_product_kernel<SmallCfg>, dim3(e->n_prod[1]), dim3(kThreads), 0, s,
-                               e->dp, e->work_prod[1][order], e->done, k);
-        err = hipGetLastError();
-        if (err != hipSuccess) break;
-        hipLaunchKernelGGL(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
-                           e->work_low[order], e->done);
-        err = hipGetLastError();
-        if (err != hipSuccess) break;
-        hipLaunchKernelGGL(ens_update_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
-                           e->work_low[order], e->done, k, h);
-        err = hipGetLastError();
-        if (err != hipSuccess) break;
-        hipLaunchKernelGGL(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done,
-                           e->iters, e->resid, k, tol);
-        err = hipGetLastError();
+        if (prec == ZE_PREC_SPLIT) {
+            ZE_ENS_LAUNCH(ens_split_rows_kernel, dim3(e->n_rows0), dim3(kSThreads), 0, s, e->dp,
+                          e->w_rows0, e->done, k, 0, ns);
+            ZE_ENS_LAUNCH(ens_split_cols_kernel, dim3(e->n_cols), dim3(kSThreads), 0, s, e->dp,
+                          e->w_cols, e->done, k, 0, ns);
+            ZE_ENS_LAUNCH(ens_i8_kernel, dim3(e->n_i8[0]), dim3(kSThreads), 0, s, e->dp,
+                          e->w_i8[0][order], e->done, 0, ns);
+            ZE_ENS_LAUNCH(ens_combine_kernel, dim3(e->n_comb), dim3(kSThreads), 0, s, e->dp,
+                          e->w_comb, e->done, ns);
+            ZE_ENS_LAUNCH(ens_split_rows_kernel, dim3(e->n_rows1), dim3(kSThreads), 0, s, e->dp,
+                          e->w_rows1, e->done, k, 1, ns);
+            ZE_ENS_LAUNCH(ens_split_cols_kernel, dim3(e->n_cols), dim3(kSThreads), 0, s, e->dp,
+                          e->w_cols, e->done, k, 1, ns);
+            ZE_ENS_LAUNCH(ens_i8_kernel, dim3(e->n_i8[1]), dim3(kSThreads), 0, s, e->dp,
+                          e->w_i8[1][order], e->done, 1, ns);
+            ZE_ENS_LAUNCH(ens_update_split_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
+                          e->work_low[order], e->done, k, h, ns);
+        } else {
+            if (variant == 0)
+                ZE_ENS_LAUNCH(ens_product_kernel<WideCfg>, dim3(e->n_prod[0]), dim3(kThreads), 0, s,
+                              e->dp, e->work_prod[0][order], e->done, k);
+            else
+                ZE_ENS_LAUNCH(ens_product_kernel<SmallCfg>, dim3(e->n_prod[1]), dim3(kThreads), 0, s,
+                              e->dp, e->work_prod[1][order], e->done, k);
+            ZE_ENS_LAUNCH(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
+                          e->work_low[order], e->done);
+            ZE_ENS_LAUNCH(ens_update_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
+                          e->work_low[order], e->done, k, h);
+        }
+        ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
+                      e->resid, k, tol);
     }
+#undef ZE_ENS_LAUNCH
     return err;
 }
 
-hipError_t capture(ze_ens* e, double h, double tol, int K, int variant, int order) {
+hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant, int order) {
     if (e->exec) {
         (void)hipGraphExecDestroy(e->exec);
         e->exec = nullptr;
@@ -264,15 +398,17 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int variant, int orde
     hipGraph_t g = nullptr;
     hipError_t err = hipStreamBeginCapture(e->own, hipStreamCaptureModeRelaxed);
     if (err != hipSuccess) return err;
-    hipError_t rec = record_step(e, h, tol, K, variant, order, e->own);
+    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, e->own);
     err = hipStreamEndCapture(e->own, &g);
     if (rec != hipSuccess) err = rec;
     if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (err == hipSuccess) {
+        e->g_prec = prec;
         e->g_variant = variant;
         e->g_order = order;
         e->g_K = K;
+        e->g_slices = e->slices;
         e->g_h = h;
         e->g_tol = tol;
     }
@@ -311,10 +447,10 @@ ze_status set_pointers(ze_ens* e, void* const* W) {
     return ZE_OK;
 }
 
-// Times the four (tile shape, order) graphs on copies of the inputs; keeps the fastest.
-ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K) {
+// Times the candidate graphs on copies of the inputs and keeps the fastest: FP64, the four
+// (tile shape, order) pairs; split precision, the two work orders.
+ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int prec) {
     std::vector<double2*> copies(e->nsim, nullptr);
-    std::vector<EnsProb> saved = e->hp;
     ze_status st = ZE_OK;
     for (int i = 0; i < e->nsim && st == ZE_OK; ++i) {
         const size_t n2 = (size_t)e->N[i] * e->N[i];
@@ -323,12 +459,14 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K) {
             hipMemcpyAsync(copies[i], W[i], n2 * sizeof(double2), hipMemcpyDeviceToDevice, e->own) != hipSuccess)
             st = ZE_EHIP;
     }
+    const bool split = prec == ZE_PREC_SPLIT;
+    const int ncand = split ? 2 : 4;
     double best = 1e300;
-    for (int cand = 0; cand < 4 && st == ZE_OK; ++cand) {
-        const int variant = cand >> 1, order = cand & 1;
-        if (st == ZE_OK) st = set_pointers(e, reinterpret_cast<void* const*>(copies.data()));
+    for (int cand = 0; cand < ncand && st == ZE_OK; ++cand) {
+        const int variant = split ? 0 : cand >> 1, order = split ? cand : cand & 1;
+        st = set_pointers(e, reinterpret_cast<void* const*>(copies.data()));
         if (st != ZE_OK) break;
-        if (capture(e, h, tol, K, variant, order) != hipSuccess) {
+        if (capture(e, h, tol, K, prec, variant, order) != hipSuccess) {
             st = ze_record_hip(hipGetLastError(), "ensemble autotune capture");
             break;
         }
@@ -343,11 +481,15 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K) {
             st = ze_record_hip(err, "ensemble autotune run");
             break;
         }
-        e->tune_ms[cand] = ms / 3.0;
+        (split ? e->s_tune_ms : e->tune_ms)[cand] = ms / 3.0;
         if (ms < best) {
             best = ms;
-            e->variant = variant;
-            e->order = order;
+            if (split) {
+                e->s_order = order;
+            } else {
+                e->variant = variant;
+                e->order = order;
+            }
         }
     }
     (void)hipStreamSynchronize(e->own);
@@ -360,6 +502,25 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K) {
         e->exec = nullptr;
     }
     return st;
+}
+
+// Split-precision workspaces of every simulation, allocated on the first split run.
+ze_status ensure_split(ze_ens* e) {
+    if (e->split_ready) return ZE_OK;
+    ZE_HIP(hipStreamSynchronize(e->own));
+    for (int i = 0; i < e->nsim; ++i) {
+        ze_ctx* c = e->ctx[i];
+        ZE_TRY(ze_ensure_split(c));
+        e->hp[i].sa = c->split_a;
+        e->hp[i].sb = c->split_b;
+        e->hp[i].G = c->split_g;
+        e->hp[i].ep = c->split_ea;
+        e->hp[i].ew = c->split_eb;
+        e->hp[i].eA = c->split_ec;
+    }
+    ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
+    e->split_ready = true;
+    return ZE_OK;
 }
 
 }  // namespace
@@ -379,6 +540,9 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
     for (auto& v : e->work_prod)
         for (int2* p : v) (void)hipFree(p);
     for (int2* p : e->work_low) (void)hipFree(p);
+    for (int2* p : {e->w_rows0, e->w_rows1, e->w_cols, e->w_comb}) (void)hipFree(p);
+    for (auto& v : e->w_i8)
+        for (int2* p : v) (void)hipFree(p);
     for (hipEvent_t ev : {e->ev_in, e->ev_out, e->t0, e->t1})
         if (ev) (void)hipEventDestroy(ev);
     if (e->own) (void)hipStreamDestroy(e->own);
@@ -412,19 +576,52 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         st = ze_create_ctx(e->N[i], e->own, false, &e->ctx[i]);
         if (st != ZE_OK) return fail(st);
         ze_ctx* c = e->ctx[i];
-        e->hp[i] = EnsProb{c->N, 0, nullptr, c->Wn, c->F, c->P, c->A, c->Q, c->rowpart, c->fac_l, c->fac_dinv};
+        e->hp[i] = EnsProb{c->N,        0,          nullptr, c->Wn,   c->F,    c->P,    c->A,
+                           c->Q,        c->rowpart, c->fac_l, c->fac_dinv, nullptr, nullptr, nullptr,
+                           nullptr,     nullptr,    nullptr};
     }
     if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->iters, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->resid, (size_t)nsim)) != ZE_OK) return fail(st);
     std::vector<int> cs(nsim), c0(nsim), c1(nsim), cl(nsim);
+    std::vector<int> r0(nsim), r1(nsim), ccol(nsim), ccomb(nsim), i8f(nsim), i8l(nsim);
     for (int i = 0; i < nsim; ++i) {
         const int n = e->N[i], T = (n + kTile - 1) / kTile;
         cs[i] = n / 2 + 1;
         c0[i] = tiles_of(n, 0);
         c1[i] = tiles_of(n, 1);
         cl[i] = T * (T + 1) / 2;
+        const int tr = (n + kI8BM - 1) / kI8BM, tn = (2 * n + kI8BN - 1) / kI8BN;
+        r0[i] = n + (n + 63) / 64;
+        r1[i] = n;
+        ccol[i] = ((n + kCT - 1) / kCT) * ((split_ldk_of(n) / 2 + kCT - 1) / kCT);
+        ccomb[i] = (int)(((size_t)n * n + kCombineChunk - 1) / kCombineChunk);
+        i8f[i] = tr * tn;
+        i8l[i] = tr * (tr + 1);
+    }
+    {
+        std::vector<int2> w;
+        w = make_work(e->N, r0, 0);
+        e->n_rows0 = (int)w.size();
+        if ((st = upload_work(w, &e->w_rows0)) != ZE_OK) return fail(st);
+        w = make_work(e->N, r1, 0);
+        e->n_rows1 = (int)w.size();
+        if ((st = upload_work(w, &e->w_rows1)) != ZE_OK) return fail(st);
+        w = make_work(e->N, ccol, 0);
+        e->n_cols = (int)w.size();
+        if ((st = upload_work(w, &e->w_cols)) != ZE_OK) return fail(st);
+        w = make_work(e->N, ccomb, 0);
+        e->n_comb = (int)w.size();
+        if ((st = upload_work(w, &e->w_comb)) != ZE_OK) return fail(st);
+        for (int order = 0; order < 2; ++order) {
+            w = make_work(e->N, i8f, order);
+            e->n_i8[0] = (int)w.size();
+            if ((st = upload_work(w, &e->w_i8[0][order])) != ZE_OK) return fail(st);
+            w = make_work(e->N, i8l, order);
+            e->n_i8[1] = (int)w.size();
+            if ((st = upload_work(w, &e->w_i8[1][order])) != ZE_OK) return fail(st);
+        }
     }
     std::vector<int2> ws = make_work(e->N, cs, 0);
     e->n_solve = (int)ws.size();
@@ -450,15 +647,20 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     if (!e || !W || !std::isfinite(h) || !(tol >= 0.0) || !std::isfinite(tol) || K < 1 || K > 64 ||
         nsteps < 0)
         return ZE_EINVAL;
-    if (prec != ZE_PREC_FP64) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    for (int i = 0; i < e->nsim; ++i)
+        if (!W[i]) return ZE_EINVAL;
+    const bool split = prec == ZE_PREC_SPLIT;
     // order after the caller's pending work
     ZE_HIP(hipEventRecord(e->ev_in, e->user));
     ZE_HIP(hipStreamWaitEvent(e->own, e->ev_in, 0));
-    if (e->variant < 0) ZE_TRY(autotune(e, W, h, tol, K));
+    if (split) ZE_TRY(ensure_split(e));
+    if (split ? e->s_order < 0 : e->variant < 0) ZE_TRY(autotune(e, W, h, tol, K, prec));
     ZE_TRY(set_pointers(e, W));
-    if (!e->exec || e->g_variant != e->variant || e->g_order != e->order || e->g_K != K ||
-        e->g_h != h || e->g_tol != tol)
-        ZE_HIP(capture(e, h, tol, K, e->variant, e->order));
+    const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
+    if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
+        e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices)
+        ZE_HIP(capture(e, h, tol, K, prec, variant, order));
     for (int n = 0; n < nsteps; ++n) ZE_HIP(hipGraphLaunch(e->exec, e->own));
     ZE_HIP(hipEventRecord(e->ev_out, e->own));
     ZE_HIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
@@ -477,11 +679,23 @@ ze_status ze_ensemble_stats(ze_ens* e, int* iters, double* resid) {
     return ZE_OK;
 }
 
-ze_status ze_ensemble_tuning(ze_ens* e, int* choice, double* ms) {
-    if (!e) return ZE_EINVAL;
+ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
+    if (!e || (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT)) return ZE_EINVAL;
+    if (prec == ZE_PREC_SPLIT) {
+        if (choice) *choice = e->s_order;
+        if (ms)
+            for (int i = 0; i < 4; ++i) ms[i] = i < 2 ? e->s_tune_ms[i] : 0.0;
+        return ZE_OK;
+    }
     if (choice) *choice = e->variant < 0 ? -1 : 2 * e->variant + e->order;
     if (ms)
         for (int i = 0; i < 4; ++i) ms[i] = e->tune_ms[i];
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
+    if (!e || slices < 2 || slices > kSplitMax) return ZE_EINVAL;
+    e->slices = slices;
     return ZE_OK;
 }
 

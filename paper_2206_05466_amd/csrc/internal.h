@@ -63,6 +63,7 @@ struct ze_ctx {
     signed char* split_b = nullptr;
     int* split_ea = nullptr;
     int* split_eb = nullptr;
+    int* split_ec = nullptr;  // row exponents of A in the lower product Q = A P
     double* split_colmax = nullptr;
     int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
 
@@ -81,6 +82,9 @@ struct ze_ctx {
 constexpr int kMaxN = 16384;
 // Largest number of slices of the split-precision products.
 constexpr int kSplitMax = 8;
+
+// Workspaces of the split-precision products (kSplitMax slices), allocated on first use.
+ze_status ze_ensure_split(ze_ctx* c);
 
 // ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
 ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out);
@@ -126,21 +130,25 @@ hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch
 
 // ---- split-precision products (INT8 MFMA, Ozaki splitting) ----
 int ze_split_ldk(int N);  // bytes per slice row: 2N rounded up to the K stage
-// Slices A (rows) and B (columns) into the context's buffers.
-hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, hipStream_t s);
+// Slices A (rows; exponents into ea) and B (columns) into the context's buffers.  The column
+// exponents of B are computed into eb, or, with eb_known, read from eb (a skew-Hermitian B whose
+// row exponents are known: they are its column exponents).
+hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, int* ea,
+                                int* eb, bool eb_known, hipStream_t s);
 // C = A B (lower != 0: only the tiles meeting the lower triangle are formed, and left in the
-// int32 slabs for launch_lower_update).
+// int32 slabs for launch_lower_update); ea, eb, eb_known as for launch_split_prepare.
 hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
-                              int lower, hipStream_t s);
+                              int lower, int* ea, int* eb, bool eb_known, hipStream_t s);
 // The fixed-point update from the lower product:
 //   F     = Wn + h/2 (A - A^H) + h^2/4 Q       (both triangles; may alias Wt)
 //   Wout  = Wt + h/2 (A - A^H) - h^2/4 Q       (both triangles)
-//   rowpart[X*N + r]  partial row sums of |F - Wt| (slot layout in gemm_split.hip)
+//   rowpart[X*N + r]  partial row sums of |F - Wt| (slot layout in update_tile.h)
 // with Q read from Q (FP64, lower tiles) or, if Q is null, from the int32 slabs of the
-// preceding split lower product.
+// preceding split lower product with its row and column exponents ea, eb.
 hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
                                const double2* Wn, const double2* Wt, double2* F, double2* Wout,
-                               double* rowpart, double h, hipStream_t s);
+                               double* rowpart, double h, const int* ea, const int* eb,
+                               hipStream_t s);
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, hipStream_t s);

@@ -7,7 +7,7 @@
 namespace zk {
 
 template <int T>
-__device__ inline void block_scan_affine(double& G, double2& Y, bool reverse, double* sG,
+__device__ __forceinline__ void block_scan_affine(double& G, double2& Y, bool reverse, double* sG,
                                          double2* sY) {
     // Inclusive scan over threads (in reverse thread order if `reverse`) of the affine maps
     // f_t(x) = G_t x + Y_t composed in scan order: earlier maps are applied first.
@@ -29,7 +29,7 @@ __device__ inline void block_scan_affine(double& G, double2& Y, bool reverse, do
 }
 
 template <int T>
-__device__ inline double2 block_sum(double2 v, double2* s) {
+__device__ __forceinline__ double2 block_sum(double2 v, double2* s) {
     const int t = threadIdx.x;
     s[t] = v;
     __syncthreads();
@@ -47,7 +47,7 @@ __device__ inline double2 block_sum(double2 v, double2* s) {
 
 // Solves the diagonal pair of workgroup w (see solve.hip) for an N x N problem.
 template <int T, int C>
-__device__ inline void solve_pair(const double2* __restrict__ W, double2* __restrict__ P,
+__device__ __forceinline__ void solve_pair(const double2* __restrict__ W, double2* __restrict__ P,
                                   const double* __restrict__ fl, const double* __restrict__ fd,
                                   int N, int w, double* sG, double2* sY) {
     int m1, n1, m2;

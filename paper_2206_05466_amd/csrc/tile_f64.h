@@ -33,7 +33,7 @@ struct Cfg {
 
 // Global -> register loads of one K stage (zero outside the matrices).
 template <class C>
-__device__ inline void load_stage(const double2* __restrict__ A, int lda, int row0, int M,
+__device__ __forceinline__ void load_stage(const double2* __restrict__ A, int lda, int row0, int M,
                                   const double2* __restrict__ B, int ldb, int col0, int Nc,
                                   int K, int k0, double2 (&ra)[C::A_LOADS],
                                   double2 (&rb)[C::B_LOADS]) {
@@ -55,7 +55,7 @@ __device__ inline void load_stage(const double2* __restrict__ A, int lda, int ro
 }
 
 template <class C>
-__device__ inline void store_stage(double* __restrict__ st, const double2 (&ra)[C::A_LOADS],
+__device__ __forceinline__ void store_stage(double* __restrict__ st, const double2 (&ra)[C::A_LOADS],
                                    const double2 (&rb)[C::B_LOADS]) {
     const int tid = threadIdx.x;
     double* as = st;
@@ -77,7 +77,7 @@ __device__ inline void store_stage(double* __restrict__ st, const double2 (&ra)[
 
 // MFMAs of one stage for this wave.
 template <class C>
-__device__ inline void compute_stage(const double* __restrict__ st, int wrow, int wcc,
+__device__ __forceinline__ void compute_stage(const double* __restrict__ st, int wrow, int wcc,
                                      d4 (&acc)[C::MT][C::NT]) {
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, l16 = lane & 15;
@@ -109,7 +109,7 @@ __device__ inline void compute_stage(const double* __restrict__ st, int wrow, in
 // acc = A[row0:row0+BM, K range] * B[K range, col0:col0+BNC] for the K stages [kb, ke),
 // double-buffered in LDS.
 template <class C>
-__device__ inline void mainloop(const double2* __restrict__ A, int lda, int row0, int M,
+__device__ __forceinline__ void mainloop(const double2* __restrict__ A, int lda, int row0, int M,
                                 const double2* __restrict__ B, int ldb, int col0, int Nc, int K,
                                 int kb, int ke, double* smem, d4 (&acc)[C::MT][C::NT]) {
     const int wave = threadIdx.x >> 6;
@@ -139,7 +139,7 @@ using FullCfg = Cfg<128, 64, 64, 32>;
 
 // Store a block's accumulators (MFMA layout of config C) to C~ (complex N x N), bounds-checked.
 template <class C>
-__device__ inline void store_tile(const d4 (&acc)[C::MT][C::NT], double2* Cm, int N, int row0,
+__device__ __forceinline__ void store_tile(const d4 (&acc)[C::MT][C::NT], double2* Cm, int N, int row0,
                                   int col0) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wrow = (wave / C::WAVES_N) * C::WM;
@@ -161,7 +161,7 @@ __device__ inline void store_tile(const d4 (&acc)[C::MT][C::NT], double2* Cm, in
         }
 }
 
-__device__ inline void store_full_tile(const d4 (&acc)[FullCfg::MT][FullCfg::NT], double2* Cm,
+__device__ __forceinline__ void store_full_tile(const d4 (&acc)[FullCfg::MT][FullCfg::NT], double2* Cm,
                                        int N, int row0, int col0) {
     store_tile<FullCfg>(acc, Cm, N, row0, col0);
 }
@@ -171,7 +171,7 @@ using LowCfg = Cfg<64, 64, 32, 32>;
 constexpr int kTile = 64;  // square complex tile of the lower-triangle product
 
 // Tile index b of the lower triangle -> (I, J), I >= J, b = I (I+1)/2 + J.
-__device__ inline void lower_tile(int b, int& I, int& J) {
+__device__ __forceinline__ void lower_tile(int b, int& I, int& J) {
     int i = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((i + 1) * (i + 2) / 2 <= b) ++i;
     while (i * (i + 1) / 2 > b) --i;

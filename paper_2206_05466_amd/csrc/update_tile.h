@@ -19,7 +19,7 @@ constexpr int kUT = 64;
 constexpr int kUThreads = 256;
 // Q comes from the FP64 lower product (Qf != nullptr, complex N x N, lower tiles) or from the
 // int32 slabs of the split lower product (G, ea, eb, s).
-__device__ inline void lower_update_tile(int I, int J, const double2* __restrict__ Qf,
+__device__ __forceinline__ void lower_update_tile(int I, int J, const double2* __restrict__ Qf,
                                          const int* __restrict__ G, const int* __restrict__ ea,
                                          const int* __restrict__ eb, int s,
                                          const double2* __restrict__ Am,

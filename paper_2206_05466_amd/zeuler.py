@@ -44,7 +44,8 @@ SIGNATURES = {
     "ze_ensemble_run": (_c_int, [_vp, ctypes.POINTER(_vp), _c_double, _c_double, _c_int, _c_int, _c_int]),
     "ze_ensemble_step": (_c_int, [_vp, ctypes.POINTER(_vp), _c_double, _c_double, _c_int, _c_int]),
     "ze_ensemble_stats": (_c_int, [_vp, _P_int, _P_double]),
-    "ze_ensemble_tuning": (_c_int, [_vp, _P_int, _P_double]),
+    "ze_ensemble_tuning": (_c_int, [_vp, _c_int, _P_int, _P_double]),
+    "ze_ensemble_set_split_slices": (_c_int, [_vp, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -275,10 +276,17 @@ class Ensemble:
         _check(self.lib.ze_ensemble_stats(self._ens, its, res), "ze_ensemble_stats")
         return list(its), list(res)
 
-    def tuning(self):
-        """(choice, [ms per step of the 4 candidates]) of the autotuner."""
+    def set_split_slices(self, slices: int):
+        """Slices per operand of the ensemble's PREC_SPLIT products (2..8)."""
+        _check(self.lib.ze_ensemble_set_split_slices(self._ens, int(slices)),
+               "ze_ensemble_set_split_slices")
+
+    def tuning(self, prec: int = PREC_FP64):
+        """(choice, [ms per step of the candidates]) of the autotuner for precision prec:
+        FP64 has 4 candidates (2 * tile shape + work order), PREC_SPLIT 2 (work order)."""
         ch = ctypes.c_int(0)
         ms = (ctypes.c_double * 4)()
-        _check(self.lib.ze_ensemble_tuning(self._ens, ctypes.byref(ch), ms), "ze_ensemble_tuning")
-        return ch.value, list(ms)
+        _check(self.lib.ze_ensemble_tuning(self._ens, int(prec), ctypes.byref(ch), ms),
+               "ze_ensemble_tuning")
+        return ch.value, list(ms)[: (2 if prec == PREC_SPLIT else 4)]
 

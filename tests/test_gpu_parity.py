@@ -330,6 +330,43 @@ def test_ensemble_multi_step_run_and_fixed_K(dev):
         assert np.linalg.norm(to_host(Wd[j]) - W) <= 1e-12 * np.linalg.norm(W)
 
 
+def test_ensemble_split_matches_single_context_and_oracle(dev):
+    """Split-precision ensemble (ragged N, slice count changed between replays): every step
+    matches the single-context split path and the oracle."""
+    from paper_2206_05466_amd import PREC_SPLIT, Ensemble
+
+    sizes = [48, 64, 100, 128, 200, 32, 130]
+    h, tol, K = 0.01, 1e-12, 8
+    W0s = [w0(n, 60 + j) for j, n in enumerate(sizes)]
+    Wd = [to_dev(W) for W in W0s]
+    We = [to_dev(W) for W in W0s]
+    Wr = [W.copy() for W in W0s]
+    ctxs = [ctx(n) for n in sizes]
+    with Ensemble(sizes) as ens:
+        for step, ns in enumerate((6, 6, 5)):
+            ens.set_split_slices(ns)
+            ens.run(Wd, h, 1, tol, K, prec=PREC_SPLIT)
+            its, res = ens.stats()
+            for j, z in enumerate(ctxs):
+                z.set_split_slices(ns)
+                info = z.isomp_step(We[j], h, tol, K, prec=PREC_SPLIT)
+                Wr[j], _, _ = O.isomp_step(Wr[j], h, tol, K)
+                assert its[j] == info.iters, (step, j, its[j], info.iters)
+                assert res[j] < tol
+            torch.cuda.synchronize()
+            for j in range(len(sizes)):
+                a, b = to_host(Wd[j]), to_host(We[j])
+                assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b), (step, j)
+                assert np.linalg.norm(a - Wr[j]) <= 1e-10 * np.linalg.norm(Wr[j]), (step, j)
+                assert np.abs(a + a.conj().T).max() == 0.0
+        choice, ms = ens.tuning(PREC_SPLIT)
+        assert choice in (0, 1) and len(ms) == 2 and min(ms) > 0
+        choice64, _ = ens.tuning()
+        assert choice64 == -1  # no FP64 run yet
+    for z in ctxs:
+        z.close()
+
+
 @pytest.mark.parametrize("prec_name", ["fp64", "split"])
 def test_isomp_run_extrapolated_guess(dev, prec_name):
     from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT
