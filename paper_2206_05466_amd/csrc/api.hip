@@ -35,8 +35,16 @@ void dfree(void* p) {
 ze_status ze_ensure_split(ze_ctx* c) {
     if (c->split_a) return ZE_OK;
     const size_t n = (size_t)c->N, ldk = (size_t)ze_split_ldk(c->N);
-    ze_status st = dalloc(&c->split_a, (size_t)kSplitMax * n * ldk);
-    if (st == ZE_OK) st = dalloc(&c->split_b, (size_t)kSplitMax * 2 * n * ldk);
+    const size_t bytes_a = (size_t)kSplitMax * split_rows_pad(c->N) * ldk;
+    const size_t bytes_b = (size_t)kSplitMax * split_cols_pad(c->N) * ldk;
+    ze_status st = dalloc(&c->split_a, bytes_a);
+    if (st == ZE_OK) st = dalloc(&c->split_b, bytes_b);
+    // zero padding rows (and everything else) once; the slicing kernels never write them
+    if (st == ZE_OK &&
+        (hipMemsetAsync(c->split_a, 0, bytes_a, c->stream) != hipSuccess ||
+         hipMemsetAsync(c->split_b, 0, bytes_b, c->stream) != hipSuccess ||
+         hipStreamSynchronize(c->stream) != hipSuccess))
+        st = ze_record_hip(hipGetLastError(), "split workspace clear");
     if (st == ZE_OK) st = dalloc(&c->split_ea, n);
     if (st == ZE_OK) st = dalloc(&c->split_eb, n);
     if (st == ZE_OK) st = dalloc(&c->split_ec, n);

@@ -86,6 +86,12 @@ constexpr int kSplitMax = 8;
 // Workspaces of the split-precision products (kSplitMax slices), allocated on first use.
 ze_status ze_ensure_split(ze_ctx* c);
 
+// Slice buffers hold whole 128-row tiles: A~ slices have split_rows_pad(N) rows and B~^T
+// slices split_cols_pad(N) rows; the rows past N (2N) are zeroed when the buffers are
+// allocated and never written, so the INT8 product reads them without bounds checks.
+__host__ __device__ inline int split_rows_pad(int N) { return ((N + 127) / 128) * 128; }
+__host__ __device__ inline int split_cols_pad(int N) { return ((2 * N + 127) / 128) * 128; }
+
 // ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
 ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out);
 

@@ -37,7 +37,7 @@ __device__ __forceinline__ void split_row_block(const double2* __restrict__ A, i
     }
     const int e = exponent_of(red[0]);
     if (threadIdx.x == 0) ea[r] = e;
-    const size_t ss = (size_t)N * ldk;  // bytes per slice
+    const size_t ss = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
     signed char* base = slices + (size_t)r * ldk;
     for (int c = threadIdx.x; c < ldk / 2; c += kSThreads) {
         double yr = 0.0, yi = 0.0;
@@ -94,7 +94,7 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
     __syncthreads();
     // Thread (tx = k offset, ty) writes, for columns c0 + ty + 8 j, the 2 bytes (t = 0, 1) of
     // output rows 2c and 2c+1 at kk = 2 (k0 + tx) + t.
-    const size_t ss = (size_t)2 * N * ldk;  // bytes per slice
+    const size_t ss = (size_t)split_cols_pad(N) * ldk;  // bytes per slice
     const int k = k0 + tx;
     if (2 * k >= ldk) return;
     for (int a = ty; a < kCT; a += 8) {
@@ -121,24 +121,39 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
 }
 
 // ---------------------------------------------------------------- INT8 product tile
-// Block tile 128 rows x 128 real columns (64 complex), 4 waves as 2 x 2 of 64 x 64;
-// K stage of 128 bytes (two MFMA k-steps), double-buffered in LDS, global loads one stage
-// ahead.  Slice pairs run in order of decreasing t = i + j; the pairs of one t share one
-// exact int32 accumulator ((t-1) 2N 127^2 < 2^31), which is stored to the slab G[t-2]
-// (int32, N x 2N) when t changes.  The FP64 weighting happens afterwards (combine or the
-// fixed-point update), so no FP64 accumulator occupies registers here.
+// Block tile 128 rows x 128 real columns (64 complex), 4 waves as 2 x 2 of 64 x 64, each wave
+// 2 x 2 tiles of v_mfma_i32_32x32x32_i8 (on gfx950 this form has about twice the throughput
+// of the 16x16x64 one; measured 4.4 vs 2.6 POPS).  K stage of 128 bytes (four MFMA k-steps),
+// double-buffered in LDS, global loads one stage ahead.  Slice pairs run in order of
+// decreasing t = i + j; the pairs of one t share one exact int32 accumulator
+// ((t-1) 2N 127^2 < 2^31), which is stored to the slab G[t-2] (int32, N x 2N) when t changes.
+// The FP64 weighting happens afterwards (combine or the fixed-point update), so no FP64
+// accumulator occupies registers here.
+//
+// MFMA operands: lane l supplies 16 bytes of A~ row (l % 32) and of B~^T row (l % 32) at
+// k = 16 (l / 32) + 0..15 of the k-step; accumulator register r of lane l holds
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] (checked on the GPU).
+//
+// LDS rows are 128 bytes with no padding; the 16-byte chunk c of row r is stored at chunk
+// position c ^ ((r & 6) | ((r >> 4) & 1)).  The operand reads (32 consecutive rows, one chunk
+// per half-wave) then fall on distinct bank groups in every group of lanes the LDS serves
+// together (measured: full read bandwidth, half of it without the swizzle).
 constexpr int kI8BM = 128, kI8BN = 128, kI8BK = 128;
-constexpr int kI8LD = kI8BK + 16;  // padded LDS row (bytes)
-constexpr int kI8Stage = (kI8BM + kI8BN) * kI8LD;
-constexpr int kMaxPairs = kSplitMax * (kSplitMax + 1) / 2;
+constexpr int kI8Stage = (kI8BM + kI8BN) * kI8BK;
+
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 // Bytes per slice row: the real K = 2N rounded up to the K stage.
 __host__ __device__ inline int split_ldk_of(int N) { return ((2 * N + kI8BK - 1) / kI8BK) * kI8BK; }
 
 struct I8Smem {
     signed char stage[2 * kI8Stage] __attribute__((aligned(16)));
-    unsigned char pt_i[kMaxPairs], pt_j[kMaxPairs], pt_flush[kMaxPairs];
 };
+
+__device__ __forceinline__ int i8_swizzle(int row) { return (row & 6) | ((row >> 4) & 1); }
+__device__ __forceinline__ int i8_lds_offset(int row, int chunk) {
+    return row * kI8BK + ((chunk ^ i8_swizzle(row)) << 4);
+}
 
 // Tiles of the lower-triangle product: row tile I (128 rows) has column tiles J = 0 .. 2I+1
 // (64 complex columns each), numbered b = I (I+1) + J.
@@ -149,104 +164,141 @@ __device__ __forceinline__ void i8_lower_tile(int b, int& I, int& J) {
     J = b - I * (I + 1);
 }
 
-// Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, N x ldk each) and sb
-// (B~^T, 2N x ldk each).
-__device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char* __restrict__ sa,
-                                     const signed char* __restrict__ sb, int* __restrict__ G, int N,
-                                     int s, int ldk, I8Smem& sm) {
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid == 0) {
-        int p = 0;
-        for (int t = s + 1; t >= 2; --t)
-            for (int a = 1; a <= t - 1; ++a, ++p) {
-                sm.pt_i[p] = (unsigned char)a;
-                sm.pt_j[p] = (unsigned char)(t - a);
-                sm.pt_flush[p] = (unsigned char)(a == t - 1);
-            }
+// Next slice pair (i, j) in order of decreasing t = i + j, i ascending within t:
+// (1, t-1), (2, t-2), ..., (t-1, 1), then (1, t-2), ...
+__device__ __forceinline__ void i8_next_pair(int& i, int& j) {
+    if (j > 1) {
+        ++i;
+        --j;
+    } else {
+        j = i - 1;  // new t = i + j - 1 = i: pairs (1, i - 1), ...
+        i = 1;
     }
+}
+
+// Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
+// each) and sb (B~^T, split_cols_pad(N) x ldk each).  Each iteration issues the global loads
+// of the next stage, computes the current stage from LDS, and stores the next stage to the
+// other LDS buffer late in the stage; scheduling barriers keep that order (left alone, the
+// compiler moves the LDS store up to the loads, which waits for them before the MFMAs).
+__device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char* __restrict__ sa,
+                                              const signed char* __restrict__ sb,
+                                              int* __restrict__ G, int N, int s, int ldk,
+                                              I8Smem& sm) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8BM;      // rows of A~ / G
     const int cc0 = tj * kI8BN;       // real columns of G (rows of B~^T)
     const int M2 = 2 * N;             // real columns
-    const size_t sA = (size_t)N * ldk, sB = (size_t)M2 * ldk;  // bytes per slice
+    const size_t sA = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
+    const size_t sB = (size_t)split_cols_pad(N) * ldk;
     const int nk = ldk / kI8BK;       // K stages (real K = 2N, zero padded to ldk)
     const int total = s * (s + 1) / 2 * nk;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    const int q = lane >> 4, l16 = lane & 15;
-    __syncthreads();
+    const int l32 = lane & 31, h = lane >> 5;
 
-    v4i acc[4][4];
+    v16i acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+        for (int c = 0; c < 2; ++c) acc[a][c] = (v16i)0;
 
-    uint4 ra[4], rb[4];
-    auto load = [&](int it) {
-        const int p = it / nk;
-        const int k0 = (it - p * nk) * kI8BK;
-        const signed char* A = sa + (size_t)(sm.pt_i[p] - 1) * sA;
-        const signed char* B = sb + (size_t)(sm.pt_j[p] - 1) * sB;
+    // this thread's rows of the A~ and B~^T tiles (padded buffers: always in range); a
+    // thread's x-th 16-byte piece of a stage is row (tid / 8) + 32 x, bytes 16 (tid % 8) ..
+    const signed char* pa = sa + (size_t)(row0 + (tid >> 3)) * ldk + (tid & 7) * 16;
+    const signed char* pb = sb + (size_t)(cc0 + (tid >> 3)) * ldk + (tid & 7) * 16;
+    const size_t xstep = (size_t)(kSThreads / 8) * ldk;
+    int soff_a[4], soff_b[4];  // LDS byte offsets of those pieces
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int id = tid + x * kSThreads;
-            const int rr = id >> 3, cb = (id & 7) * 16;
-            const int gr = row0 + rr, gc = cc0 + rr;
-            ra[x] = gr < N ? *reinterpret_cast<const uint4*>(A + (size_t)gr * ldk + k0 + cb)
-                           : make_uint4(0, 0, 0, 0);
-            rb[x] = gc < M2 ? *reinterpret_cast<const uint4*>(B + (size_t)gc * ldk + k0 + cb)
-                            : make_uint4(0, 0, 0, 0);
-        }
-    };
-    auto store = [&](signed char* st) {
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int id = tid + x * kSThreads;
-            const int rr = id >> 3, cb = (id & 7) * 16;
-            *reinterpret_cast<uint4*>(st + rr * kI8LD + cb) = ra[x];
-            *reinterpret_cast<uint4*>(st + (kI8BM + rr) * kI8LD + cb) = rb[x];
-        }
-    };
+    for (int x = 0; x < 4; ++x) {
+        const int rr = (tid >> 3) + 32 * x, ch = tid & 7;
+        soff_a[x] = i8_lds_offset(rr, ch);
+        soff_b[x] = i8_lds_offset(kI8BM + rr, ch);
+    }
+    // operand reads: rows wr/wc + 32 x + l32 (swizzle depends on l32 only), chunk 2 ks + h
+    const int swz = i8_swizzle(l32);
+    const int rda = (wr + l32) * kI8BK, rdb = (kI8BM + wc + l32) * kI8BK;
 
-    load(0);
-    store(sm.stage);
+    int li = 1, lj = s, lk = 0;  // next stage to load
+    int ci = 1, cj = s, ck = 0;  // stage in LDS
+    v4i ra[4], rb[4];  // native vectors (HIP's uint4 is a struct whose copies become memcpy)
+#define ZE_I8_LOAD()                                                              \
+    do {                                                                          \
+        const signed char* A_ = pa + (size_t)(li - 1) * sA + lk * kI8BK;          \
+        const signed char* B_ = pb + (size_t)(lj - 1) * sB + lk * kI8BK;          \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                           \
+            ra[x] = *reinterpret_cast<const v4i*>(A_ + x * xstep);                \
+            rb[x] = *reinterpret_cast<const v4i*>(B_ + x * xstep);                \
+        }                                                                         \
+        if (++lk == nk) {                                                         \
+            lk = 0;                                                               \
+            i8_next_pair(li, lj);                                                 \
+        }                                                                         \
+    } while (0)
+#define ZE_I8_STORE(st)                                                           \
+    do {                                                                          \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                           \
+            *reinterpret_cast<v4i*>((st) + soff_a[x]) = ra[x];                    \
+            *reinterpret_cast<v4i*>((st) + soff_b[x]) = rb[x];                    \
+        }                                                                         \
+    } while (0)
+
+    ZE_I8_LOAD();
+    ZE_I8_STORE(sm.stage);
     __syncthreads();
     for (int it = 0; it < total; ++it) {
-        const int cur = it & 1;
-        if (it + 1 < total) load(it + 1);
-        const signed char* st = sm.stage + cur * kI8Stage;
+        const bool more = it + 1 < total;
+        if (more) ZE_I8_LOAD();
+        __builtin_amdgcn_sched_barrier(0);
+        const signed char* st = sm.stage + (it & 1) * kI8Stage;
+        // software-pipelined operand reads: the 4 fragments of k-step ks + 1 are read while
+        // the 4 MFMAs of k-step ks run; the next stage goes to the other LDS buffer after the
+        // third k-step, when its global loads have had time to land
+        v4i fa[2][2], fb[2][2];
+#define ZE_I8_READ(ks, slot)                                                              \
+    do {                                                                                  \
+        const int chunk_ = (((ks) * 2 + h) ^ swz) << 4;                                   \
+        _Pragma("unroll") for (int x = 0; x < 2; ++x) {                                   \
+            fa[slot][x] = *reinterpret_cast<const v4i*>(st + rda + x * 32 * kI8BK + chunk_); \
+            fb[slot][x] = *reinterpret_cast<const v4i*>(st + rdb + x * 32 * kI8BK + chunk_); \
+        }                                                                                 \
+    } while (0)
+        ZE_I8_READ(0, 0);
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            v4i fa[4], fb[4];
+        for (int ks = 0; ks < 4; ++ks) {
+            if (ks < 3) ZE_I8_READ(ks + 1, (ks + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                fa[x] = *reinterpret_cast<const v4i*>(st + (wr + x * 16 + l16) * kI8LD + ks * 64 + q * 16);
-                fb[x] = *reinterpret_cast<const v4i*>(st + (kI8BM + wc + x * 16 + l16) * kI8LD + ks * 64 + q * 16);
-            }
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[c], acc[a][c], 0, 0, 0);
+                for (int c = 0; c < 2; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][a], fb[ks & 1][c], acc[a][c], 0, 0, 0);
+            if (ks == 2 && more) ZE_I8_STORE(sm.stage + ((it + 1) & 1) * kI8Stage);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        const int p = it / nk;
-        if (it - p * nk == nk - 1 && sm.pt_flush[p]) {  // last stage of the last pair of this t
-            int* g = G + (size_t)(sm.pt_i[p] + sm.pt_j[p] - 2) * N * M2;
+#undef ZE_I8_READ
+        if (ck == nk - 1 && cj == 1) {  // last stage of the last pair of this t
+            int* g = G + (size_t)(ci + cj - 2) * N * M2;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int cc = cc0 + wc + c * 16 + l16;
+                for (int c = 0; c < 2; ++c) {
+                    const int cc = cc0 + wc + 32 * c + l32;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = row0 + wr + a * 16 + 4 * q + r;
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = row0 + wr + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
                         if (row < N && cc < M2) g[(size_t)row * M2 + cc] = acc[a][c][r];
                     }
-                    acc[a][c] = v4i{0, 0, 0, 0};
+                    acc[a][c] = (v16i)0;
                 }
         }
-        if (it + 1 < total) store(sm.stage + (cur ^ 1) * kI8Stage);
+        if (++ck == nk) {
+            ck = 0;
+            i8_next_pair(ci, cj);
+        }
         __syncthreads();
     }
+#undef ZE_I8_LOAD
+#undef ZE_I8_STORE
 }
 
 // Element e (row-major complex index) of C = 2^(ea_r + eb_c) sum_{t=2}^{s+1} 2^(-7 t) G[t-2].
