@@ -154,10 +154,13 @@ ze_status ze_basis_assemble(ze_ctx* ctx, const void* omega, void* W);
 ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec);
 
 /*
- * ze_set_split_slices -- number s of 7-bit slices per operand of the ZE_PREC_SPLIT products
- * (2 <= s <= 8, default 6); the products then cost s (s + 1) / 2 INT8 products each.  The first
- * split-precision call of a context allocates its slice buffers (about 24 N^2 bytes).
- * Errors: ZE_EINVAL.
+ * ze_set_split_slices -- number s of 7-bit slices per operand of the ZE_PREC_SPLIT products;
+ * the products then cost s (s + 1) / 2 INT8 products each.  Allowed: 2 <= s <= s_max(N) with
+ * s_max(N) = min(8, floor((2^31 - 1) / (2 N 127^2))), the largest count whose int32 sums stay
+ * exact (8 up to N = 8192, 4 at N = 16384); default min(6, s_max(N)).  The first
+ * split-precision call of a context allocates its slice buffers (about 24 N^2 bytes) and
+ * int32 work slabs (up to 64 N^2 bytes).
+ * Errors: ZE_EINVAL (also for s > s_max(N)).
  */
 ze_status ze_set_split_slices(ze_ctx* ctx, int slices);
 
@@ -228,8 +231,9 @@ ze_status ze_ensemble_stats(ze_ens* ens, int* iters, double* resid);
 ze_status ze_ensemble_tuning(ze_ens* ens, int prec, int* choice, double* ms);
 
 /*
- * ze_ensemble_set_split_slices -- slices s (2..8) of the ensemble's ZE_PREC_SPLIT products
- * (default 6; see ze_set_split_slices).  Takes effect at the next ze_ensemble_run.
+ * ze_ensemble_set_split_slices -- slices s of the ensemble's ZE_PREC_SPLIT products
+ * (2 <= s <= s_max of the largest N_j, default 6; see ze_set_split_slices).  Takes effect at
+ * the next ze_ensemble_run.
  */
 ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
 

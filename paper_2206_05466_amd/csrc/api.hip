@@ -129,6 +129,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
     if (N < 1 || N > kMaxN) return ZE_EINVAL;
     ze_ctx* c = new ze_ctx();
     c->N = N;
+    c->split_slices = split_max_slices(N) < 6 ? split_max_slices(N) : 6;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -359,7 +360,7 @@ ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
 }
 
 ze_status ze_set_split_slices(ze_ctx* c, int slices) {
-    if (!c || slices < 2 || slices > kSplitMax) return ZE_EINVAL;
+    if (!c || slices < 2 || slices > split_max_slices(c->N)) return ZE_EINVAL;
     c->split_slices = slices;
     return ZE_OK;
 }

@@ -694,7 +694,7 @@ ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
 }
 
 ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
-    if (!e || slices < 2 || slices > kSplitMax) return ZE_EINVAL;
+    if (!e || slices < 2 || slices > split_max_slices(e->maxN)) return ZE_EINVAL;
     e->slices = slices;
     return ZE_OK;
 }

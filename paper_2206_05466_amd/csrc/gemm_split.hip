@@ -14,8 +14,8 @@
 // Column cc of B~ likewise with 2^-eb_c (one exponent per complex column c; both real columns
 // 2c, 2c+1 hold the same magnitudes).  Then
 //     C~[r][cc] ~= 2^(ea_r + eb_c) sum_{i + j <= s + 1} 2^(-7 (i + j)) (a_i b_j)[r][cc],
-// the products of one t = i + j summed exactly in int32 ((t-1) 2N 127^2 < 2^31 for the sizes
-// and slice counts allowed), then weighted and added in FP64 in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
+// the products of one t = i + j summed exactly in int32 ((t-1) 2N 127^2 < 2^31: the slice
+// count is capped by split_max_slices(N)), then weighted and added in FP64 in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
 // max|row of A~| max|column of B~| per term of the K sum, so s trades accuracy for speed.
 //
 // Column exponents of a skew-Hermitian B equal its row exponents (|B[k][c]| = |B[c][k]| entry

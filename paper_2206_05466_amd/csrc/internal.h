@@ -83,6 +83,15 @@ constexpr int kMaxN = 16384;
 // Largest number of slices of the split-precision products.
 constexpr int kSplitMax = 8;
 
+// Largest slice count whose int32 sums stay exact for size N: the pairs of one order t = i + j
+// (at most s of them) add up to s * 2N * 127^2 in magnitude, which must stay below 2^31
+// (8 up to N = 8192, 4 at N = 16384).
+inline int split_max_slices(int N) {
+    const long long per = 2LL * N * 127 * 127;
+    const long long m = ((1LL << 31) - 1) / per;
+    return (int)(m < kSplitMax ? m : kSplitMax);
+}
+
 // Workspaces of the split-precision products (kSplitMax slices), allocated on first use.
 ze_status ze_ensure_split(ze_ctx* c);
 

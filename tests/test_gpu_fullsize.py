@@ -158,3 +158,35 @@ def test_ensemble64_sampled_members(dev, prec_name):
         if not split:
             assert its[j] == it_ref[-1]
         assert rel(to_host(Ws[j]), Wr) < bar, (j, sizes[j])
+
+
+def test_max_size_n16384_one_step_and_slice_limit(dev):
+    """The largest N the library accepts: one FP64 step and one split-precision step (the
+    default slice count there is the int32-exactness bound, 4) from a low-degree W_0 the
+    oracle assembles.  The oracle cannot step at this size on the host; the checks are the
+    properties every step has: convergence, exact skew-Hermitian output, conservation of
+    C_2 = -||W||_F^2 (pinned at the start by the oracle's closed form), and the split result
+    within the 4-slice error of the FP64 one."""
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler, ZeulerError
+
+    N, h, L = 16384, 0.005, 6
+    W0 = O.assemble(N, omega_coeffs(N, 3, "inv1", lmax=L), lmax=L)
+    c2_ref = -np.linalg.norm(W0) ** 2  # C_2 = tr W^2 = -||W||_F^2 for skew-Hermitian W
+    z = Zeuler(N)
+    with pytest.raises(ZeulerError):
+        z.set_split_slices(5)  # 5 * 2N * 127^2 >= 2^31: int32 sums could overflow
+    Wd = to_dev(W0)
+    del W0
+    c0 = z.casimirs(Wd, 2)
+    assert abs(c0[1] - c2_ref) <= 1e-13 * abs(c2_ref)
+    Ws = Wd.clone()
+    info = z.isomp_step(Wd, h, 1e-12, 8, prec=PREC_FP64)
+    assert info.resid < 1e-12 and info.iters <= 4
+    assert float((Wd + Wd.conj().T).abs().max().item()) == 0.0
+    c1 = z.casimirs(Wd, 2)
+    assert abs(c1[1] - c0[1]) <= 1e-12 * abs(c0[1])
+    info = z.isomp_step(Ws, h, 1e-12, 8, prec=PREC_SPLIT)
+    assert info.resid < 1e-12
+    d = float((torch.linalg.norm(Ws - Wd) / torch.linalg.norm(Wd)).item())
+    assert d < 1e-8, d
+    z.close()
