@@ -333,6 +333,18 @@ def main():
         log(f"ensemble: fp64 {ens['fp64']['aggregate_steps_per_s']:.0f} steps/s, split "
             f"{ens['split']['aggregate_steps_per_s']:.0f} steps/s")
 
+    # context: the vendor library's complex GEMM (torch.matmul on complex128) at the same size
+    Xa = torch.randn(N, N, dtype=torch.complex128, device="cuda")
+    Xb = torch.randn(N, N, dtype=torch.complex128, device="cuda")
+    torch.matmul(Xa, Xb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        Xc = torch.matmul(Xa, Xb)
+    torch.cuda.synchronize()
+    lib_ms = (time.perf_counter() - t0) / 3 * 1e3
+    del Xa, Xb, Xc
+
     s_per_step = m["s_per_step"]
     iters = m["iters_per_step"]
     gemm_ms, gemm_n = prof["product_PW"]
@@ -381,6 +393,9 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": measured_traffic(N),
+            "context_library_zgemm": {"ms": lib_ms, "tflops": 8.0 * N ** 3 / (lib_ms * 1e-3) / 1e12,
+                                      "what": "torch.matmul on complex128 N x N (the vendor BLAS), "
+                                              "same size, same run"},
         },
         "solve_hbm": {
             "achieved_GBps": solve_bytes / solve_avg_s / 1e9,
