@@ -162,6 +162,48 @@ def ensemble_leg(nsteps, prec, slices=5):
     }
 
 
+def small_leg(steps):
+    """Workload n512 (one simulation, N = 512, 100 steps): the single-simulation entry point
+    (one host check of the residual per evaluation) and the same simulation as an ensemble of
+    one (graph-captured step, on-device stopping)."""
+    import torch
+
+    from paper_2206_05466_amd import PREC_FP64, Ensemble, Zeuler
+    from workloads import WORKLOADS, omega_coeffs
+
+    cfg = WORKLOADS["n512"]
+    N, h, tol = cfg["N"], cfg["h"], cfg["tol"]
+    z = Zeuler(N)
+    W0 = z.basis_assemble(omega_coeffs(N, cfg["seeds"][0], cfg["law"]))
+    z.set_initial_guess(1)
+    W = W0.clone()
+    z.isomp_run(W, h, 2, tol, cfg["maxit"])
+    W = W0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, res = z.isomp_run(W, h, steps, tol, cfg["maxit"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Wg = W0.clone()
+    with Ensemble([N]) as ens:
+        ens.run([Wg.clone()], h, 2, tol, 8, prec=PREC_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.run([Wg], h, steps, tol, 8, prec=PREC_FP64)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+    diff = float((torch.linalg.norm(Wg - W) / torch.linalg.norm(W)).item())
+    z.close()
+    return {
+        "workload": f"n512: one simulation, N={N}, sigma_l law {cfg['law']}, h={h}, tol={tol}, {steps} steps",
+        "single_context_s_per_step": dt / steps,
+        "iters_per_step": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
+        "graph_ensemble_of_one_s_per_step": dtg / steps,
+        "rel_frobenius_between_the_two": diff,
+        "note": "the graph form starts every step from W_n (no extrapolated guess)",
+    }
+
+
 def casimir_drift(c0, c1, W):
     """Relative drift of C_2, C_4; C_3 relative to ||W||_F^3 (C_3 can be tiny)."""
     import torch
@@ -288,6 +330,8 @@ def main():
                     help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
     ap.add_argument("--n2048-steps", type=int, default=20,
                     help="timed steps of the N=2048 leg, FP64 and split (0: skip it)")
+    ap.add_argument("--n512-steps", type=int, default=100,
+                    help="timed steps of the N=512 leg (0: skip it)")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -323,6 +367,8 @@ def main():
             "phases": phases_of(m2["prof"]),
             "split_precision": m2["split_precision"],
         }
+
+    n512 = small_leg(args.n512_steps) if args.n512_steps > 0 else None
 
     ens = None
     if args.ensemble_steps > 0:
@@ -407,6 +453,7 @@ def main():
         "cpu_baseline": None,
         "split_precision": m["split_precision"],
         "n2048": n2048,
+        "n512": n512,
         "ensemble": ens,
     }
     if not args.no_cpu_baseline:

@@ -381,3 +381,40 @@ def test_isomp_run_extrapolated_guess(dev, prec_name):
         W = to_host(Wd)
     assert its == it_ref and max(res) < 1e-12, (its, it_ref)
     assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
+
+
+# ------------------------------------------------------------------ long-run properties
+def test_long_run_isospectral_n64(dev):
+    """2000 steps (the paper's long run: degrees 2..20 only, unit spectral norm, Sec. 4) on the
+    GPU: the spectrum of iW and the Casimirs stay those of W_0 (the scheme is isospectral up to
+    the fixed-point tolerance), W stays exactly skew-Hermitian, and every step converges."""
+    N, h, steps = 64, 0.01, 2000
+    W0 = w0(N, 11, "paper")
+    W0 = W0 / np.linalg.norm(W0, 2)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_initial_guess(1)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 20)
+    W = to_host(Wd)
+    assert max(res) < 1e-12 and max(its) <= 4
+    assert np.abs(W + W.conj().T).max() == 0.0
+    lam0 = np.linalg.eigvalsh(1j * W0)
+    lam = np.linalg.eigvalsh(1j * W)
+    assert np.abs(lam - lam0).max() <= 1e-10, np.abs(lam - lam0).max()
+    c0, c1 = O.casimirs(W0, 4), O.casimirs(W, 4)
+    assert abs(c1[1] - c0[1]) <= 1e-10 * abs(c0[1]) and abs(c1[3] - c0[3]) <= 1e-10 * abs(c0[3])
+    assert np.linalg.norm(W - W0) > 1e-2 * np.linalg.norm(W0)  # the field did evolve
+
+
+def test_reversibility(dev):
+    """A step with h followed by a step with -h returns W_0 (the midpoint scheme is symmetric);
+    the two fixed points are each met to the tolerance."""
+    N, h = 128, 0.02
+    W0 = w0(N, 12)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        a = z.isomp_step(Wd, h, 1e-13, 50)
+        b = z.isomp_step(Wd, -h, 1e-13, 50)
+    assert a.converged and b.converged
+    W = to_host(Wd)
+    assert np.linalg.norm(W - W0) <= 1e-12 * np.linalg.norm(W0), np.linalg.norm(W - W0) / np.linalg.norm(W0)

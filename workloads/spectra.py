@@ -16,8 +16,8 @@ Spectral laws (sigma_l):
 * ``inv1``   -- (l+1)^-1 over l = 1..N-1;
 * ``inv1.5`` -- (l+1)^-1.5 over l = 1..N-1;
 * ``paper``  -- 1 over 2 <= l <= 20, 0 elsewhere: the random large-scale initial condition
-  of the paper's long simulation (Sec. 4), "modes of degree 2..20 with random values of
-  about the same magnitude".
+  of the paper's long simulation (Sec. 4), random coefficients of comparable size on the
+  degrees 2 to 20 only.
 """
 
 import numpy as np
