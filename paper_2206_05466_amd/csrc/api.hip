@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "solve_wg.h"
 
 namespace {
 
@@ -119,16 +120,18 @@ ze_status ze_destroy(ze_ctx* c) {
     return ZE_OK;
 }
 
-ze_status ze_create(int N, void* stream, ze_ctx** out) { return ze_create_ctx(N, stream, true, out); }
+ze_status ze_create(int N, void* stream, ze_ctx** out) { return ze_create_ctx(N, stream, true, 0, out); }
 
 }  // extern "C"
 
-ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
+ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx** out) {
     if (!out) return ZE_EINVAL;
     *out = nullptr;
     if (N < 1 || N > kMaxN) return ZE_EINVAL;
+    if (solve_bd_ != 0 && solve_bd_ != 1 && solve_bd_ != 2 && solve_bd_ != 4) return ZE_EINVAL;
     ze_ctx* c = new ze_ctx();
     c->N = N;
+    c->solve_bd = solve_bd_ ? solve_bd_ : zk::solve_bd(N);
     c->split_slices = split_max_slices(N) < 6 ? split_max_slices(N) : 6;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -136,7 +139,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out) {
         return ze_record_hip(hipGetLastError(), "hipGetDevice");
     }
     std::vector<double> fl, fd;
-    ze_build_factors(N, fl, fd);
+    ze_build_factors(N, c->solve_bd, fl, fd);
     const size_t nn = (size_t)N * N;
     const int T = (N + 63) / 64;
     {

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
     if (part == 0 && threadIdx.x == 0) done[sim] = 0;
 }
 
-template <int T, int C>
+template <int T, int C, int BD>
 __global__ __launch_bounds__(T) void ens_solve_kernel(const EnsProb* __restrict__ probs,
                                                       const int2* __restrict__ work,
                                                       const int* __restrict__ done, int eval) {
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(T) void ens_solve_kernel(const EnsProb* __restrict_
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
     const double2* Wt = eval == 1 ? p.Wn : p.F;
-    solve_pair<T, C>(Wt, p.P, p.fl, p.fd, p.N, it.y, sG, sY);
+    solve_band<T, C, BD>(Wt, p.P, p.fl, p.fd, p.N, it.y, sG, sY);
 }
 
 template <class C>
@@ -251,23 +251,26 @@ __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restric
     }
 }
 
-// Grouped launches of one evaluation phase, by the solve's (T, C) for the largest N.
-template <int T, int C>
+// Grouped stream solve of every simulation.  All contexts of an ensemble share one band width,
+// ens_bd(maxN), and the launch shape satisfies (T / BD) C >= N + BD for every N <= maxN.
+template <int T, int C, int BD>
 hipError_t launch_ens_solve(const EnsProb* probs, const int2* work, int n, const int* done,
                             int eval, hipStream_t s) {
-    hipLaunchKernelGGL((ens_solve_kernel<T, C>), dim3(n), dim3(T), 0, s, probs, work, done, eval);
+    hipLaunchKernelGGL((ens_solve_kernel<T, C, BD>), dim3(n), dim3(T), 0, s, probs, work, done, eval);
     return hipGetLastError();
 }
 
+int ens_bd(int maxN) { return solve_bd(maxN); }
+
 hipError_t ens_solve(int maxN, const EnsProb* probs, const int2* work, int n, const int* done,
                      int eval, hipStream_t s) {
-    if (maxN <= 64) return launch_ens_solve<64, 1>(probs, work, n, done, eval, s);
-    if (maxN <= 128) return launch_ens_solve<128, 1>(probs, work, n, done, eval, s);
-    if (maxN <= 256) return launch_ens_solve<256, 1>(probs, work, n, done, eval, s);
-    if (maxN <= 512) return launch_ens_solve<256, 2>(probs, work, n, done, eval, s);
-    if (maxN <= 1024) return launch_ens_solve<256, 4>(probs, work, n, done, eval, s);
-    if (maxN <= 2048) return launch_ens_solve<256, 8>(probs, work, n, done, eval, s);
-    return launch_ens_solve<256, 16>(probs, work, n, done, eval, s);
+    if (ens_bd(maxN) == 2) return launch_ens_solve<1024, 9, 2>(probs, work, n, done, eval, s);
+    if (maxN <= 76) return launch_ens_solve<64, 5, 4>(probs, work, n, done, eval, s);
+    if (maxN <= 156) return launch_ens_solve<128, 5, 4>(probs, work, n, done, eval, s);
+    if (maxN <= 316) return launch_ens_solve<256, 5, 4>(probs, work, n, done, eval, s);
+    if (maxN <= 572) return launch_ens_solve<256, 9, 4>(probs, work, n, done, eval, s);
+    if (maxN <= 1084) return launch_ens_solve<256, 17, 4>(probs, work, n, done, eval, s);
+    return launch_ens_solve<512, 17, 4>(probs, work, n, done, eval, s);
 }
 
 using WideCfg = FullCfg;  // 128 x 64 complex
@@ -573,7 +576,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     e->ctx.assign(nsim, nullptr);
     e->hp.resize(nsim);
     for (int i = 0; i < nsim; ++i) {
-        st = ze_create_ctx(e->N[i], e->own, false, &e->ctx[i]);
+        st = ze_create_ctx(e->N[i], e->own, false, ens_bd(e->maxN), &e->ctx[i]);
         if (st != ZE_OK) return fail(st);
         ze_ctx* c = e->ctx[i];
         e->hp[i] = EnsProb{c->N,        0,          nullptr, c->Wn,   c->F,    c->P,    c->A,
@@ -588,7 +591,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     std::vector<int> r0(nsim), r1(nsim), ccol(nsim), ccomb(nsim), i8f(nsim), i8l(nsim);
     for (int i = 0; i < nsim; ++i) {
         const int n = e->N[i], T = (n + kTile - 1) / kTile;
-        cs[i] = n / 2 + 1;
+        cs[i] = solve_bands(n, ens_bd(e->maxN));
         c0[i] = tiles_of(n, 0);
         c1[i] = tiles_of(n, 1);
         cl[i] = T * (T + 1) / 2;

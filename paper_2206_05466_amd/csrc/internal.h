@@ -36,6 +36,7 @@ struct ze_ctx {
     // first, then the pairs (m, N-m), m = 1..N/2, each at offset m*N): per element, the
     // multiplier met when the forward sweep reaches it (0 at the first element of each
     // diagonal) and 1/D (0 for the excluded last element of the singular m = 0 block).
+    int solve_bd = 4;  // lanes per band of the stream solve (factor layout, launch shape)
     double* fac_l = nullptr;
     double* fac_dinv = nullptr;
 
@@ -102,10 +103,12 @@ __host__ __device__ inline int split_rows_pad(int N) { return ((N + 127) / 128) 
 __host__ __device__ inline int split_cols_pad(int N) { return ((2 * N + 127) / 128) * 128; }
 
 // ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
-ze_status ze_create_ctx(int N, void* stream, bool split_k, ze_ctx** out);
+// solve_bd: stream-solve band width (1, 2 or 4), 0 = the default for N (solve_bd(N)).
+ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd, ze_ctx** out);
 
-// Host: the factors held in ze_ctx::fac_l / fac_dinv (N (N+1) / 2 entries each).
-void ze_build_factors(int N, std::vector<double>& fl, std::vector<double>& fd);
+// Host: the factors held in ze_ctx::fac_l / fac_dinv (about N^2 / 2 entries each, in the
+// band order of the stream solve).
+void ze_build_factors(int N, int bd, std::vector<double>& fl, std::vector<double>& fd);
 
 // ---- kernel launchers (all asynchronous on `s`) ----
 

@@ -45,145 +45,238 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* s) {
     return r;
 }
 
-// Solves the diagonal pair of workgroup w (see solve.hip) for an N x N problem.
-template <int T, int C>
-__device__ __forceinline__ void solve_pair(const double2* __restrict__ W, double2* __restrict__ P,
-                                  const double* __restrict__ fl, const double* __restrict__ fd,
-                                  int N, int w, double* sG, double2* sY) {
-    int m1, n1, m2;
-    if (w == 0) {
-        m1 = 0;
-        n1 = N;
-        m2 = -1;
-    } else {
-        m1 = w;
-        n1 = N - w;
-        m2 = (N - w != w) ? N - w : -1;
+// ---------------------------------------------------------------- band layout
+// Diagonal m is paired with m' = N - 1 - m (together N + 1 entries).  Band k holds the
+// "main" diagonals m = k BD + d (lane d = 0..BD-1) and their partners m'.  All entries a band
+// touches are placed on virtual rows rho = -BD .. N-1 so that, on every virtual row, the BD
+// lanes touch BD neighbouring entries of ONE matrix row:
+//   main entry i of diagonal m:      rho = i + m,              matrix (rho, rho - m);
+//   partner entry i of diagonal m':  rho = i - 1 - d,          matrix (rho + N - k BD, i);
+// so lane d's partner occupies rho in [-1-d, k BD) and its main diagonal rho in [k BD + d, N):
+// one chain per lane, partner first, a gap between.  The first entry of each diagonal has
+// multiplier 0, which keeps the two recurrences (and the gap) apart.  Mains cover
+// [0, K BD), partners the rest; a partner that is itself a main (m' < K BD) is skipped.
+// Default band width: a thread holds C <= 17 rows (the launch shapes of solve.hip); wider
+// bands mean longer row segments per access, narrower ones smaller workgroups and fewer
+// registers (measured: 4 lanes up to N = 2172, 2 lanes of 9 rows at N = 4096).
+__host__ __device__ inline int solve_bd(int N) { return N <= 2172 ? 4 : (N <= 4606 ? 2 : 1); }
+__host__ __device__ inline int solve_bands(int N, int bd) { return (N + 2 * bd - 1) / (2 * bd); }
+__host__ __device__ inline int solve_rows(int N, int bd) { return N + bd; }  // virtual rows
+
+// Entry of lane d at virtual row v of band k: matrix offset, or -1 for none.
+__host__ __device__ inline long long solve_entry(int N, int bd, int K, int k, int d, int v,
+                                                 bool* is_main, int* m_out) {
+    const int rho = v - bd, m0 = k * bd, m = m0 + d, mp = N - 1 - m;
+    if (m < N && rho >= m0 + d) {  // main
+        *is_main = true;
+        *m_out = m;
+        return (long long)rho * N + (rho - m);
     }
-    const int L = n1 + (m2 >= 0 ? w : 0);
-    const size_t base = (size_t)w * N;
-    const double* flw = fl + base;
-    const double* fdw = fd + base;
-    const int t = threadIdx.x;
-    const int k0 = t * C;
+    if (mp >= K * bd && rho >= -1 - d && rho < m0) {  // partner
+        *is_main = false;
+        *m_out = mp;
+        return (long long)(rho + N - m0) * N + (rho + 1 + d);
+    }
+    return -1;
+}
 
-    auto entry = [&](int k) -> size_t {  // matrix offset of virtual element k
-        const int m = k < n1 ? m1 : m2;
-        const int i = k < n1 ? k : k - n1;
-        return (size_t)(i + m) * N + i;
-    };
-
-    double2 v[C];
-    double l[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int k = k0 + c;
-        if (k < L) {
-            v[c] = W[entry(k)];
-            l[c] = flw[k];
-        } else {
-            v[c] = make_double2(0.0, 0.0);
-            l[c] = 0.0;
+// Inclusive scan over the chunks c (threads c * BD + d of one lane d, in order c, or
+// reversed) of the affine maps f(x) = G x + Y: earlier maps are applied first.
+template <int T, int BD>
+__device__ __forceinline__ void lane_scan_affine(double& G, double2& Y, bool reverse, double* sG,
+                                                 double2* sY) {
+    constexpr int CH = T / BD;
+    const int t = threadIdx.x, c = t / BD;
+    for (int off = 1; off < CH; off <<= 1) {
+        sG[t] = G;
+        sY[t] = Y;
+        __syncthreads();
+        const int sc = reverse ? c + off : c - off;
+        if (sc >= 0 && sc < CH) {
+            const int src = t + (sc - c) * BD;
+            const double pg = sG[src];
+            const double2 py = sY[src];
+            Y.x += G * py.x;
+            Y.y += G * py.y;
+            G *= pg;
         }
-    }
-
-    if (w == 0) {  // trace removal on the singular block (all L = N elements are diagonal 0)
-        double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s.x += v[c].x;
-            s.y += v[c].y;
-        }
-        const double2 tr = block_sum<T>(s, sY);
-        const double ir = tr.x / N, ii = tr.y / N;
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (k0 + c < L) {
-                v[c].x -= ir;
-                v[c].y -= ii;
-            }
-    }
-
-    // Forward sweep: local pass with zero carry.
-    double G = 1.0;
-    double2 y = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        y.x = v[c].x - l[c] * y.x;
-        y.y = v[c].y - l[c] * y.y;
-        G *= -l[c];
-        v[c] = y;
-    }
-    double2 Y = y;
-    block_scan_affine<T>(G, Y, false, sG, sY);
-    sY[t] = Y;  // inclusive: true y at the end of chunk t
-    __syncthreads();
-    const double2 cin = t > 0 ? sY[t - 1] : make_double2(0.0, 0.0);
-    __syncthreads();
-    double g = 1.0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int k = k0 + c;
-        g *= -l[c];
-        const double dv = k < L ? fdw[k] : 0.0;
-        v[c].x = (v[c].x + g * cin.x) * dv;
-        v[c].y = (v[c].y + g * cin.y) * dv;
-    }
-
-    // Backward sweep: x_k = z_k - l_{k+1} x_{k+1}; local pass from the chunk end.
-    const double lend = (k0 + C < L) ? flw[k0 + C] : 0.0;
-    G = 1.0;
-    double2 x = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = C - 1; c >= 0; --c) {
-        const double ln = (c == C - 1) ? lend : l[c + 1];
-        x.x = v[c].x - ln * x.x;
-        x.y = v[c].y - ln * x.y;
-        G *= -ln;
-        v[c] = x;
-    }
-    Y = x;
-    block_scan_affine<T>(G, Y, true, sG, sY);
-    sY[t] = Y;  // inclusive from the right: true x at the start of chunk t
-    __syncthreads();
-    const double2 cr = t + 1 < T ? sY[t + 1] : make_double2(0.0, 0.0);
-    __syncthreads();
-    g = 1.0;
-#pragma unroll
-    for (int c = C - 1; c >= 0; --c) {
-        const double ln = (c == C - 1) ? lend : l[c + 1];
-        g *= -ln;
-        v[c].x += g * cr.x;
-        v[c].y += g * cr.y;
-    }
-
-    if (w == 0) {  // minimum-norm solution: subtract the mean
-        double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s.x += v[c].x;
-            s.y += v[c].y;
-        }
-        const double2 sx = block_sum<T>(s, sY);
-        const double mr = sx.x / N, mi = sx.y / N;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            v[c].x -= mr;
-            v[c].y -= mi;
-        }
-    }
-
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int k = k0 + c;
-        if (k < L) {
-            const int m = k < n1 ? m1 : m2;
-            const int i = k < n1 ? k : k - n1;
-            P[(size_t)(i + m) * N + i] = make_double2(-v[c].x, -v[c].y);
-            if (m > 0) P[(size_t)i * N + i + m] = make_double2(v[c].x, -v[c].y);
-        }
+        __syncthreads();
     }
 }
 
+// Stream solve of band k (BD lanes, T / BD chunks of C virtual rows each) of an N x N problem.
+// Every global access is a run of BD neighbouring complex entries of one matrix row.
+template <int T, int C, int BD>
+__device__ __forceinline__ void solve_band(const double2* __restrict__ W, double2* __restrict__ P,
+                                           const double* __restrict__ fl,
+                                           const double* __restrict__ fd, int N, int k,
+                                           double* sG, double2* sY) {
+    const int K = solve_bands(N, BD), R = solve_rows(N, BD);
+    const int t = threadIdx.x, c = t / BD, d = t % BD;
+    const int v0 = c * C;
+    const int m0 = k * BD, m = m0 + d, mp = N - 1 - m;
+    const bool main_ok = m < N, part_ok = mp >= K * BD;
+    const size_t fb = (size_t)k * R * BD + d;  // factor (k, v, d) at fb + v * BD
+
+    double2 x[C];
+    double l[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int v = v0 + j;
+        bool im;
+        int mm;
+        const long long e = v < R ? solve_entry(N, BD, K, k, d, v, &im, &mm) : -1;
+        x[j] = e >= 0 ? W[e] : make_double2(0.0, 0.0);
+        l[j] = v < R ? fl[fb + (size_t)v * BD] : 0.0;
+    }
+
+    const bool sing = (k == 0 && d == 0);  // diagonal 0: pseudo-inverse
+    if (k == 0) {  // remove tr(W)/N from diagonal 0's right-hand side (its entries are main)
+        double2 sum = make_double2(0.0, 0.0);
+        if (sing)
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int rho = v0 + j - BD;  // lane 0 also holds diagonal N-1 at rho = -1
+                if (rho >= 0 && rho < N) {
+                    sum.x += x[j].x;
+                    sum.y += x[j].y;
+                }
+            }
+        const double2 tr = block_sum<T>(sum, sY);
+        if (sing) {
+            const double ir = tr.x / N, ii = tr.y / N;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int rho = v0 + j - BD;
+                if (rho >= 0 && rho < N) {
+                    x[j].x -= ir;
+                    x[j].y -= ii;
+                }
+            }
+        }
+    }
+
+    // forward sweep y_v = b_v - l_v y_{v-1}: local pass with zero carry, lane scan, fix-up
+    double G = 1.0;
+    double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        y.x = x[j].x - l[j] * y.x;
+        y.y = x[j].y - l[j] * y.y;
+        G *= -l[j];
+        x[j] = y;
+    }
+    double2 Y = y;
+    lane_scan_affine<T, BD>(G, Y, false, sG, sY);
+    sY[t] = Y;  // inclusive: true y at the end of chunk c
+    __syncthreads();
+    const double2 cin = c > 0 ? sY[t - BD] : make_double2(0.0, 0.0);
+    __syncthreads();
+    double g = 1.0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int v = v0 + j;
+        g *= -l[j];
+        const double dv = v < R ? fd[fb + (size_t)v * BD] : 0.0;
+        x[j].x = (x[j].x + g * cin.x) * dv;
+        x[j].y = (x[j].y + g * cin.y) * dv;
+    }
+
+    // backward sweep x_v = z_v - l_{v+1} x_{v+1}
+    const double lend = (v0 + C < R) ? fl[fb + (size_t)(v0 + C) * BD] : 0.0;
+    G = 1.0;
+    double2 xx = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+        const double ln = (j == C - 1) ? lend : l[j + 1];
+        xx.x = x[j].x - ln * xx.x;
+        xx.y = x[j].y - ln * xx.y;
+        G *= -ln;
+        x[j] = xx;
+    }
+    Y = xx;
+    lane_scan_affine<T, BD>(G, Y, true, sG, sY);
+    sY[t] = Y;  // inclusive from the right: true x at the start of chunk c
+    __syncthreads();
+    const double2 cr = c + 1 < T / BD ? sY[t + BD] : make_double2(0.0, 0.0);
+    __syncthreads();
+    g = 1.0;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+        const double ln = (j == C - 1) ? lend : l[j + 1];
+        g *= -ln;
+        x[j].x += g * cr.x;
+        x[j].y += g * cr.y;
+    }
+
+    if (k == 0) {  // minimum-norm solution on diagonal 0: subtract the mean
+        double2 sum = make_double2(0.0, 0.0);
+        if (sing)
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int rho = v0 + j - BD;
+                if (rho >= 0 && rho < N) {
+                    sum.x += x[j].x;
+                    sum.y += x[j].y;
+                }
+            }
+        const double2 sx = block_sum<T>(sum, sY);
+        if (sing) {
+            const double mr = sx.x / N, mi = sx.y / N;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int rho = v0 + j - BD;
+                if (rho >= 0 && rho < N) {
+                    x[j].x -= mr;
+                    x[j].y -= mi;
+                }
+            }
+        }
+    }
+
+    // lower entries: -x at the entries read (the Laplacian is -Delta^m on diagonal m)
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int v = v0 + j;
+        bool im;
+        int mm;
+        const long long e = v < R ? solve_entry(N, BD, K, k, d, v, &im, &mm) : -1;
+        if (e >= 0) P[e] = make_double2(-x[j].x, -x[j].y);
+    }
+    // upper entries conj(x), P[i][i + m]: lane d writes its entry j = q + d (main) or
+    // j = q - d (partner), which puts the BD lanes of a step on one matrix row
+#pragma unroll
+    for (int q = -(BD - 1); q < C; ++q) {
+        double2 val = make_double2(0.0, 0.0);
+        bool have = false;
+#pragma unroll
+        for (int dd = 0; dd < BD; ++dd) {
+            const int j = q + dd;
+            if (j >= 0 && j < C && d == dd) {
+                val = x[j];
+                have = true;
+            }
+        }
+        const int rho = v0 + q + d - BD;
+        if (have && main_ok && m > 0 && rho >= m0 + d && rho < N)
+            P[(size_t)(rho - m) * N + rho] = make_double2(val.x, -val.y);
+    }
+#pragma unroll
+    for (int q = 0; q < C + BD - 1; ++q) {
+        double2 val = make_double2(0.0, 0.0);
+        bool have = false;
+#pragma unroll
+        for (int dd = 0; dd < BD; ++dd) {
+            const int j = q - dd;
+            if (j >= 0 && j < C && d == dd) {
+                val = x[j];
+                have = true;
+            }
+        }
+        const int rho = v0 + q - d - BD;
+        if (have && part_ok && rho >= -1 - d && rho < m0)
+            P[(size_t)(rho + 1 + d) * N + (rho + N - m0)] = make_double2(val.x, -val.y);
+    }
+}
 
 }  // namespace zk
