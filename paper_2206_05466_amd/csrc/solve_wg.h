@@ -81,27 +81,58 @@ __host__ __device__ inline long long solve_entry(int N, int bd, int K, int k, in
 }
 
 // Inclusive scan over the chunks c (threads c * BD + d of one lane d, in order c, or
-// reversed) of the affine maps f(x) = G x + Y: earlier maps are applied first.
+// reversed) of the affine maps f(x) = G x + Y: earlier maps are applied first.  Within a wave
+// by shuffles (no barrier), then across the T / 64 waves through LDS: one barrier.
 template <int T, int BD>
 __device__ __forceinline__ void lane_scan_affine(double& G, double2& Y, bool reverse, double* sG,
                                                  double2* sY) {
-    constexpr int CH = T / BD;
-    const int t = threadIdx.x, c = t / BD;
-    for (int off = 1; off < CH; off <<= 1) {
-        sG[t] = G;
-        sY[t] = Y;
-        __syncthreads();
-        const int sc = reverse ? c + off : c - off;
-        if (sc >= 0 && sc < CH) {
-            const int src = t + (sc - c) * BD;
-            const double pg = sG[src];
-            const double2 py = sY[src];
-            Y.x += G * py.x;
-            Y.y += G * py.y;
+    constexpr int CW = 64 / BD;  // chunks per wave
+    constexpr int NW = T / 64;   // waves
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, cw = l / BD;
+#pragma unroll
+    for (int off = 1; off < CW; off <<= 1) {
+        const int sh = off * BD;
+        const double pg = reverse ? __shfl_down(G, sh, 64) : __shfl_up(G, sh, 64);
+        const double px = reverse ? __shfl_down(Y.x, sh, 64) : __shfl_up(Y.x, sh, 64);
+        const double py = reverse ? __shfl_down(Y.y, sh, 64) : __shfl_up(Y.y, sh, 64);
+        if (reverse ? cw + off < CW : cw >= off) {
+            Y.x += G * px;
+            Y.y += G * py;
             G *= pg;
         }
-        __syncthreads();
     }
+    if (NW == 1) return;
+    // wave aggregates (last chunk of the wave in scan order), one per lane d
+    if (reverse ? cw == 0 : cw == CW - 1) {
+        sG[w * BD + (l % BD)] = G;
+        sY[w * BD + (l % BD)] = Y;
+    }
+    __syncthreads();
+    // compose the aggregates of the waves before this one (in scan order), nearest first
+    double pg = 1.0;
+    double2 py = make_double2(0.0, 0.0);
+    const int d = l % BD;
+    if (reverse) {
+        for (int v = w + 1; v < NW; ++v) {  // p <- p o agg(v)
+            const double ag = sG[v * BD + d];
+            const double2 ay = sY[v * BD + d];
+            py.x += pg * ay.x;
+            py.y += pg * ay.y;
+            pg *= ag;
+        }
+    } else {
+        for (int v = w - 1; v >= 0; --v) {
+            const double ag = sG[v * BD + d];
+            const double2 ay = sY[v * BD + d];
+            py.x += pg * ay.x;
+            py.y += pg * ay.y;
+            pg *= ag;
+        }
+    }
+    Y.x += G * py.x;
+    Y.y += G * py.y;
+    G *= pg;
+    __syncthreads();  // sG / sY are reused right after
 }
 
 // Stream solve of band k (BD lanes, T / BD chunks of C virtual rows each) of an N x N problem.
