@@ -9,8 +9,10 @@
 // its memory is a real M x 2K matrix X~.  For B (K x N complex) let B~ be the real 2K x 2N
 // matrix whose 2 x 2 block (k, c) is [[Re b, Im b], [-Im b, Re b]].  Then X~ B~ is exactly
 // the interleaved storage of X B (8 M N K real flops), so the operands are read as they lie
-// in memory and B~ is formed on the fly from the LDS copy of B: each lane of the B operand
-// reads one component of one B element, with a lane-constant sign.
+// in memory and B~ is formed from the LDS copy of B: either written out when a stage is
+// stored (both rows of each 2 x 2 block, signs applied there; the full product) or read per
+// lane as one component of one B element with a lane-constant sign (the 64 x 64 tiles, where
+// the smaller stage keeps three blocks per CU).
 //
 // MFMA operand layout (16x16x4, f64): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator register r of lane l holds D[l/16 + 4*r][l%16].

@@ -11,8 +11,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;  // 4 waves
 constexpr int kBK = 8;         // complex k per LDS stage (16 real k = 4 MFMA k-steps)
 
-template <int BM_, int BNC_, int WM_, int WNC_>
+// SB_: B~ itself in LDS (both rows of each 2 x 2 block, signs applied when the stage is
+// stored: one plain read per operand, twice the B stage) or B as it lies in memory (each lane
+// reads one component and applies a lane-constant sign).  The first is faster where LDS does
+// not limit the blocks per CU (the full product), the second where it does (64 x 64 tiles).
+template <int BM_, int BNC_, int WM_, int WNC_, bool SB_>
 struct Cfg {
+    static constexpr bool SB = SB_;
     static constexpr int BM = BM_;     // block rows
     static constexpr int BNC = BNC_;   // block columns (complex)
     static constexpr int WM = WM_;     // wave rows
@@ -21,9 +26,12 @@ struct Cfg {
     static constexpr int NT = 2 * WNC / 16;   // MFMA tiles per wave, real columns
     static constexpr int WAVES_N = BNC / WNC;
     static constexpr int AS_LD = BM + 1;           // A stage: [16 real k][BM rows] (+1 pad)
-    static constexpr int BS_LD = 2 * BNC + 2;      // B stage: [8 complex k][2*BNC doubles] (+pad)
+    // B stage, SB: [16 real k rows of B~][2*BNC doubles] (+16 pad, so that the two rows one
+    // MFMA k-step reads start 32 banks apart): row 2k holds (Re b, Im b) per column, row 2k+1
+    // holds (-Im b, Re b).  Otherwise: [8 complex k][2*BNC doubles] (+2 pad).
+    static constexpr int BS_LD = SB ? 2 * BNC + 16 : 2 * BNC + 2;
     static constexpr int AS = 2 * kBK * AS_LD;
-    static constexpr int BS = kBK * BS_LD;
+    static constexpr int BS = (SB ? 2 : 1) * kBK * BS_LD;
     static constexpr int STAGE = AS + BS;          // doubles per stage
     static constexpr int A_LOADS = BM * kBK / kThreads;
     static constexpr int B_LOADS = kBK * BNC / kThreads;
@@ -71,7 +79,13 @@ __device__ __forceinline__ void store_stage(double* __restrict__ st, const doubl
     for (int j = 0; j < C::B_LOADS; ++j) {
         const int idx = tid + j * kThreads;
         const int kc = idx / C::BNC, c = idx % C::BNC;
-        *reinterpret_cast<double2*>(bs + kc * C::BS_LD + 2 * c) = rb[j];
+        if (C::SB) {
+            *reinterpret_cast<double2*>(bs + (2 * kc) * C::BS_LD + 2 * c) = rb[j];
+            *reinterpret_cast<double2*>(bs + (2 * kc + 1) * C::BS_LD + 2 * c) =
+                make_double2(-rb[j].y, rb[j].x);
+        } else {
+            *reinterpret_cast<double2*>(bs + kc * C::BS_LD + 2 * c) = rb[j];
+        }
     }
 }
 
@@ -88,7 +102,7 @@ __device__ __forceinline__ void compute_stage(const double* __restrict__ st, int
     const double* bs = st + C::AS;
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4) {
-        const int kk = 4 * k4 + q;
+        const int kk = 4 * k4 + q;  // real k: row kk of B~
         const int kc = 2 * k4 + (q >> 1);
         double a[C::MT], b[C::NT];
 #pragma unroll
@@ -96,7 +110,7 @@ __device__ __forceinline__ void compute_stage(const double* __restrict__ st, int
 #pragma unroll
         for (int nt = 0; nt < C::NT; ++nt) {
             const int cc = wcc + nt * 16 + l16;
-            b[nt] = sgn * bs[kc * C::BS_LD + (cc & ~1) + (t ^ u)];
+            b[nt] = C::SB ? bs[kk * C::BS_LD + cc] : sgn * bs[kc * C::BS_LD + (cc & ~1) + (t ^ u)];
         }
 #pragma unroll
         for (int mt = 0; mt < C::MT; ++mt)
@@ -135,7 +149,7 @@ __device__ __forceinline__ void mainloop(const double2* __restrict__ A, int lda,
     }
 }
 
-using FullCfg = Cfg<128, 64, 64, 32>;
+using FullCfg = Cfg<128, 64, 64, 32, true>;
 
 // Store a block's accumulators (MFMA layout of config C) to C~ (complex N x N), bounds-checked.
 template <class C>
@@ -167,7 +181,7 @@ __device__ __forceinline__ void store_full_tile(const d4 (&acc)[FullCfg::MT][Ful
 }
 
 // ---------------------------------------------------------------- lower product + epilogue
-using LowCfg = Cfg<64, 64, 32, 32>;
+using LowCfg = Cfg<64, 64, 32, 32, false>;
 constexpr int kTile = 64;  // square complex tile of the lower-triangle product
 
 // Tile index b of the lower triangle -> (I, J), I >= J, b = I (I+1)/2 + J.
