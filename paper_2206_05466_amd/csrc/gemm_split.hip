@@ -88,8 +88,28 @@ __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
     int ti, tj;
     const int b = blockIdx.x;
     if (mode == 0) {
-        ti = b / tiles_n;
-        tj = b % tiles_n;
+        // XCD-aware order: blocks b with b % 8 == x run on XCD x.  With the tile grid split
+        // into 2 x 4 regions, XCD x takes region (x / 4, x % 4), walked in 8 x 8 super-tiles,
+        // so the tiles an XCD holds at once share A~ and B~^T panels in its L2.
+        const int tm = gridDim.x / tiles_n;
+        if (tm % 2 == 0 && tiles_n % 4 == 0) {
+            const int x = b & 7, L = b >> 3;
+            const int rm = tm / 2, rn = tiles_n / 4;
+            int r, c;
+            if (rm % 8 == 0 && rn % 8 == 0) {
+                const int sg = L >> 6, w = L & 63, spr = rn / 8;
+                r = (sg / spr) * 8 + (w >> 3);
+                c = (sg % spr) * 8 + (w & 7);
+            } else {
+                r = L / rn;
+                c = L % rn;
+            }
+            ti = (x >> 2) * rm + r;
+            tj = (x & 3) * rn + c;
+        } else {
+            ti = b / tiles_n;
+            tj = b % tiles_n;
+        }
     } else {
         i8_lower_tile(b, ti, tj);
         if (tj >= tiles_n) return;  // ragged N: block idle (uniform)

@@ -179,8 +179,8 @@ __device__ __forceinline__ void i8_next_pair(int& i, int& j) {
 // Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
 // each) and sb (B~^T, split_cols_pad(N) x ldk each).  Each iteration issues the global loads
 // of the next stage, computes the current stage from LDS, and stores the next stage to the
-// other LDS buffer late in the stage; scheduling barriers keep that order (left alone, the
-// compiler moves the LDS store up to the loads, which waits for them before the MFMAs).
+// other LDS buffer at the end of the stage; scheduling barriers keep that order (left alone,
+// the compiler moves the LDS store up to the loads, which waits for them before the MFMAs).
 __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char* __restrict__ sa,
                                               const signed char* __restrict__ sb,
                                               int* __restrict__ G, int N, int s, int ldk,
@@ -252,7 +252,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
         const signed char* st = sm.stage + (it & 1) * kI8Stage;
         // software-pipelined operand reads: the 4 fragments of k-step ks + 1 are read while
         // the 4 MFMAs of k-step ks run; the next stage goes to the other LDS buffer after the
-        // third k-step, when its global loads have had time to land
+        // last k-step's MFMAs are issued, when its global loads have had the most time to land
         v4i fa[2][2], fb[2][2];
 #define ZE_I8_READ(ks, slot)                                                              \
     do {                                                                                  \
@@ -272,7 +272,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
                     acc[a][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][a], fb[ks & 1][c], acc[a][c], 0, 0, 0);
-            if (ks == 2 && more) ZE_I8_STORE(sm.stage + ((it + 1) & 1) * kI8Stage);
+            if (ks == 3 && more) ZE_I8_STORE(sm.stage + ((it + 1) & 1) * kI8Stage);
             __builtin_amdgcn_sched_barrier(0);
         }
 #undef ZE_I8_READ

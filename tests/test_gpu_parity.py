@@ -216,7 +216,10 @@ def test_basis_single_elements(dev):
 # Ozaki splitting on INT8 MFMA with s slices of 7 bits per row/column scale: small integers
 # are exact (one slice carries them); otherwise |C - AB| <~ 3 * 2^(-7 s) * 2N max|A| max|B|
 # (truncation of both operands plus the dropped slice products), tested with a factor 10.
-@pytest.mark.parametrize("N", [1, 7, 64, 100, 129, 256])
+# The sizes also cover every tile order of the full INT8 product: row-major (column-tile
+# count not a multiple of 4, e.g. N = 129), the 2 x 4 XCD regions walked row by row (N = 256,
+# 1000 ragged, 1024), and in 8 x 8 super-tiles (N = 2048).
+@pytest.mark.parametrize("N", [1, 7, 64, 100, 129, 256, 1000, 1024, 2048])
 def test_zgemm_split_small_integers_exact(dev, N):
     from paper_2206_05466_amd import PREC_SPLIT
 
