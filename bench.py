@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--split-slices", default="4,5,6",
+    ap.add_argument("--split-slices", default="3,4,5",
                     help="comma-separated slice counts of the split-precision runs ('' or 0: skip)")
     ap.add_argument("--n2048-steps", type=int, default=20,
                     help="timed steps of the N=2048 leg, FP64 and split (0: skip it)")

@@ -41,9 +41,10 @@ typedef enum {
 typedef enum {
     ZE_PREC_FP64 = 0,   /* FP64 MFMA products */
     ZE_PREC_SPLIT = 1   /* FP64 products emulated on INT8 MFMA: Ozaki splitting into s slices
-                           of 7 bits per row / column scale (ze_set_split_slices), exact int32
-                           slice products, FP64 accumulation; error ~2^(-7 s) relative to
-                           max|row| max|column| per term of the inner sum */
+                           (balanced digits: 7 bits, then 8 bits each) per row / column scale
+                           (ze_set_split_slices), exact int32 slice products, FP64
+                           accumulation; error ~2^(-8 s) relative to max|row| max|column| per
+                           term of the inner sum */
 } ze_prec;
 
 /* Message for a status code (static string). */
@@ -154,12 +155,13 @@ ze_status ze_basis_assemble(ze_ctx* ctx, const void* omega, void* W);
 ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec);
 
 /*
- * ze_set_split_slices -- number s of 7-bit slices per operand of the ZE_PREC_SPLIT products;
- * the products then cost s (s + 1) / 2 INT8 products each.  Allowed: 2 <= s <= s_max(N) with
- * s_max(N) = min(8, floor((2^31 - 1) / (2 N 127^2))), the largest count whose int32 sums stay
- * exact (8 up to N = 8192, 4 at N = 16384); default min(6, s_max(N)).  The first
- * split-precision call of a context allocates its slice buffers (about 24 N^2 bytes) and
- * int32 work slabs (up to 64 N^2 bytes).
+ * ze_set_split_slices -- number s of slices per operand of the ZE_PREC_SPLIT products (balanced
+ * digits: a 7-bit top slice, then 8-bit ones); the products then cost s (s + 1) / 2 INT8
+ * products each.  Allowed: 2 <= s <= s_max(N) with
+ * s_max(N) = min(8, floor((2^31 - 1) / (2 N 128^2))), the largest count whose int32 sums stay
+ * exact (8 up to N = 4096, 7 at N = 8192, 3 at N = 16384); default min(5, s_max(N)).  The
+ * first split-precision call of a context allocates its slice buffers (about 24 N^2 bytes)
+ * and int32 work slabs (up to 64 N^2 bytes).
  * Errors: ZE_EINVAL (also for s > s_max(N)).
  */
 ze_status ze_set_split_slices(ze_ctx* ctx, int slices);
@@ -232,7 +234,7 @@ ze_status ze_ensemble_tuning(ze_ens* ens, int prec, int* choice, double* ms);
 
 /*
  * ze_ensemble_set_split_slices -- slices s of the ensemble's ZE_PREC_SPLIT products
- * (2 <= s <= s_max of the largest N_j, default 6; see ze_set_split_slices).  Takes effect at
+ * (2 <= s <= s_max of the largest N_j, default 5; see ze_set_split_slices).  Takes effect at
  * the next ze_ensemble_run.
  */
 ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);

@@ -132,7 +132,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     ze_ctx* c = new ze_ctx();
     c->N = N;
     c->solve_bd = solve_bd_ ? solve_bd_ : zk::solve_bd(N);
-    c->split_slices = split_max_slices(N) < 6 ? split_max_slices(N) : 6;
+    c->split_slices = split_max_slices(N) < 5 ? split_max_slices(N) : 5;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

@@ -322,7 +322,7 @@ struct ze_ens {
     int2* work_low[2] = {nullptr, nullptr};                            // [order]
     int n_low = 0;
     // split-precision phases (work lists built at creation, buffers on first use)
-    int slices = 6;
+    int slices = 5;  // min(5, split_max_slices(maxN)), set at creation
     bool split_ready = false;
     int2* w_rows0 = nullptr;   // rows of P + column chunks of W~
     int2* w_rows1 = nullptr;   // rows of A
@@ -563,6 +563,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     e->user = reinterpret_cast<hipStream_t>(stream);
     e->N.assign(N, N + nsim);
     e->maxN = *std::max_element(e->N.begin(), e->N.end());
+    e->slices = split_max_slices(e->maxN) < 5 ? split_max_slices(e->maxN) : 5;
     ze_status st = ZE_OK;
     auto fail = [&](ze_status s) {
         ze_ensemble_destroy(e);

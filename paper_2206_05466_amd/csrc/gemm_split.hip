@@ -1,5 +1,5 @@
 // Split-precision complex products: FP64 matrix products emulated on INT8 MFMA
-// (v_mfma_i32_16x16x64_i8) by the error-free splitting of Ozaki, Ogita, Oishi & Rump,
+// (v_mfma_i32_32x32x32_i8) by the error-free splitting of Ozaki, Ogita, Oishi & Rump,
 // "Error-free transformations of matrix multiplication by using fast routines of matrix
 // multiplication and its applications", Numer. Algorithms 59 (2012), in its integer form
 // (Ootomo, Ozaki & Yokota, "DGEMM on integer matrix multiplication unit", 2024).
@@ -8,15 +8,16 @@
 // FP64 kernels, a complex product C = A B is the real product C~ = A~ B~ of the interleaved
 // A~ (N x 2N) and the 2 x 2-block form B~ (2N x 2N) of B.
 //
-// Splitting.  Row r of A~ is scaled by 2^-ea_r (ea_r = exponent of its largest magnitude, so
-// |entries| < 1) and cut into s signed 7-bit slices by exact truncation:
-//     y = x 2^-ea;  for i = 1..s:  y = 128 y;  a_i = trunc(y) in [-127, 127];  y = y - a_i.
-// Column cc of B~ likewise with 2^-eb_c (one exponent per complex column c; both real columns
-// 2c, 2c+1 hold the same magnitudes).  Then
-//     C~[r][cc] ~= 2^(ea_r + eb_c) sum_{i + j <= s + 1} 2^(-7 (i + j)) (a_i b_j)[r][cc],
-// the products of one t = i + j summed exactly in int32 ((t-1) 2N 127^2 < 2^31: the slice
-// count is capped by split_max_slices(N)), then weighted and added in FP64 in a fixed order.  The neglected terms are below ~2^(-7 s) relative to
-// max|row of A~| max|column of B~| per term of the K sum, so s trades accuracy for speed.
+// Splitting.  Row r of A~ is scaled by 2^-ea_r (ea_r chosen so the largest magnitude becomes
+// at most 0.99) and written as s balanced digits (split_digits in split_tile.h): the row value
+// rounded to a multiple of 2^(1 - 8s), then cut into a top digit in [-127, 127] (7 bits) and
+// s - 1 digits in [-128, 127] (8 bits each), y = sum_i a_i 2^(1 - 8i) + R, |R| <= 2^(-8s).
+// Column cc of B~ likewise with 2^-eb_c (one exponent per complex column c).  Then
+//     C~[r][cc] ~= 2^(ea_r + eb_c) sum_{i + j <= s + 1} 2^(2 - 8 (i + j)) (a_i b_j)[r][cc],
+// the products of one t = i + j summed exactly in int32 ((t-1) 2N 128^2 < 2^31: the slice
+// count is capped by split_max_slices(N)), then weighted and added in FP64 in a fixed order.
+// The neglected terms (the roundings R and the pairs with t > s + 1) are about 2^(-8s)
+// relative to max|row of A~| max|column of B~| per term of the K sum, and zero-mean.
 //
 // Column exponents of a skew-Hermitian B equal its row exponents (|B[k][c]| = |B[c][k]| entry
 // by entry, exactly), so the product Q = A P of the fixed-point map reuses the row exponents
@@ -24,9 +25,6 @@
 //
 // Slices: A~ slices row-major [r][kk] (N x 2N bytes each); B~ slices transposed,
 // B~^T[cc][kk] (2N x 2N bytes each), which is the MFMA's B-operand order (K contiguous).
-// INT8 MFMA operand layout (16x16x64): lane l supplies 16 bytes of A~ row l%16 and of B~^T row
-// l%16, at the same 16 k positions (k = 16 (l/16) + 0..15 here); accumulator register r of
-// lane l holds D[4 (l/16) + r][l%16].
 
 #include "split_tile.h"
 #include "update_tile.h"

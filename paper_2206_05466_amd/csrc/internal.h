@@ -59,7 +59,7 @@ struct ze_ctx {
     // Split-precision products (allocated on first use): slice count s, INT8 slices of the
     // A~ and B~^T operands (kSplitMax slices each, rows of ze_split_ldk(N) bytes), their scale
     // exponents, column-maximum partials, and the int32 product slabs.
-    int split_slices = 6;
+    int split_slices = 5;
     signed char* split_a = nullptr;
     signed char* split_b = nullptr;
     int* split_ea = nullptr;
@@ -84,11 +84,12 @@ constexpr int kMaxN = 16384;
 // Largest number of slices of the split-precision products.
 constexpr int kSplitMax = 8;
 
-// Largest slice count whose int32 sums stay exact for size N: the pairs of one order t = i + j
-// (at most s of them) add up to s * 2N * 127^2 in magnitude, which must stay below 2^31
-// (8 up to N = 8192, 4 at N = 16384).
+// Largest slice count whose int32 sums stay exact for size N: the stored digits lie in
+// [-128, 127], so the pairs of one order t = i + j (at most s of them) add up to at most
+// s * 2N * 128^2 in magnitude, which must stay below 2^31 (8 up to N = 4096, 7 at 8192,
+// 3 at 16384).
 inline int split_max_slices(int N) {
-    const long long per = 2LL * N * 127 * 127;
+    const long long per = 2LL * N * 128 * 128;
     const long long m = ((1LL << 31) - 1) / per;
     return (int)(m < kSplitMax ? m : kSplitMax);
 }

@@ -7,28 +7,6 @@
 namespace zk {
 
 template <int T>
-__device__ __forceinline__ void block_scan_affine(double& G, double2& Y, bool reverse, double* sG,
-                                         double2* sY) {
-    // Inclusive scan over threads (in reverse thread order if `reverse`) of the affine maps
-    // f_t(x) = G_t x + Y_t composed in scan order: earlier maps are applied first.
-    const int t = threadIdx.x;
-    for (int off = 1; off < T; off <<= 1) {
-        sG[t] = G;
-        sY[t] = Y;
-        __syncthreads();
-        const int src = reverse ? t + off : t - off;
-        if (src >= 0 && src < T) {
-            const double pg = sG[src];
-            const double2 py = sY[src];
-            Y.x += G * py.x;
-            Y.y += G * py.y;
-            G *= pg;
-        }
-        __syncthreads();
-    }
-}
-
-template <int T>
 __device__ __forceinline__ double2 block_sum(double2 v, double2* s) {
     const int t = threadIdx.x;
     s[t] = v;

@@ -11,11 +11,33 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kSThreads = 256;
 
-__device__ __forceinline__ int exponent_of(double m) {  // smallest e with m < 2^e (0 for m == 0)
+// Scale exponent for a row / column whose largest magnitude is m: the e with
+// 0.495 < m 2^-e <= 0.99 (0 for m == 0), which keeps the top digit of split_digits within
+// [-127, 127].
+__device__ __forceinline__ int exponent_of(double m) {
     if (!(m > 0.0)) return 0;
     int e;
-    frexp(m, &e);
-    return e;
+    const double f = frexp(m, &e);  // m = f 2^e, 0.5 <= f < 1
+    return f > 0.99 ? e + 1 : e;
+}
+
+// The s balanced base-256 digits of y = x 2^-e (|y| <= 0.99): X = y 2^(7 + 8 (s - 1)) rounded
+// to the nearest integer (|X| < 2^63 for s <= 8), then from the lowest digit up
+// d_k = ((X + 128) mod 256) - 128 in [-128, 127] and X <- (X - d_k) / 256; the top digit
+// d_1 = X is within [-127, 127].  So y = sum_k d_k 2^(1 - 8k) + R with |R| <= 2^(-8s): 7 bits
+// in the first digit and 8 in each further one, zero-mean rounding, every step exact.
+__device__ __forceinline__ void split_digits(double x, int e, int s, int (&d)[kSplitMax]) {
+    long long X = llrint(ldexp(x, 7 + 8 * (s - 1) - e));
+#pragma unroll
+    for (int k = kSplitMax - 1; k >= 1; --k) {
+        d[k] = 0;
+        if (k < s) {
+            const int dk = (int)((X + 128) & 255) - 128;
+            d[k] = dk;
+            X = (X - dk) >> 8;
+        }
+    }
+    d[0] = (int)X;
 }
 
 // Row r of A~ (complex row r of A): scale exponent ea[r] and the s slices (rows of ldk bytes,
@@ -40,20 +62,15 @@ __device__ __forceinline__ void split_row_block(const double2* __restrict__ A, i
     const size_t ss = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
     signed char* base = slices + (size_t)r * ldk;
     for (int c = threadIdx.x; c < ldk / 2; c += kSThreads) {
-        double yr = 0.0, yi = 0.0;
-        if (c < N) {
-            const double2 v = row[c];
-            yr = ldexp(v.x, -e);
-            yi = ldexp(v.y, -e);
-        }
-        for (int i = 0; i < s; ++i) {
-            yr *= 128.0;
-            yi *= 128.0;
-            const double tr = trunc(yr), ti = trunc(yi);
-            yr -= tr;
-            yi -= ti;
-            const unsigned short pk = (unsigned short)((unsigned char)(signed char)tr) |
-                                      ((unsigned short)((unsigned char)(signed char)ti) << 8);
+        const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);  // zero padding beyond N
+        int dr[kSplitMax], di[kSplitMax];
+        split_digits(v.x, e, s, dr);
+        split_digits(v.y, e, s, di);
+#pragma unroll
+        for (int i = 0; i < kSplitMax; ++i) {
+            if (i >= s) break;
+            const unsigned short pk = (unsigned short)((unsigned char)(signed char)dr[i]) |
+                                      ((unsigned short)((unsigned char)(signed char)di[i]) << 8);
             *reinterpret_cast<unsigned short*>(base + i * ss + 2 * c) = pk;
         }
     }
@@ -78,8 +95,9 @@ __device__ __forceinline__ void col_exponent_block(const double2* __restrict__ B
 }
 
 // B~^T slices, tile (bx, by) of 32 rows (k) x 32 complex columns (c) of B through LDS.  Output
-// row cc = 2c + u of B~^T holds, at kk = 2k + t:  u = 0: (Re b, -Im b), u = 1: (Im b, Re b).
-// Rows are ldk bytes; tiles with k >= N write the zero padding.
+// row cc = 2c + u of B~^T holds, at kk = 2k + t:  u = 0: (Re b, -Im b), u = 1: (Im b, Re b);
+// -Im b gets its own digits (the balanced digits of -x are minus those of x except where a
+// digit is -128).  Rows are ldk bytes; tiles with k >= N write the zero padding.
 constexpr int kCT = 32;
 __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, int N, int bx, int by, int s,
                                        int ldk, const int* __restrict__ eb,
@@ -102,18 +120,18 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
         if (c >= N) break;
         const double2 v = tile[tx][a];  // B[k][c] (0 beyond N)
         const int e = eb[c];
-        double br = ldexp(v.x, -e), bi = ldexp(v.y, -e);
+        int dr[kSplitMax], di[kSplitMax], dn[kSplitMax];
+        split_digits(v.x, e, s, dr);
+        split_digits(v.y, e, s, di);
+        split_digits(-v.y, e, s, dn);
         signed char* o0 = slices + (size_t)(2 * c) * ldk + 2 * k;
         signed char* o1 = slices + (size_t)(2 * c + 1) * ldk + 2 * k;
-        for (int i = 0; i < s; ++i) {
-            br *= 128.0;
-            bi *= 128.0;
-            const double tr = trunc(br), ti = trunc(bi);
-            br -= tr;
-            bi -= ti;
-            const unsigned char ur = (unsigned char)(signed char)tr;
-            const unsigned char ui = (unsigned char)(signed char)ti;
-            const unsigned char nui = (unsigned char)(signed char)(-ti);
+#pragma unroll
+        for (int i = 0; i < kSplitMax; ++i) {
+            if (i >= s) break;
+            const unsigned char ur = (unsigned char)(signed char)dr[i];
+            const unsigned char ui = (unsigned char)(signed char)di[i];
+            const unsigned char nui = (unsigned char)(signed char)dn[i];
             *reinterpret_cast<unsigned short*>(o0 + i * ss) = (unsigned short)ur | ((unsigned short)nui << 8);
             *reinterpret_cast<unsigned short*>(o1 + i * ss) = (unsigned short)ui | ((unsigned short)ur << 8);
         }
@@ -126,7 +144,7 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
 // of the 16x16x64 one; measured 4.4 vs 2.6 POPS).  K stage of 128 bytes (four MFMA k-steps),
 // double-buffered in LDS, global loads one stage ahead.  Slice pairs run in order of
 // decreasing t = i + j; the pairs of one t share one exact int32 accumulator
-// ((t-1) 2N 127^2 < 2^31), which is stored to the slab G[t-2] (int32, N x 2N) when t changes.
+// ((t-1) 2N 128^2 < 2^31), which is stored to the slab G[t-2] (int32, N x 2N) when t changes.
 // The FP64 weighting happens afterwards (combine or the fixed-point update), so no FP64
 // accumulator occupies registers here.
 //
@@ -301,7 +319,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
 #undef ZE_I8_STORE
 }
 
-// Element e (row-major complex index) of C = 2^(ea_r + eb_c) sum_{t=2}^{s+1} 2^(-7 t) G[t-2].
+// Element e (row-major complex index) of C = 2^(ea_r + eb_c) sum_{t=2}^{s+1} 2^(2 - 8t) G[t-2].
 __device__ __forceinline__ double2 split_combine_elem(const int* __restrict__ G, const int* __restrict__ ea,
                                              const int* __restrict__ eb, int N, int s, size_t e) {
     const size_t slab = 2 * (size_t)N * N;
@@ -309,7 +327,7 @@ __device__ __forceinline__ double2 split_combine_elem(const int* __restrict__ G,
     double vr = 0.0, vi = 0.0;
     for (int t = s + 1; t >= 2; --t) {
         const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * slab + 2 * e);
-        const double w = ldexp(1.0, -7 * t);
+        const double w = ldexp(1.0, 2 - 8 * t);
         vr += w * (double)g.x;
         vi += w * (double)g.y;
     }

@@ -55,7 +55,7 @@ __device__ __forceinline__ void lower_update_tile(int I, int J, const double2* _
             } else {  // Q = A P from the int32 slabs
                 for (int t = s + 1; t >= 2; --t) {
                     const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
-                    const double w = ldexp(1.0, -7 * t);
+                    const double w = ldexp(1.0, 2 - 8 * t);
                     qv.x += w * (double)g.x;
                     qv.y += w * (double)g.y;
                 }

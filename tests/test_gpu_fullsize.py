@@ -162,11 +162,11 @@ def test_ensemble64_sampled_members(dev, prec_name):
 
 def test_max_size_n16384_one_step_and_slice_limit(dev):
     """The largest N the library accepts: one FP64 step and one split-precision step (the
-    default slice count there is the int32-exactness bound, 4) from a low-degree W_0 the
+    default slice count there is the int32-exactness bound, 3) from a low-degree W_0 the
     oracle assembles.  The oracle cannot step at this size on the host; the checks are the
     properties every step has: convergence, exact skew-Hermitian output, conservation of
     C_2 = -||W||_F^2 (pinned at the start by the oracle's closed form), and the split result
-    within the 4-slice error of the FP64 one."""
+    within the 3-slice error of the FP64 one."""
     from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler, ZeulerError
 
     N, h, L = 16384, 0.005, 6
@@ -174,7 +174,7 @@ def test_max_size_n16384_one_step_and_slice_limit(dev):
     c2_ref = -np.linalg.norm(W0) ** 2  # C_2 = tr W^2 = -||W||_F^2 for skew-Hermitian W
     z = Zeuler(N)
     with pytest.raises(ZeulerError):
-        z.set_split_slices(5)  # 5 * 2N * 127^2 >= 2^31: int32 sums could overflow
+        z.set_split_slices(4)  # 4 * 2N * 128^2 >= 2^31: int32 sums could overflow
     Wd = to_dev(W0)
     del W0
     c0 = z.casimirs(Wd, 2)
