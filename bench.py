@@ -101,8 +101,11 @@ def cpu_baseline(N, om_seed, law, h, K, lmax=32):
     }
 
 
-def ensemble_leg(nsteps, prec, slices=5):
-    """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step."""
+def ensemble_leg(nsteps, prec, slices=4, ref=None):
+    """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step.
+    Returns the record and the final states; with `ref` (the FP64 leg's final states, same
+    initial states and step count) the record carries the largest relative Frobenius distance
+    of a member to its FP64 counterpart."""
     import torch
 
     from paper_2206_05466_amd import PREC_SPLIT, Ensemble, Zeuler
@@ -128,6 +131,9 @@ def ensemble_leg(nsteps, prec, slices=5):
     dt = time.perf_counter() - t0
     its, res = ens.stats()
     choice, tune_ms = ens.tuning(prec)
+    dist = None
+    if ref is not None:
+        dist = max(float((torch.linalg.norm(W - R) / torch.linalg.norm(R)).item()) for W, R in zip(Ws, ref))
     # sequential reference: the single-simulation entry point, one simulation after the other
     seq_steps = max(1, min(5, nsteps))
     torch.cuda.synchronize()
@@ -144,7 +150,7 @@ def ensemble_leg(nsteps, prec, slices=5):
     cands = (["work order: largest first", "work order: interleaved"] if split else
              ["128x64 tiles, largest first", "128x64 tiles, interleaved",
               "64x64 tiles, largest first", "64x64 tiles, interleaved"])
-    return {
+    rec = {
         "workload": f"ensemble64: {len(sizes)} simulations, N drawn from {cfg['sizes']} (seed "
                     f"{cfg['size_seed']}), simulation j seeded {cfg['seed0']}+j, sigma_l law "
                     f"{cfg['law']}, h={h}, tol={tol}, maxit={K}, "
@@ -160,6 +166,9 @@ def ensemble_leg(nsteps, prec, slices=5):
         "sequential_single_context_steps_per_s": len(sizes) * seq_steps / dts,
         "speedup_vs_sequential": (len(sizes) * nsteps / dt) / (len(sizes) * seq_steps / dts),
     }
+    if dist is not None:
+        rec["max_member_rel_frobenius_vs_fp64_ensemble"] = dist
+    return rec, Ws
 
 
 def small_leg(steps):
@@ -372,8 +381,10 @@ def main():
 
     ens = None
     if args.ensemble_steps > 0:
-        ens = {"fp64": ensemble_leg(args.ensemble_steps, PREC_FP64),
-               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=5)}
+        rec64, ref = ensemble_leg(args.ensemble_steps, PREC_FP64)
+        ens = {"fp64": rec64,
+               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=4, ref=ref)[0]}
+        del ref
         ens["split_speedup_vs_fp64"] = (ens["split"]["aggregate_steps_per_s"] /
                                         ens["fp64"]["aggregate_steps_per_s"])
         log(f"ensemble: fp64 {ens['fp64']['aggregate_steps_per_s']:.0f} steps/s, split "
