@@ -141,9 +141,35 @@ ze_status ze_casimirs(ze_ctx* ctx, const void* W, int kmax, double* out);
  * relative 1e-8 of the largest there, the one with the lowest index is positive.
  *   omega  device, N*N complex128 coefficients, omega_lm at index l*l + l + m.
  *   W      device, N x N complex128, fully written.
- * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Asynchronous.
+ * Allocates a scratch buffer for the eigenvectors (up to 4 GiB, freed before returning).
+ * Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.  Synchronous (waits for the context's stream).
  */
 ze_status ze_basis_assemble(ze_ctx* ctx, const void* omega, void* W);
+
+/*
+ * ze_basis_extract -- the coefficients of W in the same basis (the post-processing of
+ * Sec. 3.2): omega_lm = -i <T_lm, W>_F for every l = 0..N-1, |m| <= l, i.e.
+ *   omega_lm     = -i sum_i v^{lm}_i W[i+m][i]              (m >= 0, lower diagonal m),
+ *   omega_{l,-m} = -i (-1)^m sum_i v^{lm}_i W[i][i+m]       (m > 0, upper diagonal m),
+ * with v^{lm} the eigenvectors of ze_basis_assemble.  Inverse of ze_basis_assemble; for W in
+ * su(N) the result satisfies omega_{l,-m} = (-1)^m conj(omega_lm) and omega_00 = 0 to rounding.
+ *   W      device, N x N complex128.
+ *   omega  device, N*N complex128, fully written (index l*l + l + m).
+ * Allocates scratch like ze_basis_assemble.  Errors: ZE_EINVAL, ZE_ENOMEM, ZE_EHIP.
+ * Synchronous.
+ */
+ze_status ze_basis_extract(ze_ctx* ctx, const void* W, void* omega);
+
+/*
+ * ze_energy_spectrum -- kinetic energy per degree of the coefficients omega (the spectrum of
+ * Sec. 4): E_l = sum_{m=-l..l} |omega_lm|^2 / (l (l+1)) for l = 1..N-1 (the stream function's
+ * coefficients are -omega_lm / (l (l+1)), eq. (lap_prop)); E_0 = 0.  Sum_l l (l+1) E_l =
+ * ||W||_F^2 for W = ze_basis_assemble(omega) with omega_00 = 0.
+ *   omega  device, N*N complex128 (index l*l + l + m).
+ *   E      device, N doubles, fully written.
+ * Errors: ZE_EINVAL, ZE_EHIP.  Asynchronous.
+ */
+ze_status ze_energy_spectrum(ze_ctx* ctx, const void* omega, void* E);
 
 /*
  * ze_zgemm -- C = A B for N x N complex128 matrices with the library's product kernels

@@ -18,7 +18,8 @@ follows:
   fixed-point iteration eq. (isomp_iter) with the infinity-norm stopping rule (Sec. 2).
 * ``casimirs``   -- C_k(W) = Tr(W^k), eq. (W_pow).
 * ``basis``      -- the quantised basis T_lm as eigenvectors of Delta^m (Sec. 3.2) and the
-  assembly W = sum_lm i omega_lm T_lm, eq. (W0); plus the inverse projection.
+  assembly W = sum_lm i omega_lm T_lm, eq. (W0); plus the inverse projection and the
+  kinetic energy spectrum of the coefficients (Sec. 4).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms, brute force
 on tiny N and invariants that the paper and the mathematics fix (see the docstrings).
@@ -28,10 +29,10 @@ from .laplacian import delta_tridiag, spin_matrices, brute_laplacian, apply_lapl
 from .stream import stream_solve
 from .isomp import isomp_step, isomp_run
 from .casimirs import casimirs, casimirs_eig
-from .basis import eigvecs, assemble, extract
+from .basis import eigvecs, assemble, extract, energy_spectrum
 
 __all__ = [
     "delta_tridiag", "spin_matrices", "brute_laplacian", "apply_laplacian",
     "stream_solve", "isomp_step", "isomp_run", "casimirs", "casimirs_eig",
-    "eigvecs", "assemble", "extract",
+    "eigvecs", "assemble", "extract", "energy_spectrum",
 ]

@@ -89,3 +89,17 @@ def extract(W: np.ndarray) -> np.ndarray:
         if m > 0:
             omega[l * l + l - m] = (-1) ** m * np.conj(c)
     return omega
+
+
+def energy_spectrum(omega: np.ndarray, N: int) -> np.ndarray:
+    """Kinetic energy per degree l (the spectrum of Sec. 4): E_l = sum_m |omega_lm|^2 / (l(l+1)).
+
+    The stream matrix P = Delta_N^{-1} W has coefficients -omega_lm / (l(l+1)) (eq. (lap_prop)),
+    so sum_l E_l = tr(P W) and sum_l l(l+1) E_l = ||W||_F^2 (the T_lm are orthonormal).
+    E_0 = 0 (l = 0 carries no kinetic energy).
+    """
+    omega = np.asarray(omega, dtype=np.complex128)
+    E = np.zeros(N)
+    for l in range(1, N):
+        E[l] = np.sum(np.abs(omega[l * l:(l + 1) * (l + 1)]) ** 2) / (l * (l + 1))
+    return E

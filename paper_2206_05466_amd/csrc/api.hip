@@ -356,6 +356,29 @@ ze_status ze_basis_assemble(ze_ctx* c, const void* omega, void* W) {
     return ZE_OK;
 }
 
+ze_status ze_basis_extract(ze_ctx* c, const void* W, void* omega) {
+    if (!c || !omega || !W || omega == W) return ZE_EINVAL;
+    void* scratch = nullptr;
+    if (hipMalloc(&scratch, ze_basis_scratch_bytes(c->N)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ZE_ENOMEM;
+    }
+    hipError_t e = launch_basis_extract(static_cast<const double2*>(W), static_cast<double2*>(omega),
+                                        scratch, c->N, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return ze_record_hip(e, "launch_basis_extract");
+    if (e2 != hipSuccess) return ze_record_hip(e2, "hipStreamSynchronize(basis)");
+    return ZE_OK;
+}
+
+ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
+    if (!c || !omega || !E || omega == E) return ZE_EINVAL;
+    ZE_HIP(launch_energy_spectrum(static_cast<const double2*>(omega), static_cast<double*>(E), c->N,
+                                  c->stream));
+    return ZE_OK;
+}
+
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
     if (!c || mode < 0 || mode > 1) return ZE_EINVAL;
     c->guess_mode = mode;

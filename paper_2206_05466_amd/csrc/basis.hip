@@ -193,6 +193,54 @@ __global__ __launch_bounds__(256) void basis_project_kernel(int N, int m_begin, 
     }
 }
 
+// Inverse of the assembly (post-processing, Sec. 3.2): one thread per (m, l = m + j) forms
+// the projections onto T_lm and T_{l,-m},
+//     omega_lm = -i sum_i v_i W[i+m][i],   omega_{l,-m} = -i (-1)^m sum_i v_i W[i][i+m],
+// the lanes of a wave reading consecutive j of V_m (coalesced) and one diagonal entry of W
+// (the same address: a broadcast).
+__global__ __launch_bounds__(64) void basis_extract_kernel(int N, int m_begin, int nb,
+                                                           const double* __restrict__ V,
+                                                           const double2* __restrict__ W,
+                                                           double2* __restrict__ omega) {
+    const int m = m_begin + blockIdx.y;
+    const int n = N - m;
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= n) return;
+    const double* v = V + (sumsq((size_t)nb) - sumsq((size_t)n)) + j;
+    double lr = 0.0, li = 0.0, ur = 0.0, ui = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double x = v[(size_t)i * n];
+        const double2 lo = W[(size_t)(i + m) * N + i];
+        lr += x * lo.x;
+        li += x * lo.y;
+        if (m > 0) {
+            const double2 up = W[(size_t)i * N + i + m];
+            ur += x * up.x;
+            ui += x * up.y;
+        }
+    }
+    const size_t l = (size_t)(m + j);
+    omega[l * l + l + m] = make_double2(li, -lr);  // -i (lr + i li)
+    if (m > 0) {
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        omega[l * l + l - m] = make_double2(sg * ui, -sg * ur);
+    }
+}
+
+// Kinetic energy per degree, E_l = sum_{m=-l..l} |omega_lm|^2 / (l (l + 1)) for l >= 1 (the
+// stream function has coefficients -omega_lm / (l (l + 1)), eq. (lap_prop)); E_0 = 0.
+__global__ __launch_bounds__(256) void energy_spectrum_kernel(int N, const double2* __restrict__ omega,
+                                                             double* __restrict__ E) {
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= N) return;
+    double s = 0.0;
+    for (int k = 0; k <= 2 * l; ++k) {
+        const double2 o = omega[(size_t)l * l + k];
+        s += o.x * o.x + o.y * o.y;
+    }
+    E[l] = l > 0 ? s / ((double)l * (double)(l + 1)) : 0.0;
+}
+
 constexpr size_t kScratchBudget = (size_t)4 << 30;  // bytes for V and S of one batch
 
 }  // namespace
@@ -233,4 +281,40 @@ hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch
         m = me;
     }
     return e;
+}
+
+hipError_t launch_basis_extract(const double2* W, double2* omega, void* scratch, int N,
+                                hipStream_t s) {
+    const size_t cap = ze_basis_scratch_bytes(N) / (2 * sizeof(double));  // doubles per array
+    double* V = static_cast<double*>(scratch);
+    double* S = V + cap;
+    // Every coefficient (l, +-m) belongs to exactly one diagonal m, so all of omega is written.
+    hipError_t e = hipSuccess;
+    int m = 0;
+    while (m < N && e == hipSuccess) {
+        const int nb = N - m;
+        int me = m;
+        size_t used = 0;
+        while (me < N) {
+            const size_t need = (size_t)(N - me) * (size_t)(N - me);
+            if (me > m && used + need > cap) break;
+            used += need;
+            ++me;
+        }
+        const int count = me - m;
+        hipLaunchKernelGGL(basis_vectors_kernel, dim3((nb + 63) / 64, count), dim3(64), 0, s, N, m,
+                           nb, V, S);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(basis_extract_kernel, dim3((nb + 63) / 64, count), dim3(64), 0, s, N, m,
+                           nb, V, W, omega);
+        e = hipGetLastError();
+        m = me;
+    }
+    return e;
+}
+
+hipError_t launch_energy_spectrum(const double2* omega, double* E, int N, hipStream_t s) {
+    hipLaunchKernelGGL(energy_spectrum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, omega, E);
+    return hipGetLastError();
 }

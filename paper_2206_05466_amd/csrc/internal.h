@@ -146,6 +146,11 @@ hipError_t launch_trace(const double2* X, double2* partial, double2* out, int N,
 size_t ze_basis_scratch_bytes(int N);
 hipError_t launch_basis_assemble(const double2* omega, double2* W, void* scratch, int N,
                                  hipStream_t s);
+// omega_lm = -i <T_lm, W> for every (l, m) (the inverse of launch_basis_assemble on su(N)).
+hipError_t launch_basis_extract(const double2* W, double2* omega, void* scratch, int N,
+                                hipStream_t s);
+// E_l = sum_m |omega_lm|^2 / (l (l + 1)), l = 0..N-1 (E_0 = 0).
+hipError_t launch_energy_spectrum(const double2* omega, double* E, int N, hipStream_t s);
 
 // ---- split-precision products (INT8 MFMA, Ozaki splitting) ----
 int ze_split_ldk(int N);  // bytes per slice row: 2N rounded up to the K stage

@@ -34,6 +34,8 @@ SIGNATURES = {
     "ze_isomp_run": (_c_int, [_vp, _vp, _c_double, _c_double, _c_int, _c_int, _c_int, _P_int, _P_double]),
     "ze_casimirs": (_c_int, [_vp, _vp, _c_int, _P_double]),
     "ze_basis_assemble": (_c_int, [_vp, _vp, _vp]),
+    "ze_basis_extract": (_c_int, [_vp, _vp, _vp]),
+    "ze_energy_spectrum": (_c_int, [_vp, _vp, _vp]),
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
@@ -194,6 +196,30 @@ class Zeuler:
         _check(self.lib.ze_basis_assemble(self._ctx, ctypes.c_void_p(om.data_ptr()), self._mat(W, "W")),
                "ze_basis_assemble")
         return W
+
+    def basis_extract(self, W, out=None):
+        """omega_lm = -i <T_lm, W>_F for all (l, m), flat at index l*l+l+m (device tensor)."""
+        import torch
+
+        om = torch.empty(self.N * self.N, dtype=torch.complex128, device=self.device) if out is None else out
+        if om.numel() != self.N * self.N or om.dtype != torch.complex128 or not om.is_contiguous() \
+                or om.device != self.device:
+            raise ValueError("out must be a contiguous complex128 tensor of N*N on the context's device")
+        _check(self.lib.ze_basis_extract(self._ctx, self._mat(W, "W"), ctypes.c_void_p(om.data_ptr())),
+               "ze_basis_extract")
+        return om
+
+    def energy_spectrum(self, omega):
+        """E_l = sum_m |omega_lm|^2 / (l(l+1)), l = 0..N-1 (device tensor of N doubles)."""
+        import torch
+
+        om = torch.as_tensor(omega, dtype=torch.complex128).to(self.device).contiguous()
+        if om.numel() != self.N * self.N:
+            raise ValueError("omega must hold N*N coefficients")
+        E = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        _check(self.lib.ze_energy_spectrum(self._ctx, ctypes.c_void_p(om.data_ptr()),
+                                           ctypes.c_void_p(E.data_ptr())), "ze_energy_spectrum")
+        return E
 
     def set_initial_guess(self, mode: int):
         """0: each step starts from W_n; 1: steps after the first in isomp_run start from the

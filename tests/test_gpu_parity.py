@@ -212,6 +212,46 @@ def test_basis_single_elements(dev):
                 assert np.abs(W - O.assemble(N, om)).max() < 1e-13
 
 
+# ------------------------------------------------------------------ extraction and spectrum
+# omega_lm = -i <T_lm, W> (the inverse of the assembly, Sec. 3.2) and E_l (Sec. 4).
+@pytest.mark.parametrize("N", [1, 2, 7, 64, 129, 300])
+def test_basis_extract_and_spectrum_match_oracle(dev, N):
+    rng = np.random.default_rng(N + 11)
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    W = X - X.conj().T  # skew-Hermitian (trace not removed: omega_00 != 0)
+    with ctx(N) as z:
+        om = to_host(z.basis_extract(to_dev(W)))
+        E = to_host(z.energy_spectrum(om))
+    ref = O.extract(W)
+    assert np.abs(om - ref).max() <= 1e-12 * np.abs(ref).max(), relmax(om, ref)
+    E_ref = O.energy_spectrum(ref, N)
+    assert np.abs(E - E_ref).max() <= 1e-12 * max(E_ref.max(), 1e-300)
+
+
+def test_basis_extract_general_matrix(dev):
+    """For a W that is not skew-Hermitian the coefficients of m < 0 come from the upper
+    diagonals: each one is -i <T_lm, W>_F against the oracle's basis elements one by one."""
+    N = 7
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    with ctx(N) as z:
+        om = to_host(z.basis_extract(to_dev(W)))
+    for l in range(N):
+        for m in range(-l, l + 1):
+            e = np.zeros(N * N, complex)
+            e[l * l + l + m] = 1.0
+            T = O.assemble(N, e) / 1j
+            assert abs(om[l * l + l + m] - (-1j) * np.vdot(T, W)) < 1e-13
+
+
+def test_basis_roundtrip(dev):
+    N = 256
+    om = omega_coeffs(N, 21, "inv1")
+    with ctx(N) as z:
+        back = to_host(z.basis_extract(z.basis_assemble(om)))
+    assert np.abs(back - om).max() <= 1e-13 * np.abs(om).max()
+
+
 # ------------------------------------------------------------------ split precision
 # Ozaki splitting on INT8 MFMA with s balanced slices (7 bits, then 8 bits each) per
 # row/column scale: small integers are exact (the first slices carry them); otherwise

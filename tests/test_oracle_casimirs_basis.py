@@ -99,3 +99,23 @@ def test_truncated_assembly_matches_full():
     assert np.abs(O.assemble(N, om, lmax=L) - O.assemble(N, om)).max() < 1e-13
     with pytest.raises(ValueError):
         O.assemble(N, omega_coeffs(N, 2, "inv1"), lmax=L)
+
+
+def test_energy_spectrum_pins():
+    """E_l (Sec. 4) against two independent routes: sum_l E_l = tr(P W) with P from the
+    stream solve (eq. (sub_tria_W)), and sum_l l(l+1) E_l = ||W||_F^2 (orthonormal T_lm);
+    a single-degree field puts all its energy at that degree."""
+    N = 24
+    om = omega_coeffs(N, 5, "inv1")
+    W = O.assemble(N, om)
+    E = O.energy_spectrum(om, N)
+    P = O.stream_solve(W)
+    tPW = np.trace(P @ W)
+    assert E[0] == 0.0 and np.all(E >= 0)
+    assert abs(tPW.imag) < 1e-14 and abs(E.sum() - tPW.real) < 1e-13 * E.sum()
+    l = np.arange(N)
+    assert abs((l * (l + 1) * E).sum() - np.linalg.norm(W) ** 2) < 1e-13 * np.linalg.norm(W) ** 2
+    one = np.zeros(N * N, complex)
+    one[7 * 7 + 7 - 3] = 0.5 - 0.25j
+    E1 = O.energy_spectrum(one, N)
+    assert np.count_nonzero(E1) == 1 and abs(E1[7] - 0.3125 / 56) < 1e-17
