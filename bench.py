@@ -213,6 +213,68 @@ def small_leg(steps):
     }
 
 
+def long_leg(steps):
+    """Workload long512: the paper's long-run initial condition (random degrees 2..20, unit
+    spectral norm, Sec. 4) at N = 512, `steps` steps with the extrapolated start.  Every
+    `sample` steps: the Casimirs C_2..C_5 and the kinetic energy (sum of E_l from the basis
+    extraction); at the end the energy spectrum's share above degree 20 and its log-log
+    slope over 21 <= l <= 200."""
+    import numpy as np
+    import torch
+
+    from paper_2206_05466_amd import Zeuler
+    from workloads import WORKLOADS, omega_coeffs
+
+    cfg = WORKLOADS["long512"]
+    N, h, tol, sample = cfg["N"], cfg["h"], cfg["tol"], cfg["sample"]
+    z = Zeuler(N)
+    W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
+    W /= float(np.linalg.norm(W.cpu().numpy(), 2))  # input recipe: unit spectral norm
+    z.set_initial_guess(1)
+    nf0 = float(torch.linalg.norm(W).item())
+
+    def diag():
+        c = z.casimirs(W, 5)
+        E = z.energy_spectrum(z.basis_extract(W)).cpu().numpy()
+        return c, E
+
+    c0, E0 = diag()
+    rows, t_run, it_max = [], 0.0, 0
+    done = 0
+    while done < steps:
+        k = min(sample, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, res = z.isomp_run(W, h, k, tol, cfg["maxit"])
+        torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        it_max = max(it_max, max(its))
+        done += k
+        c, E = diag()
+        rows.append({"step": done,
+                     "C2_rel": abs(c[1] - c0[1]) / abs(c0[1]),
+                     "C3_over_normF3": abs(c[2] - c0[2]) / nf0 ** 3,
+                     "C4_rel": abs(c[3] - c0[3]) / abs(c0[3]),
+                     "C5_over_normF5": abs(c[4] - c0[4]) / nf0 ** 5,
+                     "energy_rel": abs(E.sum() - E0.sum()) / E0.sum()})
+    l = np.arange(N)
+    sel = (l >= 21) & (l <= 200) & (E > 0)
+    slope = float(np.polyfit(np.log(l[sel]), np.log(E[sel]), 1)[0]) if sel.sum() > 2 else None
+    z.close()
+    return {
+        "workload": f"long512: N={N}, sigma_l law paper (degrees 2..20, seed {cfg['seed']}), "
+                    f"unit spectral norm, h={h}, tol={tol}, {steps} steps, extrapolated start",
+        "s_per_step": t_run / steps,
+        "max_iters_per_step": it_max,
+        "drift": rows,
+        "energy_share_above_l20": {"start": float(E0[21:].sum() / E0.sum()),
+                                   "end": float(E[21:].sum() / E.sum())},
+        "end_spectrum_loglog_slope_l21_200": slope,
+        "note": "Casimirs by ze_casimirs, energy by ze_basis_extract + ze_energy_spectrum, "
+                "sampled between timed chunks (not in s_per_step)",
+    }
+
+
 def casimir_drift(c0, c1, W):
     """Relative drift of C_2, C_4; C_3 relative to ||W||_F^3 (C_3 can be tiny)."""
     import torch
@@ -341,6 +403,8 @@ def main():
                     help="timed steps of the N=2048 leg, FP64 and split (0: skip it)")
     ap.add_argument("--n512-steps", type=int, default=100,
                     help="timed steps of the N=512 leg (0: skip it)")
+    ap.add_argument("--long-steps", type=int, default=10000,
+                    help="steps of the long-run drift leg (N=512, paper initial condition; 0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -378,6 +442,7 @@ def main():
         }
 
     n512 = small_leg(args.n512_steps) if args.n512_steps > 0 else None
+    long512 = long_leg(args.long_steps) if args.long_steps > 0 else None
 
     ens = None
     if args.ensemble_steps > 0:
@@ -465,6 +530,7 @@ def main():
         "split_precision": m["split_precision"],
         "n2048": n2048,
         "n512": n512,
+        "long512": long512,
         "ensemble": ens,
     }
     if not args.no_cpu_baseline:

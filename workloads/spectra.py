@@ -70,4 +70,7 @@ WORKLOADS = {
     "n4096": dict(N=4096, law="inv1.5", h=0.005, steps=10,  tol=1e-12, maxit=50, seeds=(0,)),
     "ensemble64": dict(nsim=64, sizes=(128, 256, 384, 512), law="inv1", h=0.005, steps=50,
                        K=3, size_seed=0, seed0=1000),
+    # the paper's long-run initial condition (degrees 2..20, unit spectral norm, Sec. 4)
+    "long512": dict(N=512, law="paper", h=0.005, steps=10000, tol=1e-12, maxit=50, seed=0,
+                    sample=1000),
 }
