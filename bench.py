@@ -239,7 +239,7 @@ def long_leg(steps):
         return c, E
 
     c0, E0 = diag()
-    rows, t_run, it_max = [], 0.0, 0
+    rows, t_run, it_max, res_max = [], 0.0, 0, 0.0
     done = 0
     while done < steps:
         k = min(sample, steps - done)
@@ -249,6 +249,7 @@ def long_leg(steps):
         torch.cuda.synchronize()
         t_run += time.perf_counter() - t0
         it_max = max(it_max, max(its))
+        res_max = max(res_max, max(res))
         done += k
         c, E = diag()
         rows.append({"step": done,
@@ -260,16 +261,32 @@ def long_leg(steps):
     l = np.arange(N)
     sel = (l >= 21) & (l <= 200) & (E > 0)
     slope = float(np.polyfit(np.log(l[sel]), np.log(E[sel]), 1)[0]) if sel.sum() > 2 else None
+    # the same run from W_n at every step (3 evaluations: the last iterate much closer to the
+    # fixed point), drift at the end only
+    W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
+    W /= float(np.linalg.norm(W.cpu().numpy(), 2))
+    z.set_initial_guess(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its0, res0 = z.isomp_run(W, h, steps, tol, cfg["maxit"])
+    torch.cuda.synchronize()
+    t_wn = time.perf_counter() - t0
+    c, _ = diag()
+    wn = {"s_per_step": t_wn / steps, "mean_iters_per_step": sum(its0) / len(its0),
+          "max_resid": max(res0), "C2_rel": abs(c[1] - c0[1]) / abs(c0[1]),
+          "C4_rel": abs(c[3] - c0[3]) / abs(c0[3])}
     z.close()
     return {
         "workload": f"long512: N={N}, sigma_l law paper (degrees 2..20, seed {cfg['seed']}), "
                     f"unit spectral norm, h={h}, tol={tol}, {steps} steps, extrapolated start",
         "s_per_step": t_run / steps,
         "max_iters_per_step": it_max,
+        "max_resid": res_max,
         "drift": rows,
         "energy_share_above_l20": {"start": float(E0[21:].sum() / E0.sum()),
                                    "end": float(E[21:].sum() / E.sum())},
         "end_spectrum_loglog_slope_l21_200": slope,
+        "start_from_Wn_every_step": wn,
         "note": "Casimirs by ze_casimirs, energy by ze_basis_extract + ze_energy_spectrum, "
                 "sampled between timed chunks (not in s_per_step)",
     }
