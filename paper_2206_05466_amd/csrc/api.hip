@@ -50,6 +50,10 @@ ze_status ze_ensure_split(ze_ctx* c) {
     if (st == ZE_OK) st = dalloc(&c->split_eb, n);
     if (st == ZE_OK) st = dalloc(&c->split_ec, n);
     if (st == ZE_OK) st = dalloc(&c->split_colmax, 64 * n);
+    if (st == ZE_OK) {
+        const hipError_t ce = ze_i8_capacity(&c->cap_i8);
+        if (ce != hipSuccess) st = ze_record_hip(ce, "ze_i8_capacity");
+    }
     if (st == ZE_OK) st = dalloc(&c->split_g, (size_t)kSplitMax * 2 * n * n);
     if (st != ZE_OK) {
         dfree(c->split_a);

@@ -78,41 +78,72 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __r
     split_cols_tile(B, N, blockIdx.x, blockIdx.y, s, ldk, eb, slices, tile);
 }
 
-// mode 0: full product, tile b -> (b / tiles_n, b % tiles_n); mode 1: lower-triangle tiles.
-__global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
-    const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
-    int N, int s, int ldk, int mode, int tiles_n) {
-    __shared__ I8Smem sm;
-    int ti, tj;
-    const int b = blockIdx.x;
-    if (mode == 0) {
+// mode 0: full product (tiles_m x tiles_n tiles), mode 1: lower-triangle tiles (ntiles of
+// them in i8_lower_tile's numbering).  Blocks b < full take one whole tile each; the
+// remaining tiles (a last, partial round of the GPU's block slots) are split along K: block
+// full + S t + p takes part p of tile full + t and adds its sums to the cleared slabs.
+__device__ __forceinline__ void i8_tile_of(int mode, int tile, int tiles_n, int ntiles, bool xcd,
+                                           int b, int& ti, int& tj) {
+    if (mode == 1) {
+        i8_lower_tile(tile, ti, tj);
+        return;
+    }
+    const int tm = ntiles / tiles_n;
+    if (xcd && tm % 2 == 0 && tiles_n % 4 == 0) {
         // XCD-aware order: blocks b with b % 8 == x run on XCD x.  With the tile grid split
         // into 2 x 4 regions, XCD x takes region (x / 4, x % 4), walked in 8 x 8 super-tiles,
         // so the tiles an XCD holds at once share A~ and B~^T panels in its L2.
-        const int tm = gridDim.x / tiles_n;
-        if (tm % 2 == 0 && tiles_n % 4 == 0) {
-            const int x = b & 7, L = b >> 3;
-            const int rm = tm / 2, rn = tiles_n / 4;
-            int r, c;
-            if (rm % 8 == 0 && rn % 8 == 0) {
-                const int sg = L >> 6, w = L & 63, spr = rn / 8;
-                r = (sg / spr) * 8 + (w >> 3);
-                c = (sg % spr) * 8 + (w & 7);
-            } else {
-                r = L / rn;
-                c = L % rn;
-            }
-            ti = (x >> 2) * rm + r;
-            tj = (x & 3) * rn + c;
+        const int x = b & 7, L = b >> 3;
+        const int rm = tm / 2, rn = tiles_n / 4;
+        int r, c;
+        if (rm % 8 == 0 && rn % 8 == 0) {
+            const int sg = L >> 6, w = L & 63, spr = rn / 8;
+            r = (sg / spr) * 8 + (w >> 3);
+            c = (sg % spr) * 8 + (w & 7);
         } else {
-            ti = b / tiles_n;
-            tj = b % tiles_n;
+            r = L / rn;
+            c = L % rn;
         }
+        ti = (x >> 2) * rm + r;
+        tj = (x & 3) * rn + c;
     } else {
-        i8_lower_tile(b, ti, tj);
-        if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
+        ti = tile / tiles_n;
+        tj = tile % tiles_n;
     }
-    zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm);
+}
+
+__global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
+    const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
+    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S) {
+    __shared__ I8Smem sm;
+    int ti, tj;
+    const int b = blockIdx.x;
+    if (b < full) {
+        i8_tile_of(mode, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
+        if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
+        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm);
+    } else {
+        const int e = b - full, p = e % S, nk = ldk / kI8BK;
+        i8_tile_of(mode, full + e / S, tiles_n, ntiles, false, b, ti, tj);
+        if (tj >= tiles_n) return;
+        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
+                      (int)((long long)(p + 1) * nk / S), true);
+    }
+}
+
+// Clears the slabs G[0..s-1] over the tiles full .. ntiles-1 (the K-split ones); grid
+// (ntiles - full, s).
+__global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, int N, int mode,
+                                                          int tiles_n, int ntiles, int full) {
+    int ti, tj;
+    i8_tile_of(mode, full + blockIdx.x, tiles_n, ntiles, false, 0, ti, tj);
+    const int M2 = 2 * N;
+    if (tj >= tiles_n) return;
+    int* g = G + (size_t)blockIdx.y * N * M2;
+    for (int x = threadIdx.x; x < kI8BM * kI8BN; x += kThreads) {
+        const int row = ti * kI8BM + x / kI8BN, cc = tj * kI8BN + x % kI8BN;
+        if (row < N && cc < M2) g[(size_t)row * M2 + cc] = 0;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __restrict__ G,
@@ -145,6 +176,16 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
 
 int ze_split_ldk(int N) { return split_ldk_of(N); }
 
+hipError_t ze_i8_capacity(int* cap) {
+    int dev = 0, cus = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, zgemm_i8_kernel, kThreads, 0);
+    if (e != hipSuccess) return e;
+    *cap = (nb > 0 ? nb : 1) * cus;
+    return hipSuccess;
+}
+
 hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, int* ea,
                                 int* eb, bool eb_known, hipStream_t st) {
     const int N = c->N, s = c->split_slices, ldk = ze_split_ldk(N);
@@ -175,9 +216,30 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     if (e != hipSuccess) return e;
     const int tr = (N + kI8BM - 1) / kI8BM;
     const int tn = (2 * N + kI8BN - 1) / kI8BN;
-    const int nb = lower ? tr * (tr + 1) : tr * tn;
-    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->split_a, c->split_b,
-                       c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn);
+    const int ntiles = lower ? tr * (tr + 1) : tr * tn;
+    const int nk = ze_split_ldk(N) / kI8BK;
+    // whole rounds of the block slots one tile per block; a last partial round of `rem` tiles
+    // split along K into S parts (at least 4 stages each) when that fills the slots better
+    int full = ntiles, S = 1;
+    const int cap = c->cap_i8 > 0 ? c->cap_i8 : ntiles;
+    const int rem = ntiles % cap;
+    if (rem > 0) {
+        int sp = cap / rem;
+        if (sp > nk / 4) sp = nk / 4;
+        if (sp > 1) {
+            full = ntiles - rem;
+            S = sp;
+        }
+    }
+    if (full < ntiles) {
+        hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, s), dim3(kThreads), 0, st, c->split_g,
+                           N, lower ? 1 : 0, tn, ntiles, full);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
+                       c->split_a, c->split_b, c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn,
+                       ntiles, full, S);
     e = hipGetLastError();
     if (e != hipSuccess || lower) return e;
     const size_t n2 = (size_t)N * N;

@@ -67,6 +67,7 @@ struct ze_ctx {
     int* split_ec = nullptr;  // row exponents of A in the lower product Q = A P
     double* split_colmax = nullptr;
     int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
+    int cap_i8 = 0;          // blocks of the INT8 product kernel that fit on the device at once
 
     // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
     // (F = the previous step's converged midpoint, left in ze_ctx::F).
@@ -96,6 +97,8 @@ inline int split_max_slices(int N) {
 
 // Workspaces of the split-precision products (kSplitMax slices), allocated on first use.
 ze_status ze_ensure_split(ze_ctx* c);
+// Blocks of the single-problem INT8 product kernel that fit on the device at once.
+hipError_t ze_i8_capacity(int* cap);
 
 // Slice buffers hold whole 128-row tiles: A~ slices have split_rows_pad(N) rows and B~^T
 // slices split_cols_pad(N) rows; the rows past N (2N) are zeroed when the buffers are

@@ -195,22 +195,26 @@ __device__ __forceinline__ void i8_next_pair(int& i, int& j) {
 }
 
 // Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
-// each) and sb (B~^T, split_cols_pad(N) x ldk each).  Each iteration issues the global loads
-// of the next stage, computes the current stage from LDS, and stores the next stage to the
-// other LDS buffer at the end of the stage; scheduling barriers keep that order (left alone,
-// the compiler moves the LDS store up to the loads, which waits for them before the MFMAs).
+// each) and sb (B~^T, split_cols_pad(N) x ldk each), over the K stages [kb, ke) of every slice
+// pair (kb = 0, ke < 0: all of K).  With `add` the int32 sums are added to G with atomics
+// (exact: a tile split along K over several blocks, G cleared beforehand), else stored.
+// Each iteration issues the global loads of the next stage, computes the current stage from
+// LDS, and stores the next stage to the other LDS buffer at the end of the stage; scheduling
+// barriers keep that order (left alone, the compiler moves the LDS store up to the loads,
+// which waits for them before the MFMAs).
 __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char* __restrict__ sa,
                                               const signed char* __restrict__ sb,
                                               int* __restrict__ G, int N, int s, int ldk,
-                                              I8Smem& sm) {
+                                              I8Smem& sm, int kb = 0, int ke = -1,
+                                              bool add = false) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8BM;      // rows of A~ / G
     const int cc0 = tj * kI8BN;       // real columns of G (rows of B~^T)
     const int M2 = 2 * N;             // real columns
     const size_t sA = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
     const size_t sB = (size_t)split_cols_pad(N) * ldk;
-    const int nk = ldk / kI8BK;       // K stages (real K = 2N, zero padded to ldk)
-    const int total = s * (s + 1) / 2 * nk;
+    if (ke < 0) ke = ldk / kI8BK;     // K stages (real K = 2N, zero padded to ldk)
+    const int total = s * (s + 1) / 2 * (ke - kb);
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int l32 = lane & 31, h = lane >> 5;
 
@@ -236,8 +240,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     const int swz = i8_swizzle(l32);
     const int rda = (wr + l32) * kI8BK, rdb = (kI8BM + wc + l32) * kI8BK;
 
-    int li = 1, lj = s, lk = 0;  // next stage to load
-    int ci = 1, cj = s, ck = 0;  // stage in LDS
+    int li = 1, lj = s, lk = kb;  // next stage to load
+    int ci = 1, cj = s, ck = kb;  // stage in LDS
     v4i ra[4], rb[4];  // native vectors (HIP's uint4 is a struct whose copies become memcpy)
 #define ZE_I8_LOAD()                                                              \
     do {                                                                          \
@@ -247,8 +251,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
             ra[x] = *reinterpret_cast<const v4i*>(A_ + x * xstep);                \
             rb[x] = *reinterpret_cast<const v4i*>(B_ + x * xstep);                \
         }                                                                         \
-        if (++lk == nk) {                                                         \
-            lk = 0;                                                               \
+        if (++lk == ke) {                                                         \
+            lk = kb;                                                              \
             i8_next_pair(li, lj);                                                 \
         }                                                                         \
     } while (0)
@@ -294,7 +298,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
             __builtin_amdgcn_sched_barrier(0);
         }
 #undef ZE_I8_READ
-        if (ck == nk - 1 && cj == 1) {  // last stage of the last pair of this t
+        if (ck == ke - 1 && cj == 1) {  // last stage of the last pair of this t
             int* g = G + (size_t)(ci + cj - 2) * N * M2;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -304,13 +308,18 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int row = row0 + wr + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
-                        if (row < N && cc < M2) g[(size_t)row * M2 + cc] = acc[a][c][r];
+                        if (row < N && cc < M2) {
+                            if (add)
+                                atomicAdd(g + (size_t)row * M2 + cc, acc[a][c][r]);
+                            else
+                                g[(size_t)row * M2 + cc] = acc[a][c][r];
+                        }
                     }
                     acc[a][c] = (v16i)0;
                 }
         }
-        if (++ck == nk) {
-            ck = 0;
+        if (++ck == ke) {
+            ck = kb;
             i8_next_pair(ci, cj);
         }
         __syncthreads();

@@ -324,6 +324,25 @@ def test_isomp_split_ten_steps_n64(dev, s):
     assert rel[1] < 1e-11 and rel[3] < 1e-11
 
 
+def test_isomp_split_step_ragged_n1000(dev):
+    """One split-precision step (4 slices) at a ragged size whose INT8 products both end in a
+    partial round of block slots, split along K with exact atomic sums (full product: 128
+    tiles in 4 parts each; lower product: 72 tiles in 4 parts), against the oracle's step."""
+    from paper_2206_05466_amd import PREC_SPLIT
+
+    N, h = 1000, 0.005
+    W0 = O.assemble(N, omega_coeffs(N, 3, "inv1", lmax=40), lmax=40)
+    Wr, it_ref, _ = O.isomp_step(W0, h, 1e-12, 50)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_split_slices(4)
+        info = z.isomp_step(Wd, h, 1e-12, 50, prec=PREC_SPLIT)
+        W = to_host(Wd)
+    err = np.linalg.norm(W - Wr) / np.linalg.norm(Wr)
+    assert info.iters == it_ref and err < 1e-10, (info.iters, it_ref, err)
+    assert np.abs(W + W.conj().T).max() == 0.0
+
+
 # ------------------------------------------------------------------ ensemble (graph replays)
 def test_ensemble_matches_oracle_and_eager_each_replay(dev):
     """One graph replay per step; between replays the eager single-context path runs on the
