@@ -37,22 +37,32 @@ __device__ inline void store_partial(double* __restrict__ part, const d4 (&acc)[
                 part[((mt * C::NT + nt) * 4 + r) * kThreads + threadIdx.x] = acc[mt][nt][r];
 }
 
+// Sum over the S partial sums of accumulator tile k = mt * NT + nt (4 values per thread).
 template <class C>
-__device__ inline void sum_partials(const double* __restrict__ part, int S,
-                                    d4 (&acc)[C::MT][C::NT]) {
+__device__ inline d4 sum_partial_tile(const double* __restrict__ part, int S, int k) {
     constexpr int PS = C::MT * C::NT * 4 * kThreads;
-#pragma unroll
-    for (int mt = 0; mt < C::MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < C::NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int mt = 0; mt < C::MT; ++mt)
+        for (int r = 0; r < 4; ++r) acc[r] += part[(size_t)s * PS + (k * 4 + r) * kThreads + threadIdx.x];
+    return acc;
+}
+
+// Store accumulator tile k = mt * NT + nt of a block (MFMA layout of config C) to C~.
+template <class C>
+__device__ inline void store_acc_tile(const d4& acc, int k, double2* Cm, int N, int row0, int col0) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wrow = (wave / C::WAVES_N) * C::WM;
+    const int wcc = (wave % C::WAVES_N) * (2 * C::WNC);
+    const int q = lane >> 4, l16 = lane & 15, mt = k / C::NT, nt = k % C::NT;
+    double* Cd = reinterpret_cast<double*>(Cm);
+    const int cc = 2 * col0 + wcc + nt * 16 + l16;
+    if (cc >= 2 * N) return;
 #pragma unroll
-            for (int nt = 0; nt < C::NT; ++nt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc[mt][nt][r] += part[(size_t)s * PS + ((mt * C::NT + nt) * 4 + r) * kThreads + threadIdx.x];
+    for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wrow + mt * 16 + q + 4 * r;
+        if (row < N) Cd[(size_t)row * 2 * N + cc] = acc[r];
+    }
 }
 
 // Work split of one launch: tiles [0, full) whole, one block each; tiles [full, full + tail)
@@ -101,14 +111,16 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
         store_partial<C>(part + (size_t)(b - full) * (C::MT * C::NT * 4 * kThreads), acc);
 }
 
+// Fix-up of the split tiles: block (t, k) adds the S partial sums of accumulator tile k of
+// split tile t, in part order (deterministic), and stores it.
 __global__ __launch_bounds__(kThreads) void zgemm_f64_fixup(double2* __restrict__ Cm, int N,
                                                             int tiles_n, int full, int S,
                                                             const double* __restrict__ part) {
     using C = FullCfg;
     const int tile = full + blockIdx.x;
-    d4 acc[C::MT][C::NT];
-    sum_partials<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads), S, acc);
-    store_full_tile(acc, Cm, N, (tile / tiles_n) * C::BM, (tile % tiles_n) * C::BNC);
+    const d4 acc = sum_partial_tile<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads),
+                                       S, blockIdx.y);
+    store_acc_tile<C>(acc, blockIdx.y, Cm, N, (tile / tiles_n) * C::BM, (tile % tiles_n) * C::BNC);
 }
 
 
@@ -150,9 +162,9 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(double2* __restric
     using C = LowCfg;
     int I, J;
     lower_tile(order[full + blockIdx.x], I, J);
-    d4 acc[C::MT][C::NT];
-    sum_partials<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads), S, acc);
-    store_tile<C>(acc, Q, N, I * kTile, J * kTile);
+    const d4 acc = sum_partial_tile<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads),
+                                       S, blockIdx.y);
+    store_acc_tile<C>(acc, blockIdx.y, Q, N, I * kTile, J * kTile);
 }
 
 // ---------------------------------------------------------------- residual reduction
@@ -238,8 +250,8 @@ hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B,
                        Cm, N, tiles_n, sp.full, sp.S, c->gemm_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
-    hipLaunchKernelGGL(zgemm_f64_fixup, dim3(sp.tail), dim3(kThreads), 0, s, Cm, N, tiles_n, sp.full,
-                       sp.S, c->gemm_part);
+    hipLaunchKernelGGL(zgemm_f64_fixup, dim3(sp.tail, FullCfg::MT * FullCfg::NT), dim3(kThreads), 0, s,
+                       Cm, N, tiles_n, sp.full, sp.S, c->gemm_part);
     return hipGetLastError();
 }
 
@@ -252,8 +264,8 @@ hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* 
                        P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
-    hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail), dim3(kThreads), 0, s, Q, N, sp.full, sp.S,
-                       c->gemm_part, c->low_order);
+    hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail, LowCfg::MT * LowCfg::NT), dim3(kThreads), 0, s,
+                       Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
     return hipGetLastError();
 }
 
