@@ -265,6 +265,17 @@ ze_status ze_ensemble_tuning(ze_ens* ens, int prec, int* choice, double* ms);
  */
 ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
 
+/*
+ * ze_ensemble_set_initial_guess -- first iterate of the fixed-point map (eq. (isomp_iter)) for
+ * the ensemble's steps, as ze_set_initial_guess for one simulation: 0 (default) W_n at every
+ * step; 1: in ze_ensemble_run, every step after the first of the call starts each simulation
+ * from 2 W_n - F_prev (its previous step's converged midpoint), which saves about one
+ * evaluation per step at the same stopping rule.  Takes effect at the next ze_ensemble_run
+ * (the step graphs are captured again).
+ * Errors: ZE_EINVAL (mode not 0 or 1).
+ */
+ze_status ze_ensemble_set_initial_guess(ze_ens* ens, int mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,13 +50,26 @@ struct EnsProb {
 
 constexpr int kCopyParts = 16;
 
+// Start of a step: W_n <- W and the first iterate F <- W_n, or with `extrap` F <- 2 W_n - F,
+// the linear extrapolation of the previous step's converged midpoint (still in F).  Every
+// evaluation then reads its iterate from F (the update rewrites it in place: each entry it
+// reads is written by the same thread, and the mirrored upper entries it writes are read by
+// no other block of that launch).
 __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restrict__ probs,
-                                                        int* __restrict__ done) {
+                                                        int* __restrict__ done, int extrap) {
     const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
     const EnsProb p = probs[sim];
     const size_t n2 = (size_t)p.N * p.N;
-    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256)
-        p.Wn[e] = p.W[e];
+    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
+        const double2 w = p.W[e];
+        p.Wn[e] = w;
+        if (extrap) {
+            const double2 f = p.F[e];
+            p.F[e] = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
+        } else {
+            p.F[e] = w;
+        }
+    }
     if (part == 0 && threadIdx.x == 0) done[sim] = 0;
 }
 
@@ -69,7 +82,7 @@ __global__ __launch_bounds__(T) void ens_solve_kernel(const EnsProb* __restrict_
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
-    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    const double2* Wt = p.F;
     solve_band<T, C, BD>(Wt, p.P, p.fl, p.fd, p.N, it.y, sG, sY);
 }
 
@@ -83,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void ens_product_kernel(const EnsProb* __
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
     const int N = p.N;
-    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    const double2* Wt = p.F;
     const int tiles_n = (N + C::BNC - 1) / C::BNC;
     const int row0 = (it.y / tiles_n) * C::BM, col0 = (it.y % tiles_n) * C::BNC;
     d4 acc[C::MT][C::NT];
@@ -116,7 +129,7 @@ __global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
-    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    const double2* Wt = p.F;
     int I, J;
     lower_tile(it.y, I, J);
     lower_update_tile(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W, p.rowpart,
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(kSThreads) void ens_split_rows_kernel(const EnsProb
     } else if (it.y < N) {
         split_row_block(p.P, N, it.y, s, ldk, p.sa, p.ep, red);
     } else {
-        const double2* Wt = eval == 1 ? p.Wn : p.F;
+        const double2* Wt = p.F;
         col_exponent_block(Wt, N, 64 * (it.y - N), p.ew, reinterpret_cast<double(*)[64]>(red));
     }
 }
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(kSThreads) void ens_split_cols_kernel(const EnsProb
     const EnsProb p = probs[it.x];
     const int N = p.N, ldk = split_ldk_of(N);
     const int gx = (N + kCT - 1) / kCT;
-    const double2* B = which == 1 ? p.P : (eval == 1 ? p.Wn : p.F);
+    const double2* B = which == 1 ? p.P : p.F;
     split_cols_tile(B, N, it.y % gx, it.y / gx, s, ldk, which == 1 ? p.ep : p.ew, p.sb, tile);
 }
 
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(kUThreads) void ens_update_split_kernel(const EnsPr
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
-    const double2* Wt = eval == 1 ? p.Wn : p.F;
+    const double2* Wt = p.F;
     int I, J;
     lower_tile(it.y, I, J);
     lower_update_tile(I, J, nullptr, p.G, p.eA, p.ep, s, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, p.N,
@@ -337,15 +350,19 @@ struct ze_ens {
     double s_tune_ms[2] = {0, 0};
     // captured graph and the parameters it was captured with
     hipGraphExec_t exec = nullptr;
-    int g_prec = -1, g_variant = -1, g_order = -1, g_K = -1, g_slices = -1;
+    int g_prec = -1, g_variant = -1, g_order = -1, g_K = -1, g_slices = -1, g_guess = -1;
+    // first iterate of the steps after the first of a run: 0 = W_n, 1 = 2 W_n - F_prev
+    int guess_mode = 0;
+    hipGraphExec_t exec_x = nullptr;  // the step graph with the extrapolated first iterate
     double g_h = 0.0, g_tol = -1.0;
 };
 
 namespace {
 
 hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done);
+                       bool extrap, hipStream_t s) {
+    hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done,
+                       extrap ? 1 : 0);
     hipError_t err = hipGetLastError();
     const int ns = e->slices;
 #define ZE_ENS_LAUNCH(...)                       \
@@ -393,20 +410,31 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
     return err;
 }
 
-hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant, int order) {
-    if (e->exec) {
-        (void)hipGraphExecDestroy(e->exec);
-        e->exec = nullptr;
+hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
+                       bool extrap, hipGraphExec_t* out) {
+    if (*out) {
+        (void)hipGraphExecDestroy(*out);
+        *out = nullptr;
     }
     hipGraph_t g = nullptr;
     hipError_t err = hipStreamBeginCapture(e->own, hipStreamCaptureModeRelaxed);
     if (err != hipSuccess) return err;
-    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, e->own);
+    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, extrap, e->own);
     err = hipStreamEndCapture(e->own, &g);
     if (rec != hipSuccess) err = rec;
-    if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+    if (err == hipSuccess) err = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
+    return err;
+}
+
+// The step graph (first iterate W_n) and, with guess mode 1, the graph of the steps after the
+// first of a run (first iterate 2 W_n - F_prev).
+hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant, int order) {
+    hipError_t err = capture_one(e, h, tol, K, prec, variant, order, false, &e->exec);
+    if (err == hipSuccess && e->guess_mode == 1)
+        err = capture_one(e, h, tol, K, prec, variant, order, true, &e->exec_x);
     if (err == hipSuccess) {
+        e->g_guess = e->guess_mode;
         e->g_prec = prec;
         e->g_variant = variant;
         e->g_order = order;
@@ -469,7 +497,7 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
         const int variant = split ? 0 : cand >> 1, order = split ? cand : cand & 1;
         st = set_pointers(e, reinterpret_cast<void* const*>(copies.data()));
         if (st != ZE_OK) break;
-        if (capture(e, h, tol, K, prec, variant, order) != hipSuccess) {
+        if (capture_one(e, h, tol, K, prec, variant, order, false, &e->exec) != hipSuccess) {
             st = ze_record_hip(hipGetLastError(), "ensemble autotune capture");
             break;
         }
@@ -504,6 +532,10 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
         (void)hipGraphExecDestroy(e->exec);
         e->exec = nullptr;
     }
+    if (e->exec_x) {
+        (void)hipGraphExecDestroy(e->exec_x);
+        e->exec_x = nullptr;
+    }
     return st;
 }
 
@@ -534,6 +566,7 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
     if (!e) return ZE_OK;
     if (e->own) (void)hipStreamSynchronize(e->own);
     if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->exec_x) (void)hipGraphExecDestroy(e->exec_x);
     for (ze_ctx* c : e->ctx) ze_destroy(c);
     (void)hipFree(e->dp);
     (void)hipFree(e->done);
@@ -663,9 +696,11 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     ZE_TRY(set_pointers(e, W));
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
-        e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices)
+        e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices ||
+        e->g_guess != e->guess_mode)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
-    for (int n = 0; n < nsteps; ++n) ZE_HIP(hipGraphLaunch(e->exec, e->own));
+    for (int n = 0; n < nsteps; ++n)
+        ZE_HIP(hipGraphLaunch(n > 0 && e->guess_mode == 1 ? e->exec_x : e->exec, e->own));
     ZE_HIP(hipEventRecord(e->ev_out, e->own));
     ZE_HIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
     return ZE_OK;
@@ -694,6 +729,12 @@ ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
     if (choice) *choice = e->variant < 0 ? -1 : 2 * e->variant + e->order;
     if (ms)
         for (int i = 0; i < 4; ++i) ms[i] = e->tune_ms[i];
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
+    if (!e || mode < 0 || mode > 1) return ZE_EINVAL;
+    e->guess_mode = mode;
     return ZE_OK;
 }
 

@@ -48,6 +48,7 @@ SIGNATURES = {
     "ze_ensemble_stats": (_c_int, [_vp, _P_int, _P_double]),
     "ze_ensemble_tuning": (_c_int, [_vp, _c_int, _P_int, _P_double]),
     "ze_ensemble_set_split_slices": (_c_int, [_vp, _c_int]),
+    "ze_ensemble_set_initial_guess": (_c_int, [_vp, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -306,6 +307,12 @@ class Ensemble:
         """Slices per operand of the ensemble's PREC_SPLIT products (2..8)."""
         _check(self.lib.ze_ensemble_set_split_slices(self._ens, int(slices)),
                "ze_ensemble_set_split_slices")
+
+    def set_initial_guess(self, mode: int):
+        """0: every step starts from W_n; 1: steps after the first of a run start each simulation
+        from 2 W_n - F_prev (as Zeuler.set_initial_guess)."""
+        _check(self.lib.ze_ensemble_set_initial_guess(self._ens, int(mode)),
+               "ze_ensemble_set_initial_guess")
 
     def tuning(self, prec: int = PREC_FP64):
         """(choice, [ms per step of the candidates]) of the autotuner for precision prec:

@@ -393,6 +393,32 @@ def test_ensemble_multi_step_run_and_fixed_K(dev):
         assert np.linalg.norm(to_host(Wd[j]) - W) <= 1e-12 * np.linalg.norm(W)
 
 
+def test_ensemble_extrapolated_guess(dev):
+    """Guess mode 1 in the ensemble (steps after the first of a run start from 2 W_n - F_prev):
+    every simulation matches the single-context run in the same mode and the oracle's
+    extrapolated run, with the same iteration count on the last step."""
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [64, 40, 96]
+    h, tol, K, steps = 0.01, 1e-12, 8, 4
+    W0s = [w0(n, 60 + j) for j, n in enumerate(sizes)]
+    Wd = [to_dev(W) for W in W0s]
+    with Ensemble(sizes) as ens:
+        ens.set_initial_guess(1)
+        ens.run(Wd, h, steps, tol, K)
+        its, res = ens.stats()
+    for j, n in enumerate(sizes):
+        We = to_dev(W0s[j])
+        with ctx(n) as z:
+            z.set_initial_guess(1)
+            it1, _ = z.isomp_run(We, h, steps, tol, K)
+        Wr, itr, _ = O.isomp_run(W0s[j], h, steps, tol, K, extrapolate=True)
+        a, b = to_host(Wd[j]), to_host(We)
+        assert its[j] == it1[-1] == itr[-1] and res[j] < tol, (j, its[j], it1, itr)
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b), j
+        assert np.linalg.norm(a - Wr) <= 1e-12 * np.linalg.norm(Wr), j
+
+
 def test_ensemble_split_matches_single_context_and_oracle(dev):
     """Split-precision ensemble (ragged N, slice count changed between replays): every step
     matches the single-context split path and the oracle."""
