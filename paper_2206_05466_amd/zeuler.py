@@ -228,7 +228,8 @@ class Zeuler:
         _check(self.lib.ze_set_initial_guess(self._ctx, int(mode)), "ze_set_initial_guess")
 
     def set_split_slices(self, slices: int):
-        """Slices per operand of the PREC_SPLIT products (2..8)."""
+        """Slices per operand of the PREC_SPLIT products (2 .. s_max(N): 8 up to N = 4096, 7 at
+        8192, 3 at 16384; the int32 exactness bound)."""
         _check(self.lib.ze_set_split_slices(self._ctx, int(slices)), "ze_set_split_slices")
 
     def profile(self, on: bool = True):
@@ -304,7 +305,7 @@ class Ensemble:
         return list(its), list(res)
 
     def set_split_slices(self, slices: int):
-        """Slices per operand of the ensemble's PREC_SPLIT products (2..8)."""
+        """Slices per operand of the ensemble's PREC_SPLIT products (2 .. s_max of the largest N)."""
         _check(self.lib.ze_ensemble_set_split_slices(self._ens, int(slices)),
                "ze_ensemble_set_split_slices")
 

@@ -12,6 +12,8 @@ Tolerances (FP64 throughout):
   with the exact eigenvalue); W is compared at 1e-11 relative.
 """
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -176,6 +178,27 @@ def test_isomp_fixed_iterations_and_errors(dev):
         bad[3, 1] = float("nan")
         with pytest.raises(ZeulerError, match="non-finite"):
             z.isomp_step(bad, 0.1, 1e-12, 5)
+        with pytest.raises(ZeulerError):
+            z.set_initial_guess(2)
+        with pytest.raises(ZeulerError):
+            z.set_split_slices(1)
+        lib = z.lib
+        p = ctypes.c_void_p(Wd.data_ptr())
+        assert lib.ze_basis_extract(z._ctx, p, p) != 0  # omega aliasing W
+        assert lib.ze_energy_spectrum(z._ctx, None, p) != 0
+        assert lib.ze_basis_assemble(z._ctx, p, p) != 0
+
+
+def test_ensemble_argument_errors(dev):
+    from paper_2206_05466_amd import Ensemble, ZeulerError
+
+    with Ensemble([16, 24]) as ens:
+        with pytest.raises(ZeulerError):
+            ens.set_initial_guess(-1)
+        with pytest.raises(ZeulerError):
+            ens.set_split_slices(99)
+        with pytest.raises(ZeulerError):
+            ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], 0.01, 1, 1e-12, 0)  # K < 1
 
 
 # ------------------------------------------------------------------ Casimirs
