@@ -15,7 +15,9 @@ follows:
 * ``stream``     -- the stream solve P = Delta_N^+ W, one tridiagonal system per diagonal,
   eq. (sub_tria_W) (Sec. 3.3), with LAPACK's positive-definite tridiagonal routines.
 * ``isomp``      -- the isospectral midpoint step, eq. (isomp) (Sec. 2), reached by the
-  fixed-point iteration eq. (isomp_iter) with the infinity-norm stopping rule (Sec. 2).
+  fixed-point iteration eq. (isomp_iter) with the infinity-norm stopping rule (Sec. 2);
+  and the order-4 and order-6 symmetric compositions of that step (the higher-order members
+  of the family Sec. 2 names).
 * ``casimirs``   -- C_k(W) = Tr(W^k), eq. (W_pow).
 * ``basis``      -- the quantised basis T_lm as eigenvectors of Delta^m (Sec. 3.2) and the
   assembly W = sum_lm i omega_lm T_lm, eq. (W0); plus the inverse projection and the
@@ -27,12 +29,12 @@ on tiny N and invariants that the paper and the mathematics fix (see the docstri
 
 from .laplacian import delta_tridiag, spin_matrices, brute_laplacian, apply_laplacian
 from .stream import stream_solve
-from .isomp import isomp_step, isomp_run
+from .isomp import isomp_step, isomp_run, composition_weights, isomp_composed_run
 from .casimirs import casimirs, casimirs_eig
 from .basis import eigvecs, assemble, extract, energy_spectrum
 
 __all__ = [
     "delta_tridiag", "spin_matrices", "brute_laplacian", "apply_laplacian",
-    "stream_solve", "isomp_step", "isomp_run", "casimirs", "casimirs_eig",
+    "stream_solve", "isomp_step", "isomp_run", "composition_weights", "isomp_composed_run", "casimirs", "casimirs_eig",
     "eigvecs", "assemble", "extract", "energy_spectrum",
 ]

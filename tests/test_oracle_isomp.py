@@ -12,6 +12,11 @@ scheme and the mathematics fix:
   single degree l >= 2 the commutator vanishes and the step drifts only at O(h^3);
 * SU(2) rotation equivariance;
 * iteration counts of a few (2..5) at tolerance 1e-12 (Sec. 2 reports 2 to 3).
+
+The order-4 and order-6 compositions of the step are pinned the same way: fourth and sixth
+order against the independent ODE integration, isospectrality and reversibility of the
+composed step, the order-2 composition being the midpoint run itself, and the extrapolated
+substep starts reaching the same fixed points in fewer evaluations.
 """
 
 import numpy as np
@@ -168,3 +173,62 @@ def test_extrapolated_guess_same_fixed_point_fewer_evaluations():
     W1, _, _ = O.isomp_step(W, 0.005, 1e-13, 50)
     W1g, _, _ = O.isomp_step(W, 0.005, 1e-13, 50, guess=W + 0.01 * w0(128, 9))
     assert np.abs(W1 - W1g).max() < 1e-13
+
+
+@pytest.mark.parametrize("order,lo,hi", [(4, 14.5, 17.0), (6, 54.0, 70.0)])
+def test_composition_order_against_independent_ode(order, lo, hi):
+    """Halving h divides the error at T by 2^order (the ODE reference is ~1e-13 accurate)."""
+    N = 8
+    W = 3.0 * w0(N, 2)
+    T = 0.8
+    ref = _ode_reference(W, T)
+    errs = []
+    for nsteps in (4, 8, 16):
+        Wh, _, _ = O.isomp_composed_run(W, T / nsteps, nsteps, order, 1e-14, 100)
+        errs.append(np.abs(Wh - ref).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert lo < r1 < hi and lo < r2 < hi, (errs, r1, r2)
+    # at equal h the higher order is the more accurate one
+    W2, _, _ = O.isomp_run(W, T / 8, 8, 1e-14, 100)
+    assert errs[1] < 0.1 * np.abs(W2 - ref).max()
+
+
+def test_composition_weights_closed_form_properties():
+    """Consistency (sum 1), symmetry, the order-4 condition sum c^3 = 0 of a symmetric
+    composition, sum c^5 = 0 as well at order 6, and the known negative middle step."""
+    assert O.composition_weights(2) == [1.0]
+    for order, n in ((4, 3), (6, 9)):
+        w = np.array(O.composition_weights(order))
+        assert len(w) == n and abs(w.sum() - 1.0) < 1e-15
+        assert np.array_equal(w, w[::-1])
+        assert abs((w ** 3).sum()) < 1e-15 * (np.abs(w) ** 3).sum()
+    w6 = np.array(O.composition_weights(6))
+    assert abs((w6 ** 5).sum()) < 1e-15 * (np.abs(w6) ** 5).sum()
+    g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+    assert abs(O.composition_weights(4)[1] + 2.0 ** (1.0 / 3.0) * g1) < 1e-15  # g2 < 0
+    with pytest.raises(ValueError):
+        O.composition_weights(3)
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_composition_isospectral_and_reversible(order):
+    N = 16
+    W = 2.0 * w0(N, 6)
+    W1, its, res = O.isomp_composed_run(W, 0.1, 2, order, 1e-14, 100)
+    assert max(res) < 1e-14 and len(its) == 2
+    assert np.abs(spec(W1) - spec(W)).max() < 1e-12 * np.abs(spec(W)).max()
+    assert np.abs(W1 + W1.conj().T).max() < 1e-15
+    Wb, _, _ = O.isomp_composed_run(W1, -0.1, 2, order, 1e-14, 100)
+    assert np.abs(Wb - W).max() < 1e-12 * np.abs(W).max()
+
+
+def test_composition_order2_is_the_midpoint_run_and_extrapolation():
+    W = w0(24, 7)
+    for ex in (False, True):
+        Wa, ia, ra = O.isomp_run(W, 0.02, 3, 1e-12, 50, extrapolate=ex)
+        Wb, ib, rb = O.isomp_composed_run(W, 0.02, 3, 2, 1e-12, 50, extrapolate=ex)
+        assert np.array_equal(Wa, Wb) and ia == ib and ra == rb
+    Wa, ia, _ = O.isomp_composed_run(W, 0.02, 3, 4, 1e-13, 50)
+    Wb, ib, rb = O.isomp_composed_run(W, 0.02, 3, 4, 1e-13, 50, extrapolate=True)
+    assert max(rb) < 1e-13 and sum(ib) < sum(ia), (ia, ib)
+    assert np.abs(Wa - Wb).max() < 1e-13
