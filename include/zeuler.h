@@ -94,9 +94,11 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
  *   maxit   evaluation cap, >= 1.
  *   prec    ZE_PREC_FP64 or ZE_PREC_SPLIT.
- *   iters   host, may be NULL: evaluations done.
- *   resid   host, may be NULL: final residual.
- * Errors: ZE_EINVAL, ZE_ENOTCONV (W holds the maxit-th W_{n+1}), ZE_ENONFINITE, ZE_EHIP.
+ *   iters   host, may be NULL: evaluations done (summed over the substeps of a step of
+ *           order 4 or 6, see ze_set_order).
+ *   resid   host, may be NULL: final residual (the largest over the substeps).
+ * Errors: ZE_EINVAL, ZE_ENOTCONV (W holds the maxit-th W_{n+1}; at order 4 or 6 every substep
+ * still runs, each stopping at maxit), ZE_ENONFINITE, ZE_EHIP.
  * Synchronises the stream once per evaluation (the convergence test).
  */
 ze_status ze_isomp_step(ze_ctx* ctx, void* W, double h, double tol, int maxit, int prec,
@@ -122,6 +124,22 @@ ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, in
  * Errors: ZE_EINVAL.
  */
 ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
+
+/*
+ * ze_set_order -- order of ze_isomp_step / ze_isomp_run: 2 (default) is the midpoint map of
+ * eq. (isomp); 4 and 6 are its symmetric compositions.  Sec. 2 obtains the midpoint map as the
+ * simplest member of a family of isospectral integrators reduced from symplectic Runge--Kutta
+ * methods and names higher orders without giving them; the members built here compose the
+ * midpoint map with itself, which keeps every property the map has (isospectral, Lie--Poisson,
+ * symmetric) and raises the order by Yoshida's triple jump (Phys. Lett. A 150, 1990): substeps
+ * g1 h, g2 h, g1 h with g1 = 1 / (2 - 2^(1/(p+1))), g2 = 1 - 2 g1 take an order p to p + 2.
+ * Order 4 is 3 midpoint substeps per step (g2 < 0), order 6 the triple jump applied twice
+ * (9 substeps).  With ze_set_initial_guess mode 1 every substep after the first of a call
+ * starts from W + rho (W - F_prev), rho the ratio of its step to the previous substep's (also
+ * inside a single ze_isomp_step).  The ensemble entry points always step at order 2.
+ * Errors: ZE_EINVAL for any other order.
+ */
+ze_status ze_set_order(ze_ctx* ctx, int order);
 
 /*
  * ze_casimirs -- C_k(W) = Tr(W^k), k = 1..kmax (eq. (W_pow)), in FP64, from powers of W

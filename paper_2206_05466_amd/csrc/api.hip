@@ -218,10 +218,11 @@ ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
 
 namespace {
 
-// One step; with `extrapolate` the fixed point starts from 2 W_n - F (F = the previous step's
-// converged midpoint, still in c->F) instead of W_n.
+// One midpoint step of size h; with `extrapolate` the fixed point starts from W_n + rho (W_n - F)
+// (F = the previous step's converged midpoint, still in c->F; rho = 1 gives 2 W_n - F) instead
+// of W_n.
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                          bool extrapolate, int* iters, double* resid) {
+                          bool extrapolate, double rho, int* iters, double* resid) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
     const int N = c->N;
@@ -233,7 +234,7 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
     if (extrapolate) {
-        ZE_HIP(launch_extrapolate(Wu, c->F, N, s));
+        ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
         Wt = c->F;
     }
     double r = 0.0;
@@ -284,11 +285,47 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     return ZE_OK;
 }
 
+// One step of the context's order: a midpoint substep of size c_j h for every fraction c_j.
+// With guess mode 1, every substep after the first of the call (and the first as well when
+// first_extrap is set) starts from W + rho (W - F_prev), rho = c_j / c_{j-1} (cyclically, so
+// 1 across a step boundary).  A substep that reaches maxit above tol still completes the step
+// (the fixed-iteration mode) and the step then reports ZE_ENOTCONV; any other error ends it.
+// iters: evaluations over all substeps; resid: the largest substep residual.
+ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                        bool first_extrap, int* iters, double* resid) {
+    const std::vector<double>& w = c->comp_w;
+    const size_t ns = w.size();
+    int total = 0;
+    double rmax = 0.0;
+    ze_status out = ZE_OK;
+    for (size_t j = 0; j < ns; ++j) {
+        const bool ex = c->guess_mode == 1 && (j > 0 || first_extrap);
+        const double rho = w[j] / w[j == 0 ? ns - 1 : j - 1];
+        int k = 0;
+        double r = 0.0;
+        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, ex, rho, &k, &r);
+        total += k;
+        if (!(r <= rmax)) rmax = r;  // keeps a NaN
+        if (st == ZE_ENOTCONV) {
+            out = ZE_ENOTCONV;
+            continue;
+        }
+        if (st != ZE_OK) {
+            out = st;
+            break;
+        }
+    }
+    if (iters) *iters = total;
+    if (resid) *resid = rmax;
+    return out;
+}
+
 }  // namespace
 
 ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                         int* iters, double* resid) {
-    return isomp_step_impl(c, W, h, tol, maxit, prec, false, iters, resid);
+    if (!c) return ZE_EINVAL;
+    return composed_step(c, W, h, tol, maxit, prec, false, iters, resid);
 }
 
 ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps, int prec,
@@ -297,7 +334,7 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = isomp_step_impl(c, W, h, tol, maxit, prec, n > 0 && c->guess_mode == 1, &k, &r);
+        ze_status st = composed_step(c, W, h, tol, maxit, prec, n > 0, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) return st;
@@ -386,6 +423,24 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
     if (!c || mode < 0 || mode > 1) return ZE_EINVAL;
     c->guess_mode = mode;
+    return ZE_OK;
+}
+
+ze_status ze_set_order(ze_ctx* c, int order) {
+    if (!c || (order != 2 && order != 4 && order != 6)) return ZE_EINVAL;
+    // Triple jump (Yoshida 1990): from a symmetric method of even order p, the substeps
+    // g1, g2, g1 with g1 = 1 / (2 - 2^(1/(p+1))) and g2 = 1 - 2 g1 give order p + 2.
+    std::vector<double> w{1.0};
+    for (int p = 2; p < order; p += 2) {
+        const double g1 = 1.0 / (2.0 - std::pow(2.0, 1.0 / (p + 1)));
+        const double g2 = 1.0 - 2.0 * g1;
+        std::vector<double> next;
+        for (double g : {g1, g2, g1})
+            for (double x : w) next.push_back(g * x);
+        w.swap(next);
+    }
+    c->comp_w = w;
+    c->order = order;
     return ZE_OK;
 }
 

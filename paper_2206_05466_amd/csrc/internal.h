@@ -72,6 +72,10 @@ struct ze_ctx {
     // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
     // (F = the previous step's converged midpoint, left in ze_ctx::F).
     int guess_mode = 0;
+    // Order of the time step (2: the midpoint map; 4, 6: its symmetric compositions) and the
+    // substep fractions c_j of one step.
+    int order = 2;
+    std::vector<double> comp_w{1.0};
 
     // Optional per-phase timing (ze_profile).
     bool prof = false;
@@ -178,4 +182,4 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
                                hipStream_t s);
 
 // F <- 2 W - F (N x N complex).
-hipError_t launch_extrapolate(const double2* W, double2* F, int N, hipStream_t s);
+hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, hipStream_t s);

@@ -39,6 +39,7 @@ SIGNATURES = {
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
+    "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
     "ze_ensemble_create": (_c_int, [_c_int, _P_int, _vp, ctypes.POINTER(_vp)]),
@@ -226,6 +227,12 @@ class Zeuler:
         """0: each step starts from W_n; 1: steps after the first in isomp_run start from the
         extrapolation 2 W_n - F_prev of the previous converged midpoint."""
         _check(self.lib.ze_set_initial_guess(self._ctx, int(mode)), "ze_set_initial_guess")
+
+    def set_order(self, order: int):
+        """Order of isomp_step / isomp_run: 2 (the midpoint map), 4 or 6 (its symmetric
+        compositions, 3 and 9 midpoint substeps per step); iteration counts are then summed
+        and residuals maximised over the substeps of a step."""
+        _check(self.lib.ze_set_order(self._ctx, int(order)), "ze_set_order")
 
     def set_split_slices(self, slices: int):
         """Slices per operand of the PREC_SPLIT products (2 .. s_max(N): 8 up to N = 4096, 7 at

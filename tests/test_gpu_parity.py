@@ -530,3 +530,61 @@ def test_reversibility(dev):
     assert a.converged and b.converged
     W = to_host(Wd)
     assert np.linalg.norm(W - W0) <= 1e-12 * np.linalg.norm(W0), np.linalg.norm(W - W0) / np.linalg.norm(W0)
+
+
+# ------------------------------------------------------------------ higher order (compositions)
+@pytest.mark.parametrize("order,N,guess", [(4, 64, 0), (4, 100, 1), (6, 64, 1), (6, 33, 0)])
+def test_isomp_composed_matches_oracle(dev, order, N, guess):
+    """Order-4 and order-6 steps (3 and 9 midpoint substeps, one of each triple backwards):
+    the same evaluation counts per step as the oracle's composition and the same W to 1e-12,
+    from W_n or from the extrapolated substep starts; then one more step through the
+    single-step entry point, from the oracle's W."""
+    h, steps = 0.02, 3
+    W0 = w0(N, 5)
+    ex = bool(guess)
+    Wr, it_ref, _ = O.isomp_composed_run(W0, h, steps, order, 1e-12, 50, extrapolate=ex)
+    W1r, i1, _ = O.isomp_composed_run(Wr, h, 1, order, 1e-12, 50, extrapolate=ex)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_order(order)
+        z.set_initial_guess(guess)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 50)
+        W = to_host(Wd)
+        Wd = to_dev(Wr)
+        info = z.isomp_step(Wd, h, 1e-12, 50)
+        W1 = to_host(Wd)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
+    assert info.converged and info.iters == i1[0], (info, i1)
+    assert np.linalg.norm(W1 - W1r) <= 1e-12 * np.linalg.norm(W1r)
+    assert np.abs(W1 + W1.conj().T).max() == 0.0
+
+
+def test_isomp_composed_split_and_fixed_iterations(dev):
+    """Order 4 with the split-precision products (5 slices) against the oracle (1e-10); and
+    the fixed-iteration mode (tol = 0, maxit = 2): every substep still runs its 2 evaluations,
+    the step reports 6 and is not converged, and W matches the oracle's fixed-count run."""
+    from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
+
+    N, h = 64, 0.02
+    W0 = w0(N, 8)
+    Wr, _, _ = O.isomp_composed_run(W0, h, 3, 4, 1e-12, 50, extrapolate=True)
+    Wf, itf, _ = O.isomp_composed_run(W0, h, 1, 4, 0.0, 2)
+    with ctx(N) as z:
+        z.set_order(4)
+        z.set_initial_guess(1)
+        z.set_split_slices(5)
+        Wd = to_dev(W0)
+        its, res = z.isomp_run(Wd, h, 3, 1e-12, 50, prec=PREC_SPLIT)
+        W = to_host(Wd)
+        z.set_initial_guess(0)
+        Wd = to_dev(W0)
+        info = z.isomp_step(Wd, h, 0.0, 2)
+        Wx = to_host(Wd)
+        for bad in (0, 3, 5, 8):
+            with pytest.raises(ZeulerError):
+                z.set_order(bad)
+    assert max(res) < 1e-12
+    assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
+    assert not info.converged and info.iters == itf[0] == 6
+    assert np.linalg.norm(Wx - Wf) <= 1e-12 * np.linalg.norm(Wf)
