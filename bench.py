@@ -294,6 +294,53 @@ def long_leg(steps):
     }
 
 
+def orders_leg():
+    """Workload orders512: the long-run initial condition at N = 512 stepped to t = 2 at
+    orders 2, 4 and 6 (ze_set_order) for several h, each compared with an order-6 run at a
+    much smaller step: error, evaluations and time per unit of simulated time."""
+    import numpy as np
+    import torch
+
+    from paper_2206_05466_amd import Zeuler
+    from workloads import WORKLOADS, omega_coeffs
+
+    cfg = WORKLOADS["orders512"]
+    N, T, tol = cfg["N"], cfg["T"], cfg["tol"]
+    z = Zeuler(N)
+    W0 = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
+    W0 /= float(np.linalg.norm(W0.cpu().numpy(), 2))
+    z.set_initial_guess(1)
+
+    def run(order, h):
+        n = int(round(T / h))
+        z.set_order(order)
+        W = W0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, res = z.isomp_run(W, h, n, tol, cfg["maxit"])
+        torch.cuda.synchronize()
+        return W, time.perf_counter() - t0, sum(its), max(res)
+
+    run(4, cfg["hs"][0])  # warm-up
+    Wref, t_ref, e_ref, r_ref = run(6, cfg["h_ref"])
+    nref = float(torch.linalg.norm(Wref).item())
+    rows = []
+    for order in (2, 4, 6):
+        for h in cfg["hs"]:
+            W, dt, ev, rmax = run(order, h)
+            rows.append({"order": order, "h": h, "steps": int(round(T / h)), "evaluations": ev,
+                         "s_per_unit_time": dt / T, "max_resid": rmax, "converged": rmax < tol,
+                         "rel_frobenius_error": float(torch.linalg.norm(W - Wref).item()) / nref})
+    z.close()
+    return {
+        "workload": f"orders512: N={N}, sigma_l law paper (seed {cfg['seed']}), unit spectral "
+                    f"norm, t = 0 .. {T}, tol={tol}, extrapolated substep starts",
+        "reference": {"order": 6, "h": cfg["h_ref"], "evaluations": e_ref, "max_resid": r_ref},
+        "runs": rows,
+        "note": "error is against the order-6 reference run (self-convergence), not an exact solution",
+    }
+
+
 def casimir_drift(c0, c1, W):
     """Relative drift of C_2, C_4; C_3 relative to ||W||_F^3 (C_3 can be tiny)."""
     import torch
@@ -424,6 +471,8 @@ def main():
                     help="timed steps of the N=512 leg (0: skip it)")
     ap.add_argument("--long-steps", type=int, default=10000,
                     help="steps of the long-run drift leg (N=512, paper initial condition; 0: skip)")
+    ap.add_argument("--orders", type=int, default=1,
+                    help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -462,6 +511,7 @@ def main():
 
     n512 = small_leg(args.n512_steps) if args.n512_steps > 0 else None
     long512 = long_leg(args.long_steps) if args.long_steps > 0 else None
+    orders512 = orders_leg() if args.orders > 0 else None
 
     ens = None
     if args.ensemble_steps > 0:
@@ -550,6 +600,7 @@ def main():
         "n2048": n2048,
         "n512": n512,
         "long512": long512,
+        "orders512": orders512,
         "ensemble": ens,
     }
     if not args.no_cpu_baseline:

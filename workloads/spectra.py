@@ -73,4 +73,8 @@ WORKLOADS = {
     # the paper's long-run initial condition (degrees 2..20, unit spectral norm, Sec. 4)
     "long512": dict(N=512, law="paper", h=0.005, steps=10000, tol=1e-12, maxit=50, seed=0,
                     sample=1000),
+    # the same initial condition to t = 2 at orders 2, 4, 6 over several step sizes, against
+    # an order-6 run at a smaller step (accuracy against cost)
+    "orders512": dict(N=512, law="paper", seed=0, T=2.0, hs=(0.4, 0.2, 0.1, 0.05),
+                      h_ref=0.025, tol=1e-13, maxit=50),
 }
