@@ -20,11 +20,20 @@ Readings taken here (the paper does not state them):
   every step after the first starts from the linear extrapolation 2 W_n - F_prev of the
   previous step's converged midpoint (F_prev, the map's output at its last evaluation), since
   W~ approximates W half a step ahead; the converged result is the same fixed point;
+* with ``degree`` d >= 2 as well, a step with k >= 2 earlier steps in the run starts from the
+  polynomial of degree min(k - 1, d) through the last min(k, d + 1) midpoints, evaluated one
+  step ahead (``extrapolate_midpoints``): the midpoints are equally spaced samples of a
+  smooth curve, so the start is within O(h^(d+1)) of the fixed point; k = 1 keeps the
+  linear start above;
 * the norm is the matrix infinity norm, max_i sum_j |F_ij - W~_ij|, of the change
   F - W~ between the map's output F and its input W~;
-* W_{n+1} is the second line of eq. (isomp) evaluated at the same W~ whose change is
-  below the tolerance, reusing that evaluation's products:
-  W_{n+1} = W~ + h/2 C - h^2/4 Q, with C = A - A^H and Q = A P;
+* W_{n+1} comes from the difference of the two lines of eq. (isomp), which is exactly
+  W_{n+1} - W_n = h (P~ W~ - W~ P~): W_{n+1} = W_n + h C, with C = A - A^H the commutator of
+  the evaluation whose change is below the tolerance (its input W~).  At the fixed point this
+  is the second line of eq. (isomp); at a stopped iterate it keeps the step isospectral up to
+  O(h ||P|| r) instead of O(r) for the second line evaluated directly (r the residual:
+  W~ + h/2 C - h^2/4 Q is a unitary conjugate of W_n - (F - W~), while W_n + h C differs
+  from that by F - W~ itself, which cancels the residual to first order);
 * Q is skew-Hermitian in exact arithmetic and is projected, Q <- (Q - Q^H)/2;
 * with ``maxit`` reached first, W_{n+1} comes from the last W~ and the caller is told the
   residual (a fixed iteration count, as in the paper's timing runs, is ``tol = 0``);
@@ -66,10 +75,25 @@ def isomp_step(Wn: np.ndarray, h: float, tol: float = 1e-12, maxit: int = 50,
         F = Wn + (0.5 * h) * C + (0.25 * h * h) * Q
         r = float(np.abs(F - Wt).sum(axis=1).max())
         if r < tol or k == maxit:
-            W1 = Wt + (0.5 * h) * C - (0.25 * h * h) * Q
+            W1 = Wn + h * C
             return (W1, k, r, F) if return_midpoint else (W1, k, r)
         Wt = F
     raise ValueError("maxit must be >= 1")
+
+
+def extrapolate_midpoints(mids: list, degree: int) -> np.ndarray:
+    """Value one step ahead of the polynomial of degree ``degree`` through the equally spaced
+    samples mids[-1], mids[-2], ..., mids[-(degree+1)] (newest last): by Newton's forward
+    differences, sum_{j=1}^{d+1} (-1)^(j+1) binom(d+1, j) mids[-j]."""
+    from math import comb
+
+    d = int(degree)
+    if d < 0 or len(mids) < d + 1:
+        raise ValueError("need degree + 1 samples")
+    out = np.zeros_like(np.asarray(mids[-1], dtype=np.complex128))
+    for j in range(1, d + 2):
+        out = out + ((-1) ** (j + 1) * comb(d + 1, j)) * np.asarray(mids[-j], dtype=np.complex128)
+    return out
 
 
 def composition_weights(order: int) -> list:
@@ -113,14 +137,25 @@ def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: f
 
 
 def isomp_run(W0: np.ndarray, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
-              extrapolate: bool = False):
-    """nsteps IsoMP steps from W0.  Returns (W, [iterations], [residuals])."""
+              extrapolate: bool = False, degree: int = 1):
+    """nsteps IsoMP steps from W0.  Returns (W, [iterations], [residuals]).
+
+    ``extrapolate``: starting iterates from the previous midpoints of this run (see the
+    module notes); ``degree`` (1..3): the highest polynomial degree of that extrapolation."""
+    if degree not in (1, 2, 3):
+        raise ValueError("degree must be 1, 2 or 3")
     W = np.asarray(W0, dtype=np.complex128).copy()
     iters, res = [], []
-    mid = None
+    mids = []
     for _ in range(nsteps):
-        guess = 2.0 * W - mid if (extrapolate and mid is not None) else None
+        guess = None
+        if extrapolate and len(mids) == 1 or (extrapolate and degree == 1 and mids):
+            guess = 2.0 * W - mids[-1]
+        elif extrapolate and len(mids) >= 2:
+            d = min(len(mids) - 1, degree)
+            guess = extrapolate_midpoints(mids, d)
         W, k, r, mid = isomp_step(W, h, tol, maxit, guess=guess, return_midpoint=True)
+        mids = (mids + [mid])[-(degree + 1):]
         iters.append(k)
         res.append(r)
     return W, iters, res

@@ -232,3 +232,57 @@ def test_composition_order2_is_the_midpoint_run_and_extrapolation():
     Wb, ib, rb = O.isomp_composed_run(W, 0.02, 3, 4, 1e-13, 50, extrapolate=True)
     assert max(rb) < 1e-13 and sum(ib) < sum(ia), (ia, ib)
     assert np.abs(Wa - Wb).max() < 1e-13
+
+
+def test_stopped_iterate_stays_isospectral_to_order_h_p_r():
+    """W_{n+1} = W_n + h C at an iterate stopped early (maxit 1..3, residual r up to 1e-2):
+    W_{n+1} = U (W_n - E) U^H + E with U the Cayley transform of h P~ and E = F - W~
+    (||E||_2 <= r for skew-Hermitian E), so by Weyl its eigenvalues move by at most
+    ||U E U^H - E|| <= 2 h ||P~|| r / (1 - h ||P~|| / 2).  The second line of eq. (isomp)
+    evaluated directly at the stopped iterate would move them by O(r)."""
+    W = w0(16, 3)
+    ev = spec(W)
+    hp = np.linalg.norm(O.stream_solve(W), 2)
+    for h in (0.05, 0.1):
+        for m in (1, 2, 3):
+            W1, k, r = O.isomp_step(W, h, 0.0, m)
+            drift = np.abs(spec(W1) - ev).max()
+            assert drift <= 2.5 * h * hp * r, (h, m, drift, r)
+            assert drift < 0.02 * r
+            assert np.abs(W1 + W1.conj().T).max() < 1e-15
+
+
+def test_extrapolate_midpoints_exact_on_polynomials():
+    """Newton extrapolation of degree d reproduces every matrix polynomial of degree <= d one
+    step ahead, and misses a degree d + 1 term by exactly its (d+1)-th difference."""
+    rng = np.random.default_rng(3)
+    M = [rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5)) for _ in range(4)]
+
+    def p(t, deg):
+        return sum(M[i] * float(t) ** i for i in range(deg + 1))
+
+    for d in (1, 2, 3):
+        samples = [p(t, d) for t in range(d + 1)]
+        got = O.extrapolate_midpoints(samples, d)
+        assert np.abs(got - p(d + 1, d)).max() < 1e-12 * np.abs(p(d + 1, d)).max()
+    # degree 2 on a cubic: p(4) - extrapolation = 3! M3 (the third difference of t^3)
+    samples = [p(t, 3) for t in range(1, 4)]
+    got = O.extrapolate_midpoints(samples, 2)
+    assert np.abs((p(4, 3) - got) - 6.0 * M[3]).max() < 1e-11
+    with pytest.raises(ValueError):
+        O.extrapolate_midpoints(samples, 3)
+
+
+def test_polynomial_start_one_evaluation_same_fixed_point():
+    """Starting each step from the cubic extrapolation of the previous midpoints: after the
+    start-up (W_n, linear, then degrees 1 and 2) a step needs one evaluation at tol = 1e-12,
+    the residuals stay below it, and the trajectory agrees with the W_n-started one to the
+    tolerance."""
+    W = O.assemble(256, omega_coeffs(256, 0, "inv1.5"))
+    Wa, ia, ra = O.isomp_run(W, 0.005, 24, 1e-12, 50)
+    Wb, ib, rb = O.isomp_run(W, 0.005, 24, 1e-12, 50, extrapolate=True, degree=3)
+    assert ib[0] == ia[0] and all(k == 1 for k in ib[4:]), ib
+    assert max(rb) < 1e-12
+    assert np.linalg.norm(Wa - Wb) < 1e-12 * np.linalg.norm(Wa)
+    with pytest.raises(ValueError):
+        O.isomp_run(W, 0.005, 1, degree=4)
