@@ -88,7 +88,9 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  * the implicit W~ found by the fixed-point iteration eq. (isomp_iter) from W~ = W_n.  Each
  * evaluation is one stream solve, A = P W~, and the lower triangle of Q = A P, the
  * commutator being A - A^H (Sec. 3.1).  It stops once the matrix infinity norm of the change
- * of W~ is below tol, and W_{n+1} = W~ + h/2 (A - A^H) - h^2/4 Q from that same evaluation.
+ * of W~ is below tol, and W_{n+1} = W_n + h (A - A^H) from that same evaluation (the two lines
+ * of eq. (isomp) differ by exactly h [P~, W~]; in this form the residual left at the stop moves
+ * the spectrum only by O(h ||P|| tol)).
  *   W       device, N x N complex128, skew-Hermitian; in: W_n, out: W_{n+1}.
  *   h       time step (any finite sign).
  *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
@@ -121,7 +123,14 @@ ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, in
  *           approximates W half a step ahead, so this linear extrapolation is second-order
  *           accurate and usually saves one evaluation per step; the iteration still runs
  *           to the same tolerance and reaches the same fixed point.
- * Errors: ZE_EINVAL.
+ *   mode 2  (order 2 only) the converged midpoints of one run are equally spaced samples of
+ *           a smooth curve: the second step starts as in mode 1, the k-th (k >= 3) from the
+ *           polynomial of degree min(k - 2, 3) through the last min(k - 1, 4) midpoints,
+ *           one step ahead (c = (2, -1), (3, -3, 1), (4, -6, 4, -1), newest first).  Its error
+ *           is O(h^4), usually below tol, so after the start-up a step takes one evaluation.
+ *           Selecting it allocates three more N x N complex buffers (kept until ze_destroy).
+ * Every mode restarts at the first step of each ze_isomp_run call.
+ * Errors: ZE_EINVAL (also mode 2 while ze_set_order is 4 or 6), ZE_ENOMEM.
  */
 ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
 
@@ -137,7 +146,7 @@ ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
  * (9 substeps).  With ze_set_initial_guess mode 1 every substep after the first of a call
  * starts from W + rho (W - F_prev), rho the ratio of its step to the previous substep's (also
  * inside a single ze_isomp_step).  The ensemble entry points always step at order 2.
- * Errors: ZE_EINVAL for any other order.
+ * Errors: ZE_EINVAL for any other order, and for 4 or 6 while ze_set_initial_guess is 2.
  */
 ze_status ze_set_order(ze_ctx* ctx, int order);
 

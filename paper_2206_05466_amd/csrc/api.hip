@@ -101,7 +101,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->fac_l);
     dfree(c->fac_dinv);
     dfree(c->Wn);
-    dfree(c->F);
+    for (int i = 0; i < 4; ++i) dfree(c->Fring[i]);  // Fring[0] is the F allocation
     dfree(c->P);
     dfree(c->A);
     dfree(c->Q);
@@ -160,6 +160,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
     if (st == ZE_OK) st = dalloc(&c->Wn, nn);
     if (st == ZE_OK) st = dalloc(&c->F, nn);
+    c->Fring[0] = c->F;
     if (st == ZE_OK) st = dalloc(&c->P, nn);
     if (st == ZE_OK) st = dalloc(&c->A, nn);
     if (st == ZE_OK) st = dalloc(&c->Q, nn);
@@ -218,11 +219,13 @@ ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
 
 namespace {
 
-// One midpoint step of size h; with `extrapolate` the fixed point starts from W_n + rho (W_n - F)
-// (F = the previous step's converged midpoint, still in c->F; rho = 1 gives 2 W_n - F) instead
-// of W_n.
+enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
+
+// One midpoint step of size h.  The fixed point starts from W_n (kFromWn), from
+// W_n + rho (W_n - F) written over F (kLinear; F = the previous step's converged midpoint, still
+// in c->F; rho = 1 gives 2 W_n - F), or from the iterate the caller has put in c->F (kFromF).
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                          bool extrapolate, double rho, int* iters, double* resid) {
+                          StartFrom start, double rho, int* iters, double* resid) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
     const int N = c->N;
@@ -233,10 +236,8 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
-    if (extrapolate) {
-        ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
-        Wt = c->F;
-    }
+    if (start == kLinear) ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
+    if (start != kFromWn) Wt = c->F;
     double r = 0.0;
     int k = 0;
     const bool prof = c->prof;
@@ -303,7 +304,8 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
         const double rho = w[j] / w[j == 0 ? ns - 1 : j - 1];
         int k = 0;
         double r = 0.0;
-        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, ex, rho, &k, &r);
+        const ze_status st =
+            isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, ex ? kLinear : kFromWn, rho, &k, &r);
         total += k;
         if (!(r <= rmax)) rmax = r;  // keeps a NaN
         if (st == ZE_ENOTCONV) {
@@ -320,6 +322,32 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     return out;
 }
 
+// Mode 2 (order 2 only): the start of the step after `nmid` earlier steps of this run is put
+// in the next ring slot, which then becomes F: 2 W_n - F_1 after one step, else the polynomial
+// of degree min(nmid - 1, 3) through the midpoints F_1 (newest) .. F_{d+1}.  With four
+// midpoints the next slot is F_4's, overwritten in place.
+ze_status poly_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec, int nmid,
+                    int* iters, double* resid) {
+    if (!c || !W) return ZE_EINVAL;
+    if (nmid == 0) return isomp_step_impl(c, W, h, tol, maxit, prec, kFromWn, 1.0, iters, resid);
+    const int N = c->N;
+    const int next = (c->fhead + 1) & 3;
+    double2* out = c->Fring[next];
+    if (nmid == 1) {
+        ZE_HIP(hipMemcpyAsync(out, c->F, (size_t)N * N * sizeof(double2), hipMemcpyDeviceToDevice,
+                              c->stream));
+        ZE_HIP(launch_extrapolate(static_cast<const double2*>(W), out, N, 1.0, c->stream));
+    } else {
+        const int d = nmid - 1 < 3 ? nmid - 1 : 3;
+        const double2* Fs[4];
+        for (int j = 0; j <= d; ++j) Fs[j] = c->Fring[(c->fhead - j + 4) & 3];
+        ZE_HIP(launch_extrapolate_poly(Fs, d, out, N, c->stream));
+    }
+    c->fhead = next;
+    c->F = out;
+    return isomp_step_impl(c, W, h, tol, maxit, prec, kFromF, 1.0, iters, resid);
+}
+
 }  // namespace
 
 ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
@@ -334,7 +362,8 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = composed_step(c, W, h, tol, maxit, prec, n > 0, &k, &r);
+        ze_status st = c->guess_mode == 2 ? poly_step(c, W, h, tol, maxit, prec, n < 4 ? n : 4, &k, &r)
+                                          : composed_step(c, W, h, tol, maxit, prec, n > 0, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) return st;
@@ -421,13 +450,20 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 }
 
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
-    if (!c || mode < 0 || mode > 1) return ZE_EINVAL;
+    if (!c || mode < 0 || mode > 2) return ZE_EINVAL;
+    if (mode == 2) {
+        if (c->order != 2) return ZE_EINVAL;
+        const size_t nn = (size_t)c->N * c->N;
+        for (int i = 1; i < 4; ++i)
+            if (!c->Fring[i]) ZE_TRY(dalloc(&c->Fring[i], nn));
+    }
     c->guess_mode = mode;
     return ZE_OK;
 }
 
 ze_status ze_set_order(ze_ctx* c, int order) {
     if (!c || (order != 2 && order != 4 && order != 6)) return ZE_EINVAL;
+    if (order != 2 && c->guess_mode == 2) return ZE_EINVAL;
     // Triple jump (Yoshida 1990): from a symmetric method of even order p, the substeps
     // g1, g2, g1 with g1 = 1 / (2 - 2^(1/(p+1))) and g2 = 1 - 2 g1 give order p + 2.
     std::vector<double> w{1.0};

@@ -70,8 +70,13 @@ struct ze_ctx {
     int cap_i8 = 0;          // blocks of the INT8 product kernel that fit on the device at once
 
     // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
-    // (F = the previous step's converged midpoint, left in ze_ctx::F).
+    // (F = the previous step's converged midpoint, left in ze_ctx::F), 2 = the polynomial
+    // extrapolation of the last (up to 4) midpoints of the run.
     int guess_mode = 0;
+    // Midpoint history of mode 2: a ring of 4 buffers (Fring[0] is the allocation F starts
+    // with; the others are allocated when mode 2 is first selected), F == Fring[fhead].
+    double2* Fring[4] = {nullptr, nullptr, nullptr, nullptr};
+    int fhead = 0;
     // Order of the time step (2: the midpoint map; 4, 6: its symmetric compositions) and the
     // substep fractions c_j of one step.
     int order = 2;
@@ -183,3 +188,7 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, hipStream_t s);
+// out = polynomial extrapolation of degree d (1..3) through Fs[0] (newest) .. Fs[d], one step
+// ahead; out may be Fs[d].
+hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out, int N,
+                                   hipStream_t s);

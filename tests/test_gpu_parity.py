@@ -179,7 +179,7 @@ def test_isomp_fixed_iterations_and_errors(dev):
         with pytest.raises(ZeulerError, match="non-finite"):
             z.isomp_step(bad, 0.1, 1e-12, 5)
         with pytest.raises(ZeulerError):
-            z.set_initial_guess(2)
+            z.set_initial_guess(3)
         with pytest.raises(ZeulerError):
             z.set_split_slices(1)
         lib = z.lib
@@ -588,3 +588,51 @@ def test_isomp_composed_split_and_fixed_iterations(dev):
     assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
     assert not info.converged and info.iters == itf[0] == 6
     assert np.linalg.norm(Wx - Wf) <= 1e-12 * np.linalg.norm(Wf)
+
+
+# ------------------------------------------------------------------ polynomial starting iterates
+@pytest.mark.parametrize("N,law,h,steps", [(64, "inv1", 0.01, 12), (130, "inv1.5", 0.005, 10),
+                                           (256, "inv1.5", 0.005, 9)])
+def test_isomp_run_polynomial_guess(dev, N, law, h, steps):
+    """Mode 2 (cubic extrapolation of the run's midpoints): the same evaluation counts per step
+    as the oracle's run (one evaluation after the start-up) and the same W to 1e-12; a second
+    run call restarts the history (its first step starts from W_n again)."""
+    W0 = w0(N, 4, law)
+    Wr, it_ref, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3)
+    W2r, it2, _ = O.isomp_run(Wr, h, 3, 1e-12, 50, extrapolate=True, degree=3)
+    Wd = to_dev(W0)
+    with ctx(N) as z:
+        z.set_initial_guess(2)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 50)
+        W = to_host(Wd)
+        Wd = to_dev(Wr)
+        its2, _ = z.isomp_run(Wd, h, 3, 1e-12, 50)
+        W2 = to_host(Wd)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
+    assert its2 == it2 and np.linalg.norm(W2 - W2r) <= 1e-12 * np.linalg.norm(W2r)
+    assert np.abs(W + W.conj().T).max() == 0.0
+
+
+def test_isomp_polynomial_guess_split_and_mode_errors(dev):
+    """Mode 2 with the split-precision products (5 slices) against the oracle's FP64 run (1e-10);
+    mode 2 and orders 4 / 6 exclude each other."""
+    from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
+
+    N, h = 128, 0.005
+    W0 = w0(N, 0)
+    Wr, _, _ = O.isomp_run(W0, h, 10, 1e-12, 50, extrapolate=True, degree=3)
+    with ctx(N) as z:
+        z.set_split_slices(5)
+        z.set_initial_guess(2)
+        Wd = to_dev(W0)
+        its, res = z.isomp_run(Wd, h, 10, 1e-12, 50, prec=PREC_SPLIT)
+        W = to_host(Wd)
+        with pytest.raises(ZeulerError):
+            z.set_order(4)
+        z.set_initial_guess(0)
+        z.set_order(6)
+        with pytest.raises(ZeulerError):
+            z.set_initial_guess(2)
+    assert max(res) < 1e-12 and its[-1] == 1, its
+    assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
