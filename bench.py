@@ -185,7 +185,7 @@ def small_leg(steps):
     N, h, tol = cfg["N"], cfg["h"], cfg["tol"]
     z = Zeuler(N)
     W0 = z.basis_assemble(omega_coeffs(N, cfg["seeds"][0], cfg["law"]))
-    z.set_initial_guess(1)
+    z.set_initial_guess(2)
     W = W0.clone()
     z.isomp_run(W, h, 2, tol, cfg["maxit"])
     W = W0.clone()
@@ -211,13 +211,15 @@ def small_leg(steps):
         "iters_per_step": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
         "graph_ensemble_of_one_s_per_step": dtg / steps,
         "rel_frobenius_between_the_two": diff,
-        "note": "both forms start the steps after the first from 2 W_n - F_prev",
+        "note": "the single context starts the steps after the first from the polynomial "
+                "extrapolation of the run's midpoints (mode 2), the graph ensemble from "
+                "2 W_n - F_prev (mode 1)",
     }
 
 
 def long_leg(steps):
     """Workload long512: the paper's long-run initial condition (random degrees 2..20, unit
-    spectral norm, Sec. 4) at N = 512, `steps` steps with the extrapolated start.  Every
+    spectral norm, Sec. 4) at N = 512, `steps` steps with the polynomial start.  Every
     `sample` steps: the Casimirs C_2..C_5 and the kinetic energy (sum of E_l from the basis
     extraction); at the end the energy spectrum's share above degree 20 and its log-log
     slope over 21 <= l <= 200."""
@@ -232,7 +234,7 @@ def long_leg(steps):
     z = Zeuler(N)
     W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
     W /= float(np.linalg.norm(W.cpu().numpy(), 2))  # input recipe: unit spectral norm
-    z.set_initial_guess(1)
+    z.set_initial_guess(2)
     nf0 = float(torch.linalg.norm(W).item())
 
     def diag():
@@ -241,7 +243,7 @@ def long_leg(steps):
         return c, E
 
     c0, E0 = diag()
-    rows, t_run, it_max, res_max = [], 0.0, 0, 0.0
+    rows, t_run, it_max, res_max, it_sum = [], 0.0, 0, 0.0, 0
     done = 0
     while done < steps:
         k = min(sample, steps - done)
@@ -251,6 +253,7 @@ def long_leg(steps):
         torch.cuda.synchronize()
         t_run += time.perf_counter() - t0
         it_max = max(it_max, max(its))
+        it_sum += sum(its)
         res_max = max(res_max, max(res))
         done += k
         c, E = diag()
@@ -263,24 +266,26 @@ def long_leg(steps):
     l = np.arange(N)
     sel = (l >= 21) & (l <= 200) & (E > 0)
     slope = float(np.polyfit(np.log(l[sel]), np.log(E[sel]), 1)[0]) if sel.sum() > 2 else None
-    # the same run from W_n at every step (3 evaluations: the last iterate much closer to the
-    # fixed point), drift at the end only
-    W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
-    W /= float(np.linalg.norm(W.cpu().numpy(), 2))
-    z.set_initial_guess(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its0, res0 = z.isomp_run(W, h, steps, tol, cfg["maxit"])
-    torch.cuda.synchronize()
-    t_wn = time.perf_counter() - t0
-    c, _ = diag()
-    wn = {"s_per_step": t_wn / steps, "mean_iters_per_step": sum(its0) / len(its0),
-          "max_resid": max(res0), "C2_rel": abs(c[1] - c0[1]) / abs(c0[1]),
-          "C4_rel": abs(c[3] - c0[3]) / abs(c0[3])}
+    # the same run from W_n at every step and from the linear start, drift at the end only
+    other = {}
+    for name, mode in (("start_from_Wn_every_step", 0), ("linear_start", 1)):
+        W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
+        W /= float(np.linalg.norm(W.cpu().numpy(), 2))
+        z.set_initial_guess(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its0, res0 = z.isomp_run(W, h, steps, tol, cfg["maxit"])
+        torch.cuda.synchronize()
+        t_o = time.perf_counter() - t0
+        c, _ = diag()
+        other[name] = {"s_per_step": t_o / steps, "mean_iters_per_step": sum(its0) / len(its0),
+                       "max_resid": max(res0), "C2_rel": abs(c[1] - c0[1]) / abs(c0[1]),
+                       "C4_rel": abs(c[3] - c0[3]) / abs(c0[3])}
     z.close()
     return {
         "workload": f"long512: N={N}, sigma_l law paper (degrees 2..20, seed {cfg['seed']}), "
-                    f"unit spectral norm, h={h}, tol={tol}, {steps} steps, extrapolated start",
+                    f"unit spectral norm, h={h}, tol={tol}, {steps} steps, polynomial start "
+                    f"(restarted every {sample} steps, at each sample)",
         "s_per_step": t_run / steps,
         "max_iters_per_step": it_max,
         "max_resid": res_max,
@@ -288,7 +293,9 @@ def long_leg(steps):
         "energy_share_above_l20": {"start": float(E0[21:].sum() / E0.sum()),
                                    "end": float(E[21:].sum() / E.sum())},
         "end_spectrum_loglog_slope_l21_200": slope,
-        "start_from_Wn_every_step": wn,
+        "mean_iters_per_step": it_sum / steps,
+        "start_from_Wn_every_step": other["start_from_Wn_every_step"],
+        "linear_start": other["linear_start"],
         "note": "Casimirs by ze_casimirs, energy by ze_basis_extract + ze_energy_spectrum, "
                 "sampled between timed chunks (not in s_per_step)",
     }
@@ -350,8 +357,9 @@ def casimir_drift(c0, c1, W):
 
 
 def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
-    """One simulation of workload wname: FP64 (start from W_n, then the extrapolated start) and
-    the split-precision runs, each over `steps` timed steps of ze_isomp_run from the same W0."""
+    """One simulation of workload wname: FP64 (start from W_n, the linear start, then the
+    polynomial start of the headline) and the split-precision runs (polynomial start), each over
+    `steps` timed steps of one ze_isomp_run call from the same W0."""
     import torch
 
     from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
@@ -390,11 +398,17 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
     Wp = W0.clone()
     dt_plain, iters_plain, _, _ = timed_run(Wp, PREC_FP64, 0)
     log(f"{wname} fp64, start W_n: {dt_plain / steps * 1e3:.2f} ms/step, iters={iters_plain}")
-    # headline: steps after the first start from 2 W_n - F_prev
-    dt, iters, resids, prof = timed_run(W, PREC_FP64, 1)
-    log(f"{wname} fp64, extrapolated start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
+    # steps after the first start from 2 W_n - F_prev
+    Wl = W0.clone()
+    dt_lin, iters_lin, _, _ = timed_run(Wl, PREC_FP64, 1)
+    log(f"{wname} fp64, linear start: {dt_lin / steps * 1e3:.2f} ms/step, iters={iters_lin}")
+    # headline: polynomial extrapolation of the run's previous midpoints
+    dt, iters, resids, prof = timed_run(W, PREC_FP64, 2)
+    log(f"{wname} fp64, polynomial start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
     c1 = z.casimirs(W, 4)
     plain_vs_extrap = float(torch.linalg.norm(Wp - W).item() / torch.linalg.norm(W).item())
+    lin_vs_extrap = float(torch.linalg.norm(Wl - W).item() / torch.linalg.norm(W).item())
+    del Wl
     if copy_probe_mib > 0:
         n = copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -410,7 +424,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
         for ns in slist:
             z.set_split_slices(ns)
             Ws = W0.clone()
-            dts, its_s, _, profs = timed_run(Ws, PREC_SPLIT, 1)
+            dts, its_s, _, profs = timed_run(Ws, PREC_SPLIT, 2)
             cs = z.casimirs(Ws, 4)
             diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
             sps = dts / steps
@@ -448,6 +462,8 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
         "prof": prof, "casimir_drift_rel": casimir_drift(c0, c1, W),
         "fp64_start_from_Wn": {"s_per_step": dt_plain / steps, "iters_per_step": list(iters_plain),
                                "rel_frobenius_vs_headline_run": plain_vs_extrap},
+        "fp64_linear_start": {"s_per_step": dt_lin / steps, "iters_per_step": list(iters_lin),
+                              "rel_frobenius_vs_headline_run": lin_vs_extrap},
         "split_precision": split,
     }
 
@@ -459,7 +475,7 @@ def phases_of(prof):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -569,9 +585,11 @@ def main():
         },
         "iters_per_step": iters,
         "max_resid": m["max_resid"],
-        "initial_guess": "steps after the first start from 2 W_n - F_prev (ze_set_initial_guess 1); "
+        "initial_guess": "the second step starts from 2 W_n - F_prev, later ones from the polynomial "
+                         "(degree <= 3) through the run's previous midpoints (ze_set_initial_guess 2); "
                          "every step still iterates until the change is below tol",
         "fp64_start_from_Wn": m["fp64_start_from_Wn"],
+        "fp64_linear_start": m["fp64_linear_start"],
         "casimir_drift_rel": m["casimir_drift_rel"],
         "phases": phases_of(prof),
         "gemm_flops_per_step": sum(iters) / len(iters) * 12.0 * N ** 3,
