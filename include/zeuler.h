@@ -297,9 +297,13 @@ ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
  * the ensemble's steps, as ze_set_initial_guess for one simulation: 0 (default) W_n at every
  * step; 1: in ze_ensemble_run, every step after the first of the call starts each simulation
  * from 2 W_n - F_prev (its previous step's converged midpoint), which saves about one
- * evaluation per step at the same stopping rule.  Takes effect at the next ze_ensemble_run
- * (the step graphs are captured again).
- * Errors: ZE_EINVAL (mode not 0 or 1).
+ * evaluation per step at the same stopping rule; 2: the polynomial start of
+ * ze_set_initial_guess mode 2 per simulation (linear at the second step of the call, then
+ * degrees 1, 2, 3 through its previous midpoints), one evaluation per step after the
+ * start-up; one captured graph reads the step's index in the call from device memory.
+ * Selecting mode 2 allocates three N_j x N_j complex buffers per simulation.  Takes effect at
+ * the next ze_ensemble_run (the step graphs are captured again).
+ * Errors: ZE_EINVAL (mode not 0, 1 or 2), ZE_ENOMEM.
  */
 ze_status ze_ensemble_set_initial_guess(ze_ens* ens, int mode);
 

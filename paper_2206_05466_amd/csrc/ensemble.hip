@@ -46,31 +46,70 @@ struct EnsProb {
     int* ep;
     int* ew;
     int* eA;
+    // earlier midpoints of the run for starting-iterate mode 2 (F_{n-2}, F_{n-3}, F_{n-4});
+    // null until that mode is selected
+    double2* H1;
+    double2* H2;
+    double2* H3;
 };
 
 constexpr int kCopyParts = 16;
 
-// Start of a step: W_n <- W and the first iterate F <- W_n, or with `extrap` F <- 2 W_n - F,
-// the linear extrapolation of the previous step's converged midpoint (still in F).  Every
-// evaluation then reads its iterate from F (the update rewrites it in place: each entry it
-// reads is written by the same thread, and the mirrored upper entries it writes are read by
+// Start of a step: W_n <- W and the first iterate F.  mode 0: F <- W_n; mode 1: F <- 2 W_n - F,
+// the linear extrapolation of the previous step's converged midpoint (still in F); mode 2: by
+// the step's index n in the run (*stepc): W_n at n = 0, the linear start at n = 1, else the
+// polynomial of degree d = min(n - 1, 3) through F (newest midpoint), H1, H2, H3 one step ahead
+// (coefficients (2, -1), (3, -3, 1), (4, -6, 4, -1), summed in that order), while the history
+// moves down one place (H3 <- H2, H2 <- H1, H1 <- F; entries not yet written are never read).
+// Every evaluation then reads its iterate from F (the update rewrites it in place: each entry
+// it reads is written by the same thread, and the mirrored upper entries it writes are read by
 // no other block of that launch).
 __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restrict__ probs,
-                                                        int* __restrict__ done, int extrap) {
+                                                        int* __restrict__ done, int mode,
+                                                        const int* __restrict__ stepc) {
     const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
     const EnsProb p = probs[sim];
     const size_t n2 = (size_t)p.N * p.N;
+    const int n = mode == 2 ? stepc[0] : (mode == 1 ? 1 : 0);
+    const int d = n - 1 < 3 ? n - 1 : 3;  // polynomial degree for n >= 2
+    const double c1 = d + 1.0;
+    const double c2 = d == 1 ? -1.0 : (d == 2 ? -3.0 : -6.0);
+    const double c3 = d == 2 ? 1.0 : 4.0;
     for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
         const double2 w = p.W[e];
         p.Wn[e] = w;
-        if (extrap) {
-            const double2 f = p.F[e];
-            p.F[e] = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
-        } else {
+        if (n == 0) {
             p.F[e] = w;
+            continue;
         }
+        const double2 f = p.F[e];
+        double2 g;
+        if (n == 1) {
+            g = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
+        } else {
+            const double2 h1 = p.H1[e];
+            g = make_double2(c1 * f.x, c1 * f.y);
+            g = make_double2(g.x + c2 * h1.x, g.y + c2 * h1.y);
+            if (n >= 3) {
+                const double2 h2 = p.H2[e];
+                g = make_double2(g.x + c3 * h2.x, g.y + c3 * h2.y);
+                if (n >= 4) {
+                    const double2 h3 = p.H3[e];
+                    g = make_double2(g.x - h3.x, g.y - h3.y);
+                }
+                p.H3[e] = h2;
+            }
+            p.H2[e] = h1;
+        }
+        if (mode == 2) p.H1[e] = f;
+        p.F[e] = g;
     }
     if (part == 0 && threadIdx.x == 0) done[sim] = 0;
+}
+
+// Step index of mode 2: set before the first step of a run, advanced at the end of each step.
+__global__ __launch_bounds__(64) void ens_stepc_kernel(int* __restrict__ stepc, int set) {
+    if (threadIdx.x == 0) stepc[0] = set >= 0 ? set : stepc[0] + 1;
 }
 
 template <int T, int C, int BD>
@@ -351,8 +390,10 @@ struct ze_ens {
     // captured graph and the parameters it was captured with
     hipGraphExec_t exec = nullptr;
     int g_prec = -1, g_variant = -1, g_order = -1, g_K = -1, g_slices = -1, g_guess = -1;
-    // first iterate of the steps after the first of a run: 0 = W_n, 1 = 2 W_n - F_prev
+    // first iterate of the steps after the first of a run: 0 = W_n, 1 = 2 W_n - F_prev,
+    // 2 = polynomial extrapolation of the run's midpoints (the step index in *stepc)
     int guess_mode = 0;
+    int* stepc = nullptr;
     hipGraphExec_t exec_x = nullptr;  // the step graph with the extrapolated first iterate
     double g_h = 0.0, g_tol = -1.0;
 };
@@ -360,9 +401,9 @@ struct ze_ens {
 namespace {
 
 hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
-                       bool extrap, hipStream_t s) {
+                       int mode, hipStream_t s) {
     hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done,
-                       extrap ? 1 : 0);
+                       mode, e->stepc);
     hipError_t err = hipGetLastError();
     const int ns = e->slices;
 #define ZE_ENS_LAUNCH(...)                       \
@@ -406,12 +447,14 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
                       e->resid, k, tol);
     }
+    if (err == hipSuccess && mode == 2)
+        ZE_ENS_LAUNCH(ens_stepc_kernel, dim3(1), dim3(64), 0, s, e->stepc, -1);
 #undef ZE_ENS_LAUNCH
     return err;
 }
 
 hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
-                       bool extrap, hipGraphExec_t* out) {
+                       int mode, hipGraphExec_t* out) {
     if (*out) {
         (void)hipGraphExecDestroy(*out);
         *out = nullptr;
@@ -419,7 +462,7 @@ hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int var
     hipGraph_t g = nullptr;
     hipError_t err = hipStreamBeginCapture(e->own, hipStreamCaptureModeRelaxed);
     if (err != hipSuccess) return err;
-    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, extrap, e->own);
+    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, mode, e->own);
     err = hipStreamEndCapture(e->own, &g);
     if (rec != hipSuccess) err = rec;
     if (err == hipSuccess) err = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -427,12 +470,13 @@ hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int var
     return err;
 }
 
-// The step graph (first iterate W_n) and, with guess mode 1, the graph of the steps after the
-// first of a run (first iterate 2 W_n - F_prev).
+// The step graph (first iterate W_n, or with guess mode 2 chosen by the step index) and, with
+// guess mode 1, the graph of the steps after the first of a run (first iterate 2 W_n - F_prev).
 hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant, int order) {
-    hipError_t err = capture_one(e, h, tol, K, prec, variant, order, false, &e->exec);
+    hipError_t err =
+        capture_one(e, h, tol, K, prec, variant, order, e->guess_mode == 2 ? 2 : 0, &e->exec);
     if (err == hipSuccess && e->guess_mode == 1)
-        err = capture_one(e, h, tol, K, prec, variant, order, true, &e->exec_x);
+        err = capture_one(e, h, tol, K, prec, variant, order, 1, &e->exec_x);
     if (err == hipSuccess) {
         e->g_guess = e->guess_mode;
         e->g_prec = prec;
@@ -497,7 +541,7 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
         const int variant = split ? 0 : cand >> 1, order = split ? cand : cand & 1;
         st = set_pointers(e, reinterpret_cast<void* const*>(copies.data()));
         if (st != ZE_OK) break;
-        if (capture_one(e, h, tol, K, prec, variant, order, false, &e->exec) != hipSuccess) {
+        if (capture_one(e, h, tol, K, prec, variant, order, 0, &e->exec) != hipSuccess) {
             st = ze_record_hip(hipGetLastError(), "ensemble autotune capture");
             break;
         }
@@ -572,6 +616,7 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
     (void)hipFree(e->done);
     (void)hipFree(e->iters);
     (void)hipFree(e->resid);
+    (void)hipFree(e->stepc);
     (void)hipFree(e->work_solve);
     for (auto& v : e->work_prod)
         for (int2* p : v) (void)hipFree(p);
@@ -615,12 +660,13 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         ze_ctx* c = e->ctx[i];
         e->hp[i] = EnsProb{c->N,        0,          nullptr, c->Wn,   c->F,    c->P,    c->A,
                            c->Q,        c->rowpart, c->fac_l, c->fac_dinv, nullptr, nullptr, nullptr,
-                           nullptr,     nullptr,    nullptr};
+                           nullptr,     nullptr,    nullptr, nullptr, nullptr, nullptr};
     }
     if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->iters, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->resid, (size_t)nsim)) != ZE_OK) return fail(st);
+    if ((st = ens_alloc(&e->stepc, (size_t)1)) != ZE_OK) return fail(st);
     std::vector<int> cs(nsim), c0(nsim), c1(nsim), cl(nsim);
     std::vector<int> r0(nsim), r1(nsim), ccol(nsim), ccomb(nsim), i8f(nsim), i8l(nsim);
     for (int i = 0; i < nsim; ++i) {
@@ -699,6 +745,10 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
         e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices ||
         e->g_guess != e->guess_mode)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
+    if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
+        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0);
+        ZE_HIP(hipGetLastError());
+    }
     for (int n = 0; n < nsteps; ++n)
         ZE_HIP(hipGraphLaunch(n > 0 && e->guess_mode == 1 ? e->exec_x : e->exec, e->own));
     ZE_HIP(hipEventRecord(e->ev_out, e->own));
@@ -733,7 +783,22 @@ ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
 }
 
 ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
-    if (!e || mode < 0 || mode > 1) return ZE_EINVAL;
+    if (!e || mode < 0 || mode > 2) return ZE_EINVAL;
+    if (mode == 2 && !e->hp[0].H1) {  // history buffers, 3 per simulation
+        ZE_HIP(hipStreamSynchronize(e->own));
+        for (int i = 0; i < e->nsim; ++i) {
+            ze_ctx* c = e->ctx[i];
+            const size_t nn = (size_t)c->N * c->N;
+            for (int j = 1; j < 4; ++j)
+                if (!c->Fring[j]) ZE_TRY(ens_alloc(&c->Fring[j], nn));
+        }
+        for (int i = 0; i < e->nsim; ++i) {
+            e->hp[i].H1 = e->ctx[i]->Fring[1];
+            e->hp[i].H2 = e->ctx[i]->Fring[2];
+            e->hp[i].H3 = e->ctx[i]->Fring[3];
+        }
+        ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
+    }
     e->guess_mode = mode;
     return ZE_OK;
 }

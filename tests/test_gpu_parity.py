@@ -636,3 +636,41 @@ def test_isomp_polynomial_guess_split_and_mode_errors(dev):
             z.set_initial_guess(2)
     assert max(res) < 1e-12 and its[-1] == 1, its
     assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "split"])
+def test_ensemble_polynomial_guess(dev, prec_name):
+    """Guess mode 2 in the ensemble (one graph; the step index of the run read on the device):
+    after 7 steps every simulation matches the oracle's run with the polynomial start (FP64:
+    1e-12 and the same evaluation count on the last step; split, 5 slices: 1e-10), and a
+    second run call starts its history again (its first step from W_n)."""
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Ensemble
+
+    sizes = [64, 40, 96, 130]
+    h, tol, K, steps = 0.005, 1e-12, 8, 7
+    split = prec_name == "split"
+    W0s = [w0(n, 70 + j) for j, n in enumerate(sizes)]
+    refs = [O.isomp_run(W, h, steps, tol, K, extrapolate=True, degree=3) for W in W0s]
+    refs2 = [O.isomp_run(r[0], h, 2, tol, K, extrapolate=True, degree=3) for r in refs]
+    Wd = [to_dev(W) for W in W0s]
+    with Ensemble(sizes) as ens:
+        if split:
+            ens.set_split_slices(5)
+        ens.set_initial_guess(2)
+        prec = PREC_SPLIT if split else PREC_FP64
+        ens.run(Wd, h, steps, tol, K, prec=prec)
+        its, res = ens.stats()
+        got = [to_host(W) for W in Wd]
+        Wd2 = [to_dev(r[0]) for r in refs]
+        ens.run(Wd2, h, 2, tol, K, prec=prec)
+        its2, _ = ens.stats()
+        got2 = [to_host(W) for W in Wd2]
+    bar = 1e-10 if split else 1e-12
+    for j in range(len(sizes)):
+        Wr, itr, _ = refs[j]
+        W2r, itr2, _ = refs2[j]
+        assert res[j] < tol
+        if not split:
+            assert its[j] == itr[-1] and its2[j] == itr2[-1], (j, its[j], itr, its2[j], itr2)
+        assert np.linalg.norm(got[j] - Wr) <= bar * np.linalg.norm(Wr), j
+        assert np.linalg.norm(got2[j] - W2r) <= bar * np.linalg.norm(W2r), j
