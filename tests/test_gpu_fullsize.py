@@ -52,20 +52,21 @@ def test_n4096_steps_fp64_and_split(dev):
     from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
 
     cfg = WORKLOADS["n4096"]
-    N, h, L = cfg["N"], cfg["h"], 32
+    N, h, L, steps = cfg["N"], cfg["h"], 32, 5
     W0 = O.assemble(N, omega_coeffs(N, 0, cfg["law"], lmax=L), lmax=L)
-    Wr, it_ref, _ = O.isomp_run(W0, h, 2, cfg["tol"], cfg["maxit"], extrapolate=True)
+    # the polynomial start of the timed runs: steps 3..5 use degrees 1, 2, 3
+    Wr, it_ref, _ = O.isomp_run(W0, h, steps, cfg["tol"], cfg["maxit"], extrapolate=True, degree=3)
     z = Zeuler(N)
-    z.set_initial_guess(1)
+    z.set_initial_guess(2)
     Wd = to_dev(W0)
-    its, res = z.isomp_run(Wd, h, 2, cfg["tol"], cfg["maxit"], PREC_FP64)
+    its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_FP64)
     W = to_host(Wd)
     assert its == it_ref and max(res) < cfg["tol"], (its, it_ref)
     assert rel(W, Wr) < 1e-12, rel(W, Wr)
     assert np.abs(W + W.conj().T).max() == 0.0
     z.set_split_slices(5)
     Wd = to_dev(W0)
-    its, res = z.isomp_run(Wd, h, 2, cfg["tol"], cfg["maxit"], PREC_SPLIT)
+    its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_SPLIT)
     W = to_host(Wd)
     assert its == it_ref and rel(W, Wr) < 1e-10, (its, rel(W, Wr))
     z.close()
@@ -132,9 +133,10 @@ def test_n2048_twenty_steps(dev):
     cfg = WORKLOADS["n2048"]
     N, h, L = cfg["N"], cfg["h"], 48
     W0 = O.assemble(N, omega_coeffs(N, 0, cfg["law"], lmax=L), lmax=L)
-    Wr, it_ref, _ = O.isomp_run(W0, h, cfg["steps"], cfg["tol"], cfg["maxit"], extrapolate=True)
+    Wr, it_ref, _ = O.isomp_run(W0, h, cfg["steps"], cfg["tol"], cfg["maxit"], extrapolate=True,
+                                degree=3)
     z = Zeuler(N)
-    z.set_initial_guess(1)
+    z.set_initial_guess(2)
     Wd = to_dev(W0)
     its, res = z.isomp_run(Wd, h, cfg["steps"], cfg["tol"], cfg["maxit"])
     W = to_host(Wd)
@@ -163,13 +165,14 @@ def test_n512_hundred_steps(dev):
 
 @pytest.mark.parametrize("prec_name", ["fp64", "split"])
 def test_ensemble64_sampled_members(dev, prec_name):
-    """The full 64-simulation ensemble (bench.py's leg, FP64 and split with 5 slices) for 5
-    steps; one member of each size class is checked against the oracle."""
+    """The full 64-simulation ensemble (bench.py's leg: polynomial start; FP64, and split with 5
+    slices) for 6 steps, so the cubic start is reached; one member of each size class is checked
+    against the oracle's run with the same start."""
     from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Ensemble, Zeuler
 
     cfg = WORKLOADS["ensemble64"]
     sizes = ensemble_sizes(cfg["nsim"], cfg["size_seed"], cfg["sizes"])
-    h, tol, K, steps = cfg["h"], 1e-12, 8, 5
+    h, tol, K, steps = cfg["h"], 1e-12, 8, 6
     picks = [sizes.index(n) for n in sorted(set(sizes))]
     # checked members start from the oracle's own assembly; the others from the GPU basis
     W0s = {j: O.assemble(sizes[j], omega_coeffs(sizes[j], cfg["seed0"] + j, cfg["law"])) for j in picks}
@@ -182,12 +185,13 @@ def test_ensemble64_sampled_members(dev, prec_name):
     with Ensemble(sizes) as ens:
         if split:
             ens.set_split_slices(5)
+        ens.set_initial_guess(2)
         ens.run(Ws, h, steps, tol, K, prec=PREC_SPLIT if split else PREC_FP64)
         its, res = ens.stats()
     assert max(res) < tol
     bar = 1e-10 if split else 1e-12
     for j in picks:
-        Wr, it_ref, _ = O.isomp_run(W0s[j], h, steps, tol, K)
+        Wr, it_ref, _ = O.isomp_run(W0s[j], h, steps, tol, K, extrapolate=True, degree=3)
         if not split:
             assert its[j] == it_ref[-1]
         assert rel(to_host(Ws[j]), Wr) < bar, (j, sizes[j])
