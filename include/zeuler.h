@@ -214,10 +214,23 @@ ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec)
  * s_max(N) = min(8, floor((2^31 - 1) / (2 N 128^2))), the largest count whose int32 sums stay
  * exact (8 up to N = 4096, 7 at N = 8192, 3 at N = 16384); default min(5, s_max(N)).  The
  * first split-precision call of a context allocates its slice buffers (about 24 N^2 bytes)
- * and int32 work slabs (up to 64 N^2 bytes).
+ * and int32 work slabs (up to 64 N^2 bytes).  s applies to the product A = P W~; the lower
+ * product Q = A P takes max(2, s - 1) slices (see ze_set_split_slices_lower).
  * Errors: ZE_EINVAL (also for s > s_max(N)).
  */
 ze_status ze_set_split_slices(ze_ctx* ctx, int slices);
+
+/*
+ * ze_set_split_slices_lower -- slices s_q (2 <= s_q <= s) of the lower product Q = A P in the
+ * ZE_PREC_SPLIT step.  In the fixed-point map (eq. (isomp_iter)) Q enters F with h^2/4 and A
+ * with h/2, so at equal relative accuracy Q's rounding weighs about h ||P||_2 / 2 as much as
+ * A's.  One slice fewer (the default, s - 1) multiplies Q's relative error by 256 and keeps
+ * its share at most 128 |h| ||P||_2 of A's (0.32 at h = 0.005 for ||W||_2 = 1, since
+ * ||P||_2 <= ||W||_2 / 2); for steps with |h| ||P||_2 above ~1/128 set s_q = s.  Reset to
+ * s - 1 by ze_set_split_slices.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_set_split_slices_lower(ze_ctx* ctx, int slices);
 
 /*
  * ze_profile -- per-phase timing of ze_isomp_step, for measurement.  While on, every
@@ -287,10 +300,17 @@ ze_status ze_ensemble_tuning(ze_ens* ens, int prec, int* choice, double* ms);
 
 /*
  * ze_ensemble_set_split_slices -- slices s of the ensemble's ZE_PREC_SPLIT products
- * (2 <= s <= s_max of the largest N_j, default 5; see ze_set_split_slices).  Takes effect at
- * the next ze_ensemble_run.
+ * (2 <= s <= s_max of the largest N_j, default 5; see ze_set_split_slices; the lower product
+ * takes max(2, s - 1)).  Takes effect at the next ze_ensemble_run.
  */
 ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
+
+/*
+ * ze_ensemble_set_split_slices_lower -- slices of the ensemble's lower products Q = A P
+ * (2 <= s_q <= s; see ze_set_split_slices_lower).  Takes effect at the next ze_ensemble_run.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_ensemble_set_split_slices_lower(ze_ens* ens, int slices);
 
 /*
  * ze_ensemble_set_initial_guess -- first iterate of the fixed-point map (eq. (isomp_iter)) for

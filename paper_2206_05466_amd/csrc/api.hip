@@ -137,6 +137,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     c->N = N;
     c->solve_bd = solve_bd_ ? solve_bd_ : zk::solve_bd(N);
     c->split_slices = split_max_slices(N) < 5 ? split_max_slices(N) : 5;
+    c->split_slices_low = c->split_slices > 2 ? c->split_slices - 1 : 2;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -483,6 +484,13 @@ ze_status ze_set_order(ze_ctx* c, int order) {
 ze_status ze_set_split_slices(ze_ctx* c, int slices) {
     if (!c || slices < 2 || slices > split_max_slices(c->N)) return ZE_EINVAL;
     c->split_slices = slices;
+    c->split_slices_low = slices > 2 ? slices - 1 : 2;
+    return ZE_OK;
+}
+
+ze_status ze_set_split_slices_lower(ze_ctx* c, int slices) {
+    if (!c || slices < 2 || slices > c->split_slices) return ZE_EINVAL;
+    c->split_slices_low = slices;
     return ZE_OK;
 }
 

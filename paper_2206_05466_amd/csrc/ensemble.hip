@@ -375,6 +375,7 @@ struct ze_ens {
     int n_low = 0;
     // split-precision phases (work lists built at creation, buffers on first use)
     int slices = 5;  // min(5, split_max_slices(maxN)), set at creation
+    int slices_low = 4;  // of the lower product Q = A P (its term enters F with h^2/4)
     bool split_ready = false;
     int2* w_rows0 = nullptr;   // rows of P + column chunks of W~
     int2* w_rows1 = nullptr;   // rows of A
@@ -390,6 +391,7 @@ struct ze_ens {
     // captured graph and the parameters it was captured with
     hipGraphExec_t exec = nullptr;
     int g_prec = -1, g_variant = -1, g_order = -1, g_K = -1, g_slices = -1, g_guess = -1;
+    int g_slices_low = -1;
     // first iterate of the steps after the first of a run: 0 = W_n, 1 = 2 W_n - F_prev,
     // 2 = polynomial extrapolation of the run's midpoints (the step index in *stepc)
     int guess_mode = 0;
@@ -405,7 +407,7 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
     hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done,
                        mode, e->stepc);
     hipError_t err = hipGetLastError();
-    const int ns = e->slices;
+    const int ns = e->slices, nl = e->slices_low;
 #define ZE_ENS_LAUNCH(...)                       \
     do {                                         \
         hipLaunchKernelGGL(__VA_ARGS__);         \
@@ -425,13 +427,13 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
             ZE_ENS_LAUNCH(ens_combine_kernel, dim3(e->n_comb), dim3(kSThreads), 0, s, e->dp,
                           e->w_comb, e->done, ns);
             ZE_ENS_LAUNCH(ens_split_rows_kernel, dim3(e->n_rows1), dim3(kSThreads), 0, s, e->dp,
-                          e->w_rows1, e->done, k, 1, ns);
+                          e->w_rows1, e->done, k, 1, nl);
             ZE_ENS_LAUNCH(ens_split_cols_kernel, dim3(e->n_cols), dim3(kSThreads), 0, s, e->dp,
-                          e->w_cols, e->done, k, 1, ns);
+                          e->w_cols, e->done, k, 1, nl);
             ZE_ENS_LAUNCH(ens_i8_kernel, dim3(e->n_i8[1]), dim3(kSThreads), 0, s, e->dp,
-                          e->w_i8[1][order], e->done, 1, ns);
+                          e->w_i8[1][order], e->done, 1, nl);
             ZE_ENS_LAUNCH(ens_update_split_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
-                          e->work_low[order], e->done, k, h, ns);
+                          e->work_low[order], e->done, k, h, nl);
         } else {
             if (variant == 0)
                 ZE_ENS_LAUNCH(ens_product_kernel<WideCfg>, dim3(e->n_prod[0]), dim3(kThreads), 0, s,
@@ -484,6 +486,7 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         e->g_order = order;
         e->g_K = K;
         e->g_slices = e->slices;
+        e->g_slices_low = e->slices_low;
         e->g_h = h;
         e->g_tol = tol;
     }
@@ -642,6 +645,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     e->N.assign(N, N + nsim);
     e->maxN = *std::max_element(e->N.begin(), e->N.end());
     e->slices = split_max_slices(e->maxN) < 5 ? split_max_slices(e->maxN) : 5;
+    e->slices_low = e->slices > 2 ? e->slices - 1 : 2;
     ze_status st = ZE_OK;
     auto fail = [&](ze_status s) {
         ze_ensemble_destroy(e);
@@ -742,7 +746,7 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     ZE_TRY(set_pointers(e, W));
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
-        e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices ||
+        e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices || e->g_slices_low != e->slices_low ||
         e->g_guess != e->guess_mode)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
     if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
@@ -806,6 +810,13 @@ ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
 ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
     if (!e || slices < 2 || slices > split_max_slices(e->maxN)) return ZE_EINVAL;
     e->slices = slices;
+    e->slices_low = slices > 2 ? slices - 1 : 2;
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_split_slices_lower(ze_ens* e, int slices) {
+    if (!e || slices < 2 || slices > e->slices) return ZE_EINVAL;
+    e->slices_low = slices;
     return ZE_OK;
 }
 

@@ -186,9 +186,14 @@ hipError_t ze_i8_capacity(int* cap) {
     return hipSuccess;
 }
 
+// Slices of the product A = P W~ (lower == 0) or of the lower product Q = A P (lower != 0).
+static int slices_of(const ze_ctx* c, int lower) {
+    return lower ? c->split_slices_low : c->split_slices;
+}
+
 hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, int* ea,
-                                int* eb, bool eb_known, hipStream_t st) {
-    const int N = c->N, s = c->split_slices, ldk = ze_split_ldk(N);
+                                int* eb, bool eb_known, int lower, hipStream_t st) {
+    const int N = c->N, s = slices_of(c, lower), ldk = ze_split_ldk(N);
     hipLaunchKernelGGL(split_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, s, ldk, c->split_a,
                        ea);
     hipError_t e = hipGetLastError();
@@ -211,8 +216,8 @@ hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2
 
 hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                               int lower, int* ea, int* eb, bool eb_known, hipStream_t st) {
-    const int N = c->N, s = c->split_slices;
-    hipError_t e = launch_split_prepare(c, A, B, ea, eb, eb_known, st);
+    const int N = c->N, s = slices_of(c, lower);
+    hipError_t e = launch_split_prepare(c, A, B, ea, eb, eb_known, lower, st);
     if (e != hipSuccess) return e;
     const int tr = (N + kI8BM - 1) / kI8BM;
     const int tn = (2 * N + kI8BN - 1) / kI8BN;
@@ -256,6 +261,6 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
     const int N = c->N;
     const int T = (N + kUT - 1) / kUT;
     hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q,
-                       c->split_g, ea, eb, c->split_slices, A, Wn, Wt, F, Wout, rowpart, N, h);
+                       c->split_g, ea, eb, slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h);
     return hipGetLastError();
 }

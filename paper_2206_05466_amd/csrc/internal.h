@@ -60,6 +60,9 @@ struct ze_ctx {
     // A~ and B~^T operands (kSplitMax slices each, rows of ze_split_ldk(N) bytes), their scale
     // exponents, column-maximum partials, and the int32 product slabs.
     int split_slices = 5;
+    // Slices of the lower product Q = A P, whose term enters F with h^2/4 against h/2 for A:
+    // one slice fewer by default (ze_set_split_slices), or as ze_set_split_slices_lower sets.
+    int split_slices_low = 4;
     signed char* split_a = nullptr;
     signed char* split_b = nullptr;
     int* split_ea = nullptr;
@@ -168,9 +171,10 @@ hipError_t launch_energy_spectrum(const double2* omega, double* E, int N, hipStr
 int ze_split_ldk(int N);  // bytes per slice row: 2N rounded up to the K stage
 // Slices A (rows; exponents into ea) and B (columns) into the context's buffers.  The column
 // exponents of B are computed into eb, or, with eb_known, read from eb (a skew-Hermitian B whose
-// row exponents are known: they are its column exponents).
+// row exponents are known: they are its column exponents).  lower selects the slice count of
+// the lower product.
 hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2* B, int* ea,
-                                int* eb, bool eb_known, hipStream_t s);
+                                int* eb, bool eb_known, int lower, hipStream_t s);
 // C = A B (lower != 0: only the tiles meeting the lower triangle are formed, and left in the
 // int32 slabs for launch_lower_update); ea, eb, eb_known as for launch_split_prepare.
 hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* B, double2* C,

@@ -39,6 +39,7 @@ SIGNATURES = {
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
+    "ze_set_split_slices_lower": (_c_int, [_vp, _c_int]),
     "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
@@ -50,6 +51,7 @@ SIGNATURES = {
     "ze_ensemble_tuning": (_c_int, [_vp, _c_int, _P_int, _P_double]),
     "ze_ensemble_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_initial_guess": (_c_int, [_vp, _c_int]),
+    "ze_ensemble_set_split_slices_lower": (_c_int, [_vp, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -241,6 +243,11 @@ class Zeuler:
         8192, 3 at 16384; the int32 exactness bound)."""
         _check(self.lib.ze_set_split_slices(self._ctx, int(slices)), "ze_set_split_slices")
 
+    def set_split_slices_lower(self, slices: int):
+        """Slices of the lower product Q = A P (2 .. the product's slices; default one fewer,
+        since Q's term enters the map with h^2/4 against h/2)."""
+        _check(self.lib.ze_set_split_slices_lower(self._ctx, int(slices)), "ze_set_split_slices_lower")
+
     def profile(self, on: bool = True):
         """Turn per-phase event timing of isomp_step on or off."""
         _check(self.lib.ze_profile(self._ctx, int(bool(on))), "ze_profile")
@@ -317,6 +324,11 @@ class Ensemble:
         """Slices per operand of the ensemble's PREC_SPLIT products (2 .. s_max of the largest N)."""
         _check(self.lib.ze_ensemble_set_split_slices(self._ens, int(slices)),
                "ze_ensemble_set_split_slices")
+
+    def set_split_slices_lower(self, slices: int):
+        """Slices of the ensemble's lower products (2 .. the product's slices)."""
+        _check(self.lib.ze_ensemble_set_split_slices_lower(self._ens, int(slices)),
+               "ze_ensemble_set_split_slices_lower")
 
     def set_initial_guess(self, mode: int):
         """0: every step starts from W_n; 1: steps after the first of a run start each simulation

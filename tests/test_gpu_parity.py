@@ -674,3 +674,31 @@ def test_ensemble_polynomial_guess(dev, prec_name):
             assert its[j] == itr[-1] and its2[j] == itr2[-1], (j, its[j], itr, its2[j], itr2)
         assert np.linalg.norm(got[j] - Wr) <= bar * np.linalg.norm(Wr), j
         assert np.linalg.norm(got2[j] - W2r) <= bar * np.linalg.norm(W2r), j
+
+
+def test_split_lower_slices(dev):
+    """The lower product Q = A P with one slice fewer than A (the default) or with as many:
+    both runs stay within 1e-10 of the oracle and within 1e-12 of each other at h = 0.005 (Q's
+    term carries h^2/4), and the setters reject counts outside 2 .. s."""
+    from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
+
+    N, h, steps = 128, 0.005, 6
+    W0 = w0(N, 5)
+    Wr, _, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3)
+    out = []
+    with ctx(N) as z:
+        z.set_initial_guess(2)
+        for sq in (None, 5):
+            z.set_split_slices(5)
+            if sq:
+                z.set_split_slices_lower(sq)
+            Wd = to_dev(W0)
+            _, res = z.isomp_run(Wd, h, steps, 1e-12, 50, prec=PREC_SPLIT)
+            assert max(res) < 1e-12
+            out.append(to_host(Wd))
+        for bad in (1, 6):
+            with pytest.raises(ZeulerError):
+                z.set_split_slices_lower(bad)
+    for W in out:
+        assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
+    assert np.linalg.norm(out[0] - out[1]) <= 1e-12 * np.linalg.norm(Wr)
