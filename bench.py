@@ -364,7 +364,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
     `steps` timed steps of one ze_isomp_run call from the same W0."""
     import torch
 
-    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
+    from paper_2206_05466_amd import PREC_FP64, PREC_MIXED, PREC_SPLIT, Zeuler
     from workloads import WORKLOADS, omega_coeffs
 
     cfg = WORKLOADS[wname]
@@ -420,6 +420,21 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
         torch.cuda.synchronize()
         del src, dst
 
+    # mixed: A = P W~ in FP64, the lower product (h^2/4 weight) on INT8 with 4 slices
+    z.set_split_slices(5)
+    Wm = W0.clone()
+    dtm, its_m, res_m, prof_m = timed_run(Wm, PREC_MIXED, 2)
+    mixed = {
+        "s_per_step": dtm / steps, "speedup_vs_fp64": (dt / steps) / (dtm / steps),
+        "iters_per_step": list(its_m), "max_resid": max(res_m), "lower_product_slices": 4,
+        "rel_frobenius_vs_fp64_run": float(torch.linalg.norm(Wm - W).item() / torch.linalg.norm(W).item()),
+        "casimir_drift_rel": casimir_drift(c0, z.casimirs(Wm, 4), Wm),
+        "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof_m.items()},
+    }
+    log(f"{wname} mixed (FP64 A, 4-slice Q): {dtm / steps * 1e3:.2f} ms/step, rel diff vs fp64 "
+        f"{mixed['rel_frobenius_vs_fp64_run']:.2e}")
+    del Wm
+
     split = None
     if slist:
         runs = []
@@ -467,6 +482,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
         "fp64_linear_start": {"s_per_step": dt_lin / steps, "iters_per_step": list(iters_lin),
                               "rel_frobenius_vs_headline_run": lin_vs_extrap},
         "split_precision": split,
+        "mixed_precision": mixed,
     }
 
 
@@ -525,6 +541,7 @@ def main():
             "product_PW_tflops": 8.0 * 2048 ** 3 / (p2[0] / max(p2[1], 1) * 1e-3) / 1e12,
             "phases": phases_of(m2["prof"]),
             "split_precision": m2["split_precision"],
+            "mixed_precision": m2["mixed_precision"],
         }
 
     n512 = small_leg(args.n512_steps) if args.n512_steps > 0 else None
@@ -617,6 +634,7 @@ def main():
         "lower_product_tflops": 4.0 * N ** 3 / (low_ms * 1e-3) / 1e12,
         "cpu_baseline": None,
         "split_precision": m["split_precision"],
+        "mixed_precision": m["mixed_precision"],
         "n2048": n2048,
         "n512": n512,
         "long512": long512,

@@ -40,11 +40,16 @@ typedef enum {
 /* Arithmetic of the complex matrix products. */
 typedef enum {
     ZE_PREC_FP64 = 0,   /* FP64 MFMA products */
-    ZE_PREC_SPLIT = 1   /* FP64 products emulated on INT8 MFMA: Ozaki splitting into s slices
+    ZE_PREC_SPLIT = 1,  /* FP64 products emulated on INT8 MFMA: Ozaki splitting into s slices
                            (balanced digits: 7 bits, then 8 bits each) per row / column scale
                            (ze_set_split_slices), exact int32 slice products, FP64
                            accumulation; error ~2^(-8 s) relative to max|row| max|column| per
                            term of the inner sum */
+    ZE_PREC_MIXED = 2   /* ze_isomp_step / ze_isomp_run only: A = P W~ on FP64 MFMA, the lower
+                           product Q = A P split as above with ze_set_split_slices_lower slices
+                           (default 4).  Q's term enters the map with h^2/4, so its rounding
+                           reaches the step at ~(h^2/4) 2^(-8 s_q) relative: at h = 0.005 and
+                           s_q = 4 below the FP64 products' own rounding. */
 } ze_prec;
 
 /* Message for a status code (static string). */
@@ -95,7 +100,7 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  *   h       time step (any finite sign).
  *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
  *   maxit   evaluation cap, >= 1.
- *   prec    ZE_PREC_FP64 or ZE_PREC_SPLIT.
+ *   prec    ZE_PREC_FP64, ZE_PREC_SPLIT or ZE_PREC_MIXED.
  *   iters   host, may be NULL: evaluations done (summed over the substeps of a step of
  *           order 4 or 6, see ze_set_order).
  *   resid   host, may be NULL: final residual (the largest over the substeps).

@@ -228,12 +228,12 @@ enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                           StartFrom start, double rho, int* iters, double* resid) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
-    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED) return ZE_EINVAL;
     const int N = c->N;
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
-    const bool split = prec == ZE_PREC_SPLIT;
-    if (split) ZE_TRY(ze_ensure_split(c));
+    const bool split = prec == ZE_PREC_SPLIT, mixed = prec == ZE_PREC_MIXED;
+    if (split || mixed) ZE_TRY(ze_ensure_split(c));
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
@@ -254,6 +254,11 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
         if (split) {
             // P is skew-Hermitian: its column exponents are the row exponents just taken
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, true, s));
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+                                       c->split_ec, c->split_ea, s));
+        } else if (mixed) {
+            // A came from the FP64 product: P's column exponents are taken here
+            ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, false, s));
             ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
                                        c->split_ec, c->split_ea, s));
         } else {

@@ -49,7 +49,7 @@ def casimir_ok(W0, W):
 
 
 def test_n4096_steps_fp64_and_split(dev):
-    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
+    from paper_2206_05466_amd import PREC_FP64, PREC_MIXED, PREC_SPLIT, Zeuler
 
     cfg = WORKLOADS["n4096"]
     N, h, L, steps = cfg["N"], cfg["h"], 32, 5
@@ -69,6 +69,11 @@ def test_n4096_steps_fp64_and_split(dev):
     its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_SPLIT)
     W = to_host(Wd)
     assert its == it_ref and rel(W, Wr) < 1e-10, (its, rel(W, Wr))
+    z.set_split_slices(5)  # lower product: 4 slices
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_MIXED)
+    W = to_host(Wd)
+    assert its == it_ref and rel(W, Wr) < 1e-12, (its, rel(W, Wr))
     z.close()
 
 

@@ -702,3 +702,28 @@ def test_split_lower_slices(dev):
     for W in out:
         assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
     assert np.linalg.norm(out[0] - out[1]) <= 1e-12 * np.linalg.norm(Wr)
+
+
+@pytest.mark.parametrize("N,steps", [(128, 8), (1000, 5)])
+def test_isomp_mixed_precision_meets_fp64_bar(dev, N, steps):
+    """PREC_MIXED (FP64 product A, lower product Q on INT8 with 4 slices): the FP64 path's
+    bar against the oracle (1e-12, the same evaluation counts), because Q's term carries
+    h^2/4; ze_zgemm and the ensemble reject it."""
+    from paper_2206_05466_amd import PREC_MIXED, Ensemble, ZeulerError
+
+    h = 0.005
+    W0 = w0(N, 9, "inv1.5")
+    Wr, it_ref, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3)
+    with ctx(N) as z:
+        z.set_initial_guess(2)
+        Wd = to_dev(W0)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 50, prec=PREC_MIXED)
+        W = to_host(Wd)
+        with pytest.raises(ZeulerError):
+            z.zgemm(Wd, Wd.clone(), prec=PREC_MIXED)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
+    assert np.abs(W + W.conj().T).max() == 0.0
+    with Ensemble([16, 24]) as ens:
+        with pytest.raises(ZeulerError):
+            ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], h, 1, 1e-12, 4, prec=PREC_MIXED)
