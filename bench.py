@@ -358,13 +358,13 @@ def casimir_drift(c0, c1, W):
     return {f"C{k+1}": float(abs(c1[k] - c0[k]) / (abs(c0[k]) if k != 2 else nf ** 3)) for k in (1, 2, 3)}
 
 
-def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
+def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=True):
     """One simulation of workload wname: FP64 (start from W_n, the linear start, then the
     polynomial start of the headline) and the split-precision runs (polynomial start), each over
     `steps` timed steps of one ze_isomp_run call from the same W0."""
     import torch
 
-    from paper_2206_05466_amd import PREC_FP64, PREC_MIXED, PREC_SPLIT, Zeuler
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Zeuler
     from workloads import WORKLOADS, omega_coeffs
 
     cfg = WORKLOADS[wname]
@@ -421,19 +421,9 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
         del src, dst
 
     # mixed: A = P W~ in FP64, the lower product (h^2/4 weight) on INT8 with 4 slices
-    z.set_split_slices(5)
-    Wm = W0.clone()
-    dtm, its_m, res_m, prof_m = timed_run(Wm, PREC_MIXED, 2)
-    mixed = {
-        "s_per_step": dtm / steps, "speedup_vs_fp64": (dt / steps) / (dtm / steps),
-        "iters_per_step": list(its_m), "max_resid": max(res_m), "lower_product_slices": 4,
-        "rel_frobenius_vs_fp64_run": float(torch.linalg.norm(Wm - W).item() / torch.linalg.norm(W).item()),
-        "casimir_drift_rel": casimir_drift(c0, z.casimirs(Wm, 4), Wm),
-        "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof_m.items()},
-    }
-    log(f"{wname} mixed (FP64 A, 4-slice Q): {dtm / steps * 1e3:.2f} ms/step, rel diff vs fp64 "
-        f"{mixed['rel_frobenius_vs_fp64_run']:.2e}")
-    del Wm
+    mixed = None
+    if with_mixed:
+        mixed = mixed_run(z, timed_run, W0, W, c0, dt, steps, wname)
 
     split = None
     if slist:
@@ -486,6 +476,28 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0):
     }
 
 
+def mixed_run(z, timed_run, W0, W, c0, dt, steps, wname):
+    """The same run with ZE_PREC_MIXED (FP64 A = P W~, the lower product on INT8 with 4
+    slices), compared with the FP64 headline run W."""
+    import torch
+
+    from paper_2206_05466_amd import PREC_MIXED
+
+    z.set_split_slices(5)
+    Wm = W0.clone()
+    dtm, its_m, res_m, prof_m = timed_run(Wm, PREC_MIXED, 2)
+    mixed = {
+        "s_per_step": dtm / steps, "speedup_vs_fp64": dt / dtm,
+        "iters_per_step": list(its_m), "max_resid": max(res_m), "lower_product_slices": 4,
+        "rel_frobenius_vs_fp64_run": float(torch.linalg.norm(Wm - W).item() / torch.linalg.norm(W).item()),
+        "casimir_drift_rel": casimir_drift(c0, z.casimirs(Wm, 4), Wm),
+        "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof_m.items()},
+    }
+    log(f"{wname} mixed (FP64 A, 4-slice Q): {dtm / steps * 1e3:.2f} ms/step, rel diff vs fp64 "
+        f"{mixed['rel_frobenius_vs_fp64_run']:.2e}")
+    return mixed
+
+
 def phases_of(prof):
     return {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
 
@@ -505,6 +517,8 @@ def main():
                     help="timed steps of the N=512 leg (0: skip it)")
     ap.add_argument("--long-steps", type=int, default=10000,
                     help="steps of the long-run drift leg (N=512, paper initial condition; 0: skip)")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="1: also time the mixed-precision run (FP64 A, INT8 lower product), 0: skip")
     ap.add_argument("--orders", type=int, default=1,
                     help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
@@ -524,12 +538,13 @@ def main():
 
     torch.cuda.set_device(0)
     slist = [int(x) for x in str(args.split_slices).split(",") if x.strip() and int(x) > 0]
-    m = measure_single(args.workload, args.steps, args.warmup, slist, args.copy_probe_mib)
+    m = measure_single(args.workload, args.steps, args.warmup, slist, args.copy_probe_mib,
+                       args.mixed > 0)
     N, prof = m["N"], m["prof"]
 
     n2048 = None
     if args.n2048_steps > 0 and args.workload != "n2048":
-        m2 = measure_single("n2048", args.n2048_steps, args.warmup, slist)
+        m2 = measure_single("n2048", args.n2048_steps, args.warmup, slist, 0, args.mixed > 0)
         p2 = m2["prof"]["product_PW"]
         n2048 = {
             "workload": f"n2048: one simulation, N=2048, sigma_l law {m2['law']}, h={m2['h']}, "
