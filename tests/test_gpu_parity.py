@@ -727,3 +727,29 @@ def test_isomp_mixed_precision_meets_fp64_bar(dev, N, steps):
     with Ensemble([16, 24]) as ens:
         with pytest.raises(ZeulerError):
             ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], h, 1, 1e-12, 4, prec=PREC_MIXED)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 17])
+def test_tiny_sizes_every_mode(dev, N):
+    """N = 1, 2, 3, 17 through the polynomial start, mixed precision and the order-4 step,
+    each against the oracle's run of the same kind (1e-12 of ||W||, or exact zeros)."""
+    from paper_2206_05466_amd import PREC_MIXED
+
+    h = 0.01
+    W0 = w0(N, 2)
+    Wr, it_ref, _ = O.isomp_run(W0, h, 6, 1e-12, 50, extrapolate=True, degree=3)
+    W4, it4, _ = O.isomp_composed_run(W0, h, 2, 4, 1e-12, 50)
+    scale = max(np.linalg.norm(W0), 1e-300)
+    with ctx(N) as z:
+        z.set_initial_guess(2)
+        for prec in (0, PREC_MIXED):
+            Wd = to_dev(W0)
+            its, res = z.isomp_run(Wd, h, 6, 1e-12, 50, prec=prec)
+            assert its == it_ref, (prec, its, it_ref)
+            assert np.linalg.norm(to_host(Wd) - Wr) <= 1e-12 * scale
+        z.set_initial_guess(0)
+        z.set_order(4)
+        Wd = to_dev(W0)
+        its, _ = z.isomp_run(Wd, h, 2, 1e-12, 50)
+        assert its == it4
+        assert np.linalg.norm(to_host(Wd) - W4) <= 1e-12 * scale
