@@ -24,16 +24,20 @@ Readings taken here (the paper does not state them):
   polynomial of degree min(k - 1, d) through the last min(k, d + 1) midpoints, evaluated one
   step ahead (``extrapolate_midpoints``): the midpoints are equally spaced samples of a
   smooth curve, so the start is within O(h^(d+1)) of the fixed point; k = 1 keeps the
-  linear start above;
+  linear start above.  With the difference form of W_{n+1} the trajectory carries residual
+  noise only at O(h ||P|| r) and a step then takes one evaluation; with the second-line form
+  the O(r) kinks that accepted one-evaluation steps leave, amplified by the extrapolation
+  weights, push every few steps back to two;
 * the norm is the matrix infinity norm, max_i sum_j |F_ij - W~_ij|, of the change
   F - W~ between the map's output F and its input W~;
-* W_{n+1} comes from the difference of the two lines of eq. (isomp), which is exactly
-  W_{n+1} - W_n = h (P~ W~ - W~ P~): W_{n+1} = W_n + h C, with C = A - A^H the commutator of
-  the evaluation whose change is below the tolerance (its input W~).  At the fixed point this
-  is the second line of eq. (isomp); at a stopped iterate it keeps the step isospectral up to
-  O(h ||P|| r) instead of O(r) for the second line evaluated directly (r the residual:
-  W~ + h/2 C - h^2/4 Q is a unitary conjugate of W_n - (F - W~), while W_n + h C differs
-  from that by F - W~ itself, which cancels the residual to first order);
+* W_{n+1} is the second line of eq. (isomp) evaluated at the same W~ whose change is below
+  the tolerance, reusing that evaluation's products (``update="second_line"``, the default):
+  W_{n+1} = W~ + h/2 C - h^2/4 Q, with C = A - A^H and Q = A P.  Optionally
+  (``update="difference"``) W_{n+1} = W_n + h C: the two lines of eq. (isomp) differ by
+  exactly h (P~ W~ - W~ P~), so at the fixed point both forms agree; at a stopped iterate the
+  second line is a unitary conjugate of W_n - (F - W~) (spectrum off by O(r), r the
+  residual), while W_n + h C differs from that by F - W~ itself, which cancels the residual
+  to first order (spectrum off by O(h ||P|| r));
 * Q is skew-Hermitian in exact arithmetic and is projected, Q <- (Q - Q^H)/2;
 * with ``maxit`` reached first, W_{n+1} comes from the last W~ and the caller is told the
   residual (a fixed iteration count, as in the paper's timing runs, is ``tol = 0``);
@@ -57,13 +61,20 @@ import numpy as np
 from .stream import stream_solve
 
 
+UPDATE_FORMS = ("second_line", "difference")
+
+
 def isomp_step(Wn: np.ndarray, h: float, tol: float = 1e-12, maxit: int = 50,
-               guess: np.ndarray | None = None, return_midpoint: bool = False):
+               guess: np.ndarray | None = None, return_midpoint: bool = False,
+               update: str = "second_line"):
     """One IsoMP step.  Returns (W_{n+1}, iterations, final residual).
 
     ``guess`` replaces the starting iterate W~ = W_n; with ``return_midpoint`` the map's last
-    output F (the converged midpoint) is returned as a fourth value.
+    output F (the converged midpoint) is returned as a fourth value; ``update`` selects the
+    form of W_{n+1} (see the module notes).
     """
+    if update not in UPDATE_FORMS:
+        raise ValueError("update must be 'second_line' or 'difference'")
     Wn = np.asarray(Wn, dtype=np.complex128)
     Wt = Wn.copy() if guess is None else np.asarray(guess, dtype=np.complex128).copy()
     for k in range(1, maxit + 1):
@@ -75,7 +86,10 @@ def isomp_step(Wn: np.ndarray, h: float, tol: float = 1e-12, maxit: int = 50,
         F = Wn + (0.5 * h) * C + (0.25 * h * h) * Q
         r = float(np.abs(F - Wt).sum(axis=1).max())
         if r < tol or k == maxit:
-            W1 = Wn + h * C
+            if update == "difference":
+                W1 = Wn + h * C
+            else:
+                W1 = Wt + (0.5 * h) * C - (0.25 * h * h) * Q
             return (W1, k, r, F) if return_midpoint else (W1, k, r)
         Wt = F
     raise ValueError("maxit must be >= 1")
@@ -112,7 +126,7 @@ def composition_weights(order: int) -> list:
 
 
 def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: float = 1e-12,
-                       maxit: int = 50, extrapolate: bool = False):
+                       maxit: int = 50, extrapolate: bool = False, update: str = "second_line"):
     """nsteps steps of the composition of ``order`` from W0: each step is one midpoint substep
     of size c_j h for every c_j of ``composition_weights(order)``, in that order.  Returns
     (W, [evaluations per step], [largest substep residual per step])."""
@@ -127,7 +141,8 @@ def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: f
             if extrapolate and mid is not None:
                 rho = c / prev
                 guess = 2.0 * W - mid if rho == 1.0 else W + rho * (W - mid)
-            W, k, r, mid = isomp_step(W, c * h, tol, maxit, guess=guess, return_midpoint=True)
+            W, k, r, mid = isomp_step(W, c * h, tol, maxit, guess=guess, return_midpoint=True,
+                                      update=update)
             prev = c
             its += k
             rmax = max(rmax, r)
@@ -137,7 +152,7 @@ def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: f
 
 
 def isomp_run(W0: np.ndarray, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
-              extrapolate: bool = False, degree: int = 1):
+              extrapolate: bool = False, degree: int = 1, update: str = "second_line"):
     """nsteps IsoMP steps from W0.  Returns (W, [iterations], [residuals]).
 
     ``extrapolate``: starting iterates from the previous midpoints of this run (see the
@@ -154,7 +169,8 @@ def isomp_run(W0: np.ndarray, h: float, nsteps: int, tol: float = 1e-12, maxit: 
         elif extrapolate and len(mids) >= 2:
             d = min(len(mids) - 1, degree)
             guess = extrapolate_midpoints(mids, d)
-        W, k, r, mid = isomp_step(W, h, tol, maxit, guess=guess, return_midpoint=True)
+        W, k, r, mid = isomp_step(W, h, tol, maxit, guess=guess, return_midpoint=True,
+                                  update=update)
         mids = (mids + [mid])[-(degree + 1):]
         iters.append(k)
         res.append(r)

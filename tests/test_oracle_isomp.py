@@ -235,21 +235,25 @@ def test_composition_order2_is_the_midpoint_run_and_extrapolation():
 
 
 def test_stopped_iterate_stays_isospectral_to_order_h_p_r():
-    """W_{n+1} = W_n + h C at an iterate stopped early (maxit 1..3, residual r up to 1e-2):
-    W_{n+1} = U (W_n - E) U^H + E with U the Cayley transform of h P~ and E = F - W~
-    (||E||_2 <= r for skew-Hermitian E), so by Weyl its eigenvalues move by at most
-    ||U E U^H - E|| <= 2 h ||P~|| r / (1 - h ||P~|| / 2).  The second line of eq. (isomp)
-    evaluated directly at the stopped iterate would move them by O(r)."""
+    """The difference form W_{n+1} = W_n + h C at an iterate stopped early (maxit 1..3,
+    residual r up to 1e-2): W_{n+1} = U (W_n - E) U^H + E with U the Cayley transform of h P~
+    and E = F - W~ (||E||_2 <= r for skew-Hermitian E), so by Weyl its eigenvalues move by at
+    most ||U E U^H - E|| <= 2 h ||P~|| r / (1 - h ||P~|| / 2).  The second line of eq. (isomp)
+    evaluated at the stopped iterate (the default form) moves them by O(r): after two
+    evaluations it exceeds that bound."""
     W = w0(16, 3)
     ev = spec(W)
     hp = np.linalg.norm(O.stream_solve(W), 2)
     for h in (0.05, 0.1):
         for m in (1, 2, 3):
-            W1, k, r = O.isomp_step(W, h, 0.0, m)
+            W1, k, r = O.isomp_step(W, h, 0.0, m, update="difference")
             drift = np.abs(spec(W1) - ev).max()
             assert drift <= 2.5 * h * hp * r, (h, m, drift, r)
             assert drift < 0.02 * r
             assert np.abs(W1 + W1.conj().T).max() < 1e-15
+            if m == 2:
+                W2, _, r2 = O.isomp_step(W, h, 0.0, m)
+                assert r2 == r and np.abs(spec(W2) - ev).max() > 2.5 * h * hp * r
 
 
 def test_extrapolate_midpoints_exact_on_polynomials():
@@ -274,15 +278,20 @@ def test_extrapolate_midpoints_exact_on_polynomials():
 
 
 def test_polynomial_start_one_evaluation_same_fixed_point():
-    """Starting each step from the cubic extrapolation of the previous midpoints: after the
-    start-up (W_n, linear, then degrees 1 and 2) a step needs one evaluation at tol = 1e-12,
-    the residuals stay below it, and the trajectory agrees with the W_n-started one to the
-    tolerance."""
+    """Starting each step from the cubic extrapolation of the previous midpoints, with the
+    difference form of W_{n+1}: after the start-up (W_n, linear, then degrees 1 and 2) a step
+    needs one evaluation at tol = 1e-12, the residuals stay below it, and the trajectory agrees
+    with the W_n-started one to the tolerance.  With the second-line form the same start
+    reaches the same trajectory but needs a second evaluation every few steps."""
     W = O.assemble(256, omega_coeffs(256, 0, "inv1.5"))
-    Wa, ia, ra = O.isomp_run(W, 0.005, 24, 1e-12, 50)
-    Wb, ib, rb = O.isomp_run(W, 0.005, 24, 1e-12, 50, extrapolate=True, degree=3)
+    Wa, ia, ra = O.isomp_run(W, 0.005, 24, 1e-12, 50, update="difference")
+    Wb, ib, rb = O.isomp_run(W, 0.005, 24, 1e-12, 50, extrapolate=True, degree=3,
+                             update="difference")
     assert ib[0] == ia[0] and all(k == 1 for k in ib[4:]), ib
     assert max(rb) < 1e-12
     assert np.linalg.norm(Wa - Wb) < 1e-12 * np.linalg.norm(Wa)
+    Wc, ic, rc = O.isomp_run(W, 0.005, 24, 1e-12, 50, extrapolate=True, degree=3)
+    assert max(rc) < 1e-12 and 1.0 < sum(ic[4:]) / len(ic[4:]) < 2.0, ic
+    assert np.linalg.norm(Wa - Wc) < 1e-12 * np.linalg.norm(Wa)
     with pytest.raises(ValueError):
         O.isomp_run(W, 0.005, 1, degree=4)
