@@ -93,9 +93,9 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  * the implicit W~ found by the fixed-point iteration eq. (isomp_iter) from W~ = W_n.  Each
  * evaluation is one stream solve, A = P W~, and the lower triangle of Q = A P, the
  * commutator being A - A^H (Sec. 3.1).  It stops once the matrix infinity norm of the change
- * of W~ is below tol, and W_{n+1} = W_n + h (A - A^H) from that same evaluation (the two lines
- * of eq. (isomp) differ by exactly h [P~, W~]; in this form the residual left at the stop moves
- * the spectrum only by O(h ||P|| tol)).
+ * of W~ is below tol, and W_{n+1} is formed from that same evaluation's products: by default
+ * the second line of eq. (isomp) at that W~, W~ + h/2 (A - A^H) - h^2/4 Q; or, with
+ * ze_set_update_form 1, W_n + h (A - A^H).
  *   W       device, N x N complex128, skew-Hermitian; in: W_n, out: W_{n+1}.
  *   h       time step (any finite sign).
  *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
@@ -154,6 +154,21 @@ ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
  * Errors: ZE_EINVAL for any other order, and for 4 or 6 while ze_set_initial_guess is 2.
  */
 ze_status ze_set_order(ze_ctx* ctx, int order);
+
+/*
+ * ze_set_update_form -- how W_{n+1} is formed from the last evaluation's products.
+ *   form 0  (default) the second line of eq. (isomp) at the last iterate W~:
+ *           W~ + h/2 (A - A^H) - h^2/4 Q.
+ *   form 1  W_n + h (A - A^H): the two lines of eq. (isomp) differ by exactly h [P~, W~], so
+ *           both forms agree at the fixed point.  At a stopped iterate (residual r), form 0 is
+ *           a unitary conjugate of W_n - (F - W~), with eigenvalues off by O(r); form 1 differs
+ *           from it by F - W~ itself, with eigenvalues off by only O(h ||P~|| r).  With
+ *           ze_set_initial_guess 2 a step then takes one evaluation after the start-up,
+ *           against about 1.5 with form 0, whose O(r) trajectory kinks the extrapolation
+ *           amplifies.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_set_update_form(ze_ctx* ctx, int form);
 
 /*
  * ze_casimirs -- C_k(W) = Tr(W^k), k = 1..kmax (eq. (W_pow)), in FP64, from powers of W
@@ -316,6 +331,13 @@ ze_status ze_ensemble_set_split_slices(ze_ens* ens, int slices);
  * Errors: ZE_EINVAL.
  */
 ze_status ze_ensemble_set_split_slices_lower(ze_ens* ens, int slices);
+
+/*
+ * ze_ensemble_set_update_form -- form of W_{n+1} for the ensemble's steps (0 default, 1; see
+ * ze_set_update_form).  Takes effect at the next ze_ensemble_run.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_ensemble_set_update_form(ze_ens* ens, int form);
 
 /*
  * ze_ensemble_set_initial_guess -- first iterate of the fixed-point map (eq. (isomp_iter)) for

@@ -493,6 +493,12 @@ ze_status ze_set_split_slices(ze_ctx* c, int slices) {
     return ZE_OK;
 }
 
+ze_status ze_set_update_form(ze_ctx* c, int form) {
+    if (!c || form < 0 || form > 1) return ZE_EINVAL;
+    c->update_form = form;
+    return ZE_OK;
+}
+
 ze_status ze_set_split_slices_lower(ze_ctx* c, int slices) {
     if (!c || slices < 2 || slices > c->split_slices) return ZE_EINVAL;
     c->split_slices_low = slices;

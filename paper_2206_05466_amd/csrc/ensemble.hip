@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void ens_lower_kernel(const EnsProb* __re
 __global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __restrict__ probs,
                                                                const int2* __restrict__ work,
                                                                const int* __restrict__ done,
-                                                               int eval, double h) {
+                                                               int eval, double h, int form) {
     __shared__ double2 sT[kUT][kUT + 1];
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __
     int I, J;
     lower_tile(it.y, I, J);
     lower_update_tile(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W, p.rowpart,
-                      p.N, h, sT);
+                      p.N, h, form, sT);
 }
 
 // ---------------------------------------------------------------- split-precision phases
@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kSThreads) void ens_combine_kernel(const EnsProb* _
 __global__ __launch_bounds__(kUThreads) void ens_update_split_kernel(const EnsProb* __restrict__ probs,
                                                                      const int2* __restrict__ work,
                                                                      const int* __restrict__ done,
-                                                                     int eval, double h, int s) {
+                                                                     int eval, double h, int s,
+                                                                     int form) {
     __shared__ double2 sT[kUT][kUT + 1];
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kUThreads) void ens_update_split_kernel(const EnsPr
     int I, J;
     lower_tile(it.y, I, J);
     lower_update_tile(I, J, nullptr, p.G, p.eA, p.ep, s, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, p.N,
-                      h, sT);
+                      h, form, sT);
 }
 
 __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restrict__ probs,
@@ -396,6 +397,8 @@ struct ze_ens {
     // 2 = polynomial extrapolation of the run's midpoints (the step index in *stepc)
     int guess_mode = 0;
     int* stepc = nullptr;
+    int update_form = 0;  // W_{n+1}: 0 the second line of eq. (isomp), 1 W_n + h [P~, W~]
+    int g_form = -1;
     hipGraphExec_t exec_x = nullptr;  // the step graph with the extrapolated first iterate
     double g_h = 0.0, g_tol = -1.0;
 };
@@ -433,7 +436,7 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
             ZE_ENS_LAUNCH(ens_i8_kernel, dim3(e->n_i8[1]), dim3(kSThreads), 0, s, e->dp,
                           e->w_i8[1][order], e->done, 1, nl);
             ZE_ENS_LAUNCH(ens_update_split_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
-                          e->work_low[order], e->done, k, h, nl);
+                          e->work_low[order], e->done, k, h, nl, e->update_form);
         } else {
             if (variant == 0)
                 ZE_ENS_LAUNCH(ens_product_kernel<WideCfg>, dim3(e->n_prod[0]), dim3(kThreads), 0, s,
@@ -444,7 +447,7 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
             ZE_ENS_LAUNCH(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
                           e->work_low[order], e->done);
             ZE_ENS_LAUNCH(ens_update_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
-                          e->work_low[order], e->done, k, h);
+                          e->work_low[order], e->done, k, h, e->update_form);
         }
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
                       e->resid, k, tol);
@@ -487,6 +490,7 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         e->g_K = K;
         e->g_slices = e->slices;
         e->g_slices_low = e->slices_low;
+        e->g_form = e->update_form;
         e->g_h = h;
         e->g_tol = tol;
     }
@@ -747,6 +751,7 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
         e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices || e->g_slices_low != e->slices_low ||
+        e->g_form != e->update_form ||
         e->g_guess != e->guess_mode)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
     if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
@@ -811,6 +816,12 @@ ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
     if (!e || slices < 2 || slices > split_max_slices(e->maxN)) return ZE_EINVAL;
     e->slices = slices;
     e->slices_low = slices > 2 ? slices - 1 : 2;
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_update_form(ze_ens* e, int form) {
+    if (!e || form < 0 || form > 1) return ZE_EINVAL;
+    e->update_form = form;
     return ZE_OK;
 }
 

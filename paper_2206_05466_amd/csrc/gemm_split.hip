@@ -162,14 +162,14 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
     const double2* __restrict__ Qf, const int* __restrict__ G, const int* __restrict__ ea,
     const int* __restrict__ eb, int s, const double2* __restrict__ Am,
     const double2* __restrict__ Wn, const double2* Wt, double2* F, double2* __restrict__ Wout,
-    double* __restrict__ rowpart, int N, double h) {
+    double* __restrict__ rowpart, int N, double h, int form) {
     __shared__ double2 sT[kUT][kUT + 1];
     const int b = blockIdx.x;
     int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= b) ++I;
     while (I * (I + 1) / 2 > b) --I;
     const int J = b - I * (I + 1) / 2;
-    lower_update_tile(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, sT);
+    lower_update_tile(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
 }
 
 }  // namespace
@@ -261,6 +261,7 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
     const int N = c->N;
     const int T = (N + kUT - 1) / kUT;
     hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q,
-                       c->split_g, ea, eb, slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h);
+                       c->split_g, ea, eb, slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h,
+                       c->update_form);
     return hipGetLastError();
 }

@@ -84,6 +84,8 @@ struct ze_ctx {
     // substep fractions c_j of one step.
     int order = 2;
     std::vector<double> comp_w{1.0};
+    // Form of W_{n+1}: 0 the second line of eq. (isomp) at the last iterate, 1 W_n + h [P~, W~].
+    int update_form = 0;
 
     // Optional per-phase timing (ze_profile).
     bool prof = false;

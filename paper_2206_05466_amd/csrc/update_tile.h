@@ -8,9 +8,11 @@ namespace zk {
 
 // ---------------------------------------------------------------- fixed-point update
 // For tile (I, J), I >= J, of 64 x 64 complex entries, from Q (lower tiles valid):
-//   F = Wn + h/2 (A - A^H) + h^2/4 Q   (Re Q_RR := 0),   Wout = Wn + h (A - A^H)
-// (Wout is the difference of the two lines of eq. (isomp), W_{n+1} - W_n = h [P~, W~], at the
-// iterate Wt: at a stopped iterate this keeps the spectrum to O(h ||P|| residual)),
+//   F = Wn + h/2 (A - A^H) + h^2/4 Q   (Re Q_RR := 0),
+//   Wout = Wt + h/2 (A - A^H) - h^2/4 Q   (form 0: the second line of eq. (isomp) at Wt), or
+//   Wout = Wn + h (A - A^H)               (form 1: the two lines differ by h [P~, W~]; at a
+//                                          stopped iterate the spectrum is then off by
+//                                          O(h ||P|| residual) instead of O(residual)),
 // lower entries written directly, upper ones (-conj) through an LDS transpose so every
 // global access is a coalesced row segment.  Row sums of |F - Wt| go to slots
 // rowpart[X*N + r] (tile-column X, row r): tile (I, J), I > J, writes the row sums of its
@@ -27,7 +29,7 @@ __device__ __forceinline__ void lower_update_tile(int I, int J, const double2* _
                                          const double2* __restrict__ Am,
                                          const double2* __restrict__ Wn, const double2* Wt,
                                          double2* F, double2* __restrict__ Wout,
-                                         double* __restrict__ rowpart, int N, double h,
+                                         double* __restrict__ rowpart, int N, double h, int form,
                                          double2 (*sT)[kUT + 1]) {
     double(*sD)[kUT + 1] = reinterpret_cast<double(*)[kUT + 1]>(&sT[0][0]);  // reused at the end
     const int R0 = I * kUT, C0 = J * kUT;
@@ -70,7 +72,8 @@ __device__ __forceinline__ void lower_update_tile(int I, int J, const double2* _
             const double cr = arc.x - acr.x, ci = arc.y + acr.y;  // (A - A^H)_{Rc}
             const double2 wn = Wn[o], wt = Wt[o];
             f = make_double2(wn.x + h2 * cr + h4 * qv.x, wn.y + h2 * ci + h4 * qv.y);
-            wo = make_double2(wn.x + h * cr, wn.y + h * ci);
+            wo = form == 1 ? make_double2(wn.x + h * cr, wn.y + h * ci)
+                           : make_double2(wt.x + h2 * cr - h4 * qv.x, wt.y + h2 * ci - h4 * qv.y);
             d = make_double2(f.x - wt.x, f.y - wt.y);
             F[o] = f;
             Wout[o] = wo;

@@ -40,6 +40,7 @@ SIGNATURES = {
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_set_split_slices_lower": (_c_int, [_vp, _c_int]),
+    "ze_set_update_form": (_c_int, [_vp, _c_int]),
     "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
@@ -52,6 +53,7 @@ SIGNATURES = {
     "ze_ensemble_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_split_slices_lower": (_c_int, [_vp, _c_int]),
+    "ze_ensemble_set_update_form": (_c_int, [_vp, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -243,6 +245,12 @@ class Zeuler:
         8192, 3 at 16384; the int32 exactness bound)."""
         _check(self.lib.ze_set_split_slices(self._ctx, int(slices)), "ze_set_split_slices")
 
+    def set_update_form(self, form: int):
+        """How W_{n+1} is formed: 0 (default) the second line of eq. (isomp) at the last
+        iterate; 1 W_n + h (A - A^H), which conserves the spectrum to O(h ||P|| r) at a stopped
+        iterate and lets the polynomial start take one evaluation per step."""
+        _check(self.lib.ze_set_update_form(self._ctx, int(form)), "ze_set_update_form")
+
     def set_split_slices_lower(self, slices: int):
         """Slices of the lower product Q = A P (2 .. the product's slices; default one fewer,
         since Q's term enters the map with h^2/4 against h/2)."""
@@ -324,6 +332,11 @@ class Ensemble:
         """Slices per operand of the ensemble's PREC_SPLIT products (2 .. s_max of the largest N)."""
         _check(self.lib.ze_ensemble_set_split_slices(self._ens, int(slices)),
                "ze_ensemble_set_split_slices")
+
+    def set_update_form(self, form: int):
+        """Form of W_{n+1} for the ensemble's steps (as Zeuler.set_update_form)."""
+        _check(self.lib.ze_ensemble_set_update_form(self._ens, int(form)),
+               "ze_ensemble_set_update_form")
 
     def set_split_slices_lower(self, slices: int):
         """Slices of the ensemble's lower products (2 .. the product's slices)."""

@@ -74,6 +74,14 @@ def test_n4096_steps_fp64_and_split(dev):
     its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_MIXED)
     W = to_host(Wd)
     assert its == it_ref and rel(W, Wr) < 1e-12, (its, rel(W, Wr))
+    # the timed headline form: W_{n+1} = W_n + h (A - A^H)
+    Wd_r, itd, _ = O.isomp_run(W0, h, steps, cfg["tol"], cfg["maxit"], extrapolate=True, degree=3,
+                               update="difference")
+    z.set_update_form(1)
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_FP64)
+    W = to_host(Wd)
+    assert its == itd and max(res) < cfg["tol"] and rel(W, Wd_r) < 1e-12, (its, itd)
     z.close()
 
 

@@ -591,17 +591,20 @@ def test_isomp_composed_split_and_fixed_iterations(dev):
 
 
 # ------------------------------------------------------------------ polynomial starting iterates
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("N,law,h,steps", [(64, "inv1", 0.01, 12), (130, "inv1.5", 0.005, 10),
                                            (256, "inv1.5", 0.005, 9)])
-def test_isomp_run_polynomial_guess(dev, N, law, h, steps):
-    """Mode 2 (cubic extrapolation of the run's midpoints): the same evaluation counts per step
-    as the oracle's run (one evaluation after the start-up) and the same W to 1e-12; a second
-    run call restarts the history (its first step starts from W_n again)."""
+def test_isomp_run_polynomial_guess(dev, N, law, h, steps, form):
+    """Mode 2 (cubic extrapolation of the run's midpoints), with either form of W_{n+1}: the
+    same evaluation counts per step as the oracle's run of that form and the same W to 1e-12;
+    a second run call restarts the history (its first step starts from W_n again)."""
+    upd = ("second_line", "difference")[form]
     W0 = w0(N, 4, law)
-    Wr, it_ref, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3)
-    W2r, it2, _ = O.isomp_run(Wr, h, 3, 1e-12, 50, extrapolate=True, degree=3)
+    Wr, it_ref, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3, update=upd)
+    W2r, it2, _ = O.isomp_run(Wr, h, 3, 1e-12, 50, extrapolate=True, degree=3, update=upd)
     Wd = to_dev(W0)
     with ctx(N) as z:
+        z.set_update_form(form)
         z.set_initial_guess(2)
         its, res = z.isomp_run(Wd, h, steps, 1e-12, 50)
         W = to_host(Wd)
@@ -615,15 +618,20 @@ def test_isomp_run_polynomial_guess(dev, N, law, h, steps):
 
 
 def test_isomp_polynomial_guess_split_and_mode_errors(dev):
-    """Mode 2 with the split-precision products (5 slices) against the oracle's FP64 run (1e-10);
-    mode 2 and orders 4 / 6 exclude each other."""
+    """Mode 2 with the split-precision products (5 slices) and the difference form of W_{n+1}
+    against the oracle's FP64 run (1e-10), one evaluation per step at the end; mode 2 and
+    orders 4 / 6 exclude each other; update forms other than 0 and 1 are rejected."""
     from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
 
     N, h = 128, 0.005
     W0 = w0(N, 0)
-    Wr, _, _ = O.isomp_run(W0, h, 10, 1e-12, 50, extrapolate=True, degree=3)
+    Wr, _, _ = O.isomp_run(W0, h, 10, 1e-12, 50, extrapolate=True, degree=3, update="difference")
     with ctx(N) as z:
         z.set_split_slices(5)
+        z.set_update_form(1)
+        for bad in (-1, 2):
+            with pytest.raises(ZeulerError):
+                z.set_update_form(bad)
         z.set_initial_guess(2)
         Wd = to_dev(W0)
         its, res = z.isomp_run(Wd, h, 10, 1e-12, 50, prec=PREC_SPLIT)
@@ -638,8 +646,8 @@ def test_isomp_polynomial_guess_split_and_mode_errors(dev):
     assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "split"])
-def test_ensemble_polynomial_guess(dev, prec_name):
+@pytest.mark.parametrize("prec_name,form", [("fp64", 0), ("split", 0), ("fp64", 1), ("split", 1)])
+def test_ensemble_polynomial_guess(dev, prec_name, form):
     """Guess mode 2 in the ensemble (one graph; the step index of the run read on the device):
     after 7 steps every simulation matches the oracle's run with the polynomial start (FP64:
     1e-12 and the same evaluation count on the last step; split, 5 slices: 1e-10), and a
@@ -649,11 +657,13 @@ def test_ensemble_polynomial_guess(dev, prec_name):
     sizes = [64, 40, 96, 130]
     h, tol, K, steps = 0.005, 1e-12, 8, 7
     split = prec_name == "split"
+    upd = ("second_line", "difference")[form]
     W0s = [w0(n, 70 + j) for j, n in enumerate(sizes)]
-    refs = [O.isomp_run(W, h, steps, tol, K, extrapolate=True, degree=3) for W in W0s]
-    refs2 = [O.isomp_run(r[0], h, 2, tol, K, extrapolate=True, degree=3) for r in refs]
+    refs = [O.isomp_run(W, h, steps, tol, K, extrapolate=True, degree=3, update=upd) for W in W0s]
+    refs2 = [O.isomp_run(r[0], h, 2, tol, K, extrapolate=True, degree=3, update=upd) for r in refs]
     Wd = [to_dev(W) for W in W0s]
     with Ensemble(sizes) as ens:
+        ens.set_update_form(form)
         if split:
             ens.set_split_slices(5)
         ens.set_initial_guess(2)
