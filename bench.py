@@ -123,6 +123,7 @@ def ensemble_leg(nsteps, prec, slices=4, ref=None):
     Wseq = [W.clone() for W in Ws]
     ens = Ensemble(sizes)
     ens.set_initial_guess(2)  # polynomial start from the run's midpoints (reading 9)
+    ens.set_update_form(1)    # W_{n+1} = W_n + h (A - A^H) (reading 12)
     if split:
         ens.set_split_slices(slices)
         for z in ctxs.values():
@@ -144,6 +145,7 @@ def ensemble_leg(nsteps, prec, slices=4, ref=None):
     t1 = time.perf_counter()
     for j, n in enumerate(sizes):
         ctxs[n].set_initial_guess(2)
+        ctxs[n].set_update_form(1)
         ctxs[n].isomp_run(Wseq[j], h, seq_steps, tol, K, prec=prec)
     torch.cuda.synchronize()
     dts = time.perf_counter() - t1
@@ -189,6 +191,7 @@ def small_leg(steps):
     z = Zeuler(N)
     W0 = z.basis_assemble(omega_coeffs(N, cfg["seeds"][0], cfg["law"]))
     z.set_initial_guess(2)
+    z.set_update_form(1)
     W = W0.clone()
     z.isomp_run(W, h, 2, tol, cfg["maxit"])
     W = W0.clone()
@@ -200,6 +203,7 @@ def small_leg(steps):
     Wg = W0.clone()
     with Ensemble([N]) as ens:
         ens.set_initial_guess(2)
+        ens.set_update_form(1)
         ens.run([Wg.clone()], h, 2, tol, 8, prec=PREC_FP64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -215,7 +219,7 @@ def small_leg(steps):
         "graph_ensemble_of_one_s_per_step": dtg / steps,
         "rel_frobenius_between_the_two": diff,
         "note": "both forms start the steps after the first from the polynomial extrapolation "
-                "of the run's midpoints (mode 2)",
+                "of the run's midpoints (mode 2) and form W_{n+1} = W_n + h (A - A^H)",
     }
 
 
@@ -237,6 +241,7 @@ def long_leg(steps):
     W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
     W /= float(np.linalg.norm(W.cpu().numpy(), 2))  # input recipe: unit spectral norm
     z.set_initial_guess(2)
+    z.set_update_form(1)
     nf0 = float(torch.linalg.norm(W).item())
 
     def diag():
@@ -270,10 +275,13 @@ def long_leg(steps):
     slope = float(np.polyfit(np.log(l[sel]), np.log(E[sel]), 1)[0]) if sel.sum() > 2 else None
     # the same run from W_n at every step and from the linear start, drift at the end only
     other = {}
-    for name, mode in (("start_from_Wn_every_step", 0), ("linear_start", 1)):
+    for name, mode, form in (("start_from_Wn_every_step", 0, 0), ("linear_start", 1, 0),
+                             ("polynomial_start_second_line_form", 2, 0),
+                             ("linear_start_difference_form", 1, 1)):
         W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
         W /= float(np.linalg.norm(W.cpu().numpy(), 2))
         z.set_initial_guess(mode)
+        z.set_update_form(form)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its0, res0 = z.isomp_run(W, h, steps, tol, cfg["maxit"])
@@ -298,6 +306,10 @@ def long_leg(steps):
         "mean_iters_per_step": it_sum / steps,
         "start_from_Wn_every_step": other["start_from_Wn_every_step"],
         "linear_start": other["linear_start"],
+        "polynomial_start_second_line_form": other["polynomial_start_second_line_form"],
+        "linear_start_difference_form": other["linear_start_difference_form"],
+        "update_forms": "main run: W_{n+1} = W_n + h (A - A^H); the comparison runs name theirs "
+                        "(second line: the default, the second line of eq. (isomp))",
         "note": "Casimirs by ze_casimirs, energy by ze_basis_extract + ze_energy_spectrum, "
                 "sampled between timed chunks (not in s_per_step)",
     }
@@ -319,6 +331,7 @@ def orders_leg():
     W0 = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
     W0 /= float(np.linalg.norm(W0.cpu().numpy(), 2))
     z.set_initial_guess(1)
+    z.set_update_form(1)
 
     def run(order, h):
         n = int(round(T / h))
@@ -343,7 +356,7 @@ def orders_leg():
     z.close()
     return {
         "workload": f"orders512: N={N}, sigma_l law paper (seed {cfg['seed']}), unit spectral "
-                    f"norm, t = 0 .. {T}, tol={tol}, extrapolated substep starts",
+                    f"norm, t = 0 .. {T}, tol={tol}, extrapolated substep starts, W_{{n+1}} = W_n + h C",
         "reference": {"order": 6, "h": cfg["h_ref"], "evaluations": e_ref, "max_resid": r_ref},
         "runs": rows,
         "note": "error is against the order-6 reference run (self-convergence), not an exact solution",
@@ -379,8 +392,9 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
     c0 = z.casimirs(W, 4)
     W0 = W.clone()
 
-    def timed_run(Wx, prec, guess):
+    def timed_run(Wx, prec, guess, form=1):
         """Warm-up run, then one timed ze_isomp_run of `steps` steps on Wx (in place)."""
+        z.set_update_form(form)
         z.set_initial_guess(guess)
         Ww = Wx.clone()
         z.isomp_run(Ww, h, max(warmup, 1), tol, maxit, prec)
@@ -396,21 +410,27 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
         z.profile(False)
         return dtx, its, res, prof
 
-    # W~ starts from W_n in every step (the default reading of the paper)
+    # the default readings: W~ starts from W_n, W_{n+1} from the second line of eq. (isomp)
     Wp = W0.clone()
-    dt_plain, iters_plain, _, _ = timed_run(Wp, PREC_FP64, 0)
+    dt_plain, iters_plain, _, _ = timed_run(Wp, PREC_FP64, 0, 0)
     log(f"{wname} fp64, start W_n: {dt_plain / steps * 1e3:.2f} ms/step, iters={iters_plain}")
     # steps after the first start from 2 W_n - F_prev
     Wl = W0.clone()
-    dt_lin, iters_lin, _, _ = timed_run(Wl, PREC_FP64, 1)
+    dt_lin, iters_lin, _, _ = timed_run(Wl, PREC_FP64, 1, 0)
     log(f"{wname} fp64, linear start: {dt_lin / steps * 1e3:.2f} ms/step, iters={iters_lin}")
-    # headline: polynomial extrapolation of the run's previous midpoints
-    dt, iters, resids, prof = timed_run(W, PREC_FP64, 2)
+    # polynomial start with the second-line form of W_{n+1}
+    Ws2 = W0.clone()
+    dt_p0, iters_p0, _, _ = timed_run(Ws2, PREC_FP64, 2, 0)
+    log(f"{wname} fp64, polynomial start, second-line form: {dt_p0 / steps * 1e3:.2f} ms/step, "
+        f"iters={iters_p0}")
+    # headline: polynomial extrapolation of the run's previous midpoints, W_{n+1} = W_n + h C
+    dt, iters, resids, prof = timed_run(W, PREC_FP64, 2, 1)
     log(f"{wname} fp64, polynomial start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
     c1 = z.casimirs(W, 4)
     plain_vs_extrap = float(torch.linalg.norm(Wp - W).item() / torch.linalg.norm(W).item())
     lin_vs_extrap = float(torch.linalg.norm(Wl - W).item() / torch.linalg.norm(W).item())
-    del Wl
+    p0_vs_extrap = float(torch.linalg.norm(Ws2 - W).item() / torch.linalg.norm(W).item())
+    del Wl, Ws2
     if copy_probe_mib > 0:
         n = copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -471,6 +491,9 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
                                "rel_frobenius_vs_headline_run": plain_vs_extrap},
         "fp64_linear_start": {"s_per_step": dt_lin / steps, "iters_per_step": list(iters_lin),
                               "rel_frobenius_vs_headline_run": lin_vs_extrap},
+        "fp64_polynomial_start_second_line_form": {
+            "s_per_step": dt_p0 / steps, "iters_per_step": list(iters_p0),
+            "rel_frobenius_vs_headline_run": p0_vs_extrap},
         "split_precision": split,
         "mixed_precision": mixed,
     }
@@ -624,6 +647,10 @@ def main():
                          "every step still iterates until the change is below tol",
         "fp64_start_from_Wn": m["fp64_start_from_Wn"],
         "fp64_linear_start": m["fp64_linear_start"],
+        "fp64_polynomial_start_second_line_form": m["fp64_polynomial_start_second_line_form"],
+        "update_form": "W_{n+1} = W_n + h (A - A^H) (ze_set_update_form 1; the two lines of "
+                       "eq. (isomp) differ by exactly h [P~, W~]); the W_n, linear and "
+                       "second-line-form runs use the default form, the second line of eq. (isomp)",
         "casimir_drift_rel": m["casimir_drift_rel"],
         "phases": phases_of(prof),
         "gemm_flops_per_step": sum(iters) / len(iters) * 12.0 * N ** 3,
