@@ -126,23 +126,36 @@ def composition_weights(order: int) -> list:
 
 
 def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: float = 1e-12,
-                       maxit: int = 50, extrapolate: bool = False, update: str = "second_line"):
+                       maxit: int = 50, extrapolate: bool = False, update: str = "second_line",
+                       degree: int = 1):
     """nsteps steps of the composition of ``order`` from W0: each step is one midpoint substep
     of size c_j h for every c_j of ``composition_weights(order)``, in that order.  Returns
-    (W, [evaluations per step], [largest substep residual per step])."""
+    (W, [evaluations per step], [largest substep residual per step]).
+
+    With ``extrapolate`` a substep starts from W + rho (W - F_prev) (the previous substep's
+    midpoint F_prev, rho the ratio of the two substeps); with ``degree`` d >= 2 as well, substep
+    j of a step with k >= 2 earlier steps in the run starts from the polynomial of degree
+    min(k - 1, d) through the last min(k, d + 1) midpoints of substep j (equally spaced, one
+    step apart).  For order 2 this is ``isomp_run``'s start."""
+    if degree not in (1, 2, 3):
+        raise ValueError("degree must be 1, 2 or 3")
     w = composition_weights(order)
     W = np.asarray(W0, dtype=np.complex128).copy()
     iters, res = [], []
     mid, prev = None, None
+    hist = [[] for _ in w]
     for _ in range(nsteps):
         its, rmax = 0, 0.0
-        for c in w:
+        for j, c in enumerate(w):
             guess = None
-            if extrapolate and mid is not None:
+            if extrapolate and degree >= 2 and len(hist[j]) >= 2:
+                guess = extrapolate_midpoints(hist[j], min(len(hist[j]) - 1, degree))
+            elif extrapolate and mid is not None:
                 rho = c / prev
                 guess = 2.0 * W - mid if rho == 1.0 else W + rho * (W - mid)
             W, k, r, mid = isomp_step(W, c * h, tol, maxit, guess=guess, return_midpoint=True,
                                       update=update)
+            hist[j] = (hist[j] + [mid])[-(degree + 1):]
             prev = c
             its += k
             rmax = max(rmax, r)

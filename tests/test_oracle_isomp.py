@@ -295,3 +295,24 @@ def test_polynomial_start_one_evaluation_same_fixed_point():
     assert np.linalg.norm(Wa - Wc) < 1e-12 * np.linalg.norm(Wa)
     with pytest.raises(ValueError):
         O.isomp_run(W, 0.005, 1, degree=4)
+
+
+def test_composition_polynomial_substep_starts():
+    """Per-substep polynomial starts: for order 2 the composed run is the midpoint run with the
+    same start, bit for bit; for orders 4 and 6 (difference form) every substep takes one
+    evaluation after the start-up and the trajectory matches the W_n-started one to 1e-12."""
+    W = w0(64, 0)
+    for d in (2, 3):
+        for u in ("second_line", "difference"):
+            a = O.isomp_run(W, 0.01, 7, 1e-12, 50, extrapolate=True, degree=d, update=u)
+            b = O.isomp_composed_run(W, 0.01, 7, 2, 1e-12, 50, extrapolate=True, update=u, degree=d)
+            assert a[1] == b[1] and np.array_equal(a[0], b[0])
+    W = O.assemble(128, omega_coeffs(128, 0, "inv1.5"))
+    for order, ns in ((4, 3), (6, 9)):
+        Wa, ia, _ = O.isomp_composed_run(W, 0.02, 8, order, 1e-12, 50, update="difference")
+        Wb, ib, rb = O.isomp_composed_run(W, 0.02, 8, order, 1e-12, 50, extrapolate=True,
+                                          update="difference", degree=3)
+        assert all(k == ns for k in ib[4:]) and max(rb) < 1e-12, ib
+        assert np.linalg.norm(Wa - Wb) < 1e-12 * np.linalg.norm(Wa)
+    with pytest.raises(ValueError):
+        O.isomp_composed_run(W, 0.02, 1, 4, degree=0)
