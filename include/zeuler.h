@@ -128,14 +128,17 @@ ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, in
  *           approximates W half a step ahead, so this linear extrapolation is second-order
  *           accurate and usually saves one evaluation per step; the iteration still runs
  *           to the same tolerance and reaches the same fixed point.
- *   mode 2  (order 2 only) the converged midpoints of one run are equally spaced samples of
- *           a smooth curve: the second step starts as in mode 1, the k-th (k >= 3) from the
- *           polynomial of degree min(k - 2, 3) through the last min(k - 1, 4) midpoints,
- *           one step ahead (c = (2, -1), (3, -3, 1), (4, -6, 4, -1), newest first).  Its error
- *           is O(h^4), usually below tol, so after the start-up a step takes one evaluation.
- *           Selecting it allocates three more N x N complex buffers (kept until ze_destroy).
+ *   mode 2  the converged midpoints of one run are equally spaced samples of a smooth curve:
+ *           the second step starts as in mode 1, the k-th (k >= 3) from the polynomial of
+ *           degree min(k - 2, 3) through the last min(k - 1, 4) midpoints, one step ahead
+ *           (c = (2, -1), (3, -3, 1), (4, -6, 4, -1), newest first).  Its error is O(h^4),
+ *           usually below tol, so after the start-up a step takes one evaluation (with
+ *           ze_set_update_form 1).  At order 4 or 6 (ze_set_order) each substep extrapolates
+ *           from its own midpoints of the earlier steps (the other substeps of the first
+ *           step start as in mode 1).  Selecting it allocates 4 N x N complex buffers per
+ *           substep, less the one F already is (kept until ze_destroy).
  * Every mode restarts at the first step of each ze_isomp_run call.
- * Errors: ZE_EINVAL (also mode 2 while ze_set_order is 4 or 6), ZE_ENOMEM.
+ * Errors: ZE_EINVAL, ZE_ENOMEM.
  */
 ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
 
@@ -150,8 +153,9 @@ ze_status ze_set_initial_guess(ze_ctx* ctx, int mode);
  * Order 4 is 3 midpoint substeps per step (g2 < 0), order 6 the triple jump applied twice
  * (9 substeps).  With ze_set_initial_guess mode 1 every substep after the first of a call
  * starts from W + rho (W - F_prev), rho the ratio of its step to the previous substep's (also
- * inside a single ze_isomp_step).  The ensemble entry points always step at order 2.
- * Errors: ZE_EINVAL for any other order, and for 4 or 6 while ze_set_initial_guess is 2.
+ * inside a single ze_isomp_step); with mode 2 see ze_set_initial_guess.  The ensemble entry
+ * points always step at order 2.
+ * Errors: ZE_EINVAL for any other order, ZE_ENOMEM (mode 2's buffers for more substeps).
  */
 ze_status ze_set_order(ze_ctx* ctx, int order);
 

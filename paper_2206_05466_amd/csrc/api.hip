@@ -33,6 +33,23 @@ void dfree(void* p) {
 }  // namespace
 
 // Workspaces of the split-precision products, allocated on first use.
+ze_status ze_ensure_rings(ze_ctx* c, int ns) {
+    const size_t need = 4 * (size_t)ns, nn = (size_t)c->N * c->N;
+    const size_t had = c->ring.size();
+    if (had >= need) return ZE_OK;
+    c->ring.resize(need, nullptr);
+    for (size_t i = had; i < need; ++i) {
+        const ze_status st = dalloc(&c->ring[i], nn);
+        if (st != ZE_OK) {
+            for (size_t k = had; k < i; ++k) dfree(c->ring[k]);
+            c->ring.resize(had);
+            return st;
+        }
+    }
+    c->rhead.resize((size_t)ns, 0);
+    return ZE_OK;
+}
+
 ze_status ze_ensure_split(ze_ctx* c) {
     if (c->split_a) return ZE_OK;
     const size_t n = (size_t)c->N, ldk = (size_t)ze_split_ldk(c->N);
@@ -101,7 +118,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->fac_l);
     dfree(c->fac_dinv);
     dfree(c->Wn);
-    for (int i = 0; i < 4; ++i) dfree(c->Fring[i]);  // Fring[0] is the F allocation
+    for (double2* p : c->ring) dfree(p);  // ring[0] is the F allocation
     dfree(c->P);
     dfree(c->A);
     dfree(c->Q);
@@ -161,7 +178,8 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     if (st == ZE_OK) st = dalloc(&c->fac_dinv, fd.size());
     if (st == ZE_OK) st = dalloc(&c->Wn, nn);
     if (st == ZE_OK) st = dalloc(&c->F, nn);
-    c->Fring[0] = c->F;
+    c->ring.assign(1, c->F);
+    c->rhead.assign(1, 0);
     if (st == ZE_OK) st = dalloc(&c->P, nn);
     if (st == ZE_OK) st = dalloc(&c->A, nn);
     if (st == ZE_OK) st = dalloc(&c->Q, nn);
@@ -292,26 +310,60 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     return ZE_OK;
 }
 
+// Start of substep j of the step with index n in the run, guess mode 2: the next slot of
+// substep j's ring receives the polynomial of degree min(nm - 1, 3) through that substep's
+// nm = min(n, 4) previous midpoints when nm >= 2 (with four, the slot is the oldest one's,
+// overwritten in place), else W + rho (W - F_prev) from the previous substep's midpoint F_prev
+// (in F) when there is one; the slot then becomes F and receives this substep's midpoint.
+ze_status ring_start(ze_ctx* c, const void* W, size_t j, int n, double rho, StartFrom* start) {
+    const int N = c->N;
+    double2** rg = c->ring.data() + 4 * j;
+    const int head = c->rhead[j], next = (head + 1) & 3;
+    double2* out = rg[next];
+    const int nm = n < 4 ? n : 4;
+    if (nm >= 2) {
+        const int d = nm - 1 < 3 ? nm - 1 : 3;
+        const double2* Fs[4];
+        for (int i = 0; i <= d; ++i) Fs[i] = rg[(head - i + 4) & 3];
+        ZE_HIP(launch_extrapolate_poly(Fs, d, out, N, c->stream));
+        *start = kFromF;
+    } else if (n > 0 || j > 0) {
+        ZE_HIP(hipMemcpyAsync(out, c->F, (size_t)N * N * sizeof(double2), hipMemcpyDeviceToDevice,
+                              c->stream));
+        ZE_HIP(launch_extrapolate(static_cast<const double2*>(W), out, N, rho, c->stream));
+        *start = kFromF;
+    } else {
+        *start = kFromWn;
+    }
+    c->rhead[j] = next;
+    c->F = out;
+    return ZE_OK;
+}
+
 // One step of the context's order: a midpoint substep of size c_j h for every fraction c_j.
-// With guess mode 1, every substep after the first of the call (and the first as well when
-// first_extrap is set) starts from W + rho (W - F_prev), rho = c_j / c_{j-1} (cyclically, so
-// 1 across a step boundary).  A substep that reaches maxit above tol still completes the step
-// (the fixed-iteration mode) and the step then reports ZE_ENOTCONV; any other error ends it.
-// iters: evaluations over all substeps; resid: the largest substep residual.
-ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                        bool first_extrap, int* iters, double* resid) {
+// n is the step's index in the run.  Guess mode 1: every substep after the first of the call
+// (n > 0 or j > 0) starts from W + rho (W - F_prev), rho = c_j / c_{j-1} (cyclically, so 1
+// across a step boundary), written over F_prev in place.  Guess mode 2: see ring_start.  A
+// substep that reaches maxit above tol still completes the step (the fixed-iteration mode)
+// and the step then reports ZE_ENOTCONV; any other error ends it.  iters: evaluations over all
+// substeps; resid: the largest substep residual.
+ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec, int n,
+                        int* iters, double* resid) {
+    if (!c || !W) return ZE_EINVAL;
     const std::vector<double>& w = c->comp_w;
     const size_t ns = w.size();
+    if (c->guess_mode == 2) ZE_TRY(ze_ensure_rings(c, (int)ns));
     int total = 0;
     double rmax = 0.0;
     ze_status out = ZE_OK;
     for (size_t j = 0; j < ns; ++j) {
-        const bool ex = c->guess_mode == 1 && (j > 0 || first_extrap);
         const double rho = w[j] / w[j == 0 ? ns - 1 : j - 1];
+        StartFrom start = kFromWn;
+        if (c->guess_mode == 1 && (j > 0 || n > 0)) start = kLinear;
+        if (c->guess_mode == 2) ZE_TRY(ring_start(c, W, j, n, rho, &start));
         int k = 0;
         double r = 0.0;
-        const ze_status st =
-            isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, ex ? kLinear : kFromWn, rho, &k, &r);
+        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, start, rho, &k, &r);
         total += k;
         if (!(r <= rmax)) rmax = r;  // keeps a NaN
         if (st == ZE_ENOTCONV) {
@@ -328,38 +380,12 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     return out;
 }
 
-// Mode 2 (order 2 only): the start of the step after `nmid` earlier steps of this run is put
-// in the next ring slot, which then becomes F: 2 W_n - F_1 after one step, else the polynomial
-// of degree min(nmid - 1, 3) through the midpoints F_1 (newest) .. F_{d+1}.  With four
-// midpoints the next slot is F_4's, overwritten in place.
-ze_status poly_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec, int nmid,
-                    int* iters, double* resid) {
-    if (!c || !W) return ZE_EINVAL;
-    if (nmid == 0) return isomp_step_impl(c, W, h, tol, maxit, prec, kFromWn, 1.0, iters, resid);
-    const int N = c->N;
-    const int next = (c->fhead + 1) & 3;
-    double2* out = c->Fring[next];
-    if (nmid == 1) {
-        ZE_HIP(hipMemcpyAsync(out, c->F, (size_t)N * N * sizeof(double2), hipMemcpyDeviceToDevice,
-                              c->stream));
-        ZE_HIP(launch_extrapolate(static_cast<const double2*>(W), out, N, 1.0, c->stream));
-    } else {
-        const int d = nmid - 1 < 3 ? nmid - 1 : 3;
-        const double2* Fs[4];
-        for (int j = 0; j <= d; ++j) Fs[j] = c->Fring[(c->fhead - j + 4) & 3];
-        ZE_HIP(launch_extrapolate_poly(Fs, d, out, N, c->stream));
-    }
-    c->fhead = next;
-    c->F = out;
-    return isomp_step_impl(c, W, h, tol, maxit, prec, kFromF, 1.0, iters, resid);
-}
-
 }  // namespace
 
 ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                         int* iters, double* resid) {
     if (!c) return ZE_EINVAL;
-    return composed_step(c, W, h, tol, maxit, prec, false, iters, resid);
+    return composed_step(c, W, h, tol, maxit, prec, 0, iters, resid);
 }
 
 ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps, int prec,
@@ -368,8 +394,7 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = c->guess_mode == 2 ? poly_step(c, W, h, tol, maxit, prec, n < 4 ? n : 4, &k, &r)
-                                          : composed_step(c, W, h, tol, maxit, prec, n > 0, &k, &r);
+        ze_status st = composed_step(c, W, h, tol, maxit, prec, n, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) return st;
@@ -457,19 +482,13 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
     if (!c || mode < 0 || mode > 2) return ZE_EINVAL;
-    if (mode == 2) {
-        if (c->order != 2) return ZE_EINVAL;
-        const size_t nn = (size_t)c->N * c->N;
-        for (int i = 1; i < 4; ++i)
-            if (!c->Fring[i]) ZE_TRY(dalloc(&c->Fring[i], nn));
-    }
+    if (mode == 2) ZE_TRY(ze_ensure_rings(c, (int)c->comp_w.size()));
     c->guess_mode = mode;
     return ZE_OK;
 }
 
 ze_status ze_set_order(ze_ctx* c, int order) {
     if (!c || (order != 2 && order != 4 && order != 6)) return ZE_EINVAL;
-    if (order != 2 && c->guess_mode == 2) return ZE_EINVAL;
     // Triple jump (Yoshida 1990): from a symmetric method of even order p, the substeps
     // g1, g2, g1 with g1 = 1 / (2 - 2^(1/(p+1))) and g2 = 1 - 2 g1 give order p + 2.
     std::vector<double> w{1.0};
@@ -481,6 +500,7 @@ ze_status ze_set_order(ze_ctx* c, int order) {
             for (double x : w) next.push_back(g * x);
         w.swap(next);
     }
+    if (c->guess_mode == 2) ZE_TRY(ze_ensure_rings(c, (int)w.size()));
     c->comp_w = w;
     c->order = order;
     return ZE_OK;

@@ -795,16 +795,11 @@ ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
     if (!e || mode < 0 || mode > 2) return ZE_EINVAL;
     if (mode == 2 && !e->hp[0].H1) {  // history buffers, 3 per simulation
         ZE_HIP(hipStreamSynchronize(e->own));
+        for (int i = 0; i < e->nsim; ++i) ZE_TRY(ze_ensure_rings(e->ctx[i], 1));
         for (int i = 0; i < e->nsim; ++i) {
-            ze_ctx* c = e->ctx[i];
-            const size_t nn = (size_t)c->N * c->N;
-            for (int j = 1; j < 4; ++j)
-                if (!c->Fring[j]) ZE_TRY(ens_alloc(&c->Fring[j], nn));
-        }
-        for (int i = 0; i < e->nsim; ++i) {
-            e->hp[i].H1 = e->ctx[i]->Fring[1];
-            e->hp[i].H2 = e->ctx[i]->Fring[2];
-            e->hp[i].H3 = e->ctx[i]->Fring[3];
+            e->hp[i].H1 = e->ctx[i]->ring[1];
+            e->hp[i].H2 = e->ctx[i]->ring[2];
+            e->hp[i].H3 = e->ctx[i]->ring[3];
         }
         ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
     }

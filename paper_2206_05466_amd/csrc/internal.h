@@ -76,10 +76,11 @@ struct ze_ctx {
     // (F = the previous step's converged midpoint, left in ze_ctx::F), 2 = the polynomial
     // extrapolation of the last (up to 4) midpoints of the run.
     int guess_mode = 0;
-    // Midpoint history of mode 2: a ring of 4 buffers (Fring[0] is the allocation F starts
-    // with; the others are allocated when mode 2 is first selected), F == Fring[fhead].
-    double2* Fring[4] = {nullptr, nullptr, nullptr, nullptr};
-    int fhead = 0;
+    // Midpoint history of mode 2: a ring of 4 buffers per substep of a step, ring[4 j + i]
+    // (ring[0] is the allocation F starts with; the others are allocated on first use); the
+    // newest midpoint of substep j is ring[4 j + rhead[j]].
+    std::vector<double2*> ring;
+    std::vector<int> rhead;
     // Order of the time step (2: the midpoint map; 4, 6: its symmetric compositions) and the
     // substep fractions c_j of one step.
     int order = 2;
@@ -198,3 +199,5 @@ hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, h
 // ahead; out may be Fs[d].
 hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out, int N,
                                    hipStream_t s);
+// Grows the context's midpoint rings to 4 buffers for each of ns substeps.
+ze_status ze_ensure_rings(ze_ctx* c, int ns);

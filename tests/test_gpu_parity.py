@@ -619,8 +619,8 @@ def test_isomp_run_polynomial_guess(dev, N, law, h, steps, form):
 
 def test_isomp_polynomial_guess_split_and_mode_errors(dev):
     """Mode 2 with the split-precision products (5 slices) and the difference form of W_{n+1}
-    against the oracle's FP64 run (1e-10), one evaluation per step at the end; mode 2 and
-    orders 4 / 6 exclude each other; update forms other than 0 and 1 are rejected."""
+    against the oracle's FP64 run (1e-10), one evaluation per step at the end; update forms
+    other than 0 and 1 and guess modes outside 0..2 are rejected."""
     from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
 
     N, h = 128, 0.005
@@ -637,11 +637,7 @@ def test_isomp_polynomial_guess_split_and_mode_errors(dev):
         its, res = z.isomp_run(Wd, h, 10, 1e-12, 50, prec=PREC_SPLIT)
         W = to_host(Wd)
         with pytest.raises(ZeulerError):
-            z.set_order(4)
-        z.set_initial_guess(0)
-        z.set_order(6)
-        with pytest.raises(ZeulerError):
-            z.set_initial_guess(2)
+            z.set_initial_guess(3)
     assert max(res) < 1e-12 and its[-1] == 1, its
     assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
 
@@ -763,3 +759,26 @@ def test_tiny_sizes_every_mode(dev, N):
         its, _ = z.isomp_run(Wd, h, 2, 1e-12, 50)
         assert its == it4
         assert np.linalg.norm(to_host(Wd) - W4) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("order,N,form,h", [(4, 64, 1, 0.01), (4, 100, 0, 0.01), (6, 48, 1, 0.005)])
+def test_isomp_composed_polynomial_guess(dev, order, N, form, h):
+    """Orders 4 and 6 with the per-substep polynomial starts (mode 2): the oracle's evaluation
+    counts per step and its W to 1e-12, for either form of W_{n+1}; with the difference form
+    every substep of the later steps takes one evaluation."""
+    upd = ("second_line", "difference")[form]
+    steps = 7
+    W0 = w0(N, 5, "inv1.5")
+    Wr, it_ref, _ = O.isomp_composed_run(W0, h, steps, order, 1e-12, 50, extrapolate=True,
+                                         update=upd, degree=3)
+    with ctx(N) as z:
+        z.set_order(order)
+        z.set_update_form(form)
+        z.set_initial_guess(2)
+        Wd = to_dev(W0)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 50)
+        W = to_host(Wd)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
+    if form == 1:
+        assert its[-1] == len(O.composition_weights(order)), its
