@@ -330,7 +330,7 @@ def orders_leg():
     z = Zeuler(N)
     W0 = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
     W0 /= float(np.linalg.norm(W0.cpu().numpy(), 2))
-    z.set_initial_guess(1)
+    z.set_initial_guess(2)
     z.set_update_form(1)
 
     def run(order, h):
@@ -356,7 +356,7 @@ def orders_leg():
     z.close()
     return {
         "workload": f"orders512: N={N}, sigma_l law paper (seed {cfg['seed']}), unit spectral "
-                    f"norm, t = 0 .. {T}, tol={tol}, extrapolated substep starts, W_{{n+1}} = W_n + h C",
+                    f"norm, t = 0 .. {T}, tol={tol}, polynomial substep starts, W_{{n+1}} = W_n + h C",
         "reference": {"order": 6, "h": cfg["h_ref"], "evaluations": e_ref, "max_resid": r_ref},
         "runs": rows,
         "note": "error is against the order-6 reference run (self-convergence), not an exact solution",
