@@ -57,10 +57,13 @@ constexpr int kCopyParts = 16;
 
 // Start of a step: W_n <- W and the first iterate F.  mode 0: F <- W_n; mode 1: F <- 2 W_n - F,
 // the linear extrapolation of the previous step's converged midpoint (still in F); mode 2: by
-// the step's index n in the run (*stepc): W_n at n = 0, the linear start at n = 1, else the
-// polynomial of degree d = min(n - 1, 3) through F (newest midpoint), H1, H2, H3 one step ahead
-// (coefficients (2, -1), (3, -3, 1), (4, -6, 4, -1), summed in that order), while the history
-// moves down one place (H3 <- H2, H2 <- H1, H1 <- F; entries not yet written are never read).
+// the step's index n in the run (*stepc): W_n at n = 0, 2 W_n - H1 at n = 1, else the
+// polynomial of degree d = min(n - 1, 3) through the midpoints H1 (newest), H2, H3 and F (the
+// oldest, overwritten in place) one step ahead (coefficients (2, -1), (3, -3, 1),
+// (4, -6, 4, -1), summed in that order).  In mode 2 the four buffers form a ring: at the end
+// of each step ens_stepc_kernel turns the descriptors (F, H1, H2, H3) <- (H3, F, H1, H2), so
+// the midpoint just written to F becomes H1 and the oldest slot becomes the next F; entries
+// not yet written in this run are never read.
 // Every evaluation then reads its iterate from F (the update rewrites it in place: each entry
 // it reads is written by the same thread, and the mirrored upper entries it writes are read by
 // no other block of that launch).
@@ -82,34 +85,45 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
             p.F[e] = w;
             continue;
         }
-        const double2 f = p.F[e];
         double2 g;
-        if (n == 1) {
+        if (mode == 1) {
+            const double2 f = p.F[e];
             g = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
+        } else if (n == 1) {
+            const double2 f1 = p.H1[e];
+            g = make_double2(2.0 * w.x - f1.x, 2.0 * w.y - f1.y);
         } else {
-            const double2 h1 = p.H1[e];
-            g = make_double2(c1 * f.x, c1 * f.y);
-            g = make_double2(g.x + c2 * h1.x, g.y + c2 * h1.y);
+            const double2 f1 = p.H1[e], f2 = p.H2[e];
+            g = make_double2(c1 * f1.x, c1 * f1.y);
+            g = make_double2(g.x + c2 * f2.x, g.y + c2 * f2.y);
             if (n >= 3) {
-                const double2 h2 = p.H2[e];
-                g = make_double2(g.x + c3 * h2.x, g.y + c3 * h2.y);
+                const double2 f3 = p.H3[e];
+                g = make_double2(g.x + c3 * f3.x, g.y + c3 * f3.y);
                 if (n >= 4) {
-                    const double2 h3 = p.H3[e];
-                    g = make_double2(g.x - h3.x, g.y - h3.y);
+                    const double2 f4 = p.F[e];
+                    g = make_double2(g.x - f4.x, g.y - f4.y);
                 }
-                p.H3[e] = h2;
             }
-            p.H2[e] = h1;
         }
-        if (mode == 2) p.H1[e] = f;
         p.F[e] = g;
     }
     if (part == 0 && threadIdx.x == 0) done[sim] = 0;
 }
 
-// Step index of mode 2: set before the first step of a run, advanced at the end of each step.
-__global__ __launch_bounds__(64) void ens_stepc_kernel(int* __restrict__ stepc, int set) {
-    if (threadIdx.x == 0) stepc[0] = set >= 0 ? set : stepc[0] + 1;
+// Step index of mode 2: set before the first step of a run (set >= 0), or advanced at the end
+// of each step (set < 0), when each simulation's midpoint ring also turns (see ens_begin_kernel).
+__global__ __launch_bounds__(64) void ens_stepc_kernel(int* __restrict__ stepc, int set,
+                                                       EnsProb* __restrict__ probs, int nsim) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (set < 0 && i < nsim) {
+        EnsProb& p = probs[i];
+        double2* oldest = p.H3;
+        p.H3 = p.H2;
+        p.H2 = p.H1;
+        p.H1 = p.F;
+        p.F = oldest;
+    }
+    if (i == 0) stepc[0] = set >= 0 ? set : stepc[0] + 1;
 }
 
 template <int T, int C, int BD>
@@ -453,7 +467,8 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
                       e->resid, k, tol);
     }
     if (err == hipSuccess && mode == 2)
-        ZE_ENS_LAUNCH(ens_stepc_kernel, dim3(1), dim3(64), 0, s, e->stepc, -1);
+        ZE_ENS_LAUNCH(ens_stepc_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, s, e->stepc, -1,
+                      e->dp, e->nsim);
 #undef ZE_ENS_LAUNCH
     return err;
 }
@@ -755,7 +770,7 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
         e->g_guess != e->guess_mode)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
     if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
-        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0);
+        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0, e->dp, 0);
         ZE_HIP(hipGetLastError());
     }
     for (int n = 0; n < nsteps; ++n)
