@@ -199,6 +199,16 @@ def test_ensemble_argument_errors(dev):
             ens.set_split_slices(99)
         with pytest.raises(ZeulerError):
             ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], 0.01, 1, 1e-12, 0)  # K < 1
+        for bad in (-1, 3):
+            with pytest.raises(ZeulerError):
+                ens.set_initial_guess(bad)
+        for bad in (-1, 2):
+            with pytest.raises(ZeulerError):
+                ens.set_update_form(bad)
+        ens.set_split_slices(4)
+        for bad in (1, 5):
+            with pytest.raises(ZeulerError):
+                ens.set_split_slices_lower(bad)
 
 
 # ------------------------------------------------------------------ Casimirs
