@@ -55,7 +55,9 @@ typedef enum {
 /* Message for a status code (static string). */
 const char* ze_strerror(ze_status s);
 
-/* Last HIP error message recorded by the library in this thread ("" if none). */
+/* Last message recorded by the library in this thread ("" if none): the failing HIP call of a
+ * ZE_EHIP, or the measured values of a W refused by ze_set_validation (cleared at the start
+ * of each ze_isomp_step / ze_isomp_run). */
 const char* ze_last_error(void);
 
 /*
@@ -173,6 +175,17 @@ ze_status ze_set_order(ze_ctx* ctx, int order);
  * Errors: ZE_EINVAL.
  */
 ze_status ze_set_update_form(ze_ctx* ctx, int form);
+
+/*
+ * ze_set_validation -- input check of ze_isomp_step and ze_isomp_run (off by default: the
+ * inputs are assumed to lie in su(N), the phase space of eq. (Euler_vort_mat)).  With on = 1
+ * each call first checks its W on the GPU, max |W_rc + conj(W_cr)| <= 1e-12 max |W_rc| and
+ * |tr W| <= 1e-12 N max |W_rc|, and returns ZE_EINVAL, with the measured values in
+ * ze_last_error, when W fails (or holds a NaN or Inf); W is then left unchanged.  The check
+ * reads W once and synchronises the stream.
+ * Errors: ZE_EINVAL (on not 0 or 1).
+ */
+ze_status ze_set_validation(ze_ctx* ctx, int on);
 
 /*
  * ze_casimirs -- C_k(W) = Tr(W^k), k = 1..kmax (eq. (W_pow)), in FP64, from powers of W

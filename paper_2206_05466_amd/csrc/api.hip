@@ -94,6 +94,27 @@ ze_status ze_record_hip(hipError_t e, const char* what) {
     return ZE_EHIP;
 }
 
+// Input check of ze_set_validation: W must be skew-Hermitian and traceless to 1e-12 relative,
+// max |W_rc + conj(W_cr)| <= 1e-12 max |W_rc| and |tr W| <= 1e-12 N max |W_rc| (non-finite
+// entries fail).  Synchronises the context's stream.
+static ze_status check_su(ze_ctx* c, const void* W) {
+    const int N = c->N, G = ze_su_check_blocks(N);
+    if (!c->val_part) ZE_TRY(dalloc(&c->val_part, 4 * (size_t)G + 4));
+    double* out = c->val_part + 4 * (size_t)G;
+    ZE_HIP(launch_su_check(static_cast<const double2*>(W), N, c->val_part, out, c->stream));
+    double h[4] = {0, 0, 0, 0};
+    ZE_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    ZE_HIP(hipStreamSynchronize(c->stream));
+    const double asym = h[0], amax = h[1], tr = std::hypot(h[2], h[3]);
+    if (asym <= 1e-12 * amax && tr <= 1e-12 * N * amax && std::isfinite(amax)) return ZE_OK;
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "W is not in su(N) to 1e-12: max|W + W^H| = %.3e, |tr W| = %.3e, max|W| = %.3e",
+                  asym, tr, amax);
+    g_last_error = msg;
+    return ZE_EINVAL;
+}
+
 extern "C" {
 
 const char* ze_strerror(ze_status s) {
@@ -134,6 +155,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->split_colmax);
     dfree(c->split_g);
     dfree(c->resid);
+    dfree(c->val_part);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -384,13 +406,23 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
 
 ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                         int* iters, double* resid) {
-    if (!c) return ZE_EINVAL;
+    g_last_error.clear();
+    if (!c || !W) return ZE_EINVAL;
+    if (c->validate) ZE_TRY(check_su(c, W));
     return composed_step(c, W, h, tol, maxit, prec, 0, iters, resid);
+}
+
+ze_status ze_set_validation(ze_ctx* c, int on) {
+    if (!c || on < 0 || on > 1) return ZE_EINVAL;
+    c->validate = on == 1;
+    return ZE_OK;
 }
 
 ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps, int prec,
                        int* iters, double* resid) {
+    g_last_error.clear();
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
+    if (c->validate && nsteps > 0) ZE_TRY(check_su(c, W));
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;

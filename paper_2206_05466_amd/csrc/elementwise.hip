@@ -45,7 +45,109 @@ __global__ __launch_bounds__(256) void extrapolate_poly_kernel(const double2* F1
     }
 }
 
+// Input check of W: block b takes the 32 x 32 tile pair (I, J), (J, I), I >= J, of the lower
+// triangle of tiles, staged in LDS so both are read row-wise, and writes part[4 b ..]: the
+// largest |W_rc + conj(W_cr)| of the pair, the largest |W_rc| of both tiles, and (diagonal
+// tiles only, else 0) the real and imaginary parts of the tile's trace, summed in a fixed order.
+constexpr int kVT = 32;
+__global__ __launch_bounds__(256) void su_check_kernel(const double2* __restrict__ W, int N,
+                                                      double* __restrict__ part) {
+    __shared__ double2 ta[kVT][kVT + 1], tb[kVT][kVT + 1];
+    __shared__ double r0[256], r1[256], r2[256], r3[256];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int J = b - I * (I + 1) / 2;
+    const int c = tid & 31;
+    for (int r = tid >> 5; r < kVT; r += 8) {
+        const int ra = I * kVT + r, ca = J * kVT + c, rb = J * kVT + r, cb = I * kVT + c;
+        ta[r][c] = (ra < N && ca < N) ? W[(size_t)ra * N + ca] : make_double2(0.0, 0.0);
+        tb[r][c] = (rb < N && cb < N) ? W[(size_t)rb * N + cb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double asym = 0.0, amax = 0.0, tre = 0.0, tim = 0.0;
+    for (int r = tid >> 5; r < kVT; r += 8) {
+        const double2 x = ta[r][c], y = tb[c][r], z = tb[r][c];  // y = W_cr for x = W_rc
+        const double dx = x.x + y.x, dy = x.y - y.y;             // W_rc + conj(W_cr)
+        const double d = sqrt(dx * dx + dy * dy);
+        asym = (d != d || d > asym) ? d : asym;
+        const double m = fmax(sqrt(x.x * x.x + x.y * x.y), sqrt(z.x * z.x + z.y * z.y));
+        amax = (m != m || m > amax) ? m : amax;
+        if (I == J && r == c) {
+            tre += x.x;
+            tim += x.y;
+        }
+    }
+    r0[tid] = asym;
+    r1[tid] = amax;
+    r2[tid] = tre;
+    r3[tid] = tim;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double a0 = r0[tid + s], a1 = r1[tid + s];
+            r0[tid] = (a0 != a0 || a0 > r0[tid]) ? a0 : r0[tid];
+            r1[tid] = (a1 != a1 || a1 > r1[tid]) ? a1 : r1[tid];
+            r2[tid] += r2[tid + s];
+            r3[tid] += r3[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[4 * (size_t)b] = r0[0];
+        part[4 * (size_t)b + 1] = r1[0];
+        part[4 * (size_t)b + 2] = r2[0];
+        part[4 * (size_t)b + 3] = r3[0];
+    }
+}
+
+// out[0..3] = the maxima and sums of su_check_kernel over its G blocks (fixed order).
+__global__ __launch_bounds__(256) void su_check_final(const double* __restrict__ part, int G,
+                                                     double* __restrict__ out) {
+    __shared__ double r0[256], r1[256], r2[256], r3[256];
+    const int tid = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int b = tid; b < G; b += 256) {
+        const double p0 = part[4 * (size_t)b], p1 = part[4 * (size_t)b + 1];
+        a0 = (p0 != p0 || p0 > a0) ? p0 : a0;
+        a1 = (p1 != p1 || p1 > a1) ? p1 : a1;
+        a2 += part[4 * (size_t)b + 2];
+        a3 += part[4 * (size_t)b + 3];
+    }
+    r0[tid] = a0;
+    r1[tid] = a1;
+    r2[tid] = a2;
+    r3[tid] = a3;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double b0 = r0[tid + s], b1 = r1[tid + s];
+            r0[tid] = (b0 != b0 || b0 > r0[tid]) ? b0 : r0[tid];
+            r1[tid] = (b1 != b1 || b1 > r1[tid]) ? b1 : r1[tid];
+            r2[tid] += r2[tid + s];
+            r3[tid] += r3[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid < 4) out[tid] = tid == 0 ? r0[0] : tid == 1 ? r1[0] : tid == 2 ? r2[0] : r3[0];
+}
+
 }  // namespace
+
+int ze_su_check_blocks(int N) {
+    const int T = (N + kVT - 1) / kVT;
+    return T * (T + 1) / 2;
+}
+
+hipError_t launch_su_check(const double2* W, int N, double* part, double* out, hipStream_t s) {
+    const int G = ze_su_check_blocks(N);
+    hipLaunchKernelGGL(su_check_kernel, dim3(G), dim3(256), 0, s, W, N, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(su_check_final, dim3(1), dim3(256), 0, s, part, G, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out, int N,
                                    hipStream_t s) {

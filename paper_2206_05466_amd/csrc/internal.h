@@ -87,6 +87,9 @@ struct ze_ctx {
     std::vector<double> comp_w{1.0};
     // Form of W_{n+1}: 0 the second line of eq. (isomp) at the last iterate, 1 W_n + h [P~, W~].
     int update_form = 0;
+    // Input check of ze_isomp_step / ze_isomp_run (ze_set_validation) and its buffers.
+    bool validate = false;
+    double* val_part = nullptr;
 
     // Optional per-phase timing (ze_profile).
     bool prof = false;
@@ -201,3 +204,7 @@ hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out
                                    hipStream_t s);
 // Grows the context's midpoint rings to 4 buffers for each of ns substeps.
 ze_status ze_ensure_rings(ze_ctx* c, int ns);
+// Input check of W (ze_set_validation): out[0..3] = max |W + W^H|, max |W|, Re tr W, Im tr W;
+// part holds 4 doubles per block of ze_su_check_blocks(N).
+int ze_su_check_blocks(int N);
+hipError_t launch_su_check(const double2* W, int N, double* part, double* out, hipStream_t s);

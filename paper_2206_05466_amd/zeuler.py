@@ -41,6 +41,7 @@ SIGNATURES = {
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_set_split_slices_lower": (_c_int, [_vp, _c_int]),
     "ze_set_update_form": (_c_int, [_vp, _c_int]),
+    "ze_set_validation": (_c_int, [_vp, _c_int]),
     "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
@@ -78,17 +79,17 @@ def load_library():
 
 
 class ZeulerError(RuntimeError):
-    def __init__(self, status: int, where: str):
+    def __init__(self, status: int, where: str, detail: bool = False):
         lib = load_library()
         msg = lib.ze_strerror(status).decode()
-        extra = lib.ze_last_error().decode() if status == ZE_EHIP else ""
+        extra = lib.ze_last_error().decode() if (status == ZE_EHIP or detail) else ""
         super().__init__(f"{where}: {msg}" + (f" ({extra})" if extra else ""))
         self.status = status
 
 
-def _check(status: int, where: str):
+def _check(status: int, where: str, detail: bool = False):
     if status != ZE_OK:
-        raise ZeulerError(status, where)
+        raise ZeulerError(status, where, detail)
 
 
 @dataclass
@@ -170,7 +171,7 @@ class Zeuler:
                                     int(prec), ctypes.byref(k), ctypes.byref(r))
         if st == ZE_ENOTCONV and allow_notconv:
             return StepInfo(k.value, r.value, False)
-        _check(st, "ze_isomp_step")
+        _check(st, "ze_isomp_step", detail=True)
         return StepInfo(k.value, r.value, True)
 
     def isomp_run(self, W, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
@@ -181,7 +182,7 @@ class Zeuler:
         st = self.lib.ze_isomp_run(self._ctx, self._mat(W, "W"), float(h), float(tol), int(maxit),
                                    int(nsteps), int(prec), its, res)
         if st not in (ZE_OK, ZE_ENOTCONV):
-            _check(st, "ze_isomp_run")
+            _check(st, "ze_isomp_run", detail=True)
         return list(its)[:nsteps], list(res)[:nsteps]
 
     def casimirs(self, W, kmax: int) -> np.ndarray:
@@ -244,6 +245,11 @@ class Zeuler:
         """Slices per operand of the PREC_SPLIT products (2 .. s_max(N): 8 up to N = 4096, 7 at
         8192, 3 at 16384; the int32 exactness bound)."""
         _check(self.lib.ze_set_split_slices(self._ctx, int(slices)), "ze_set_split_slices")
+
+    def set_validation(self, on: bool = True):
+        """Check the input W of isomp_step / isomp_run for skew-Hermitian and traceless to 1e-12
+        (relative to max |W_rc|) before stepping; a failing W raises ZeulerError."""
+        _check(self.lib.ze_set_validation(self._ctx, 1 if on else 0), "ze_set_validation")
 
     def set_update_form(self, form: int):
         """How W_{n+1} is formed: 0 (default) the second line of eq. (isomp) at the last

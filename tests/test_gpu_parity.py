@@ -792,3 +792,36 @@ def test_isomp_composed_polynomial_guess(dev, order, N, form, h):
     assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
     if form == 1:
         assert its[-1] == len(O.composition_weights(order)), its
+
+
+@pytest.mark.parametrize("N", [1, 33, 100])
+def test_input_validation(dev, N):
+    """ze_set_validation: a W in su(N) passes and steps as without the check; W with a
+    Hermitian part of 1e-9 relative, with a trace of 1e-6, or with a NaN is refused with
+    ZE_EINVAL and left unchanged; the check is off by default."""
+    from paper_2206_05466_amd import ZeulerError
+
+    W0 = w0(N, 3)
+    scale = max(np.abs(W0).max(), 1.0)
+    W1r, _, _ = O.isomp_step(W0, 0.01, 1e-12, 50)
+    bad_h = W0.copy()
+    bad_h[N - 1, 0] += 1e-9 * scale  # breaks W_rc = -conj(W_cr) (on the diagonal when N = 1)
+    bad_t = W0 + 1e-6 * scale * 1j * np.eye(N)
+    bad_n = W0.copy()
+    bad_n[0, N - 1] = np.nan
+    with ctx(N) as z:
+        Wd = to_dev(bad_h)
+        z.isomp_step(Wd, 0.01, 1e-12, 50)  # unchecked by default
+        z.set_validation(True)
+        Wd = to_dev(W0)
+        info = z.isomp_step(Wd, 0.01, 1e-12, 50)
+        assert info.converged
+        assert np.linalg.norm(to_host(Wd) - W1r) <= 1e-12 * max(np.linalg.norm(W1r), 1e-300)
+        for bad in (bad_h, bad_t, bad_n):
+            Wd = to_dev(bad)
+            with pytest.raises(ZeulerError, match="su"):
+                z.isomp_step(Wd, 0.01, 1e-12, 50)
+            with pytest.raises(ZeulerError):
+                z.isomp_run(Wd, 0.01, 2, 1e-12, 50)
+            got = to_host(Wd)
+            assert np.array_equal(got[~np.isnan(got)], bad[~np.isnan(bad)])
