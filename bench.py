@@ -71,6 +71,36 @@ def blas_threads():
         return os.cpu_count()
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def ensemble_cpu_baseline(sizes, law, seed0, h, evals):
+    """The oracle over the ensemble, one simulation after the other: one oracle step with
+    `evals` evaluations (tol = 0) timed for the first simulation of each size, weighted by how
+    many simulations have that size.  Returns oracle steps/s over the whole ensemble."""
+    import oracle
+    from workloads import omega_coeffs
+
+    total = 0.0
+    for n in sorted(set(sizes)):
+        j = sizes.index(n)
+        W0 = oracle.assemble(n, omega_coeffs(n, seed0 + j, law))
+        t0 = time.perf_counter()
+        oracle.isomp_step(W0, h, 0.0, evals)
+        total += (time.perf_counter() - t0) * sizes.count(n)
+    return {"value": len(sizes) / total, "unit": "steps/s", "cores": blas_threads(),
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"one oracle step with {evals} evaluation(s) per size class, weighted by the "
+                      f"class counts {[sizes.count(n) for n in sorted(set(sizes))]}"}
+
+
 def cpu_baseline(N, om_seed, law, h, mean_evals, lmax=32):
     """Oracle IsoMP step at the same N, scaled to the GPU run's mean number of evaluations.
 
@@ -96,6 +126,7 @@ def cpu_baseline(N, om_seed, law, h, mean_evals, lmax=32):
         "value": dt * mean_evals / K,
         "unit": "s/step",
         "cores": blas_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"1 oracle IsoMP step at N={N} with K={K} evaluations ({dt:.2f} s), scaled by "
                    f"{mean_evals:.3f}/{K} to the GPU run's mean evaluations per step; input "
@@ -104,7 +135,7 @@ def cpu_baseline(N, om_seed, law, h, mean_evals, lmax=32):
     }
 
 
-def ensemble_leg(nsteps, prec, slices=4, ref=None):
+def ensemble_leg(nsteps, prec, slices=4, ref=None, with_cpu=False):
     """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step.
     Returns the record and the final states; with `ref` (the FP64 leg's final states, same
     initial states and step count) the record carries the largest relative Frobenius distance
@@ -174,6 +205,9 @@ def ensemble_leg(nsteps, prec, slices=4, ref=None):
     }
     if dist is not None:
         rec["max_member_rel_frobenius_vs_fp64_ensemble"] = dist
+    if with_cpu:
+        ev = max(1, int(round(sum(its) / len(its))))
+        rec["cpu_baseline"] = ensemble_cpu_baseline(sizes, cfg["law"], cfg["seed0"], h, ev)
     return rec, Ws
 
 
@@ -593,7 +627,7 @@ def main():
 
     ens = None
     if args.ensemble_steps > 0:
-        rec64, ref = ensemble_leg(args.ensemble_steps, PREC_FP64)
+        rec64, ref = ensemble_leg(args.ensemble_steps, PREC_FP64, with_cpu=not args.no_cpu_baseline)
         ens = {"fp64": rec64,
                "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=4, ref=ref)[0]}
         del ref
