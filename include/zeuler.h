@@ -45,11 +45,19 @@ typedef enum {
                            (ze_set_split_slices), exact int32 slice products, FP64
                            accumulation; error ~2^(-8 s) relative to max|row| max|column| per
                            term of the inner sum */
-    ZE_PREC_MIXED = 2   /* ze_isomp_step / ze_isomp_run only: A = P W~ on FP64 MFMA, the lower
+    ZE_PREC_MIXED = 2,  /* ze_isomp_step / ze_isomp_run only: A = P W~ on FP64 MFMA, the lower
                            product Q = A P split as above with ze_set_split_slices_lower slices
                            (default 4).  Q's term enters the map with h^2/4, so its rounding
                            reaches the step at ~(h^2/4) 2^(-8 s_q) relative: at h = 0.005 and
                            s_q = 4 below the FP64 products' own rounding. */
+    ZE_PREC_CRT = 3     /* the modular form of the INT8 emulation (Ozaki scheme II): rows of
+                           A~ / columns of B~ scaled by powers of two to integers of b bits
+                           (b = 55 up to N = 4096, 54 beyond), residues modulo 16 pairwise
+                           coprime moduli <= 256, one exact INT8 product per modulus, and the
+                           Chinese remainder theorem; the only error is the rounding of the
+                           scaled inputs, 2^-b relative to the row / column maximum, i.e.
+                           FP64-level.  ze_zgemm, and in ze_isomp_step / ze_isomp_run the
+                           product A = P W~ (the lower product then as ZE_PREC_MIXED's). */
 } ze_prec;
 
 /* Message for a status code (static string). */
@@ -102,7 +110,7 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  *   h       time step (any finite sign).
  *   tol     stopping tolerance (>= 0; 0 runs exactly maxit evaluations).
  *   maxit   evaluation cap, >= 1.
- *   prec    ZE_PREC_FP64, ZE_PREC_SPLIT or ZE_PREC_MIXED.
+ *   prec    ZE_PREC_FP64, ZE_PREC_SPLIT, ZE_PREC_MIXED or ZE_PREC_CRT.
  *   iters   host, may be NULL: evaluations done (summed over the substeps of a step of
  *           order 4 or 6, see ze_set_order).
  *   resid   host, may be NULL: final residual (the largest over the substeps).

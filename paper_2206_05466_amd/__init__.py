@@ -5,9 +5,9 @@ The computation lives in ``libzeuler.so`` (HIP, gfx950; C ABI in ``include/zeule
 """
 
 from .zeuler import (
-    LIB_PATH, PREC_FP64, PREC_MIXED, PREC_SPLIT, SIGNATURES, Ensemble, StepInfo, Zeuler, ZeulerError,
+    LIB_PATH, PREC_CRT, PREC_FP64, PREC_MIXED, PREC_SPLIT, SIGNATURES, Ensemble, StepInfo, Zeuler, ZeulerError,
     load_library,
 )
 
-__all__ = ["LIB_PATH", "PREC_FP64", "PREC_MIXED", "PREC_SPLIT", "SIGNATURES", "Ensemble", "StepInfo", "Zeuler",
+__all__ = ["LIB_PATH", "PREC_CRT", "PREC_FP64", "PREC_MIXED", "PREC_SPLIT", "SIGNATURES", "Ensemble", "StepInfo", "Zeuler",
            "ZeulerError", "load_library"]

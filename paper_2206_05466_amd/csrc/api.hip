@@ -50,6 +50,31 @@ ze_status ze_ensure_rings(ze_ctx* c, int ns) {
     return ZE_OK;
 }
 
+ze_status ze_ensure_crt(ze_ctx* c) {
+    if (c->crt_g) return ZE_OK;
+    ZE_TRY(ze_ensure_split(c));  // exponent vectors and column-maximum partials
+    const size_t ldk = (size_t)ze_split_ldk(c->N);
+    const size_t bytes_a = (size_t)kCrtMods * split_rows_pad(c->N) * ldk;
+    const size_t bytes_b = (size_t)kCrtMods * split_cols_pad(c->N) * ldk;
+    ze_status st = dalloc(&c->crt_a, bytes_a);
+    if (st == ZE_OK) st = dalloc(&c->crt_b, bytes_b);
+    // zero padding rows once; the residue kernels never write them
+    if (st == ZE_OK &&
+        (hipMemsetAsync(c->crt_a, 0, bytes_a, c->stream) != hipSuccess ||
+         hipMemsetAsync(c->crt_b, 0, bytes_b, c->stream) != hipSuccess ||
+         hipStreamSynchronize(c->stream) != hipSuccess))
+        st = ze_record_hip(hipGetLastError(), "residue workspace clear");
+    if (st == ZE_OK) st = dalloc(&c->crt_g, ze_crt_slab_ints(c->N));
+    if (st != ZE_OK) {
+        dfree(c->crt_a);
+        dfree(c->crt_b);
+        dfree(c->crt_g);
+        c->crt_a = c->crt_b = nullptr;
+        c->crt_g = nullptr;
+    }
+    return st;
+}
+
 ze_status ze_ensure_split(ze_ctx* c) {
     if (c->split_a) return ZE_OK;
     const size_t n = (size_t)c->N, ldk = (size_t)ze_split_ldk(c->N);
@@ -154,6 +179,9 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->split_ec);
     dfree(c->split_colmax);
     dfree(c->split_g);
+    dfree(c->crt_a);
+    dfree(c->crt_b);
+    dfree(c->crt_g);
     dfree(c->resid);
     dfree(c->val_part);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
@@ -245,7 +273,13 @@ ze_status ze_stream_solve(ze_ctx* c, const void* W, void* P) {
 
 ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     if (!c || !A || !B || !C || C == A || C == B) return ZE_EINVAL;
-    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_CRT) return ZE_EINVAL;
+    if (prec == ZE_PREC_CRT) {
+        ZE_TRY(ze_ensure_crt(c));
+        ZE_HIP(launch_zgemm_crt(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
+                                static_cast<double2*>(C), c->stream));
+        return ZE_OK;
+    }
     if (prec == ZE_PREC_SPLIT) {
         ZE_TRY(ze_ensure_split(c));
         ZE_HIP(launch_zgemm_split(c, static_cast<const double2*>(A), static_cast<const double2*>(B),
@@ -268,12 +302,16 @@ enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                           StartFrom start, double rho, int* iters, double* resid) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
-    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED) return ZE_EINVAL;
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED &&
+        prec != ZE_PREC_CRT)
+        return ZE_EINVAL;
     const int N = c->N;
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
     const bool split = prec == ZE_PREC_SPLIT, mixed = prec == ZE_PREC_MIXED;
+    const bool crt = prec == ZE_PREC_CRT;
     if (split || mixed) ZE_TRY(ze_ensure_split(c));
+    if (crt) ZE_TRY(ze_ensure_crt(c));
     hipStream_t s = c->stream;
     ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
     const double2* Wt = c->Wn;
@@ -288,10 +326,12 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
         if (prof) ZE_HIP(hipEventRecord(c->ev[1], s));
         if (split)
             ZE_HIP(launch_zgemm_split(c, c->P, Wt, c->A, 0, c->split_ea, c->split_eb, false, s));
+        else if (crt)
+            ZE_HIP(launch_zgemm_crt(c, c->P, Wt, c->A, s));
         else
             ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[2], s));
-        if (split) {
+        if (split || crt) {
             // P is skew-Hermitian: its column exponents are the row exponents just taken
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, true, s));
             ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,

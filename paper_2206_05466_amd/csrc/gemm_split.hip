@@ -25,6 +25,19 @@
 //
 // Slices: A~ slices row-major [r][kk] (N x 2N bytes each); B~ slices transposed,
 // B~^T[cc][kk] (2N x 2N bytes each), which is the MFMA's B-operand order (K contiguous).
+//
+// Modular form (ZE_PREC_CRT; Ozaki scheme II: Ozaki, Uchino & Imamura, "Ozaki scheme II: a
+// GEMM-oriented emulation of floating-point matrix multiplication using an integer modular
+// technique", 2025).  Rows of A~ and columns of B~ are scaled by powers of two to integers of
+// at most b bits, exactly, up to the one rounding to an integer; their residues modulo 16
+// pairwise coprime moduli <= 256 take the place of the slices (same layouts), one exact INT8
+// product per modulus (the diagonal pairs of the INT8 kernel) gives each product modulo p_k,
+// and the Chinese remainder theorem recovers the integer product exactly, since b is chosen
+// so that 2N 2^(2b) < M / 2, M = prod p_k ~ 2^125.2.  The only error is the rounding of the
+// scaled inputs to integers, 2^-b relative to the row / column maximum, with b = 55 up to
+// N = 4096: FP64-level accuracy from 16 INT8 products where the sliced form needs 28.
+
+#include <cmath>
 
 #include "split_tile.h"
 #include "update_tile.h"
@@ -78,6 +91,46 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __r
     split_cols_tile(B, N, blockIdx.x, blockIdx.y, s, ldk, eb, slices, tile);
 }
 
+// Residue form of A~ (one block per row) and of B~^T (tiles as split_cols_kernel).
+__global__ __launch_bounds__(kThreads) void crt_rows_kernel(const double2* __restrict__ A, int N,
+                                                            int b, int ldk,
+                                                            signed char* __restrict__ slices,
+                                                            int* __restrict__ ea) {
+    __shared__ double red[kThreads];
+    crt_row_block(A, N, blockIdx.x, b, ldk, slices, ea, red);
+}
+
+__global__ __launch_bounds__(kThreads) void crt_cols_kernel(const double2* __restrict__ B, int N,
+                                                            int b, int ldk,
+                                                            const int* __restrict__ eb,
+                                                            signed char* __restrict__ slices) {
+    __shared__ double2 tile[kCT][kCT + 1];
+    crt_cols_tile(B, N, blockIdx.x, blockIdx.y, b, ldk, eb, slices, tile);
+}
+
+// C[e] from the residue products: both real parts of complex element e through the CRT, then
+// scaled by 2^(ea_r + eb_c - 2b).
+__global__ __launch_bounds__(kThreads) void crt_combine_kernel(const int* __restrict__ G,
+                                                               const int* __restrict__ ea,
+                                                               const int* __restrict__ eb,
+                                                               double2* __restrict__ Cm, int N,
+                                                               int b) {
+    const size_t n2 = (size_t)N * N, slab = 2 * n2;
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
+         e += (size_t)gridDim.x * kThreads) {
+        int gr[kCrtMods], gi[kCrtMods];
+#pragma unroll
+        for (int k = 0; k < kCrtMods; ++k) {
+            const int2 g = *reinterpret_cast<const int2*>(G + (size_t)k * slab + 2 * e);
+            gr[k] = g.x;
+            gi[k] = g.y;
+        }
+        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
+        const int sh = ea[r] + eb[c] - 2 * b;
+        Cm[e] = make_double2(ldexp(crt_reconstruct(gr), sh), ldexp(crt_reconstruct(gi), sh));
+    }
+}
+
 // mode 0: full product (tiles_m x tiles_n tiles), mode 1: lower-triangle tiles (ntiles of
 // them in i8_lower_tile's numbering).  Blocks b < full take one whole tile each; the
 // remaining tiles (a last, partial round of the GPU's block slots) are split along K: block
@@ -114,20 +167,20 @@ __device__ __forceinline__ void i8_tile_of(int mode, int tile, int tiles_n, int 
 
 __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
-    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S) {
+    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S, int diag) {
     __shared__ I8Smem sm;
     int ti, tj;
     const int b = blockIdx.x;
     if (b < full) {
         i8_tile_of(mode, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
         if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
-        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm);
+        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false, diag != 0);
     } else {
         const int e = b - full, p = e % S, nk = ldk / kI8BK;
         i8_tile_of(mode, full + e / S, tiles_n, ntiles, false, b, ti, tj);
         if (tj >= tiles_n) return;
         zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
-                      (int)((long long)(p + 1) * nk / S), true);
+                      (int)((long long)(p + 1) * nk / S), true, diag != 0);
     }
 }
 
@@ -244,13 +297,76 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     }
     hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
                        c->split_a, c->split_b, c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn,
-                       ntiles, full, S);
+                       ntiles, full, S, 0);
     e = hipGetLastError();
     if (e != hipSuccess || lower) return e;
     const size_t n2 = (size_t)N * N;
     const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
     hipLaunchKernelGGL(split_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->split_g, ea, eb,
                        C, N, s);
+    return hipGetLastError();
+}
+
+int ze_crt_bits(int N) {
+    double log2m = 0.0;
+    for (int k = 0; k < kCrtMods; ++k) log2m += std::log2((double)kCrtP[k]);
+    // 2N (0.99 2^b)^2 < M / 2
+    const int b = (int)std::floor((log2m - 1.0 - std::log2(2.0 * N)) / 2.0 - 1e-9);
+    return b < 55 ? b : 55;
+}
+
+size_t ze_crt_slab_ints(int N) { return (size_t)kCrtMods * 2 * N * (size_t)N; }
+
+hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
+                            hipStream_t st) {
+    const int N = c->N, ldk = ze_split_ldk(N), b = ze_crt_bits(N);
+    hipLaunchKernelGGL(crt_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, b, ldk, c->crt_a,
+                       c->split_ea);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gx = (N + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(col_max_partial, dim3(gx, kColChunks), dim3(kThreads), 0, st, B, N,
+                       c->split_colmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(col_exponent_kernel, dim3(gx), dim3(kThreads), 0, st, c->split_colmax, N,
+                       c->split_eb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g((N + kCT - 1) / kCT, (ldk / 2 + kCT - 1) / kCT);
+    hipLaunchKernelGGL(crt_cols_kernel, g, dim3(kThreads), 0, st, B, N, b, ldk, c->split_eb,
+                       c->crt_b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tr = (N + kI8BM - 1) / kI8BM;
+    const int tn = (2 * N + kI8BN - 1) / kI8BN;
+    const int ntiles = tr * tn;
+    const int nk = ldk / kI8BK;
+    int full = ntiles, S = 1;
+    const int cap = c->cap_i8 > 0 ? c->cap_i8 : ntiles;
+    const int rem = ntiles % cap;
+    if (rem > 0) {
+        int sp = cap / rem;
+        if (sp > nk / 4) sp = nk / 4;
+        if (sp > 1) {
+            full = ntiles - rem;
+            S = sp;
+        }
+    }
+    if (full < ntiles) {
+        hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, kCrtMods), dim3(kThreads), 0, st,
+                           c->crt_g, N, 0, tn, ntiles, full);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
+                       c->crt_a, c->crt_b, c->crt_g, N, kCrtMods, ldk, 0, tn, ntiles, full, S, 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t n2 = (size_t)N * N;
+    const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
+    hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->crt_g,
+                       c->split_ea, c->split_eb, C, N, b);
     return hipGetLastError();
 }
 

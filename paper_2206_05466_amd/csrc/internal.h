@@ -71,6 +71,11 @@ struct ze_ctx {
     double* split_colmax = nullptr;
     int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
     int cap_i8 = 0;          // blocks of the INT8 product kernel that fit on the device at once
+    // Modular (CRT) form of the product A = P W~: residues of A~ and B~^T for 16 moduli (split
+    // layouts) and the 16 int32 residue products, N x 2N each; allocated on first use.
+    signed char* crt_a = nullptr;
+    signed char* crt_b = nullptr;
+    int* crt_g = nullptr;
 
     // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
     // (F = the previous step's converged midpoint, left in ze_ctx::F), 2 = the polynomial
@@ -102,6 +107,8 @@ struct ze_ctx {
 constexpr int kMaxN = 16384;
 // Largest number of slices of the split-precision products.
 constexpr int kSplitMax = 8;
+// Number of moduli of the modular (CRT) form of the product.
+constexpr int kCrtMods = 16;
 
 // Largest slice count whose int32 sums stay exact for size N: the stored digits lie in
 // [-128, 127], so the pairs of one order t = i + j (at most s of them) add up to at most
@@ -202,6 +209,13 @@ hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, h
 // ahead; out may be Fs[d].
 hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out, int N,
                                    hipStream_t s);
+// Modular form: bits of the scaled integers for size N, int32 count of the residue products,
+// the product C = A B (full), and the context's buffers for it.
+int ze_crt_bits(int N);
+size_t ze_crt_slab_ints(int N);
+hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
+                            hipStream_t s);
+ze_status ze_ensure_crt(ze_ctx* c);
 // Grows the context's midpoint rings to 4 buffers for each of ns substeps.
 ze_status ze_ensure_rings(ze_ctx* c, int ns);
 // Input check of W (ze_set_validation): out[0..3] = max |W + W^H|, max |W|, Re tr W, Im tr W;

@@ -138,6 +138,185 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
     }
 }
 
+// ---------------------------------------------------------------- modular (CRT) form
+// Ozaki scheme II: a row of A~ (column of B~) scaled by a power of two to integers X with
+// |X| <= 0.99 2^b is represented exactly by its residues modulo kCrtMods pairwise coprime
+// moduli p_k <= 256 (balanced, so each fits an int8); one exact INT8 product per modulus gives
+// the integer product modulo p_k, and the Chinese remainder theorem (Garner's mixed radix)
+// recovers it exactly while |X_A X_B| summed stays below M / 2, M = prod p_k (~2^125.2).
+constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                 229, 227, 223, 211, 199, 197, 193, 191};
+struct CrtTables {
+    int inv[kCrtMods][kCrtMods];  // inv[j][k] = p_j^-1 mod p_k (j < k)
+    int r21[kCrtMods];            // 2^21 mod p_k
+    int r42[kCrtMods];            // 2^42 mod p_k
+};
+constexpr CrtTables make_crt_tables() {
+    CrtTables t{};
+    for (int k = 0; k < kCrtMods; ++k) {
+        const long long p = kCrtP[k];
+        long long a = 1;
+        for (int i = 0; i < 21; ++i) a = (a * 2) % p;
+        t.r21[k] = (int)a;
+        t.r42[k] = (int)((a * a) % p);
+        for (int j = 0; j < k; ++j) {
+            const long long q = kCrtP[j] % p;
+            int inv = 0;
+            for (int x = 1; x < p; ++x)
+                if ((q * x) % p == 1) {
+                    inv = x;
+                    break;
+                }
+            t.inv[j][k] = inv;
+        }
+    }
+    return t;
+}
+constexpr CrtTables kCrt = make_crt_tables();
+
+// v mod p in [0, p) for |v| < 2^24 (float quotient, corrected by one step either way).
+__device__ __forceinline__ int crt_mod(int v, int p) {
+    const int q = (int)floorf((float)v * (1.0f / (float)p));
+    int r = v - q * p;
+    r = r < 0 ? r + p : r;
+    return r >= p ? r - p : r;
+}
+
+// Balanced residue of the integer X (|X| < 2^56) modulo p_k, in [-(p_k)/2, (p_k - 1)/2].
+template <int K>
+__device__ __forceinline__ int crt_residue(long long X) {
+    constexpr int p = kCrtP[K];
+    const int l = (int)(X & 0x1FFFFF), h1 = (int)((X >> 21) & 0x1FFFFF), h2 = (int)(X >> 42);
+    const int r = crt_mod(crt_mod(h2, p) * kCrt.r42[K] + crt_mod(h1, p) * kCrt.r21[K] +
+                              crt_mod(l, p), p);
+    return r > (p - 1) / 2 ? r - p : r;
+}
+
+template <int K>
+struct CrtResidues {
+    // d[k] = balanced residue of X modulo p_k for k < K
+    __device__ __forceinline__ static void run(long long X, int (&d)[kCrtMods]) {
+        CrtResidues<K - 1>::run(X, d);
+        d[K - 1] = crt_residue<K - 1>(X);
+    }
+};
+template <>
+struct CrtResidues<0> {
+    __device__ __forceinline__ static void run(long long, int (&)[kCrtMods]) {}
+};
+
+// Residues of x scaled by 2^(b - e) and rounded to the nearest integer.
+__device__ __forceinline__ void crt_digits(double x, int e, int b, int (&d)[kCrtMods]) {
+    CrtResidues<kCrtMods>::run(llrint(ldexp(x, b - e)), d);
+}
+
+// Row r of A~ in residue form: slice k holds the residues modulo p_k (layout of split_row_block).
+__device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int N, int r, int b, int ldk,
+                                      signed char* __restrict__ slices, int* __restrict__ ea,
+                                      double* red) {
+    const double2* row = A + (size_t)r * N;
+    double m = 0.0;
+    for (int c = threadIdx.x; c < N; c += kSThreads) {
+        const double2 v = row[c];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = kSThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const int e = exponent_of(red[0]);
+    if (threadIdx.x == 0) ea[r] = e;
+    const size_t ss = (size_t)split_rows_pad(N) * ldk;
+    signed char* base = slices + (size_t)r * ldk;
+    for (int c = threadIdx.x; c < ldk / 2; c += kSThreads) {
+        const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);
+        int dr[kCrtMods], di[kCrtMods];
+        crt_digits(v.x, e, b, dr);
+        crt_digits(v.y, e, b, di);
+#pragma unroll
+        for (int i = 0; i < kCrtMods; ++i) {
+            const unsigned short pk = (unsigned short)((unsigned char)(signed char)dr[i]) |
+                                      ((unsigned short)((unsigned char)(signed char)di[i]) << 8);
+            *reinterpret_cast<unsigned short*>(base + i * ss + 2 * c) = pk;
+        }
+    }
+}
+
+// B~^T in residue form, tile (bx, by) as split_cols_tile (same layout); the residues of -Im b
+// are minus those of Im b, except that -(-128) = 128 is -128 modulo 256.
+__device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int N, int bx, int by, int b,
+                                      int ldk, const int* __restrict__ eb,
+                                      signed char* __restrict__ slices,
+                                      double2 (*tile)[kCT + 1]) {
+    const int k0 = by * kCT, c0 = bx * kCT;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int a = ty; a < kCT; a += 8) {
+        const int k = k0 + a, c = c0 + tx;
+        tile[a][tx] = (k < N && c < N) ? B[(size_t)k * N + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const size_t ss = (size_t)split_cols_pad(N) * ldk;
+    const int k = k0 + tx;
+    if (2 * k >= ldk) return;
+    for (int a = ty; a < kCT; a += 8) {
+        const int c = c0 + a;
+        if (c >= N) break;
+        const double2 v = tile[tx][a];
+        const int e = eb[c];
+        int dr[kCrtMods], di[kCrtMods];
+        crt_digits(v.x, e, b, dr);
+        crt_digits(v.y, e, b, di);
+        signed char* o0 = slices + (size_t)(2 * c) * ldk + 2 * k;
+        signed char* o1 = slices + (size_t)(2 * c + 1) * ldk + 2 * k;
+#pragma unroll
+        for (int i = 0; i < kCrtMods; ++i) {
+            const int n = di[i] == -128 ? -128 : -di[i];
+            const unsigned char ur = (unsigned char)(signed char)dr[i];
+            const unsigned char ui = (unsigned char)(signed char)di[i];
+            const unsigned char nui = (unsigned char)(signed char)n;
+            *reinterpret_cast<unsigned short*>(o0 + i * ss) = (unsigned short)ur | ((unsigned short)nui << 8);
+            *reinterpret_cast<unsigned short*>(o1 + i * ss) = (unsigned short)ui | ((unsigned short)ur << 8);
+        }
+    }
+}
+
+// Exact integer from the kCrtMods int32 products g_k (|g_k| < 2^31) of one output value:
+// c_k = g_k mod p_k, Garner's digits in balanced form (v_k in [-(p_k)/2, (p_k - 1)/2], so the
+// represented integer is the one in [-M/2, M/2)), evaluated by Horner's rule from the top digit
+// in double-double arithmetic (error-free product by FMA, error-free sum; no cancellation:
+// each partial value is the integer divided by the lower moduli), so the result is the
+// integer rounded to FP64 within 2^-100 relative: exact whenever it is representable.
+__device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
+    // the error-free transformations below need every product and sum rounded as written
+#pragma clang fp contract(off)
+    int v[kCrtMods];
+#pragma unroll
+    for (int k = 0; k < kCrtMods; ++k) {
+        const int p = kCrtP[k];
+        // g mod p for |g| < 2^31 via its 16-bit halves (each below 2^24 after the product)
+        const int hi = g[k] >> 16, lo = g[k] & 0xFFFF;
+        int t = crt_mod(crt_mod(hi, p) * crt_mod(65536, p) + crt_mod(lo, p), p);
+#pragma unroll
+        for (int j = 0; j < k; ++j) t = crt_mod((t - v[j]) * kCrt.inv[j][k], p);
+        v[k] = t > (p - 1) / 2 ? t - p : t;
+    }
+    double xh = (double)v[kCrtMods - 1], xl = 0.0;
+#pragma unroll
+    for (int k = kCrtMods - 2; k >= 0; --k) {
+        const double P = (double)kCrtP[k], d = (double)v[k];
+        const double ph = xh * P;
+        double pl = fma(xh, P, -ph) + xl * P;  // (xh + xl) P = ph + pl
+        const double sh = ph + d;                // two-sum of ph and d
+        const double bv = sh - ph;
+        pl += (ph - (sh - bv)) + (d - bv);
+        xh = sh + pl;                            // renormalise
+        xl = pl - (xh - sh);
+    }
+    return xh;
+}
+
 // ---------------------------------------------------------------- INT8 product tile
 // Block tile 128 rows x 128 real columns (64 complex), 4 waves as 2 x 2 of 64 x 64, each wave
 // 2 x 2 tiles of v_mfma_i32_32x32x32_i8 (on gfx950 this form has about twice the throughput
@@ -197,7 +376,9 @@ __device__ __forceinline__ void i8_next_pair(int& i, int& j) {
 // Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
 // each) and sb (B~^T, split_cols_pad(N) x ldk each), over the K stages [kb, ke) of every slice
 // pair (kb = 0, ke < 0: all of K).  With `add` the int32 sums are added to G with atomics
-// (exact: a tile split along K over several blocks, G cleared beforehand), else stored.
+// (exact: a tile split along K over several blocks, G cleared beforehand), else stored.  With
+// `diag` the pairs are (1, 1) .. (s, s) instead, each into its own slab G[i-1] (the residue
+// products of the modular form).
 // Each iteration issues the global loads of the next stage, computes the current stage from
 // LDS, and stores the next stage to the other LDS buffer at the end of the stage; scheduling
 // barriers keep that order (left alone, the compiler moves the LDS store up to the loads,
@@ -206,7 +387,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
                                               const signed char* __restrict__ sb,
                                               int* __restrict__ G, int N, int s, int ldk,
                                               I8Smem& sm, int kb = 0, int ke = -1,
-                                              bool add = false) {
+                                              bool add = false, bool diag = false) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8BM;      // rows of A~ / G
     const int cc0 = tj * kI8BN;       // real columns of G (rows of B~^T)
@@ -214,7 +395,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     const size_t sA = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
     const size_t sB = (size_t)split_cols_pad(N) * ldk;
     if (ke < 0) ke = ldk / kI8BK;     // K stages (real K = 2N, zero padded to ldk)
-    const int total = s * (s + 1) / 2 * (ke - kb);
+    const int total = (diag ? s : s * (s + 1) / 2) * (ke - kb);
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int l32 = lane & 31, h = lane >> 5;
 
@@ -240,8 +421,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     const int swz = i8_swizzle(l32);
     const int rda = (wr + l32) * kI8BK, rdb = (kI8BM + wc + l32) * kI8BK;
 
-    int li = 1, lj = s, lk = kb;  // next stage to load
-    int ci = 1, cj = s, ck = kb;  // stage in LDS
+    int li = 1, lj = diag ? 1 : s, lk = kb;  // next stage to load
+    int ci = 1, cj = diag ? 1 : s, ck = kb;  // stage in LDS
     v4i ra[4], rb[4];  // native vectors (HIP's uint4 is a struct whose copies become memcpy)
 #define ZE_I8_LOAD()                                                              \
     do {                                                                          \
@@ -253,7 +434,12 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
         }                                                                         \
         if (++lk == ke) {                                                         \
             lk = kb;                                                              \
-            i8_next_pair(li, lj);                                                 \
+            if (diag) {                                                           \
+                ++li;                                                             \
+                ++lj;                                                             \
+            } else {                                                              \
+                i8_next_pair(li, lj);                                             \
+            }                                                                     \
         }                                                                         \
     } while (0)
 #define ZE_I8_STORE(st)                                                           \
@@ -298,8 +484,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
             __builtin_amdgcn_sched_barrier(0);
         }
 #undef ZE_I8_READ
-        if (ck == ke - 1 && cj == 1) {  // last stage of the last pair of this t
-            int* g = G + (size_t)(ci + cj - 2) * N * M2;
+        if (ck == ke - 1 && (diag || cj == 1)) {  // last stage of the last pair of this t
+            int* g = G + (size_t)(diag ? ci - 1 : ci + cj - 2) * N * M2;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -320,7 +506,12 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
         }
         if (++ck == ke) {
             ck = kb;
-            i8_next_pair(ci, cj);
+            if (diag) {
+                ++ci;
+                ++cj;
+            } else {
+                i8_next_pair(ci, cj);
+            }
         }
         __syncthreads();
     }

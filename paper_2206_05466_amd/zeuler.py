@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzeuler.so")
 
 ZE_OK, ZE_EINVAL, ZE_ENOMEM, ZE_ENOTCONV, ZE_ENONFINITE, ZE_EHIP = range(6)
-PREC_FP64, PREC_SPLIT, PREC_MIXED = 0, 1, 2
+PREC_FP64, PREC_SPLIT, PREC_MIXED, PREC_CRT = 0, 1, 2, 3
 
 # Exported names and signatures, as declared in include/zeuler.h.
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p

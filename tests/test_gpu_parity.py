@@ -825,3 +825,72 @@ def test_input_validation(dev, N):
                 z.isomp_run(Wd, 0.01, 2, 1e-12, 50)
             got = to_host(Wd)
             assert np.array_equal(got[~np.isnan(got)], bad[~np.isnan(bad)])
+
+
+# ------------------------------------------------------------------ modular (CRT) form
+@pytest.mark.parametrize("N", [1, 7, 64, 129, 300, 1000])
+def test_zgemm_crt_small_integers_exact(dev, N):
+    """The modular form recovers integer products exactly (every input is a small integer, so
+    the scaling rounds nothing and the CRT gives the exact sums), including values that need
+    every modulus: entries up to 2^20."""
+    from paper_2206_05466_amd import PREC_CRT
+
+    rng = np.random.default_rng(N + 11)
+    for lim in (9, 2 ** 20):
+        A = rng.integers(-lim, lim + 1, (N, N)) + 1j * rng.integers(-lim, lim + 1, (N, N))
+        B = rng.integers(-lim, lim + 1, (N, N)) + 1j * rng.integers(-lim, lim + 1, (N, N))
+        with ctx(N) as z:
+            C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_CRT))
+        exact = A @ B  # |entries| < 2^53: numpy's FP64 sums are exact here
+        assert np.array_equal(C, exact), (N, lim)
+
+
+@pytest.mark.parametrize("N", [64, 131, 384])
+def test_zgemm_crt_random_fp64_level(dev, N):
+    """Random complex operands with entries spread over 2^-20 .. 1: the modular form's error is
+    the rounding of the scaled inputs to 55-bit integers, 2^-55 relative to the row / column
+    maxima per term, i.e. at the level of the FP64 product itself: both within
+    4 * 2N * 2^-52 max|A| max|B| of the exact product (from exact integer arithmetic on the
+    FP64 inputs), and the CRT result no worse than 2x the FP64 product's own error."""
+    from fractions import Fraction
+
+    from paper_2206_05466_amd import PREC_CRT, PREC_FP64
+
+    rng = np.random.default_rng(N)
+    sc = 2.0 ** rng.integers(-20, 1, (N, N))
+    A = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * sc
+    B = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * sc.T
+    with ctx(N) as z:
+        C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_CRT))
+        F = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_FP64))
+    # exact reference on sampled entries, in rational arithmetic of the FP64 inputs
+    idx = rng.integers(0, N, (24, 2))
+    bound = 4 * 2 * N * 2.0 ** -52 * np.abs(A).max() * np.abs(B).max()
+    ec = ef = 0.0
+    for r, c in idx:
+        re = sum(Fraction(a.real) * Fraction(b.real) - Fraction(a.imag) * Fraction(b.imag)
+                 for a, b in zip(A[r], B[:, c]))
+        im = sum(Fraction(a.real) * Fraction(b.imag) + Fraction(a.imag) * Fraction(b.real)
+                 for a, b in zip(A[r], B[:, c]))
+        ec = max(ec, abs(float(Fraction(C[r, c].real) - re)), abs(float(Fraction(C[r, c].imag) - im)))
+        ef = max(ef, abs(float(Fraction(F[r, c].real) - re)), abs(float(Fraction(F[r, c].imag) - im)))
+    assert ec <= bound, (ec, bound)
+    assert ec <= 2 * ef + 1e-300, (ec, ef)
+
+
+@pytest.mark.parametrize("N,steps", [(128, 8), (1000, 5)])
+def test_isomp_crt_meets_fp64_bar(dev, N, steps):
+    """PREC_CRT (the product A = P W~ in the modular form, the lower product as PREC_MIXED):
+    the FP64 path's bar against the oracle (1e-12, the same evaluation counts)."""
+    from paper_2206_05466_amd import PREC_CRT
+
+    h = 0.005
+    W0 = w0(N, 9, "inv1.5")
+    Wr, it_ref, _ = O.isomp_run(W0, h, steps, 1e-12, 50, extrapolate=True, degree=3)
+    with ctx(N) as z:
+        z.set_initial_guess(2)
+        Wd = to_dev(W0)
+        its, res = z.isomp_run(Wd, h, steps, 1e-12, 50, prec=PREC_CRT)
+        W = to_host(Wd)
+    assert its == it_ref and max(res) < 1e-12, (its, it_ref)
+    assert np.linalg.norm(W - Wr) <= 1e-12 * np.linalg.norm(Wr)
