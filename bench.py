@@ -487,9 +487,10 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
         del src, dst
 
     # mixed: A = P W~ in FP64, the lower product (h^2/4 weight) on INT8 with 4 slices
-    mixed = None
+    mixed = crt = None
     if with_mixed:
         mixed = mixed_run(z, timed_run, W0, W, c0, dt, steps, wname)
+        crt = crt_run(z, timed_run, W0, W, c0, dt, steps, wname)
 
     split = None
     if slist:
@@ -542,7 +543,48 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
             "rel_frobenius_vs_headline_run": p0_vs_extrap},
         "split_precision": split,
         "mixed_precision": mixed,
+        "crt_precision": crt,
     }
+
+
+def crt_run(z, timed_run, W0, W, c0, dt, steps, wname):
+    """The same run with ZE_PREC_CRT (A = P W~ in the modular INT8 form, the lower product on
+    INT8 with 4 slices), compared with the FP64 headline run W; plus the product alone."""
+    import torch
+
+    from paper_2206_05466_amd import PREC_CRT, PREC_FP64
+
+    z.set_split_slices(5)
+    Wc = W0.clone()
+    dtc, its_c, res_c, prof_c = timed_run(Wc, PREC_CRT, 2)
+    N = W.shape[0]
+    Xa, Xb = W0.clone(), Wc.clone()
+    out = torch.empty_like(Xa)
+    gemm = {}
+    for name, prec in (("fp64", PREC_FP64), ("crt", PREC_CRT)):
+        z.zgemm(Xa, Xb, out, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            z.zgemm(Xa, Xb, out, prec)
+        torch.cuda.synchronize()
+        gemm[name] = (time.perf_counter() - t0) / 3
+        gemm[name + "_result"] = out.clone()
+    rel_gemm = float((torch.linalg.norm(gemm["crt_result"] - gemm["fp64_result"]) /
+                      torch.linalg.norm(gemm["fp64_result"])).item())
+    rec = {
+        "s_per_step": dtc / steps, "speedup_vs_fp64": dt / dtc,
+        "iters_per_step": list(its_c), "max_resid": max(res_c), "moduli": 16,
+        "rel_frobenius_vs_fp64_run": float(torch.linalg.norm(Wc - W).item() / torch.linalg.norm(W).item()),
+        "casimir_drift_rel": casimir_drift(c0, z.casimirs(Wc, 4), Wc),
+        "phases": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof_c.items()},
+        "zgemm_ms": {"fp64": gemm["fp64"] * 1e3, "crt": gemm["crt"] * 1e3},
+        "zgemm_crt_fp64_equiv_tflops": 8.0 * N ** 3 / gemm["crt"] / 1e12,
+        "zgemm_rel_frobenius_crt_vs_fp64": rel_gemm,
+    }
+    log(f"{wname} crt (modular INT8 A, 4-slice Q): {dtc / steps * 1e3:.2f} ms/step, rel diff vs fp64 "
+        f"{rec['rel_frobenius_vs_fp64_run']:.2e}; zgemm {gemm['crt'] * 1e3:.2f} vs fp64 {gemm['fp64'] * 1e3:.2f} ms")
+    return rec
 
 
 def mixed_run(z, timed_run, W0, W, c0, dt, steps, wname):
@@ -587,7 +629,7 @@ def main():
     ap.add_argument("--long-steps", type=int, default=10000,
                     help="steps of the long-run drift leg (N=512, paper initial condition; 0: skip)")
     ap.add_argument("--mixed", type=int, default=1,
-                    help="1: also time the mixed-precision run (FP64 A, INT8 lower product), 0: skip")
+                    help="1: also time the mixed-precision runs (FP64 A or modular-INT8 A, INT8 lower product), 0: skip")
     ap.add_argument("--orders", type=int, default=1,
                     help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
@@ -626,6 +668,7 @@ def main():
             "phases": phases_of(m2["prof"]),
             "split_precision": m2["split_precision"],
             "mixed_precision": m2["mixed_precision"],
+            "crt_precision": m2["crt_precision"],
         }
 
     n512 = small_leg(args.n512_steps) if args.n512_steps > 0 else None
@@ -723,6 +766,7 @@ def main():
         "cpu_baseline": None,
         "split_precision": m["split_precision"],
         "mixed_precision": m["mixed_precision"],
+        "crt_precision": m["crt_precision"],
         "n2048": n2048,
         "n512": n512,
         "long512": long512,

@@ -142,54 +142,26 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
 // Ozaki scheme II: a row of A~ (column of B~) scaled by a power of two to integers X with
 // |X| <= 0.99 2^b is represented exactly by its residues modulo kCrtMods pairwise coprime
 // moduli p_k <= 256 (balanced, so each fits an int8); one exact INT8 product per modulus gives
-// the integer product modulo p_k, and the Chinese remainder theorem (Garner's mixed radix)
-// recovers it exactly while |X_A X_B| summed stays below M / 2, M = prod p_k (~2^125.2).
+// the integer product modulo p_k, and the Chinese remainder theorem recovers it exactly while
+// |X_A X_B| summed stays below M / 4, M = prod p_k (~2^125.2).
 constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
                                  229, 227, 223, 211, 199, 197, 193, 191};
-struct CrtTables {
-    int inv[kCrtMods][kCrtMods];  // inv[j][k] = p_j^-1 mod p_k (j < k)
-    int r21[kCrtMods];            // 2^21 mod p_k
-    int r42[kCrtMods];            // 2^42 mod p_k
-};
-constexpr CrtTables make_crt_tables() {
-    CrtTables t{};
-    for (int k = 0; k < kCrtMods; ++k) {
-        const long long p = kCrtP[k];
-        long long a = 1;
-        for (int i = 0; i < 21; ++i) a = (a * 2) % p;
-        t.r21[k] = (int)a;
-        t.r42[k] = (int)((a * a) % p);
-        for (int j = 0; j < k; ++j) {
-            const long long q = kCrtP[j] % p;
-            int inv = 0;
-            for (int x = 1; x < p; ++x)
-                if ((q * x) % p == 1) {
-                    inv = x;
-                    break;
-                }
-            t.inv[j][k] = inv;
-        }
-    }
-    return t;
-}
-constexpr CrtTables kCrt = make_crt_tables();
 
-// v mod p in [0, p) for |v| < 2^24 (float quotient, corrected by one step either way).
-__device__ __forceinline__ int crt_mod(int v, int p) {
-    const int q = (int)floorf((float)v * (1.0f / (float)p));
-    int r = v - q * p;
-    r = r < 0 ? r + p : r;
-    return r >= p ? r - p : r;
-}
 
-// Balanced residue of the integer X (|X| < 2^56) modulo p_k, in [-(p_k)/2, (p_k - 1)/2].
+// Balanced residue of the integer X (|X| < 2^63) modulo p_k, in [-(p_k)/2, (p_k - 1)/2]:
+// |X| mod p from a 64-bit reciprocal (q = the high half of |X| floor(2^64 / p), at most one
+// below the true quotient), then the sign.
 template <int K>
 __device__ __forceinline__ int crt_residue(long long X) {
     constexpr int p = kCrtP[K];
-    const int l = (int)(X & 0x1FFFFF), h1 = (int)((X >> 21) & 0x1FFFFF), h2 = (int)(X >> 42);
-    const int r = crt_mod(crt_mod(h2, p) * kCrt.r42[K] + crt_mod(h1, p) * kCrt.r21[K] +
-                              crt_mod(l, p), p);
-    return r > (p - 1) / 2 ? r - p : r;
+    constexpr unsigned long long magic = ~0ull / (unsigned long long)p;
+    const unsigned long long a = X < 0 ? (unsigned long long)(-X) : (unsigned long long)X;
+    const unsigned long long q = (unsigned long long)(((unsigned __int128)a * magic) >> 64);
+    unsigned long long r = a - q * (unsigned long long)p;
+    r = r >= (unsigned long long)p ? r - p : r;
+    int t = (int)r;
+    if (X < 0 && t != 0) t = p - t;
+    return t > (p - 1) / 2 ? t - p : t;
 }
 
 template <int K>
@@ -282,39 +254,69 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
     }
 }
 
-// Exact integer from the kCrtMods int32 products g_k (|g_k| < 2^31) of one output value:
-// c_k = g_k mod p_k, Garner's digits in balanced form (v_k in [-(p_k)/2, (p_k - 1)/2], so the
-// represented integer is the one in [-M/2, M/2)), evaluated by Horner's rule from the top digit
-// in double-double arithmetic (error-free product by FMA, error-free sum; no cancellation:
-// each partial value is the integer divided by the lower moduli), so the result is the
-// integer rounded to FP64 within 2^-100 relative: exact whenever it is representable.
+// Constants of the reconstruction: W_k = (M / p_k) ((M / p_k)^-1 mod p_k) < M, so that
+// X = sum_k c_k W_k mod M for c_k = X mod p_k; as two 64-bit halves and as doubles; M likewise.
+struct CrtConst {
+    unsigned long long wlo[kCrtMods], whi[kCrtMods];
+    double wd[kCrtMods];
+    unsigned long long mlo, mhi;
+    double md;
+};
+
+constexpr double crt_u128_to_double(unsigned __int128 v) {
+    return (double)(unsigned long long)(v >> 64) * 18446744073709551616.0 +
+           (double)(unsigned long long)v;
+}
+
+constexpr CrtConst make_crt_const() {
+    CrtConst k{};
+    unsigned __int128 M = 1;
+    for (int i = 0; i < kCrtMods; ++i) M *= (unsigned __int128)kCrtP[i];
+    for (int i = 0; i < kCrtMods; ++i) {
+        const unsigned p = (unsigned)kCrtP[i];
+        const unsigned __int128 Mk = M / p;
+        const unsigned r = (unsigned)(Mk % p);
+        unsigned y = 0;
+        for (unsigned x = 1; x < p && y == 0; ++x)
+            if ((r * x) % p == 1) y = x;
+        const unsigned __int128 W = Mk * y;
+        k.wlo[i] = (unsigned long long)W;
+        k.whi[i] = (unsigned long long)(W >> 64);
+        k.wd[i] = crt_u128_to_double(W);
+    }
+    k.mlo = (unsigned long long)M;
+    k.mhi = (unsigned long long)(M >> 64);
+    k.md = crt_u128_to_double(M);
+    return k;
+}
+
+constexpr CrtConst kCrtK = make_crt_const();
+
+// The integer X with |X| < M / 4 from the kCrtMods int32 products g_k (|g_k| < 2^31) of one
+// output value, rounded to FP64: c_k = g_k mod p_k; S = sum_k c_k W_k exactly modulo 2^128
+// (unsigned 128-bit arithmetic) and approximately in FP64; q = S / M rounded to the nearest
+// integer (exact: S / M lies within 1/4 of an integer since |X| < M / 4, and the FP64
+// estimate is off by far less); X = S - q M modulo 2^128 is X itself, read as signed.  The
+// magnitude is converted from its two 64-bit halves, each exact when X is representable.
 __device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
-    // the error-free transformations below need every product and sum rounded as written
-#pragma clang fp contract(off)
-    int v[kCrtMods];
+    constexpr CrtConst C = kCrtK;
+    unsigned __int128 S = 0;
+    double Sd = 0.0;
 #pragma unroll
     for (int k = 0; k < kCrtMods; ++k) {
         const int p = kCrtP[k];
-        // g mod p for |g| < 2^31 via its 16-bit halves (each below 2^24 after the product)
-        const int hi = g[k] >> 16, lo = g[k] & 0xFFFF;
-        int t = crt_mod(crt_mod(hi, p) * crt_mod(65536, p) + crt_mod(lo, p), p);
-#pragma unroll
-        for (int j = 0; j < k; ++j) t = crt_mod((t - v[j]) * kCrt.inv[j][k], p);
-        v[k] = t > (p - 1) / 2 ? t - p : t;
+        int c = g[k] - (int)floor((double)g[k] * (1.0 / (double)p)) * p;
+        c = c < 0 ? c + p : (c >= p ? c - p : c);
+        const unsigned __int128 W = ((unsigned __int128)C.whi[k] << 64) | C.wlo[k];
+        S += (unsigned __int128)(unsigned)c * W;
+        Sd += (double)c * C.wd[k];
     }
-    double xh = (double)v[kCrtMods - 1], xl = 0.0;
-#pragma unroll
-    for (int k = kCrtMods - 2; k >= 0; --k) {
-        const double P = (double)kCrtP[k], d = (double)v[k];
-        const double ph = xh * P;
-        double pl = fma(xh, P, -ph) + xl * P;  // (xh + xl) P = ph + pl
-        const double sh = ph + d;                // two-sum of ph and d
-        const double bv = sh - ph;
-        pl += (ph - (sh - bv)) + (d - bv);
-        xh = sh + pl;                            // renormalise
-        xl = pl - (xh - sh);
-    }
-    return xh;
+    const unsigned long long q = (unsigned long long)rint(Sd / C.md);
+    const unsigned __int128 M = ((unsigned __int128)C.mhi << 64) | C.mlo;
+    const __int128 X = (__int128)(S - (unsigned __int128)q * M);
+    const unsigned __int128 a = X < 0 ? (unsigned __int128)(-X) : (unsigned __int128)X;
+    const double v = (double)(unsigned long long)(a >> 64) * 0x1p64 + (double)(unsigned long long)a;
+    return X < 0 ? -v : v;
 }
 
 // ---------------------------------------------------------------- INT8 product tile
