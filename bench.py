@@ -417,7 +417,7 @@ def casimir_drift(c0, c1, W):
     return {f"C{k+1}": float(abs(c1[k] - c0[k]) / (abs(c0[k]) if k != 2 else nf ** 3)) for k in (1, 2, 3)}
 
 
-def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=True):
+def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=True, with_crt=True):
     """One simulation of workload wname: FP64 (start from W_n, the linear start, then the
     polynomial start of the headline) and the split-precision runs (polynomial start), each over
     `steps` timed steps of one ze_isomp_run call from the same W0."""
@@ -490,6 +490,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
     mixed = crt = None
     if with_mixed:
         mixed = mixed_run(z, timed_run, W0, W, c0, dt, steps, wname)
+    if with_crt:
         crt = crt_run(z, timed_run, W0, W, c0, dt, steps, wname)
 
     split = None
@@ -629,7 +630,9 @@ def main():
     ap.add_argument("--long-steps", type=int, default=10000,
                     help="steps of the long-run drift leg (N=512, paper initial condition; 0: skip)")
     ap.add_argument("--mixed", type=int, default=1,
-                    help="1: also time the mixed-precision runs (FP64 A or modular-INT8 A, INT8 lower product), 0: skip")
+                    help="1: also time the mixed-precision run (FP64 A, INT8 lower product), 0: skip")
+    ap.add_argument("--crt", type=int, default=1,
+                    help="1: also time the modular-INT8 run (ZE_PREC_CRT A, INT8 lower product), 0: skip")
     ap.add_argument("--orders", type=int, default=1,
                     help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
@@ -650,12 +653,13 @@ def main():
     torch.cuda.set_device(0)
     slist = [int(x) for x in str(args.split_slices).split(",") if x.strip() and int(x) > 0]
     m = measure_single(args.workload, args.steps, args.warmup, slist, args.copy_probe_mib,
-                       args.mixed > 0)
+                       args.mixed > 0, args.crt > 0)
     N, prof = m["N"], m["prof"]
 
     n2048 = None
     if args.n2048_steps > 0 and args.workload != "n2048":
-        m2 = measure_single("n2048", args.n2048_steps, args.warmup, slist, 0, args.mixed > 0)
+        m2 = measure_single("n2048", args.n2048_steps, args.warmup, slist, 0, args.mixed > 0,
+                            args.crt > 0)
         p2 = m2["prof"]["product_PW"]
         n2048 = {
             "workload": f"n2048: one simulation, N=2048, sigma_l law {m2['law']}, h={m2['h']}, "
