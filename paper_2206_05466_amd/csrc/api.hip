@@ -54,8 +54,8 @@ ze_status ze_ensure_crt(ze_ctx* c) {
     if (c->crt_g) return ZE_OK;
     ZE_TRY(ze_ensure_split(c));  // exponent vectors and column-maximum partials
     const size_t ldk = (size_t)ze_split_ldk(c->N);
-    const size_t bytes_a = (size_t)kCrtMods * split_rows_pad(c->N) * ldk;
-    const size_t bytes_b = (size_t)kCrtMods * split_cols_pad(c->N) * ldk;
+    const size_t bytes_a = (size_t)kCrtMods * crt_rows_pad(c->N) * ldk;
+    const size_t bytes_b = (size_t)kCrtMods * crt_cols_pad(c->N) * ldk;
     ze_status st = dalloc(&c->crt_a, bytes_a);
     if (st == ZE_OK) st = dalloc(&c->crt_b, bytes_b);
     // zero padding rows once; the residue kernels never write them
@@ -93,7 +93,7 @@ ze_status ze_ensure_split(ze_ctx* c) {
     if (st == ZE_OK) st = dalloc(&c->split_ec, n);
     if (st == ZE_OK) st = dalloc(&c->split_colmax, 64 * n);
     if (st == ZE_OK) {
-        const hipError_t ce = ze_i8_capacity(&c->cap_i8);
+        const hipError_t ce = ze_i8_capacity(&c->cap_i8, &c->cap_i8l);
         if (ce != hipSuccess) st = ze_record_hip(ce, "ze_i8_capacity");
     }
     if (st == ZE_OK) st = dalloc(&c->split_g, (size_t)kSplitMax * 2 * n * n);

@@ -184,18 +184,40 @@ __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
     }
 }
 
-// Clears the slabs G[0..s-1] over the tiles full .. ntiles-1 (the K-split ones); grid
-// (ntiles - full, s).
+// Clears the slabs G[0..s-1] over the tiles full .. ntiles-1 (the K-split ones) of bm x bn
+// tiles; grid (ntiles - full, s).
 __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, int N, int mode,
-                                                          int tiles_n, int ntiles, int full) {
+                                                          int tiles_n, int ntiles, int full,
+                                                          int bm, int bn) {
     int ti, tj;
     i8_tile_of(mode, full + blockIdx.x, tiles_n, ntiles, false, 0, ti, tj);
     const int M2 = 2 * N;
     if (tj >= tiles_n) return;
     int* g = G + (size_t)blockIdx.y * N * M2;
-    for (int x = threadIdx.x; x < kI8BM * kI8BN; x += kThreads) {
-        const int row = ti * kI8BM + x / kI8BN, cc = tj * kI8BN + x % kI8BN;
+    for (int x = threadIdx.x; x < bm * bn; x += kThreads) {
+        const int row = ti * bm + x / bn, cc = tj * bn + x % bn;
         if (row < N && cc < M2) g[(size_t)row * M2 + cc] = 0;
+    }
+}
+
+// The modular form's residue products on 256 x 256 tiles (zgemm_i8_tile_large); blocks as in
+// zgemm_i8_kernel's full-product mode.
+__global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
+    const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
+    int N, int s, int ldk, int tiles_n, int ntiles, int full, int S) {
+    __shared__ I8LSmem sm;
+    int ti, tj;
+    const int b = blockIdx.x;
+    if (b < full) {
+        i8_tile_of(0, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
+        if (tj >= tiles_n) return;
+        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false);
+    } else {
+        const int e = b - full, p = e % S, nk = ldk / kI8BK;
+        i8_tile_of(0, full + e / S, tiles_n, ntiles, false, b, ti, tj);
+        if (tj >= tiles_n) return;
+        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
+                            (int)((long long)(p + 1) * nk / S), true);
     }
 }
 
@@ -229,13 +251,16 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
 
 int ze_split_ldk(int N) { return split_ldk_of(N); }
 
-hipError_t ze_i8_capacity(int* cap) {
-    int dev = 0, cus = 0, nb = 0;
+hipError_t ze_i8_capacity(int* cap, int* cap_large) {
+    int dev = 0, cus = 0, nb = 0, nl = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, zgemm_i8_kernel, kThreads, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, zgemm_i8_large_kernel, kI8LThreads, 0);
     if (e != hipSuccess) return e;
     *cap = (nb > 0 ? nb : 1) * cus;
+    *cap_large = (nl > 0 ? nl : 1) * cus;
     return hipSuccess;
 }
 
@@ -291,7 +316,7 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     }
     if (full < ntiles) {
         hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, s), dim3(kThreads), 0, st, c->split_g,
-                           N, lower ? 1 : 0, tn, ntiles, full);
+                           N, lower ? 1 : 0, tn, ntiles, full, kI8BM, kI8BN);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -338,12 +363,17 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
                        c->crt_b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tr = (N + kI8BM - 1) / kI8BM;
-    const int tn = (2 * N + kI8BN - 1) / kI8BN;
+    // 256 x 256 tiles when they fill at least one round of the GPU's block slots, else the
+    // 128 x 128 kernel's diagonal mode (more tiles, no K split at mid sizes)
+    const bool large = ((N + kI8LM - 1) / kI8LM) * ((2 * N + kI8LN - 1) / kI8LN) >= c->cap_i8l;
+    const int bm = large ? kI8LM : kI8BM, bn = large ? kI8LN : kI8BN;
+    const int tr = (N + bm - 1) / bm;
+    const int tn = (2 * N + bn - 1) / bn;
     const int ntiles = tr * tn;
     const int nk = ldk / kI8BK;
     int full = ntiles, S = 1;
-    const int cap = c->cap_i8 > 0 ? c->cap_i8 : ntiles;
+    const int capk = large ? c->cap_i8l : c->cap_i8;
+    const int cap = capk > 0 ? capk : ntiles;
     const int rem = ntiles % cap;
     if (rem > 0) {
         int sp = cap / rem;
@@ -355,12 +385,17 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
     }
     if (full < ntiles) {
         hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, kCrtMods), dim3(kThreads), 0, st,
-                           c->crt_g, N, 0, tn, ntiles, full);
+                           c->crt_g, N, 0, tn, ntiles, full, bm, bn);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
-                       c->crt_a, c->crt_b, c->crt_g, N, kCrtMods, ldk, 0, tn, ntiles, full, S, 1);
+    const unsigned nb = (unsigned)(full + (ntiles - full) * S);
+    if (large)
+        hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(nb), dim3(kI8LThreads), 0, st, c->crt_a,
+                           c->crt_b, c->crt_g, N, kCrtMods, ldk, tn, ntiles, full, S);
+    else
+        hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->crt_a, c->crt_b,
+                           c->crt_g, N, kCrtMods, ldk, 0, tn, ntiles, full, S, 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t n2 = (size_t)N * N;

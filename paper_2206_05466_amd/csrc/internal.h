@@ -71,6 +71,7 @@ struct ze_ctx {
     double* split_colmax = nullptr;
     int* split_g = nullptr;  // int32 slabs G[t-2], N x 2N each, t = 2..s+1
     int cap_i8 = 0;          // blocks of the INT8 product kernel that fit on the device at once
+    int cap_i8l = 0;         // the same for the 256 x 256 residue-product kernel
     // Modular (CRT) form of the product A = P W~: residues of A~ and B~^T for 16 moduli (split
     // layouts) and the 16 int32 residue products, N x 2N each; allocated on first use.
     signed char* crt_a = nullptr;
@@ -123,13 +124,16 @@ inline int split_max_slices(int N) {
 // Workspaces of the split-precision products (kSplitMax slices), allocated on first use.
 ze_status ze_ensure_split(ze_ctx* c);
 // Blocks of the single-problem INT8 product kernel that fit on the device at once.
-hipError_t ze_i8_capacity(int* cap);
+hipError_t ze_i8_capacity(int* cap, int* cap_large);
 
 // Slice buffers hold whole 128-row tiles: A~ slices have split_rows_pad(N) rows and B~^T
 // slices split_cols_pad(N) rows; the rows past N (2N) are zeroed when the buffers are
 // allocated and never written, so the INT8 product reads them without bounds checks.
 __host__ __device__ inline int split_rows_pad(int N) { return ((N + 127) / 128) * 128; }
 __host__ __device__ inline int split_cols_pad(int N) { return ((2 * N + 127) / 128) * 128; }
+// Rows of the residue slabs of A~ and of B~^T (the modular form), padded to its 256-row tiles.
+__host__ __device__ inline int crt_rows_pad(int N) { return ((N + 255) / 256) * 256; }
+__host__ __device__ inline int crt_cols_pad(int N) { return ((2 * N + 255) / 256) * 256; }
 
 // ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
 // solve_bd: stream-solve band width (1, 2 or 4), 0 = the default for N (solve_bd(N)).

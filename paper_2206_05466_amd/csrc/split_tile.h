@@ -200,7 +200,7 @@ __device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int
     }
     const int e = exponent_of(red[0]);
     if (threadIdx.x == 0) ea[r] = e;
-    const size_t ss = (size_t)split_rows_pad(N) * ldk;
+    const size_t ss = (size_t)crt_rows_pad(N) * ldk;
     signed char* base = slices + (size_t)r * ldk;
     for (int c = threadIdx.x; c < ldk / 2; c += kSThreads) {
         const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);
@@ -229,7 +229,7 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
         tile[a][tx] = (k < N && c < N) ? B[(size_t)k * N + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const size_t ss = (size_t)split_cols_pad(N) * ldk;
+    const size_t ss = (size_t)crt_cols_pad(N) * ldk;
     const int k = k0 + tx;
     if (2 * k >= ldk) return;
     for (int a = ty; a < kCT; a += 8) {
@@ -376,7 +376,8 @@ __device__ __forceinline__ void i8_next_pair(int& i, int& j) {
 }
 
 // Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
-// each) and sb (B~^T, split_cols_pad(N) x ldk each), over the K stages [kb, ke) of every slice
+// each; crt_rows_pad(N) in the diagonal mode) and sb (B~^T, split_cols_pad(N) x ldk each;
+// crt_cols_pad(N)), over the K stages [kb, ke) of every slice
 // pair (kb = 0, ke < 0: all of K).  With `add` the int32 sums are added to G with atomics
 // (exact: a tile split along K over several blocks, G cleared beforehand), else stored.  With
 // `diag` the pairs are (1, 1) .. (s, s) instead, each into its own slab G[i-1] (the residue
@@ -394,8 +395,9 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     const int row0 = ti * kI8BM;      // rows of A~ / G
     const int cc0 = tj * kI8BN;       // real columns of G (rows of B~^T)
     const int M2 = 2 * N;             // real columns
-    const size_t sA = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
-    const size_t sB = (size_t)split_cols_pad(N) * ldk;
+    // bytes per slice (the residue slabs of the diagonal mode are padded to 256 rows)
+    const size_t sA = (size_t)(diag ? crt_rows_pad(N) : split_rows_pad(N)) * ldk;
+    const size_t sB = (size_t)(diag ? crt_cols_pad(N) : split_cols_pad(N)) * ldk;
     if (ke < 0) ke = ldk / kI8BK;     // K stages (real K = 2N, zero padded to ldk)
     const int total = (diag ? s : s * (s + 1) / 2) * (ke - kb);
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
@@ -519,6 +521,144 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     }
 #undef ZE_I8_LOAD
 #undef ZE_I8_STORE
+}
+
+// ------------------------------------------------- INT8 residue products, 256 x 256 tiles
+// The modular form's products (one per modulus) use a larger tile than zgemm_i8_tile's:
+// 256 rows x 256 real columns with 8 waves of
+// 128 x 64 (4 x 2 tiles of v_mfma_i32_32x32x32_i8): per MFMA half the global bytes and 3/4
+// of the LDS operand reads of the 128 x 128 tile.  LDS: two 64 KiB stages.  Same operand
+// layout, LDS row swizzle and stage pipeline as zgemm_i8_tile.
+constexpr int kI8LM = 256, kI8LN = 256, kI8LThreads = 512;
+constexpr int kI8LStage = (kI8LM + kI8LN) * kI8BK;
+
+struct I8LSmem {
+    signed char stage[2 * kI8LStage] __attribute__((aligned(16)));
+};
+
+// Slab G[k] (N x 2N int32) of tile (ti, tj) for every residue pair k < s, from sa (A~ residues,
+// crt_rows_pad(N) x ldk per modulus) and sb (B~^T residues, crt_cols_pad(N) x ldk), over the K
+// stages [kb, ke) (kb = 0, ke < 0: all of K); with `add` the sums are added with atomics.
+__device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed char* __restrict__ sa,
+                                                    const signed char* __restrict__ sb,
+                                                    int* __restrict__ G, int N, int s, int ldk,
+                                                    I8LSmem& sm, int kb, int ke, bool add) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int row0 = ti * kI8LM, cc0 = tj * kI8LN, M2 = 2 * N;
+    const size_t sA = (size_t)crt_rows_pad(N) * ldk, sB = (size_t)crt_cols_pad(N) * ldk;
+    if (ke < 0) ke = ldk / kI8BK;
+    const int total = s * (ke - kb);
+    const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+    const int l32 = lane & 31, h = lane >> 5;
+
+    v16i acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = (v16i)0;
+
+    // thread's x-th 16-byte piece of a stage: row (tid / 8) + 64 x, bytes 16 (tid % 8) ..
+    const signed char* pa = sa + (size_t)(row0 + (tid >> 3)) * ldk + (tid & 7) * 16;
+    const signed char* pb = sb + (size_t)(cc0 + (tid >> 3)) * ldk + (tid & 7) * 16;
+    const size_t xstep = (size_t)(kI8LThreads / 8) * ldk;
+    int soff_a[4], soff_b[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int rr = (tid >> 3) + 64 * x, ch = tid & 7;
+        soff_a[x] = i8_lds_offset(rr, ch);
+        soff_b[x] = i8_lds_offset(kI8LM + rr, ch);
+    }
+    const int swz = i8_swizzle(l32);
+    const int rda = (wr + l32) * kI8BK, rdb = (kI8LM + wc + l32) * kI8BK;
+
+    // next stage to load: K stage lk of the modulus whose slabs start at A_ / B_
+    int lk = kb;
+    const signed char* A_ = pa + kb * kI8BK;
+    const signed char* B_ = pb + kb * kI8BK;
+    const size_t wrapA = sA - (size_t)(ke - kb) * kI8BK, wrapB = sB - (size_t)(ke - kb) * kI8BK;
+    int cm = 0, ck = kb;  // stage in LDS
+    v4i ra[4], rb[4];
+#define ZE_I8L_LOAD()                                                             \
+    do {                                                                          \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                           \
+            ra[x] = *reinterpret_cast<const v4i*>(A_ + x * xstep);                \
+            rb[x] = *reinterpret_cast<const v4i*>(B_ + x * xstep);                \
+        }                                                                         \
+        A_ += kI8BK;                                                              \
+        B_ += kI8BK;                                                              \
+        if (++lk == ke) {                                                         \
+            lk = kb;                                                              \
+            A_ += wrapA;                                                          \
+            B_ += wrapB;                                                          \
+        }                                                                         \
+    } while (0)
+#define ZE_I8L_STORE(st)                                                          \
+    do {                                                                          \
+        _Pragma("unroll") for (int x = 0; x < 4; ++x) {                           \
+            *reinterpret_cast<v4i*>((st) + soff_a[x]) = ra[x];                    \
+            *reinterpret_cast<v4i*>((st) + soff_b[x]) = rb[x];                    \
+        }                                                                         \
+    } while (0)
+
+    ZE_I8L_LOAD();
+    ZE_I8L_STORE(sm.stage);
+    __syncthreads();
+    for (int it = 0; it < total; ++it) {
+        const bool more = it + 1 < total;
+        if (more) ZE_I8L_LOAD();
+        __builtin_amdgcn_sched_barrier(0);
+        const signed char* st = sm.stage + (it & 1) * kI8LStage;
+        v4i fa[4], fb[2];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int chunk = ((ks * 2 + h) ^ swz) << 4;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                fa[x] = *reinterpret_cast<const v4i*>(st + rda + x * 32 * kI8BK + chunk);
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                fb[x] = *reinterpret_cast<const v4i*>(st + rdb + x * 32 * kI8BK + chunk);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            if (ks == 3 && more) ZE_I8L_STORE(sm.stage + ((it + 1) & 1) * kI8LStage);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (ck == ke - 1) {  // last K stage of modulus cm: flush its accumulators to G[cm]
+            // the row stride passes through an empty asm statement so that the 128 output
+            // addresses are formed here, not kept in registers across the whole loop
+            int m2 = M2;
+            asm volatile("" : "+v"(m2));
+            int* g = G + (size_t)cm * N * M2;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int cc = cc0 + wc + 32 * c + l32;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = row0 + wr + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
+                        if (row < N && cc < M2) {
+                            if (add)
+                                atomicAdd(g + (size_t)row * m2 + cc, acc[a][c][r]);
+                            else
+                                g[(size_t)row * m2 + cc] = acc[a][c][r];
+                        }
+                    }
+                    acc[a][c] = (v16i)0;
+                }
+        }
+        if (++ck == ke) {
+            ck = kb;
+            ++cm;
+        }
+        __syncthreads();
+    }
+#undef ZE_I8L_LOAD
+#undef ZE_I8L_STORE
 }
 
 // Element e (row-major complex index) of C = 2^(ea_r + eb_c) sum_{t=2}^{s+1} 2^(2 - 8t) G[t-2].

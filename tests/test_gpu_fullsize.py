@@ -49,7 +49,7 @@ def casimir_ok(W0, W):
 
 
 def test_n4096_steps_fp64_and_split(dev):
-    from paper_2206_05466_amd import PREC_FP64, PREC_MIXED, PREC_SPLIT, Zeuler
+    from paper_2206_05466_amd import PREC_CRT, PREC_FP64, PREC_MIXED, PREC_SPLIT, Zeuler
 
     cfg = WORKLOADS["n4096"]
     N, h, L, steps = cfg["N"], cfg["h"], 32, 5
@@ -74,6 +74,10 @@ def test_n4096_steps_fp64_and_split(dev):
     its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_MIXED)
     W = to_host(Wd)
     assert its == it_ref and rel(W, Wr) < 1e-12, (its, rel(W, Wr))
+    Wd = to_dev(W0)
+    its, res = z.isomp_run(Wd, h, steps, cfg["tol"], cfg["maxit"], PREC_CRT)
+    W = to_host(Wd)
+    assert its == it_ref and rel(W, Wr) < 1e-12, (its, rel(W, Wr))
     # the timed headline form: W_{n+1} = W_n + h (A - A^H)
     Wd_r, itd, _ = O.isomp_run(W0, h, steps, cfg["tol"], cfg["maxit"], extrapolate=True, degree=3,
                                update="difference")
@@ -83,6 +87,27 @@ def test_n4096_steps_fp64_and_split(dev):
     W = to_host(Wd)
     assert its == itd and max(res) < cfg["tol"] and rel(W, Wd_r) < 1e-12, (its, itd)
     z.close()
+
+
+@pytest.mark.parametrize("N", [4096, 3000, 2048])
+def test_zgemm_crt_full_size_integers_exact_sampled_rows(dev, N):
+    """The modular product at the full sizes on integer operands up to 2^19, where every
+    modulus is needed and the exact sums (< 2^51) are FP64 integers: sampled rows equal numpy's
+    exact row products.  N = 4096: two whole rounds of 256 x 256 tiles, XCD-ordered; N = 3000
+    (ragged): one round of 256 x 256 tiles plus 32 tiles split along K; N = 2048: 128 x 128
+    tiles (too few large ones to fill the GPU)."""
+    from paper_2206_05466_amd import PREC_CRT, Zeuler
+
+    rng = np.random.default_rng(N + 5)
+    lim = 2 ** 19
+    A = rng.integers(-lim, lim + 1, (N, N)) + 1j * rng.integers(-lim, lim + 1, (N, N))
+    B = rng.integers(-lim, lim + 1, (N, N)) + 1j * rng.integers(-lim, lim + 1, (N, N))
+    z = Zeuler(N)
+    C = to_host(z.zgemm(to_dev(A), to_dev(B), prec=PREC_CRT))
+    z.close()
+    rows = np.concatenate([[0, N - 1], rng.integers(0, N, 6)])
+    for r in rows:
+        assert np.array_equal(C[r], A[r] @ B), r
 
 
 def test_n4096_basis_sampled_diagonals(dev):
