@@ -131,6 +131,26 @@ __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const int* __rest
     }
 }
 
+// The same from byte residues (slab k: N x 2N bytes, already reduced modulo p_k).
+__global__ __launch_bounds__(kThreads) void crt_combine_bytes_kernel(
+    const unsigned char* __restrict__ G8, const int* __restrict__ ea, const int* __restrict__ eb,
+    double2* __restrict__ Cm, int N, int b) {
+    const size_t n2 = (size_t)N * N, slab = 2 * n2;
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
+         e += (size_t)gridDim.x * kThreads) {
+        int gr[kCrtMods], gi[kCrtMods];
+#pragma unroll
+        for (int k = 0; k < kCrtMods; ++k) {
+            const unsigned short g = *reinterpret_cast<const unsigned short*>(G8 + (size_t)k * slab + 2 * e);
+            gr[k] = g & 0xff;
+            gi[k] = g >> 8;
+        }
+        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
+        const int sh = ea[r] + eb[c] - 2 * b;
+        Cm[e] = make_double2(ldexp(crt_reconstruct(gr), sh), ldexp(crt_reconstruct(gi), sh));
+    }
+}
+
 // mode 0: full product (tiles_m x tiles_n tiles), mode 1: lower-triangle tiles (ntiles of
 // them in i8_lower_tile's numbering).  Blocks b < full take one whole tile each; the
 // remaining tiles (a last, partial round of the GPU's block slots) are split along K: block
@@ -201,7 +221,8 @@ __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, i
 }
 
 // The modular form's residue products on 256 x 256 tiles (zgemm_i8_tile_large); blocks as in
-// zgemm_i8_kernel's full-product mode.
+// zgemm_i8_kernel's full-product mode.  Without a K split (full == ntiles) the sums are stored
+// as byte residues, else as int32 sums added over the K parts.
 __global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
     int N, int s, int ldk, int tiles_n, int ntiles, int full, int S) {
@@ -211,13 +232,13 @@ __global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
     if (b < full) {
         i8_tile_of(0, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
         if (tj >= tiles_n) return;
-        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false);
+        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false, full == ntiles);
     } else {
         const int e = b - full, p = e % S, nk = ldk / kI8BK;
         i8_tile_of(0, full + e / S, tiles_n, ntiles, false, b, ti, tj);
         if (tj >= tiles_n) return;
         zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
-                            (int)((long long)(p + 1) * nk / S), true);
+                            (int)((long long)(p + 1) * nk / S), true, false);
     }
 }
 
@@ -400,8 +421,13 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
     if (e != hipSuccess) return e;
     const size_t n2 = (size_t)N * N;
     const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
-    hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->crt_g,
-                       c->split_ea, c->split_eb, C, N, b);
+    if (large && full == ntiles)
+        hipLaunchKernelGGL(crt_combine_bytes_kernel, dim3(grid), dim3(kThreads), 0, st,
+                           reinterpret_cast<const unsigned char*>(c->crt_g), c->split_ea,
+                           c->split_eb, C, N, b);
+    else
+        hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->crt_g,
+                           c->split_ea, c->split_eb, C, N, b);
     return hipGetLastError();
 }
 

@@ -151,6 +151,14 @@ constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
 // Balanced residue of the integer X (|X| < 2^63) modulo p_k, in [-(p_k)/2, (p_k - 1)/2]:
 // |X| mod p from a 64-bit reciprocal (q = the high half of |X| floor(2^64 / p), at most one
 // below the true quotient), then the sign.
+// p_k for a wave-uniform runtime k.
+__device__ __forceinline__ int crt_modulus(int k) {
+    int p = kCrtP[0];
+#pragma unroll
+    for (int j = 1; j < kCrtMods; ++j) p = k == j ? kCrtP[j] : p;
+    return p;
+}
+
 template <int K>
 __device__ __forceinline__ int crt_residue(long long X) {
     constexpr int p = kCrtP[K];
@@ -539,10 +547,13 @@ struct I8LSmem {
 // Slab G[k] (N x 2N int32) of tile (ti, tj) for every residue pair k < s, from sa (A~ residues,
 // crt_rows_pad(N) x ldk per modulus) and sb (B~^T residues, crt_cols_pad(N) x ldk), over the K
 // stages [kb, ke) (kb = 0, ke < 0: all of K); with `add` the sums are added with atomics.
+// With `bytes` (whole K only) each sum is stored reduced modulo its p_k, as one byte, into
+// the N x 2N byte slab k of G.
 __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed char* __restrict__ sa,
                                                     const signed char* __restrict__ sb,
                                                     int* __restrict__ G, int N, int s, int ldk,
-                                                    I8LSmem& sm, int kb, int ke, bool add) {
+                                                    I8LSmem& sm, int kb, int ke, bool add,
+                                                    bool bytes) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8LM, cc0 = tj * kI8LN, M2 = 2 * N;
     const size_t sA = (size_t)crt_rows_pad(N) * ldk, sB = (size_t)crt_cols_pad(N) * ldk;
@@ -633,6 +644,9 @@ __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed
             int m2 = M2;
             asm volatile("" : "+v"(m2));
             int* g = G + (size_t)cm * N * M2;
+            unsigned char* g8 = reinterpret_cast<unsigned char*>(G) + (size_t)cm * N * M2;
+            const int p = crt_modulus(cm);
+            const double rp = 1.0 / (double)p;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -642,10 +656,16 @@ __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed
                     for (int r = 0; r < 16; ++r) {
                         const int row = row0 + wr + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
                         if (row < N && cc < M2) {
-                            if (add)
-                                atomicAdd(g + (size_t)row * m2 + cc, acc[a][c][r]);
-                            else
-                                g[(size_t)row * m2 + cc] = acc[a][c][r];
+                            const int v = acc[a][c][r];
+                            if (bytes) {
+                                int t = v - (int)floor((double)v * rp) * p;
+                                t = t < 0 ? t + p : (t >= p ? t - p : t);
+                                g8[(size_t)row * m2 + cc] = (unsigned char)t;
+                            } else if (add) {
+                                atomicAdd(g + (size_t)row * m2 + cc, v);
+                            } else {
+                                g[(size_t)row * m2 + cc] = v;
+                            }
                         }
                     }
                     acc[a][c] = (v16i)0;
