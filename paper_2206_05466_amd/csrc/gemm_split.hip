@@ -147,7 +147,8 @@ __global__ __launch_bounds__(kThreads) void crt_combine_bytes_kernel(
         }
         const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
         const int sh = ea[r] + eb[c] - 2 * b;
-        Cm[e] = make_double2(ldexp(crt_reconstruct(gr), sh), ldexp(crt_reconstruct(gi), sh));
+        Cm[e] = make_double2(ldexp(crt_reconstruct<true>(gr), sh),
+                             ldexp(crt_reconstruct<true>(gi), sh));
     }
 }
 

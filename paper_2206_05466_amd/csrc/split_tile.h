@@ -265,7 +265,7 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
 // Constants of the reconstruction: W_k = (M / p_k) ((M / p_k)^-1 mod p_k) < M, so that
 // X = sum_k c_k W_k mod M for c_k = X mod p_k; as two 64-bit halves and as doubles; M likewise.
 struct CrtConst {
-    unsigned long long wlo[kCrtMods], whi[kCrtMods];
+    unsigned wl[kCrtMods][4];  // W_k in 32-bit limbs, least significant first
     double wd[kCrtMods];
     unsigned long long mlo, mhi;
     double md;
@@ -288,8 +288,7 @@ constexpr CrtConst make_crt_const() {
         for (unsigned x = 1; x < p && y == 0; ++x)
             if ((r * x) % p == 1) y = x;
         const unsigned __int128 W = Mk * y;
-        k.wlo[i] = (unsigned long long)W;
-        k.whi[i] = (unsigned long long)(W >> 64);
+        for (int j = 0; j < 4; ++j) k.wl[i][j] = (unsigned)(W >> (32 * j));
         k.wd[i] = crt_u128_to_double(W);
     }
     k.mlo = (unsigned long long)M;
@@ -301,24 +300,35 @@ constexpr CrtConst make_crt_const() {
 constexpr CrtConst kCrtK = make_crt_const();
 
 // The integer X with |X| < M / 4 from the kCrtMods int32 products g_k (|g_k| < 2^31) of one
-// output value, rounded to FP64: c_k = g_k mod p_k; S = sum_k c_k W_k exactly modulo 2^128
-// (unsigned 128-bit arithmetic) and approximately in FP64; q = S / M rounded to the nearest
-// integer (exact: S / M lies within 1/4 of an integer since |X| < M / 4, and the FP64
-// estimate is off by far less); X = S - q M modulo 2^128 is X itself, read as signed.  The
-// magnitude is converted from its two 64-bit halves, each exact when X is representable.
+// output value (with `Reduced`, g_k = c_k already in [0, p_k)), rounded to FP64:
+// c_k = g_k mod p_k; S = sum_k c_k W_k exactly modulo 2^128, each 32-bit limb of W_k times c_k
+// summed in its own 64-bit accumulator (16 terms below 2^40 each), and approximately in FP64;
+// q = S / M rounded to the nearest integer (exact: S / M lies within 1/4 of an integer since
+// |X| < M / 4, and the FP64 estimate is off by far less); X = S - q M modulo 2^128 is X
+// itself, read as signed.  The magnitude is converted from its two 64-bit halves, each exact
+// when X is representable.
+template <bool Reduced = false>
 __device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
     constexpr CrtConst C = kCrtK;
-    unsigned __int128 S = 0;
+    unsigned long long l0 = 0, l1 = 0, l2 = 0, l3 = 0;
     double Sd = 0.0;
 #pragma unroll
     for (int k = 0; k < kCrtMods; ++k) {
-        const int p = kCrtP[k];
-        int c = g[k] - (int)floor((double)g[k] * (1.0 / (double)p)) * p;
-        c = c < 0 ? c + p : (c >= p ? c - p : c);
-        const unsigned __int128 W = ((unsigned __int128)C.whi[k] << 64) | C.wlo[k];
-        S += (unsigned __int128)(unsigned)c * W;
+        int c = g[k];
+        if (!Reduced) {
+            const int p = kCrtP[k];
+            c = c - (int)floor((double)c * (1.0 / (double)p)) * p;
+            c = c < 0 ? c + p : (c >= p ? c - p : c);
+        }
+        const unsigned long long u = (unsigned)c;
+        l0 += u * C.wl[k][0];
+        l1 += u * C.wl[k][1];
+        l2 += u * C.wl[k][2];
+        l3 += u * C.wl[k][3];
         Sd += (double)c * C.wd[k];
     }
+    const unsigned __int128 S = (unsigned __int128)l0 + ((unsigned __int128)l1 << 32) +
+                                ((unsigned __int128)l2 << 64) + ((unsigned __int128)l3 << 96);
     const unsigned long long q = (unsigned long long)rint(Sd / C.md);
     const unsigned __int128 M = ((unsigned __int128)C.mhi << 64) | C.mlo;
     const __int128 X = (__int128)(S - (unsigned __int128)q * M);
