@@ -52,7 +52,7 @@ typedef enum {
                            s_q = 4 below the FP64 products' own rounding. */
     ZE_PREC_CRT = 3     /* the modular form of the INT8 emulation (Ozaki scheme II): rows of
                            A~ / columns of B~ scaled by powers of two to integers of b bits
-                           (b = 55 up to N = 4096, 54 beyond), residues modulo 16 pairwise
+                           (b = 55 up to N = 8192, 54 at 16384), residues modulo 16 pairwise
                            coprime moduli <= 256, one exact INT8 product per modulus, and the
                            Chinese remainder theorem; the only error is the rounding of the
                            scaled inputs, 2^-b relative to the row / column maximum, i.e.

@@ -143,7 +143,7 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
 // |X| <= 0.99 2^b is represented exactly by its residues modulo kCrtMods pairwise coprime
 // moduli p_k <= 256 (balanced, so each fits an int8); one exact INT8 product per modulus gives
 // the integer product modulo p_k, and the Chinese remainder theorem recovers it exactly while
-// |X_A X_B| summed stays below M / 4, M = prod p_k (~2^125.2).
+// |X_A X_B| summed stays below 0.99^2 M / 2, M = prod p_k (~2^125.2).
 constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
                                  229, 227, 223, 211, 199, 197, 193, 191};
 
@@ -299,12 +299,13 @@ constexpr CrtConst make_crt_const() {
 
 constexpr CrtConst kCrtK = make_crt_const();
 
-// The integer X with |X| < M / 4 from the kCrtMods int32 products g_k (|g_k| < 2^31) of one
+// The integer X with |X| <= 0.99^2 M / 2 from the kCrtMods int32 products g_k (|g_k| < 2^31) of one
 // output value (with `Reduced`, g_k = c_k already in [0, p_k)), rounded to FP64:
 // c_k = g_k mod p_k; S = sum_k c_k W_k exactly modulo 2^128, each 32-bit limb of W_k times c_k
 // summed in its own 64-bit accumulator (16 terms below 2^40 each), and approximately in FP64;
-// q = S / M rounded to the nearest integer (exact: S / M lies within 1/4 of an integer since
-// |X| < M / 4, and the FP64 estimate is off by far less); X = S - q M modulo 2^128 is X
+// q = S / M rounded to the nearest integer (exact: S / M = q + X / M lies at least 0.01 from
+// a half-integer, and the FP64 estimate of S / M < 2^12 is off by less than 2^-36);
+// X = S - q M modulo 2^128 is X
 // itself, read as signed.  The magnitude is converted from its two 64-bit halves, each exact
 // when X is representable.
 template <bool Reduced = false>
