@@ -209,6 +209,29 @@ def test_ensemble_argument_errors(dev):
         for bad in (1, 5):
             with pytest.raises(ZeulerError):
                 ens.set_split_slices_lower(bad)
+        # the ensemble runs FP64 or split products only; the single-context modes and
+        # unknown codes are refused before any launch
+        from paper_2206_05466_amd import PREC_CRT, PREC_MIXED
+
+        for bad in (PREC_MIXED, PREC_CRT, 4, -1):
+            with pytest.raises(ZeulerError):
+                ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], 0.01, 1, 1e-12, 4, prec=bad)
+
+
+def test_unknown_precision_codes_rejected(dev):
+    from paper_2206_05466_amd import PREC_MIXED, Zeuler, ZeulerError
+
+    W = to_dev(w0(20, 3))
+    before = W.clone()
+    with Zeuler(20) as z:
+        with pytest.raises(ZeulerError):  # mixed precision applies to the step only
+            z.zgemm(W, W, prec=PREC_MIXED)
+        for bad in (4, -1):
+            with pytest.raises(ZeulerError):
+                z.zgemm(W, W, prec=bad)
+            with pytest.raises(ZeulerError):
+                z.isomp_step(W, 0.01, prec=bad)
+    assert torch.equal(W, before)
 
 
 # ------------------------------------------------------------------ Casimirs
