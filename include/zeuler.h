@@ -53,7 +53,7 @@ typedef enum {
     ZE_PREC_CRT = 3     /* the modular form of the INT8 emulation (Ozaki scheme II): rows of
                            A~ / columns of B~ scaled by powers of two to integers of b bits
                            (b = 55 up to N = 8192, 54 at 16384), residues modulo 16 pairwise
-                           coprime moduli <= 256, one exact INT8 product per modulus, and the
+                           coprime moduli <= 256, three exact INT8 products per modulus, and the
                            Chinese remainder theorem; the only error is the rounding of the
                            scaled inputs, 2^-b relative to the row / column maximum, i.e.
                            FP64-level.  ze_zgemm, and in ze_isomp_step / ze_isomp_run the

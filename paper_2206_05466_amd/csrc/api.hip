@@ -53,9 +53,9 @@ ze_status ze_ensure_rings(ze_ctx* c, int ns) {
 ze_status ze_ensure_crt(ze_ctx* c) {
     if (c->crt_g) return ZE_OK;
     ZE_TRY(ze_ensure_split(c));  // exponent vectors and column-maximum partials
-    const size_t ldk = (size_t)ze_split_ldk(c->N);
-    const size_t bytes_a = (size_t)kCrtMods * crt_rows_pad(c->N) * ldk;
-    const size_t bytes_b = (size_t)kCrtMods * crt_cols_pad(c->N) * ldk;
+    const size_t ldk = (size_t)ze_crt_ldk(c->N);
+    const size_t bytes_a = (size_t)3 * kCrtMods * crt_rows_pad(c->N) * ldk;
+    const size_t bytes_b = bytes_a;
     ze_status st = dalloc(&c->crt_a, bytes_a);
     if (st == ZE_OK) st = dalloc(&c->crt_b, bytes_b);
     // zero padding rows once; the residue kernels never write them

@@ -108,42 +108,40 @@ __global__ __launch_bounds__(kThreads) void crt_cols_kernel(const double2* __res
     crt_cols_tile(B, N, blockIdx.x, blockIdx.y, b, ldk, eb, slices, tile);
 }
 
-// C[e] from the residue products: both real parts of complex element e through the CRT, then
+// C[e] from the residue products, three N x N byte slabs per modulus k (P1 = ar br,
+// P2 = ai bi, P3 = (ar + ai)(br + bi), each reduced modulo p_k), in S parts along K whose
+// residues add modulo p_k: Re = P1 - P2 and Im = P3 - P1 - P2 modulo p_k through the CRT, then
 // scaled by 2^(ea_r + eb_c - 2b).
-__global__ __launch_bounds__(kThreads) void crt_combine_kernel(const int* __restrict__ G,
+__global__ __launch_bounds__(kThreads) void crt_combine_kernel(const unsigned char* __restrict__ G8,
+                                                               int S,
                                                                const int* __restrict__ ea,
                                                                const int* __restrict__ eb,
                                                                double2* __restrict__ Cm, int N,
                                                                int b) {
-    const size_t n2 = (size_t)N * N, slab = 2 * n2;
+    const size_t n2 = (size_t)N * N, part = (size_t)3 * kCrtMods * n2;
     for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
          e += (size_t)gridDim.x * kThreads) {
         int gr[kCrtMods], gi[kCrtMods];
 #pragma unroll
         for (int k = 0; k < kCrtMods; ++k) {
-            const int2 g = *reinterpret_cast<const int2*>(G + (size_t)k * slab + 2 * e);
-            gr[k] = g.x;
-            gi[k] = g.y;
-        }
-        const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
-        const int sh = ea[r] + eb[c] - 2 * b;
-        Cm[e] = make_double2(ldexp(crt_reconstruct(gr), sh), ldexp(crt_reconstruct(gi), sh));
-    }
-}
-
-// The same from byte residues (slab k: N x 2N bytes, already reduced modulo p_k).
-__global__ __launch_bounds__(kThreads) void crt_combine_bytes_kernel(
-    const unsigned char* __restrict__ G8, const int* __restrict__ ea, const int* __restrict__ eb,
-    double2* __restrict__ Cm, int N, int b) {
-    const size_t n2 = (size_t)N * N, slab = 2 * n2;
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
-         e += (size_t)gridDim.x * kThreads) {
-        int gr[kCrtMods], gi[kCrtMods];
-#pragma unroll
-        for (int k = 0; k < kCrtMods; ++k) {
-            const unsigned short g = *reinterpret_cast<const unsigned short*>(G8 + (size_t)k * slab + 2 * e);
-            gr[k] = g & 0xff;
-            gi[k] = g >> 8;
+            const int p = kCrtP[k];
+            const size_t o = (size_t)(3 * k) * n2 + e;
+            int p1 = 0, p2 = 0, p3 = 0;
+            for (int q = 0; q < S; ++q) {
+                p1 += G8[q * part + o];
+                p2 += G8[q * part + o + n2];
+                p3 += G8[q * part + o + 2 * n2];
+            }
+            p1 %= p;
+            p2 %= p;
+            p3 %= p;
+            int re = p1 - p2;
+            re = re < 0 ? re + p : re;
+            int im = p3 - p1 - p2;
+            im = im < 0 ? im + p : im;
+            im = im < 0 ? im + p : im;
+            gr[k] = re;
+            gi[k] = im;
         }
         const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
         const int sh = ea[r] + eb[c] - 2 * b;
@@ -188,31 +186,31 @@ __device__ __forceinline__ void i8_tile_of(int mode, int tile, int tiles_n, int 
 
 __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
-    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S, int diag) {
+    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S) {
     __shared__ I8Smem sm;
     int ti, tj;
     const int b = blockIdx.x;
     if (b < full) {
         i8_tile_of(mode, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
         if (tj >= tiles_n) return;  // ragged N: block idle (uniform)
-        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false, diag != 0);
+        zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false);
     } else {
         const int e = b - full, p = e % S, nk = ldk / kI8BK;
         i8_tile_of(mode, full + e / S, tiles_n, ntiles, false, b, ti, tj);
         if (tj >= tiles_n) return;
         zgemm_i8_tile(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
-                      (int)((long long)(p + 1) * nk / S), true, diag != 0);
+                      (int)((long long)(p + 1) * nk / S), true);
     }
 }
 
-// Clears the slabs G[0..s-1] over the tiles full .. ntiles-1 (the K-split ones) of bm x bn
-// tiles; grid (ntiles - full, s).
+// Clears the slabs G[0..s-1] (N x ncols each) over the tiles full .. ntiles-1 (the K-split
+// ones) of bm x bn tiles; grid (ntiles - full, s).
 __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, int N, int mode,
                                                           int tiles_n, int ntiles, int full,
-                                                          int bm, int bn) {
+                                                          int bm, int bn, int ncols) {
     int ti, tj;
     i8_tile_of(mode, full + blockIdx.x, tiles_n, ntiles, false, 0, ti, tj);
-    const int M2 = 2 * N;
+    const int M2 = ncols;
     if (tj >= tiles_n) return;
     int* g = G + (size_t)blockIdx.y * N * M2;
     for (int x = threadIdx.x; x < bm * bn; x += kThreads) {
@@ -221,26 +219,19 @@ __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, i
     }
 }
 
-// The modular form's residue products on 256 x 256 tiles (zgemm_i8_tile_large); blocks as in
-// zgemm_i8_kernel's full-product mode.  Without a K split (full == ntiles) the sums are stored
-// as byte residues, else as int32 sums added over the K parts.
+// The modular form's residue products on 256 x 256 tiles (zgemm_i8_tile_large) over the N x N
+// output: block b takes part b % S of the K stages of tile b / S and writes its byte residues
+// to part region b % S of G8 (regions of 3 kCrtMods N^2 bytes).
 __global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
-    const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
-    int N, int s, int ldk, int tiles_n, int ntiles, int full, int S) {
+    const signed char* __restrict__ sa, const signed char* __restrict__ sb,
+    unsigned char* __restrict__ G8, int N, int s, int ldk, int tiles_n, int ntiles, int S) {
     __shared__ I8LSmem sm;
+    const int b = blockIdx.x, tile = b / S, part = b % S, nk = ldk / kI8BK;
     int ti, tj;
-    const int b = blockIdx.x;
-    if (b < full) {
-        i8_tile_of(0, b, tiles_n, ntiles, full == ntiles, b, ti, tj);
-        if (tj >= tiles_n) return;
-        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, 0, -1, false, full == ntiles);
-    } else {
-        const int e = b - full, p = e % S, nk = ldk / kI8BK;
-        i8_tile_of(0, full + e / S, tiles_n, ntiles, false, b, ti, tj);
-        if (tj >= tiles_n) return;
-        zgemm_i8_tile_large(ti, tj, sa, sb, G, N, s, ldk, sm, (int)((long long)p * nk / S),
-                            (int)((long long)(p + 1) * nk / S), true, false);
-    }
+    i8_tile_of(0, tile, tiles_n, ntiles, S == 1, b, ti, tj);
+    if (tj >= tiles_n) return;
+    zgemm_i8_tile_large(ti, tj, sa, sb, G8 + (size_t)part * s * N * (size_t)N, N, s, ldk, sm,
+                        (int)((long long)part * nk / S), (int)((long long)(part + 1) * nk / S));
 }
 
 __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __restrict__ G,
@@ -338,13 +329,13 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     }
     if (full < ntiles) {
         hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, s), dim3(kThreads), 0, st, c->split_g,
-                           N, lower ? 1 : 0, tn, ntiles, full, kI8BM, kI8BN);
+                           N, lower ? 1 : 0, tn, ntiles, full, kI8BM, kI8BN, 2 * N);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
                        c->split_a, c->split_b, c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn,
-                       ntiles, full, S, 0);
+                       ntiles, full, S);
     e = hipGetLastError();
     if (e != hipSuccess || lower) return e;
     const size_t n2 = (size_t)N * N;
@@ -362,11 +353,32 @@ int ze_crt_bits(int N) {
     return b < 55 ? b : 55;
 }
 
-size_t ze_crt_slab_ints(int N) { return (size_t)kCrtMods * 2 * N * (size_t)N; }
+size_t ze_crt_slab_ints(int N) { return (size_t)3 * kCrtMods * N * (size_t)N; }
+
+int ze_crt_ldk(int N) { return ((N + kI8BK - 1) / kI8BK) * kI8BK; }
+
+// Tiles of the modular product (256 x 256 over the N x N output).  When they fill at least
+// one round of the block slots each tile is one block; else each is split along K into
+// S <= 4 parts (at least 4 stages each) to fill the slots, as many byte regions as the int32
+// slab allocation holds.
+void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* S) {
+    const int t = (N + kI8LM - 1) / kI8LM;
+    *tn = t;
+    *ntiles = t * t;
+    *S = 1;
+    const int nk = ze_crt_ldk(N) / kI8BK;
+    const int cap = cap_blocks > 0 ? cap_blocks : *ntiles;
+    if (*ntiles < cap) {
+        int sp = cap / *ntiles;
+        if (sp > nk / 4) sp = nk / 4;
+        if (sp > 4) sp = 4;
+        if (sp > 1) *S = sp;
+    }
+}
 
 hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                             hipStream_t st) {
-    const int N = c->N, ldk = ze_split_ldk(N), b = ze_crt_bits(N);
+    const int N = c->N, ldk = ze_crt_ldk(N), b = ze_crt_bits(N);
     hipLaunchKernelGGL(crt_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, b, ldk, c->crt_a,
                        c->split_ea);
     hipError_t e = hipGetLastError();
@@ -380,55 +392,22 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
                        c->split_eb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g((N + kCT - 1) / kCT, (ldk / 2 + kCT - 1) / kCT);
+    dim3 g((N + kCT - 1) / kCT, (ldk + kCT - 1) / kCT);
     hipLaunchKernelGGL(crt_cols_kernel, g, dim3(kThreads), 0, st, B, N, b, ldk, c->split_eb,
                        c->crt_b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // 256 x 256 tiles when they fill at least one round of the GPU's block slots, else the
-    // 128 x 128 kernel's diagonal mode (more tiles, no K split at mid sizes)
-    const bool large = ((N + kI8LM - 1) / kI8LM) * ((2 * N + kI8LN - 1) / kI8LN) >= c->cap_i8l;
-    const int bm = large ? kI8LM : kI8BM, bn = large ? kI8LN : kI8BN;
-    const int tr = (N + bm - 1) / bm;
-    const int tn = (2 * N + bn - 1) / bn;
-    const int ntiles = tr * tn;
-    const int nk = ldk / kI8BK;
-    int full = ntiles, S = 1;
-    const int capk = large ? c->cap_i8l : c->cap_i8;
-    const int cap = capk > 0 ? capk : ntiles;
-    const int rem = ntiles % cap;
-    if (rem > 0) {
-        int sp = cap / rem;
-        if (sp > nk / 4) sp = nk / 4;
-        if (sp > 1) {
-            full = ntiles - rem;
-            S = sp;
-        }
-    }
-    if (full < ntiles) {
-        hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, kCrtMods), dim3(kThreads), 0, st,
-                           c->crt_g, N, 0, tn, ntiles, full, bm, bn);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    const unsigned nb = (unsigned)(full + (ntiles - full) * S);
-    if (large)
-        hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(nb), dim3(kI8LThreads), 0, st, c->crt_a,
-                           c->crt_b, c->crt_g, N, kCrtMods, ldk, tn, ntiles, full, S);
-    else
-        hipLaunchKernelGGL(zgemm_i8_kernel, dim3(nb), dim3(kThreads), 0, st, c->crt_a, c->crt_b,
-                           c->crt_g, N, kCrtMods, ldk, 0, tn, ntiles, full, S, 1);
+    int ntiles, tn, S;
+    ze_crt_plan(N, c->cap_i8l, &ntiles, &tn, &S);
+    unsigned char* G8 = reinterpret_cast<unsigned char*>(c->crt_g);
+    hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(ntiles * S), dim3(kI8LThreads), 0, st,
+                       c->crt_a, c->crt_b, G8, N, 3 * kCrtMods, ldk, tn, ntiles, S);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t n2 = (size_t)N * N;
     const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
-    if (large && full == ntiles)
-        hipLaunchKernelGGL(crt_combine_bytes_kernel, dim3(grid), dim3(kThreads), 0, st,
-                           reinterpret_cast<const unsigned char*>(c->crt_g), c->split_ea,
-                           c->split_eb, C, N, b);
-    else
-        hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->crt_g,
-                           c->split_ea, c->split_eb, C, N, b);
+    hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, G8, S, c->split_ea,
+                       c->split_eb, C, N, b);
     return hipGetLastError();
 }
 

@@ -133,7 +133,6 @@ __host__ __device__ inline int split_rows_pad(int N) { return ((N + 127) / 128) 
 __host__ __device__ inline int split_cols_pad(int N) { return ((2 * N + 127) / 128) * 128; }
 // Rows of the residue slabs of A~ and of B~^T (the modular form), padded to its 256-row tiles.
 __host__ __device__ inline int crt_rows_pad(int N) { return ((N + 255) / 256) * 256; }
-__host__ __device__ inline int crt_cols_pad(int N) { return ((2 * N + 255) / 256) * 256; }
 
 // ze_create without (split_k = false) the split-K partial buffer of the single-problem products.
 // solve_bd: stream-solve band width (1, 2 or 4), 0 = the default for N (solve_bd(N)).
@@ -217,6 +216,8 @@ hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out
 // the product C = A B (full), and the context's buffers for it.
 int ze_crt_bits(int N);
 size_t ze_crt_slab_ints(int N);
+int ze_crt_ldk(int N);
+void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* S);
 hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                             hipStream_t s);
 ze_status ze_ensure_crt(ze_ctx* c);

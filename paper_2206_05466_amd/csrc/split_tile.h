@@ -141,7 +141,7 @@ __device__ __forceinline__ void split_cols_tile(const double2* __restrict__ B, i
 // ---------------------------------------------------------------- modular (CRT) form
 // Ozaki scheme II: a row of A~ (column of B~) scaled by a power of two to integers X with
 // |X| <= 0.99 2^b is represented exactly by its residues modulo kCrtMods pairwise coprime
-// moduli p_k <= 256 (balanced, so each fits an int8); one exact INT8 product per modulus gives
+// moduli p_k <= 256 (balanced, so each fits an int8); exact INT8 products per modulus give
 // the integer product modulo p_k, and the Chinese remainder theorem recovers it exactly while
 // |X_A X_B| summed stays below 0.99^2 M / 2, M = prod p_k (~2^125.2).
 constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
@@ -191,8 +191,40 @@ __device__ __forceinline__ void crt_digits(double x, int e, int b, int (&d)[kCrt
 }
 
 // Row r of A~ in residue form: slice k holds the residues modulo p_k (layout of split_row_block).
+// Balanced residue of d1 + d2 (both balanced residues modulo p_K).
+template <int K>
+__device__ __forceinline__ int crt_balanced_sum(int d1, int d2) {
+    constexpr int p = kCrtP[K];
+    int t = d1 + d2;
+    t = t > (p - 1) / 2 ? t - p : t;
+    return t < -(p / 2) ? t + p : t;
+}
+
+// Stores the three residues of modulus k (real part, imaginary part, their sum) at o in slabs
+// 3k, 3k + 1, 3k + 2 (slab stride ss), for k < K.
+template <int K>
+struct CrtStore3 {
+    __device__ __forceinline__ static void run(const int (&dr)[kCrtMods], const int (&di)[kCrtMods],
+                                               signed char* o, size_t ss) {
+        CrtStore3<K - 1>::run(dr, di, o, ss);
+        constexpr int k = K - 1;
+        o[(3 * k) * ss] = (signed char)dr[k];
+        o[(3 * k + 1) * ss] = (signed char)di[k];
+        o[(3 * k + 2) * ss] = (signed char)crt_balanced_sum<k>(dr[k], di[k]);
+    }
+};
+template <>
+struct CrtStore3<0> {
+    __device__ __forceinline__ static void run(const int (&)[kCrtMods], const int (&)[kCrtMods],
+                                               signed char*, size_t) {}
+};
+
+// Residues for the complex product in three real products per modulus (exact modulo p_k):
+// Re = ar br - ai bi, Im = (ar + ai)(br + bi) - ar br - ai bi.  Slab 3k + q (q = 0: real part,
+// 1: imaginary part, 2: their sum, all modulo p_k) holds crt_rows_pad(N) rows of ldk bytes
+// (K = N, zero padded).  Row r of A~ (one block per row; the row exponent from its maximum):
 __device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int N, int r, int b, int ldk,
-                                      signed char* __restrict__ slices, int* __restrict__ ea,
+                                      signed char* __restrict__ slabs, int* __restrict__ ea,
                                       double* red) {
     const double2* row = A + (size_t)r * N;
     double m = 0.0;
@@ -209,26 +241,21 @@ __device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int
     const int e = exponent_of(red[0]);
     if (threadIdx.x == 0) ea[r] = e;
     const size_t ss = (size_t)crt_rows_pad(N) * ldk;
-    signed char* base = slices + (size_t)r * ldk;
-    for (int c = threadIdx.x; c < ldk / 2; c += kSThreads) {
+    signed char* base = slabs + (size_t)r * ldk;
+    for (int c = threadIdx.x; c < ldk; c += kSThreads) {
         const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);
         int dr[kCrtMods], di[kCrtMods];
         crt_digits(v.x, e, b, dr);
         crt_digits(v.y, e, b, di);
-#pragma unroll
-        for (int i = 0; i < kCrtMods; ++i) {
-            const unsigned short pk = (unsigned short)((unsigned char)(signed char)dr[i]) |
-                                      ((unsigned short)((unsigned char)(signed char)di[i]) << 8);
-            *reinterpret_cast<unsigned short*>(base + i * ss + 2 * c) = pk;
-        }
+        CrtStore3<kCrtMods>::run(dr, di, base + c, ss);
     }
 }
 
-// B~^T in residue form, tile (bx, by) as split_cols_tile (same layout); the residues of -Im b
-// are minus those of Im b, except that -(-128) = 128 is -128 modulo 256.
+// B~^T rows (one per column c of B, K = N along the row), tile (bx, by) of kCT columns x kCT
+// K values staged through LDS so that both the reads of B and the byte stores are coalesced.
 __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int N, int bx, int by, int b,
                                       int ldk, const int* __restrict__ eb,
-                                      signed char* __restrict__ slices,
+                                      signed char* __restrict__ slabs,
                                       double2 (*tile)[kCT + 1]) {
     const int k0 = by * kCT, c0 = bx * kCT;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -237,9 +264,9 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
         tile[a][tx] = (k < N && c < N) ? B[(size_t)k * N + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const size_t ss = (size_t)crt_cols_pad(N) * ldk;
+    const size_t ss = (size_t)crt_rows_pad(N) * ldk;
     const int k = k0 + tx;
-    if (2 * k >= ldk) return;
+    if (k >= ldk) return;
     for (int a = ty; a < kCT; a += 8) {
         const int c = c0 + a;
         if (c >= N) break;
@@ -248,17 +275,7 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
         int dr[kCrtMods], di[kCrtMods];
         crt_digits(v.x, e, b, dr);
         crt_digits(v.y, e, b, di);
-        signed char* o0 = slices + (size_t)(2 * c) * ldk + 2 * k;
-        signed char* o1 = slices + (size_t)(2 * c + 1) * ldk + 2 * k;
-#pragma unroll
-        for (int i = 0; i < kCrtMods; ++i) {
-            const int n = di[i] == -128 ? -128 : -di[i];
-            const unsigned char ur = (unsigned char)(signed char)dr[i];
-            const unsigned char ui = (unsigned char)(signed char)di[i];
-            const unsigned char nui = (unsigned char)(signed char)n;
-            *reinterpret_cast<unsigned short*>(o0 + i * ss) = (unsigned short)ur | ((unsigned short)nui << 8);
-            *reinterpret_cast<unsigned short*>(o1 + i * ss) = (unsigned short)ui | ((unsigned short)ur << 8);
-        }
+        CrtStore3<kCrtMods>::run(dr, di, slabs + (size_t)c * ldk + k, ss);
     }
 }
 
@@ -395,12 +412,9 @@ __device__ __forceinline__ void i8_next_pair(int& i, int& j) {
 }
 
 // Slabs G[t-2] of tile (ti, tj) of A~ B~ from the slices sa (A~, split_rows_pad(N) x ldk
-// each; crt_rows_pad(N) in the diagonal mode) and sb (B~^T, split_cols_pad(N) x ldk each;
-// crt_cols_pad(N)), over the K stages [kb, ke) of every slice
+// each) and sb (B~^T, split_cols_pad(N) x ldk each), over the K stages [kb, ke) of every slice
 // pair (kb = 0, ke < 0: all of K).  With `add` the int32 sums are added to G with atomics
-// (exact: a tile split along K over several blocks, G cleared beforehand), else stored.  With
-// `diag` the pairs are (1, 1) .. (s, s) instead, each into its own slab G[i-1] (the residue
-// products of the modular form).
+// (exact: a tile split along K over several blocks, G cleared beforehand), else stored.
 // Each iteration issues the global loads of the next stage, computes the current stage from
 // LDS, and stores the next stage to the other LDS buffer at the end of the stage; scheduling
 // barriers keep that order (left alone, the compiler moves the LDS store up to the loads,
@@ -409,16 +423,15 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
                                               const signed char* __restrict__ sb,
                                               int* __restrict__ G, int N, int s, int ldk,
                                               I8Smem& sm, int kb = 0, int ke = -1,
-                                              bool add = false, bool diag = false) {
+                                              bool add = false) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8BM;      // rows of A~ / G
     const int cc0 = tj * kI8BN;       // real columns of G (rows of B~^T)
     const int M2 = 2 * N;             // real columns
-    // bytes per slice (the residue slabs of the diagonal mode are padded to 256 rows)
-    const size_t sA = (size_t)(diag ? crt_rows_pad(N) : split_rows_pad(N)) * ldk;
-    const size_t sB = (size_t)(diag ? crt_cols_pad(N) : split_cols_pad(N)) * ldk;
+    const size_t sA = (size_t)split_rows_pad(N) * ldk;  // bytes per slice
+    const size_t sB = (size_t)split_cols_pad(N) * ldk;
     if (ke < 0) ke = ldk / kI8BK;     // K stages (real K = 2N, zero padded to ldk)
-    const int total = (diag ? s : s * (s + 1) / 2) * (ke - kb);
+    const int total = s * (s + 1) / 2 * (ke - kb);
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int l32 = lane & 31, h = lane >> 5;
 
@@ -444,8 +457,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
     const int swz = i8_swizzle(l32);
     const int rda = (wr + l32) * kI8BK, rdb = (kI8BM + wc + l32) * kI8BK;
 
-    int li = 1, lj = diag ? 1 : s, lk = kb;  // next stage to load
-    int ci = 1, cj = diag ? 1 : s, ck = kb;  // stage in LDS
+    int li = 1, lj = s, lk = kb;  // next stage to load
+    int ci = 1, cj = s, ck = kb;  // stage in LDS
     v4i ra[4], rb[4];  // native vectors (HIP's uint4 is a struct whose copies become memcpy)
 #define ZE_I8_LOAD()                                                              \
     do {                                                                          \
@@ -457,12 +470,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
         }                                                                         \
         if (++lk == ke) {                                                         \
             lk = kb;                                                              \
-            if (diag) {                                                           \
-                ++li;                                                             \
-                ++lj;                                                             \
-            } else {                                                              \
-                i8_next_pair(li, lj);                                             \
-            }                                                                     \
+            i8_next_pair(li, lj);                                                 \
         }                                                                         \
     } while (0)
 #define ZE_I8_STORE(st)                                                           \
@@ -507,8 +515,8 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
             __builtin_amdgcn_sched_barrier(0);
         }
 #undef ZE_I8_READ
-        if (ck == ke - 1 && (diag || cj == 1)) {  // last stage of the last pair of this t
-            int* g = G + (size_t)(diag ? ci - 1 : ci + cj - 2) * N * M2;
+        if (ck == ke - 1 && cj == 1) {  // last stage of the last pair of this t
+            int* g = G + (size_t)(ci + cj - 2) * N * M2;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -529,12 +537,7 @@ __device__ __forceinline__ void zgemm_i8_tile(int ti, int tj, const signed char*
         }
         if (++ck == ke) {
             ck = kb;
-            if (diag) {
-                ++ci;
-                ++cj;
-            } else {
-                i8_next_pair(ci, cj);
-            }
+            i8_next_pair(ci, cj);
         }
         __syncthreads();
     }
@@ -555,20 +558,16 @@ struct I8LSmem {
     signed char stage[2 * kI8LStage] __attribute__((aligned(16)));
 };
 
-// Slab G[k] (N x 2N int32) of tile (ti, tj) for every residue pair k < s, from sa (A~ residues,
-// crt_rows_pad(N) x ldk per modulus) and sb (B~^T residues, crt_cols_pad(N) x ldk), over the K
-// stages [kb, ke) (kb = 0, ke < 0: all of K); with `add` the sums are added with atomics.
-// With `bytes` (whole K only) each sum is stored reduced modulo its p_k, as one byte, into
-// the N x 2N byte slab k of G.
+// Byte slab G8[j] (N x N) of tile (ti, tj) for every residue slab pair j < s (three per
+// modulus, see crt_row_block), from sa and sb (crt_rows_pad(N) x ldk bytes per slab), over the
+// K stages [kb, ke): each int32 sum is stored reduced modulo p_(j / 3).
 __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed char* __restrict__ sa,
                                                     const signed char* __restrict__ sb,
-                                                    int* __restrict__ G, int N, int s, int ldk,
-                                                    I8LSmem& sm, int kb, int ke, bool add,
-                                                    bool bytes) {
+                                                    unsigned char* __restrict__ G8, int N, int s,
+                                                    int ldk, I8LSmem& sm, int kb, int ke) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int row0 = ti * kI8LM, cc0 = tj * kI8LN, M2 = 2 * N;
-    const size_t sA = (size_t)crt_rows_pad(N) * ldk, sB = (size_t)crt_cols_pad(N) * ldk;
-    if (ke < 0) ke = ldk / kI8BK;
+    const int row0 = ti * kI8LM, cc0 = tj * kI8LN, M2 = N;  // N output columns per slab
+    const size_t sA = (size_t)crt_rows_pad(N) * ldk, sB = sA;
     const int total = s * (ke - kb);
     const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
     const int l32 = lane & 31, h = lane >> 5;
@@ -654,9 +653,8 @@ __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed
             // addresses are formed here, not kept in registers across the whole loop
             int m2 = M2;
             asm volatile("" : "+v"(m2));
-            int* g = G + (size_t)cm * N * M2;
-            unsigned char* g8 = reinterpret_cast<unsigned char*>(G) + (size_t)cm * N * M2;
-            const int p = crt_modulus(cm);
+            unsigned char* g8 = G8 + (size_t)cm * N * M2;
+            const int p = crt_modulus(cm / 3);
             const double rp = 1.0 / (double)p;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -668,15 +666,9 @@ __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed
                         const int row = row0 + wr + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
                         if (row < N && cc < M2) {
                             const int v = acc[a][c][r];
-                            if (bytes) {
-                                int t = v - (int)floor((double)v * rp) * p;
-                                t = t < 0 ? t + p : (t >= p ? t - p : t);
-                                g8[(size_t)row * m2 + cc] = (unsigned char)t;
-                            } else if (add) {
-                                atomicAdd(g + (size_t)row * m2 + cc, v);
-                            } else {
-                                g[(size_t)row * m2 + cc] = v;
-                            }
+                            int t = v - (int)floor((double)v * rp) * p;
+                            t = t < 0 ? t + p : (t >= p ? t - p : t);
+                            g8[(size_t)row * m2 + cc] = (unsigned char)t;
                         }
                     }
                     acc[a][c] = (v16i)0;
