@@ -93,9 +93,9 @@ def test_n4096_steps_fp64_and_split(dev):
 def test_zgemm_crt_full_size_integers_exact_sampled_rows(dev, N):
     """The modular product at the full sizes on integer operands up to 2^19, where every
     modulus is needed and the exact sums (< 2^51) are FP64 integers: sampled rows equal numpy's
-    exact row products.  N = 4096: two whole rounds of 256 x 256 tiles, XCD-ordered; N = 3000
-    (ragged): one round of 256 x 256 tiles plus 32 tiles split along K; N = 2048: 128 x 128
-    tiles (too few large ones to fill the GPU)."""
+    exact row products.  N = 4096: one whole round of 256 x 256 tiles, XCD-ordered; N = 3000
+    (ragged): 144 tiles over the whole K; N = 2048: 64 tiles, each split along K into 4 parts
+    whose byte residues the combine adds."""
     from paper_2206_05466_amd import PREC_CRT, Zeuler
 
     rng = np.random.default_rng(N + 5)
