@@ -30,12 +30,13 @@
 // GEMM-oriented emulation of floating-point matrix multiplication using an integer modular
 // technique", 2025).  Rows of A~ and columns of B~ are scaled by powers of two to integers of
 // at most b bits, exactly, up to the one rounding to an integer; their residues modulo 16
-// pairwise coprime moduli <= 256 take the place of the slices (same layouts), one exact INT8
-// product per modulus (the diagonal pairs of the INT8 kernel) gives each product modulo p_k,
-// and the Chinese remainder theorem recovers the integer product exactly, since b is chosen
-// so that 2N 2^(2b) < M / 2, M = prod p_k ~ 2^125.2.  The only error is the rounding of the
-// scaled inputs to integers, 2^-b relative to the row / column maximum, with b = 55 up to
-// N = 4096: FP64-level accuracy from 16 INT8 products where the sliced form needs 28.
+// pairwise coprime moduli <= 256 are stored for the real part, the imaginary part and their
+// sum; three exact INT8 products per modulus (ar br, ai bi, (ar + ai)(br + bi)) give the real
+// and imaginary parts of the complex product modulo p_k, and the Chinese remainder theorem
+// recovers the integer product exactly, since b is chosen so that 2N 2^(2b) < M / 2,
+// M = prod p_k ~ 2^125.2.  The only error is the rounding of the scaled inputs to integers,
+// 2^-b relative to the row / column maximum, with b = 55 up to N = 8192: FP64-level accuracy
+// from 48 INT8 products of N x N x N.
 
 #include <cmath>
 
