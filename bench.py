@@ -7,7 +7,8 @@ A = P W~, lower Q = A P with the fused update and residual) until the change of 
 1e-12 in the infinity norm.  The workload is synthetic: W_0 = sum_lm i omega_lm T_lm with seeded
 random omega_lm (workloads/), assembled on the GPU by the library's basis kernel.
 
-Prints ONE JSON line (rank 0 of 1):
+Prints ONE compact JSON line last on stdout (rank 0 of 1; the full record of every leg goes to
+the --detail-out file, progress to stderr):
   value = seconds per step (lower is better), with inputs resident in HBM;
   roofline = the product A = P W~ (8 N^3 flops per launch) against the FP64 MFMA peak, its
   average launch time taken from HIP events recorded on the library's stream during the timed
@@ -53,6 +54,9 @@ def measured_traffic(N):
         return MEASURED_TRAFFIC["bytes"]
     return None
 
+
+# slices of the split-precision ensemble leg (the lower product takes one fewer)
+ENS_SPLIT_SLICES = 4
 
 PAPER_S_PER_STEP_N4096 = 0.55  # Sec. 3.4: ~2500 CPU cores, ScaLAPACK, N = 4096, 3 iterations
 
@@ -128,6 +132,7 @@ def cpu_baseline(N, om_seed, law, h, mean_evals, lmax=32):
         "cores": blas_threads(),
         "cpu_model": cpu_model(),
         "kind": "oracle",
+        "sample_short": f"1 oracle step, N={N}, {K} evaluations, scaled to {mean_evals:.2f}",
         "sample": (f"1 oracle IsoMP step at N={N} with K={K} evaluations ({dt:.2f} s), scaled by "
                    f"{mean_evals:.3f}/{K} to the GPU run's mean evaluations per step; input "
                    f"assembled by the oracle from the same seeded coefficients truncated to "
@@ -614,6 +619,93 @@ def phases_of(prof):
     return {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
 
 
+def _sig(x, digits=4):
+    """x rounded to `digits` significant digits (None and non-floats pass through)."""
+    if isinstance(x, float) and x == x and x not in (float("inf"), float("-inf")) and x != 0.0:
+        return float(f"{x:.{digits - 1}e}")
+    return x
+
+
+def _pick(rec, *keys):
+    for k in keys:
+        if rec is None:
+            return None
+        rec = rec.get(k) if isinstance(rec, dict) else None
+    return rec
+
+
+def compact_record(out, detail_path=None):
+    """The one JSON line bench.py prints last: the headline, the roofline and the CPU baseline
+    of the full record, and one or two figures from each leg (the whole record goes to the
+    detail file).  Stays well under 2 KB."""
+    def leg_split(rec):
+        best = _pick(rec, "split_precision", "best_at_stated_accuracy")
+        if not best:
+            return None
+        return {"slices": best["slices"], "s_per_step": _sig(best["s_per_step"]),
+                "speedup_vs_fp64": _sig(best["speedup_vs_fp64"], 3),
+                "rel_vs_fp64_run": _sig(best["rel_frobenius_vs_fp64_run"], 2)}
+
+    def leg_alt(rec):
+        if not rec:
+            return None
+        return {"s_per_step": _sig(rec["s_per_step"]), "speedup_vs_fp64": _sig(rec["speedup_vs_fp64"], 3),
+                "rel_vs_fp64_run": _sig(rec["rel_frobenius_vs_fp64_run"], 2)}
+
+    iters = out["iters_per_step"]
+    ph = out["phases"]
+    roof = dict(out["roofline"])
+    roof.pop("context_library_zgemm", None)
+    roof = {k: _sig(v) for k, v in roof.items()}
+    wn = out["fp64_start_from_Wn"]
+    rec = {k: out[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                               "steps_per_s", "higher_is_better", "scaling", "vs_baseline", "dtype",
+                               "data")}
+    for k in ("ms_per_step", "steps_per_s", "vs_baseline"):
+        rec[k] = _sig(rec[k])
+    cfg = out["config"]
+    rec["config"] = {"workload": cfg["workload"].split(":")[0], "N": cfg["N"], "h": cfg["h"],
+                     "tol": cfg["tol"], "law": cfg["law"], "seed": cfg["seed"],
+                     "start": "polynomial", "update": "W_n + h C"}
+    rec["iters_per_step"] = iters
+    rec["evals_per_step"] = _sig(sum(iters) / len(iters))
+    rec["eval_ms"] = {k: _sig(v["avg_ms"]) for k, v in ph.items()}
+    rec["fp64_start_from_Wn"] = {"s_per_step": _sig(wn["s_per_step"]),
+                                 "evals_per_step": _sig(sum(wn["iters_per_step"]) / len(wn["iters_per_step"])),
+                                 "vs_paper_0.55s": _sig(wn["s_per_step"] / PAPER_S_PER_STEP_N4096)}
+    rec["roofline"] = roof
+    lib = out["roofline"].get("context_library_zgemm")
+    if lib:
+        rec["vendor_zgemm_ms"] = _sig(lib["ms"])
+    rec["solve_hbm_GBps"] = _sig(out["solve_hbm"]["achieved_GBps"])
+    rec["split"] = leg_split(out)
+    rec["crt"] = leg_alt(out.get("crt_precision"))
+    rec["mixed"] = leg_alt(out.get("mixed_precision"))
+    n2 = out.get("n2048")
+    if n2:
+        rec["n2048"] = {"fp64_s_per_step": _sig(n2["fp64_s_per_step"]), "split": leg_split(n2),
+                        "crt_s_per_step": _sig(_pick(n2, "crt_precision", "s_per_step"))}
+    ens = out.get("ensemble")
+    if ens:
+        rec["ensemble64_steps_per_s"] = {
+            "fp64": _sig(ens["fp64"]["aggregate_steps_per_s"]),
+            "split": _sig(ens["split"]["aggregate_steps_per_s"]),
+            "split_slices": ens.get("split_slices"),
+            "split_rel_vs_fp64": _sig(ens["split"].get("max_member_rel_frobenius_vs_fp64_ensemble"), 2)}
+    n512 = out.get("n512")
+    if n512:
+        rec["n512_s_per_step"] = _sig(n512["single_context_s_per_step"])
+    cb = out.get("cpu_baseline")
+    if cb:
+        rec["cpu_baseline"] = {"value": _sig(cb["value"]), "unit": cb["unit"], "cores": cb["cores"],
+                               "kind": cb["kind"], "sample": cb["sample_short"],
+                               "cpu_model": cb.get("cpu_model")}
+    else:
+        rec["cpu_baseline"] = None
+    rec["detail"] = detail_path
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +729,9 @@ def main():
                     help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives the full record of every leg ('' : none); the last "
+                         "stdout line is a compact summary of it")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, run 3 plain device-to-device copies of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -683,7 +778,9 @@ def main():
     if args.ensemble_steps > 0:
         rec64, ref = ensemble_leg(args.ensemble_steps, PREC_FP64, with_cpu=not args.no_cpu_baseline)
         ens = {"fp64": rec64,
-               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=4, ref=ref)[0]}
+               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=ENS_SPLIT_SLICES,
+                                     ref=ref)[0],
+               "split_slices": ENS_SPLIT_SLICES}
         del ref
         ens["split_speedup_vs_fp64"] = (ens["split"]["aggregate_steps_per_s"] /
                                         ens["fp64"]["aggregate_steps_per_s"])
@@ -782,7 +879,15 @@ def main():
         log(f"cpu baseline: oracle step at N={N}, {mean_evals:.3f} evaluations per step ...")
         out["cpu_baseline"] = cpu_baseline(N, m["seed"], m["law"], m["h"], mean_evals)
         log(f"cpu baseline {out['cpu_baseline']['value']:.2f} s/step")
-    print(json.dumps(out), flush=True)
+    detail = args.detail_out or None
+    if detail:
+        d = os.path.dirname(detail)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(detail, "w") as f:
+            json.dump(out, f, indent=1)
+        log(f"full record written to {detail}")
+    print(json.dumps(compact_record(out, detail)), flush=True)
 
 
 if __name__ == "__main__":
