@@ -253,6 +253,25 @@ ze_status ze_energy_spectrum(ze_ctx* ctx, const void* omega, void* E);
 ze_status ze_zgemm(ze_ctx* ctx, const void* A, const void* B, void* C, int prec);
 
 /*
+ * ze_zgemm_noalloc -- C = A B in FP64 (the ze_zgemm product with ZE_PREC_FP64) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It takes no context and calls no hipMalloc, hipFree or allocating
+ * library routine; the split-K partial sums of the product live in a fixed 32 MiB device array
+ * of the library, one per GPU, held until the process ends (the split adapts to that size, so
+ * every N in range fits; results equal ze_zgemm's up to the rounding of a different K split).
+ *   N        1 <= N <= 16384; larger or smaller N is refused with ZE_EINVAL (ze_last_error
+ *            names the limit).
+ *   A, B, C  device, N x N complex128, row-major; C must not alias A or B.  Caller-owned.
+ *   stream   HIP stream of the current device (NULL: the null stream); a stream of another
+ *            device is refused with ZE_EINVAL.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or host threads) race and must be ordered by the caller.  The first call on a device
+ * looks the array's address up on that device (it synchronises nothing).
+ * Errors: ZE_EINVAL, ZE_EHIP.  Asynchronous on `stream`.
+ */
+ze_status ze_zgemm_noalloc(int N, const void* A, const void* B, void* C, void* stream);
+
+/*
  * ze_set_split_slices -- number s of slices per operand of the ZE_PREC_SPLIT products (balanced
  * digits: a 7-bit top slice, then 8-bit ones); the products then cost s (s + 1) / 2 INT8
  * products each.  Allowed: 2 <= s <= s_max(N) with

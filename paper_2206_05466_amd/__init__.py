@@ -6,8 +6,8 @@ The computation lives in ``libzeuler.so`` (HIP, gfx950; C ABI in ``include/zeule
 
 from .zeuler import (
     LIB_PATH, PREC_CRT, PREC_FP64, PREC_MIXED, PREC_SPLIT, SIGNATURES, Ensemble, StepInfo, Zeuler, ZeulerError,
-    load_library,
+    load_library, zgemm_noalloc,
 )
 
 __all__ = ["LIB_PATH", "PREC_CRT", "PREC_FP64", "PREC_MIXED", "PREC_SPLIT", "SIGNATURES", "Ensemble", "StepInfo", "Zeuler",
-           "ZeulerError", "load_library"]
+           "ZeulerError", "load_library", "zgemm_noalloc"]

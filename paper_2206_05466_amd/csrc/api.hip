@@ -292,6 +292,32 @@ ze_status ze_zgemm(ze_ctx* c, const void* A, const void* B, void* C, int prec) {
     return ZE_OK;
 }
 
+ze_status ze_zgemm_noalloc(int N, const void* A, const void* B, void* C, void* stream) {
+    if (N < 1 || N > kMaxN) {
+        g_last_error = "ze_zgemm_noalloc: N = " + std::to_string(N) + " outside 1.." +
+                       std::to_string(kMaxN);
+        return ZE_EINVAL;
+    }
+    if (!A || !B || !C || C == A || C == B) {
+        g_last_error = "ze_zgemm_noalloc: null or aliased matrix pointer";
+        return ZE_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0, sdev = 0;
+    ZE_HIP(hipGetDevice(&dev));
+    if (s) {
+        ZE_HIP(hipStreamGetDevice(s, &sdev));
+        if (sdev != dev) {
+            g_last_error = "ze_zgemm_noalloc: the stream belongs to device " + std::to_string(sdev) +
+                           ", the current device is " + std::to_string(dev);
+            return ZE_EINVAL;
+        }
+    }
+    ZE_HIP(launch_zgemm_f64_noalloc(N, static_cast<const double2*>(A), static_cast<const double2*>(B),
+                                    static_cast<double2*>(C), s));
+    return ZE_OK;
+}
+
 namespace {
 
 enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };

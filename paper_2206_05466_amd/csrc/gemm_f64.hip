@@ -17,6 +17,7 @@
 // MFMA operand layout (16x16x4, f64): lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator register r of lane l holds D[l/16 + 4*r][l%16].
 
+#include <mutex>
 #include <vector>
 
 #include "tile_f64.h"
@@ -72,12 +73,14 @@ struct Split {
     int full, tail, S;
 };
 
-Split make_split(int ntiles, int nk, int cap) {
+// `pmax`: the most split blocks whose partial sums the partial buffer holds.
+Split make_split(int ntiles, int nk, int cap, int pmax) {
     const int rounds = ntiles / cap, rem = ntiles % cap;
     if (rem == 0) return {ntiles, 0, 1};
     int S = cap / rem;
     const int smax = nk / 8 > 1 ? nk / 8 : 1;  // at least 8 stages (64 complex k) per range
     if (S > smax) S = smax;
+    if (S > pmax / rem) S = pmax / rem;
     if (S <= 1) return {ntiles, 0, 1};
     return {rounds * cap, rem, S};
 }
@@ -240,26 +243,87 @@ hipError_t ze_gemm_capacity(int* cap_full, int* cap_low) {
     return hipSuccess;
 }
 
-hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* Cm,
-                            hipStream_t s) {
-    const int N = c->N;
+namespace {
+
+// The full product with `cap` concurrent blocks and a partial buffer `part` of `pmax` split
+// blocks' partial sums.
+hipError_t launch_full(int N, int cap, double* part, int pmax, const double2* A, const double2* B,
+                       double2* Cm, hipStream_t s) {
     const int tiles_n = (N + FullCfg::BNC - 1) / FullCfg::BNC;
     const int tiles = tiles_n * ((N + FullCfg::BM - 1) / FullCfg::BM);
-    const Split sp = make_split(tiles, (N + kBK - 1) / kBK, c->cap_full);
+    const Split sp = make_split(tiles, (N + kBK - 1) / kBK, cap, pmax);
     hipLaunchKernelGGL(zgemm_f64_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A, B,
-                       Cm, N, tiles_n, sp.full, sp.S, c->gemm_part);
+                       Cm, N, tiles_n, sp.full, sp.S, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
     hipLaunchKernelGGL(zgemm_f64_fixup, dim3(sp.tail, FullCfg::MT * FullCfg::NT), dim3(kThreads), 0, s,
-                       Cm, N, tiles_n, sp.full, sp.S, c->gemm_part);
+                       Cm, N, tiles_n, sp.full, sp.S, part);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* Cm,
+                            hipStream_t s) {
+    // the context's buffer holds cap_full blocks' partial sums (ze_gemm_part_bytes)
+    return launch_full(c->N, c->cap_full, c->gemm_part, c->cap_full, A, B, Cm, s);
+}
+
+// ---------------------------------------------------------------- allocation-free product
+// ze_zgemm_noalloc keeps the split-K partial sums of the full product in this fixed device
+// array instead of a context's buffer: each GPU holds its own copy until the process ends.
+// In host code `scratch` is a host-side stand-in, not a device address; its address on a
+// device is looked up once per device (hipGetSymbolAddress, with that device current) and
+// only that address reaches a kernel.  Every call on one GPU shares the array: calls that
+// overlap on one GPU race.  Nothing in it has to start at zero (each partial slot is written
+// by its block before the fix-up reads it).
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+
+struct NoAllocDevice {
+    double* ptr = nullptr;  // device address of `scratch` on this device
+    int cap_full = 0;       // concurrent blocks of the full product
+};
+
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+constexpr int kPartialDoubles = FullCfg::MT * FullCfg::NT * 4 * kThreads;  // one split block
+
+}  // namespace
+
+hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, double2* Cm,
+                                    hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    NoAllocDevice d;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc[dev].ptr) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            int cap_low = 0;
+            e = ze_gemm_capacity(&g_noalloc[dev].cap_full, &cap_low);
+            if (e != hipSuccess) return e;
+            g_noalloc[dev].ptr = static_cast<double*>(ptr);
+        }
+        d = g_noalloc[dev];
+    }
+    const int pmax = (int)(kNoAllocScratchBytes / sizeof(double) / kPartialDoubles);
+    return launch_full(N, d.cap_full, d.ptr, pmax, A, B, Cm, s);
 }
 
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
                               hipStream_t s) {
     const int N = c->N;
     const int T = (N + kTile - 1) / kTile;
-    const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low);
+    const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low, c->cap_low);
     hipLaunchKernelGGL(zgemm_lower_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A,
                        P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
     hipError_t e = hipGetLastError();

@@ -158,6 +158,12 @@ void ze_lower_tile_order(int N, std::vector<int>& order);
 hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                             hipStream_t s);
 
+// The same product with its split-K partial sums in the library's fixed device array (no
+// allocation; ze_zgemm_noalloc): N x N, on the current device, asynchronous on `s`.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, double2* C,
+                                    hipStream_t s);
+
 // Lower-triangle Q = A P (64 x 64 complex tiles meeting the lower triangle) into Q.
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
                               hipStream_t s);

@@ -37,6 +37,7 @@ SIGNATURES = {
     "ze_basis_extract": (_c_int, [_vp, _vp, _vp]),
     "ze_energy_spectrum": (_c_int, [_vp, _vp, _vp]),
     "ze_zgemm": (_c_int, [_vp, _vp, _vp, _vp, _c_int]),
+    "ze_zgemm_noalloc": (_c_int, [_c_int, _vp, _vp, _vp, _vp]),
     "ze_set_split_slices": (_c_int, [_vp, _c_int]),
     "ze_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_set_split_slices_lower": (_c_int, [_vp, _c_int]),
@@ -90,6 +91,25 @@ class ZeulerError(RuntimeError):
 def _check(status: int, where: str, detail: bool = False):
     if status != ZE_OK:
         raise ZeulerError(status, where, detail)
+
+
+def zgemm_noalloc(A, B, out, stream=None):
+    """C = A B (FP64) through ze_zgemm_noalloc: no context, no device allocation in the
+    library.  A, B, out: contiguous N x N complex128 tensors on the current device; `out` is
+    caller-allocated (this function allocates nothing either)."""
+    import torch
+
+    lib = load_library()
+    N = A.shape[0] if A.dim() == 2 else -1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    for name, X in (("A", A), ("B", B), ("out", out)):
+        if (not isinstance(X, torch.Tensor) or X.dtype != torch.complex128 or X.device != dev
+                or tuple(X.shape) != (N, N) or not X.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {N}x{N} complex128 tensor on {dev}")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib.ze_zgemm_noalloc(N, _vp(A.data_ptr()), _vp(B.data_ptr()), _vp(out.data_ptr()),
+                                _vp(st.cuda_stream)), "ze_zgemm_noalloc", detail=True)
+    return out
 
 
 @dataclass

@@ -54,6 +54,17 @@ def test_strerror_and_invalid_create_without_gpu():
     assert lib.ze_isomp_step(None, None, 0.1, 1e-12, 5, 0, None, None) == zeuler.ZE_EINVAL
 
 
+def test_noalloc_product_refuses_sizes_without_gpu():
+    """ze_zgemm_noalloc checks N (1..16384) and its pointers before any HIP call."""
+    lib = pkg.load_library()
+    p = ctypes.c_void_p(4096)
+    for N in (0, -1, 16385):
+        assert lib.ze_zgemm_noalloc(N, p, ctypes.c_void_p(8192), ctypes.c_void_p(12288), None) == zeuler.ZE_EINVAL
+        assert b"outside 1..16384" in lib.ze_last_error()
+    assert lib.ze_zgemm_noalloc(64, p, ctypes.c_void_p(8192), p, None) == zeuler.ZE_EINVAL
+    assert lib.ze_zgemm_noalloc(64, None, p, ctypes.c_void_p(8192), None) == zeuler.ZE_EINVAL
+
+
 def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(zeuler, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(zeuler, "_lib", None)
