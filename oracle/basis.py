@@ -52,25 +52,46 @@ def eigvecs(N: int, m: int, count: int | None = None):
     return w, V * sgn
 
 
-def assemble(N: int, omega: np.ndarray, lmax: int | None = None) -> np.ndarray:
+def _diagonal(args):
+    """Entries of diagonal m of W: the lower one (i+m, i) and, for m > 0, the upper (i, i+m)."""
+    N, m, top, om_pos, om_neg = args
+    _, V = eigvecs(N, m, top - m + 1)
+    low = 1j * (V @ om_pos)
+    up = 1j * (-1) ** m * (V @ om_neg) if m > 0 else None
+    return low, up
+
+
+def assemble(N: int, omega: np.ndarray, lmax: int | None = None, workers: int = 1) -> np.ndarray:
     """W = sum_{l,m} i omega_lm T_lm (eq. (W0)) from flat coefficients omega[l*l+l+m].
 
     With ``lmax`` the coefficients of degree l > lmax must be zero, and only the basis
     elements up to degree lmax are computed (the large-scale initial conditions).
+    ``workers`` > 1 forms the diagonals in that many processes (each diagonal is independent
+    of the others; the result is the same bit for bit).
     """
     omega = np.asarray(omega, dtype=np.complex128)
     W = np.zeros((N, N), dtype=np.complex128)
     top = N - 1 if lmax is None else min(int(lmax), N - 1)
     if np.any(omega[(top + 1) ** 2:] != 0):
         raise ValueError("coefficients beyond lmax must be zero")
-    for m in range(top + 1):
-        _, V = eigvecs(N, m, top - m + 1)
-        n = N - m
-        i = np.arange(n)
-        l = np.arange(m, top + 1)
-        W[i + m, i] = 1j * (V @ omega[l * l + l + m])
+
+    def jobs():
+        for m in range(top + 1):
+            l = np.arange(m, top + 1)
+            yield N, m, top, omega[l * l + l + m], omega[l * l + l - m]
+
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            diags = list(ex.map(_diagonal, jobs(), chunksize=4))
+    else:
+        diags = map(_diagonal, jobs())
+    for m, (low, up) in enumerate(diags):
+        i = np.arange(N - m)
+        W[i + m, i] = low
         if m > 0:
-            W[i, i + m] = 1j * (-1) ** m * (V @ omega[l * l + l - m])
+            W[i, i + m] = up
     return W
 
 

@@ -165,11 +165,13 @@ def isomp_composed_run(W0: np.ndarray, h: float, nsteps: int, order: int, tol: f
 
 
 def isomp_run(W0: np.ndarray, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
-              extrapolate: bool = False, degree: int = 1, update: str = "second_line"):
+              extrapolate: bool = False, degree: int = 1, update: str = "second_line",
+              on_step=None):
     """nsteps IsoMP steps from W0.  Returns (W, [iterations], [residuals]).
 
     ``extrapolate``: starting iterates from the previous midpoints of this run (see the
-    module notes); ``degree`` (1..3): the highest polynomial degree of that extrapolation."""
+    module notes); ``degree`` (1..3): the highest polynomial degree of that extrapolation.
+    ``on_step(n, W)`` is called after step n (1-based) with the current state."""
     if degree not in (1, 2, 3):
         raise ValueError("degree must be 1, 2 or 3")
     W = np.asarray(W0, dtype=np.complex128).copy()
@@ -187,4 +189,6 @@ def isomp_run(W0: np.ndarray, h: float, nsteps: int, tol: float = 1e-12, maxit: 
         mids = (mids + [mid])[-(degree + 1):]
         iters.append(k)
         res.append(r)
+        if on_step is not None:
+            on_step(len(iters), W)
     return W, iters, res
