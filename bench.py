@@ -55,8 +55,6 @@ def measured_traffic(N):
     return None
 
 
-# slices of the split-precision ensemble leg (the lower product takes one fewer)
-ENS_SPLIT_SLICES = 4
 
 PAPER_S_PER_STEP_N4096 = 0.55  # Sec. 3.4: ~2500 CPU cores, ScaLAPACK, N = 4096, 3 iterations
 
@@ -140,7 +138,13 @@ def cpu_baseline(N, om_seed, law, h, mean_evals, lmax=32):
     }
 
 
-def ensemble_leg(nsteps, prec, slices=4, ref=None, with_cpu=False):
+def _ens_split_slices():
+    from workloads import WORKLOADS
+
+    return WORKLOADS["ensemble64"]["split_slices"]
+
+
+def ensemble_leg(nsteps, prec, ref=None, with_cpu=False):
     """64 independent simulations, N uniform over {128, 256, 384, 512}: one graph launch per step.
     Returns the record and the final states; with `ref` (the FP64 leg's final states, same
     initial states and step count) the record carries the largest relative Frobenius distance
@@ -152,10 +156,11 @@ def ensemble_leg(nsteps, prec, slices=4, ref=None, with_cpu=False):
 
     cfg = WORKLOADS["ensemble64"]
     sizes = ensemble_sizes(cfg["nsim"], cfg["size_seed"], cfg["sizes"])
-    # evaluation cap of the captured step: 5, one above the most any step of this workload
-    # needs (4, the first, from W_n, whose residual then just meets tol); start_step_* report
-    # that step
-    h, K, tol = cfg["h"], 5, 1e-12
+    # evaluation cap of the captured step: one above the most any step of this workload needs
+    # (4, the first, from W_n, whose residual then just meets tol); start_step_* report that
+    # step.  Split precision: the slices the parity tests check at this run's length (the
+    # lower product takes one fewer)
+    h, K, tol, slices = cfg["h"], cfg["K"], cfg["tol"], cfg["split_slices"]
     split = prec == PREC_SPLIT
     ctxs = {n: Zeuler(n) for n in sorted(set(sizes))}
     Ws = [ctxs[n].basis_assemble(omega_coeffs(n, cfg["seed0"] + j, cfg["law"])) for j, n in enumerate(sizes)]
@@ -778,9 +783,8 @@ def main():
     if args.ensemble_steps > 0:
         rec64, ref = ensemble_leg(args.ensemble_steps, PREC_FP64, with_cpu=not args.no_cpu_baseline)
         ens = {"fp64": rec64,
-               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, slices=ENS_SPLIT_SLICES,
-                                     ref=ref)[0],
-               "split_slices": ENS_SPLIT_SLICES}
+               "split": ensemble_leg(args.ensemble_steps, PREC_SPLIT, ref=ref)[0],
+               "split_slices": _ens_split_slices()}
         del ref
         ens["split_speedup_vs_fp64"] = (ens["split"]["aggregate_steps_per_s"] /
                                         ens["fp64"]["aggregate_steps_per_s"])
