@@ -109,45 +109,69 @@ __global__ __launch_bounds__(kThreads) void crt_cols_kernel(const double2* __res
     crt_cols_tile(B, N, blockIdx.x, blockIdx.y, b, ldk, eb, slices, tile);
 }
 
+// Residues c_k of the real and imaginary parts of one output value from its P1, P2, P3
+// (bytes sh .. sh + 7 of the loaded words, each in [0, p_k)).
+__device__ __forceinline__ void crt_parts_to_residues(unsigned p1, unsigned p2, unsigned p3, int sh,
+                                                      int p, int& re, int& im) {
+    const int a = (int)((p1 >> sh) & 0xffu), b = (int)((p2 >> sh) & 0xffu);
+    const int c = (int)((p3 >> sh) & 0xffu);
+    re = a - b;
+    re = re < 0 ? re + p : re;
+    im = c - a - b;
+    im = im < 0 ? im + p : im;
+    im = im < 0 ? im + p : im;
+}
+
 // C[e] from the residue products, three N x N byte slabs per modulus k (P1 = ar br,
-// P2 = ai bi, P3 = (ar + ai)(br + bi), each reduced modulo p_k), in S parts along K whose
-// residues add modulo p_k: Re = P1 - P2 and Im = P3 - P1 - P2 modulo p_k through the CRT, then
-// scaled by 2^(ea_r + eb_c - 2b).
+// P2 = ai bi, P3 = (ar + ai)(br + bi), each reduced modulo p_k): Re = P1 - P2 and
+// Im = P3 - P1 - P2 modulo p_k through the CRT, then scaled by 2^(ea_r + eb_c - 2b).  Four
+// consecutive outputs 4v .. 4v + 3 per thread (one 32-bit load of each slab) when N^2 is a
+// multiple of 4 (so every slab starts 4-byte aligned); otherwise one output per thread.
 __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const unsigned char* __restrict__ G8,
-                                                               int S,
                                                                const int* __restrict__ ea,
                                                                const int* __restrict__ eb,
                                                                double2* __restrict__ Cm, int N,
                                                                int b) {
-    const size_t n2 = (size_t)N * N, part = (size_t)3 * kCrtMods * n2;
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
-         e += (size_t)gridDim.x * kThreads) {
-        int gr[kCrtMods], gi[kCrtMods];
+    const size_t n2 = (size_t)N * N;
+    const size_t n4 = n2 % 4 == 0 ? n2 / 4 : 0;
+    const unsigned* G32 = reinterpret_cast<const unsigned*>(G8);
+    for (size_t v = (size_t)blockIdx.x * kThreads + threadIdx.x; v < n4;
+         v += (size_t)gridDim.x * kThreads) {
+        CrtAcc ar[4], ai[4];
 #pragma unroll
         for (int k = 0; k < kCrtMods; ++k) {
-            const int p = kCrtP[k];
-            const size_t o = (size_t)(3 * k) * n2 + e;
-            int p1 = 0, p2 = 0, p3 = 0;
-            for (int q = 0; q < S; ++q) {
-                p1 += G8[q * part + o];
-                p2 += G8[q * part + o + n2];
-                p3 += G8[q * part + o + 2 * n2];
+            const size_t o = (size_t)(3 * k) * n4 + v;
+            const unsigned p1 = G32[o], p2 = G32[o + n4], p3 = G32[o + 2 * n4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int re, im;
+                crt_parts_to_residues(p1, p2, p3, 8 * j, kCrtP[k], re, im);
+                ar[j].add(k, re);
+                ai[j].add(k, im);
             }
-            p1 %= p;
-            p2 %= p;
-            p3 %= p;
-            int re = p1 - p2;
-            re = re < 0 ? re + p : re;
-            int im = p3 - p1 - p2;
-            im = im < 0 ? im + p : im;
-            im = im < 0 ? im + p : im;
-            gr[k] = re;
-            gi[k] = im;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t e = 4 * v + j;
+            const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
+            const int sh = ea[r] + eb[c] - 2 * b;
+            Cm[e] = make_double2(ldexp(ar[j].value(), sh), ldexp(ai[j].value(), sh));
+        }
+    }
+    for (size_t e = 4 * n4 + (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
+         e += (size_t)gridDim.x * kThreads) {
+        CrtAcc ar, ai;
+#pragma unroll
+        for (int k = 0; k < kCrtMods; ++k) {
+            const size_t o = (size_t)(3 * k) * n2 + e;
+            int re, im;
+            crt_parts_to_residues(G8[o], G8[o + n2], G8[o + 2 * n2], 0, kCrtP[k], re, im);
+            ar.add(k, re);
+            ai.add(k, im);
         }
         const int r = (int)(e / N), c = (int)(e - (size_t)r * N);
         const int sh = ea[r] + eb[c] - 2 * b;
-        Cm[e] = make_double2(ldexp(crt_reconstruct<true>(gr), sh),
-                             ldexp(crt_reconstruct<true>(gi), sh));
+        Cm[e] = make_double2(ldexp(ar.value(), sh), ldexp(ai.value(), sh));
     }
 }
 
@@ -223,16 +247,20 @@ __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, i
 // The modular form's residue products on 256 x 256 tiles (zgemm_i8_tile_large) over the N x N
 // output: block b takes part b % S of the K stages of tile b / S and writes its byte residues
 // to part region b % S of G8 (regions of 3 kCrtMods N^2 bytes).
+// Block b: slab group g = b / ntiles (slabs [g s / G, (g + 1) s / G), whole moduli when G
+// divides the modulus count) of tile b % ntiles, over all of K.  Within a group, consecutive
+// blocks run on consecutive XCDs; with whole rounds of 8 the XCD-aware tile order keeps the
+// tiles an XCD holds at once on shared panels.
 __global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb,
-    unsigned char* __restrict__ G8, int N, int s, int ldk, int tiles_n, int ntiles, int S) {
+    unsigned char* __restrict__ G8, int N, int s, int ldk, int tiles_n, int ntiles, int G) {
     __shared__ I8LSmem sm;
-    const int b = blockIdx.x, tile = b / S, part = b % S, nk = ldk / kI8BK;
+    const int b = blockIdx.x, g = b / ntiles, tile = b % ntiles;
     int ti, tj;
-    i8_tile_of(0, tile, tiles_n, ntiles, S == 1, b, ti, tj);
+    i8_tile_of(0, tile, tiles_n, ntiles, ntiles % 8 == 0, tile, ti, tj);
     if (tj >= tiles_n) return;
-    zgemm_i8_tile_large(ti, tj, sa, sb, G8 + (size_t)part * s * N * (size_t)N, N, s, ldk, sm,
-                        (int)((long long)part * nk / S), (int)((long long)(part + 1) * nk / S));
+    const int j0 = g * s / G, j1 = (g + 1) * s / G;
+    zgemm_i8_tile_large(ti, tj, sa, sb, G8, N, j0, j1 - j0, ldk, sm, 0, ldk / kI8BK);
 }
 
 __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __restrict__ G,
@@ -354,27 +382,27 @@ int ze_crt_bits(int N) {
     return b < 55 ? b : 55;
 }
 
-size_t ze_crt_slab_ints(int N) { return (size_t)3 * kCrtMods * N * (size_t)N; }
+// int32 words holding the 3 kCrtMods byte slabs (N x N bytes each) of the residue products.
+size_t ze_crt_slab_ints(int N) { return ((size_t)3 * kCrtMods * N * (size_t)N + 3) / 4; }
 
 int ze_crt_ldk(int N) { return ((N + kI8BK - 1) / kI8BK) * kI8BK; }
 
 // Tiles of the modular product (256 x 256 over the N x N output).  When they fill at least
-// one round of the block slots each tile is one block; else each is split along K into
-// S <= 4 parts (at least 4 stages each) to fill the slots, as many byte regions as the int32
-// slab allocation holds.
-void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* S) {
+// one round of the block slots each tile is one block over all slabs; else the 3 kCrtMods
+// slabs are split into G groups (G the largest divisor of 3 kCrtMods with ntiles G <= the
+// slots), each block one tile and one group, so every block still runs the whole K of its
+// slabs and flushes once per slab.
+void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* G) {
     const int t = (N + kI8LM - 1) / kI8LM;
     *tn = t;
     *ntiles = t * t;
-    *S = 1;
-    const int nk = ze_crt_ldk(N) / kI8BK;
+    *G = 1;
     const int cap = cap_blocks > 0 ? cap_blocks : *ntiles;
-    if (*ntiles < cap) {
-        int sp = cap / *ntiles;
-        if (sp > nk / 4) sp = nk / 4;
-        if (sp > 4) sp = 4;
-        if (sp > 1) *S = sp;
-    }
+    for (int g = 3 * kCrtMods; g > 1; --g)
+        if ((3 * kCrtMods) % g == 0 && (long long)*ntiles * g <= cap) {
+            *G = g;
+            break;
+        }
 }
 
 hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
@@ -398,16 +426,17 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
                        c->crt_b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int ntiles, tn, S;
-    ze_crt_plan(N, c->cap_i8l, &ntiles, &tn, &S);
+    int ntiles, tn, G;
+    ze_crt_plan(N, c->cap_i8l, &ntiles, &tn, &G);
     unsigned char* G8 = reinterpret_cast<unsigned char*>(c->crt_g);
-    hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(ntiles * S), dim3(kI8LThreads), 0, st,
-                       c->crt_a, c->crt_b, G8, N, 3 * kCrtMods, ldk, tn, ntiles, S);
+    hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(ntiles * G), dim3(kI8LThreads), 0, st,
+                       c->crt_a, c->crt_b, G8, N, 3 * kCrtMods, ldk, tn, ntiles, G);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t n2 = (size_t)N * N;
-    const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
-    hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, G8, S, c->split_ea,
+    const size_t n2 = (size_t)N * N, per = n2 % 4 == 0 ? n2 / 4 : n2;  // outputs / thread: 4 or 1
+    const size_t want = (per + kThreads - 1) / kThreads;  // one pass: no loop-carried addresses
+    const unsigned grid = (unsigned)(want < 1 ? 1 : want);
+    hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, G8, c->split_ea,
                        c->split_eb, C, N, b);
     return hipGetLastError();
 }

@@ -223,7 +223,7 @@ hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out
 int ze_crt_bits(int N);
 size_t ze_crt_slab_ints(int N);
 int ze_crt_ldk(int N);
-void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* S);
+void ze_crt_plan(int N, int cap_blocks, int* ntiles, int* tn, int* G);
 hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B, double2* C,
                             hipStream_t s);
 ze_status ze_ensure_crt(ze_ctx* c);

@@ -148,9 +148,6 @@ constexpr int kCrtP[kCrtMods] = {256, 255, 253, 251, 247, 241, 239, 233,
                                  229, 227, 223, 211, 199, 197, 193, 191};
 
 
-// Balanced residue of the integer X (|X| < 2^63) modulo p_k, in [-(p_k)/2, (p_k - 1)/2]:
-// |X| mod p from a 64-bit reciprocal (q = the high half of |X| floor(2^64 / p), at most one
-// below the true quotient), then the sign.
 // p_k for a wave-uniform runtime k.
 __device__ __forceinline__ int crt_modulus(int k) {
     int p = kCrtP[0];
@@ -159,38 +156,49 @@ __device__ __forceinline__ int crt_modulus(int k) {
     return p;
 }
 
+// Balanced residue, in [-(p_K)/2, (p_K - 1)/2], of an integer X held exactly in a double
+// (|X| < 2^62), given as X = hi 2^28 + lo with hi = floor(X 2^-28) and 0 <= lo < 2^28 (both
+// exact).  All in FP64 on integers: d = hi (2^28 mod p) + lo (|d| < 2^42, exact), the quotient
+// estimate floor(d / p) is off by at most one (d / p < 2^42, relative error ~2^-52), so
+// t = d - q p (exact) needs one correction into [0, p).
 template <int K>
-__device__ __forceinline__ int crt_residue(long long X) {
+__device__ __forceinline__ int crt_residue(double hi, double lo) {
     constexpr int p = kCrtP[K];
-    constexpr unsigned long long magic = ~0ull / (unsigned long long)p;
-    const unsigned long long a = X < 0 ? (unsigned long long)(-X) : (unsigned long long)X;
-    const unsigned long long q = (unsigned long long)(((unsigned __int128)a * magic) >> 64);
-    unsigned long long r = a - q * (unsigned long long)p;
-    r = r >= (unsigned long long)p ? r - p : r;
-    int t = (int)r;
-    if (X < 0 && t != 0) t = p - t;
-    return t > (p - 1) / 2 ? t - p : t;
+    constexpr double r28 = (double)((1LL << 28) % p);
+    const double d = fma(hi, r28, lo);
+    const double q = floor(d * (1.0 / (double)p));
+    double t = fma(-q, (double)p, d);
+    t = t < 0.0 ? t + (double)p : (t >= (double)p ? t - (double)p : t);
+    const int ti = (int)t;
+    return ti > (p - 1) / 2 ? ti - p : ti;
 }
 
 template <int K>
 struct CrtResidues {
-    // d[k] = balanced residue of X modulo p_k for k < K
-    __device__ __forceinline__ static void run(long long X, int (&d)[kCrtMods]) {
-        CrtResidues<K - 1>::run(X, d);
-        d[K - 1] = crt_residue<K - 1>(X);
+    // d[k] = balanced residue of X = hi 2^28 + lo modulo p_k for k < K
+    __device__ __forceinline__ static void run(double hi, double lo, int (&d)[kCrtMods]) {
+        CrtResidues<K - 1>::run(hi, lo, d);
+        d[K - 1] = crt_residue<K - 1>(hi, lo);
     }
 };
 template <>
 struct CrtResidues<0> {
-    __device__ __forceinline__ static void run(long long, int (&)[kCrtMods]) {}
+    __device__ __forceinline__ static void run(double, double, int (&)[kCrtMods]) {}
 };
 
-// Residues of x scaled by 2^(b - e) and rounded to the nearest integer.
-__device__ __forceinline__ void crt_digits(double x, int e, int b, int (&d)[kCrtMods]) {
-    CrtResidues<kCrtMods>::run(llrint(ldexp(x, b - e)), d);
+// Residues of the integer X (exactly representable as a double, |X| < 2^62).
+__device__ __forceinline__ void crt_residues_of(double X, int (&d)[kCrtMods]) {
+    const double hi = floor(X * 0x1p-28);
+    const double lo = fma(-hi, 0x1p28, X);
+    CrtResidues<kCrtMods>::run(hi, lo, d);
 }
 
-// Row r of A~ in residue form: slice k holds the residues modulo p_k (layout of split_row_block).
+// Residues of x scaled by 2^(b - e) and rounded to the nearest integer (ties to even): the
+// scaled value is exact, and from 2^52 on it is already an integer, so X is exact too.
+__device__ __forceinline__ void crt_digits(double x, int e, int b, int (&d)[kCrtMods]) {
+    crt_residues_of(rint(ldexp(x, b - e)), d);
+}
+
 // Balanced residue of d1 + d2 (both balanced residues modulo p_K).
 template <int K>
 __device__ __forceinline__ int crt_balanced_sum(int d1, int d2) {
@@ -200,29 +208,39 @@ __device__ __forceinline__ int crt_balanced_sum(int d1, int d2) {
     return t < -(p / 2) ? t + p : t;
 }
 
-// Stores the three residues of modulus k (real part, imaginary part, their sum) at o in slabs
-// 3k, 3k + 1, 3k + 2 (slab stride ss), for k < K.
+// Residues of four consecutive K positions j = 0..3 of one A~ row / B~^T row: the real and
+// imaginary parts' residues dr[j], di[j], stored as one 32-bit word per slab at o (4-byte
+// aligned) in slabs 3k (real part), 3k + 1 (imaginary part) and 3k + 2 (their sum modulo p_k),
+// slab stride ss, for every modulus k.
+__device__ __forceinline__ unsigned crt_pack4(int a0, int a1, int a2, int a3) {
+    return (unsigned)(a0 & 0xff) | ((unsigned)(a1 & 0xff) << 8) | ((unsigned)(a2 & 0xff) << 16) |
+           ((unsigned)(a3 & 0xff) << 24);
+}
+
 template <int K>
-struct CrtStore3 {
-    __device__ __forceinline__ static void run(const int (&dr)[kCrtMods], const int (&di)[kCrtMods],
+struct CrtStore3x4 {
+    __device__ __forceinline__ static void run(const int (&dr)[4][kCrtMods], const int (&di)[4][kCrtMods],
                                                signed char* o, size_t ss) {
-        CrtStore3<K - 1>::run(dr, di, o, ss);
+        CrtStore3x4<K - 1>::run(dr, di, o, ss);
         constexpr int k = K - 1;
-        o[(3 * k) * ss] = (signed char)dr[k];
-        o[(3 * k + 1) * ss] = (signed char)di[k];
-        o[(3 * k + 2) * ss] = (signed char)crt_balanced_sum<k>(dr[k], di[k]);
+        *reinterpret_cast<unsigned*>(o + (3 * k) * ss) = crt_pack4(dr[0][k], dr[1][k], dr[2][k], dr[3][k]);
+        *reinterpret_cast<unsigned*>(o + (3 * k + 1) * ss) = crt_pack4(di[0][k], di[1][k], di[2][k], di[3][k]);
+        *reinterpret_cast<unsigned*>(o + (3 * k + 2) * ss) =
+            crt_pack4(crt_balanced_sum<k>(dr[0][k], di[0][k]), crt_balanced_sum<k>(dr[1][k], di[1][k]),
+                      crt_balanced_sum<k>(dr[2][k], di[2][k]), crt_balanced_sum<k>(dr[3][k], di[3][k]));
     }
 };
 template <>
-struct CrtStore3<0> {
-    __device__ __forceinline__ static void run(const int (&)[kCrtMods], const int (&)[kCrtMods],
+struct CrtStore3x4<0> {
+    __device__ __forceinline__ static void run(const int (&)[4][kCrtMods], const int (&)[4][kCrtMods],
                                                signed char*, size_t) {}
 };
 
 // Residues for the complex product in three real products per modulus (exact modulo p_k):
 // Re = ar br - ai bi, Im = (ar + ai)(br + bi) - ar br - ai bi.  Slab 3k + q (q = 0: real part,
 // 1: imaginary part, 2: their sum, all modulo p_k) holds crt_rows_pad(N) rows of ldk bytes
-// (K = N, zero padded).  Row r of A~ (one block per row; the row exponent from its maximum):
+// (K = N, zero padded; ldk a multiple of 128).  Row r of A~ (one block per row; the row
+// exponent from its maximum), four consecutive columns per thread:
 __device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int N, int r, int b, int ldk,
                                       signed char* __restrict__ slabs, int* __restrict__ ea,
                                       double* red) {
@@ -242,21 +260,27 @@ __device__ __forceinline__ void crt_row_block(const double2* __restrict__ A, int
     if (threadIdx.x == 0) ea[r] = e;
     const size_t ss = (size_t)crt_rows_pad(N) * ldk;
     signed char* base = slabs + (size_t)r * ldk;
-    for (int c = threadIdx.x; c < ldk; c += kSThreads) {
-        const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);
-        int dr[kCrtMods], di[kCrtMods];
-        crt_digits(v.x, e, b, dr);
-        crt_digits(v.y, e, b, di);
-        CrtStore3<kCrtMods>::run(dr, di, base + c, ss);
+    for (int c0 = 4 * threadIdx.x; c0 < ldk; c0 += 4 * kSThreads) {
+        int dr[4][kCrtMods], di[4][kCrtMods];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + j;
+            const double2 v = c < N ? row[c] : make_double2(0.0, 0.0);
+            crt_digits(v.x, e, b, dr[j]);
+            crt_digits(v.y, e, b, di[j]);
+        }
+        CrtStore3x4<kCrtMods>::run(dr, di, base + c0, ss);
     }
 }
 
 // B~^T rows (one per column c of B, K = N along the row), tile (bx, by) of kCT columns x kCT
-// K values staged through LDS so that both the reads of B and the byte stores are coalesced.
+// K values staged through LDS so that both the reads of B and the word stores are coalesced:
+// thread t takes column c0 + t / 8 and K positions k0 + 4 (t % 8) .. + 3.
 __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int N, int bx, int by, int b,
                                       int ldk, const int* __restrict__ eb,
                                       signed char* __restrict__ slabs,
                                       double2 (*tile)[kCT + 1]) {
+    static_assert(kCT * kCT == 4 * kSThreads, "one pass of four K positions per thread");
     const int k0 = by * kCT, c0 = bx * kCT;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int a = ty; a < kCT; a += 8) {
@@ -265,18 +289,18 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
     }
     __syncthreads();
     const size_t ss = (size_t)crt_rows_pad(N) * ldk;
-    const int k = k0 + tx;
-    if (k >= ldk) return;
-    for (int a = ty; a < kCT; a += 8) {
-        const int c = c0 + a;
-        if (c >= N) break;
-        const double2 v = tile[tx][a];
-        const int e = eb[c];
-        int dr[kCrtMods], di[kCrtMods];
-        crt_digits(v.x, e, b, dr);
-        crt_digits(v.y, e, b, di);
-        CrtStore3<kCrtMods>::run(dr, di, slabs + (size_t)c * ldk + k, ss);
+    const int kq = 4 * (threadIdx.x & 7), cl = threadIdx.x >> 3;
+    const int c = c0 + cl, k = k0 + kq;
+    if (c >= N || k >= ldk) return;
+    const int e = eb[c];
+    int dr[4][kCrtMods], di[4][kCrtMods];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double2 v = tile[kq + j][cl];
+        crt_digits(v.x, e, b, dr[j]);
+        crt_digits(v.y, e, b, di[j]);
     }
+    CrtStore3x4<kCrtMods>::run(dr, di, slabs + (size_t)c * ldk + k, ss);
 }
 
 // Constants of the reconstruction: W_k = (M / p_k) ((M / p_k)^-1 mod p_k) < M, so that
@@ -325,11 +349,35 @@ constexpr CrtConst kCrtK = make_crt_const();
 // X = S - q M modulo 2^128 is X
 // itself, read as signed.  The magnitude is converted from its two 64-bit halves, each exact
 // when X is representable.
-template <bool Reduced = false>
-__device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
-    constexpr CrtConst C = kCrtK;
+// Running sums of that reconstruction: add(k, c) takes c = c_k in [0, p_k); value() gives X.
+struct CrtAcc {
     unsigned long long l0 = 0, l1 = 0, l2 = 0, l3 = 0;
     double Sd = 0.0;
+    __device__ __forceinline__ void add(int k, int c) {
+        constexpr CrtConst C = kCrtK;
+        const unsigned long long u = (unsigned)c;
+        l0 += u * C.wl[k][0];
+        l1 += u * C.wl[k][1];
+        l2 += u * C.wl[k][2];
+        l3 += u * C.wl[k][3];
+        Sd += (double)c * C.wd[k];
+    }
+    __device__ __forceinline__ double value() const {
+        constexpr CrtConst C = kCrtK;
+        const unsigned __int128 S = (unsigned __int128)l0 + ((unsigned __int128)l1 << 32) +
+                                    ((unsigned __int128)l2 << 64) + ((unsigned __int128)l3 << 96);
+        const unsigned long long q = (unsigned long long)rint(Sd / C.md);
+        const unsigned __int128 M = ((unsigned __int128)C.mhi << 64) | C.mlo;
+        const __int128 X = (__int128)(S - (unsigned __int128)q * M);
+        const unsigned __int128 a = X < 0 ? (unsigned __int128)(-X) : (unsigned __int128)X;
+        const double v = (double)(unsigned long long)(a >> 64) * 0x1p64 + (double)(unsigned long long)a;
+        return X < 0 ? -v : v;
+    }
+};
+
+template <bool Reduced = false>
+__device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
+    CrtAcc acc;
 #pragma unroll
     for (int k = 0; k < kCrtMods; ++k) {
         int c = g[k];
@@ -338,21 +386,9 @@ __device__ __forceinline__ double crt_reconstruct(const int (&g)[kCrtMods]) {
             c = c - (int)floor((double)c * (1.0 / (double)p)) * p;
             c = c < 0 ? c + p : (c >= p ? c - p : c);
         }
-        const unsigned long long u = (unsigned)c;
-        l0 += u * C.wl[k][0];
-        l1 += u * C.wl[k][1];
-        l2 += u * C.wl[k][2];
-        l3 += u * C.wl[k][3];
-        Sd += (double)c * C.wd[k];
+        acc.add(k, c);
     }
-    const unsigned __int128 S = (unsigned __int128)l0 + ((unsigned __int128)l1 << 32) +
-                                ((unsigned __int128)l2 << 64) + ((unsigned __int128)l3 << 96);
-    const unsigned long long q = (unsigned long long)rint(Sd / C.md);
-    const unsigned __int128 M = ((unsigned __int128)C.mhi << 64) | C.mlo;
-    const __int128 X = (__int128)(S - (unsigned __int128)q * M);
-    const unsigned __int128 a = X < 0 ? (unsigned __int128)(-X) : (unsigned __int128)X;
-    const double v = (double)(unsigned long long)(a >> 64) * 0x1p64 + (double)(unsigned long long)a;
-    return X < 0 ? -v : v;
+    return acc.value();
 }
 
 // ---------------------------------------------------------------- INT8 product tile
@@ -558,16 +594,20 @@ struct I8LSmem {
     signed char stage[2 * kI8LStage] __attribute__((aligned(16)));
 };
 
-// Byte slab G8[j] (N x N) of tile (ti, tj) for every residue slab pair j < s (three per
-// modulus, see crt_row_block), from sa and sb (crt_rows_pad(N) x ldk bytes per slab), over the
-// K stages [kb, ke): each int32 sum is stored reduced modulo p_(j / 3).
+// Byte slabs G8[j] (N x N) of tile (ti, tj) for the residue slab pairs j = j0 .. j0 + s - 1
+// (three per modulus, see crt_row_block), from sa and sb (crt_rows_pad(N) x ldk bytes per
+// slab, slab j at offset j times that), over the K stages [kb, ke): each int32 sum is stored
+// reduced modulo p_(j / 3).
 __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed char* __restrict__ sa,
                                                     const signed char* __restrict__ sb,
-                                                    unsigned char* __restrict__ G8, int N, int s,
-                                                    int ldk, I8LSmem& sm, int kb, int ke) {
+                                                    unsigned char* __restrict__ G8, int N, int j0,
+                                                    int s, int ldk, I8LSmem& sm, int kb, int ke) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = ti * kI8LM, cc0 = tj * kI8LN, M2 = N;  // N output columns per slab
     const size_t sA = (size_t)crt_rows_pad(N) * ldk, sB = sA;
+    sa += (size_t)j0 * sA;
+    sb += (size_t)j0 * sB;
+    G8 += (size_t)j0 * N * M2;
     const int total = s * (ke - kb);
     const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
     const int l32 = lane & 31, h = lane >> 5;
@@ -654,7 +694,7 @@ __device__ __forceinline__ void zgemm_i8_tile_large(int ti, int tj, const signed
             int m2 = M2;
             asm volatile("" : "+v"(m2));
             unsigned char* g8 = G8 + (size_t)cm * N * M2;
-            const int p = crt_modulus(cm / 3);
+            const int p = crt_modulus((j0 + cm) / 3);
             const double rp = 1.0 / (double)p;
 #pragma unroll
             for (int a = 0; a < 4; ++a)

@@ -1,8 +1,9 @@
 // Host build of the modular form's residue and reconstruction functions (split_tile.h), for a
 // CPU test: the device-only qualifier is widened to host + device before the header is read.
 // Reads lines "X g_0 .. g_15" (X a signed integer of up to 126 bits in decimal, g_k int32 with
-// g_k = X mod p_k) and prints, per line, crt_reconstruct(g) as a hex float and the balanced
-// residues of the low 63 bits of X (as a signed 64-bit value) from CrtResidues.
+// g_k = X mod p_k, then y, an integer of at most 53 significant bits with |y| < 2^62) and prints,
+// per line, crt_reconstruct(g) as a hex float and the balanced residues of y from
+// crt_residues_of((double) y), the FP64 residue routine of the residue kernels.
 #include <hip/hip_runtime.h>
 #undef __device__
 #define __device__ __attribute__((host)) __attribute__((device))
@@ -22,7 +23,7 @@ int main() {
         long long y;
         if (scanf("%lld", &y) != 1) return 2;
         int d[kCrtMods];
-        CrtResidues<kCrtMods>::run(y, d);
+        crt_residues_of((double)y, d);
         printf("%a", crt_reconstruct(g));
         for (int k = 0; k < kCrtMods; ++k) printf(" %d", d[k]);
         printf("\n");

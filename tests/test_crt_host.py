@@ -1,7 +1,9 @@
 """The modular (CRT) form's integer arithmetic, built for the host from the same header the
 kernels use and checked against Python's exact integers (no GPU): the reconstruction of X from
 int32 values congruent to X modulo the 16 moduli, over |X| up to 0.49 M (the bit count keeps
-the products below 0.99^2 M / 2), and the balanced residues of 63-bit integers."""
+the products below 0.99^2 M / 2), and the balanced residues of integers held exactly in a
+double (up to 53 significant bits, below 2^61 in magnitude), which the residue kernels form in
+FP64."""
 
 import os
 import random
@@ -56,7 +58,8 @@ def test_reconstruct_and_residues_exact(prog):
         for p in MODULI:
             # some int32 congruent to X mod p, as the INT8 products give (|g| < 2^31)
             g.append(X % p + p * rng.randint(-(2 ** 30) // p, (2 ** 30) // p))
-        y = rng.choice([-1, 1]) * rng.getrandbits(rng.randint(0, 62))
+        # an integer as the residue kernels hold it: exact in a double, |y| < 2^62
+        y = rng.choice([-1, 1]) * (rng.getrandbits(rng.randint(0, 53)) << rng.randint(0, 8))
         ys.append(y)
         lines.append(" ".join([str(X)] + [str(v) for v in g] + [str(y)]))
     r = subprocess.run([prog], input="\n".join(lines) + "\n", capture_output=True, text=True,
