@@ -251,6 +251,39 @@ def small_leg(steps):
     its, res = z.isomp_run(W, h, steps, tol, cfg["maxit"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the stopping rule on the device (every evaluation up to the cap enqueued, skipped once the
+    # step has converged): eagerly, and the whole run captured into one graph and replayed
+    cap = 5
+    z.set_stopping(1)
+    Wd = W0.clone()
+    z.isomp_run(Wd, h, 2, tol, cap)
+    Wd = W0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_d, _ = z.isomp_run(Wd, h, steps, tol, cap)
+    torch.cuda.synchronize()
+    dt_dev = time.perf_counter() - t0
+    sg = torch.cuda.Stream()
+    zg = Zeuler(N, stream=sg)
+    zg.set_stopping(1)
+    zg.set_initial_guess(2)
+    zg.set_update_form(1)
+    Wgr = W0.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=sg):
+        zg.isomp_run_async(Wgr, h, steps, tol, cap)
+    graph.replay()  # warm-up replay from W0
+    torch.cuda.synchronize()
+    Wgr.copy_(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t0
+    its_g, _, _ = zg.run_stats(steps)
+    dev_diff = float(torch.linalg.norm(Wgr - W).item() + torch.linalg.norm(Wd - W).item())
+    del graph
+    zg.close()
     Wg = W0.clone()
     with Ensemble([N]) as ens:
         ens.set_initial_guess(2)
@@ -267,6 +300,10 @@ def small_leg(steps):
         "workload": f"n512: one simulation, N={N}, sigma_l law {cfg['law']}, h={h}, tol={tol}, {steps} steps",
         "single_context_s_per_step": dt / steps,
         "iters_per_step": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
+        "device_stopping_s_per_step": dt_dev / steps,
+        "device_stopping_graph_s_per_step": dt_graph / steps,
+        "device_stopping_evaluation_cap": cap,
+        "device_stopping_same_counts_and_result": its_d == list(its) and its_g == list(its) and dev_diff == 0.0,
         "graph_ensemble_of_one_s_per_step": dtg / steps,
         "rel_frobenius_between_the_two": diff,
         "note": "both forms start the steps after the first from the polynomial extrapolation "
@@ -700,6 +737,7 @@ def compact_record(out, detail_path=None):
     n512 = out.get("n512")
     if n512:
         rec["n512_s_per_step"] = _sig(n512["single_context_s_per_step"])
+        rec["n512_device_stop_graph_s_per_step"] = _sig(n512.get("device_stopping_graph_s_per_step"))
     cb = out.get("cpu_baseline")
     if cb:
         rec["cpu_baseline"] = {"value": _sig(cb["value"]), "unit": cb["unit"], "cores": cb["cores"],

@@ -116,7 +116,8 @@ ze_status ze_stream_solve(ze_ctx* ctx, const void* W, void* P);
  *   resid   host, may be NULL: final residual (the largest over the substeps).
  * Errors: ZE_EINVAL, ZE_ENOTCONV (W holds the maxit-th W_{n+1}; at order 4 or 6 every substep
  * still runs, each stopping at maxit), ZE_ENONFINITE, ZE_EHIP.
- * Synchronises the stream once per evaluation (the convergence test).
+ * Synchronises the stream once per evaluation (the convergence test), unless the stopping rule
+ * runs on the device (ze_set_stopping).
  */
 ze_status ze_isomp_step(ze_ctx* ctx, void* W, double h, double tol, int maxit, int prec,
                         int* iters, double* resid);
@@ -125,10 +126,41 @@ ze_status ze_isomp_step(ze_ctx* ctx, void* W, double h, double tol, int maxit, i
  * ze_isomp_run -- nsteps IsoMP steps on the same W (the first exactly as ze_isomp_step; the
  * later ones start their fixed-point iteration as ze_set_initial_guess selects).
  *   iters, resid  host arrays of nsteps entries, may be NULL.
- * Stops at the first step that returns an error and returns it.
+ * Stops at the first step that returns an error and returns it (host stopping rule; with the
+ * rule on the device every step runs, and the status covers the whole run).
  */
 ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, int nsteps,
                        int prec, int* iters, double* resid);
+
+/*
+ * ze_set_stopping -- where the tolerance test of eq. (isomp_iter) (Sec. 2: stop once the
+ * infinity norm of the change of W~ is below tol) is taken.
+ *   mode 0  on the host (default): the residual is read back after each evaluation.
+ *   mode 1  on the device: ze_isomp_step / ze_isomp_run enqueue maxit evaluations per step
+ *           (substep at order 4 or 6); the residual kernel sets a device flag once the change
+ *           is below tol (or not finite) and every later kernel of that step returns at once,
+ *           so W_{n+1} is that of the same evaluation as with mode 0 (same kernels, same order:
+ *           bit-identical results).  Nothing synchronises except, at the end of the call, the
+ *           copy of the per-step counts when iters or resid is non-NULL; with both NULL the
+ *           call is asynchronous and can be captured into a HIP graph (ze_run_stats reads the
+ *           counts afterwards).  Every step of a run is executed even when one fails to
+ *           converge.  A skipped evaluation still costs its (empty) launches, so maxit is best
+ *           set near the most evaluations a step needs.  FP64 products only (ZE_PREC_FP64;
+ *           other precisions return ZE_EINVAL); ze_profile's per-phase timing is not taken.
+ * Selecting mode 1 allocates the per-step records (65536 steps; older steps of a longer run
+ * are reported as -1).
+ * Errors: ZE_EINVAL, ZE_ENOMEM.
+ */
+ze_status ze_set_stopping(ze_ctx* ctx, int mode);
+
+/*
+ * ze_run_stats -- on-device stopping: synchronises the context's stream and reads the last
+ * nsteps steps of the last ze_isomp_run / ze_isomp_step call (nsteps <= its length).
+ *   iters, resid  host arrays of nsteps entries (may be NULL), as ze_isomp_run fills them.
+ * Returns the run's status: ZE_ENONFINITE or ZE_ENOTCONV if any of its steps had it, else
+ * ZE_OK; ZE_EINVAL if mode 1 is not selected or nsteps is out of range; ZE_EHIP.
+ */
+ze_status ze_run_stats(ze_ctx* ctx, int nsteps, int* iters, double* resid);
 
 /*
  * ze_set_initial_guess -- starting iterate of the fixed-point iteration (eq. (isomp_iter))

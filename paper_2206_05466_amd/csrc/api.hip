@@ -1,6 +1,7 @@
 // C ABI of libzeuler: context set-up (Laplacian factors), stream solve, IsoMP step driver,
 // Casimirs, products.  Host code; the arithmetic of every step runs in the HIP kernels.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -183,6 +184,10 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->crt_b);
     dfree(c->crt_g);
     dfree(c->resid);
+    dfree(c->dctl);
+    dfree(c->dctld);
+    dfree(c->dstep_it);
+    dfree(c->dstep_r);
     dfree(c->val_part);
     if (c->host_resid) (void)hipHostFree(c->host_resid);
     for (hipEvent_t e : c->ev)
@@ -236,6 +241,11 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     if (st == ZE_OK) st = dalloc(&c->rowpart, (size_t)T * N);
     if (st == ZE_OK) st = dalloc(&c->blockmax, (size_t)(N + 255) / 256 + 1);
     if (st == ZE_OK) st = dalloc(&c->resid, 1);
+    if (st == ZE_OK) st = dalloc(&c->dctl, kCtlWords);
+    if (st == ZE_OK) st = dalloc(&c->dctld, 2);
+    if (st == ZE_OK && (hipMemset(c->dctl, 0, kCtlWords * sizeof(int)) != hipSuccess ||
+                        hipMemset(c->dctld, 0, 2 * sizeof(double)) != hipSuccess))
+        st = ze_record_hip(hipGetLastError(), "control words clear");
     if (st == ZE_OK && hipHostMalloc(reinterpret_cast<void**>(&c->host_resid), sizeof(double)) != hipSuccess) {
         c->host_resid = nullptr;
         (void)hipGetLastError();
@@ -325,12 +335,23 @@ enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
 // One midpoint step of size h.  The fixed point starts from W_n (kFromWn), from
 // W_n + rho (W_n - F) written over F (kLinear; F = the previous step's converged midpoint, still
 // in c->F; rho = 1 gives 2 W_n - F), or from the iterate the caller has put in c->F (kFromF).
+ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, StartFrom start,
+                            double rho, bool first, bool last);
+
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                          StartFrom start, double rho, int* iters, double* resid) {
+                          StartFrom start, double rho, int* iters, double* resid, bool first = true,
+                          bool last = true) {
     if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED &&
         prec != ZE_PREC_CRT)
         return ZE_EINVAL;
+    if (c->stop_mode == 1) {
+        if (prec != ZE_PREC_FP64) {
+            g_last_error = "on-device stopping runs the FP64 products only";
+            return ZE_EINVAL;
+        }
+        return isomp_step_device(c, W, h, tol, maxit, start, rho, first, last);
+    }
     const int N = c->N;
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
@@ -373,7 +394,8 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
                                        nullptr, s));
         }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
-        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, c->resid, N, s));
+        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax,
+                                   reinterpret_cast<unsigned*>(c->dctl + kCtlCounter), c->resid, N, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
         ZE_HIP(hipMemcpyAsync(c->host_resid, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
         ZE_HIP(hipStreamSynchronize(s));
@@ -395,6 +417,36 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     if (resid) *resid = r;
     if (!std::isfinite(r)) return ZE_ENONFINITE;
     if (!(r < tol)) return ZE_ENOTCONV;
+    return ZE_OK;
+}
+
+// The same substep with the stopping rule on the device: maxit evaluations are enqueued, each
+// kernel of an evaluation reads the done flag (dctl[0]) first and returns at once when it is
+// set, and the residual reduction sets it once the change of W~ is below tol (or not finite).
+// The caller's W receives W_{n+1} from every evaluation that runs, so it ends with that of the
+// last one, as in the host loop.  Nothing synchronises; the counts and residuals go to the
+// control words and the per-step records (first / last: the substep opens / closes the step).
+ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, StartFrom start,
+                            double rho, bool first, bool last) {
+    const int N = c->N;
+    double2* Wu = static_cast<double2*>(W);
+    hipStream_t s = c->stream;
+    const int* skip = c->dctl;
+    unsigned* counter = reinterpret_cast<unsigned*>(c->dctl + kCtlCounter);
+    ZE_HIP(launch_ctl_substep_begin(Wu, c->Wn, N, c->dctl, c->dctld, first, s));
+    if (start == kLinear) ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
+    const double2* Wt = start == kFromWn ? c->Wn : c->F;
+    for (int k = 1; k <= maxit; ++k) {
+        ZE_HIP(launch_stream_solve(c, Wt, c->P, s, skip));
+        ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s, skip));
+        ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s, skip));
+        ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
+                                   nullptr, s, skip));
+        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, counter, c->resid, N, s, skip, c->dctl,
+                                   tol));
+        Wt = c->F;
+    }
+    ZE_HIP(launch_ctl_substep_end(c->dctl, c->dctld, c->resid, tol, last, c->dstep_it, c->dstep_r, s));
     return ZE_OK;
 }
 
@@ -451,7 +503,8 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
         if (c->guess_mode == 2) ZE_TRY(ring_start(c, W, j, n, rho, &start));
         int k = 0;
         double r = 0.0;
-        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, start, rho, &k, &r);
+        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, start, rho, &k, &r,
+                                             j == 0, j + 1 == ns);
         total += k;
         if (!(r <= rmax)) rmax = r;  // keeps a NaN
         if (st == ZE_ENOTCONV) {
@@ -470,12 +523,80 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
 
 }  // namespace
 
+// On-device stopping: the records of the last run (nsteps <= its length) and its status.
+static ze_status read_run_records(ze_ctx* c, int nsteps, int* iters, double* resid) {
+    if (nsteps < 0 || nsteps > c->last_run_steps) return ZE_EINVAL;
+    // the last m = min(nsteps, kDevSteps) steps of the run: step n sits at n % kDevSteps, so
+    // they are at most two contiguous pieces of the records
+    const int total = c->last_run_steps, m = nsteps < kDevSteps ? nsteps : kDevSteps;
+    int ctl[kCtlWords];
+    std::vector<int> it((size_t)m);
+    std::vector<double> rr((size_t)m);
+    ZE_HIP(hipMemcpyAsync(ctl, c->dctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
+    for (int done = 0; done < m;) {
+        const int pos = (total - m + done) % kDevSteps;
+        const int len = std::min(m - done, kDevSteps - pos);
+        ZE_HIP(hipMemcpyAsync(it.data() + done, c->dstep_it + pos, (size_t)len * sizeof(int),
+                              hipMemcpyDeviceToHost, c->stream));
+        ZE_HIP(hipMemcpyAsync(rr.data() + done, c->dstep_r + pos, (size_t)len * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+        done += len;
+    }
+    ZE_HIP(hipStreamSynchronize(c->stream));
+    // steps older than the last kDevSteps are reported as -1
+    for (int i = 0; i < nsteps; ++i) {
+        const int j = i - (nsteps - m);
+        if (iters) iters[i] = j >= 0 ? it[(size_t)j] : -1;
+        if (resid) resid[i] = j >= 0 ? rr[(size_t)j] : -1.0;
+    }
+    if (ctl[5] > 0) return ZE_ENONFINITE;
+    if (ctl[4] > 0) return ZE_ENOTCONV;
+    return ZE_OK;
+}
+
+// A run with on-device stopping: every step enqueued, one synchronisation at the end only if
+// per-step results are asked for.
+static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps,
+                            int prec, int* iters, double* resid) {
+    if (prec != ZE_PREC_FP64) {
+        g_last_error = "on-device stopping runs the FP64 products only";
+        return ZE_EINVAL;
+    }
+    if (!is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
+    ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
+    for (int n = 0; n < nsteps; ++n) ZE_TRY(composed_step(c, W, h, tol, maxit, prec, n, nullptr, nullptr));
+    c->last_run_steps = nsteps;
+    if (!iters && !resid) return ZE_OK;
+    return read_run_records(c, nsteps, iters, resid);
+}
+
 ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                         int* iters, double* resid) {
     g_last_error.clear();
     if (!c || !W) return ZE_EINVAL;
     if (c->validate) ZE_TRY(check_su(c, W));
+    if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, 1, prec, iters, resid);
     return composed_step(c, W, h, tol, maxit, prec, 0, iters, resid);
+}
+
+ze_status ze_set_stopping(ze_ctx* c, int mode) {
+    if (!c || mode < 0 || mode > 1) return ZE_EINVAL;
+    if (mode == 1 && !c->dstep_it) {
+        ZE_TRY(dalloc(&c->dstep_it, (size_t)kDevSteps));
+        const ze_status st = dalloc(&c->dstep_r, (size_t)kDevSteps);
+        if (st != ZE_OK) {
+            dfree(c->dstep_it);
+            c->dstep_it = nullptr;
+            return st;
+        }
+    }
+    c->stop_mode = mode;
+    return ZE_OK;
+}
+
+ze_status ze_run_stats(ze_ctx* c, int nsteps, int* iters, double* resid) {
+    if (!c || c->stop_mode != 1) return ZE_EINVAL;
+    return read_run_records(c, nsteps, iters, resid);
 }
 
 ze_status ze_set_validation(ze_ctx* c, int on) {
@@ -489,6 +610,7 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     g_last_error.clear();
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
     if (c->validate && nsteps > 0) ZE_TRY(check_su(c, W));
+    if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, nsteps, prec, iters, resid);
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;

@@ -133,6 +133,56 @@ __global__ __launch_bounds__(256) void su_check_final(const double* __restrict__
     if (tid < 4) out[tid] = tid == 0 ? r0[0] : tid == 1 ? r1[0] : tid == 2 ? r2[0] : r3[0];
 }
 
+// ---------------------------------------------------------------- on-device stopping
+// Control words: see kCtlWords in internal.h.  NaN-propagating maximum.
+__device__ __forceinline__ double nanmax(double a, double o) { return (o != o || o > a) ? o : a; }
+
+__global__ __launch_bounds__(64) void ctl_run_begin_kernel(int* ctl, double* ctld) {
+    if (threadIdx.x == 0) {
+        for (int w = 4; w <= 7; ++w) ctl[w] = 0;
+        ctl[9] = 0;
+        ctld[1] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void ctl_substep_begin_kernel(const double2* __restrict__ W,
+                                                                double2* __restrict__ Wn, size_t n2,
+                                                                int* ctl, double* ctld, int first) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256)
+        Wn[e] = W[e];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl[0] = 0;
+        ctl[1] = 0;
+        if (first) {
+            ctl[2] = 0;
+            ctl[3] = 0;
+            ctld[0] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void ctl_substep_end_kernel(int* ctl, double* ctld,
+                                                             const double* __restrict__ resid,
+                                                             double tol, int last, int* step_it,
+                                                             double* step_r) {
+    if (threadIdx.x != 0) return;
+    const double r = resid[0];
+    ctl[2] += ctl[1];
+    ctld[0] = nanmax(ctld[0], r);
+    if (!(r < tol)) ctl[3] |= 1;
+    if (!isfinite(r)) ctl[3] |= 2;
+    if (!last) return;
+    const int n = ctl[9];
+    step_it[n % kDevSteps] = ctl[2];
+    step_r[n % kDevSteps] = ctld[0];
+    if (ctl[3] & 1) ctl[4] += 1;
+    if (ctl[3] & 2) ctl[5] += 1;
+    ctl[6] += ctl[2];
+    ctl[7] = ctl[2] > ctl[7] ? ctl[2] : ctl[7];
+    ctld[1] = nanmax(ctld[1], ctld[0]);
+    ctl[9] = n + 1;
+}
+
 }  // namespace
 
 int ze_su_check_blocks(int N) {
@@ -165,5 +215,26 @@ hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, h
     const size_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(extrapolate_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256),
                        0, s, W, F, n, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_run_begin(int* ctl, double* ctld, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_run_begin_kernel, dim3(1), dim3(64), 0, s, ctl, ctld);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_substep_begin(const double2* W, double2* Wn, int N, int* ctl, double* ctld,
+                                    bool first, hipStream_t s) {
+    const size_t n2 = (size_t)N * N;
+    const size_t blocks = (n2 + 255) / 256;
+    hipLaunchKernelGGL(ctl_substep_begin_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
+                       dim3(256), 0, s, W, Wn, n2, ctl, ctld, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_substep_end(int* ctl, double* ctld, const double* resid, double tol, bool last,
+                                  int* step_it, double* step_r, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_substep_end_kernel, dim3(1), dim3(64), 0, s, ctl, ctld, resid, tol,
+                       last ? 1 : 0, step_it, step_r);
     return hipGetLastError();
 }

@@ -90,9 +90,11 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
                                                              const double2* __restrict__ B,
                                                              double2* __restrict__ Cm, int N,
                                                              int tiles_n, int full, int S,
-                                                             double* __restrict__ part) {
+                                                             double* __restrict__ part,
+                                                             const int* __restrict__ skip) {
     using C = FullCfg;
     __shared__ double smem[2 * C::STAGE];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const int nk = (N + kBK - 1) / kBK;
     const int b = blockIdx.x;
     int tile, kb = 0, ke = nk;
@@ -118,8 +120,10 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
 // split tile t, in part order (deterministic), and stores it.
 __global__ __launch_bounds__(kThreads) void zgemm_f64_fixup(double2* __restrict__ Cm, int N,
                                                             int tiles_n, int full, int S,
-                                                            const double* __restrict__ part) {
+                                                            const double* __restrict__ part,
+                                                            const int* __restrict__ skip) {
     using C = FullCfg;
+    if (skip && *skip) return;
     const int tile = full + blockIdx.x;
     const d4 acc = sum_partial_tile<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads),
                                        S, blockIdx.y);
@@ -134,9 +138,11 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_fixup(double2* __restrict_
 // share A row panels and P column panels in its L2.
 __global__ __launch_bounds__(kThreads) void zgemm_lower_kernel(
     const double2* __restrict__ Am, const double2* __restrict__ Pm, double2* __restrict__ Q,
-    int N, int full, int S, double* __restrict__ part, const int* __restrict__ order) {
+    int N, int full, int S, double* __restrict__ part, const int* __restrict__ order,
+    const int* __restrict__ skip) {
     using C = LowCfg;
     __shared__ double smem[2 * C::STAGE];
+    if (skip && *skip) return;
     const int nk = (N + kBK - 1) / kBK;
     const int b = blockIdx.x;
     int tile, kb = 0, ke = nk;
@@ -161,8 +167,10 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_kernel(
 __global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(double2* __restrict__ Q, int N,
                                                               int full, int S,
                                                               const double* __restrict__ part,
-                                                              const int* __restrict__ order) {
+                                                              const int* __restrict__ order,
+                                                              const int* __restrict__ skip) {
     using C = LowCfg;
+    if (skip && *skip) return;
     int I, J;
     lower_tile(order[full + blockIdx.x], I, J);
     const d4 acc = sum_partial_tile<C>(part + (size_t)blockIdx.x * S * (C::MT * C::NT * 4 * kThreads),
@@ -173,10 +181,19 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(double2* __restric
 // ---------------------------------------------------------------- residual reduction
 constexpr int kRedThreads = 256;
 
-__global__ __launch_bounds__(kRedThreads) void rowsum_max_kernel(const double* __restrict__ rowpart,
-                                                                  int T, int N,
-                                                                  double* __restrict__ blockmax) {
+// resid = max_r sum_X rowpart[X N + r] (NaN propagates) in one launch: each block takes the
+// row sums of 256 rows and stores their maximum; the last block to finish (a counter, reset
+// by that block) takes the maximum over the blocks.  With ctl (on-device stopping) that block
+// also counts the evaluation (ctl[1]) and sets the step's done flag ctl[0] when resid < tol or
+// resid is not finite; with skip set at entry (the step had already converged) it does nothing.
+__global__ __launch_bounds__(kRedThreads) void resid_kernel(const double* __restrict__ rowpart,
+                                                            int T, int N, double* blockmax,
+                                                            unsigned* counter, double* resid,
+                                                            const int* __restrict__ skip, int* ctl,
+                                                            double tol) {
     __shared__ double sm[kRedThreads];
+    __shared__ bool last;
+    if (skip && *skip) return;
     const int i = blockIdx.x * kRedThreads + threadIdx.x;
     double v = 0.0;
     if (i < N)
@@ -190,18 +207,20 @@ __global__ __launch_bounds__(kRedThreads) void rowsum_max_kernel(const double* _
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) blockmax[blockIdx.x] = sm[0];
-}
-
-__global__ __launch_bounds__(kRedThreads) void max_final_kernel(const double* __restrict__ blockmax,
-                                                                 int G, double* __restrict__ out) {
-    __shared__ double sm[kRedThreads];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < G; i += kRedThreads) {
-        const double o = blockmax[i];
-        v = (o != o || o > v) ? o : v;
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(blockmax + blockIdx.x, sm[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
-    sm[threadIdx.x] = v;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double m = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kRedThreads) {
+        const double o = __hip_atomic_load(blockmax + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m = (o != o || o > m) ? o : m;
+    }
+    sm[threadIdx.x] = m;
     __syncthreads();
     for (int s = kRedThreads / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
@@ -210,7 +229,15 @@ __global__ __launch_bounds__(kRedThreads) void max_final_kernel(const double* __
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sm[0];
+    if (threadIdx.x == 0) {
+        const double r = sm[0];
+        resid[0] = r;
+        *counter = 0u;
+        if (ctl) {
+            ctl[1] += 1;
+            if (r < tol || !isfinite(r)) ctl[0] = 1;
+        }
+    }
 }
 
 }  // namespace
@@ -248,25 +275,25 @@ namespace {
 // The full product with `cap` concurrent blocks and a partial buffer `part` of `pmax` split
 // blocks' partial sums.
 hipError_t launch_full(int N, int cap, double* part, int pmax, const double2* A, const double2* B,
-                       double2* Cm, hipStream_t s) {
+                       double2* Cm, hipStream_t s, const int* skip = nullptr) {
     const int tiles_n = (N + FullCfg::BNC - 1) / FullCfg::BNC;
     const int tiles = tiles_n * ((N + FullCfg::BM - 1) / FullCfg::BM);
     const Split sp = make_split(tiles, (N + kBK - 1) / kBK, cap, pmax);
     hipLaunchKernelGGL(zgemm_f64_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A, B,
-                       Cm, N, tiles_n, sp.full, sp.S, part);
+                       Cm, N, tiles_n, sp.full, sp.S, part, skip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
     hipLaunchKernelGGL(zgemm_f64_fixup, dim3(sp.tail, FullCfg::MT * FullCfg::NT), dim3(kThreads), 0, s,
-                       Cm, N, tiles_n, sp.full, sp.S, part);
+                       Cm, N, tiles_n, sp.full, sp.S, part, skip);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* Cm,
-                            hipStream_t s) {
+                            hipStream_t s, const int* skip) {
     // the context's buffer holds cap_full blocks' partial sums (ze_gemm_part_bytes)
-    return launch_full(c->N, c->cap_full, c->gemm_part, c->cap_full, A, B, Cm, s);
+    return launch_full(c->N, c->cap_full, c->gemm_part, c->cap_full, A, B, Cm, s, skip);
 }
 
 // ---------------------------------------------------------------- allocation-free product
@@ -320,27 +347,25 @@ hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, d
 }
 
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
-                              hipStream_t s) {
+                              hipStream_t s, const int* skip) {
     const int N = c->N;
     const int T = (N + kTile - 1) / kTile;
     const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low, c->cap_low);
     hipLaunchKernelGGL(zgemm_lower_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A,
-                       P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
+                       P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order, skip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sp.tail == 0) return e;
     hipLaunchKernelGGL(zgemm_lower_fixup, dim3(sp.tail, LowCfg::MT * LowCfg::NT), dim3(kThreads), 0, s,
-                       Q, N, sp.full, sp.S, c->gemm_part, c->low_order);
+                       Q, N, sp.full, sp.S, c->gemm_part, c->low_order, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, double* resid, int N,
-                               hipStream_t s) {
+hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, unsigned* counter,
+                               double* resid, int N, hipStream_t s, const int* skip, int* ctl,
+                               double tol) {
     const int T = (N + kTile - 1) / kTile;
     const int G = (N + kRedThreads - 1) / kRedThreads;
-    hipLaunchKernelGGL(rowsum_max_kernel, dim3(G), dim3(kRedThreads), 0, s, rowpart, T, N,
-                       blockmax);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(max_final_kernel, dim3(1), dim3(kRedThreads), 0, s, blockmax, G, resid);
+    hipLaunchKernelGGL(resid_kernel, dim3(G), dim3(kRedThreads), 0, s, rowpart, T, N, blockmax,
+                       counter, resid, skip, ctl, tol);
     return hipGetLastError();
 }

@@ -97,12 +97,36 @@ struct ze_ctx {
     bool validate = false;
     double* val_part = nullptr;
 
+    // Stopping rule (ze_set_stopping): 0 = the host reads the residual after each evaluation;
+    // 1 = on the device: every evaluation up to maxit is enqueued, its kernels skip themselves
+    // once the step's done flag is set, and nothing waits for the host.  Control words dctl
+    // (kCtlWords ints, always allocated; dctl[kCtlCounter] is the residual reduction's block
+    // counter) and dctld (2 doubles); per-step records of the last run (kDevSteps each,
+    // allocated with mode 1).
+    int stop_mode = 0;
+    int* dctl = nullptr;
+    double* dctld = nullptr;
+    int* dstep_it = nullptr;
+    double* dstep_r = nullptr;
+    int last_run_steps = 0;
+
     // Optional per-phase timing (ze_profile).
     bool prof = false;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double prof_ms[4] = {0, 0, 0, 0};
     long long prof_n[4] = {0, 0, 0, 0};
 };
+
+// Control words of on-device stopping: [0] done flag of the current substep, [1] its
+// evaluations, [2] evaluations of the current step, [3] the step's flags (1: not converged,
+// 2: non-finite residual), [4] steps of the run not converged, [5] steps with a non-finite
+// residual, [6] evaluations of the run, [7] most evaluations of one step, [kCtlCounter] the
+// residual reduction's block counter, [9] index of the current step in the run.  dctld:
+// [0] the step's largest residual, [1] the run's.
+constexpr int kCtlWords = 16;
+constexpr int kCtlCounter = 8;
+// Per-step records kept by on-device stopping (step n of a run at n % kDevSteps).
+constexpr int kDevSteps = 1 << 16;
 
 // Largest matrix size a context accepts.
 constexpr int kMaxN = 16384;
@@ -144,8 +168,10 @@ void ze_build_factors(int N, int bd, std::vector<double>& fl, std::vector<double
 
 // ---- kernel launchers (all asynchronous on `s`) ----
 
-// Stream solve P = Delta_N^+ W (both N x N, row-major, leading dimension N).
-hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s);
+// Stream solve P = Delta_N^+ W (both N x N, row-major, leading dimension N); skip as for the
+// products.
+hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s,
+                               const int* skip = nullptr);
 
 // Blocks of the two product kernels that fit on the device at once, and the bytes of the
 // split-K partial buffer (ze_ctx::gemm_part) those capacities need.
@@ -154,9 +180,10 @@ size_t ze_gemm_part_bytes(int cap_full, int cap_low);
 // Lower-triangle tile indices (64 x 64 complex tiles) in 8 x 8 super-tile order.
 void ze_lower_tile_order(int N, std::vector<int>& order);
 
-// C = A B, all N x N complex (leading dimension N = c->N), FP64 MFMA.
+// C = A B, all N x N complex (leading dimension N = c->N), FP64 MFMA.  skip: a device flag
+// read at the start of every block (on-device stopping); nonzero there makes the launch a no-op.
 hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* C,
-                            hipStream_t s);
+                            hipStream_t s, const int* skip = nullptr);
 
 // The same product with its split-K partial sums in the library's fixed device array (no
 // allocation; ze_zgemm_noalloc): N x N, on the current device, asynchronous on `s`.
@@ -166,11 +193,14 @@ hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, d
 
 // Lower-triangle Q = A P (64 x 64 complex tiles meeting the lower triangle) into Q.
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
-                              hipStream_t s);
+                              hipStream_t s, const int* skip = nullptr);
 
-// resid = max_r sum_X rowpart[X*N + r]  (NaN propagates).
-hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, double* resid, int N,
-                               hipStream_t s);
+// resid = max_r sum_X rowpart[X*N + r]  (NaN propagates), one launch (counter: a zeroed device
+// word the launch leaves zeroed).  With ctl: ctl[1] += 1 and ctl[0] = 1 once resid < tol or is
+// not finite; skip as for the products.
+hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, unsigned* counter,
+                               double* resid, int N, hipStream_t s, const int* skip = nullptr,
+                               int* ctl = nullptr, double tol = 0.0);
 
 // out[0] = sum_ij X_ij Y_ji (complex), through `partial` (>= ze_trace_partials(N) doubles2).
 int ze_trace_partials(int N);
@@ -210,7 +240,16 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
 hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2* A,
                                const double2* Wn, const double2* Wt, double2* F, double2* Wout,
                                double* rowpart, double h, const int* ea, const int* eb,
-                               hipStream_t s);
+                               hipStream_t s, const int* skip = nullptr);
+
+// On-device stopping: start of a run (clears the run's records); start of a substep (Wn <- W,
+// done and the substep's count cleared; first: also the step's); end of a substep (its count
+// and residual into the step's; last: the step's record written at its index, run totals).
+hipError_t launch_ctl_run_begin(int* ctl, double* ctld, hipStream_t s);
+hipError_t launch_ctl_substep_begin(const double2* W, double2* Wn, int N, int* ctl, double* ctld,
+                                    bool first, hipStream_t s);
+hipError_t launch_ctl_substep_end(int* ctl, double* ctld, const double* resid, double tol, bool last,
+                                  int* step_it, double* step_r, hipStream_t s);
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, hipStream_t s);

@@ -43,9 +43,11 @@ __global__ __launch_bounds__(T) void stream_solve_kernel(const double2* __restri
                                                          double2* __restrict__ P,
                                                          const double* __restrict__ fl,
                                                          const double* __restrict__ fd,
-                                                         int N, int nwg, int per) {
+                                                         int N, int nwg, int per,
+                                                         const int* __restrict__ skip) {
     __shared__ double sG[T];
     __shared__ double2 sY[T];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const int b = blockIdx.x;
     const int w = (b & 7) * per + (b >> 3);
     if (w >= nwg) return;  // uniform for the block
@@ -53,13 +55,13 @@ __global__ __launch_bounds__(T) void stream_solve_kernel(const double2* __restri
 }
 
 template <int T, int C, int BD>
-hipError_t launch_tc(const ze_ctx* c, const double2* W, double2* P, hipStream_t s) {
+hipError_t launch_tc(const ze_ctx* c, const double2* W, double2* P, hipStream_t s, const int* skip) {
     const int N = c->N;
     static_assert(T % BD == 0, "lanes");
     const int nwg = solve_bands(N, BD);
     const int per = (nwg + 7) / 8;
     hipLaunchKernelGGL((stream_solve_kernel<T, C, BD>), dim3(8 * per), dim3(T), 0, s, W, P,
-                       c->fac_l, c->fac_dinv, N, nwg, per);
+                       c->fac_l, c->fac_dinv, N, nwg, per, skip);
     return hipGetLastError();
 }
 
@@ -125,21 +127,22 @@ void ze_build_factors(int N, int bd, std::vector<double>& fl, std::vector<double
 
 // The (threads, rows per chunk) shape for N and the context's band width:
 // (T / BD) C >= N + BD, C <= 17.
-hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s) {
+hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hipStream_t s,
+                               const int* skip) {
     const int N = c->N;
     if (c->solve_bd == 4) {
-        if (N <= 76) return launch_tc<64, 5, 4>(c, W, P, s);
-        if (N <= 156) return launch_tc<128, 5, 4>(c, W, P, s);
-        if (N <= 316) return launch_tc<256, 5, 4>(c, W, P, s);
-        if (N <= 572) return launch_tc<256, 9, 4>(c, W, P, s);
-        if (N <= 1084) return launch_tc<256, 17, 4>(c, W, P, s);
-        if (N <= 2172) return launch_tc<512, 17, 4>(c, W, P, s);
+        if (N <= 76) return launch_tc<64, 5, 4>(c, W, P, s, skip);
+        if (N <= 156) return launch_tc<128, 5, 4>(c, W, P, s, skip);
+        if (N <= 316) return launch_tc<256, 5, 4>(c, W, P, s, skip);
+        if (N <= 572) return launch_tc<256, 9, 4>(c, W, P, s, skip);
+        if (N <= 1084) return launch_tc<256, 17, 4>(c, W, P, s, skip);
+        if (N <= 2172) return launch_tc<512, 17, 4>(c, W, P, s, skip);
         return hipErrorInvalidValue;  // band width 4 is only chosen up to N = 2172
     }
     if (c->solve_bd == 2) {
-        if (N <= 4606) return launch_tc<1024, 9, 2>(c, W, P, s);
+        if (N <= 4606) return launch_tc<1024, 9, 2>(c, W, P, s, skip);
         return hipErrorInvalidValue;  // band width 2 is only chosen up to N = 4606
     }
-    if (N <= 9215) return launch_tc<1024, 9, 1>(c, W, P, s);
-    return launch_tc<1024, 17, 1>(c, W, P, s);
+    if (N <= 9215) return launch_tc<1024, 9, 1>(c, W, P, s, skip);
+    return launch_tc<1024, 17, 1>(c, W, P, s, skip);
 }

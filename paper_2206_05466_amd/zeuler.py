@@ -44,6 +44,8 @@ SIGNATURES = {
     "ze_set_update_form": (_c_int, [_vp, _c_int]),
     "ze_set_validation": (_c_int, [_vp, _c_int]),
     "ze_set_order": (_c_int, [_vp, _c_int]),
+    "ze_set_stopping": (_c_int, [_vp, _c_int]),
+    "ze_run_stats": (_c_int, [_vp, _c_int, _P_int, _P_double]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
     "ze_ensemble_create": (_c_int, [_c_int, _P_int, _vp, ctypes.POINTER(_vp)]),
@@ -204,6 +206,28 @@ class Zeuler:
         if st not in (ZE_OK, ZE_ENOTCONV):
             _check(st, "ze_isomp_run", detail=True)
         return list(its)[:nsteps], list(res)[:nsteps]
+
+    def isomp_run_async(self, W, h: float, nsteps: int, tol: float = 1e-12, maxit: int = 50,
+                        prec: int = PREC_FP64):
+        """nsteps steps with no per-step results and (with set_stopping(1)) no synchronisation:
+        the form that can be captured into a graph; run_stats() reads the counts afterwards."""
+        _check(self.lib.ze_isomp_run(self._ctx, self._mat(W, "W"), float(h), float(tol), int(maxit),
+                                     int(nsteps), int(prec), None, None), "ze_isomp_run", detail=True)
+
+    def set_stopping(self, mode: int):
+        """0: tolerance test on the host after each evaluation; 1: on the device (no
+        synchronisation per evaluation; FP64 products)."""
+        _check(self.lib.ze_set_stopping(self._ctx, int(mode)), "ze_set_stopping")
+
+    def run_stats(self, nsteps: int):
+        """(iterations, residuals, status) of the last nsteps steps of the last run (on-device
+        stopping); synchronises the context's stream."""
+        its = (ctypes.c_int * max(nsteps, 1))()
+        res = (ctypes.c_double * max(nsteps, 1))()
+        st = self.lib.ze_run_stats(self._ctx, int(nsteps), its, res)
+        if st not in (ZE_OK, ZE_ENOTCONV, ZE_ENONFINITE):
+            _check(st, "ze_run_stats", detail=True)
+        return list(its)[:nsteps], list(res)[:nsteps], st
 
     def casimirs(self, W, kmax: int) -> np.ndarray:
         """[Tr W, Tr W^2, ..., Tr W^kmax] (complex128 numpy array)."""

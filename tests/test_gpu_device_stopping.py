@@ -1,0 +1,133 @@
+"""On-device stopping rule (ze_set_stopping 1): the tolerance test of eq. (isomp_iter) taken on
+the GPU, every evaluation up to maxit enqueued and skipped once the step has converged.
+
+The kernels and their order are those of the host-tested loop, so the results are compared
+with it bit for bit (W, evaluation counts, residuals), and with the oracle at the FP64 bar.
+A run captured into a HIP graph is replayed several times, with eager work and
+synchronisations between the replays, each replay checked against an eager run on a second
+context.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import WORKLOADS, omega_coeffs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_05466_amd import load_library
+
+    load_library()
+    return torch.device("cuda", 0)
+
+
+def field(N, seed=0, law="inv1"):
+    return O.assemble(N, omega_coeffs(N, seed, law))
+
+
+def run(z, W0, h, steps, tol, maxit, mode, guess, form, order=2):
+    z.set_stopping(mode)
+    z.set_initial_guess(guess)
+    z.set_update_form(form)
+    z.set_order(order)
+    W = torch.from_numpy(W0).cuda()
+    its, res = z.isomp_run(W, h, steps, tol, maxit)
+    torch.cuda.synchronize()
+    return W.cpu().numpy(), its, res
+
+
+@pytest.mark.parametrize("N,guess,form", [(64, 0, 0), (64, 2, 1), (129, 1, 0), (512, 2, 1)])
+def test_device_stopping_bit_identical_to_host_loop(dev, N, guess, form):
+    from paper_2206_05466_amd import Zeuler
+
+    h, tol, maxit, steps = 0.01, 1e-12, 6, 8
+    W0 = field(N)
+    with Zeuler(N) as z:
+        Wh, ith, rh = run(z, W0, h, steps, tol, maxit, 0, guess, form)
+        Wd, itd, rd = run(z, W0, h, steps, tol, maxit, 1, guess, form)
+    assert itd == ith and rd == rh
+    assert np.array_equal(Wd, Wh)
+    if N == 64:
+        Wr, itr, _ = O.isomp_run(W0, h, steps, tol, maxit, extrapolate=guess > 0,
+                                 degree=3 if guess == 2 else 1,
+                                 update="difference" if form == 1 else "second_line")
+        assert itd == itr
+        assert np.linalg.norm(Wd - Wr) / np.linalg.norm(Wr) < 1e-12
+
+
+def test_device_stopping_fixed_count_and_order4(dev):
+    """tol = 0 runs exactly maxit evaluations and reports non-convergence; the order-4
+    composition (three substeps per step) matches the host loop bit for bit."""
+    from paper_2206_05466_amd import Zeuler
+    from paper_2206_05466_amd.zeuler import ZE_ENOTCONV
+
+    N, h = 96, 0.02
+    W0 = field(N, 3)
+    with Zeuler(N) as z:
+        # the host loop stops a run at its first unconverged step: step it one call at a time
+        z.set_stopping(0)
+        Wt = torch.from_numpy(W0).cuda()
+        infos = [z.isomp_step(Wt, h, 0.0, 3) for _ in range(3)]
+        torch.cuda.synchronize()
+        Wh = Wt.cpu().numpy()
+        assert all(i.iters == 3 and not i.converged for i in infos)
+        Wd, itd, rd = run(z, W0, h, 3, 0.0, 3, 1, 0, 0)
+        assert itd == [3, 3, 3] and rd == [i.resid for i in infos] and np.array_equal(Wd, Wh)
+        _, _, st = z.run_stats(3)
+        assert st == ZE_ENOTCONV
+        Wh, ith, rh = run(z, W0, h, 4, 1e-12, 6, 0, 2, 1, order=4)
+        Wd, itd, rd = run(z, W0, h, 4, 1e-12, 6, 1, 2, 1, order=4)
+    assert itd == ith and rd == rh and np.array_equal(Wd, Wh)
+
+
+def test_device_stopping_graph_capture_replays(dev):
+    """A 6-step run (polynomial start, difference form) captured into a graph on the context's
+    stream and replayed three times; after each replay W and the run's counts equal those of
+    an eager 6-step run from the same state on a second context."""
+    from paper_2206_05466_amd import Zeuler
+
+    cfg = WORKLOADS["n512"]
+    N, h, tol, maxit, steps = 256, cfg["h"], 1e-12, 5, 6
+    W0 = field(N, 1)
+    s = torch.cuda.Stream()
+    zg = Zeuler(N, stream=s)
+    ze = Zeuler(N)
+    for z in (zg, ze):
+        z.set_stopping(1)
+        z.set_initial_guess(2)
+        z.set_update_form(1)
+    Wg = torch.from_numpy(W0).cuda()
+    We = Wg.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        zg.isomp_run_async(Wg, h, steps, tol, maxit)
+    torch.cuda.synchronize()
+    assert torch.equal(Wg, We)  # capture records, it does not run
+    for rep in range(3):
+        g.replay()  # on the current stream
+        torch.cuda.synchronize()
+        its_g, res_g, st_g = zg.run_stats(steps)
+        its_e, res_e = ze.isomp_run(We, h, steps, tol, maxit)
+        torch.cuda.synchronize()
+        assert its_g == its_e and res_g == res_e and st_g == 0, (rep, its_g, its_e)
+        assert torch.equal(Wg, We), rep
+        # eager work between the replays
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+    Wr = W0
+    for _ in range(3):
+        Wr, _, _ = O.isomp_run(Wr, h, steps, tol, maxit, extrapolate=True, degree=3, update="difference")
+    got = Wg.cpu().numpy()
+    assert np.linalg.norm(got - Wr) / np.linalg.norm(Wr) < 1e-12
+    zg.close()
+    ze.close()
