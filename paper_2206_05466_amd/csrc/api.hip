@@ -10,6 +10,7 @@
 
 #include "internal.h"
 #include "solve_wg.h"
+#include "update_tile.h"
 
 namespace {
 
@@ -218,7 +219,8 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     std::vector<double> fl, fd;
     ze_build_factors(N, c->solve_bd, fl, fd);
     const size_t nn = (size_t)N * N;
-    const int T = (N + 63) / 64;
+    c->ut = zk::update_tile_of(N);
+    const int T = (N + c->ut - 1) / c->ut;
     {
         hipError_t ce = ze_gemm_capacity(&c->cap_full, &c->cap_low);
         if (ce != hipSuccess) {
@@ -246,7 +248,13 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     if (st == ZE_OK && (hipMemset(c->dctl, 0, kCtlWords * sizeof(int)) != hipSuccess ||
                         hipMemset(c->dctld, 0, 2 * sizeof(double)) != hipSuccess))
         st = ze_record_hip(hipGetLastError(), "control words clear");
-    if (st == ZE_OK && hipHostMalloc(reinterpret_cast<void**>(&c->host_resid), sizeof(double)) != hipSuccess) {
+    // the residual kernel writes the infinity norm straight into this pinned, mapped host word
+    if (st == ZE_OK &&
+        (hipHostMalloc(reinterpret_cast<void**>(&c->host_resid), sizeof(double),
+                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+         hipHostGetDevicePointer(reinterpret_cast<void**>(&c->host_resid_dev), c->host_resid, 0) !=
+             hipSuccess)) {
+        if (c->host_resid) (void)hipHostFree(c->host_resid);
         c->host_resid = nullptr;
         (void)hipGetLastError();
         st = ZE_ENOMEM;
@@ -394,10 +402,10 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
                                        nullptr, s));
         }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
-        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax,
-                                   reinterpret_cast<unsigned*>(c->dctl + kCtlCounter), c->resid, N, s));
+        ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax,
+                                   reinterpret_cast<unsigned*>(c->dctl + kCtlCounter), c->resid, N, s,
+                                   nullptr, nullptr, 0.0, c->host_resid_dev));
         if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
-        ZE_HIP(hipMemcpyAsync(c->host_resid, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
         ZE_HIP(hipStreamSynchronize(s));
         if (prof) {
             for (int p = 0; p < 4; ++p) {
@@ -442,8 +450,8 @@ ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit,
         ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s, skip));
         ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
                                    nullptr, s, skip));
-        ZE_HIP(launch_resid_reduce(c->rowpart, c->blockmax, counter, c->resid, N, s, skip, c->dctl,
-                                   tol));
+        ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax, counter,
+                                   c->resid, N, s, skip, c->dctl, tol));
         Wt = c->F;
     }
     ZE_HIP(launch_ctl_substep_end(c->dctl, c->dctld, c->resid, tol, last, c->dstep_it, c->dstep_r, s));

@@ -181,7 +181,8 @@ __global__ __launch_bounds__(kThreads) void zgemm_lower_fixup(double2* __restric
 // ---------------------------------------------------------------- residual reduction
 constexpr int kRedThreads = 256;
 
-// resid = max_r sum_X rowpart[X N + r] (NaN propagates) in one launch: each block takes the
+// resid = max_r sum_X rowpart[X N + r] (NaN propagates; also to host_out if given, a mapped
+// host word) in one launch: each block takes the
 // row sums of 256 rows and stores their maximum; the last block to finish (a counter, reset
 // by that block) takes the maximum over the blocks.  With ctl (on-device stopping) that block
 // also counts the evaluation (ctl[1]) and sets the step's done flag ctl[0] when resid < tol or
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(kRedThreads) void resid_kernel(const double* __rest
                                                             int T, int N, double* blockmax,
                                                             unsigned* counter, double* resid,
                                                             const int* __restrict__ skip, int* ctl,
-                                                            double tol) {
+                                                            double tol, double* host_out) {
     __shared__ double sm[kRedThreads];
     __shared__ bool last;
     if (skip && *skip) return;
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(kRedThreads) void resid_kernel(const double* __rest
     if (threadIdx.x == 0) {
         const double r = sm[0];
         resid[0] = r;
+        if (host_out) __hip_atomic_store(host_out, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         *counter = 0u;
         if (ctl) {
             ctl[1] += 1;
@@ -360,12 +362,11 @@ hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* 
     return hipGetLastError();
 }
 
-hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, unsigned* counter,
+hipError_t launch_resid_reduce(const double* rowpart, int T, double* blockmax, unsigned* counter,
                                double* resid, int N, hipStream_t s, const int* skip, int* ctl,
-                               double tol) {
-    const int T = (N + kTile - 1) / kTile;
+                               double tol, double* host_out) {
     const int G = (N + kRedThreads - 1) / kRedThreads;
     hipLaunchKernelGGL(resid_kernel, dim3(G), dim3(kRedThreads), 0, s, rowpart, T, N, blockmax,
-                       counter, resid, skip, ctl, tol);
+                       counter, resid, skip, ctl, tol, host_out);
     return hipGetLastError();
 }

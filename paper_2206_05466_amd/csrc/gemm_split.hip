@@ -275,19 +275,20 @@ __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __re
 }
 
 // ---------------------------------------------------------------- fixed-point update
+template <int UT>
 __global__ __launch_bounds__(kThreads) void lower_update_kernel(
     const double2* __restrict__ Qf, const int* __restrict__ G, const int* __restrict__ ea,
     const int* __restrict__ eb, int s, const double2* __restrict__ Am,
     const double2* __restrict__ Wn, const double2* Wt, double2* F, double2* __restrict__ Wout,
     double* __restrict__ rowpart, int N, double h, int form, const int* __restrict__ skip) {
-    __shared__ double2 sT[kUT][kUT + 1];
+    __shared__ double2 sT[UT][UT + 1];
     if (skip && *skip) return;  // on-device stopping: the step has converged
     const int b = blockIdx.x;
     int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= b) ++I;
     while (I * (I + 1) / 2 > b) --I;
     const int J = b - I * (I + 1) / 2;
-    lower_update_tile(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
+    lower_update_tile_t<UT>(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
 }
 
 }  // namespace
@@ -446,10 +447,10 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
                                const double2* Wn, const double2* Wt, double2* F, double2* Wout,
                                double* rowpart, double h, const int* ea, const int* eb,
                                hipStream_t st, const int* skip) {
-    const int N = c->N;
-    const int T = (N + kUT - 1) / kUT;
-    hipLaunchKernelGGL(lower_update_kernel, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q,
-                       c->split_g, ea, eb, slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h,
-                       c->update_form, skip);
+    const int N = c->N, ut = c->ut;
+    const int T = (N + ut - 1) / ut;
+    auto kern = ut == 64 ? lower_update_kernel<64> : (ut == 32 ? lower_update_kernel<32> : lower_update_kernel<16>);
+    hipLaunchKernelGGL(kern, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q, c->split_g, ea, eb,
+                       slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h, c->update_form, skip);
     return hipGetLastError();
 }

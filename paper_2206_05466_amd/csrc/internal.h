@@ -46,10 +46,12 @@ struct ze_ctx {
     double2* P = nullptr;    // stream matrix
     double2* A = nullptr;    // A = P W~
     double2* Q = nullptr;    // lower product Q = A P (FP64 path)
-    double* rowpart = nullptr;  // ntile64 x N partial row sums of |F - W~|
+    int ut = 64;                // tile of the fixed-point update (update_tile_of(N))
+    double* rowpart = nullptr;  // ceil(N / ut) x N partial row sums of |F - W~|
     double* blockmax = nullptr; // per-block maxima of the row sums
     double* resid = nullptr;    // device scalar: infinity norm of F - W~
-    double* host_resid = nullptr;  // pinned host copy
+    double* host_resid = nullptr;      // pinned, mapped host word of the residual
+    double* host_resid_dev = nullptr;  // its device address
 
     // Products: concurrent-block capacities and the split-K partial buffer.
     int cap_full = 0, cap_low = 0;
@@ -195,12 +197,13 @@ hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, d
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
                               hipStream_t s, const int* skip = nullptr);
 
-// resid = max_r sum_X rowpart[X*N + r]  (NaN propagates), one launch (counter: a zeroed device
-// word the launch leaves zeroed).  With ctl: ctl[1] += 1 and ctl[0] = 1 once resid < tol or is
+// resid = max_r sum_{X < T} rowpart[X*N + r]  (NaN propagates), one launch (counter: a zeroed device
+// word the launch leaves zeroed), also stored to host_out (device address of mapped host
+// memory) if given.  With ctl: ctl[1] += 1 and ctl[0] = 1 once resid < tol or is
 // not finite; skip as for the products.
-hipError_t launch_resid_reduce(const double* rowpart, double* blockmax, unsigned* counter,
+hipError_t launch_resid_reduce(const double* rowpart, int T, double* blockmax, unsigned* counter,
                                double* resid, int N, hipStream_t s, const int* skip = nullptr,
-                               int* ctl = nullptr, double tol = 0.0);
+                               int* ctl = nullptr, double tol = 0.0, double* host_out = nullptr);
 
 // out[0] = sum_ij X_ij Y_ji (complex), through `partial` (>= ze_trace_partials(N) doubles2).
 int ze_trace_partials(int N);

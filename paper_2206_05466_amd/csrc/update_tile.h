@@ -7,7 +7,8 @@
 namespace zk {
 
 // ---------------------------------------------------------------- fixed-point update
-// For tile (I, J), I >= J, of 64 x 64 complex entries, from Q (lower tiles valid):
+// For tile (I, J), I >= J, of UT x UT complex entries (UT = 64, 32 or 16: smaller tiles give a
+// small N enough blocks), from Q (lower tiles valid):
 //   F = Wn + h/2 (A - A^H) + h^2/4 Q   (Re Q_RR := 0),
 //   Wout = Wt + h/2 (A - A^H) - h^2/4 Q   (form 0: the second line of eq. (isomp) at Wt), or
 //   Wout = Wn + h (A - A^H)               (form 1: the two lines differ by h [P~, W~]; at a
@@ -19,36 +20,39 @@ namespace zk {
 // entries to slots (J, rows of I) and their column sums (the mirrored upper entries, which
 // lie in the rows of J) to slots (I, rows of J); a diagonal tile writes the full row sums of
 // its rows to (I, rows of I).  Every slot with r < N is written once (deterministic sums).
-constexpr int kUT = 64;
+constexpr int kUT = 64;  // the tile of the ensemble kernels (and of the single context from N = 2048)
 constexpr int kUThreads = 256;
 // Q comes from the FP64 lower product (Qf != nullptr, complex N x N, lower tiles) or from the
 // int32 slabs of the split lower product (G, ea, eb, s).
-__device__ __forceinline__ void lower_update_tile(int I, int J, const double2* __restrict__ Qf,
+template <int UT>
+__device__ __forceinline__ void lower_update_tile_t(int I, int J, const double2* __restrict__ Qf,
                                          const int* __restrict__ G, const int* __restrict__ ea,
                                          const int* __restrict__ eb, int s,
                                          const double2* __restrict__ Am,
                                          const double2* __restrict__ Wn, const double2* Wt,
                                          double2* F, double2* __restrict__ Wout,
                                          double* __restrict__ rowpart, int N, double h, int form,
-                                         double2 (*sT)[kUT + 1]) {
-    double(*sD)[kUT + 1] = reinterpret_cast<double(*)[kUT + 1]>(&sT[0][0]);  // reused at the end
-    const int R0 = I * kUT, C0 = J * kUT;
+                                         double2 (*sT)[UT + 1]) {
+    static_assert(kUThreads % UT == 0 && 2 * UT <= kUThreads, "tile");
+    constexpr int RP = kUThreads / UT;  // rows per pass; each thread takes UT / RP of them
+    double(*sD)[UT + 1] = reinterpret_cast<double(*)[UT + 1]>(&sT[0][0]);  // reused at the end
+    const int R0 = I * UT, C0 = J * UT;
     const int tid = threadIdx.x;
-    const int lc = tid & 63, lr0 = tid >> 6;  // 4 rows per pass, 64 consecutive columns
+    const int lc = tid % UT, lr0 = tid / UT;  // RP rows per pass, UT consecutive columns
     const double h2 = 0.5 * h, h4 = 0.25 * h * h;
 
     // A^T tile: sT[c][R] = A[C0 + c][R0 + R].
-    for (int rr = lr0; rr < kUT; rr += 4) {
+    for (int rr = lr0; rr < UT; rr += RP) {
         const int gr = C0 + rr, gc = R0 + lc;
         sT[rr][lc] = (gr < N && gc < N) ? Am[(size_t)gr * N + gc] : make_double2(0.0, 0.0);
     }
     __syncthreads();
 
-    double2 fv[kUT / 4], wv[kUT / 4];
-    double dv[kUT / 4];
+    double2 fv[UT / RP], wv[UT / RP];
+    double dv[UT / RP];
 #pragma unroll
-    for (int x = 0; x < kUT / 4; ++x) {
-        const int r = lr0 + 4 * x, R = R0 + r, c = C0 + lc;
+    for (int x = 0; x < UT / RP; ++x) {
+        const int r = lr0 + RP * x, R = R0 + r, c = C0 + lc;
         const bool ok = R < N && c < N && c <= R;
         double2 f = make_double2(0.0, 0.0), wo = f, d = f;
         if (ok) {
@@ -86,40 +90,62 @@ __device__ __forceinline__ void lower_update_tile(int I, int J, const double2* _
     // Upper entries: F[c][R] = -conj(F[R][c]) for c < R, via sT.
     for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-        for (int x = 0; x < kUT / 4; ++x) {
-            const int r = lr0 + 4 * x;
+        for (int x = 0; x < UT / RP; ++x) {
+            const int r = lr0 + RP * x;
             const double2 v = pass == 0 ? fv[x] : wv[x];
             sT[lc][r] = make_double2(-v.x, v.y);
         }
         __syncthreads();
         double2* out = pass == 0 ? F : Wout;
-        for (int cr = lr0; cr < kUT; cr += 4) {  // row C0 + cr of the upper tile, columns R0 + lc
+        for (int cr = lr0; cr < UT; cr += RP) {  // row C0 + cr of the upper tile, columns R0 + lc
             const int gc = C0 + cr, gR = R0 + lc;
             if (gc < N && gR < N && gc < gR) out[(size_t)gc * N + gR] = sT[cr][lc];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int x = 0; x < kUT / 4; ++x) sD[lr0 + 4 * x][lc] = dv[x];
+    for (int x = 0; x < UT / RP; ++x) sD[lr0 + RP * x][lc] = dv[x];
     __syncthreads();
     if (I != J) {
-        if (tid < kUT) {
+        if (tid < UT) {
             double sum = 0.0;
-            for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
+            for (int k = 0; k < UT; ++k) sum += sD[tid][k];
             if (R0 + tid < N) rowpart[(size_t)J * N + R0 + tid] = sum;
-        } else if (tid < 2 * kUT) {
-            const int j = tid - kUT;
+        } else if (tid < 2 * UT) {
+            const int j = tid - UT;
             double sum = 0.0;
-            for (int k = 0; k < kUT; ++k) sum += sD[k][j];
+            for (int k = 0; k < UT; ++k) sum += sD[k][j];
             if (C0 + j < N) rowpart[(size_t)I * N + C0 + j] = sum;
         }
-    } else if (tid < kUT) {
+    } else if (tid < UT) {
         double sum = 0.0;
-        for (int k = 0; k < kUT; ++k) sum += sD[tid][k];
-        for (int k = tid + 1; k < kUT; ++k) sum += sD[k][tid];
+        for (int k = 0; k < UT; ++k) sum += sD[tid][k];
+        for (int k = tid + 1; k < UT; ++k) sum += sD[k][tid];
         if (R0 + tid < N) rowpart[(size_t)I * N + R0 + tid] = sum;
     }
 }
 
+
+// The 64 x 64 form (ensemble kernels).
+__device__ __forceinline__ void lower_update_tile(int I, int J, const double2* __restrict__ Qf,
+                                         const int* __restrict__ G, const int* __restrict__ ea,
+                                         const int* __restrict__ eb, int s,
+                                         const double2* __restrict__ Am,
+                                         const double2* __restrict__ Wn, const double2* Wt,
+                                         double2* F, double2* __restrict__ Wout,
+                                         double* __restrict__ rowpart, int N, double h, int form,
+                                         double2 (*sT)[kUT + 1]) {
+    lower_update_tile_t<kUT>(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
+}
+
+// Update tile of a single context of size N: the largest of 64, 32, 16 whose lower tiles
+// number at least 512 (two rounds of one block per CU), else 16.
+__host__ __device__ inline int update_tile_of(int N) {
+    for (int ut = 64; ut > 16; ut /= 2) {
+        const long long t = (N + ut - 1) / ut;
+        if (t * (t + 1) / 2 >= 512) return ut;
+    }
+    return 16;
+}
 
 }  // namespace zk
