@@ -28,14 +28,15 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
 
-# HBM bytes per launch of zgemm_f64_kernel (A = P W~) at N = 4096, from two rocprofv3 --pmc
-# passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors read off a plain 1 GiB device
-# copy in the same runs).  Valid only for the kernel sources the counters were taken on.
+# Memory bytes per launch of zgemm_f64_kernel (A = P W~) at N = 4096, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+# reads for a plain copy of known size in the same runs (torch's clone of the 256 MiB W_0:
+# 1.00 both ways).  Valid only for the kernel sources the counters were taken on.
 MEASURED_TRAFFIC = {"N": 4096,
                     "sources": ["paper_2206_05466_amd/csrc/gemm_f64.hip",
                                 "paper_2206_05466_amd/csrc/tile_f64.h"],
-                    "sha256_16": "e07a8ca6605db613",
-                    "bytes": (1572337.5 * 2.00 + 262144.0 * 1.00) * 1024}
+                    "sha256_16": "bdc4f9d0528d36b3",
+                    "bytes": (2567745.3 * 1.00 + 262144.0 * 1.00) * 1024}
 
 
 def sources_hash(paths):
