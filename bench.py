@@ -169,6 +169,7 @@ def ensemble_leg(nsteps, prec, ref=None, with_cpu=False):
     ens = Ensemble(sizes)
     ens.set_initial_guess(2)  # polynomial start from the run's midpoints (reading 9)
     ens.set_update_form(1)    # W_{n+1} = W_n + h (A - A^H) (reading 12)
+    ens.set_steady_cap(cfg["steady_cap"], cfg["steady_from"])
     if split:
         ens.set_split_slices(slices)
         for z in ctxs.values():
@@ -216,6 +217,7 @@ def ensemble_leg(nsteps, prec, ref=None, with_cpu=False):
         "start_step_iters": {"min": min(its0), "max": max(its0)},
         "start_step_max_resid": max(res0),
         "evaluation_cap": K,
+        "steady_cap": {"cap": cfg["steady_cap"], "from_step": cfg["steady_from"]},
         "fp64_equiv_tflops": 12.0 * n3 * len(sizes) * sum(its) / len(its) / (dt / nsteps) / 1e12,
         "autotune": {"choice": choice, "ms_per_step": tune_ms, "candidates": cands},
         "sequential_single_context_steps_per_s": len(sizes) * seq_steps / dts,

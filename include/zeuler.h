@@ -430,6 +430,18 @@ ze_status ze_ensemble_set_update_form(ze_ens* ens, int form);
  */
 ze_status ze_ensemble_set_initial_guess(ze_ens* ens, int mode);
 
+/*
+ * ze_ensemble_set_steady_cap -- evaluation cap of the steps with index >= from_step in a
+ * ze_ensemble_run call, with the polynomial start (mode 2 of ze_ensemble_set_initial_guess):
+ * min(K, cap) instead of K, captured as a second step graph (cap 0, the default: K for every
+ * step).  Once the polynomial start has reached degree 3 (from the fifth step of a call) a step
+ * needs one evaluation at these workloads, and every capped evaluation a step does not need
+ * still costs its launches (they return at once), so a small cap saves them; a step that would
+ * need more stops at the cap with its residual reported by ze_ensemble_stats (the fixed-count
+ * mode of Sec. 3.4).  Takes effect at the next ze_ensemble_run.  Errors: ZE_EINVAL.
+ */
+ze_status ze_ensemble_set_steady_cap(ze_ens* ens, int cap, int from_step);
+
 #ifdef __cplusplus
 }
 #endif

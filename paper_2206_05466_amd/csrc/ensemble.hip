@@ -29,8 +29,13 @@ using namespace zk;
 struct EnsProb {
     int N;
     int pad;
-    double2* W;  // caller's matrix (in: W_n, out: W_{n+1})
+    // W_n of the step and where its W_{n+1} goes: the caller's matrix Wc and the scratch
+    // matrix X take turns (set at the start of a run; swapped at the end of each step, so no
+    // step copies W_n; the run's last W_{n+1} is copied to Wc if it ended in X)
+    double2* W;
     double2* Wn;
+    double2* Wc;
+    double2* X;
     double2* F;
     double2* P;
     double2* A;
@@ -55,7 +60,8 @@ struct EnsProb {
 
 constexpr int kCopyParts = 16;
 
-// Start of a step: W_n <- W and the first iterate F.  mode 0: F <- W_n; mode 1: F <- 2 W_n - F,
+// Start of a step: the first iterate F (W_n is read where the previous step left it, Wn).
+// mode 0: F <- W_n; mode 1: F <- 2 W_n - F,
 // the linear extrapolation of the previous step's converged midpoint (still in F); mode 2: by
 // the step's index n in the run (*stepc): W_n at n = 0, 2 W_n - H1 at n = 1, else the
 // polynomial of degree d = min(n - 1, 3) through the midpoints H1 (newest), H2, H3 and F (the
@@ -79,8 +85,7 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
     const double c2 = d == 1 ? -1.0 : (d == 2 ? -3.0 : -6.0);
     const double c3 = d == 2 ? 1.0 : 4.0;
     for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
-        const double2 w = p.W[e];
-        p.Wn[e] = w;
+        const double2 w = p.Wn[e];
         if (n == 0) {
             p.F[e] = w;
             continue;
@@ -111,19 +116,45 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
 }
 
 // Step index of mode 2: set before the first step of a run (set >= 0), or advanced at the end
-// of each step (set < 0), when each simulation's midpoint ring also turns (see ens_begin_kernel).
+// of each step (set < 0), when each simulation's W_n and W_{n+1} buffers swap and, with ring,
+// its midpoint ring also turns (see ens_begin_kernel).
 __global__ __launch_bounds__(64) void ens_stepc_kernel(int* __restrict__ stepc, int set,
-                                                       EnsProb* __restrict__ probs, int nsim) {
+                                                       EnsProb* __restrict__ probs, int nsim,
+                                                       int ring) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (set < 0 && i < nsim) {
         EnsProb& p = probs[i];
-        double2* oldest = p.H3;
-        p.H3 = p.H2;
-        p.H2 = p.H1;
-        p.H1 = p.F;
-        p.F = oldest;
+        double2* w = p.W;
+        p.W = p.Wn;
+        p.Wn = w;
+        if (ring) {
+            double2* oldest = p.H3;
+            p.H3 = p.H2;
+            p.H2 = p.H1;
+            p.H1 = p.F;
+            p.F = oldest;
+        }
     }
     if (i == 0) stepc[0] = set >= 0 ? set : stepc[0] + 1;
+}
+
+// Start of a run: W_n in the caller's matrix, W_{n+1} to the scratch one.
+__global__ __launch_bounds__(64) void ens_run_begin_kernel(EnsProb* __restrict__ probs, int nsim) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < nsim) {
+        probs[i].Wn = probs[i].Wc;
+        probs[i].W = probs[i].X;
+    }
+}
+
+// End of a run: the last W_{n+1} (now in Wn) copied to the caller's matrix if it is in X.
+__global__ __launch_bounds__(256) void ens_run_end_kernel(const EnsProb* __restrict__ probs) {
+    const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
+    const EnsProb p = probs[sim];
+    if (p.Wn == p.Wc) return;
+    const size_t n2 = (size_t)p.N * p.N;
+    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256)
+        p.Wc[e] = p.Wn[e];
 }
 
 template <int T, int C, int BD>
@@ -415,6 +446,10 @@ struct ze_ens {
     int g_form = -1;
     hipGraphExec_t exec_x = nullptr;  // the step graph with the extrapolated first iterate
     double g_h = 0.0, g_tol = -1.0;
+    // evaluation cap of the steps from index cap2_after on (guess mode 2; 0: the run's cap K)
+    // and the step graph captured with it
+    int cap2 = 0, cap2_after = 0, g_cap2 = -1;
+    hipGraphExec_t exec_s = nullptr;
 };
 
 namespace {
@@ -466,9 +501,9 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
                       e->resid, k, tol);
     }
-    if (err == hipSuccess && mode == 2)
+    if (err == hipSuccess)
         ZE_ENS_LAUNCH(ens_stepc_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, s, e->stepc, -1,
-                      e->dp, e->nsim);
+                      e->dp, e->nsim, mode == 2 ? 1 : 0);
 #undef ZE_ENS_LAUNCH
     return err;
 }
@@ -497,6 +532,12 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         capture_one(e, h, tol, K, prec, variant, order, e->guess_mode == 2 ? 2 : 0, &e->exec);
     if (err == hipSuccess && e->guess_mode == 1)
         err = capture_one(e, h, tol, K, prec, variant, order, 1, &e->exec_x);
+    if (e->exec_s) {
+        (void)hipGraphExecDestroy(e->exec_s);
+        e->exec_s = nullptr;
+    }
+    if (err == hipSuccess && e->guess_mode == 2 && e->cap2 > 0 && e->cap2 < K)
+        err = capture_one(e, h, tol, e->cap2, prec, variant, order, 2, &e->exec_s);
     if (err == hipSuccess) {
         e->g_guess = e->guess_mode;
         e->g_prec = prec;
@@ -508,6 +549,7 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         e->g_form = e->update_form;
         e->g_h = h;
         e->g_tol = tol;
+        e->g_cap2 = e->cap2;
     }
     return err;
 }
@@ -532,8 +574,8 @@ ze_status set_pointers(ze_ens* e, void* const* W) {
     bool changed = false;
     for (int i = 0; i < e->nsim; ++i) {
         if (!W[i]) return ZE_EINVAL;
-        if (e->hp[i].W != W[i]) {
-            e->hp[i].W = static_cast<double2*>(W[i]);
+        if (e->hp[i].Wc != W[i]) {
+            e->hp[i].Wc = static_cast<double2*>(W[i]);
             changed = true;
         }
     }
@@ -568,7 +610,10 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
             break;
         }
         float ms = 0.f;
-        hipError_t err = hipGraphLaunch(e->exec, e->own);  // warm-up
+        hipLaunchKernelGGL(ens_run_begin_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, e->own,
+                           e->dp, e->nsim);
+        hipError_t err = hipGetLastError();
+        if (err == hipSuccess) err = hipGraphLaunch(e->exec, e->own);  // warm-up
         if (err == hipSuccess) err = hipEventRecord(e->t0, e->own);
         for (int r = 0; r < 3 && err == hipSuccess; ++r) err = hipGraphLaunch(e->exec, e->own);
         if (err == hipSuccess) err = hipEventRecord(e->t1, e->own);
@@ -593,7 +638,7 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
     for (double2* c : copies)
         if (c) (void)hipFree(c);
     // restore the caller's pointers (set_pointers compares against hp)
-    for (int i = 0; i < e->nsim; ++i) e->hp[i].W = nullptr;
+    for (int i = 0; i < e->nsim; ++i) e->hp[i].Wc = nullptr;
     if (e->exec) {
         (void)hipGraphExecDestroy(e->exec);
         e->exec = nullptr;
@@ -601,6 +646,10 @@ ze_status autotune(ze_ens* e, void* const* W, double h, double tol, int K, int p
     if (e->exec_x) {
         (void)hipGraphExecDestroy(e->exec_x);
         e->exec_x = nullptr;
+    }
+    if (e->exec_s) {
+        (void)hipGraphExecDestroy(e->exec_s);
+        e->exec_s = nullptr;
     }
     return st;
 }
@@ -633,6 +682,7 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
     if (e->own) (void)hipStreamSynchronize(e->own);
     if (e->exec) (void)hipGraphExecDestroy(e->exec);
     if (e->exec_x) (void)hipGraphExecDestroy(e->exec_x);
+    if (e->exec_s) (void)hipGraphExecDestroy(e->exec_s);
     for (ze_ctx* c : e->ctx) ze_destroy(c);
     (void)hipFree(e->dp);
     (void)hipFree(e->done);
@@ -681,9 +731,10 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         st = ze_create_ctx(e->N[i], e->own, false, ens_bd(e->maxN), &e->ctx[i]);
         if (st != ZE_OK) return fail(st);
         ze_ctx* c = e->ctx[i];
-        e->hp[i] = EnsProb{c->N,        0,          nullptr, c->Wn,   c->F,    c->P,    c->A,
-                           c->Q,        c->rowpart, c->fac_l, c->fac_dinv, nullptr, nullptr, nullptr,
-                           nullptr,     nullptr,    nullptr, nullptr, nullptr, nullptr};
+        e->hp[i] = EnsProb{c->N,       0,       nullptr,  c->Wn,       nullptr, c->Wn,   c->F,
+                           c->P,       c->A,    c->Q,     c->rowpart,  c->fac_l, c->fac_dinv,
+                           nullptr,    nullptr, nullptr,  nullptr,     nullptr, nullptr,
+                           nullptr,    nullptr, nullptr};
     }
     if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);
@@ -766,15 +817,26 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
         e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices || e->g_slices_low != e->slices_low ||
-        e->g_form != e->update_form ||
-        e->g_guess != e->guess_mode)
+        e->g_form != e->update_form || e->g_guess != e->guess_mode || e->g_cap2 != e->cap2)
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
-    if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
-        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0, e->dp, 0);
+    if (nsteps > 0) {
+        hipLaunchKernelGGL(ens_run_begin_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, e->own,
+                           e->dp, e->nsim);
         ZE_HIP(hipGetLastError());
     }
-    for (int n = 0; n < nsteps; ++n)
-        ZE_HIP(hipGraphLaunch(n > 0 && e->guess_mode == 1 ? e->exec_x : e->exec, e->own));
+    if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
+        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0, e->dp, 0, 0);
+        ZE_HIP(hipGetLastError());
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        hipGraphExec_t g = n > 0 && e->guess_mode == 1 ? e->exec_x : e->exec;
+        if (e->exec_s && n >= e->cap2_after) g = e->exec_s;
+        ZE_HIP(hipGraphLaunch(g, e->own));
+    }
+    if (nsteps > 0) {
+        hipLaunchKernelGGL(ens_run_end_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, e->own, e->dp);
+        ZE_HIP(hipGetLastError());
+    }
     ZE_HIP(hipEventRecord(e->ev_out, e->own));
     ZE_HIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
     return ZE_OK;
@@ -819,6 +881,13 @@ ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
         ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
     }
     e->guess_mode = mode;
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_steady_cap(ze_ens* e, int cap, int from_step) {
+    if (!e || cap < 0 || cap > 64 || from_step < 0) return ZE_EINVAL;
+    e->cap2 = cap;
+    e->cap2_after = from_step;
     return ZE_OK;
 }
 

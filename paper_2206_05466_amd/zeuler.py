@@ -58,6 +58,7 @@ SIGNATURES = {
     "ze_ensemble_set_initial_guess": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_split_slices_lower": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_update_form": (_c_int, [_vp, _c_int]),
+    "ze_ensemble_set_steady_cap": (_c_int, [_vp, _c_int, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -398,6 +399,12 @@ class Ensemble:
         from 2 W_n - F_prev; 2: the polynomial start (as Zeuler.set_initial_guess)."""
         _check(self.lib.ze_ensemble_set_initial_guess(self._ens, int(mode)),
                "ze_ensemble_set_initial_guess")
+
+    def set_steady_cap(self, cap: int, from_step: int = 4):
+        """Evaluation cap min(K, cap) for the steps from index from_step on of each run (with the
+        polynomial start); 0 restores K for every step."""
+        _check(self.lib.ze_ensemble_set_steady_cap(self._ens, int(cap), int(from_step)),
+               "ze_ensemble_set_steady_cap")
 
     def tuning(self, prec: int = PREC_FP64):
         """(choice, [ms per step of the candidates]) of the autotuner for precision prec:

@@ -449,6 +449,33 @@ def test_ensemble_multi_step_run_and_fixed_K(dev):
         assert np.linalg.norm(to_host(Wd[j]) - W) <= 1e-12 * np.linalg.norm(W)
 
 
+def test_ensemble_steady_cap_same_steps(dev):
+    """The steady cap (2 evaluations from the fifth step of a run, polynomial start) gives the
+    same steps, bit for bit, as the full cap whenever the later steps need at most 2, and an odd
+    step count (the last W_{n+1} in the scratch buffer, copied back) matches the oracle."""
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [64, 96, 130]
+    h, tol, K, steps = 0.01, 1e-12, 6, 9
+    W0s = [w0(n, 80 + j) for j, n in enumerate(sizes)]
+    out = {}
+    for cap in (0, 2):
+        Wd = [to_dev(W) for W in W0s]
+        with Ensemble(sizes) as ens:
+            ens.set_initial_guess(2)
+            ens.set_update_form(1)
+            ens.set_steady_cap(cap, 4)
+            ens.run(Wd, h, steps, tol, K)
+            its, res = ens.stats()
+        assert max(res) < tol and max(its) <= 2, (cap, its)
+        out[cap] = [to_host(W) for W in Wd]
+    for j in range(len(sizes)):
+        assert np.array_equal(out[0][j], out[2][j]), j
+        Wr, _, _ = O.isomp_run(W0s[j], h, steps, tol, K, extrapolate=True, degree=3,
+                               update="difference")
+        assert np.linalg.norm(out[2][j] - Wr) <= 1e-12 * np.linalg.norm(Wr), j
+
+
 def test_ensemble_extrapolated_guess(dev):
     """Guess mode 1 in the ensemble (steps after the first of a run start from 2 W_n - F_prev):
     every simulation matches the single-context run in the same mode and the oracle's

@@ -13,8 +13,9 @@ oracle's evaluation counts for the FP64 form, and Casimir drift <= 1e-11 (C_2, C
 C_3 against ||W_0||_F^3).
 
 The 64-simulation ensemble: the bench's run (one step, then 50, each a run call of its own;
-evaluation cap 5; FP64 and the split form at the workload's slice count), one member of each
-size class against the oracle's run of the same two calls.
+evaluation cap 5, and 2 from the fifth step of a call; FP64 and the split form at the
+workload's slice count), one member of each size class against the oracle's run of the same
+two calls.
 """
 
 import os
@@ -141,6 +142,7 @@ def test_ensemble64_timed_configuration(dev, prec_name):
     with Ensemble(sizes) as ens:
         ens.set_initial_guess(2)
         ens.set_update_form(1)
+        ens.set_steady_cap(cfg["steady_cap"], cfg["steady_from"])
         if split:
             ens.set_split_slices(cfg["split_slices"])
         ens.run(Ws, h, 1, tol, K, prec=prec)   # the bench's first call (tuning, capture)

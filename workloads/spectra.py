@@ -69,9 +69,12 @@ WORKLOADS = {
     "n2048": dict(N=2048, law="inv1.5", h=0.005, steps=20,  tol=1e-12, maxit=50, seeds=(0,)),
     "n4096": dict(N=4096, law="inv1.5", h=0.005, steps=10,  tol=1e-12, maxit=50, seeds=(0,)),
     # K: the evaluation cap of the graph-captured ensemble step (one above the 4 that the
-    # first step, from W_n, needs); split_slices: the slices of its split-precision products
+    # first step, from W_n, needs); steady_cap from steady_from: the cap of the later steps of
+    # a run (one above the single evaluation they need once the polynomial start has reached
+    # degree 3); split_slices: the slices of its split-precision products
     "ensemble64": dict(nsim=64, sizes=(128, 256, 384, 512), law="inv1", h=0.005, steps=50,
-                       K=5, tol=1e-12, split_slices=5, size_seed=0, seed0=1000),
+                       K=5, steady_cap=2, steady_from=4, tol=1e-12, split_slices=5, size_seed=0,
+                       seed0=1000),
     # the paper's long-run initial condition (degrees 2..20, unit spectral norm, Sec. 4)
     "long512": dict(N=512, law="paper", h=0.005, steps=10000, tol=1e-12, maxit=50, seed=0,
                     sample=1000),
