@@ -145,8 +145,8 @@ ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, in
  *           call is asynchronous and can be captured into a HIP graph (ze_run_stats reads the
  *           counts afterwards).  Every step of a run is executed even when one fails to
  *           converge.  A skipped evaluation still costs its (empty) launches, so maxit is best
- *           set near the most evaluations a step needs.  FP64 products only (ZE_PREC_FP64;
- *           other precisions return ZE_EINVAL); ze_profile's per-phase timing is not taken.
+ *           set near the most evaluations a step needs.  Every precision (the split and modular
+ *           products' kernels read the flag too); ze_profile's per-phase timing is not taken.
  * Selecting mode 1 allocates the per-step records (65536 steps; older steps of a longer run
  * are reported as -1).
  * Errors: ZE_EINVAL, ZE_ENOMEM.

@@ -343,8 +343,8 @@ enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
 // One midpoint step of size h.  The fixed point starts from W_n (kFromWn), from
 // W_n + rho (W_n - F) written over F (kLinear; F = the previous step's converged midpoint, still
 // in c->F; rho = 1 gives 2 W_n - F), or from the iterate the caller has put in c->F (kFromF).
-ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, StartFrom start,
-                            double rho, bool first, bool last);
+ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                            StartFrom start, double rho, bool first, bool last);
 
 ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
                           StartFrom start, double rho, int* iters, double* resid, bool first = true,
@@ -353,13 +353,7 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED &&
         prec != ZE_PREC_CRT)
         return ZE_EINVAL;
-    if (c->stop_mode == 1) {
-        if (prec != ZE_PREC_FP64) {
-            g_last_error = "on-device stopping runs the FP64 products only";
-            return ZE_EINVAL;
-        }
-        return isomp_step_device(c, W, h, tol, maxit, start, rho, first, last);
-    }
+    if (c->stop_mode == 1) return isomp_step_device(c, W, h, tol, maxit, prec, start, rho, first, last);
     const int N = c->N;
     const size_t bytes = (size_t)N * N * sizeof(double2);
     double2* Wu = static_cast<double2*>(W);
@@ -434,22 +428,46 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
 // The caller's W receives W_{n+1} from every evaluation that runs, so it ends with that of the
 // last one, as in the host loop.  Nothing synchronises; the counts and residuals go to the
 // control words and the per-step records (first / last: the substep opens / closes the step).
-ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, StartFrom start,
-                            double rho, bool first, bool last) {
+ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
+                            StartFrom start, double rho, bool first, bool last) {
     const int N = c->N;
     double2* Wu = static_cast<double2*>(W);
     hipStream_t s = c->stream;
+    const bool split = prec == ZE_PREC_SPLIT, mixed = prec == ZE_PREC_MIXED;
+    const bool crt = prec == ZE_PREC_CRT;
+    if (split || mixed) ZE_TRY(ze_ensure_split(c));
+    if (crt) ZE_TRY(ze_ensure_crt(c));
     const int* skip = c->dctl;
+    // the split and modular launchers take the flag from the context while this substep is
+    // enqueued; it is cleared on every way out
+    struct SkipScope {
+        ze_ctx* c;
+        ~SkipScope() { c->skip = nullptr; }
+    } scope{c};
+    c->skip = skip;
     unsigned* counter = reinterpret_cast<unsigned*>(c->dctl + kCtlCounter);
     ZE_HIP(launch_ctl_substep_begin(Wu, c->Wn, N, c->dctl, c->dctld, first, s));
     if (start == kLinear) ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
     const double2* Wt = start == kFromWn ? c->Wn : c->F;
     for (int k = 1; k <= maxit; ++k) {
         ZE_HIP(launch_stream_solve(c, Wt, c->P, s, skip));
-        ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s, skip));
-        ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s, skip));
-        ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
-                                   nullptr, s, skip));
+        if (split)
+            ZE_HIP(launch_zgemm_split(c, c->P, Wt, c->A, 0, c->split_ea, c->split_eb, false, s));
+        else if (crt)
+            ZE_HIP(launch_zgemm_crt(c, c->P, Wt, c->A, s));
+        else
+            ZE_HIP(launch_zgemm_f64(c, c->P, Wt, c->A, s, skip));
+        if (split || crt || mixed) {
+            // P is skew-Hermitian: after the split or modular product its column exponents are
+            // the row exponents just taken; after the FP64 product (mixed) they are taken here
+            ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, !mixed, s));
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+                                       c->split_ec, c->split_ea, s, skip));
+        } else {
+            ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s, skip));
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
+                                       nullptr, s, skip));
+        }
         ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax, counter,
                                    c->resid, N, s, skip, c->dctl, tol));
         Wt = c->F;
@@ -566,10 +584,9 @@ static ze_status read_run_records(ze_ctx* c, int nsteps, int* iters, double* res
 // per-step results are asked for.
 static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit, int nsteps,
                             int prec, int* iters, double* resid) {
-    if (prec != ZE_PREC_FP64) {
-        g_last_error = "on-device stopping runs the FP64 products only";
+    if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED &&
+        prec != ZE_PREC_CRT)
         return ZE_EINVAL;
-    }
     if (!is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
     for (int n = 0; n < nsteps; ++n) ZE_TRY(composed_step(c, W, h, tol, maxit, prec, n, nullptr, nullptr));

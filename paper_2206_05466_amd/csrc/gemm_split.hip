@@ -53,8 +53,10 @@ constexpr int kThreads = kSThreads;
 __global__ __launch_bounds__(kThreads) void split_rows_kernel(const double2* __restrict__ A,
                                                               int N, int s, int ldk,
                                                               signed char* __restrict__ slices,
-                                                              int* __restrict__ ea) {
+                                                              int* __restrict__ ea,
+                                                              const int* __restrict__ skip) {
     __shared__ double red[kThreads];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     split_row_block(A, N, blockIdx.x, s, ldk, slices, ea, red);
 }
 
@@ -62,7 +64,9 @@ __global__ __launch_bounds__(kThreads) void split_rows_kernel(const double2* __r
 // columns over the row chunk y; then one thread per column combines the chunks.
 constexpr int kColChunks = 64;
 __global__ __launch_bounds__(kThreads) void col_max_partial(const double2* __restrict__ B, int N,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part,
+                                                            const int* __restrict__ skip) {
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const int c = blockIdx.x * kThreads + threadIdx.x;
     if (c >= N) return;
     const int k0 = (int)((long long)blockIdx.y * N / kColChunks);
@@ -76,7 +80,9 @@ __global__ __launch_bounds__(kThreads) void col_max_partial(const double2* __res
 }
 
 __global__ __launch_bounds__(kThreads) void col_exponent_kernel(const double* __restrict__ part,
-                                                                int N, int* __restrict__ eb) {
+                                                                int N, int* __restrict__ eb,
+                                                                const int* __restrict__ skip) {
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const int c = blockIdx.x * kThreads + threadIdx.x;
     if (c >= N) return;
     double m = 0.0;
@@ -87,8 +93,10 @@ __global__ __launch_bounds__(kThreads) void col_exponent_kernel(const double* __
 __global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __restrict__ B,
                                                               int N, int s, int ldk,
                                                               const int* __restrict__ eb,
-                                                              signed char* __restrict__ slices) {
+                                                              signed char* __restrict__ slices,
+                                                              const int* __restrict__ skip) {
     __shared__ double2 tile[kCT][kCT + 1];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     split_cols_tile(B, N, blockIdx.x, blockIdx.y, s, ldk, eb, slices, tile);
 }
 
@@ -96,16 +104,20 @@ __global__ __launch_bounds__(kThreads) void split_cols_kernel(const double2* __r
 __global__ __launch_bounds__(kThreads) void crt_rows_kernel(const double2* __restrict__ A, int N,
                                                             int b, int ldk,
                                                             signed char* __restrict__ slices,
-                                                            int* __restrict__ ea) {
+                                                            int* __restrict__ ea,
+                                                            const int* __restrict__ skip) {
     __shared__ double red[kThreads];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     crt_row_block(A, N, blockIdx.x, b, ldk, slices, ea, red);
 }
 
 __global__ __launch_bounds__(kThreads) void crt_cols_kernel(const double2* __restrict__ B, int N,
                                                             int b, int ldk,
                                                             const int* __restrict__ eb,
-                                                            signed char* __restrict__ slices) {
+                                                            signed char* __restrict__ slices,
+                                                            const int* __restrict__ skip) {
     __shared__ double2 tile[kCT][kCT + 1];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     crt_cols_tile(B, N, blockIdx.x, blockIdx.y, b, ldk, eb, slices, tile);
 }
 
@@ -131,7 +143,9 @@ __global__ __launch_bounds__(kThreads) void crt_combine_kernel(const unsigned ch
                                                                const int* __restrict__ ea,
                                                                const int* __restrict__ eb,
                                                                double2* __restrict__ Cm, int N,
-                                                               int b) {
+                                                               int b,
+                                                               const int* __restrict__ skip) {
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const size_t n2 = (size_t)N * N;
     const size_t n4 = n2 % 4 == 0 ? n2 / 4 : 0;
     const unsigned* G32 = reinterpret_cast<const unsigned*>(G8);
@@ -211,8 +225,10 @@ __device__ __forceinline__ void i8_tile_of(int mode, int tile, int tiles_n, int 
 
 __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb, int* __restrict__ G,
-    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S) {
+    int N, int s, int ldk, int mode, int tiles_n, int ntiles, int full, int S,
+    const int* __restrict__ skip) {
     __shared__ I8Smem sm;
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     int ti, tj;
     const int b = blockIdx.x;
     if (b < full) {
@@ -232,7 +248,9 @@ __global__ __launch_bounds__(kThreads, 2) void zgemm_i8_kernel(
 // ones) of bm x bn tiles; grid (ntiles - full, s).
 __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, int N, int mode,
                                                           int tiles_n, int ntiles, int full,
-                                                          int bm, int bn, int ncols) {
+                                                          int bm, int bn, int ncols,
+                                                          const int* __restrict__ skip) {
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     int ti, tj;
     i8_tile_of(mode, full + blockIdx.x, tiles_n, ntiles, false, 0, ti, tj);
     const int M2 = ncols;
@@ -253,8 +271,10 @@ __global__ __launch_bounds__(kThreads) void i8_clear_tail(int* __restrict__ G, i
 // tiles an XCD holds at once on shared panels.
 __global__ __launch_bounds__(kI8LThreads, 1) void zgemm_i8_large_kernel(
     const signed char* __restrict__ sa, const signed char* __restrict__ sb,
-    unsigned char* __restrict__ G8, int N, int s, int ldk, int tiles_n, int ntiles, int G) {
+    unsigned char* __restrict__ G8, int N, int s, int ldk, int tiles_n, int ntiles, int G,
+    const int* __restrict__ skip) {
     __shared__ I8LSmem sm;
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const int b = blockIdx.x, g = b / ntiles, tile = b % ntiles;
     int ti, tj;
     i8_tile_of(0, tile, tiles_n, ntiles, ntiles % 8 == 0, tile, ti, tj);
@@ -267,7 +287,9 @@ __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __re
                                                                  const int* __restrict__ ea,
                                                                  const int* __restrict__ eb,
                                                                  double2* __restrict__ Cm, int N,
-                                                                 int s) {
+                                                                 int s,
+                                                                 const int* __restrict__ skip) {
+    if (skip && *skip) return;  // on-device stopping: the step has converged
     const size_t n2 = (size_t)N * N;
     for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n2;
          e += (size_t)gridDim.x * kThreads)
@@ -317,22 +339,22 @@ hipError_t launch_split_prepare(const ze_ctx* c, const double2* A, const double2
                                 int* eb, bool eb_known, int lower, hipStream_t st) {
     const int N = c->N, s = slices_of(c, lower), ldk = ze_split_ldk(N);
     hipLaunchKernelGGL(split_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, s, ldk, c->split_a,
-                       ea);
+                       ea, c->skip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!eb_known) {
         const int gx = (N + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(col_max_partial, dim3(gx, kColChunks), dim3(kThreads), 0, st, B, N,
-                           c->split_colmax);
+                           c->split_colmax, c->skip);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(col_exponent_kernel, dim3(gx), dim3(kThreads), 0, st, c->split_colmax,
-                           N, eb);
+                           N, eb, c->skip);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     dim3 g((N + kCT - 1) / kCT, (ldk / 2 + kCT - 1) / kCT);
-    hipLaunchKernelGGL(split_cols_kernel, g, dim3(kThreads), 0, st, B, N, s, ldk, eb, c->split_b);
+    hipLaunchKernelGGL(split_cols_kernel, g, dim3(kThreads), 0, st, B, N, s, ldk, eb, c->split_b, c->skip);
     return hipGetLastError();
 }
 
@@ -360,19 +382,19 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     }
     if (full < ntiles) {
         hipLaunchKernelGGL(i8_clear_tail, dim3(ntiles - full, s), dim3(kThreads), 0, st, c->split_g,
-                           N, lower ? 1 : 0, tn, ntiles, full, kI8BM, kI8BN, 2 * N);
+                           N, lower ? 1 : 0, tn, ntiles, full, kI8BM, kI8BN, 2 * N, c->skip);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(zgemm_i8_kernel, dim3(full + (ntiles - full) * S), dim3(kThreads), 0, st,
                        c->split_a, c->split_b, c->split_g, N, s, ze_split_ldk(N), lower ? 1 : 0, tn,
-                       ntiles, full, S);
+                       ntiles, full, S, c->skip);
     e = hipGetLastError();
     if (e != hipSuccess || lower) return e;
     const size_t n2 = (size_t)N * N;
     const unsigned grid = (unsigned)((n2 + kThreads - 1) / kThreads < 16384 ? (n2 + kThreads - 1) / kThreads : 16384);
     hipLaunchKernelGGL(split_combine_kernel, dim3(grid), dim3(kThreads), 0, st, c->split_g, ea, eb,
-                       C, N, s);
+                       C, N, s, c->skip);
     return hipGetLastError();
 }
 
@@ -411,35 +433,35 @@ hipError_t launch_zgemm_crt(const ze_ctx* c, const double2* A, const double2* B,
                             hipStream_t st) {
     const int N = c->N, ldk = ze_crt_ldk(N), b = ze_crt_bits(N);
     hipLaunchKernelGGL(crt_rows_kernel, dim3(N), dim3(kThreads), 0, st, A, N, b, ldk, c->crt_a,
-                       c->split_ea);
+                       c->split_ea, c->skip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int gx = (N + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(col_max_partial, dim3(gx, kColChunks), dim3(kThreads), 0, st, B, N,
-                       c->split_colmax);
+                       c->split_colmax, c->skip);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(col_exponent_kernel, dim3(gx), dim3(kThreads), 0, st, c->split_colmax, N,
-                       c->split_eb);
+                       c->split_eb, c->skip);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g((N + kCT - 1) / kCT, (ldk + kCT - 1) / kCT);
     hipLaunchKernelGGL(crt_cols_kernel, g, dim3(kThreads), 0, st, B, N, b, ldk, c->split_eb,
-                       c->crt_b);
+                       c->crt_b, c->skip);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     int ntiles, tn, G;
     ze_crt_plan(N, c->cap_i8l, &ntiles, &tn, &G);
     unsigned char* G8 = reinterpret_cast<unsigned char*>(c->crt_g);
     hipLaunchKernelGGL(zgemm_i8_large_kernel, dim3(ntiles * G), dim3(kI8LThreads), 0, st,
-                       c->crt_a, c->crt_b, G8, N, 3 * kCrtMods, ldk, tn, ntiles, G);
+                       c->crt_a, c->crt_b, G8, N, 3 * kCrtMods, ldk, tn, ntiles, G, c->skip);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t n2 = (size_t)N * N, per = n2 % 4 == 0 ? n2 / 4 : n2;  // outputs / thread: 4 or 1
     const size_t want = (per + kThreads - 1) / kThreads;  // one pass: no loop-carried addresses
     const unsigned grid = (unsigned)(want < 1 ? 1 : want);
     hipLaunchKernelGGL(crt_combine_kernel, dim3(grid), dim3(kThreads), 0, st, G8, c->split_ea,
-                       c->split_eb, C, N, b);
+                       c->split_eb, C, N, b, c->skip);
     return hipGetLastError();
 }
 

@@ -111,6 +111,9 @@ struct ze_ctx {
     int* dstep_it = nullptr;
     double* dstep_r = nullptr;
     int last_run_steps = 0;
+    // Done flag read by the split and modular products' kernels while a substep with on-device
+    // stopping is being enqueued (dctl then, else null: they always run).
+    const int* skip = nullptr;
 
     // Optional per-phase timing (ze_profile).
     bool prof = false;

@@ -217,7 +217,7 @@ class Zeuler:
 
     def set_stopping(self, mode: int):
         """0: tolerance test on the host after each evaluation; 1: on the device (no
-        synchronisation per evaluation; FP64 products)."""
+        synchronisation per evaluation; every precision)."""
         _check(self.lib.ze_set_stopping(self._ctx, int(mode)), "ze_set_stopping")
 
     def run_stats(self, nsteps: int):

@@ -33,13 +33,13 @@ def field(N, seed=0, law="inv1"):
     return O.assemble(N, omega_coeffs(N, seed, law))
 
 
-def run(z, W0, h, steps, tol, maxit, mode, guess, form, order=2):
+def run(z, W0, h, steps, tol, maxit, mode, guess, form, order=2, prec=0):
     z.set_stopping(mode)
     z.set_initial_guess(guess)
     z.set_update_form(form)
     z.set_order(order)
     W = torch.from_numpy(W0).cuda()
-    its, res = z.isomp_run(W, h, steps, tol, maxit)
+    its, res = z.isomp_run(W, h, steps, tol, maxit, prec)
     torch.cuda.synchronize()
     return W.cpu().numpy(), its, res
 
@@ -61,6 +61,31 @@ def test_device_stopping_bit_identical_to_host_loop(dev, N, guess, form):
                                  update="difference" if form == 1 else "second_line")
         assert itd == itr
         assert np.linalg.norm(Wd - Wr) / np.linalg.norm(Wr) < 1e-12
+
+
+@pytest.mark.parametrize("prec_name,N", [("split", 160), ("mixed", 160), ("crt", 160),
+                                         ("crt", 512), ("split", 512)])
+def test_device_stopping_other_precisions_bit_identical(dev, prec_name, N):
+    """The split (4 slices), mixed and modular products with the rule on the device: the same
+    W, evaluation counts and residuals as their host loop, bit for bit (polynomial start,
+    difference form), and the oracle's trajectory within each form's bar."""
+    from paper_2206_05466_amd import PREC_CRT, PREC_MIXED, PREC_SPLIT, Zeuler
+
+    prec = {"split": PREC_SPLIT, "mixed": PREC_MIXED, "crt": PREC_CRT}[prec_name]
+    h, tol, maxit, steps = 0.01, 1e-12, 6, 8
+    W0 = field(N, 5)
+    with Zeuler(N) as z:
+        z.set_split_slices(4)
+        Wh, ith, rh = run(z, W0, h, steps, tol, maxit, 0, 2, 1, prec=prec)
+        Wd, itd, rd = run(z, W0, h, steps, tol, maxit, 1, 2, 1, prec=prec)
+        _, _, st = z.run_stats(steps)
+    assert itd == ith and rd == rh and st == 0, (itd, ith)
+    assert np.array_equal(Wd, Wh)
+    if N == 160:
+        Wr, itr, _ = O.isomp_run(W0, h, steps, tol, maxit, extrapolate=True, degree=3,
+                                 update="difference")
+        e = np.linalg.norm(Wd - Wr) / np.linalg.norm(Wr)
+        assert e < (1e-12 if prec_name != "split" else 1e-9), e
 
 
 def test_device_stopping_fixed_count_and_order4(dev):
