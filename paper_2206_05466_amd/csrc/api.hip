@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -222,7 +223,7 @@ ze_status ze_create_ctx(int N, void* stream, bool split_k, int solve_bd_, ze_ctx
     c->ut = zk::update_tile_of(N);
     const int T = (N + c->ut - 1) / c->ut;
     {
-        hipError_t ce = ze_gemm_capacity(&c->cap_full, &c->cap_low);
+        hipError_t ce = ze_gemm_capacity(&c->cap_full, &c->cap_low, &c->cus);
         if (ce != hipSuccess) {
             delete c;
             return ze_record_hip(ce, "ze_gemm_capacity");
@@ -340,31 +341,34 @@ namespace {
 
 enum StartFrom { kFromWn = 0, kLinear = 1, kFromF = 2 };
 
-// One midpoint step of size h.  The fixed point starts from W_n (kFromWn), from
-// W_n + rho (W_n - F) written over F (kLinear; F = the previous step's converged midpoint, still
-// in c->F; rho = 1 gives 2 W_n - F), or from the iterate the caller has put in c->F (kFromF).
-ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                            StartFrom start, double rho, bool first, bool last);
+// One midpoint step of size h from W_n in Win (read only) to W_{n+1} in Wout (another buffer,
+// written by every evaluation, so it ends with that of the last one).  The fixed point starts
+// from W_n (kFromWn), from W_n + rho (W_n - F) written over F (kLinear; F = the previous step's
+// converged midpoint, still in c->F; rho = 1 gives 2 W_n - F), or from the iterate the caller
+// has put in c->F (kFromF).
+ze_status isomp_step_device(ze_ctx* c, const double2* Win, double2* Wout, double h, double tol,
+                            int maxit, int prec, StartFrom start, double rho, bool last);
 
-ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                          StartFrom start, double rho, int* iters, double* resid, bool first = true,
-                          bool last = true) {
-    if (!c || !W || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
+ze_status isomp_step_impl(ze_ctx* c, const double2* Win, double2* Wout, double h, double tol,
+                          int maxit, int prec, StartFrom start, double rho, int* iters,
+                          double* resid, bool last) {
+    if (!c || !Win || !Wout || Win == Wout || !is_finite(h) || !(tol >= 0.0) || !is_finite(tol) ||
+        maxit < 1)
+        return ZE_EINVAL;
     if (prec != ZE_PREC_FP64 && prec != ZE_PREC_SPLIT && prec != ZE_PREC_MIXED &&
         prec != ZE_PREC_CRT)
         return ZE_EINVAL;
-    if (c->stop_mode == 1) return isomp_step_device(c, W, h, tol, maxit, prec, start, rho, first, last);
+    if (c->stop_mode == 1) return isomp_step_device(c, Win, Wout, h, tol, maxit, prec, start, rho, last);
     const int N = c->N;
-    const size_t bytes = (size_t)N * N * sizeof(double2);
-    double2* Wu = static_cast<double2*>(W);
+    double2* Wu = Wout;
     const bool split = prec == ZE_PREC_SPLIT, mixed = prec == ZE_PREC_MIXED;
     const bool crt = prec == ZE_PREC_CRT;
     if (split || mixed) ZE_TRY(ze_ensure_split(c));
     if (crt) ZE_TRY(ze_ensure_crt(c));
     hipStream_t s = c->stream;
-    ZE_HIP(hipMemcpyAsync(c->Wn, Wu, bytes, hipMemcpyDeviceToDevice, s));
-    const double2* Wt = c->Wn;
-    if (start == kLinear) ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
+    const double2* Wn = Win;
+    const double2* Wt = Wn;
+    if (start == kLinear) ZE_HIP(launch_extrapolate(Wn, c->F, N, rho, s));
     if (start != kFromWn) Wt = c->F;
     double r = 0.0;
     int k = 0;
@@ -383,16 +387,16 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
         if (split || crt) {
             // P is skew-Hermitian: its column exponents are the row exponents just taken
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, true, s));
-            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, Wn, Wt, c->F, Wu, c->rowpart, h,
                                        c->split_ec, c->split_ea, s));
         } else if (mixed) {
             // A came from the FP64 product: P's column exponents are taken here
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, false, s));
-            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, Wn, Wt, c->F, Wu, c->rowpart, h,
                                        c->split_ec, c->split_ea, s));
         } else {
             ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s));
-            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
                                        nullptr, s));
         }
         if (prof) ZE_HIP(hipEventRecord(c->ev[3], s));
@@ -425,13 +429,14 @@ ze_status isomp_step_impl(ze_ctx* c, void* W, double h, double tol, int maxit, i
 // The same substep with the stopping rule on the device: maxit evaluations are enqueued, each
 // kernel of an evaluation reads the done flag (dctl[0]) first and returns at once when it is
 // set, and the residual reduction sets it once the change of W~ is below tol (or not finite).
-// The caller's W receives W_{n+1} from every evaluation that runs, so it ends with that of the
-// last one, as in the host loop.  Nothing synchronises; the counts and residuals go to the
-// control words and the per-step records (first / last: the substep opens / closes the step).
-ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit, int prec,
-                            StartFrom start, double rho, bool first, bool last) {
+// Wout receives W_{n+1} from every evaluation that runs, so it ends with that of the last one,
+// as in the host loop.  Nothing synchronises; the counts and residuals go to the control words
+// and the per-step records (last: the substep closes the step).
+ze_status isomp_step_device(ze_ctx* c, const double2* Win, double2* Wout, double h, double tol,
+                            int maxit, int prec, StartFrom start, double rho, bool last) {
     const int N = c->N;
-    double2* Wu = static_cast<double2*>(W);
+    double2* Wu = Wout;
+    const double2* Wn = Win;
     hipStream_t s = c->stream;
     const bool split = prec == ZE_PREC_SPLIT, mixed = prec == ZE_PREC_MIXED;
     const bool crt = prec == ZE_PREC_CRT;
@@ -446,9 +451,8 @@ ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit,
     } scope{c};
     c->skip = skip;
     unsigned* counter = reinterpret_cast<unsigned*>(c->dctl + kCtlCounter);
-    ZE_HIP(launch_ctl_substep_begin(Wu, c->Wn, N, c->dctl, c->dctld, first, s));
-    if (start == kLinear) ZE_HIP(launch_extrapolate(Wu, c->F, N, rho, s));
-    const double2* Wt = start == kFromWn ? c->Wn : c->F;
+    if (start == kLinear) ZE_HIP(launch_extrapolate(Wn, c->F, N, rho, s));
+    const double2* Wt = start == kFromWn ? Wn : c->F;
     for (int k = 1; k <= maxit; ++k) {
         ZE_HIP(launch_stream_solve(c, Wt, c->P, s, skip));
         if (split)
@@ -461,11 +465,11 @@ ze_status isomp_step_device(ze_ctx* c, void* W, double h, double tol, int maxit,
             // P is skew-Hermitian: after the split or modular product its column exponents are
             // the row exponents just taken; after the FP64 product (mixed) they are taken here
             ZE_HIP(launch_zgemm_split(c, c->A, c->P, nullptr, 1, c->split_ec, c->split_ea, !mixed, s));
-            ZE_HIP(launch_lower_update(c, nullptr, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h,
+            ZE_HIP(launch_lower_update(c, nullptr, c->A, Wn, Wt, c->F, Wu, c->rowpart, h,
                                        c->split_ec, c->split_ea, s, skip));
         } else {
             ZE_HIP(launch_zgemm_lower(c, c->A, c->P, c->Q, s, skip));
-            ZE_HIP(launch_lower_update(c, c->Q, c->A, c->Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
+            ZE_HIP(launch_lower_update(c, c->Q, c->A, Wn, Wt, c->F, Wu, c->rowpart, h, nullptr,
                                        nullptr, s, skip));
         }
         ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax, counter,
@@ -506,6 +510,20 @@ ze_status ring_start(ze_ctx* c, const void* W, size_t j, int n, double rho, Star
     return ZE_OK;
 }
 
+// The state of a run: W_n in cur; a substep writes W_{n+1} into other, and the two swap.  The
+// caller's W and the context's Wn take turns, and the run ends with a copy into the caller's
+// W when the last substep left it in Wn.
+struct RunState {
+    double2* user;
+    double2* cur;
+    double2* other;
+};
+
+ze_status finish_run(ze_ctx* c, const RunState& rs) {
+    if (rs.cur != rs.user) ZE_HIP(launch_copy(rs.cur, rs.user, c->N, c->stream));
+    return ZE_OK;
+}
+
 // One step of the context's order: a midpoint substep of size c_j h for every fraction c_j.
 // n is the step's index in the run.  Guess mode 1: every substep after the first of the call
 // (n > 0 or j > 0) starts from W + rho (W - F_prev), rho = c_j / c_{j-1} (cyclically, so 1
@@ -513,9 +531,9 @@ ze_status ring_start(ze_ctx* c, const void* W, size_t j, int n, double rho, Star
 // substep that reaches maxit above tol still completes the step (the fixed-iteration mode)
 // and the step then reports ZE_ENOTCONV; any other error ends it.  iters: evaluations over all
 // substeps; resid: the largest substep residual.
-ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int prec, int n,
+ze_status composed_step(ze_ctx* c, RunState& rs, double h, double tol, int maxit, int prec, int n,
                         int* iters, double* resid) {
-    if (!c || !W) return ZE_EINVAL;
+    if (!c || !rs.cur) return ZE_EINVAL;
     const std::vector<double>& w = c->comp_w;
     const size_t ns = w.size();
     if (c->guess_mode == 2) ZE_TRY(ze_ensure_rings(c, (int)ns));
@@ -526,11 +544,12 @@ ze_status composed_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
         const double rho = w[j] / w[j == 0 ? ns - 1 : j - 1];
         StartFrom start = kFromWn;
         if (c->guess_mode == 1 && (j > 0 || n > 0)) start = kLinear;
-        if (c->guess_mode == 2) ZE_TRY(ring_start(c, W, j, n, rho, &start));
+        if (c->guess_mode == 2) ZE_TRY(ring_start(c, rs.cur, j, n, rho, &start));
         int k = 0;
         double r = 0.0;
-        const ze_status st = isomp_step_impl(c, W, w[j] * h, tol, maxit, prec, start, rho, &k, &r,
-                                             j == 0, j + 1 == ns);
+        const ze_status st = isomp_step_impl(c, rs.cur, rs.other, w[j] * h, tol, maxit, prec, start,
+                                             rho, &k, &r, j + 1 == ns);
+        if (st == ZE_OK || st == ZE_ENOTCONV || st == ZE_ENONFINITE) std::swap(rs.cur, rs.other);
         total += k;
         if (!(r <= rmax)) rmax = r;  // keeps a NaN
         if (st == ZE_ENOTCONV) {
@@ -589,7 +608,15 @@ static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit,
         return ZE_EINVAL;
     if (!is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
-    for (int n = 0; n < nsteps; ++n) ZE_TRY(composed_step(c, W, h, tol, maxit, prec, n, nullptr, nullptr));
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
+    for (int n = 0; n < nsteps; ++n) {
+        const ze_status st = composed_step(c, rs, h, tol, maxit, prec, n, nullptr, nullptr);
+        if (st != ZE_OK) {
+            finish_run(c, rs);
+            return st;
+        }
+    }
+    ZE_TRY(finish_run(c, rs));
     c->last_run_steps = nsteps;
     if (!iters && !resid) return ZE_OK;
     return read_run_records(c, nsteps, iters, resid);
@@ -601,7 +628,10 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     if (!c || !W) return ZE_EINVAL;
     if (c->validate) ZE_TRY(check_su(c, W));
     if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, 1, prec, iters, resid);
-    return composed_step(c, W, h, tol, maxit, prec, 0, iters, resid);
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
+    const ze_status st = composed_step(c, rs, h, tol, maxit, prec, 0, iters, resid);
+    const ze_status fin = finish_run(c, rs);
+    return st != ZE_OK ? st : fin;
 }
 
 ze_status ze_set_stopping(ze_ctx* c, int mode) {
@@ -636,15 +666,19 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
     if (c->validate && nsteps > 0) ZE_TRY(check_su(c, W));
     if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, nsteps, prec, iters, resid);
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = composed_step(c, W, h, tol, maxit, prec, n, &k, &r);
+        ze_status st = composed_step(c, rs, h, tol, maxit, prec, n, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
-        if (st != ZE_OK) return st;
+        if (st != ZE_OK) {
+            finish_run(c, rs);
+            return st;
+        }
     }
-    return ZE_OK;
+    return finish_run(c, rs);
 }
 
 ze_status ze_casimirs(ze_ctx* c, const void* W, int kmax, double* out) {

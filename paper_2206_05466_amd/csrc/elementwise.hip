@@ -137,30 +137,20 @@ __global__ __launch_bounds__(256) void su_check_final(const double* __restrict__
 // Control words: see kCtlWords in internal.h.  NaN-propagating maximum.
 __device__ __forceinline__ double nanmax(double a, double o) { return (o != o || o > a) ? o : a; }
 
+// Run start: the run's totals and the first step's fields cleared.  Every later step and
+// substep starts from the fields the end of the previous one cleared.
 __global__ __launch_bounds__(64) void ctl_run_begin_kernel(int* ctl, double* ctld) {
     if (threadIdx.x == 0) {
-        for (int w = 4; w <= 7; ++w) ctl[w] = 0;
+        for (int w = 0; w <= 7; ++w) ctl[w] = 0;
         ctl[9] = 0;
+        ctld[0] = 0.0;
         ctld[1] = 0.0;
     }
 }
 
-__global__ __launch_bounds__(256) void ctl_substep_begin_kernel(const double2* __restrict__ W,
-                                                                double2* __restrict__ Wn, size_t n2,
-                                                                int* ctl, double* ctld, int first) {
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256)
-        Wn[e] = W[e];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl[0] = 0;
-        ctl[1] = 0;
-        if (first) {
-            ctl[2] = 0;
-            ctl[3] = 0;
-            ctld[0] = 0.0;
-        }
-    }
-}
-
+// Substep end: its count and residual into the step's; the done flag and the substep's count
+// cleared for the next substep; last: the step's record written at its index, the run totals
+// updated and the step's fields cleared for the next step.
 __global__ __launch_bounds__(64) void ctl_substep_end_kernel(int* ctl, double* ctld,
                                                              const double* __restrict__ resid,
                                                              double tol, int last, int* step_it,
@@ -171,6 +161,8 @@ __global__ __launch_bounds__(64) void ctl_substep_end_kernel(int* ctl, double* c
     ctld[0] = nanmax(ctld[0], r);
     if (!(r < tol)) ctl[3] |= 1;
     if (!isfinite(r)) ctl[3] |= 2;
+    ctl[0] = 0;
+    ctl[1] = 0;
     if (!last) return;
     const int n = ctl[9];
     step_it[n % kDevSteps] = ctl[2];
@@ -181,6 +173,15 @@ __global__ __launch_bounds__(64) void ctl_substep_end_kernel(int* ctl, double* c
     ctl[7] = ctl[2] > ctl[7] ? ctl[2] : ctl[7];
     ctld[1] = nanmax(ctld[1], ctld[0]);
     ctl[9] = n + 1;
+    ctl[2] = 0;
+    ctl[3] = 0;
+    ctld[0] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const double2* __restrict__ src,
+                                                   double2* __restrict__ dst, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+        dst[e] = src[e];
 }
 
 }  // namespace
@@ -223,12 +224,11 @@ hipError_t launch_ctl_run_begin(int* ctl, double* ctld, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_substep_begin(const double2* W, double2* Wn, int N, int* ctl, double* ctld,
-                                    bool first, hipStream_t s) {
+hipError_t launch_copy(const double2* src, double2* dst, int N, hipStream_t s) {
     const size_t n2 = (size_t)N * N;
     const size_t blocks = (n2 + 255) / 256;
-    hipLaunchKernelGGL(ctl_substep_begin_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
-                       dim3(256), 0, s, W, Wn, n2, ctl, ctld, first ? 1 : 0);
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
+                       s, src, dst, n2);
     return hipGetLastError();
 }
 

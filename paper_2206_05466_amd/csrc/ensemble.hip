@@ -327,8 +327,7 @@ __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restric
     const int N = p.N, T = (N + kTile - 1) / kTile;
     double best = 0.0;
     for (int i = threadIdx.x; i < N; i += 256) {
-        double v = 0.0;
-        for (int X = 0; X < T; ++X) v += p.rowpart[(size_t)X * N + i];
+        const double v = slot_row_sum<8>(p.rowpart, T, N, i);
         best = (v != v || v > best) ? v : best;
     }
     sm[threadIdx.x] = best;

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "tile_f64.h"
+#include "update_tile.h"
 
 namespace {
 
@@ -73,14 +74,26 @@ struct Split {
     int full, tail, S;
 };
 
-// `pmax`: the most split blocks whose partial sums the partial buffer holds.
-Split make_split(int ntiles, int nk, int cap, int pmax) {
+// `cap`: concurrent blocks of the kernel, `cus` the CUs they share, `pmax` the most split
+// blocks whose partial sums the partial buffer holds.  S is the one that finishes the split
+// round first when the rem * S blocks are dealt out evenly over the CUs: ceil(rem S / cus)
+// blocks on the busiest CU, of ceil(nk / S) stages each (ties: the larger S).
+Split make_split(int ntiles, int nk, int cap, int pmax, int cus) {
     const int rounds = ntiles / cap, rem = ntiles % cap;
     if (rem == 0) return {ntiles, 0, 1};
-    int S = cap / rem;
-    const int smax = nk / 8 > 1 ? nk / 8 : 1;  // at least 8 stages (64 complex k) per range
-    if (S > smax) S = smax;
-    if (S > pmax / rem) S = pmax / rem;
+    int smax = nk / 8 > 1 ? nk / 8 : 1;  // at least 8 stages (64 complex k) per range
+    if (smax > cap / rem) smax = cap / rem;
+    if (smax > pmax / rem) smax = pmax / rem;
+    if (cus < 1) cus = 1;
+    int S = 1;
+    long long best = (long long)((rem + cus - 1) / cus) * nk;
+    for (int s = 2; s <= smax; ++s) {
+        const long long L = (long long)((rem * s + cus - 1) / cus) * ((nk + s - 1) / s);
+        if (L <= best) {
+            best = L;
+            S = s;
+        }
+    }
     if (S <= 1) return {ntiles, 0, 1};
     return {rounds * cap, rem, S};
 }
@@ -114,6 +127,18 @@ __global__ __launch_bounds__(kThreads) void zgemm_f64_kernel(const double2* __re
         store_full_tile(acc, Cm, N, row0, col0);
     else
         store_partial<C>(part + (size_t)(b - full) * (C::MT * C::NT * 4 * kThreads), acc);
+}
+
+// Small sizes (ceil(N/32)^2 tiles, at most one per CU): block b forms the 32 x 32 tile b of C.
+__global__ __launch_bounds__(kThreads) void zgemm_small_kernel(const double2* __restrict__ A,
+                                                               const double2* __restrict__ B,
+                                                               double2* __restrict__ Cm, int N,
+                                                               int tiles_n,
+                                                               const int* __restrict__ skip) {
+    __shared__ double red[kSmallRed];
+    if (skip && *skip) return;  // on-device stopping: the step has converged
+    const int tile = blockIdx.x;
+    small_product(A, B, Cm, N, (tile / tiles_n) * kSmallTile, (tile % tiles_n) * kSmallTile, red);
 }
 
 // Fix-up of the split tiles: block (t, k) adds the S partial sums of accumulator tile k of
@@ -196,9 +221,7 @@ __global__ __launch_bounds__(kRedThreads) void resid_kernel(const double* __rest
     __shared__ bool last;
     if (skip && *skip) return;
     const int i = blockIdx.x * kRedThreads + threadIdx.x;
-    double v = 0.0;
-    if (i < N)
-        for (int X = 0; X < T; ++X) v += rowpart[(size_t)X * N + i];
+    const double v = i < N ? slot_row_sum<32>(rowpart, T, N, i) : 0.0;
     sm[threadIdx.x] = v;
     __syncthreads();
     for (int s = kRedThreads / 2; s > 0; s >>= 1) {
@@ -259,7 +282,7 @@ size_t ze_gemm_part_bytes(int cap_full, int cap_low) {
     return (a > b ? a : b) * sizeof(double);
 }
 
-hipError_t ze_gemm_capacity(int* cap_full, int* cap_low) {
+hipError_t ze_gemm_capacity(int* cap_full, int* cap_low, int* cus_out) {
     int dev = 0, cus = 0, nf = 0, nl = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -269,18 +292,25 @@ hipError_t ze_gemm_capacity(int* cap_full, int* cap_low) {
     if (e != hipSuccess) return e;
     *cap_full = (nf > 0 ? nf : 1) * cus;
     *cap_low = (nl > 0 ? nl : 1) * cus;
+    *cus_out = cus;
     return hipSuccess;
 }
 
 namespace {
 
-// The full product with `cap` concurrent blocks and a partial buffer `part` of `pmax` split
-// blocks' partial sums.
-hipError_t launch_full(int N, int cap, double* part, int pmax, const double2* A, const double2* B,
-                       double2* Cm, hipStream_t s, const int* skip = nullptr) {
+// The full product with `cap` concurrent blocks on `cus` CUs and a partial buffer `part` of
+// `pmax` split blocks' partial sums.  Sizes whose 32 x 32 tiles fit one per CU take the small
+// kernel (no split, no fix-up).
+hipError_t launch_full(int N, int cap, int cus, double* part, int pmax, const double2* A,
+                       const double2* B, double2* Cm, hipStream_t s, const int* skip = nullptr) {
+    const int wn = (N + kSmallTile - 1) / kSmallTile;
+    if ((long long)wn * wn <= cus) {
+        hipLaunchKernelGGL(zgemm_small_kernel, dim3(wn * wn), dim3(kThreads), 0, s, A, B, Cm, N, wn, skip);
+        return hipGetLastError();
+    }
     const int tiles_n = (N + FullCfg::BNC - 1) / FullCfg::BNC;
     const int tiles = tiles_n * ((N + FullCfg::BM - 1) / FullCfg::BM);
-    const Split sp = make_split(tiles, (N + kBK - 1) / kBK, cap, pmax);
+    const Split sp = make_split(tiles, (N + kBK - 1) / kBK, cap, pmax, cus);
     hipLaunchKernelGGL(zgemm_f64_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A, B,
                        Cm, N, tiles_n, sp.full, sp.S, part, skip);
     hipError_t e = hipGetLastError();
@@ -295,7 +325,7 @@ hipError_t launch_full(int N, int cap, double* part, int pmax, const double2* A,
 hipError_t launch_zgemm_f64(const ze_ctx* c, const double2* A, const double2* B, double2* Cm,
                             hipStream_t s, const int* skip) {
     // the context's buffer holds cap_full blocks' partial sums (ze_gemm_part_bytes)
-    return launch_full(c->N, c->cap_full, c->gemm_part, c->cap_full, A, B, Cm, s, skip);
+    return launch_full(c->N, c->cap_full, c->cus, c->gemm_part, c->cap_full, A, B, Cm, s, skip);
 }
 
 // ---------------------------------------------------------------- allocation-free product
@@ -315,6 +345,7 @@ constexpr int kNoAllocMaxDevices = 64;
 struct NoAllocDevice {
     double* ptr = nullptr;  // device address of `scratch` on this device
     int cap_full = 0;       // concurrent blocks of the full product
+    int cus = 0;            // compute units
 };
 
 std::mutex g_noalloc_mu;
@@ -338,21 +369,21 @@ hipError_t launch_zgemm_f64_noalloc(int N, const double2* A, const double2* B, d
             e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
             if (e != hipSuccess) return e;
             int cap_low = 0;
-            e = ze_gemm_capacity(&g_noalloc[dev].cap_full, &cap_low);
+            e = ze_gemm_capacity(&g_noalloc[dev].cap_full, &cap_low, &g_noalloc[dev].cus);
             if (e != hipSuccess) return e;
             g_noalloc[dev].ptr = static_cast<double*>(ptr);
         }
         d = g_noalloc[dev];
     }
     const int pmax = (int)(kNoAllocScratchBytes / sizeof(double) / kPartialDoubles);
-    return launch_full(N, d.cap_full, d.ptr, pmax, A, B, Cm, s);
+    return launch_full(N, d.cap_full, d.cus, d.ptr, pmax, A, B, Cm, s);
 }
 
 hipError_t launch_zgemm_lower(const ze_ctx* c, const double2* A, const double2* P, double2* Q,
                               hipStream_t s, const int* skip) {
     const int N = c->N;
     const int T = (N + kTile - 1) / kTile;
-    const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low, c->cap_low);
+    const Split sp = make_split(T * (T + 1) / 2, (N + kBK - 1) / kBK, c->cap_low, c->cap_low, c->cus);
     hipLaunchKernelGGL(zgemm_lower_kernel, dim3(sp.full + sp.tail * sp.S), dim3(kThreads), 0, s, A,
                        P, Q, N, sp.full, sp.S, c->gemm_part, c->low_order, skip);
     hipError_t e = hipGetLastError();

@@ -41,7 +41,7 @@ struct ze_ctx {
     double* fac_dinv = nullptr;
 
     // Step workspaces, N x N complex each.
-    double2* Wn = nullptr;   // copy of W_n
+    double2* Wn = nullptr;   // second state buffer: a run's steps alternate between it and W
     double2* F = nullptr;    // fixed-point iterate W~ (after the first evaluation)
     double2* P = nullptr;    // stream matrix
     double2* A = nullptr;    // A = P W~
@@ -54,7 +54,7 @@ struct ze_ctx {
     double* host_resid_dev = nullptr;  // its device address
 
     // Products: concurrent-block capacities and the split-K partial buffer.
-    int cap_full = 0, cap_low = 0;
+    int cap_full = 0, cap_low = 0, cus = 0;
     double* gemm_part = nullptr;
     int* low_order = nullptr;  // lower-product tiles in 8 x 8 super-tile order
 
@@ -180,7 +180,7 @@ hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hi
 
 // Blocks of the two product kernels that fit on the device at once, and the bytes of the
 // split-K partial buffer (ze_ctx::gemm_part) those capacities need.
-hipError_t ze_gemm_capacity(int* cap_full, int* cap_low);
+hipError_t ze_gemm_capacity(int* cap_full, int* cap_low, int* cus);
 size_t ze_gemm_part_bytes(int cap_full, int cap_low);
 // Lower-triangle tile indices (64 x 64 complex tiles) in 8 x 8 super-tile order.
 void ze_lower_tile_order(int N, std::vector<int>& order);
@@ -248,17 +248,18 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
                                double* rowpart, double h, const int* ea, const int* eb,
                                hipStream_t s, const int* skip = nullptr);
 
-// On-device stopping: start of a run (clears the run's records); start of a substep (Wn <- W,
-// done and the substep's count cleared; first: also the step's); end of a substep (its count
-// and residual into the step's; last: the step's record written at its index, run totals).
+// On-device stopping: start of a run (clears the run's totals and the first step's fields);
+// end of a substep (its count and residual into the step's, then its done flag and count
+// cleared; last: the step's record written at its index, run totals, the step's fields
+// cleared).
 hipError_t launch_ctl_run_begin(int* ctl, double* ctld, hipStream_t s);
-hipError_t launch_ctl_substep_begin(const double2* W, double2* Wn, int N, int* ctl, double* ctld,
-                                    bool first, hipStream_t s);
 hipError_t launch_ctl_substep_end(int* ctl, double* ctld, const double* resid, double tol, bool last,
                                   int* step_it, double* step_r, hipStream_t s);
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, hipStream_t s);
+// dst <- src, N x N complex (a kernel, so a captured graph holds no copy node).
+hipError_t launch_copy(const double2* src, double2* dst, int N, hipStream_t s);
 // out = polynomial extrapolation of degree d (1..3) through Fs[0] (newest) .. Fs[d], one step
 // ahead; out may be Fs[d].
 hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out, int N,

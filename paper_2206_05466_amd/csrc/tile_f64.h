@@ -180,6 +180,105 @@ __device__ __forceinline__ void store_full_tile(const d4 (&acc)[FullCfg::MT][Ful
     store_tile<FullCfg>(acc, Cm, N, row0, col0);
 }
 
+// ---------------------------------------------------------------- small products
+// Up to one tile per CU (N <= 512 on 256 CUs): one block per 32 x 32 complex tile of C.  Each
+// of the 4 waves takes a contiguous quarter of K and holds the whole tile (2 x 4 MFMA tiles,
+// 32 rows x 64 real columns).  A wave needs no LDS in its K loop: every lane loads from global
+// memory exactly the double its MFMA operand is (A~ entry; B~ entry, whose sign the lane
+// applies), kSmallDepth k-steps ahead in registers.  The quarters' sums are added in wave
+// order through LDS at the end.  No split-K partial sums and no fix-up launch.
+constexpr int kSmallTile = 32;
+constexpr int kSmallDepth = 8;                         // k-steps of loads in flight per wave
+constexpr int kSmallRed = 4 * 8 * 4 * 64;              // the 4 waves' sums (doubles)
+
+// C[row0:row0+32, col0:col0+32] = A[row0:, :] B[:, col0:] (all N x N, leading dimension N),
+// bounds-checked; red holds kSmallRed doubles of LDS.
+__device__ __forceinline__ void small_product(const double2* __restrict__ A,
+                                              const double2* __restrict__ B,
+                                              double2* __restrict__ Cm, int N, int row0, int col0,
+                                              double* red) {
+    constexpr int P = kSmallDepth;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, l16 = lane & 15;
+    const int t = q & 1;   // real-k parity of this lane's k-row: 0 -> Re(a) row of B~, 1 -> Im(a)
+    const int u = l16 & 1; // real-column parity: 0 -> Re(c), 1 -> Im(c)
+    // one k-step = 4 real k = 2 complex k; lanes q = 0, 1 take the first, q = 2, 3 the second
+    const int kl = q >> 1;
+    const int kq0 = (int)((long long)wave * N / 4), kq1 = (int)((long long)(wave + 1) * N / 4);
+    const int nst = (kq1 - kq0 + 1) / 2;
+    // Clamped indices keep every load in bounds.  Rows and columns beyond N feed only outputs
+    // that are not stored; k beyond the quarter feeds only steps that are not computed, except
+    // the second k of the last step of an odd-length quarter, which is zeroed through a.
+    const int ra0 = min(row0 + l16, N - 1), ra1 = min(row0 + 16 + l16, N - 1);
+    int cb[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) cb[nt] = min(col0 + nt * 8 + (l16 >> 1), N - 1);
+    const int bcomp = t ^ u;  // B~[2k + t][2c + u] = +-(Re b, Im b)[t ^ u]
+    const double bsgn = (t == 1 && u == 0) ? -1.0 : 1.0;
+    const double* As = reinterpret_cast<const double*>(A);
+    const double* Bs = reinterpret_cast<const double*>(B);
+    d4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    double ring[P][6];
+    auto issue = [&](int st, double (&r)[6]) {
+        const int k = max(min(kq0 + 2 * st + kl, kq1 - 1), 0);
+        r[0] = As[2 * ((size_t)ra0 * N + k) + t];
+        r[1] = As[2 * ((size_t)ra1 * N + k) + t];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) r[2 + nt] = Bs[2 * ((size_t)k * N + cb[nt]) + bcomp];
+    };
+    auto mma = [&](const double (&r)[6], bool zero) {
+        const double a0 = zero ? 0.0 : r[0], a1 = zero ? 0.0 : r[1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double b = bsgn * r[2 + j];
+            acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][j], 0, 0, 0);
+            acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][j], 0, 0, 0);
+        }
+    };
+    const bool odd_last = ((kq1 - kq0) & 1) && kl == 1;
+#pragma unroll
+    for (int p = 0; p < P; ++p) issue(p, ring[p]);
+    int st = 0;
+    for (; st + P < nst; st += P) {  // every step of the group has a successor group
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            mma(ring[p], false);
+            issue(st + P + p, ring[p]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (st + p < nst) mma(ring[p], odd_last && st + p == nst - 1);
+    // the quarters' sums: each wave stores its 8 MFMA tiles, then wave w adds tiles 2w, 2w+1
+    // over the four waves in wave order and stores them
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[((wave * 8 + i * 4 + j) * 4 + r) * 64 + lane] = acc[i][j][r];
+    __syncthreads();
+    double* Cd = reinterpret_cast<double*>(Cm);
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+        const int tt = 2 * wave + t2, mt = tt / 4, nt = tt % 4;
+        const int cc = 2 * col0 + nt * 16 + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double x = red[((0 * 8 + tt) * 4 + r) * 64 + lane];
+            x += red[((1 * 8 + tt) * 4 + r) * 64 + lane];
+            x += red[((2 * 8 + tt) * 4 + r) * 64 + lane];
+            x += red[((3 * 8 + tt) * 4 + r) * 64 + lane];
+            const int row = row0 + mt * 16 + q + 4 * r;
+            if (row < N && cc < 2 * N) Cd[(size_t)row * 2 * N + cc] = x;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- lower product + epilogue
 using LowCfg = Cfg<64, 64, 32, 32, false>;
 constexpr int kTile = 64;  // square complex tile of the lower-triangle product

@@ -140,6 +140,25 @@ __device__ __forceinline__ void lower_update_tile(int I, int J, const double2* _
 
 // Update tile of a single context of size N: the largest of 64, 32, 16 whose lower tiles
 // number at least 512 (two rounds of one block per CU), else 16.
+// Row sum sum_X rowpart[X N + r] over the T slots of row r, added in slot order; the loads are
+// issued B at a time, so a small N (many slots of few rows) waits for T / B memory latencies
+// rather than T.
+template <int B>
+__device__ __forceinline__ double slot_row_sum(const double* __restrict__ rowpart, int T, int N,
+                                               int r) {
+    double v = 0.0;
+    int X = 0;
+    for (; X + B <= T; X += B) {
+        double t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = rowpart[(size_t)(X + u) * N + r];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v += t[u];
+    }
+    for (; X < T; ++X) v += rowpart[(size_t)X * N + r];
+    return v;
+}
+
 __host__ __device__ inline int update_tile_of(int N) {
     for (int ut = 64; ut > 16; ut /= 2) {
         const long long t = (N + ut - 1) / ut;

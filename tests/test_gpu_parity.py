@@ -87,7 +87,8 @@ def test_stream_solve_single_degree(dev):
 
 
 # ------------------------------------------------------------------ products
-@pytest.mark.parametrize("N", [1, 7, 64, 100, 128, 129, 200, 256])
+# sizes on both sides of the small kernel's limit (32 x 32 tiles, one per CU: N <= 512 on 256 CUs)
+@pytest.mark.parametrize("N", [1, 7, 64, 100, 128, 129, 200, 256, 511, 512, 513])
 def test_zgemm_small_integers_exact(dev, N):
     rng = np.random.default_rng(N)
     A = rng.integers(-8, 9, (N, N)) + 1j * rng.integers(-8, 9, (N, N))
@@ -97,7 +98,7 @@ def test_zgemm_small_integers_exact(dev, N):
     assert np.array_equal(C, A @ B)
 
 
-@pytest.mark.parametrize("N", [64, 131, 384])
+@pytest.mark.parametrize("N", [64, 131, 384, 512, 544])
 def test_zgemm_random(dev, N):
     rng = np.random.default_rng(N + 1)
     A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))

@@ -27,8 +27,10 @@ def test_noalloc_product_matches_context_product_twice():
 
     rng = np.random.default_rng(77)
     # N = 1000: 128 tiles of 128 x 64, a partial round split along K into partial sums in the
-    # array; N = 200: 8 tiles split 3 ways; N = 2048: whole rounds only, no partial sums
-    for N in (1000, 200, 2048):
+    # array; N = 600: 50 such tiles, split again (fewer partial sums over the last call's);
+    # N = 200: the small kernel (49 tiles of 32 x 32, no partial sums); N = 2048: whole rounds
+    # only, no partial sums
+    for N in (1000, 600, 200, 2048):
         A, B = _rand(rng, N), _rand(rng, N)
         Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
         out = torch.full((N, N), complex(np.nan, np.nan), dtype=torch.complex128, device="cuda")
