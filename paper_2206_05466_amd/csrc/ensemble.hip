@@ -58,7 +58,8 @@ struct EnsProb {
     double2* H3;
 };
 
-constexpr int kCopyParts = 16;
+// blocks per simulation of the whole-matrix passes (the step start, the run's last copy)
+constexpr int kCopyParts = 64;
 
 // Start of a step: the first iterate F (W_n is read where the previous step left it, Wn).
 // mode 0: F <- W_n; mode 1: F <- 2 W_n - F,
@@ -85,17 +86,16 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
     const double c2 = d == 1 ? -1.0 : (d == 2 ? -3.0 : -6.0);
     const double c3 = d == 2 ? 1.0 : 4.0;
     for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
-        const double2 w = p.Wn[e];
         if (n == 0) {
-            p.F[e] = w;
+            p.F[e] = p.Wn[e];
             continue;
         }
         double2 g;
         if (mode == 1) {
-            const double2 f = p.F[e];
+            const double2 w = p.Wn[e], f = p.F[e];
             g = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
         } else if (n == 1) {
-            const double2 f1 = p.H1[e];
+            const double2 w = p.Wn[e], f1 = p.H1[e];
             g = make_double2(2.0 * w.x - f1.x, 2.0 * w.y - f1.y);
         } else {
             const double2 f1 = p.H1[e], f2 = p.H2[e];
@@ -205,19 +205,21 @@ __global__ __launch_bounds__(kThreads) void ens_lower_kernel(const EnsProb* __re
     store_tile<LowCfg>(acc, p.Q, N, I * kTile, J * kTile);
 }
 
+// The fixed-point update of the FP64 products, on UT x UT lower tiles (work items (sim, tile)).
+template <int UT>
 __global__ __launch_bounds__(kUThreads) void ens_update_kernel(const EnsProb* __restrict__ probs,
                                                                const int2* __restrict__ work,
                                                                const int* __restrict__ done,
                                                                int eval, double h, int form) {
-    __shared__ double2 sT[kUT][kUT + 1];
+    __shared__ double2 sT[UT][UT + 1];
     const int2 it = work[blockIdx.x];
     if (done[it.x]) return;
     const EnsProb p = probs[it.x];
     const double2* Wt = p.F;
     int I, J;
     lower_tile(it.y, I, J);
-    lower_update_tile(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W, p.rowpart,
-                      p.N, h, form, sT);
+    lower_update_tile_t<UT>(I, J, p.Q, nullptr, nullptr, nullptr, 0, p.A, p.Wn, Wt, p.F, p.W,
+                            p.rowpart, p.N, h, form, sT);
 }
 
 // ---------------------------------------------------------------- split-precision phases
@@ -319,12 +321,12 @@ __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restric
                                                         int* __restrict__ done,
                                                         int* __restrict__ iters,
                                                         double* __restrict__ resid, int eval,
-                                                        double tol) {
+                                                        double tol, int ut) {
     __shared__ double sm[256];
     const int sim = blockIdx.x;
     if (done[sim]) return;
     const EnsProb p = probs[sim];
-    const int N = p.N, T = (N + kTile - 1) / kTile;
+    const int N = p.N, T = (N + ut - 1) / ut;  // row-sum slots of the update's ut x ut tiles
     double best = 0.0;
     for (int i = threadIdx.x; i < N; i += 256) {
         const double v = slot_row_sum<8>(p.rowpart, T, N, i);
@@ -418,6 +420,11 @@ struct ze_ens {
     int n_prod[2] = {0, 0};
     int2* work_low[2] = {nullptr, nullptr};                            // [order]
     int n_low = 0;
+    // the FP64 path's update tile (32, or 64 when a context's row-sum slots are 64 wide) and
+    // its lower tiles
+    int ut = 32;
+    int2* work_up[2] = {nullptr, nullptr};                             // [order]
+    int n_up = 0;
     // split-precision phases (work lists built at creation, buffers on first use)
     int slices = 5;  // min(5, split_max_slices(maxN)), set at creation
     int slices_low = 4;  // of the lower product Q = A P (its term enters F with h^2/4)
@@ -494,11 +501,15 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
                               e->dp, e->work_prod[1][order], e->done, k);
             ZE_ENS_LAUNCH(ens_lower_kernel, dim3(e->n_low), dim3(kThreads), 0, s, e->dp,
                           e->work_low[order], e->done);
-            ZE_ENS_LAUNCH(ens_update_kernel, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
-                          e->work_low[order], e->done, k, h, e->update_form);
+            if (e->ut == 32)
+                ZE_ENS_LAUNCH(ens_update_kernel<32>, dim3(e->n_up), dim3(kUThreads), 0, s, e->dp,
+                              e->work_up[order], e->done, k, h, e->update_form);
+            else
+                ZE_ENS_LAUNCH(ens_update_kernel<kUT>, dim3(e->n_low), dim3(kUThreads), 0, s, e->dp,
+                              e->work_low[order], e->done, k, h, e->update_form);
         }
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
-                      e->resid, k, tol);
+                      e->resid, k, tol, prec == ZE_PREC_SPLIT ? kUT : e->ut);
     }
     if (err == hipSuccess)
         ZE_ENS_LAUNCH(ens_stepc_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, s, e->stepc, -1,
@@ -692,6 +703,7 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
     for (auto& v : e->work_prod)
         for (int2* p : v) (void)hipFree(p);
     for (int2* p : e->work_low) (void)hipFree(p);
+    for (int2* p : e->work_up) (void)hipFree(p);
     for (int2* p : {e->w_rows0, e->w_rows1, e->w_cols, e->w_comb}) (void)hipFree(p);
     for (auto& v : e->w_i8)
         for (int2* p : v) (void)hipFree(p);
@@ -740,7 +752,10 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     if ((st = ens_alloc(&e->iters, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->resid, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->stepc, (size_t)1)) != ZE_OK) return fail(st);
-    std::vector<int> cs(nsim), c0(nsim), c1(nsim), cl(nsim);
+    std::vector<int> cs(nsim), c0(nsim), c1(nsim), cl(nsim), cu(nsim);
+    // the update's tile: 32, unless a context keeps only 64-wide row-sum slots
+    for (int i = 0; i < nsim; ++i)
+        if (e->ctx[i]->ut > 32) e->ut = kUT;
     std::vector<int> r0(nsim), r1(nsim), ccol(nsim), ccomb(nsim), i8f(nsim), i8l(nsim);
     for (int i = 0; i < nsim; ++i) {
         const int n = e->N[i], T = (n + kTile - 1) / kTile;
@@ -748,6 +763,8 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         c0[i] = tiles_of(n, 0);
         c1[i] = tiles_of(n, 1);
         cl[i] = T * (T + 1) / 2;
+        const int Tu = (n + e->ut - 1) / e->ut;
+        cu[i] = Tu * (Tu + 1) / 2;
         const int tr = (n + kI8BM - 1) / kI8BM, tn = (2 * n + kI8BN - 1) / kI8BN;
         r0[i] = n + (n + 63) / 64;
         r1[i] = n;
@@ -784,13 +801,15 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
     if ((st = upload_work(ws, &e->work_solve)) != ZE_OK) return fail(st);
     for (int order = 0; order < 2; ++order) {
         std::vector<int2> w0 = make_work(e->N, c0, order), w1 = make_work(e->N, c1, order);
-        std::vector<int2> wl = make_work(e->N, cl, order);
+        std::vector<int2> wl = make_work(e->N, cl, order), wu = make_work(e->N, cu, order);
         e->n_prod[0] = (int)w0.size();
         e->n_prod[1] = (int)w1.size();
         e->n_low = (int)wl.size();
         if ((st = upload_work(w0, &e->work_prod[0][order])) != ZE_OK) return fail(st);
         if ((st = upload_work(w1, &e->work_prod[1][order])) != ZE_OK) return fail(st);
         if ((st = upload_work(wl, &e->work_low[order])) != ZE_OK) return fail(st);
+        e->n_up = (int)wu.size();
+        if ((st = upload_work(wu, &e->work_up[order])) != ZE_OK) return fail(st);
     }
     if (hipMemcpy(e->dp, e->hp.data(), nsim * sizeof(EnsProb), hipMemcpyHostToDevice) != hipSuccess)
         return fail(ze_record_hip(hipGetLastError(), "ensemble descriptors"));
