@@ -297,6 +297,89 @@ def test_polynomial_start_one_evaluation_same_fixed_point():
         O.isomp_run(W, 0.005, 1, degree=4)
 
 
+def test_start_from_history_exact_on_polynomial_states_and_offsets():
+    """With states W_j = p(j) of degree k and midpoint offsets delta_j = q(j) of degree k - 1
+    (F_j = (W_j + W_{j+1})/2 + delta_j), the start of step k is exactly F_k; a degree k + 1
+    term c t^(k+1) in the states is missed by exactly half its (k+1)-th difference, (k+1)! c / 2
+    (the state extrapolation enters the start with weight 1/2); and the start equals the
+    midpoint polynomial of degree k - 1 plus the k-th backward difference of the states."""
+    from math import comb, factorial
+
+    rng = np.random.default_rng(11)
+    M = [rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6)) for _ in range(5)]
+    D = [rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6)) for _ in range(4)]
+
+    def p(t, deg):
+        return sum(M[i] * float(t) ** i for i in range(deg + 1))
+
+    def q(t, deg):
+        return sum(D[i] * float(t) ** i for i in range(deg + 1))
+
+    for k in (1, 2, 3):
+        states = [p(j, k) for j in range(k + 1)]
+        mids = [0.5 * (p(j, k) + p(j + 1, k)) + q(j, k - 1) for j in range(k)]
+        want = 0.5 * (p(k, k) + p(k + 1, k)) + q(k, k - 1)
+        got = O.start_from_history(mids, states)
+        assert np.abs(got - want).max() < 1e-11 * np.abs(want).max(), k
+        # the simplified form: midpoint polynomial of degree k - 1 + k-th difference of states
+        diff = sum((-1) ** j * comb(k, j) * states[k - j] for j in range(k + 1))
+        alt = O.extrapolate_midpoints(mids, k - 1) + diff
+        assert np.abs(got - alt).max() < 1e-11 * np.abs(want).max(), k
+        # one degree too many in the states
+        states1 = [p(j, k + 1) for j in range(k + 1)]
+        mids1 = [0.5 * (p(j, k + 1) + p(j + 1, k + 1)) + q(j, k - 1) for j in range(k)]
+        want1 = 0.5 * (p(k, k + 1) + p(k + 1, k + 1)) + q(k, k - 1)
+        miss = want1 - O.start_from_history(mids1, states1)
+        assert np.abs(miss - 0.5 * factorial(k + 1) * M[k + 1]).max() < 1e-10, k
+    with pytest.raises(ValueError):
+        O.start_from_history([M[0]], [M[0]])
+
+
+def test_start_from_history_orders_on_a_trajectory():
+    """On an IsoMP trajectory (N = 24, sigma_l = (l+1)^-1), halving h shrinks the distance of
+    the start of step 2 to that step's converged midpoint about 8x (O(h^3)) and of step 3
+    about 16x (O(h^4)); the midpoint polynomials alone give 4x and 8x."""
+    W0 = O.assemble(24, omega_coeffs(24, 0, "inv1"))
+
+    def errs(h):
+        Ws, Fs = [W0], []
+        for _ in range(4):
+            W1, _, _, F = O.isomp_step(Ws[-1], h, 1e-15, 80, return_midpoint=True,
+                                       update="difference")
+            Ws.append(W1)
+            Fs.append(F)
+        e = lambda a, b: float(np.abs(a - b).sum(axis=1).max())  # noqa: E731
+        return (e(O.start_from_history(Fs[:2], Ws[:3]), Fs[2]),
+                e(O.start_from_history(Fs[:3], Ws[:4]), Fs[3]),
+                e(O.extrapolate_midpoints(Fs[:2], 1), Fs[2]),
+                e(O.extrapolate_midpoints(Fs[:3], 2), Fs[3]))
+
+    a, b = errs(0.04), errs(0.02)
+    r = [x / y for x, y in zip(a, b)]
+    assert 6.5 < r[0] < 10 and 13 < r[1] < 20, r
+    assert 3.3 < r[2] < 4.8 and 6.5 < r[3] < 10, r
+    assert b[0] < 0.01 * b[2] and b[1] < 0.01 * b[3], b
+
+
+def test_solution_difference_start_saves_an_evaluation():
+    """The n4096 field law at N = 256, h = 0.005, difference form: with the states in the
+    starts of steps 2 and 3 the run takes 3, 2, 1, 1, ... evaluations (the midpoints alone:
+    3, 2, 2, 1, ...), its residuals stay below tol and it reaches the W_n-started trajectory
+    to 1e-12."""
+    W = O.assemble(256, omega_coeffs(256, 0, "inv1.5"))
+    Wa, ia, _ = O.isomp_run(W, 0.005, 12, 1e-12, 50, update="difference")
+    Wb, ib, _ = O.isomp_run(W, 0.005, 12, 1e-12, 50, extrapolate=True, degree=3,
+                            update="difference")
+    Wc, ic, rc = O.isomp_run(W, 0.005, 12, 1e-12, 50, extrapolate=True, degree=3,
+                             update="difference", solution_differences=True)
+    assert ib[:4] == [3, 2, 2, 1], ib
+    assert ic[:3] == [3, 2, 1] and all(k == 1 for k in ic[2:]), ic
+    assert max(rc) < 1e-12
+    assert np.linalg.norm(Wa - Wc) < 1e-12 * np.linalg.norm(Wa)
+    with pytest.raises(ValueError):
+        O.isomp_run(W, 0.005, 1, extrapolate=True, degree=2, solution_differences=True)
+
+
 def test_composition_polynomial_substep_starts():
     """Per-substep polynomial starts: for order 2 the composed run is the midpoint run with the
     same start, bit for bit; for orders 4 and 6 (difference form) every substep takes one
