@@ -179,6 +179,15 @@ ze_status ze_run_stats(ze_ctx* ctx, int nsteps, int* iters, double* resid);
  *           from its own midpoints of the earlier steps (the other substeps of the first
  *           step start as in mode 1).  Selecting it allocates 4 N x N complex buffers per
  *           substep, less the one F already is (kept until ze_destroy).
+ *   mode 3  as mode 2, and at order 2 the third and fourth steps of a run (n = 2, 3) add the
+ *           n-th backward difference of the run's states W_n .. W_0 to the midpoint
+ *           polynomial: each midpoint is the average of its step's two states plus an offset
+ *           of order h^2 (the sum of the two lines of eq. (isomp)), so extrapolating the next
+ *           state and the offset separately, which that sum works out to, gives an O(h^(n+1))
+ *           start where the midpoints alone give O(h^n); those steps then usually take one
+ *           evaluation.  Selecting it also allocates 2 N x N complex buffers, which hold the
+ *           run's first states (the steps' outputs rotate through them; a run that ends away
+ *           from the caller's W copies back once).  At order 4 or 6 it is mode 2.
  * Every mode restarts at the first step of each ze_isomp_run call.
  * Errors: ZE_EINVAL, ZE_ENOMEM.
  */

@@ -167,6 +167,8 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->fac_l);
     dfree(c->fac_dinv);
     dfree(c->Wn);
+    dfree(c->Wh[0]);
+    dfree(c->Wh[1]);
     for (double2* p : c->ring) dfree(p);  // ring[0] is the F allocation
     dfree(c->P);
     dfree(c->A);
@@ -480,18 +482,57 @@ ze_status isomp_step_device(ze_ctx* c, const double2* Win, double2* Wout, double
     return ZE_OK;
 }
 
-// Start of substep j of the step with index n in the run, guess mode 2: the next slot of
+// The state of a run: W_n in cur; a substep writes W_{n+1} into other, and the two swap.  The
+// caller's W and the context's Wn take turns (guess mode 3 at order 2: Wh[0], Wh[1] too, for
+// the first steps), and the run ends with a copy into the caller's W when the last substep
+// left it elsewhere.
+struct RunState {
+    double2* user;
+    double2* cur;
+    double2* other;
+};
+
+ze_status finish_run(ze_ctx* c, const RunState& rs) {
+    if (rs.cur != rs.user) ZE_HIP(launch_copy(rs.cur, rs.user, c->N, c->stream));
+    return ZE_OK;
+}
+
+// Start of substep j of the step with index n in the run, guess mode 2 (and 3): the next slot of
 // substep j's ring receives the polynomial of degree min(nm - 1, 3) through that substep's
 // nm = min(n, 4) previous midpoints when nm >= 2 (with four, the slot is the oldest one's,
 // overwritten in place), else W + rho (W - F_prev) from the previous substep's midpoint F_prev
 // (in F) when there is one; the slot then becomes F and receives this substep's midpoint.
-ze_status ring_start(ze_ctx* c, const void* W, size_t j, int n, double rho, StartFrom* start) {
+// hist (guess mode 3 at order 2): steps 2 and 3 also use the states W_0 .. W_n.
+ze_status ring_start(ze_ctx* c, const RunState& rs, size_t j, int n, double rho, bool hist,
+                     StartFrom* start) {
     const int N = c->N;
+    const void* W = rs.cur;
     double2** rg = c->ring.data() + 4 * j;
     const int head = c->rhead[j], next = (head + 1) & 3;
     double2* out = rg[next];
     const int nm = n < 4 ? n : 4;
-    if (nm >= 2) {
+    if (hist && (n == 2 || n == 3)) {
+        // guess mode 3: the midpoint polynomial of degree n - 1 through F_{n-1} .. F_0 plus the
+        // n-th backward difference of the states W_n .. W_0 (each midpoint is the average of
+        // its step's states plus an O(h^2) offset; the next state and the offset are each
+        // extrapolated one step ahead), newest first in both sums
+        static const double cf2[2] = {2.0, -1.0}, cf3[3] = {3.0, -3.0, 1.0};
+        static const double cw2[3] = {1.0, -2.0, 1.0}, cw3[4] = {1.0, -3.0, 3.0, -1.0};
+        const double2* states[4] = {rs.user, c->Wn, c->Wh[0], c->Wh[1]};  // W_0 .. W_3
+        const double2* src[kLinCombMax];
+        double coef[kLinCombMax];
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+            src[m] = rg[(head - i + 4) & 3];
+            coef[m++] = n == 2 ? cf2[i] : cf3[i];
+        }
+        for (int i = 0; i <= n; ++i) {
+            src[m] = states[n - i];
+            coef[m++] = n == 2 ? cw2[i] : cw3[i];
+        }
+        ZE_HIP(launch_lincomb(src, coef, m, out, N, c->stream));
+        *start = kFromF;
+    } else if (nm >= 2) {
         const int d = nm - 1 < 3 ? nm - 1 : 3;
         const double2* Fs[4];
         for (int i = 0; i <= d; ++i) Fs[i] = rg[(head - i + 4) & 3];
@@ -510,20 +551,6 @@ ze_status ring_start(ze_ctx* c, const void* W, size_t j, int n, double rho, Star
     return ZE_OK;
 }
 
-// The state of a run: W_n in cur; a substep writes W_{n+1} into other, and the two swap.  The
-// caller's W and the context's Wn take turns, and the run ends with a copy into the caller's
-// W when the last substep left it in Wn.
-struct RunState {
-    double2* user;
-    double2* cur;
-    double2* other;
-};
-
-ze_status finish_run(ze_ctx* c, const RunState& rs) {
-    if (rs.cur != rs.user) ZE_HIP(launch_copy(rs.cur, rs.user, c->N, c->stream));
-    return ZE_OK;
-}
-
 // One step of the context's order: a midpoint substep of size c_j h for every fraction c_j.
 // n is the step's index in the run.  Guess mode 1: every substep after the first of the call
 // (n > 0 or j > 0) starts from W + rho (W - F_prev), rho = c_j / c_{j-1} (cyclically, so 1
@@ -536,7 +563,10 @@ ze_status composed_step(ze_ctx* c, RunState& rs, double h, double tol, int maxit
     if (!c || !rs.cur) return ZE_EINVAL;
     const std::vector<double>& w = c->comp_w;
     const size_t ns = w.size();
-    if (c->guess_mode == 2) ZE_TRY(ze_ensure_rings(c, (int)ns));
+    if (c->guess_mode >= 2) ZE_TRY(ze_ensure_rings(c, (int)ns));
+    // guess mode 3 at order 2: steps 0 .. 3 write W_1 .. W_4 into Wn, Wh[0], Wh[1] and the
+    // caller's W, so W_0 .. W_3 are all in memory when step 3 starts; later steps alternate
+    const bool hist = c->guess_mode == 3 && ns == 1;
     int total = 0;
     double rmax = 0.0;
     ze_status out = ZE_OK;
@@ -544,7 +574,11 @@ ze_status composed_step(ze_ctx* c, RunState& rs, double h, double tol, int maxit
         const double rho = w[j] / w[j == 0 ? ns - 1 : j - 1];
         StartFrom start = kFromWn;
         if (c->guess_mode == 1 && (j > 0 || n > 0)) start = kLinear;
-        if (c->guess_mode == 2) ZE_TRY(ring_start(c, rs.cur, j, n, rho, &start));
+        if (c->guess_mode >= 2) ZE_TRY(ring_start(c, rs, j, n, rho, hist, &start));
+        if (hist && n <= 3) {
+            double2* const outs[4] = {c->Wn, c->Wh[0], c->Wh[1], rs.user};
+            rs.other = outs[n];
+        }
         int k = 0;
         double r = 0.0;
         const ze_status st = isomp_step_impl(c, rs.cur, rs.other, w[j] * h, tol, maxit, prec, start,
@@ -760,8 +794,11 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 }
 
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
-    if (!c || mode < 0 || mode > 2) return ZE_EINVAL;
-    if (mode == 2) ZE_TRY(ze_ensure_rings(c, (int)c->comp_w.size()));
+    if (!c || mode < 0 || mode > 3) return ZE_EINVAL;
+    if (mode >= 2) ZE_TRY(ze_ensure_rings(c, (int)c->comp_w.size()));
+    if (mode == 3)
+        for (double2*& b : c->Wh)
+            if (!b) ZE_TRY(dalloc(&b, (size_t)c->N * c->N));
     c->guess_mode = mode;
     return ZE_OK;
 }
@@ -779,7 +816,7 @@ ze_status ze_set_order(ze_ctx* c, int order) {
             for (double x : w) next.push_back(g * x);
         w.swap(next);
     }
-    if (c->guess_mode == 2) ZE_TRY(ze_ensure_rings(c, (int)w.size()));
+    if (c->guess_mode >= 2) ZE_TRY(ze_ensure_rings(c, (int)w.size()));
     c->comp_w = w;
     c->order = order;
     return ZE_OK;

@@ -45,6 +45,25 @@ __global__ __launch_bounds__(256) void extrapolate_poly_kernel(const double2* F1
     }
 }
 
+// out <- sum_i c_i src_i over m <= kLinCombMax matrices, added in index order (each entry read
+// before it is written, by the same thread).
+struct LinComb {
+    const double2* src[kLinCombMax];
+    double c[kLinCombMax];
+    int m;
+};
+
+__global__ __launch_bounds__(256) void lincomb_kernel(LinComb lc, double2* out, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        double2 o = make_double2(0.0, 0.0);
+        for (int i = 0; i < lc.m; ++i) {
+            const double2 v = lc.src[i][e];
+            o = make_double2(o.x + lc.c[i] * v.x, o.y + lc.c[i] * v.y);
+        }
+        out[e] = o;
+    }
+}
+
 // Input check of W: block b takes the 32 x 32 tile pair (I, J), (J, I), I >= J, of the lower
 // triangle of tiles, staged in LDS so both are read row-wise, and writes part[4 b ..]: the
 // largest |W_rc + conj(W_cr)| of the pair, the largest |W_rc| of both tiles, and (diagonal
@@ -208,6 +227,22 @@ hipError_t launch_extrapolate_poly(const double2* const* Fs, int d, double2* out
     hipLaunchKernelGGL(extrapolate_poly_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)),
                        dim3(256), 0, s, Fs[0], Fs[1], d >= 2 ? Fs[2] : nullptr,
                        d >= 3 ? Fs[3] : nullptr, out, n, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const double2* const* src, const double* coef, int m, double2* out, int N,
+                          hipStream_t s) {
+    if (m < 1 || m > kLinCombMax) return hipErrorInvalidValue;
+    LinComb lc{};
+    for (int i = 0; i < m; ++i) {
+        lc.src[i] = src[i];
+        lc.c[i] = coef[i];
+    }
+    lc.m = m;
+    const size_t n = (size_t)N * N;
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(lincomb_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
+                       s, lc, out, n);
     return hipGetLastError();
 }
 

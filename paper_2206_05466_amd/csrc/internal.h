@@ -82,13 +82,17 @@ struct ze_ctx {
 
     // Starting iterate of the steps after the first in ze_isomp_run: 0 = W_n, 1 = 2 W_n - F
     // (F = the previous step's converged midpoint, left in ze_ctx::F), 2 = the polynomial
-    // extrapolation of the last (up to 4) midpoints of the run.
+    // extrapolation of the last (up to 4) midpoints of the run, 3 = as 2, and at order 2 the
+    // starts of steps 2 and 3 add the n-th backward difference of the run's states.
     int guess_mode = 0;
     // Midpoint history of mode 2: a ring of 4 buffers per substep of a step, ring[4 j + i]
     // (ring[0] is the allocation F starts with; the others are allocated on first use); the
     // newest midpoint of substep j is ring[4 j + rhead[j]].
     std::vector<double2*> ring;
     std::vector<int> rhead;
+    // Guess mode 3 at order 2: two more state buffers, so that the states W_0 .. W_3 of a run's
+    // first steps stay in memory until the start of step 3 (allocated with the mode).
+    double2* Wh[2] = {nullptr, nullptr};
     // Order of the time step (2: the midpoint map; 4, 6: its symmetric compositions) and the
     // substep fractions c_j of one step.
     int order = 2;
@@ -258,6 +262,10 @@ hipError_t launch_ctl_substep_end(int* ctl, double* ctld, const double* resid, d
 
 // F <- 2 W - F (N x N complex).
 hipError_t launch_extrapolate(const double2* W, double2* F, int N, double rho, hipStream_t s);
+// out <- sum_i coef[i] src[i] (i = 0 .. m-1, in that order), N x N complex, m <= kLinCombMax.
+constexpr int kLinCombMax = 8;
+hipError_t launch_lincomb(const double2* const* src, const double* coef, int m, double2* out, int N,
+                          hipStream_t s);
 // dst <- src, N x N complex (a kernel, so a captured graph holds no copy node).
 hipError_t launch_copy(const double2* src, double2* dst, int N, hipStream_t s);
 // out = polynomial extrapolation of degree d (1..3) through Fs[0] (newest) .. Fs[d], one step

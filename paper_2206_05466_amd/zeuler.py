@@ -277,7 +277,9 @@ class Zeuler:
         """0: each step starts from W_n; 1: steps after the first in isomp_run start from the
         extrapolation 2 W_n - F_prev of the previous converged midpoint; 2 (order 2 only):
         from the polynomial extrapolation (degree up to 3) of the run's previous midpoints,
-        after which a step usually takes one evaluation."""
+        after which a step usually takes one evaluation; 3: as 2, with the run's states added
+        to the starts of its third and fourth steps (order 2), which saves their second
+        evaluation."""
         _check(self.lib.ze_set_initial_guess(self._ctx, int(mode)), "ze_set_initial_guess")
 
     def set_order(self, order: int):
