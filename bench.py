@@ -244,7 +244,7 @@ def small_leg(steps):
     N, h, tol = cfg["N"], cfg["h"], cfg["tol"]
     z = Zeuler(N)
     W0 = z.basis_assemble(omega_coeffs(N, cfg["seeds"][0], cfg["law"]))
-    z.set_initial_guess(2)
+    z.set_initial_guess(3)
     z.set_update_form(1)
     W = W0.clone()
     z.isomp_run(W, h, 2, tol, cfg["maxit"])
@@ -269,7 +269,7 @@ def small_leg(steps):
     sg = torch.cuda.Stream()
     zg = Zeuler(N, stream=sg)
     zg.set_stopping(1)
-    zg.set_initial_guess(2)
+    zg.set_initial_guess(3)
     zg.set_update_form(1)
     Wgr = W0.clone()
     graph = torch.cuda.CUDAGraph()
@@ -331,7 +331,7 @@ def long_leg(steps):
     z = Zeuler(N)
     W = z.basis_assemble(omega_coeffs(N, cfg["seed"], cfg["law"]))
     W /= float(np.linalg.norm(W.cpu().numpy(), 2))  # input recipe: unit spectral norm
-    z.set_initial_guess(2)
+    z.set_initial_guess(3)
     z.set_update_form(1)
     nf0 = float(torch.linalg.norm(W).item())
 
@@ -519,14 +519,21 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
     dt_p0, iters_p0, _, _ = timed_run(Ws2, PREC_FP64, 2, 0)
     log(f"{wname} fp64, polynomial start, second-line form: {dt_p0 / steps * 1e3:.2f} ms/step, "
         f"iters={iters_p0}")
-    # headline: polynomial extrapolation of the run's previous midpoints, W_{n+1} = W_n + h C
-    dt, iters, resids, prof = timed_run(W, PREC_FP64, 2, 1)
+    # the polynomial start from the midpoints alone, W_{n+1} = W_n + h C
+    Wm2 = W0.clone()
+    dt_m2, iters_m2, _, _ = timed_run(Wm2, PREC_FP64, 2, 1)
+    log(f"{wname} fp64, polynomial start (midpoints only): {dt_m2 / steps * 1e3:.2f} ms/step, "
+        f"iters={iters_m2}")
+    # headline: polynomial extrapolation of the run's previous midpoints, the third and fourth
+    # steps with the run's states as well, W_{n+1} = W_n + h C
+    dt, iters, resids, prof = timed_run(W, PREC_FP64, 3, 1)
     log(f"{wname} fp64, polynomial start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
     c1 = z.casimirs(W, 4)
     plain_vs_extrap = float(torch.linalg.norm(Wp - W).item() / torch.linalg.norm(W).item())
     lin_vs_extrap = float(torch.linalg.norm(Wl - W).item() / torch.linalg.norm(W).item())
     p0_vs_extrap = float(torch.linalg.norm(Ws2 - W).item() / torch.linalg.norm(W).item())
-    del Wl, Ws2
+    m2_vs_extrap = float(torch.linalg.norm(Wm2 - W).item() / torch.linalg.norm(W).item())
+    del Wl, Ws2, Wm2
     if copy_probe_mib > 0:
         n = copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -549,7 +556,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
         for ns in slist:
             z.set_split_slices(ns)
             Ws = W0.clone()
-            dts, its_s, _, profs = timed_run(Ws, PREC_SPLIT, 2)
+            dts, its_s, _, profs = timed_run(Ws, PREC_SPLIT, 3)
             cs = z.casimirs(Ws, 4)
             diff = float(torch.linalg.norm(Ws - W).item() / torch.linalg.norm(W).item())
             sps = dts / steps
@@ -592,6 +599,9 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
         "fp64_polynomial_start_second_line_form": {
             "s_per_step": dt_p0 / steps, "iters_per_step": list(iters_p0),
             "rel_frobenius_vs_headline_run": p0_vs_extrap},
+        "fp64_polynomial_start_midpoints_only": {
+            "s_per_step": dt_m2 / steps, "iters_per_step": list(iters_m2),
+            "rel_frobenius_vs_headline_run": m2_vs_extrap},
         "split_precision": split,
         "mixed_precision": mixed,
         "crt_precision": crt,
@@ -607,7 +617,7 @@ def crt_run(z, timed_run, W0, W, c0, dt, steps, wname):
 
     z.set_split_slices(5)
     Wc = W0.clone()
-    dtc, its_c, res_c, prof_c = timed_run(Wc, PREC_CRT, 2)
+    dtc, its_c, res_c, prof_c = timed_run(Wc, PREC_CRT, 3)
     N = W.shape[0]
     Xa, Xb = W0.clone(), Wc.clone()
     out = torch.empty_like(Xa)
@@ -647,7 +657,7 @@ def mixed_run(z, timed_run, W0, W, c0, dt, steps, wname):
 
     z.set_split_slices(5)
     Wm = W0.clone()
-    dtm, its_m, res_m, prof_m = timed_run(Wm, PREC_MIXED, 2)
+    dtm, its_m, res_m, prof_m = timed_run(Wm, PREC_MIXED, 3)
     mixed = {
         "s_per_step": dtm / steps, "speedup_vs_fp64": dt / dtm,
         "iters_per_step": list(its_m), "max_resid": max(res_m), "lower_product_slices": 4,
@@ -878,8 +888,11 @@ def main():
         "iters_per_step": iters,
         "max_resid": m["max_resid"],
         "initial_guess": "the second step starts from 2 W_n - F_prev, later ones from the polynomial "
-                         "(degree <= 3) through the run's previous midpoints (ze_set_initial_guess 2); "
-                         "every step still iterates until the change is below tol",
+                         "(degree <= 3) through the run's previous midpoints, the third and fourth "
+                         "with the n-th backward difference of the run's states added "
+                         "(ze_set_initial_guess 3); every step still iterates until the change "
+                         "is below tol",
+        "fp64_polynomial_start_midpoints_only": m["fp64_polynomial_start_midpoints_only"],
         "fp64_start_from_Wn": m["fp64_start_from_Wn"],
         "fp64_linear_start": m["fp64_linear_start"],
         "fp64_polynomial_start_second_line_form": m["fp64_polynomial_start_second_line_form"],

@@ -3,7 +3,8 @@
 
 The full-size parity tests step the workloads' full-spectrum fields (every degree l <= N - 1)
 in the configuration bench.py times: polynomial starting iterate from the run's midpoints
-(degree 3), W_{n+1} = W_n + h (A - A^H), tol 1e-12.  The oracle needs minutes for that at
+(degree 3; the third and fourth steps from the midpoints and the states), W_{n+1} = W_n +
+h (A - A^H), tol 1e-12.  The oracle needs minutes for that at
 N = 2048 and 4096 (the full eigenvector basis of every diagonal, then dense FP64 products),
 so this script runs it once and stores what the tests compare against: every entry of a few
 rows and a seeded random sample of entries, of W_0 and of the state after the stored step
@@ -51,7 +52,8 @@ def make(N, workers):
     W0 = oracle.assemble(N, omega_coeffs(N, seed, cfg["law"]), workers=workers)
     print(f"N={N}: W_0 assembled in {time.time() - t0:.0f} s", flush=True)
     out = {"N": N, "h": cfg["h"], "tol": cfg["tol"], "maxit": cfg["maxit"], "seed": seed,
-           "law": cfg["law"], "degree": 3, "update": "difference", "steps": np.array(counts),
+           "law": cfg["law"], "degree": 3, "solution_differences": True,
+           "update": "difference", "steps": np.array(counts),
            "rows": rows, "sample_r": r, "sample_c": c}
 
     def store(tag, W):
@@ -69,7 +71,7 @@ def make(N, workers):
 
     _, iters, res = oracle.isomp_run(W0, cfg["h"], max(counts), cfg["tol"], cfg["maxit"],
                                      extrapolate=True, degree=3, update="difference",
-                                     on_step=on_step)
+                                     on_step=on_step, solution_differences=True)
     out["iters"] = np.array(iters)
     out["resid"] = np.array(res)
     path = os.path.join(HERE, f"fullsize_n{N}.npz")

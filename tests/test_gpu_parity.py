@@ -180,7 +180,7 @@ def test_isomp_fixed_iterations_and_errors(dev):
         with pytest.raises(ZeulerError, match="non-finite"):
             z.isomp_step(bad, 0.1, 1e-12, 5)
         with pytest.raises(ZeulerError):
-            z.set_initial_guess(3)
+            z.set_initial_guess(4)
         with pytest.raises(ZeulerError):
             z.set_split_slices(1)
         lib = z.lib
@@ -681,7 +681,7 @@ def test_isomp_run_polynomial_guess(dev, N, law, h, steps, form):
 def test_isomp_polynomial_guess_split_and_mode_errors(dev):
     """Mode 2 with the split-precision products (5 slices) and the difference form of W_{n+1}
     against the oracle's FP64 run (1e-10), one evaluation per step at the end; update forms
-    other than 0 and 1 and guess modes outside 0..2 are rejected."""
+    other than 0 and 1 and guess modes outside 0..3 are rejected."""
     from paper_2206_05466_amd import PREC_SPLIT, ZeulerError
 
     N, h = 128, 0.005
@@ -698,7 +698,7 @@ def test_isomp_polynomial_guess_split_and_mode_errors(dev):
         its, res = z.isomp_run(Wd, h, 10, 1e-12, 50, prec=PREC_SPLIT)
         W = to_host(Wd)
         with pytest.raises(ZeulerError):
-            z.set_initial_guess(3)
+            z.set_initial_guess(4)
     assert max(res) < 1e-12 and its[-1] == 1, its
     assert np.linalg.norm(W - Wr) <= 1e-10 * np.linalg.norm(Wr)
 

@@ -2,7 +2,8 @@
 
 Full sizes (N = 4096 and 2048): the workloads' full-spectrum fields (every degree l <= N - 1),
 W_0 assembled by the library's basis kernel as in the bench; polynomial starting iterate from
-the run's midpoints, W_{n+1} = W_n + h (A - A^H), tol 1e-12; FP64, the split form at the
+the run's midpoints, the third and fourth steps with the run's states as well (guess mode 3,
+the oracle's solution_differences), W_{n+1} = W_n + h (A - A^H), tol 1e-12; FP64, the split form at the
 bench's slice count (4; the lower product 3), the modular INT8 form and the mixed form.  The
 oracle's trajectories come from tests/golden/fullsize_n*.npz (written by
 make_fullsize_reference.py there, which calls only the oracle): every entry of three rows and
@@ -70,7 +71,8 @@ def casimir_drift(z, Wd, c0, nf0):
 
 def run_timed(z, W0d, ref, steps, prec, slices=None):
     cfg_h, tol, maxit = float(ref["h"]), float(ref["tol"]), int(ref["maxit"])
-    z.set_initial_guess(2)
+    assert bool(ref["solution_differences"])  # the stored run's start: guess mode 3
+    z.set_initial_guess(3)
     z.set_update_form(1)
     if slices is not None:
         z.set_split_slices(slices)
