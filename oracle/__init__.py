@@ -30,13 +30,14 @@ on tiny N and invariants that the paper and the mathematics fix (see the docstri
 from .laplacian import delta_tridiag, spin_matrices, brute_laplacian, apply_laplacian
 from .stream import stream_solve
 from .isomp import (isomp_step, isomp_run, extrapolate_midpoints, start_from_history,
-                    composition_weights, isomp_composed_run)
+                    start_second_step, composition_weights, isomp_composed_run)
 from .casimirs import casimirs, casimirs_eig
 from .basis import eigvecs, assemble, extract, energy_spectrum
 
 __all__ = [
     "delta_tridiag", "spin_matrices", "brute_laplacian", "apply_laplacian",
     "stream_solve", "isomp_step", "isomp_run", "extrapolate_midpoints", "start_from_history",
+    "start_second_step",
     "composition_weights", "isomp_composed_run", "casimirs", "casimirs_eig",
     "eigvecs", "assemble", "extract", "energy_spectrum",
 ]

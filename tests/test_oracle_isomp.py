@@ -335,6 +335,37 @@ def test_start_from_history_exact_on_polynomial_states_and_offsets():
         O.start_from_history([M[0]], [M[0]])
 
 
+def test_start_second_step_exact_on_quadratic_states():
+    """States on a quadratic W(t) = a + b t + c t^2 sampled at t = 0, h, 2h (slope b at t = 0)
+    with a constant midpoint offset: the second step's start is exactly F_1; with a cubic term
+    d t^3 as well it misses F_1 by exactly 2 d h^3 (half of what the quadratic misses W(2h)
+    by); and the slope formed from Delta_N^+ when not given is P W_0 - W_0 P."""
+    rng = np.random.default_rng(5)
+    a, b, c, d, e = [rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5)) for _ in range(5)]
+    h = 0.3
+
+    def W(t, cubic=0.0):
+        return a + b * t + c * t * t + cubic * d * t ** 3
+
+    F0 = 0.5 * (W(0) + W(h)) + e
+    F1 = 0.5 * (W(h) + W(2 * h)) + e
+    got = O.start_second_step(F0, W(0), W(h), h, D0=b)
+    assert np.abs(got - F1).max() < 1e-12 * np.abs(F1).max()
+    # with d t^3: the quadratic (W0, slope b, W1) extrapolates W(2h) = ... + 8 d h^3 as
+    # 4 W(h) - 3 W(0) - 2 h b = ... + 4 d h^3, so the start misses F_1 by (8 - 4) d h^3 / 2
+    F0c = 0.5 * (W(0, 1) + W(h, 1)) + e
+    F1c = 0.5 * (W(h, 1) + W(2 * h, 1)) + e
+    miss = F1c - O.start_second_step(F0c, W(0, 1), W(h, 1), h, D0=b)
+    assert np.abs(miss - 2.0 * d * h ** 3).max() < 1e-12
+    # the slope from the definition: D0 = P W0 - W0 P with P = Delta_N^+ W0
+    W0 = O.assemble(12, omega_coeffs(12, 3, "inv1"))
+    P = O.stream_solve(W0)
+    D0 = P @ W0 - W0 @ P
+    F = W0 + 0.1 * D0
+    diff = O.start_second_step(F, W0, F, 0.01) - O.start_second_step(F, W0, F, 0.01, D0=D0)
+    assert np.abs(diff).max() < 1e-15
+
+
 def test_start_from_history_orders_on_a_trajectory():
     """On an IsoMP trajectory (N = 24, sigma_l = (l+1)^-1), halving h shrinks the distance of
     the start of step 2 to that step's converged midpoint about 8x (O(h^3)) and of step 3
@@ -352,20 +383,24 @@ def test_start_from_history_orders_on_a_trajectory():
         return (e(O.start_from_history(Fs[:2], Ws[:3]), Fs[2]),
                 e(O.start_from_history(Fs[:3], Ws[:4]), Fs[3]),
                 e(O.extrapolate_midpoints(Fs[:2], 1), Fs[2]),
-                e(O.extrapolate_midpoints(Fs[:3], 2), Fs[3]))
+                e(O.extrapolate_midpoints(Fs[:3], 2), Fs[3]),
+                e(O.start_second_step(Fs[0], Ws[0], Ws[1], h), Fs[1]),
+                e(2.0 * Ws[1] - Fs[0], Fs[1]))
 
     a, b = errs(0.04), errs(0.02)
     r = [x / y for x, y in zip(a, b)]
     assert 6.5 < r[0] < 10 and 13 < r[1] < 20, r
     assert 3.3 < r[2] < 4.8 and 6.5 < r[3] < 10, r
-    assert b[0] < 0.01 * b[2] and b[1] < 0.01 * b[3], b
+    assert 6.5 < r[4] < 10 and 3.3 < r[5] < 4.8, r  # second step: O(h^3) against O(h^2)
+    assert b[0] < 0.01 * b[2] and b[1] < 0.01 * b[3] and b[4] < 0.01 * b[5], b
 
 
 def test_solution_difference_start_saves_an_evaluation():
-    """The n4096 field law at N = 256, h = 0.005, difference form: with the states in the
-    starts of steps 2 and 3 the run takes 3, 2, 1, 1, ... evaluations (the midpoints alone:
-    3, 2, 2, 1, ...), its residuals stay below tol and it reaches the W_n-started trajectory
-    to 1e-12."""
+    """The n4096 field law at N = 256, h = 0.005, difference form: with the slope at W_0 in
+    the second step's start and the states in the third's and fourth's the run takes
+    3, 1, 1, ... evaluations (the midpoints alone: 3, 2, 2, 1, ...), its residuals stay below
+    tol and it reaches the W_n-started trajectory to 1e-12; with the second-line form the second
+    step keeps the linear start."""
     W = O.assemble(256, omega_coeffs(256, 0, "inv1.5"))
     Wa, ia, _ = O.isomp_run(W, 0.005, 12, 1e-12, 50, update="difference")
     Wb, ib, _ = O.isomp_run(W, 0.005, 12, 1e-12, 50, extrapolate=True, degree=3,
@@ -373,9 +408,13 @@ def test_solution_difference_start_saves_an_evaluation():
     Wc, ic, rc = O.isomp_run(W, 0.005, 12, 1e-12, 50, extrapolate=True, degree=3,
                              update="difference", solution_differences=True)
     assert ib[:4] == [3, 2, 2, 1], ib
-    assert ic[:3] == [3, 2, 1] and all(k == 1 for k in ic[2:]), ic
+    assert ic[0] == 3 and all(k == 1 for k in ic[1:]), ic
     assert max(rc) < 1e-12
     assert np.linalg.norm(Wa - Wc) < 1e-12 * np.linalg.norm(Wa)
+    _, idd, _ = O.isomp_run(W, 0.005, 5, 1e-12, 50, extrapolate=True, degree=3,
+                            solution_differences=True)
+    _, ie, _ = O.isomp_run(W, 0.005, 5, 1e-12, 50, extrapolate=True, degree=3)
+    assert idd[:2] == ie[:2], (idd, ie)
     with pytest.raises(ValueError):
         O.isomp_run(W, 0.005, 1, extrapolate=True, degree=2, solution_differences=True)
 
