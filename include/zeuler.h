@@ -185,9 +185,13 @@ ze_status ze_run_stats(ze_ctx* ctx, int nsteps, int* iters, double* resid);
  *           of order h^2 (the sum of the two lines of eq. (isomp)), so extrapolating the next
  *           state and the offset separately, which that sum works out to, gives an O(h^(n+1))
  *           start where the midpoints alone give O(h^n); those steps then usually take one
- *           evaluation.  Selecting it also allocates 2 N x N complex buffers, which hold the
- *           run's first states (the steps' outputs rotate through them; a run that ends away
- *           from the caller's W copies back once).  At order 4 or 6 it is mode 2.
+ *           evaluation.  With the difference form of W_{n+1} (ze_set_update_form 1) the second
+ *           step too starts from F_0 + 2 (W_1 - W_0) - h D_0, D_0 = P_0 W_0 - W_0 P_0 the slope
+ *           at W_0 (kept from the first step's first evaluation, whose W_{n+1} is W_0 + h D_0):
+ *           O(h^3) against the linear start's O(h^2).  Selecting it also allocates 3 N x N
+ *           complex buffers: two hold the run's first states (the steps' outputs rotate
+ *           through them; a run that ends away from the caller's W copies back once), one
+ *           W_0 + h D_0.  At order 4 or 6 it is mode 2.
  * Every mode restarts at the first step of each ze_isomp_run call.
  * Errors: ZE_EINVAL, ZE_ENOMEM.
  */

@@ -169,6 +169,7 @@ ze_status ze_destroy(ze_ctx* c) {
     dfree(c->Wn);
     dfree(c->Wh[0]);
     dfree(c->Wh[1]);
+    dfree(c->Wd);
     for (double2* p : c->ring) dfree(p);  // ring[0] is the F allocation
     dfree(c->P);
     dfree(c->A);
@@ -405,6 +406,7 @@ ze_status isomp_step_impl(ze_ctx* c, const double2* Win, double2* Wout, double h
         ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax,
                                    reinterpret_cast<unsigned*>(c->dctl + kCtlCounter), c->resid, N, s,
                                    nullptr, nullptr, 0.0, c->host_resid_dev));
+        if (k == 1 && c->save_first) ZE_HIP(launch_copy(Wu, c->save_first, N, s));
         if (prof) ZE_HIP(hipEventRecord(c->ev[4], s));
         ZE_HIP(hipStreamSynchronize(s));
         if (prof) {
@@ -476,6 +478,8 @@ ze_status isomp_step_device(ze_ctx* c, const double2* Win, double2* Wout, double
         }
         ZE_HIP(launch_resid_reduce(c->rowpart, (N + c->ut - 1) / c->ut, c->blockmax, counter,
                                    c->resid, N, s, skip, c->dctl, tol));
+        // the first evaluation always runs: its W_{n+1} is kept unguarded
+        if (k == 1 && c->save_first) ZE_HIP(launch_copy(Wu, c->save_first, N, s));
         Wt = c->F;
     }
     ZE_HIP(launch_ctl_substep_end(c->dctl, c->dctld, c->resid, tol, last, c->dstep_it, c->dstep_r, s));
@@ -490,6 +494,7 @@ struct RunState {
     double2* user;
     double2* cur;
     double2* other;
+    int nsteps;  // steps of the run (the first step keeps its first output only if there are more)
 };
 
 ze_status finish_run(ze_ctx* c, const RunState& rs) {
@@ -502,7 +507,8 @@ ze_status finish_run(ze_ctx* c, const RunState& rs) {
 // nm = min(n, 4) previous midpoints when nm >= 2 (with four, the slot is the oldest one's,
 // overwritten in place), else W + rho (W - F_prev) from the previous substep's midpoint F_prev
 // (in F) when there is one; the slot then becomes F and receives this substep's midpoint.
-// hist (guess mode 3 at order 2): steps 2 and 3 also use the states W_0 .. W_n.
+// hist (guess mode 3 at order 2): steps 2 and 3 also use the states W_0 .. W_n, and with the
+// difference form step 1 the slope at W_0 (from the first step's first evaluation).
 ze_status ring_start(ze_ctx* c, const RunState& rs, size_t j, int n, double rho, bool hist,
                      StartFrom* start) {
     const int N = c->N;
@@ -531,6 +537,14 @@ ze_status ring_start(ze_ctx* c, const RunState& rs, size_t j, int n, double rho,
             coef[m++] = n == 2 ? cw2[i] : cw3[i];
         }
         ZE_HIP(launch_lincomb(src, coef, m, out, N, c->stream));
+        *start = kFromF;
+    } else if (hist && n == 1 && c->update_form == 1) {
+        // guess mode 3, difference form: F_0 + 2 (W_1 - W_0) - h D_0, with h D_0 = Wd - W_0
+        // (Wd: the first step's first output, W_0 + h (P_0 W_0 - W_0 P_0)), formed as
+        // F_0 + 2 W_1 - W_0 - Wd
+        const double2* src[4] = {rg[head], rs.cur, rs.user, c->Wd};
+        const double coef[4] = {1.0, 2.0, -1.0, -1.0};
+        ZE_HIP(launch_lincomb(src, coef, 4, out, N, c->stream));
         *start = kFromF;
     } else if (nm >= 2) {
         const int d = nm - 1 < 3 ? nm - 1 : 3;
@@ -579,10 +593,13 @@ ze_status composed_step(ze_ctx* c, RunState& rs, double h, double tol, int maxit
             double2* const outs[4] = {c->Wn, c->Wh[0], c->Wh[1], rs.user};
             rs.other = outs[n];
         }
+        // the second step's start needs h D_0 = (first output of step 0) - W_0
+        c->save_first = (hist && n == 0 && rs.nsteps >= 2 && c->update_form == 1) ? c->Wd : nullptr;
         int k = 0;
         double r = 0.0;
         const ze_status st = isomp_step_impl(c, rs.cur, rs.other, w[j] * h, tol, maxit, prec, start,
                                              rho, &k, &r, j + 1 == ns);
+        c->save_first = nullptr;
         if (st == ZE_OK || st == ZE_ENOTCONV || st == ZE_ENONFINITE) std::swap(rs.cur, rs.other);
         total += k;
         if (!(r <= rmax)) rmax = r;  // keeps a NaN
@@ -642,7 +659,7 @@ static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit,
         return ZE_EINVAL;
     if (!is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
-    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, nsteps};
     for (int n = 0; n < nsteps; ++n) {
         const ze_status st = composed_step(c, rs, h, tol, maxit, prec, n, nullptr, nullptr);
         if (st != ZE_OK) {
@@ -662,7 +679,7 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     if (!c || !W) return ZE_EINVAL;
     if (c->validate) ZE_TRY(check_su(c, W));
     if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, 1, prec, iters, resid);
-    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, 1};
     const ze_status st = composed_step(c, rs, h, tol, maxit, prec, 0, iters, resid);
     const ze_status fin = finish_run(c, rs);
     return st != ZE_OK ? st : fin;
@@ -700,7 +717,7 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
     if (c->validate && nsteps > 0) ZE_TRY(check_su(c, W));
     if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, nsteps, prec, iters, resid);
-    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn};
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, nsteps};
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
@@ -796,9 +813,11 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
     if (!c || mode < 0 || mode > 3) return ZE_EINVAL;
     if (mode >= 2) ZE_TRY(ze_ensure_rings(c, (int)c->comp_w.size()));
-    if (mode == 3)
+    if (mode == 3) {
         for (double2*& b : c->Wh)
             if (!b) ZE_TRY(dalloc(&b, (size_t)c->N * c->N));
+        if (!c->Wd) ZE_TRY(dalloc(&c->Wd, (size_t)c->N * c->N));
+    }
     c->guess_mode = mode;
     return ZE_OK;
 }

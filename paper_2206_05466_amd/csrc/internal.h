@@ -93,6 +93,11 @@ struct ze_ctx {
     // Guess mode 3 at order 2: two more state buffers, so that the states W_0 .. W_3 of a run's
     // first steps stay in memory until the start of step 3 (allocated with the mode).
     double2* Wh[2] = {nullptr, nullptr};
+    // ... and with the difference form of W_{n+1}, the first evaluation's W_{n+1} of a run's
+    // first step, W_0 + h (P_0 W_0 - W_0 P_0), for the second step's start (allocated with the
+    // mode); save_first points at it while that step is enqueued, else null.
+    double2* Wd = nullptr;
+    double2* save_first = nullptr;
     // Order of the time step (2: the midpoint map; 4, 6: its symmetric compositions) and the
     // substep fractions c_j of one step.
     int order = 2;

@@ -278,8 +278,8 @@ class Zeuler:
         extrapolation 2 W_n - F_prev of the previous converged midpoint; 2 (order 2 only):
         from the polynomial extrapolation (degree up to 3) of the run's previous midpoints,
         after which a step usually takes one evaluation; 3: as 2, with the run's states added
-        to the starts of its third and fourth steps (order 2), which saves their second
-        evaluation."""
+        to the starts of its third and fourth steps (order 2) and, with update form 1, the
+        slope at W_0 to the second step's, which saves their second evaluations."""
         _check(self.lib.ze_set_initial_guess(self._ctx, int(mode)), "ze_set_initial_guess")
 
     def set_order(self, order: int):

@@ -1,5 +1,6 @@
 """Guess mode 3: the third and fourth steps of a run start from the midpoint polynomial plus the
-backward difference of the run's states (the oracle's ``solution_differences``).
+backward difference of the run's states, and with the difference form the second from the first
+midpoint, the states and the slope at W_0 (the oracle's ``solution_differences``).
 
 Checked against the oracle: evaluation counts equal and states within 1e-12 (relative
 Frobenius) for both update forms and runs of every length up to 6 steps (the states rotate
