@@ -167,7 +167,7 @@ def ensemble_leg(nsteps, prec, ref=None, with_cpu=False):
     Ws = [ctxs[n].basis_assemble(omega_coeffs(n, cfg["seed0"] + j, cfg["law"])) for j, n in enumerate(sizes)]
     Wseq = [W.clone() for W in Ws]
     ens = Ensemble(sizes)
-    ens.set_initial_guess(2)  # polynomial start from the run's midpoints (reading 9)
+    ens.set_initial_guess(3)  # polynomial start, steps 1-3 with the run's states (reading 9)
     ens.set_update_form(1)    # W_{n+1} = W_n + h (A - A^H) (reading 12)
     ens.set_steady_cap(cfg["steady_cap"], cfg["steady_from"])
     if split:
@@ -191,7 +191,7 @@ def ensemble_leg(nsteps, prec, ref=None, with_cpu=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for j, n in enumerate(sizes):
-        ctxs[n].set_initial_guess(2)
+        ctxs[n].set_initial_guess(3)
         ctxs[n].set_update_form(1)
         ctxs[n].isomp_run(Wseq[j], h, seq_steps, tol, K, prec=prec)
     torch.cuda.synchronize()

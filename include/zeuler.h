@@ -436,10 +436,13 @@ ze_status ze_ensemble_set_update_form(ze_ens* ens, int form);
  * evaluation per step at the same stopping rule; 2: the polynomial start of
  * ze_set_initial_guess mode 2 per simulation (linear at the second step of the call, then
  * degrees 1, 2, 3 through its previous midpoints), one evaluation per step after the
- * start-up; one captured graph reads the step's index in the call from device memory.
- * Selecting mode 2 allocates three N_j x N_j complex buffers per simulation.  Takes effect at
- * the next ze_ensemble_run (the step graphs are captured again).
- * Errors: ZE_EINVAL (mode not 0, 1 or 2), ZE_ENOMEM.
+ * start-up; one captured graph reads the step's index in the call from device memory; 3: as
+ * ze_set_initial_guess mode 3 per simulation (the third and fourth steps with the run's states,
+ * with the difference form the second with the slope at W_0; the first states rotate through
+ * two more buffers per simulation, the rotation done on the device at each step's end).
+ * Selecting mode 2 allocates three N_j x N_j complex buffers per simulation, mode 3 three more.
+ * Takes effect at the next ze_ensemble_run (the step graphs are captured again).
+ * Errors: ZE_EINVAL (mode not 0 .. 3), ZE_ENOMEM.
  */
 ze_status ze_ensemble_set_initial_guess(ze_ens* ens, int mode);
 

@@ -56,6 +56,12 @@ struct EnsProb {
     double2* H1;
     double2* H2;
     double2* H3;
+    // guess mode 3: two more state buffers (the first steps' outputs rotate through X, S1, S2
+    // and Wc, so W_0 .. W_3 are in memory at the start of step 3) and the first step's first
+    // output W_0 + h D_0 (difference form); null until that mode is selected
+    double2* S1;
+    double2* S2;
+    double2* Wd;
 };
 
 // blocks per simulation of the whole-matrix passes (the step start, the run's last copy)
@@ -74,13 +80,42 @@ constexpr int kCopyParts = 64;
 // Every evaluation then reads its iterate from F (the update rewrites it in place: each entry
 // it reads is written by the same thread, and the mirrored upper entries it writes are read by
 // no other block of that launch).
+// mode 3 (guess mode 3; slope: with the difference form): as mode 2, except that step 1 starts
+// from F_0 + 2 W_1 - W_0 - Wd (slope; Wd = W_0 + h D_0, D_0 the slope of the states at W_0),
+// step 2 from 2 H1 - H2 + W_2 - 2 W_1 + W_0 and step 3 from 3 H1 - 3 H2 + H3 + W_3 - 3 W_2 +
+// 3 W_1 - W_0: the midpoint polynomial plus the backward difference of the states, which sit in
+// Wc (W_0), X (W_1), S1 (W_2) and S2 (W_3) then.
 __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restrict__ probs,
                                                         int* __restrict__ done, int mode,
-                                                        const int* __restrict__ stepc) {
+                                                        const int* __restrict__ stepc, int slope) {
     const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
     const EnsProb p = probs[sim];
     const size_t n2 = (size_t)p.N * p.N;
-    const int n = mode == 2 ? stepc[0] : (mode == 1 ? 1 : 0);
+    const int n = mode >= 2 ? stepc[0] : (mode == 1 ? 1 : 0);
+    if (mode == 3 && ((n == 1 && slope) || n == 2 || n == 3)) {
+        for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
+            double2 g;
+            if (n == 1) {
+                const double2 f = p.H1[e], w1 = p.Wn[e], w0 = p.Wc[e], wd = p.Wd[e];
+                g = make_double2(f.x + 2.0 * w1.x, f.y + 2.0 * w1.y);
+                g = make_double2(g.x - w0.x - wd.x, g.y - w0.y - wd.y);
+            } else if (n == 2) {
+                const double2 f1 = p.H1[e], f2 = p.H2[e];
+                const double2 w2 = p.Wn[e], w1 = p.X[e], w0 = p.Wc[e];
+                g = make_double2(2.0 * f1.x - f2.x, 2.0 * f1.y - f2.y);
+                g = make_double2(g.x + w2.x - 2.0 * w1.x + w0.x, g.y + w2.y - 2.0 * w1.y + w0.y);
+            } else {
+                const double2 f1 = p.H1[e], f2 = p.H2[e], f3 = p.H3[e];
+                const double2 w3 = p.Wn[e], w2 = p.S1[e], w1 = p.X[e], w0 = p.Wc[e];
+                g = make_double2(3.0 * f1.x - 3.0 * f2.x + f3.x, 3.0 * f1.y - 3.0 * f2.y + f3.y);
+                g = make_double2(g.x + w3.x - 3.0 * w2.x + 3.0 * w1.x - w0.x,
+                                 g.y + w3.y - 3.0 * w2.y + 3.0 * w1.y - w0.y);
+            }
+            p.F[e] = g;
+        }
+        if (part == 0 && threadIdx.x == 0) done[sim] = 0;
+        return;
+    }
     const int d = n - 1 < 3 ? n - 1 : 3;  // polynomial degree for n >= 2
     const double c1 = d + 1.0;
     const double c2 = d == 1 ? -1.0 : (d == 2 ? -3.0 : -6.0);
@@ -118,24 +153,36 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
 // Step index of mode 2: set before the first step of a run (set >= 0), or advanced at the end
 // of each step (set < 0), when each simulation's W_n and W_{n+1} buffers swap and, with ring,
 // its midpoint ring also turns (see ens_begin_kernel).
-__global__ __launch_bounds__(64) void ens_stepc_kernel(int* __restrict__ stepc, int set,
-                                                       EnsProb* __restrict__ probs, int nsim,
-                                                       int ring) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (set < 0 && i < nsim) {
-        EnsProb& p = probs[i];
-        double2* w = p.W;
-        p.W = p.Wn;
-        p.Wn = w;
-        if (ring) {
-            double2* oldest = p.H3;
-            p.H3 = p.H2;
-            p.H2 = p.H1;
-            p.H1 = p.F;
-            p.F = oldest;
+// rot (guess mode 3): after steps 0, 1, 2 of a run the next output is S1, S2, then Wc, so the
+// states W_0 .. W_3 stay in Wc, X, S1, S2 until step 3 has started.
+// One block: every thread reads the step index before thread 0 advances it.
+constexpr int kStepcThreads = 256;
+__global__ __launch_bounds__(kStepcThreads) void ens_stepc_kernel(int* __restrict__ stepc, int set,
+                                                                  EnsProb* __restrict__ probs,
+                                                                  int nsim, int ring, int rot) {
+    const int n = stepc[0];  // the step that ends
+    if (set < 0) {
+        for (int i = threadIdx.x; i < nsim; i += kStepcThreads) {
+            EnsProb& p = probs[i];
+            double2* w = p.W;
+            if (rot && n <= 2) {
+                p.Wn = w;
+                p.W = n == 0 ? p.S1 : (n == 1 ? p.S2 : p.Wc);
+            } else {
+                p.W = p.Wn;
+                p.Wn = w;
+            }
+            if (ring) {
+                double2* oldest = p.H3;
+                p.H3 = p.H2;
+                p.H2 = p.H1;
+                p.H1 = p.F;
+                p.F = oldest;
+            }
         }
     }
-    if (i == 0) stepc[0] = set >= 0 ? set : stepc[0] + 1;
+    __syncthreads();
+    if (threadIdx.x == 0) stepc[0] = set >= 0 ? set : n + 1;
 }
 
 // Start of a run: W_n in the caller's matrix, W_{n+1} to the scratch one.
@@ -145,6 +192,18 @@ __global__ __launch_bounds__(64) void ens_run_begin_kernel(EnsProb* __restrict__
         probs[i].Wn = probs[i].Wc;
         probs[i].W = probs[i].X;
     }
+}
+
+// Guess mode 3 with the difference form: after the first evaluation of a run's first step
+// (step index 0), its W_{n+1} = W_0 + h D_0 is kept in Wd for the second step's start.
+__global__ __launch_bounds__(256) void ens_save_first_kernel(const EnsProb* __restrict__ probs,
+                                                             const int* __restrict__ stepc) {
+    if (stepc[0] != 0) return;
+    const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
+    const EnsProb p = probs[sim];
+    const size_t n2 = (size_t)p.N * p.N;
+    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256)
+        p.Wd[e] = p.W[e];
 }
 
 // End of a run: the last W_{n+1} (now in Wn) copied to the caller's matrix if it is in X.
@@ -462,8 +521,9 @@ namespace {
 
 hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
                        int mode, hipStream_t s) {
+    const int slope = mode == 3 && e->update_form == 1 ? 1 : 0;
     hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done,
-                       mode, e->stepc);
+                       mode, e->stepc, slope);
     hipError_t err = hipGetLastError();
     const int ns = e->slices, nl = e->slices_low;
 #define ZE_ENS_LAUNCH(...)                       \
@@ -510,10 +570,13 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
         }
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
                       e->resid, k, tol, prec == ZE_PREC_SPLIT ? kUT : e->ut);
+        if (k == 1 && slope)
+            ZE_ENS_LAUNCH(ens_save_first_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp,
+                          e->stepc);
     }
     if (err == hipSuccess)
-        ZE_ENS_LAUNCH(ens_stepc_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, s, e->stepc, -1,
-                      e->dp, e->nsim, mode == 2 ? 1 : 0);
+        ZE_ENS_LAUNCH(ens_stepc_kernel, dim3(1), dim3(kStepcThreads), 0, s, e->stepc, -1,
+                      e->dp, e->nsim, mode >= 2 ? 1 : 0, mode == 3 ? 1 : 0);
 #undef ZE_ENS_LAUNCH
     return err;
 }
@@ -538,16 +601,16 @@ hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int var
 // The step graph (first iterate W_n, or with guess mode 2 chosen by the step index) and, with
 // guess mode 1, the graph of the steps after the first of a run (first iterate 2 W_n - F_prev).
 hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant, int order) {
-    hipError_t err =
-        capture_one(e, h, tol, K, prec, variant, order, e->guess_mode == 2 ? 2 : 0, &e->exec);
+    hipError_t err = capture_one(e, h, tol, K, prec, variant, order,
+                                 e->guess_mode >= 2 ? e->guess_mode : 0, &e->exec);
     if (err == hipSuccess && e->guess_mode == 1)
         err = capture_one(e, h, tol, K, prec, variant, order, 1, &e->exec_x);
     if (e->exec_s) {
         (void)hipGraphExecDestroy(e->exec_s);
         e->exec_s = nullptr;
     }
-    if (err == hipSuccess && e->guess_mode == 2 && e->cap2 > 0 && e->cap2 < K)
-        err = capture_one(e, h, tol, e->cap2, prec, variant, order, 2, &e->exec_s);
+    if (err == hipSuccess && e->guess_mode >= 2 && e->cap2 > 0 && e->cap2 < K)
+        err = capture_one(e, h, tol, e->cap2, prec, variant, order, e->guess_mode, &e->exec_s);
     if (err == hipSuccess) {
         e->g_guess = e->guess_mode;
         e->g_prec = prec;
@@ -745,7 +808,7 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
         e->hp[i] = EnsProb{c->N,       0,       nullptr,  c->Wn,       nullptr, c->Wn,   c->F,
                            c->P,       c->A,    c->Q,     c->rowpart,  c->fac_l, c->fac_dinv,
                            nullptr,    nullptr, nullptr,  nullptr,     nullptr, nullptr,
-                           nullptr,    nullptr, nullptr};
+                           nullptr,    nullptr, nullptr,  nullptr,     nullptr, nullptr};
     }
     if ((st = ens_alloc(&e->dp, (size_t)nsim)) != ZE_OK) return fail(st);
     if ((st = ens_alloc(&e->done, (size_t)nsim)) != ZE_OK) return fail(st);
@@ -842,8 +905,9 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
                            e->dp, e->nsim);
         ZE_HIP(hipGetLastError());
     }
-    if (e->guess_mode == 2 && nsteps > 0) {  // the run's step index starts at 0
-        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(64), 0, e->own, e->stepc, 0, e->dp, 0, 0);
+    if (e->guess_mode >= 2 && nsteps > 0) {  // the run's step index starts at 0
+        hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(kStepcThreads), 0, e->own, e->stepc, 0,
+                           e->dp, 0, 0, 0);
         ZE_HIP(hipGetLastError());
     }
     for (int n = 0; n < nsteps; ++n) {
@@ -887,14 +951,27 @@ ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
 }
 
 ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
-    if (!e || mode < 0 || mode > 2) return ZE_EINVAL;
-    if (mode == 2 && !e->hp[0].H1) {  // history buffers, 3 per simulation
+    if (!e || mode < 0 || mode > 3) return ZE_EINVAL;
+    const bool ring = mode >= 2 && !e->hp[0].H1, states = mode == 3 && !e->hp[0].S1;
+    if (ring || states) {
+        // the descriptors on the device are the current ones (the steps turn them): fetch, add
+        // the new buffers, put back
         ZE_HIP(hipStreamSynchronize(e->own));
-        for (int i = 0; i < e->nsim; ++i) ZE_TRY(ze_ensure_rings(e->ctx[i], 1));
+        ZE_HIP(hipMemcpy(e->hp.data(), e->dp, e->hp.size() * sizeof(EnsProb), hipMemcpyDeviceToHost));
         for (int i = 0; i < e->nsim; ++i) {
-            e->hp[i].H1 = e->ctx[i]->ring[1];
-            e->hp[i].H2 = e->ctx[i]->ring[2];
-            e->hp[i].H3 = e->ctx[i]->ring[3];
+            ze_ctx* c = e->ctx[i];
+            if (ring) {  // midpoint history, 3 buffers per simulation
+                ZE_TRY(ze_ensure_rings(c, 1));
+                e->hp[i].H1 = c->ring[1];
+                e->hp[i].H2 = c->ring[2];
+                e->hp[i].H3 = c->ring[3];
+            }
+            if (states) {  // two more states and W_0 + h D_0 per simulation
+                ZE_TRY(ze_set_initial_guess(c, 3));
+                e->hp[i].S1 = c->Wh[0];
+                e->hp[i].S2 = c->Wh[1];
+                e->hp[i].Wd = c->Wd;
+            }
         }
         ZE_HIP(hipMemcpy(e->dp, e->hp.data(), e->hp.size() * sizeof(EnsProb), hipMemcpyHostToDevice));
     }

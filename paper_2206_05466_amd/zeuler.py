@@ -398,7 +398,7 @@ class Ensemble:
 
     def set_initial_guess(self, mode: int):
         """0: every step starts from W_n; 1: steps after the first of a run start each simulation
-        from 2 W_n - F_prev; 2: the polynomial start (as Zeuler.set_initial_guess)."""
+        from 2 W_n - F_prev; 2, 3: the polynomial starts (as Zeuler.set_initial_guess)."""
         _check(self.lib.ze_ensemble_set_initial_guess(self._ens, int(mode)),
                "ze_ensemble_set_initial_guess")
 

@@ -200,7 +200,7 @@ def test_ensemble_argument_errors(dev):
             ens.set_split_slices(99)
         with pytest.raises(ZeulerError):
             ens.run([to_dev(w0(16, 1)), to_dev(w0(24, 2))], 0.01, 1, 1e-12, 0)  # K < 1
-        for bad in (-1, 3):
+        for bad in (-1, 4):
             with pytest.raises(ZeulerError):
                 ens.set_initial_guess(bad)
         for bad in (-1, 2):
@@ -741,6 +741,42 @@ def test_ensemble_polynomial_guess(dev, prec_name, form):
             assert its[j] == itr[-1] and its2[j] == itr2[-1], (j, its[j], itr, its2[j], itr2)
         assert np.linalg.norm(got[j] - Wr) <= bar * np.linalg.norm(Wr), j
         assert np.linalg.norm(got2[j] - W2r) <= bar * np.linalg.norm(W2r), j
+
+
+@pytest.mark.parametrize("prec_name,form", [("fp64", 1), ("fp64", 0), ("split", 1)])
+def test_ensemble_history_start(dev, prec_name, form):
+    """Guess mode 3 in the ensemble: runs of 1 .. 5 steps (each a call of its own from W_0, so
+    each ends in another buffer of the states' rotation) end, for every simulation, where the
+    oracle's run with solution_differences does (FP64: 1e-12 and the evaluation count of the
+    run's last step, i.e. of every step in turn; split, 5 slices: 1e-10)."""
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Ensemble
+
+    sizes = [64, 40, 96, 130]
+    h, tol, K = 0.005, 1e-12, 8
+    split = prec_name == "split"
+    upd = ("second_line", "difference")[form]
+    W0s = [w0(n, 90 + j) for j, n in enumerate(sizes)]
+    refs = [O.isomp_run(W, h, 5, tol, K, extrapolate=True, degree=3, update=upd,
+                        solution_differences=True)[1] for W in W0s]
+    bar = 1e-10 if split else 1e-12
+    with Ensemble(sizes) as ens:
+        ens.set_update_form(form)
+        if split:
+            ens.set_split_slices(5)
+        ens.set_initial_guess(3)
+        prec = PREC_SPLIT if split else PREC_FP64
+        for L in range(1, 6):
+            Wd = [to_dev(W) for W in W0s]
+            ens.run(Wd, h, L, tol, K, prec=prec)
+            its, res = ens.stats()
+            got = [to_host(W) for W in Wd]
+            for j in range(len(sizes)):
+                Wr, _, _ = O.isomp_run(W0s[j], h, L, tol, K, extrapolate=True, degree=3,
+                                       update=upd, solution_differences=True)
+                assert res[j] < tol, (L, j)
+                if not split:
+                    assert its[j] == refs[j][L - 1], (L, j, its[j], refs[j])
+                assert np.linalg.norm(got[j] - Wr) <= bar * np.linalg.norm(Wr), (L, j)
 
 
 def test_split_lower_slices(dev):

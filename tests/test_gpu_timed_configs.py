@@ -14,8 +14,8 @@ oracle's evaluation counts for the FP64 form, and Casimir drift <= 1e-11 (C_2, C
 C_3 against ||W_0||_F^3).
 
 The 64-simulation ensemble: the bench's run (one step, then 50, each a run call of its own;
-evaluation cap 5, and 2 from the fifth step of a call; FP64 and the split form at the
-workload's slice count), one member of each size class against the oracle's run of the same
+guess mode 3; evaluation cap 5, and 2 from the fifth step of a call; FP64 and the split form at
+the workload's slice count), one member of each size class against the oracle's run of the same
 two calls.
 """
 
@@ -142,7 +142,7 @@ def test_ensemble64_timed_configuration(dev, prec_name):
         z.close()
     prec = PREC_SPLIT if split else PREC_FP64
     with Ensemble(sizes) as ens:
-        ens.set_initial_guess(2)
+        ens.set_initial_guess(3)
         ens.set_update_form(1)
         ens.set_steady_cap(cfg["steady_cap"], cfg["steady_from"])
         if split:
@@ -155,9 +155,10 @@ def test_ensemble64_timed_configuration(dev, prec_name):
     bar = 1e-10 if split else 1e-12
     worst = 0.0
     for j in picks:
-        W1, _, _ = O.isomp_run(W0s[j], h, 1, tol, K, extrapolate=True, degree=3, update="difference")
+        W1, _, _ = O.isomp_run(W0s[j], h, 1, tol, K, extrapolate=True, degree=3, update="difference",
+                               solution_differences=True)
         Wr, it_ref, _ = O.isomp_run(W1, h, steps, tol, K, extrapolate=True, degree=3,
-                                    update="difference")
+                                    update="difference", solution_differences=True)
         W = Ws[j].cpu().numpy()
         e = np.linalg.norm(W - Wr) / np.linalg.norm(Wr)
         worst = max(worst, e)
