@@ -271,6 +271,7 @@ def small_leg(steps):
     zg.set_stopping(1)
     zg.set_initial_guess(3)
     zg.set_update_form(1)
+    zg.set_steady_cap(2, 4)  # from the fifth step: one skipped evaluation per step, not four
     Wgr = W0.clone()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=sg):

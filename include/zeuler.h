@@ -154,6 +154,17 @@ ze_status ze_isomp_run(ze_ctx* ctx, void* W, double h, double tol, int maxit, in
 ze_status ze_set_stopping(ze_ctx* ctx, int mode);
 
 /*
+ * ze_set_steady_cap -- evaluation cap of the steps with index >= from_step in a ze_isomp_run
+ * call: min(maxit, cap) instead of maxit (cap 0, the default: maxit for every step).  Meant for
+ * the polynomial starts (ze_set_initial_guess 2, 3), after whose start-up a step takes one
+ * evaluation: with the stopping rule on the device every step enqueues its cap of evaluations,
+ * so a cap of 2 leaves one skipped evaluation per step instead of maxit - 1.  A step that
+ * reaches the cap above tol reports ZE_ENOTCONV as with maxit.
+ * Errors: ZE_EINVAL (cap or from_step negative).
+ */
+ze_status ze_set_steady_cap(ze_ctx* ctx, int cap, int from_step);
+
+/*
  * ze_run_stats -- on-device stopping: synchronises the context's stream and reads the last
  * nsteps steps of the last ze_isomp_run / ze_isomp_step call (nsteps <= its length).
  *   iters, resid  host arrays of nsteps entries (may be NULL), as ze_isomp_run fills them.

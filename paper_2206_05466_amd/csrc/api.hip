@@ -619,6 +619,11 @@ ze_status composed_step(ze_ctx* c, RunState& rs, double h, double tol, int maxit
 
 }  // namespace
 
+// The evaluation cap of step n of a run (ze_set_steady_cap).
+static int step_cap(const ze_ctx* c, int maxit, int n) {
+    return (c->cap2 > 0 && n >= c->cap2_after) ? std::min(maxit, c->cap2) : maxit;
+}
+
 // On-device stopping: the records of the last run (nsteps <= its length) and its status.
 static ze_status read_run_records(ze_ctx* c, int nsteps, int* iters, double* resid) {
     if (nsteps < 0 || nsteps > c->last_run_steps) return ZE_EINVAL;
@@ -661,7 +666,8 @@ static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit,
     ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
     RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, nsteps};
     for (int n = 0; n < nsteps; ++n) {
-        const ze_status st = composed_step(c, rs, h, tol, maxit, prec, n, nullptr, nullptr);
+        const ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n), prec, n, nullptr,
+                                           nullptr);
         if (st != ZE_OK) {
             finish_run(c, rs);
             return st;
@@ -700,6 +706,13 @@ ze_status ze_set_stopping(ze_ctx* c, int mode) {
     return ZE_OK;
 }
 
+ze_status ze_set_steady_cap(ze_ctx* c, int cap, int from_step) {
+    if (!c || cap < 0 || from_step < 0) return ZE_EINVAL;
+    c->cap2 = cap;
+    c->cap2_after = from_step;
+    return ZE_OK;
+}
+
 ze_status ze_run_stats(ze_ctx* c, int nsteps, int* iters, double* resid) {
     if (!c || c->stop_mode != 1) return ZE_EINVAL;
     return read_run_records(c, nsteps, iters, resid);
@@ -721,7 +734,7 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = composed_step(c, rs, h, tol, maxit, prec, n, &k, &r);
+        ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n), prec, n, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) {

@@ -115,6 +115,9 @@ struct ze_ctx {
     // counter) and dctld (2 doubles); per-step records of the last run (kDevSteps each,
     // allocated with mode 1).
     int stop_mode = 0;
+    // Evaluation cap min(maxit, cap2) of the steps with index >= cap2_after in a run (cap2 0:
+    // maxit for every step; ze_set_steady_cap).
+    int cap2 = 0, cap2_after = 0;
     int* dctl = nullptr;
     double* dctld = nullptr;
     int* dstep_it = nullptr;

@@ -45,6 +45,7 @@ SIGNATURES = {
     "ze_set_validation": (_c_int, [_vp, _c_int]),
     "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_set_stopping": (_c_int, [_vp, _c_int]),
+    "ze_set_steady_cap": (_c_int, [_vp, _c_int, _c_int]),
     "ze_run_stats": (_c_int, [_vp, _c_int, _P_int, _P_double]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
@@ -219,6 +220,11 @@ class Zeuler:
         """0: tolerance test on the host after each evaluation; 1: on the device (no
         synchronisation per evaluation; every precision)."""
         _check(self.lib.ze_set_stopping(self._ctx, int(mode)), "ze_set_stopping")
+
+    def set_steady_cap(self, cap: int, from_step: int = 4):
+        """Evaluation cap min(maxit, cap) for the steps from index from_step on of each run (with
+        the polynomial starts); 0 restores maxit for every step."""
+        _check(self.lib.ze_set_steady_cap(self._ctx, int(cap), int(from_step)), "ze_set_steady_cap")
 
     def run_stats(self, nsteps: int):
         """(iterations, residuals, status) of the last nsteps steps of the last run (on-device

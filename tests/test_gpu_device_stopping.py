@@ -39,7 +39,11 @@ def run(z, W0, h, steps, tol, maxit, mode, guess, form, order=2, prec=0):
     z.set_update_form(form)
     z.set_order(order)
     W = torch.from_numpy(W0).cuda()
-    its, res = z.isomp_run(W, h, steps, tol, maxit, prec)
+    if mode == 1:  # every step runs; the counts come back whatever the status
+        z.isomp_run_async(W, h, steps, tol, maxit, prec)
+        its, res, _ = z.run_stats(steps)
+    else:
+        its, res = z.isomp_run(W, h, steps, tol, maxit, prec)
     torch.cuda.synchronize()
     return W.cpu().numpy(), its, res
 
@@ -111,6 +115,28 @@ def test_device_stopping_fixed_count_and_order4(dev):
         Wh, ith, rh = run(z, W0, h, 4, 1e-12, 6, 0, 2, 1, order=4)
         Wd, itd, rd = run(z, W0, h, 4, 1e-12, 6, 1, 2, 1, order=4)
     assert itd == ith and rd == rh and np.array_equal(Wd, Wh)
+
+
+def test_steady_cap_same_steps(dev):
+    """A steady cap of 2 from the fourth step (guess mode 3, difference form; no step needs more
+    there) gives the uncapped run's W, counts and residuals bit for bit, on the host and on the
+    device; a cap of 1 from the first step reports the start-up steps as not converged."""
+    from paper_2206_05466_amd import Zeuler
+    from paper_2206_05466_amd.zeuler import ZE_ENOTCONV
+
+    N, h, tol, maxit, steps = 200, 0.005, 1e-12, 6, 9
+    W0 = field(N, 6, "inv1.5")
+    with Zeuler(N) as z:
+        base = run(z, W0, h, steps, tol, maxit, 0, 3, 1)
+        z.set_steady_cap(2, 3)
+        for mode in (0, 1):
+            got = run(z, W0, h, steps, tol, maxit, mode, 3, 1)
+            assert got[1] == base[1] and got[2] == base[2] and np.array_equal(got[0], base[0]), mode
+        z.set_steady_cap(1, 0)
+        run(z, W0, h, steps, tol, maxit, 1, 3, 1)
+        its, _, st = z.run_stats(steps)
+        assert its[0] == 1 and st == ZE_ENOTCONV, its
+        z.set_steady_cap(0, 0)
 
 
 def test_device_stopping_graph_capture_replays(dev):
