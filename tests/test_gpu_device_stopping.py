@@ -137,6 +137,11 @@ def test_steady_cap_same_steps(dev):
         its, _, st = z.run_stats(steps)
         assert its[0] == 1 and st == ZE_ENOTCONV, its
         z.set_steady_cap(0, 0)
+        from paper_2206_05466_amd import ZeulerError
+
+        for cap, frm in ((-1, 0), (2, -1)):
+            with pytest.raises(ZeulerError):
+                z.set_steady_cap(cap, frm)
 
 
 def test_device_stopping_graph_capture_replays(dev):

@@ -52,6 +52,10 @@ def test_strerror_and_invalid_create_without_gpu():
     assert lib.ze_destroy(None) == zeuler.ZE_OK
     assert lib.ze_stream_solve(None, None, None) == zeuler.ZE_EINVAL
     assert lib.ze_isomp_step(None, None, 0.1, 1e-12, 5, 0, None, None) == zeuler.ZE_EINVAL
+    # setters with no context
+    assert lib.ze_set_steady_cap(None, 2, 4) == zeuler.ZE_EINVAL
+    assert lib.ze_set_initial_guess(None, 3) == zeuler.ZE_EINVAL
+    assert lib.ze_set_stopping(None, 1) == zeuler.ZE_EINVAL
 
 
 def test_noalloc_product_refuses_sizes_without_gpu():
