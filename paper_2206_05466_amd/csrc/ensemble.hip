@@ -85,69 +85,79 @@ constexpr int kCopyParts = 64;
 // step 2 from 2 H1 - H2 + W_2 - 2 W_1 + W_0 and step 3 from 3 H1 - 3 H2 + H3 + W_3 - 3 W_2 +
 // 3 W_1 - W_0: the midpoint polynomial plus the backward difference of the states, which sit in
 // Wc (W_0), X (W_1), S1 (W_2) and S2 (W_3) then.
+// begin_value gives that starting iterate at entry e of one simulation; c1..c3 are the
+// coefficients of the midpoint polynomial of degree min(n - 1, 3).
+__device__ __forceinline__ double2 begin_value(const EnsProb& p, size_t e, int mode, int n, int slope,
+                                               double c1, double c2, double c3) {
+    if (n == 0) return p.Wn[e];
+    if (mode == 3 && n == 1 && slope) {
+        const double2 f = p.H1[e], w1 = p.Wn[e], w0 = p.Wc[e], wd = p.Wd[e];
+        double2 g = make_double2(f.x + 2.0 * w1.x, f.y + 2.0 * w1.y);
+        return make_double2(g.x - w0.x - wd.x, g.y - w0.y - wd.y);
+    }
+    if (mode == 3 && n == 2) {
+        const double2 f1 = p.H1[e], f2 = p.H2[e];
+        const double2 w2 = p.Wn[e], w1 = p.X[e], w0 = p.Wc[e];
+        const double2 g = make_double2(2.0 * f1.x - f2.x, 2.0 * f1.y - f2.y);
+        return make_double2(g.x + w2.x - 2.0 * w1.x + w0.x, g.y + w2.y - 2.0 * w1.y + w0.y);
+    }
+    if (mode == 3 && n == 3) {
+        const double2 f1 = p.H1[e], f2 = p.H2[e], f3 = p.H3[e];
+        const double2 w3 = p.Wn[e], w2 = p.S1[e], w1 = p.X[e], w0 = p.Wc[e];
+        const double2 g = make_double2(3.0 * f1.x - 3.0 * f2.x + f3.x, 3.0 * f1.y - 3.0 * f2.y + f3.y);
+        return make_double2(g.x + w3.x - 3.0 * w2.x + 3.0 * w1.x - w0.x,
+                            g.y + w3.y - 3.0 * w2.y + 3.0 * w1.y - w0.y);
+    }
+    if (mode == 1) {
+        const double2 w = p.Wn[e], f = p.F[e];
+        return make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
+    }
+    if (n == 1) {
+        const double2 w = p.Wn[e], f1 = p.H1[e];
+        return make_double2(2.0 * w.x - f1.x, 2.0 * w.y - f1.y);
+    }
+    const double2 f1 = p.H1[e], f2 = p.H2[e];
+    double2 g = make_double2(c1 * f1.x, c1 * f1.y);
+    g = make_double2(g.x + c2 * f2.x, g.y + c2 * f2.y);
+    if (n >= 3) {
+        const double2 f3 = p.H3[e];
+        g = make_double2(g.x + c3 * f3.x, g.y + c3 * f3.y);
+        if (n >= 4) {
+            const double2 f4 = p.F[e];
+            g = make_double2(g.x - f4.x, g.y - f4.y);
+        }
+    }
+    return g;
+}
+
+// Work item (simulation, chunk): entries chunk * kBeginChunk + u * 256 + thread, u = 0 .. 3, all
+// read before any is written (the oldest midpoint slot may be the one written).
+constexpr int kBeginChunk = 4 * 256;
 __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restrict__ probs,
+                                                        const int2* __restrict__ work,
                                                         int* __restrict__ done, int mode,
                                                         const int* __restrict__ stepc, int slope) {
-    const int sim = blockIdx.x / kCopyParts, part = blockIdx.x % kCopyParts;
-    const EnsProb p = probs[sim];
+    const int2 it = work[blockIdx.x];
+    const EnsProb p = probs[it.x];
     const size_t n2 = (size_t)p.N * p.N;
     const int n = mode >= 2 ? stepc[0] : (mode == 1 ? 1 : 0);
-    if (mode == 3 && ((n == 1 && slope) || n == 2 || n == 3)) {
-        for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
-            double2 g;
-            if (n == 1) {
-                const double2 f = p.H1[e], w1 = p.Wn[e], w0 = p.Wc[e], wd = p.Wd[e];
-                g = make_double2(f.x + 2.0 * w1.x, f.y + 2.0 * w1.y);
-                g = make_double2(g.x - w0.x - wd.x, g.y - w0.y - wd.y);
-            } else if (n == 2) {
-                const double2 f1 = p.H1[e], f2 = p.H2[e];
-                const double2 w2 = p.Wn[e], w1 = p.X[e], w0 = p.Wc[e];
-                g = make_double2(2.0 * f1.x - f2.x, 2.0 * f1.y - f2.y);
-                g = make_double2(g.x + w2.x - 2.0 * w1.x + w0.x, g.y + w2.y - 2.0 * w1.y + w0.y);
-            } else {
-                const double2 f1 = p.H1[e], f2 = p.H2[e], f3 = p.H3[e];
-                const double2 w3 = p.Wn[e], w2 = p.S1[e], w1 = p.X[e], w0 = p.Wc[e];
-                g = make_double2(3.0 * f1.x - 3.0 * f2.x + f3.x, 3.0 * f1.y - 3.0 * f2.y + f3.y);
-                g = make_double2(g.x + w3.x - 3.0 * w2.x + 3.0 * w1.x - w0.x,
-                                 g.y + w3.y - 3.0 * w2.y + 3.0 * w1.y - w0.y);
-            }
-            p.F[e] = g;
-        }
-        if (part == 0 && threadIdx.x == 0) done[sim] = 0;
-        return;
-    }
     const int d = n - 1 < 3 ? n - 1 : 3;  // polynomial degree for n >= 2
     const double c1 = d + 1.0;
     const double c2 = d == 1 ? -1.0 : (d == 2 ? -3.0 : -6.0);
     const double c3 = d == 2 ? 1.0 : 4.0;
-    for (size_t e = (size_t)part * 256 + threadIdx.x; e < n2; e += (size_t)kCopyParts * 256) {
-        if (n == 0) {
-            p.F[e] = p.Wn[e];
-            continue;
-        }
-        double2 g;
-        if (mode == 1) {
-            const double2 w = p.Wn[e], f = p.F[e];
-            g = make_double2(2.0 * w.x - f.x, 2.0 * w.y - f.y);
-        } else if (n == 1) {
-            const double2 w = p.Wn[e], f1 = p.H1[e];
-            g = make_double2(2.0 * w.x - f1.x, 2.0 * w.y - f1.y);
-        } else {
-            const double2 f1 = p.H1[e], f2 = p.H2[e];
-            g = make_double2(c1 * f1.x, c1 * f1.y);
-            g = make_double2(g.x + c2 * f2.x, g.y + c2 * f2.y);
-            if (n >= 3) {
-                const double2 f3 = p.H3[e];
-                g = make_double2(g.x + c3 * f3.x, g.y + c3 * f3.y);
-                if (n >= 4) {
-                    const double2 f4 = p.F[e];
-                    g = make_double2(g.x - f4.x, g.y - f4.y);
-                }
-            }
-        }
-        p.F[e] = g;
+    const size_t e0 = (size_t)it.y * kBeginChunk + threadIdx.x;
+    double2 g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const size_t e = e0 + (size_t)u * 256;
+        g[u] = begin_value(p, e < n2 ? e : n2 - 1, mode, n, slope, c1, c2, c3);  // in bounds
     }
-    if (part == 0 && threadIdx.x == 0) done[sim] = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const size_t e = e0 + (size_t)u * 256;
+        if (e < n2) p.F[e] = g[u];
+    }
+    if (it.y == 0 && threadIdx.x == 0) done[it.x] = 0;
 }
 
 // Step index of mode 2: set before the first step of a run (set >= 0), or advanced at the end
@@ -479,6 +489,8 @@ struct ze_ens {
     int n_prod[2] = {0, 0};
     int2* work_low[2] = {nullptr, nullptr};                            // [order]
     int n_low = 0;
+    int2* work_begin = nullptr;  // (simulation, chunk of kBeginChunk entries) of the step start
+    int n_begin = 0;
     // the FP64 path's update tile (32, or 64 when a context's row-sum slots are 64 wide) and
     // its lower tiles
     int ut = 32;
@@ -522,8 +534,8 @@ namespace {
 hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
                        int mode, hipStream_t s) {
     const int slope = mode == 3 && e->update_form == 1 ? 1 : 0;
-    hipLaunchKernelGGL(ens_begin_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp, e->done,
-                       mode, e->stepc, slope);
+    hipLaunchKernelGGL(ens_begin_kernel, dim3(e->n_begin), dim3(256), 0, s, e->dp, e->work_begin,
+                       e->done, mode, e->stepc, slope);
     hipError_t err = hipGetLastError();
     const int ns = e->slices, nl = e->slices_low;
 #define ZE_ENS_LAUNCH(...)                       \
@@ -767,6 +779,7 @@ ze_status ze_ensemble_destroy(ze_ens* e) {
         for (int2* p : v) (void)hipFree(p);
     for (int2* p : e->work_low) (void)hipFree(p);
     for (int2* p : e->work_up) (void)hipFree(p);
+    if (e->work_begin) (void)hipFree(e->work_begin);
     for (int2* p : {e->w_rows0, e->w_rows1, e->w_cols, e->w_comb}) (void)hipFree(p);
     for (auto& v : e->w_i8)
         for (int2* p : v) (void)hipFree(p);
@@ -858,6 +871,14 @@ ze_status ze_ensemble_create(int nsim, const int* N, void* stream, ze_ens** out)
             e->n_i8[1] = (int)w.size();
             if ((st = upload_work(w, &e->w_i8[1][order])) != ZE_OK) return fail(st);
         }
+    }
+    {
+        std::vector<int> cb(nsim);
+        for (int i = 0; i < nsim; ++i)
+            cb[i] = (int)(((size_t)e->N[i] * e->N[i] + kBeginChunk - 1) / kBeginChunk);
+        std::vector<int2> wb = make_work(e->N, cb, 0);
+        e->n_begin = (int)wb.size();
+        if ((st = upload_work(wb, &e->work_begin)) != ZE_OK) return fail(st);
     }
     std::vector<int2> ws = make_work(e->N, cs, 0);
     e->n_solve = (int)ws.size();
