@@ -428,11 +428,19 @@ hipError_t launch_ens_solve(const EnsProb* probs, const int2* work, int n, const
     return hipGetLastError();
 }
 
-int ens_bd(int maxN) { return solve_bd(maxN); }
+// Band width of an ensemble's stream solve.  Not solve_bd's: the many bands of an ensemble
+// keep the GPU busy, so the longer row segments of wide bands pay even where one small problem
+// alone wants one-lane bands (64 simulations, N <= 512: 97 us with 4 lanes, 192 with 1).
+int ens_bd(int maxN) { return maxN <= 2172 ? 4 : (maxN <= 4606 ? 2 : 1); }
 
 hipError_t ens_solve(int maxN, const EnsProb* probs, const int2* work, int n, const int* done,
                      int eval, hipStream_t s) {
-    if (ens_bd(maxN) == 2) return launch_ens_solve<1024, 9, 2>(probs, work, n, done, eval, s);
+    const int bd = ens_bd(maxN);
+    if (bd == 1) {  // maxN > 4606
+        if (maxN <= 9215) return launch_ens_solve<1024, 9, 1>(probs, work, n, done, eval, s);
+        return launch_ens_solve<1024, 17, 1>(probs, work, n, done, eval, s);
+    }
+    if (bd == 2) return launch_ens_solve<1024, 9, 2>(probs, work, n, done, eval, s);
     if (maxN <= 76) return launch_ens_solve<64, 5, 4>(probs, work, n, done, eval, s);
     if (maxN <= 156) return launch_ens_solve<128, 5, 4>(probs, work, n, done, eval, s);
     if (maxN <= 316) return launch_ens_solve<256, 5, 4>(probs, work, n, done, eval, s);

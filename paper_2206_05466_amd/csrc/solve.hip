@@ -7,8 +7,9 @@
 // solve_band in solve_wg.h) so that at every step the BD lanes of a group read or write BD
 // neighbouring entries of one matrix row: the accesses are row segments, not the one-entry-
 // per-row pattern of a diagonal.  The factors are stored in the same (band, virtual row,
-// lane) order.  BD (solve_bd) = 4 up to N = 2172, then 2 up to 4606, then 1 (the chunk a
-// thread holds must fit in registers).
+// lane) order.  BD (solve_bd) = 1 up to N = 639, 2 up to 1150, 4 up to 2172, then 2 up to
+// 4606, then 1 (small problems want many short chains; the chunk a thread holds must fit in
+// registers).
 //
 // Within a workgroup, thread (c, d) owns C consecutive virtual rows of lane d in registers.
 // Each sweep is a first-order linear recurrence, solved as: local sweep of every chunk with a
@@ -140,9 +141,13 @@ hipError_t launch_stream_solve(const ze_ctx* c, const double2* W, double2* P, hi
         return hipErrorInvalidValue;  // band width 4 is only chosen up to N = 2172
     }
     if (c->solve_bd == 2) {
+        if (N <= 1150) return launch_tc<256, 9, 2>(c, W, P, s, skip);
         if (N <= 4606) return launch_tc<1024, 9, 2>(c, W, P, s, skip);
         return hipErrorInvalidValue;  // band width 2 is only chosen up to N = 4606
     }
+    if (N <= 191) return launch_tc<64, 3, 1>(c, W, P, s, skip);
+    if (N <= 383) return launch_tc<128, 3, 1>(c, W, P, s, skip);
+    if (N <= 639) return launch_tc<128, 5, 1>(c, W, P, s, skip);
     if (N <= 9215) return launch_tc<1024, 9, 1>(c, W, P, s, skip);
     return launch_tc<1024, 17, 1>(c, W, P, s, skip);
 }

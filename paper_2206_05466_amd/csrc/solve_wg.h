@@ -35,9 +35,16 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* s) {
 // multiplier 0, which keeps the two recurrences (and the gap) apart.  Mains cover
 // [0, K BD), partners the rest; a partner that is itself a main (m' < K BD) is skipped.
 // Default band width: a thread holds C <= 17 rows (the launch shapes of solve.hip); wider
-// bands mean longer row segments per access, narrower ones smaller workgroups and fewer
-// registers (measured: 4 lanes up to N = 2172, 2 lanes of 9 rows at N = 4096).
-__host__ __device__ inline int solve_bd(int N) { return N <= 2172 ? 4 : (N <= 4606 ? 2 : 1); }
+// bands mean longer row segments per access, narrower ones more and smaller workgroups with
+// shorter chains, which is what the small problems (latency-bound) want.  Measured: 1 lane up
+// to N = 639 (N = 512: 5.5 us against 7.9 with 4 lanes), 2 up to 1150, 4 up to 2172, 2 lanes
+// of 9 rows up to 4606, then 1.
+__host__ __device__ inline int solve_bd(int N) {
+    if (N <= 639) return 1;
+    if (N <= 1150) return 2;
+    if (N <= 2172) return 4;
+    return N <= 4606 ? 2 : 1;
+}
 __host__ __device__ inline int solve_bands(int N, int bd) { return (N + 2 * bd - 1) / (2 * bd); }
 __host__ __device__ inline int solve_rows(int N, int bd) { return N + bd; }  // virtual rows
 

@@ -64,7 +64,9 @@ def relmax(a, b):
 
 
 # ------------------------------------------------------------------ stream solve
-@pytest.mark.parametrize("N", [1, 2, 3, 5, 63, 64, 65, 130, 257, 512])
+# launch-shape limits of the band widths: 191/383/639 (one lane), 1150 (two lanes), 2172 (four)
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 63, 64, 65, 130, 191, 192, 257, 383, 384, 512, 639, 640,
+                               1150, 1151, 2172, 2173])
 @pytest.mark.parametrize("traceless", [True, False])
 def test_stream_solve_parity(dev, N, traceless):
     W = rand_skew(N, N, traceless)
