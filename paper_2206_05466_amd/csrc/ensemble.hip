@@ -534,13 +534,16 @@ struct ze_ens {
     // evaluation cap of the steps from index cap2_after on (guess mode 2; 0: the run's cap K)
     // and the step graph captured with it
     int cap2 = 0, cap2_after = 0, g_cap2 = -1;
+    bool g_cap2_first = true;  // the capped graph was captured for a step index that may be 0
     hipGraphExec_t exec_s = nullptr;
 };
 
 namespace {
 
+// first: the graph may run the first step of a call (the step index 0), whose first
+// evaluation's output the second step's slope start needs.
 hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
-                       int mode, hipStream_t s) {
+                       int mode, hipStream_t s, bool first = true) {
     const int slope = mode == 3 && e->update_form == 1 ? 1 : 0;
     hipLaunchKernelGGL(ens_begin_kernel, dim3(e->n_begin), dim3(256), 0, s, e->dp, e->work_begin,
                        e->done, mode, e->stepc, slope);
@@ -590,7 +593,7 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
         }
         ZE_ENS_LAUNCH(ens_resid_kernel, dim3(e->nsim), dim3(256), 0, s, e->dp, e->done, e->iters,
                       e->resid, k, tol, prec == ZE_PREC_SPLIT ? kUT : e->ut);
-        if (k == 1 && slope)
+        if (k == 1 && slope && first)
             ZE_ENS_LAUNCH(ens_save_first_kernel, dim3(e->nsim * kCopyParts), dim3(256), 0, s, e->dp,
                           e->stepc);
     }
@@ -602,7 +605,7 @@ hipError_t record_step(ze_ens* e, double h, double tol, int K, int prec, int var
 }
 
 hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int variant, int order,
-                       int mode, hipGraphExec_t* out) {
+                       int mode, hipGraphExec_t* out, bool first = true) {
     if (*out) {
         (void)hipGraphExecDestroy(*out);
         *out = nullptr;
@@ -610,7 +613,7 @@ hipError_t capture_one(ze_ens* e, double h, double tol, int K, int prec, int var
     hipGraph_t g = nullptr;
     hipError_t err = hipStreamBeginCapture(e->own, hipStreamCaptureModeRelaxed);
     if (err != hipSuccess) return err;
-    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, mode, e->own);
+    hipError_t rec = record_step(e, h, tol, K, prec, variant, order, mode, e->own, first);
     err = hipStreamEndCapture(e->own, &g);
     if (rec != hipSuccess) err = rec;
     if (err == hipSuccess) err = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -630,7 +633,8 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         e->exec_s = nullptr;
     }
     if (err == hipSuccess && e->guess_mode >= 2 && e->cap2 > 0 && e->cap2 < K)
-        err = capture_one(e, h, tol, e->cap2, prec, variant, order, e->guess_mode, &e->exec_s);
+        err = capture_one(e, h, tol, e->cap2, prec, variant, order, e->guess_mode, &e->exec_s,
+                          e->cap2_after == 0);
     if (err == hipSuccess) {
         e->g_guess = e->guess_mode;
         e->g_prec = prec;
@@ -643,6 +647,7 @@ hipError_t capture(ze_ens* e, double h, double tol, int K, int prec, int variant
         e->g_h = h;
         e->g_tol = tol;
         e->g_cap2 = e->cap2;
+        e->g_cap2_first = e->cap2_after == 0;
     }
     return err;
 }
@@ -927,7 +932,8 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
         e->g_K != K || e->g_h != h || e->g_tol != tol || e->g_slices != e->slices || e->g_slices_low != e->slices_low ||
-        e->g_form != e->update_form || e->g_guess != e->guess_mode || e->g_cap2 != e->cap2)
+        e->g_form != e->update_form || e->g_guess != e->guess_mode || e->g_cap2 != e->cap2 ||
+        e->g_cap2_first != (e->cap2_after == 0))
         ZE_HIP(capture(e, h, tol, K, prec, variant, order));
     if (nsteps > 0) {
         hipLaunchKernelGGL(ens_run_begin_kernel, dim3((e->nsim + 63) / 64), dim3(64), 0, e->own,

@@ -479,6 +479,35 @@ def test_ensemble_steady_cap_same_steps(dev):
         assert np.linalg.norm(out[2][j] - Wr) <= 1e-12 * np.linalg.norm(Wr), j
 
 
+@pytest.mark.parametrize("cap,from_step", [(5, 0), (3, 1), (2, 4)])
+def test_ensemble_steady_cap_history_start(dev, cap, from_step):
+    """Guess mode 3 with the difference form under a steady cap whose graph runs from step 0,
+    1 or 4 of the call (from step 1 on it has no copy of the first evaluation's output, which
+    only step 0 makes): the same steps, bit for bit, as without the cap, and the oracle's run
+    with solution_differences."""
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [64, 96, 130]
+    h, tol, K, steps = 0.01, 1e-12, 6, 7
+    W0s = [w0(n, 80 + j) for j, n in enumerate(sizes)]
+    out = {}
+    for c in (0, cap):
+        Wd = [to_dev(W) for W in W0s]
+        with Ensemble(sizes) as ens:
+            ens.set_initial_guess(3)
+            ens.set_update_form(1)
+            ens.set_steady_cap(c, from_step)
+            ens.run(Wd, h, steps, tol, K)
+            its, res = ens.stats()
+        assert max(res) < tol, (c, its, res)
+        out[c] = [to_host(W) for W in Wd]
+    for j in range(len(sizes)):
+        assert np.array_equal(out[0][j], out[cap][j]), j
+        Wr, _, _ = O.isomp_run(W0s[j], h, steps, tol, K, extrapolate=True, degree=3,
+                               update="difference", solution_differences=True)
+        assert np.linalg.norm(out[cap][j] - Wr) <= 1e-12 * np.linalg.norm(Wr), j
+
+
 def test_ensemble_extrapolated_guess(dev):
     """Guess mode 1 in the ensemble (steps after the first of a run start from 2 W_n - F_prev):
     every simulation matches the single-context run in the same mode and the oracle's
