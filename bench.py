@@ -489,21 +489,22 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
     c0 = z.casimirs(W, 4)
     W0 = W.clone()
 
-    def timed_run(Wx, prec, guess, form=1):
-        """Warm-up run, then one timed ze_isomp_run of `steps` steps on Wx (in place)."""
+    def timed_run(Wx, prec, guess, form=1, events=True):
+        """Warm-up run, then one timed ze_isomp_run of `steps` steps on Wx (in place); events:
+        the per-phase HIP events on (the kernels' live durations) or off."""
         z.set_update_form(form)
         z.set_initial_guess(guess)
         Ww = Wx.clone()
         z.isomp_run(Ww, h, max(warmup, 1), tol, maxit, prec)
         del Ww
-        z.profile(True)
+        z.profile(events)
         z.profile_read(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its, res = z.isomp_run(Wx, h, steps, tol, maxit, prec)
         torch.cuda.synchronize()
         dtx = time.perf_counter() - t0
-        prof = z.profile_read()
+        prof = z.profile_read() if events else None
         z.profile(False)
         return dtx, its, res, prof
 
@@ -529,6 +530,13 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
     # steps with the run's states as well, W_{n+1} = W_n + h C
     dt, iters, resids, prof = timed_run(W, PREC_FP64, 3, 1)
     log(f"{wname} fp64, polynomial start: {dt / steps * 1e3:.2f} ms/step, iters={iters}")
+    # the same run without the per-phase events: what they cost
+    Wq = W0.clone()
+    dt_q, iters_q, _, _ = timed_run(Wq, PREC_FP64, 3, 1, events=False)
+    quiet_same = bool(torch.equal(Wq, W)) and list(iters_q) == list(iters)
+    del Wq
+    log(f"{wname} fp64, polynomial start, no phase events: {dt_q / steps * 1e3:.2f} ms/step "
+        f"(same result: {quiet_same})")
     c1 = z.casimirs(W, 4)
     plain_vs_extrap = float(torch.linalg.norm(Wp - W).item() / torch.linalg.norm(W).item())
     lin_vs_extrap = float(torch.linalg.norm(Wl - W).item() / torch.linalg.norm(W).item())
@@ -593,6 +601,7 @@ def measure_single(wname, steps, warmup, slist, copy_probe_mib=0, with_mixed=Tru
         "N": N, "h": h, "tol": tol, "maxit": maxit, "law": law, "seed": seed, "steps": steps,
         "s_per_step": dt / steps, "iters_per_step": list(iters), "max_resid": max(resids),
         "prof": prof, "casimir_drift_rel": casimir_drift(c0, c1, W),
+        "without_phase_events": {"s_per_step": dt_q / steps, "same_result": quiet_same},
         "fp64_start_from_Wn": {"s_per_step": dt_plain / steps, "iters_per_step": list(iters_plain),
                                "rel_frobenius_vs_headline_run": plain_vs_extrap},
         "fp64_linear_start": {"s_per_step": dt_lin / steps, "iters_per_step": list(iters_lin),
@@ -894,6 +903,7 @@ def main():
                          "(ze_set_initial_guess 3); every step still iterates until the change "
                          "is below tol",
         "fp64_polynomial_start_midpoints_only": m["fp64_polynomial_start_midpoints_only"],
+        "fp64_without_phase_events": m["without_phase_events"],
         "fp64_start_from_Wn": m["fp64_start_from_Wn"],
         "fp64_linear_start": m["fp64_linear_start"],
         "fp64_polynomial_start_second_line_form": m["fp64_polynomial_start_second_line_form"],
