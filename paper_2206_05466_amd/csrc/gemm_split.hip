@@ -121,17 +121,16 @@ __global__ __launch_bounds__(kThreads) void crt_cols_kernel(const double2* __res
     crt_cols_tile(B, N, blockIdx.x, blockIdx.y, b, ldk, eb, slices, tile);
 }
 
-// Residues c_k of the real and imaginary parts of one output value from its P1, P2, P3
-// (bytes sh .. sh + 7 of the loaded words, each in [0, p_k)).
+// Representatives of the residues of the real and imaginary parts of one output value from its
+// P1, P2, P3 (bytes sh .. sh + 7 of the loaded words, each in [0, p_k)): Re = P1 - P2 + p_k in
+// [1, 2 p_k), Im = P3 - P1 - P2 + 2 p_k in [1, 3 p_k), left unreduced (the CRT sums take them;
+// a reduction would cost two compares and selects per value and modulus).
 __device__ __forceinline__ void crt_parts_to_residues(unsigned p1, unsigned p2, unsigned p3, int sh,
                                                       int p, int& re, int& im) {
     const int a = (int)((p1 >> sh) & 0xffu), b = (int)((p2 >> sh) & 0xffu);
     const int c = (int)((p3 >> sh) & 0xffu);
-    re = a - b;
-    re = re < 0 ? re + p : re;
-    im = c - a - b;
-    im = im < 0 ? im + p : im;
-    im = im < 0 ? im + p : im;
+    re = a - b + p;
+    im = c + 2 * p - a - b;
 }
 
 // C[e] from the residue products, three N x N byte slabs per modulus k (P1 = ar br,

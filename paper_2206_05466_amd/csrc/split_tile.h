@@ -304,10 +304,10 @@ __device__ __forceinline__ void crt_cols_tile(const double2* __restrict__ B, int
 }
 
 // Constants of the reconstruction: W_k = (M / p_k) ((M / p_k)^-1 mod p_k) < M, so that
-// X = sum_k c_k W_k mod M for c_k = X mod p_k; as two 64-bit halves and as doubles; M likewise.
+// X = sum_k c_k W_k mod M for c_k = X mod p_k, in 32-bit limbs; M as two 64-bit halves and as a
+// double.
 struct CrtConst {
     unsigned wl[kCrtMods][4];  // W_k in 32-bit limbs, least significant first
-    double wd[kCrtMods];
     unsigned long long mlo, mhi;
     double md;
 };
@@ -330,7 +330,6 @@ constexpr CrtConst make_crt_const() {
             if ((r * x) % p == 1) y = x;
         const unsigned __int128 W = Mk * y;
         for (int j = 0; j < 4; ++j) k.wl[i][j] = (unsigned)(W >> (32 * j));
-        k.wd[i] = crt_u128_to_double(W);
     }
     k.mlo = (unsigned long long)M;
     k.mhi = (unsigned long long)(M >> 64);
@@ -342,17 +341,18 @@ constexpr CrtConst kCrtK = make_crt_const();
 
 // The integer X with |X| <= 0.99^2 M / 2 from the kCrtMods int32 products g_k (|g_k| < 2^31) of one
 // output value (with `Reduced`, g_k = c_k already in [0, p_k)), rounded to FP64:
-// c_k = g_k mod p_k; S = sum_k c_k W_k exactly modulo 2^128, each 32-bit limb of W_k times c_k
-// summed in its own 64-bit accumulator (16 terms below 2^40 each), and approximately in FP64;
-// q = S / M rounded to the nearest integer (exact: S / M = q + X / M lies at least 0.01 from
-// a half-integer, and the FP64 estimate of S / M < 2^12 is off by less than 2^-36);
+// c_k = g_k mod p_k, or any representative of it in [0, 3 p_k); S = sum_k c_k W_k < 2^14 M
+// exactly modulo 2^128, each 32-bit limb of W_k times c_k summed in its own 64-bit accumulator
+// (16 terms below 2^42 each); q = S / M rounded to the nearest integer, from an FP64 estimate
+// of S built from the exact limb sums (exact: S / M = q + X / M lies at least 0.01 from a
+// half-integer, and the estimate of S / M < 2^14 is off by less than 2^-35);
 // X = S - q M modulo 2^128 is X
 // itself, read as signed.  The magnitude is converted from its two 64-bit halves, each exact
 // when X is representable.
-// Running sums of that reconstruction: add(k, c) takes c = c_k in [0, p_k); value() gives X.
+// Running sums of that reconstruction: add(k, c) takes c = c_k + j p_k, j in {0, 1, 2} (the
+// combine passes unreduced differences of residues); value() gives X.
 struct CrtAcc {
     unsigned long long l0 = 0, l1 = 0, l2 = 0, l3 = 0;
-    double Sd = 0.0;
     __device__ __forceinline__ void add(int k, int c) {
         constexpr CrtConst C = kCrtK;
         const unsigned long long u = (unsigned)c;
@@ -360,12 +360,14 @@ struct CrtAcc {
         l1 += u * C.wl[k][1];
         l2 += u * C.wl[k][2];
         l3 += u * C.wl[k][3];
-        Sd += (double)c * C.wd[k];
     }
     __device__ __forceinline__ double value() const {
         constexpr CrtConst C = kCrtK;
         const unsigned __int128 S = (unsigned __int128)l0 + ((unsigned __int128)l1 << 32) +
                                     ((unsigned __int128)l2 << 64) + ((unsigned __int128)l3 << 96);
+        // S itself, not modulo 2^128 (it may reach 2^141): the limb sums are exact integers
+        const double Sd = (((double)l3 * 0x1p32 + (double)l2) * 0x1p32 + (double)l1) * 0x1p32 +
+                          (double)l0;
         const unsigned long long q = (unsigned long long)rint(Sd / C.md);
         const unsigned __int128 M = ((unsigned __int128)C.mhi << 64) | C.mlo;
         const __int128 X = (__int128)(S - (unsigned __int128)q * M);
