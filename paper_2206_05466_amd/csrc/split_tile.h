@@ -157,40 +157,52 @@ __device__ __forceinline__ int crt_modulus(int k) {
 }
 
 // Balanced residue, in [-(p_K)/2, (p_K - 1)/2], of an integer X held exactly in a double
-// (|X| < 2^62), given as X = hi 2^28 + lo with hi = floor(X 2^-28) and 0 <= lo < 2^28 (both
-// exact).  All in FP64 on integers: d = hi (2^28 mod p) + lo (|d| < 2^42, exact), the quotient
-// estimate floor(d / p) is off by at most one (d / p < 2^42, relative error ~2^-52), so
-// t = d - q p (exact) needs one correction into [0, p).
+// (|X| < 2^62), given in four exact pieces X = (x3 - 2^14) 2^48 + x2 2^32 + x1 2^16 + x0 with
+// 0 <= x3 < 2^15 and 0 <= x2, x1, x0 < 2^16.  In 32-bit integer arithmetic: d = x3 (2^48 mod p)
+// + x2 (2^32 mod p) + x1 (2^16 mod p) + x0 - 2^14 (2^48 mod p), congruent to X, each product a
+// 24-bit multiply-add (-2^22 < d < 2^26); q = d / p rounded to the nearest integer from an
+// FP32 estimate (d / p < 2^19: off by less than 0.1 before the rounding), so r = d - q p (exact)
+// lies in [-0.6 p, 0.6 p] and one step brings it into the balanced range.
 template <int K>
-__device__ __forceinline__ int crt_residue(double hi, double lo) {
+__device__ __forceinline__ int crt_residue(unsigned x3, unsigned x2, unsigned x1, unsigned x0) {
     constexpr int p = kCrtP[K];
-    constexpr double r28 = (double)((1LL << 28) % p);
-    const double d = fma(hi, r28, lo);
-    const double q = floor(d * (1.0 / (double)p));
-    double t = fma(-q, (double)p, d);
-    t = t < 0.0 ? t + (double)p : (t >= (double)p ? t - (double)p : t);
-    const int ti = (int)t;
-    return ti > (p - 1) / 2 ? ti - p : ti;
+    constexpr unsigned c48 = (unsigned)((1ULL << 48) % p), c32 = (unsigned)((1ULL << 32) % p);
+    constexpr unsigned c16 = (unsigned)((1ULL << 16) % p);
+    const int d = (int)(x3 * c48 + x2 * c32 + x1 * c16 + x0) - (int)((1u << 14) * c48);
+    const int q = (int)rintf((float)d * (1.0f / (float)p));
+    int r = d - q * p;
+    r = r > (p - 1) / 2 ? r - p : r;
+    return r < -(p / 2) ? r + p : r;
 }
 
 template <int K>
 struct CrtResidues {
-    // d[k] = balanced residue of X = hi 2^28 + lo modulo p_k for k < K
-    __device__ __forceinline__ static void run(double hi, double lo, int (&d)[kCrtMods]) {
-        CrtResidues<K - 1>::run(hi, lo, d);
-        d[K - 1] = crt_residue<K - 1>(hi, lo);
+    // d[k] = balanced residue of X (in the pieces of crt_residue) modulo p_k for k < K
+    __device__ __forceinline__ static void run(unsigned x3, unsigned x2, unsigned x1, unsigned x0,
+                                               int (&d)[kCrtMods]) {
+        CrtResidues<K - 1>::run(x3, x2, x1, x0, d);
+        d[K - 1] = crt_residue<K - 1>(x3, x2, x1, x0);
     }
 };
 template <>
 struct CrtResidues<0> {
-    __device__ __forceinline__ static void run(double, double, int (&)[kCrtMods]) {}
+    __device__ __forceinline__ static void run(unsigned, unsigned, unsigned, unsigned,
+                                               int (&)[kCrtMods]) {}
 };
 
-// Residues of the integer X (exactly representable as a double, |X| < 2^62).
+// Residues of the integer X (exactly representable as a double, |X| < 2^62): its 16-bit pieces,
+// taken in FP64 (exact: floors, and differences of exact multiples of powers of two); the masks
+// change no value and let the compiler use 24-bit multiplies.
 __device__ __forceinline__ void crt_residues_of(double X, int (&d)[kCrtMods]) {
-    const double hi = floor(X * 0x1p-28);
-    const double lo = fma(-hi, 0x1p28, X);
-    CrtResidues<kCrtMods>::run(hi, lo, d);
+    const double h3 = floor(X * 0x1p-48);      // [-2^14, 2^14)
+    const double r3 = fma(-h3, 0x1p48, X);     // [0, 2^48)
+    const double h2 = floor(r3 * 0x1p-32);
+    const double r2 = fma(-h2, 0x1p32, r3);    // [0, 2^32)
+    const double h1 = floor(r2 * 0x1p-16);
+    const double h0 = fma(-h1, 0x1p16, r2);    // [0, 2^16)
+    const unsigned x3 = (unsigned)((int)h3 + (1 << 14)) & 0x7fffu;
+    CrtResidues<kCrtMods>::run(x3, (unsigned)h2 & 0xffffu, (unsigned)h1 & 0xffffu,
+                               (unsigned)h0 & 0xffffu, d);
 }
 
 // Residues of x scaled by 2^(b - e) and rounded to the nearest integer (ties to even): the
