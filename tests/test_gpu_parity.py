@@ -889,6 +889,33 @@ def test_tiny_sizes_every_mode(dev, N):
         assert np.linalg.norm(to_host(Wd) - W4) <= 1e-12 * scale
 
 
+def test_ensemble_tiny_sizes_history_start(dev):
+    """An ensemble of N = 1, 2, 3, 5, 17 and 40 with guess mode 3 and the difference form over 6
+    steps (the start kernel's 1024-entry work items cover a whole small matrix in one, partly
+    empty, item; the solve's bands, the products' and the update's tiles are ragged): every
+    simulation ends where the oracle's run does (1e-12 of ||W||, exact zeros for N = 1), with
+    its evaluation count in the last step."""
+    from paper_2206_05466_amd import Ensemble
+
+    sizes = [1, 2, 3, 5, 17, 40]
+    h, tol, K, steps = 0.01, 1e-12, 50, 6
+    W0s = [w0(n, 500 + j) for j, n in enumerate(sizes)]
+    Wd = [to_dev(W) for W in W0s]
+    with Ensemble(sizes) as ens:
+        ens.set_initial_guess(3)
+        ens.set_update_form(1)
+        ens.run(Wd, h, steps, tol, K)
+        its, res = ens.stats()
+    for j, n in enumerate(sizes):
+        Wr, it_ref, _ = O.isomp_run(W0s[j], h, steps, tol, K, extrapolate=True, degree=3,
+                                    update="difference", solution_differences=True)
+        scale = max(np.linalg.norm(W0s[j]), 1e-300)
+        got = to_host(Wd[j])
+        assert its[j] == it_ref[-1] and res[j] < tol, (n, its[j], it_ref)
+        assert np.linalg.norm(got - Wr) <= 1e-12 * scale, (n, np.linalg.norm(got - Wr))
+        assert np.abs(got + got.conj().T).max() == 0.0, n
+
+
 @pytest.mark.parametrize("order,N,form,h", [(4, 64, 1, 0.01), (4, 100, 0, 0.01), (6, 48, 1, 0.005)])
 def test_isomp_composed_polynomial_guess(dev, order, N, form, h):
     """Orders 4 and 6 with the per-substep polynomial starts (mode 2): the oracle's evaluation
