@@ -165,6 +165,22 @@ ze_status ze_set_stopping(ze_ctx* ctx, int mode);
 ze_status ze_set_steady_cap(ze_ctx* ctx, int cap, int from_step);
 
 /*
+ * ze_set_continuation -- 1: a ze_isomp_run on the same W (the same device pointer, holding the
+ * last run's result unchanged), with the same h, precision, starting-iterate mode, order and
+ * update form as the last successful run on this context, continues that run's trajectory: its
+ * steps carry on the step index (which the starting iterate and ze_set_steady_cap go by) and
+ * the history of midpoints, so a long simulation split into calls (diagnostics between them,
+ * as in the long runs of Sec. 4) takes the same steps as one call.  Anything else starts a new
+ * run at step 0: a call that differs in one of those, a step of ze_isomp_step in between, a run
+ * that ended early with an error or ZE_ENOTCONV; with guess mode 3 at order 2, a previous
+ * trajectory of fewer than 4 steps (the states its first steps use are not kept).  0 (the
+ * default): every call starts at step 0.  The library cannot see whether W was changed
+ * between the calls: the caller keeps it unchanged.  A run captured into a graph is recorded
+ * with the step indices it had at capture.  Errors: ZE_EINVAL.
+ */
+ze_status ze_set_continuation(ze_ctx* ctx, int on);
+
+/*
  * ze_run_stats -- on-device stopping: synchronises the context's stream and reads the last
  * nsteps steps of the last ze_isomp_run / ze_isomp_step call (nsteps <= its length).
  *   iters, resid  host arrays of nsteps entries (may be NULL), as ze_isomp_run fills them.

@@ -624,6 +624,35 @@ static int step_cap(const ze_ctx* c, int maxit, int n) {
     return (c->cap2 > 0 && n >= c->cap2_after) ? std::min(maxit, c->cap2) : maxit;
 }
 
+// The step index a run on W starts from: that of the run it continues (ze_set_continuation),
+// else 0.  Guess mode 3 at order 2 needs the states of the first four steps for steps 1 .. 3,
+// which a run does not keep, so it continues only from step 4 on.
+static int run_first_step(const ze_ctx* c, const void* W, double h, int prec) {
+    if (!c->cont || c->cont_n < 0 || W != c->cont_w || h != c->cont_h || prec != c->cont_prec ||
+        c->guess_mode != c->cont_guess || c->update_form != c->cont_form ||
+        c->comp_w.size() != c->cont_ns)
+        return 0;
+    if (c->guess_mode == 3 && c->comp_w.size() == 1 && c->cont_n < 4) return 0;
+    return c->cont_n;
+}
+
+// After a run from step n0 of nsteps steps: a successful one (ZE_OK, or ZE_ENOTCONV, whose
+// steps all completed) can be continued; any other outcome ends the continuation.
+static void run_finished(ze_ctx* c, const void* W, double h, int prec, int n0, int nsteps,
+                         ze_status st) {
+    if (c->cont && (st == ZE_OK || st == ZE_ENOTCONV)) {
+        c->cont_n = n0 + nsteps;
+        c->cont_w = W;
+        c->cont_h = h;
+        c->cont_prec = prec;
+        c->cont_guess = c->guess_mode;
+        c->cont_form = c->update_form;
+        c->cont_ns = c->comp_w.size();
+    } else {
+        c->cont_n = -1;
+    }
+}
+
 // On-device stopping: the records of the last run (nsteps <= its length) and its status.
 static ze_status read_run_records(ze_ctx* c, int nsteps, int* iters, double* resid) {
     if (nsteps < 0 || nsteps > c->last_run_steps) return ZE_EINVAL;
@@ -664,16 +693,19 @@ static ze_status run_device(ze_ctx* c, void* W, double h, double tol, int maxit,
         return ZE_EINVAL;
     if (!is_finite(h) || !(tol >= 0.0) || !is_finite(tol) || maxit < 1) return ZE_EINVAL;
     ZE_HIP(launch_ctl_run_begin(c->dctl, c->dctld, c->stream));
-    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, nsteps};
+    const int n0 = run_first_step(c, W, h, prec);
+    c->cont_n = -1;
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, n0 + nsteps};
     for (int n = 0; n < nsteps; ++n) {
-        const ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n), prec, n, nullptr,
-                                           nullptr);
+        const ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n0 + n), prec, n0 + n,
+                                           nullptr, nullptr);
         if (st != ZE_OK) {
             finish_run(c, rs);
             return st;
         }
     }
     ZE_TRY(finish_run(c, rs));
+    run_finished(c, W, h, prec, n0, nsteps, ZE_OK);
     c->last_run_steps = nsteps;
     if (!iters && !resid) return ZE_OK;
     return read_run_records(c, nsteps, iters, resid);
@@ -684,7 +716,14 @@ ze_status ze_isomp_step(ze_ctx* c, void* W, double h, double tol, int maxit, int
     g_last_error.clear();
     if (!c || !W) return ZE_EINVAL;
     if (c->validate) ZE_TRY(check_su(c, W));
-    if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, 1, prec, iters, resid);
+    c->cont_n = -1;  // a single step uses the workspaces a continued run would need
+    if (c->stop_mode == 1) {
+        const int keep = c->cont;
+        c->cont = 0;
+        const ze_status st = run_device(c, W, h, tol, maxit, 1, prec, iters, resid);
+        c->cont = keep;
+        return st;
+    }
     RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, 1};
     const ze_status st = composed_step(c, rs, h, tol, maxit, prec, 0, iters, resid);
     const ze_status fin = finish_run(c, rs);
@@ -730,11 +769,14 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
     if (!c || !W || nsteps < 0) return ZE_EINVAL;
     if (c->validate && nsteps > 0) ZE_TRY(check_su(c, W));
     if (c->stop_mode == 1) return run_device(c, W, h, tol, maxit, nsteps, prec, iters, resid);
-    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, nsteps};
+    const int n0 = run_first_step(c, W, h, prec);
+    c->cont_n = -1;
+    RunState rs{static_cast<double2*>(W), static_cast<double2*>(W), c->Wn, n0 + nsteps};
+    ze_status out = ZE_OK;
     for (int n = 0; n < nsteps; ++n) {
         int k = 0;
         double r = 0.0;
-        ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n), prec, n, &k, &r);
+        ze_status st = composed_step(c, rs, h, tol, step_cap(c, maxit, n0 + n), prec, n0 + n, &k, &r);
         if (iters) iters[n] = k;
         if (resid) resid[n] = r;
         if (st != ZE_OK) {
@@ -742,7 +784,16 @@ ze_status ze_isomp_run(ze_ctx* c, void* W, double h, double tol, int maxit, int 
             return st;
         }
     }
-    return finish_run(c, rs);
+    out = finish_run(c, rs);
+    run_finished(c, W, h, prec, n0, nsteps, out);
+    return out;
+}
+
+ze_status ze_set_continuation(ze_ctx* c, int on) {
+    if (!c || on < 0 || on > 1) return ZE_EINVAL;
+    c->cont = on;
+    c->cont_n = -1;
+    return ZE_OK;
 }
 
 ze_status ze_casimirs(ze_ctx* c, const void* W, int kmax, double* out) {

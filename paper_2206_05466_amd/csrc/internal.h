@@ -118,6 +118,14 @@ struct ze_ctx {
     // Evaluation cap min(maxit, cap2) of the steps with index >= cap2_after in a run (cap2 0:
     // maxit for every step; ze_set_steady_cap).
     int cap2 = 0, cap2_after = 0;
+    // Continuation (ze_set_continuation): with cont on, the step index cont_n the next run
+    // starts from when it continues the last successful run (same W pointer, h, precision,
+    // starting-iterate mode, order and update form); cont_n < 0: no run to continue.
+    int cont = 0, cont_n = -1;
+    const void* cont_w = nullptr;
+    double cont_h = 0.0;
+    int cont_prec = -1, cont_guess = -1, cont_form = -1;
+    size_t cont_ns = 0;
     int* dctl = nullptr;
     double* dctld = nullptr;
     int* dstep_it = nullptr;

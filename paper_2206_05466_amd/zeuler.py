@@ -46,6 +46,7 @@ SIGNATURES = {
     "ze_set_order": (_c_int, [_vp, _c_int]),
     "ze_set_stopping": (_c_int, [_vp, _c_int]),
     "ze_set_steady_cap": (_c_int, [_vp, _c_int, _c_int]),
+    "ze_set_continuation": (_c_int, [_vp, _c_int]),
     "ze_run_stats": (_c_int, [_vp, _c_int, _P_int, _P_double]),
     "ze_profile": (_c_int, [_vp, _c_int]),
     "ze_profile_read": (_c_int, [_vp, _P_double, ctypes.POINTER(ctypes.c_longlong), _c_int]),
@@ -225,6 +226,12 @@ class Zeuler:
         """Evaluation cap min(maxit, cap) for the steps from index from_step on of each run (with
         the polynomial starts); 0 restores maxit for every step."""
         _check(self.lib.ze_set_steady_cap(self._ctx, int(cap), int(from_step)), "ze_set_steady_cap")
+
+    def set_continuation(self, on: bool = True):
+        """With it on, an isomp_run on the same W (unchanged since) with the same h, precision
+        and step options as the last one continues its trajectory (step index and midpoint
+        history) instead of starting at step 0."""
+        _check(self.lib.ze_set_continuation(self._ctx, int(bool(on))), "ze_set_continuation")
 
     def run_stats(self, nsteps: int):
         """(iterations, residuals, status) of the last nsteps steps of the last run (on-device
