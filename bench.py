@@ -334,6 +334,7 @@ def long_leg(steps):
     W /= float(np.linalg.norm(W.cpu().numpy(), 2))  # input recipe: unit spectral norm
     z.set_initial_guess(3)
     z.set_update_form(1)
+    z.set_continuation(True)  # one trajectory: each call continues the last one's history
     nf0 = float(torch.linalg.norm(W).item())
 
     def diag():
@@ -367,6 +368,7 @@ def long_leg(steps):
     l = np.arange(N)
     sel = (l >= 21) & (l <= 200) & (E > 0)
     slope = float(np.polyfit(np.log(l[sel]), np.log(E[sel]), 1)[0]) if sel.sum() > 2 else None
+    z.set_continuation(False)
     # the same run from W_n at every step and from the linear start, drift at the end only
     # (at most 10^4 steps each)
     csteps = min(steps, 10000)
@@ -392,7 +394,8 @@ def long_leg(steps):
     return {
         "workload": f"long512: N={N}, sigma_l law paper (degrees 2..20, seed {cfg['seed']}), "
                     f"unit spectral norm, h={h}, tol={tol}, {steps} steps, polynomial start "
-                    f"(restarted every {sample} steps, at each sample)",
+                    f"(one trajectory: the calls between the samples every {sample} steps "
+                    f"continue each other, ze_set_continuation)",
         "s_per_step": t_run / steps,
         "max_iters_per_step": it_max,
         "max_resid": res_max,
