@@ -171,8 +171,9 @@ ze_status ze_set_steady_cap(ze_ctx* ctx, int cap, int from_step);
  * steps carry on the step index (which the starting iterate and ze_set_steady_cap go by) and
  * the history of midpoints, so a long simulation split into calls (diagnostics between them,
  * as in the long runs of Sec. 4) takes the same steps as one call.  Anything else starts a new
- * run at step 0: a call that differs in one of those, a step of ze_isomp_step in between, a run
- * that ended early with an error or ZE_ENOTCONV; with guess mode 3 at order 2, a previous
+ * run at step 0: a call that differs in one of those, a step of ze_isomp_step or a call of a
+ * step-option setter (initial guess, order, update form, slices) in between, a run that ended
+ * early with an error or ZE_ENOTCONV; with guess mode 3 at order 2, a previous
  * trajectory of fewer than 4 steps (the states its first steps use are not kept).  0 (the
  * default): every call starts at step 0.  The library cannot see whether W was changed
  * between the calls: the caller keeps it unchanged.  A run captured into a graph is recorded

@@ -876,6 +876,7 @@ ze_status ze_energy_spectrum(ze_ctx* c, const void* omega, void* E) {
 
 ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
     if (!c || mode < 0 || mode > 3) return ZE_EINVAL;
+    c->cont_n = -1;  // the next run starts at step 0
     if (mode >= 2) ZE_TRY(ze_ensure_rings(c, (int)c->comp_w.size()));
     if (mode == 3) {
         for (double2*& b : c->Wh)
@@ -888,6 +889,7 @@ ze_status ze_set_initial_guess(ze_ctx* c, int mode) {
 
 ze_status ze_set_order(ze_ctx* c, int order) {
     if (!c || (order != 2 && order != 4 && order != 6)) return ZE_EINVAL;
+    c->cont_n = -1;  // the next run starts at step 0
     // Triple jump (Yoshida 1990): from a symmetric method of even order p, the substeps
     // g1, g2, g1 with g1 = 1 / (2 - 2^(1/(p+1))) and g2 = 1 - 2 g1 give order p + 2.
     std::vector<double> w{1.0};
@@ -907,6 +909,7 @@ ze_status ze_set_order(ze_ctx* c, int order) {
 
 ze_status ze_set_split_slices(ze_ctx* c, int slices) {
     if (!c || slices < 2 || slices > split_max_slices(c->N)) return ZE_EINVAL;
+    c->cont_n = -1;  // the next run starts at step 0
     c->split_slices = slices;
     c->split_slices_low = slices > 2 ? slices - 1 : 2;
     return ZE_OK;
@@ -914,12 +917,14 @@ ze_status ze_set_split_slices(ze_ctx* c, int slices) {
 
 ze_status ze_set_update_form(ze_ctx* c, int form) {
     if (!c || form < 0 || form > 1) return ZE_EINVAL;
+    c->cont_n = -1;  // the next run starts at step 0
     c->update_form = form;
     return ZE_OK;
 }
 
 ze_status ze_set_split_slices_lower(ze_ctx* c, int slices) {
     if (!c || slices < 2 || slices > c->split_slices) return ZE_EINVAL;
+    c->cont_n = -1;  // the next run starts at step 0
     c->split_slices_low = slices;
     return ZE_OK;
 }

@@ -114,5 +114,8 @@ def test_what_starts_over(dev):
         z.isomp_run(W, h, 5, 1e-12, 50)
         W2 = W.clone()                   # another buffer
         check(W2, h, 3)
+        z.isomp_run(W, h, 5, 1e-12, 50)
+        z.set_initial_guess(3)           # a step-option setter in between, even to the same
+        check(W, h, 3)
         z.set_continuation(False)        # off
         check(W, h, 3)
