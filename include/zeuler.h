@@ -486,6 +486,18 @@ ze_status ze_ensemble_set_initial_guess(ze_ens* ens, int mode);
  */
 ze_status ze_ensemble_set_steady_cap(ze_ens* ens, int cap, int from_step);
 
+/*
+ * ze_ensemble_set_continuation -- as ze_set_continuation for the ensemble: with 1, a
+ * ze_ensemble_run (or ze_ensemble_step) on the same nsim device pointers, holding the last
+ * run's results unchanged, with the same h, precision, start mode and update form, continues
+ * that run's trajectories (the step index on the device and every simulation's history of
+ * midpoints) instead of starting at step 0; a start-mode, update-form or slice setter in
+ * between, the autotuner's first run in a precision, or with guess mode 3 a trajectory of
+ * fewer than 4 steps so far, starts over.  0 (the default): every call starts at step 0.
+ * Errors: ZE_EINVAL.
+ */
+ze_status ze_ensemble_set_continuation(ze_ens* ens, int on);
+
 #ifdef __cplusplus
 }
 #endif

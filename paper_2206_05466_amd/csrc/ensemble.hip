@@ -534,6 +534,13 @@ struct ze_ens {
     // evaluation cap of the steps from index cap2_after on (guess mode 2; 0: the run's cap K)
     // and the step graph captured with it
     int cap2 = 0, cap2_after = 0, g_cap2 = -1;
+    // continuation (ze_ensemble_set_continuation): the step index cont_n the next run starts
+    // from when it continues the last one (same matrices, h, precision, start mode and update
+    // form); cont_n < 0: none
+    int cont = 0, cont_n = -1;
+    std::vector<void*> cont_w;
+    double cont_h = 0.0;
+    int cont_prec = -1, cont_guess = -1, cont_form = -1;
     bool g_cap2_first = true;  // the capped graph was captured for a step index that may be 0
     hipGraphExec_t exec_s = nullptr;
 };
@@ -923,11 +930,25 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     for (int i = 0; i < e->nsim; ++i)
         if (!W[i]) return ZE_EINVAL;
     const bool split = prec == ZE_PREC_SPLIT;
+    // the step index this run starts from: that of the run it continues, else 0 (guess mode 3
+    // needs the states of the first four steps for steps 1 .. 3, which a run does not keep)
+    int n0 = 0;
+    if (e->cont && e->cont_n >= 0 && h == e->cont_h && prec == e->cont_prec &&
+        e->guess_mode == e->cont_guess && e->update_form == e->cont_form &&
+        (e->guess_mode != 3 || e->cont_n >= 4)) {
+        n0 = e->cont_n;
+        for (int i = 0; i < e->nsim; ++i)
+            if (W[i] != e->cont_w[i]) n0 = 0;
+    }
+    e->cont_n = -1;
     // order after the caller's pending work
     ZE_HIP(hipEventRecord(e->ev_in, e->user));
     ZE_HIP(hipStreamWaitEvent(e->own, e->ev_in, 0));
     if (split) ZE_TRY(ensure_split(e));
-    if (split ? e->s_order < 0 : e->variant < 0) ZE_TRY(autotune(e, W, h, tol, K, prec));
+    if (split ? e->s_order < 0 : e->variant < 0) {
+        ZE_TRY(autotune(e, W, h, tol, K, prec));
+        n0 = 0;  // the candidates' steps moved the step index
+    }
     ZE_TRY(set_pointers(e, W));
     const int variant = split ? 0 : e->variant, order = split ? e->s_order : e->order;
     if (!e->exec || e->g_prec != prec || e->g_variant != variant || e->g_order != order ||
@@ -940,12 +961,12 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
                            e->dp, e->nsim);
         ZE_HIP(hipGetLastError());
     }
-    if (e->guess_mode >= 2 && nsteps > 0) {  // the run's step index starts at 0
+    if (e->guess_mode >= 2 && nsteps > 0 && n0 == 0) {  // the run's step index starts at 0
         hipLaunchKernelGGL(ens_stepc_kernel, dim3(1), dim3(kStepcThreads), 0, e->own, e->stepc, 0,
                            e->dp, 0, 0, 0);
         ZE_HIP(hipGetLastError());
     }
-    for (int n = 0; n < nsteps; ++n) {
+    for (int n = n0; n < n0 + nsteps; ++n) {
         hipGraphExec_t g = n > 0 && e->guess_mode == 1 ? e->exec_x : e->exec;
         if (e->exec_s && n >= e->cap2_after) g = e->exec_s;
         ZE_HIP(hipGraphLaunch(g, e->own));
@@ -956,6 +977,21 @@ ze_status ze_ensemble_run(ze_ens* e, void* const* W, double h, double tol, int K
     }
     ZE_HIP(hipEventRecord(e->ev_out, e->own));
     ZE_HIP(hipStreamWaitEvent(e->user, e->ev_out, 0));
+    if (e->cont) {
+        e->cont_n = n0 + nsteps;
+        e->cont_w.assign(W, W + e->nsim);
+        e->cont_h = h;
+        e->cont_prec = prec;
+        e->cont_guess = e->guess_mode;
+        e->cont_form = e->update_form;
+    }
+    return ZE_OK;
+}
+
+ze_status ze_ensemble_set_continuation(ze_ens* e, int on) {
+    if (!e || on < 0 || on > 1) return ZE_EINVAL;
+    e->cont = on;
+    e->cont_n = -1;
     return ZE_OK;
 }
 
@@ -987,6 +1023,7 @@ ze_status ze_ensemble_tuning(ze_ens* e, int prec, int* choice, double* ms) {
 
 ze_status ze_ensemble_set_initial_guess(ze_ens* e, int mode) {
     if (!e || mode < 0 || mode > 3) return ZE_EINVAL;
+    e->cont_n = -1;  // the next run starts at step 0
     const bool ring = mode >= 2 && !e->hp[0].H1, states = mode == 3 && !e->hp[0].S1;
     if (ring || states) {
         // the descriptors on the device are the current ones (the steps turn them): fetch, add
@@ -1023,6 +1060,7 @@ ze_status ze_ensemble_set_steady_cap(ze_ens* e, int cap, int from_step) {
 
 ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
     if (!e || slices < 2 || slices > split_max_slices(e->maxN)) return ZE_EINVAL;
+    e->cont_n = -1;  // the next run starts at step 0
     e->slices = slices;
     e->slices_low = slices > 2 ? slices - 1 : 2;
     return ZE_OK;
@@ -1030,12 +1068,14 @@ ze_status ze_ensemble_set_split_slices(ze_ens* e, int slices) {
 
 ze_status ze_ensemble_set_update_form(ze_ens* e, int form) {
     if (!e || form < 0 || form > 1) return ZE_EINVAL;
+    e->cont_n = -1;  // the next run starts at step 0
     e->update_form = form;
     return ZE_OK;
 }
 
 ze_status ze_ensemble_set_split_slices_lower(ze_ens* e, int slices) {
     if (!e || slices < 2 || slices > e->slices) return ZE_EINVAL;
+    e->cont_n = -1;  // the next run starts at step 0
     e->slices_low = slices;
     return ZE_OK;
 }

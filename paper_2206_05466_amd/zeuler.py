@@ -61,6 +61,7 @@ SIGNATURES = {
     "ze_ensemble_set_split_slices_lower": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_update_form": (_c_int, [_vp, _c_int]),
     "ze_ensemble_set_steady_cap": (_c_int, [_vp, _c_int, _c_int]),
+    "ze_ensemble_set_continuation": (_c_int, [_vp, _c_int]),
 }
 
 PHASES = ("stream_solve", "product_PW", "lower_product_epilogue", "residual_reduce")
@@ -408,6 +409,12 @@ class Ensemble:
         """Slices of the ensemble's lower products (2 .. the product's slices)."""
         _check(self.lib.ze_ensemble_set_split_slices_lower(self._ens, int(slices)),
                "ze_ensemble_set_split_slices_lower")
+
+    def set_continuation(self, on: bool = True):
+        """With it on, a run on the same matrices (unchanged since) with the same h, precision
+        and step options continues the last run's trajectories instead of starting at step 0."""
+        _check(self.lib.ze_ensemble_set_continuation(self._ens, int(bool(on))),
+               "ze_ensemble_set_continuation")
 
     def set_initial_guess(self, mode: int):
         """0: every step starts from W_n; 1: steps after the first of a run start each simulation

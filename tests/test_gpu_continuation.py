@@ -119,3 +119,39 @@ def test_what_starts_over(dev):
         check(W, h, 3)
         z.set_continuation(False)        # off
         check(W, h, 3)
+
+
+@pytest.mark.parametrize("prec_name,mode", [("fp64", 3), ("fp64", 2), ("fp64", 1), ("split", 3)])
+def test_ensemble_split_run_equals_one_run(dev, prec_name, mode):
+    """The ensemble's trajectories taken as calls of 5, 1 and 6 steps with continuation equal,
+    bit for bit, one call of 12 (matrices and the last step's counts and residuals); with a
+    steady cap from step 4 as well."""
+    from paper_2206_05466_amd import PREC_FP64, PREC_SPLIT, Ensemble
+
+    sizes = [40, 64, 96, 17]
+    h, tol, K = 0.01, 1e-12, 8
+    prec = PREC_SPLIT if prec_name == "split" else PREC_FP64
+    W0s = [field(n, 20 + j) for j, n in enumerate(sizes)]
+    out = []
+    with Ensemble(sizes) as ens:  # one ensemble: the autotuner's choice is the same for both
+        ens.set_initial_guess(mode)
+        ens.set_update_form(1)
+        ens.set_steady_cap(3, 4)
+        if prec == PREC_SPLIT:
+            ens.set_split_slices(5)
+        ens.set_continuation(True)
+        for chunks in ([12], [5, 1, 6]):  # the second set of matrices starts at step 0
+            Wd = [torch.from_numpy(W).cuda() for W in W0s]
+            for k in chunks:
+                ens.run(Wd, h, k, tol, K, prec=prec)
+            its, res = ens.stats()
+            torch.cuda.synchronize()
+            out.append(([W.cpu().numpy() for W in Wd], list(its), list(res)))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    if prec == PREC_FP64 and mode == 3:
+        for j in range(len(sizes)):
+            Wr, ir, _ = O.isomp_run(W0s[j], h, 12, tol, K, extrapolate=True, degree=3,
+                                    update="difference", solution_differences=True)
+            assert np.linalg.norm(out[1][0][j] - Wr) <= 1e-12 * np.linalg.norm(Wr)

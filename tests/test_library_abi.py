@@ -57,6 +57,7 @@ def test_strerror_and_invalid_create_without_gpu():
     assert lib.ze_set_initial_guess(None, 3) == zeuler.ZE_EINVAL
     assert lib.ze_set_stopping(None, 1) == zeuler.ZE_EINVAL
     assert lib.ze_set_continuation(None, 1) == zeuler.ZE_EINVAL
+    assert lib.ze_ensemble_set_continuation(None, 1) == zeuler.ZE_EINVAL
 
 
 def test_noalloc_product_refuses_sizes_without_gpu():
