@@ -798,7 +798,7 @@ def main():
                     help="1: run the orders512 leg (orders 2/4/6 accuracy against cost), 0: skip")
     ap.add_argument("--ensemble-steps", type=int, default=50,
                     help="steps of the 64-simulation ensemble legs, FP64 and split (0: skip them)")
-    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail-out", default="bench_detail.json",
                     help="file that receives the full record of every leg ('' : none); the last "
                          "stdout line is a compact summary of it")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

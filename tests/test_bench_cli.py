@@ -80,7 +80,7 @@ def test_compact_line_parses_and_stays_small():
     sys.path.insert(0, ROOT)
     import bench
 
-    rec = bench.compact_record(_canned_record(), "gpurun_out/bench_detail.json")
+    rec = bench.compact_record(_canned_record(), "bench_detail.json")
     line = json.dumps(rec)
     assert "\n" not in line and len(line) < 2048, len(line)
     back = json.loads(line)
