@@ -147,10 +147,30 @@ __global__ __launch_bounds__(256) void ens_begin_kernel(const EnsProb* __restric
     const double c3 = d == 2 ? 1.0 : 4.0;
     const size_t e0 = (size_t)it.y * kBeginChunk + threadIdx.x;
     double2 g[4];
+    if (mode >= 2 && n >= 4) {  // the steady case, one straight pass: all 16 loads issued first
+        double2 f1[4], f2[4], f3[4], f4[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const size_t e = e0 + (size_t)u * 256;
-        g[u] = begin_value(p, e < n2 ? e : n2 - 1, mode, n, slope, c1, c2, c3);  // in bounds
+        for (int u = 0; u < 4; ++u) {
+            size_t e = e0 + (size_t)u * 256;
+            e = e < n2 ? e : n2 - 1;  // in bounds
+            f1[u] = p.H1[e];
+            f2[u] = p.H2[e];
+            f3[u] = p.H3[e];
+            f4[u] = p.F[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // 4 H1 - 6 H2 + 4 H3 - F, summed in that order
+            double2 t = make_double2(4.0 * f1[u].x, 4.0 * f1[u].y);
+            t = make_double2(t.x + -6.0 * f2[u].x, t.y + -6.0 * f2[u].y);
+            t = make_double2(t.x + 4.0 * f3[u].x, t.y + 4.0 * f3[u].y);
+            g[u] = make_double2(t.x - f4[u].x, t.y - f4[u].y);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t e = e0 + (size_t)u * 256;
+            g[u] = begin_value(p, e < n2 ? e : n2 - 1, mode, n, slope, c1, c2, c3);  // in bounds
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
