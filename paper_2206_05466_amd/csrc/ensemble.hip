@@ -402,8 +402,8 @@ __global__ __launch_bounds__(kUThreads) void ens_update_split_kernel(const EnsPr
     const double2* Wt = p.F;
     int I, J;
     lower_tile(it.y, I, J);
-    lower_update_tile(I, J, nullptr, p.G, p.eA, p.ep, s, p.A, p.Wn, Wt, p.F, p.W, p.rowpart, p.N,
-                      h, form, sT);
+    lower_update_tile_t<kUT, true>(I, J, nullptr, p.G, p.eA, p.ep, s, p.A, p.Wn, Wt, p.F, p.W,
+                                   p.rowpart, p.N, h, form, sT);
 }
 
 __global__ __launch_bounds__(256) void ens_resid_kernel(const EnsProb* __restrict__ probs,

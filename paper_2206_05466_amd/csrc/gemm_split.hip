@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void split_combine_kernel(const int* __re
 }
 
 // ---------------------------------------------------------------- fixed-point update
-template <int UT>
+template <int UT, bool SLABS>
 __global__ __launch_bounds__(kThreads) void lower_update_kernel(
     const double2* __restrict__ Qf, const int* __restrict__ G, const int* __restrict__ ea,
     const int* __restrict__ eb, int s, const double2* __restrict__ Am,
@@ -309,7 +309,8 @@ __global__ __launch_bounds__(kThreads) void lower_update_kernel(
     while ((I + 1) * (I + 2) / 2 <= b) ++I;
     while (I * (I + 1) / 2 > b) --I;
     const int J = b - I * (I + 1) / 2;
-    lower_update_tile_t<UT>(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
+    lower_update_tile_t<UT, SLABS>(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form,
+                                   sT);
 }
 
 }  // namespace
@@ -470,7 +471,10 @@ hipError_t launch_lower_update(const ze_ctx* c, const double2* Q, const double2*
                                hipStream_t st, const int* skip) {
     const int N = c->N, ut = c->ut;
     const int T = (N + ut - 1) / ut;
-    auto kern = ut == 64 ? lower_update_kernel<64> : (ut == 32 ? lower_update_kernel<32> : lower_update_kernel<16>);
+    auto kern = Q ? (ut == 64 ? lower_update_kernel<64, false>
+                              : (ut == 32 ? lower_update_kernel<32, false> : lower_update_kernel<16, false>))
+                  : (ut == 64 ? lower_update_kernel<64, true>
+                              : (ut == 32 ? lower_update_kernel<32, true> : lower_update_kernel<16, true>));
     hipLaunchKernelGGL(kern, dim3(T * (T + 1) / 2), dim3(kThreads), 0, st, Q, c->split_g, ea, eb,
                        slices_of(c, 1), A, Wn, Wt, F, Wout, rowpart, N, h, c->update_form, skip);
     return hipGetLastError();

@@ -24,7 +24,9 @@ constexpr int kUT = 64;  // the tile of the ensemble kernels (and of the single 
 constexpr int kUThreads = 256;
 // Q comes from the FP64 lower product (Qf != nullptr, complex N x N, lower tiles) or from the
 // int32 slabs of the split lower product (G, ea, eb, s).
-template <int UT>
+// SLABS: Q from the slabs (Qf unused), else from Qf; each form is its own instance, so the
+// registers the slab sums need do not cost the FP64 form occupancy.
+template <int UT, bool SLABS = false>
 __device__ __forceinline__ void lower_update_tile_t(int I, int J, const double2* __restrict__ Qf,
                                          const int* __restrict__ G, const int* __restrict__ ea,
                                          const int* __restrict__ eb, int s,
@@ -58,14 +60,24 @@ __device__ __forceinline__ void lower_update_tile_t(int I, int J, const double2*
         if (ok) {
             const size_t o = (size_t)R * N + c;
             double2 qv = make_double2(0.0, 0.0);
-            if (Qf) {
+            if (!SLABS) {
                 qv = Qf[o];
-            } else {  // Q = A P from the int32 slabs
-                for (int t = s + 1; t >= 2; --t) {
-                    const int2 g = *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o);
-                    const double w = ldexp(1.0, 2 - 8 * t);
-                    qv.x += w * (double)g.x;
-                    qv.y += w * (double)g.y;
+            } else {  // Q = A P from the int32 slabs t = s + 1 .. 2, summed in that order
+                int2 gv[kSplitMax];
+#pragma unroll
+                for (int u = 0; u < kSplitMax; ++u) {  // all loads first (s <= kSplitMax)
+                    const int t = s + 1 - u;
+                    gv[u] = t >= 2 ? *reinterpret_cast<const int2*>(G + (size_t)(t - 2) * 2 * N * N + 2 * o)
+                                   : make_int2(0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < kSplitMax; ++u) {
+                    const int t = s + 1 - u;
+                    if (t >= 2) {
+                        const double w = ldexp(1.0, 2 - 8 * t);
+                        qv.x += w * (double)gv[u].x;
+                        qv.y += w * (double)gv[u].y;
+                    }
                 }
                 const int ex = ea[R] + eb[c];
                 qv.x = ldexp(qv.x, ex);
@@ -125,18 +137,6 @@ __device__ __forceinline__ void lower_update_tile_t(int I, int J, const double2*
     }
 }
 
-
-// The 64 x 64 form (ensemble kernels).
-__device__ __forceinline__ void lower_update_tile(int I, int J, const double2* __restrict__ Qf,
-                                         const int* __restrict__ G, const int* __restrict__ ea,
-                                         const int* __restrict__ eb, int s,
-                                         const double2* __restrict__ Am,
-                                         const double2* __restrict__ Wn, const double2* Wt,
-                                         double2* F, double2* __restrict__ Wout,
-                                         double* __restrict__ rowpart, int N, double h, int form,
-                                         double2 (*sT)[kUT + 1]) {
-    lower_update_tile_t<kUT>(I, J, Qf, G, ea, eb, s, Am, Wn, Wt, F, Wout, rowpart, N, h, form, sT);
-}
 
 // Update tile of a single context of size N: the largest of 64, 32, 16 whose lower tiles
 // number at least 512 (two rounds of one block per CU), else 16.
