@@ -69,33 +69,42 @@ __device__ inline void store_acc_tile(const d4& acc, int k, double2* Cm, int N, 
 
 // Work split of one launch: tiles [0, full) whole, one block each; tiles [full, full + tail)
 // split into S ranges of K stages (blocks full + t*S + s), whose partial sums a fix-up kernel
-// adds in a fixed order.  The split only covers the last, partial round of tiles.
+// adds in a fixed order.
 struct Split {
     int full, tail, S;
 };
 
 // `cap`: concurrent blocks of the kernel, `cus` the CUs they share, `pmax` the most split
-// blocks whose partial sums the partial buffer holds.  S is the one that finishes the split
-// round first when the rem * S blocks are dealt out evenly over the CUs: ceil(rem S / cus)
-// blocks on the busiest CU, of ceil(nk / S) stages each (ties: the larger S).
+// blocks whose partial sums the partial buffer holds.  Blocks are dealt out evenly over the
+// CUs, so the busiest CU runs ceil(full / cus) whole tiles of nk stages and ceil(tail S / cus)
+// ranges of ceil(nk / S) stages; the split minimising that is taken (ties: the larger S).  Two
+// places for the whole tiles are tried: whole rounds of `cap` blocks (the tail is the last,
+// partial round), and whole multiples of `cus` (the tail is what is left over one per CU: at
+// N = 2048 the lower product's 528 tiles on 256 CUs holding 4 blocks each are one partial
+// round, whose busiest CUs would run 3 tiles; as 512 whole tiles and 16 tiles in 16 K ranges
+// every CU runs 2 tiles and one range).  At least 8 K stages (64 complex k) per range.
 Split make_split(int ntiles, int nk, int cap, int pmax, int cus) {
-    const int rounds = ntiles / cap, rem = ntiles % cap;
-    if (rem == 0) return {ntiles, 0, 1};
-    int smax = nk / 8 > 1 ? nk / 8 : 1;  // at least 8 stages (64 complex k) per range
-    if (smax > cap / rem) smax = cap / rem;
-    if (smax > pmax / rem) smax = pmax / rem;
     if (cus < 1) cus = 1;
-    int S = 1;
-    long long best = (long long)((rem + cus - 1) / cus) * nk;
-    for (int s = 2; s <= smax; ++s) {
-        const long long L = (long long)((rem * s + cus - 1) / cus) * ((nk + s - 1) / s);
-        if (L <= best) {
-            best = L;
-            S = s;
+    if (cap < 1) cap = 1;
+    auto busiest = [&](long long n) { return (n + cus - 1) / cus; };
+    Split best{ntiles, 0, 1};
+    long long best_cost = busiest(ntiles) * nk;
+    const int fulls[2] = {(ntiles / cap) * cap, (ntiles / cus) * cus};
+    for (int f : fulls) {
+        const int rem = ntiles - f;
+        if (rem <= 0) continue;
+        int smax = nk / 8 > 1 ? nk / 8 : 1;
+        if (smax > (cap - f % cap) / rem) smax = (cap - f % cap) / rem;  // the tail fits beside
+        if (smax > pmax / rem) smax = pmax / rem;
+        for (int s = 2; s <= smax; ++s) {
+            const long long L = busiest(f) * nk + busiest((long long)rem * s) * ((nk + s - 1) / s);
+            if (L <= best_cost) {
+                best_cost = L;
+                best = {f, rem, s};
+            }
         }
     }
-    if (S <= 1) return {ntiles, 0, 1};
-    return {rounds * cap, rem, S};
+    return best;
 }
 
 // ---------------------------------------------------------------- full product

@@ -100,7 +100,8 @@ def test_zgemm_small_integers_exact(dev, N):
     assert np.array_equal(C, A @ B)
 
 
-@pytest.mark.parametrize("N", [64, 131, 384, 512, 544])
+# 1500: the split rule's whole tiles a multiple of the CU count (256 whole, 32 tiles in K ranges)
+@pytest.mark.parametrize("N", [64, 131, 384, 512, 544, 1500])
 def test_zgemm_random(dev, N):
     rng = np.random.default_rng(N + 1)
     A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
