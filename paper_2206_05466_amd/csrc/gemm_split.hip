@@ -367,17 +367,29 @@ hipError_t launch_zgemm_split(const ze_ctx* c, const double2* A, const double2* 
     const int tn = (2 * N + kI8BN - 1) / kI8BN;
     const int ntiles = lower ? tr * (tr + 1) : tr * tn;
     const int nk = ze_split_ldk(N) / kI8BK;
-    // whole rounds of the block slots one tile per block; a last partial round of `rem` tiles
-    // split along K into S parts (at least 4 stages each) when that fills the slots better
+    // whole tiles one block each, the rest split along K into S parts (at least 4 stages each,
+    // summed by integer atomics), by the rule of the FP64 products: the busiest CU's stages,
+    // ceil(full / cus) nk + ceil(tail S / cus) ceil(nk / S), minimised over whole tiles in
+    // rounds of the block slots or in multiples of the CU count (ties: the larger S; the
+    // tail's blocks fit in the slots beside the last whole round)
     int full = ntiles, S = 1;
-    const int cap = c->cap_i8 > 0 ? c->cap_i8 : ntiles;
-    const int rem = ntiles % cap;
-    if (rem > 0) {
-        int sp = cap / rem;
-        if (sp > nk / 4) sp = nk / 4;
-        if (sp > 1) {
-            full = ntiles - rem;
-            S = sp;
+    {
+        const int cap = c->cap_i8 > 0 ? c->cap_i8 : ntiles, cus = c->cus > 0 ? c->cus : 1;
+        auto busiest = [&](long long n) { return (n + cus - 1) / cus; };
+        long long best = busiest(ntiles) * nk;
+        for (int f : {(ntiles / cap) * cap, (ntiles / cus) * cus}) {
+            const int rem = ntiles - f;
+            if (rem <= 0) continue;
+            int smax = nk / 4;
+            if (smax > (cap - f % cap) / rem) smax = (cap - f % cap) / rem;
+            for (int sp = 2; sp <= smax; ++sp) {
+                const long long L = busiest(f) * nk + busiest((long long)rem * sp) * ((nk + sp - 1) / sp);
+                if (L <= best) {
+                    best = L;
+                    full = f;
+                    S = sp;
+                }
+            }
         }
     }
     if (full < ntiles) {
