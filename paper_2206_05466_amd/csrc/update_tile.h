@@ -138,10 +138,11 @@ __device__ __forceinline__ void lower_update_tile_t(int I, int J, const double2*
 }
 
 
-// Update tile of a single context of size N: 64 where its lower tiles number at least 1024
-// (four rounds of one block per CU; at two per CU, as its registers allow, a count just above
-// one round left a tail: N = 2048, 528 tiles, 66 us against 47 us with 32 x 32 tiles), else 32
-// where those number at least 512, else 16.
+// Update tile of a single context of size N: 64 where its lower tiles number at least 4096
+// (eight rounds of its two blocks per CU, so a partial last round costs little), else 32 where
+// those number at least 512, else 16.  Measured: N = 2048, 528 tiles of 64 (one round and a
+// tail of 16) 66 us against 47 us with 32 x 32 tiles; N = 4096, 2080 tiles of 64 (four rounds
+// and a tail of 32) 243 us against 225 us.
 // Row sum sum_X rowpart[X N + r] over the T slots of row r, added in slot order; the loads are
 // issued B at a time, so a small N (many slots of few rows) waits for T / B memory latencies
 // rather than T.
@@ -163,7 +164,7 @@ __device__ __forceinline__ double slot_row_sum(const double* __restrict__ rowpar
 
 __host__ __device__ inline int update_tile_of(int N) {
     const long long t64 = (N + 63) / 64, t32 = (N + 31) / 32;
-    if (t64 * (t64 + 1) / 2 >= 1024) return 64;
+    if (t64 * (t64 + 1) / 2 >= 4096) return 64;
     if (t32 * (t32 + 1) / 2 >= 512) return 32;
     return 16;
 }
