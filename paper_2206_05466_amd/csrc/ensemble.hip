@@ -1,6 +1,7 @@
 // Ensembles of independent IsoMP simulations of uneven N (statistics over many initial
-// conditions): every phase of a fixed-point evaluation -- copy, stream solve, A = P W~, lower
-// Q = A P, the update, residual -- runs as ONE grouped launch over a work list of
+// conditions): the step's starting iterate and every phase of a fixed-point evaluation --
+// stream solve, A = P W~, lower Q = A P, the update, residual -- run as ONE grouped launch each
+// over a work list of
 // (simulation, tile) items, and the 1 + 5K launches of a step are captured once into a HIP
 // graph and replayed, one graph launch per step.
 //
@@ -64,7 +65,8 @@ struct EnsProb {
     double2* Wd;
 };
 
-// blocks per simulation of the whole-matrix passes (the step start, the run's last copy)
+// blocks per simulation of the whole-matrix copies (the first evaluation's output, the run's last
+// state)
 constexpr int kCopyParts = 64;
 
 // Start of a step: the first iterate F (W_n is read where the previous step left it, Wn).
