@@ -1,9 +1,8 @@
 // Ensembles of independent IsoMP simulations of uneven N (statistics over many initial
 // conditions): the step's starting iterate and every phase of a fixed-point evaluation --
 // stream solve, A = P W~, lower Q = A P, the update, residual -- run as ONE grouped launch each
-// over a work list of
-// (simulation, tile) items, and the 1 + 5K launches of a step are captured once into a HIP
-// graph and replayed, one graph launch per step.
+// over a work list of (simulation, tile) items, and the 1 + 5K launches of a step are captured
+// once into a HIP graph and replayed, one graph launch per step.
 //
 // Convergence stays tolerance-driven without host round trips: per-simulation device flags
 // `done` are cleared at the start of a step and set by the residual kernel once the change of
