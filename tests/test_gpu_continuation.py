@@ -66,6 +66,29 @@ def test_split_run_equals_one_run(dev, mode, order, stop):
         assert np.linalg.norm(Wb - Wr) <= 1e-12 * np.linalg.norm(Wr)
 
 
+def test_continuation_across_stopping_modes(dev):
+    """The stopping rule's place (host or device) may change between continued calls: both take
+    the same evaluations, so the trajectory is that of one call."""
+    from paper_2206_05466_amd import Zeuler
+
+    N, h = 64, 0.01
+    W0 = field(N, 14)
+    with Zeuler(N) as z:
+        z.set_initial_guess(3)
+        z.set_update_form(1)
+        Wa, ia = run_calls(z, W0, h, [11])
+        z.set_continuation(True)
+        W = torch.from_numpy(W0).cuda()
+        ib = []
+        for k, stop in ((5, 0), (3, 1), (3, 0)):
+            z.set_stopping(stop)
+            i, _ = z.isomp_run(W, h, k, 1e-12, 50)
+            ib += i
+        torch.cuda.synchronize()
+    assert ia == ib, (ia, ib)
+    assert np.array_equal(Wa, W.cpu().numpy())
+
+
 def test_continuation_with_steady_cap(dev):
     """The steady cap goes by the trajectory's step index: a continued call's steps are capped
     from the trajectory's step 4 on, as in one call."""
