@@ -76,3 +76,71 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(zeuler, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         zeuler.load_library()
+
+
+def declared_prototypes():
+    """{name: (return type, [parameter types])} from the comment-stripped header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = {}
+    for ret, name, params in re.findall(r"([A-Za-z_][\w\s\*]*?)\b(ze_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        types = []
+        for p in params.split(","):
+            p = " ".join(p.split())
+            if not p or p == "void":
+                continue
+            # drop the parameter name: the last identifier, unless the declaration is only a type
+            m = re.match(r"^(.*?[\s\*])([A-Za-z_]\w*)$", p)
+            types.append((m.group(1) if m else p).replace(" ", "").strip())
+        protos[name] = (" ".join(ret.split()), types)
+    return protos
+
+
+def ctypes_kind(t):
+    if t in (ctypes.c_int,):
+        return "int"
+    if t is ctypes.c_double:
+        return "double"
+    if t is ctypes.c_char_p:
+        return "string"
+    if t is ctypes.c_void_p:
+        return "pointer"
+    if isinstance(t, type) and issubclass(t, ctypes._Pointer):
+        inner = t._type_
+        return {ctypes.c_int: "int*", ctypes.c_double: "double*", ctypes.c_longlong: "longlong*",
+                ctypes.c_void_p: "pointer*"}[inner]
+    raise AssertionError(f"unexpected ctypes type {t}")
+
+
+def c_kind(t):
+    t = t.replace("const", "")
+    if t in ("int", "ze_status"):
+        return "int"
+    if t == "double":
+        return "double"
+    if t == "char*":
+        return "string"
+    if t == "int*":
+        return "int*"
+    if t == "double*":
+        return "double*"
+    if t == "longlong*":
+        return "longlong*"
+    if t in ("ze_ctx**", "ze_ens**", "void**"):
+        return "pointer*"
+    if t in ("void*", "ze_ctx*", "ze_ens*"):
+        return "pointer"
+    raise AssertionError(f"unexpected C type {t!r}")
+
+
+def test_binding_signatures_match_the_header():
+    """Every ctypes argtypes/restype of the binding has the arity and kind of the header's
+    prototype (an int passed where a double is declared would be marshalled wrongly)."""
+    protos = declared_prototypes()
+    assert sorted(protos) == declared_functions()
+    for name, (res, args) in zeuler.SIGNATURES.items():
+        ret, params = protos[name]
+        ckinds = [c_kind(p) for p in params]
+        pykinds = [ctypes_kind(a) for a in args]
+        assert ckinds == pykinds, (name, params, pykinds)
+        want_ret = "string" if "char" in ret else ("int" if ret in ("ze_status", "int") else ret)
+        assert ctypes_kind(res) == want_ret, (name, ret, res)
